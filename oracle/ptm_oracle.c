@@ -1,0 +1,1400 @@
+/*
+ * ptm_oracle.c -- plain, slow FP64 CPU reference of Polyhedral Template
+ * Matching (Larsen, Schmidt & Schiotz, arXiv:1603.05143).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library under paper_1603_05143_amd/) never calls it, links it or
+ * shares code, headers or tables with it.
+ *
+ * Every step is written for clarity, not speed, and follows the paper:
+ *   neighbours  -- brute force over all atoms, ordered by distance
+ *                  (Sec. 3; Alg. 1 takes A sorted by distance)
+ *   hull        -- every triple tested against every other point with exact
+ *                  orientation predicates and symbolic perturbation
+ *                  (Sec. 4: convex hull of the innermost |W| atoms; Alg. 1
+ *                  requires the central atom strictly inside)
+ *   graph       -- Weinberg-style walk code restricted to one embedding
+ *                  (Sec. 4: orientation-preserving canonical form); the
+ *                  lexicographically smallest walk over all directed start
+ *                  edges is the canonical form, the start edges reaching it
+ *                  give the automorphisms
+ *   templates   -- every triangulation of every template hull (1/64/64/1/4096)
+ *                  enumerated with no symmetry reduction (Sec. 4, App. A)
+ *   RMSD        -- eq. (3)/(4): both sets centred, template scaled to unit
+ *                  mean distance; rotation from the top eigenvector of Horn's
+ *                  4x4 quaternion matrix (cyclic Jacobi), scale s = lambda/G_a,
+ *                  RMSD from the explicit residual
+ *   decision    -- Alg. 1: minimum RMSD, template order SC,FCC,HCP,ICO,BCC,
+ *                  strict improvement only (ties resolved as documented)
+ *   strain      -- eq. (6) least squares with the pseudoinverse of the ideal
+ *                  template, then the symmetric factor P of the left polar
+ *                  decomposition A = P U (Sec. 8)
+ *   alloy       -- Table 3 (FCC coplanar groups) and the A1/A2/B2 rules of
+ *                  Sec. 6.
+ *
+ * Readings where the paper is silent are listed in DESIGN.md ("readings").
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KMAX 14
+#define NMAX (KMAX + 1)
+#define TIE_EPS 1e-12
+
+enum { T_SC = 0, T_FCC = 1, T_HCP = 2, T_ICO = 3, T_BCC = 4, NTEMPL = 5 };
+static const int TEMPL_K[NTEMPL] = {6, 12, 12, 12, 14};
+
+/* ======================================================================== */
+/* exact arithmetic: nonoverlapping floating-point expansions               */
+/* (error-free transformations of Knuth/Dekker; expansion growth as in       */
+/*  Shewchuk 1997).  Components are kept in order of increasing magnitude.   */
+/* ======================================================================== */
+typedef struct {
+    int n;
+    double c[200];
+} expan;
+
+static void two_sum(double a, double b, double *s, double *e) {
+    double x = a + b;
+    double bv = x - a;
+    double av = x - bv;
+    *s = x;
+    *e = (a - av) + (b - bv);
+}
+
+static void two_prod(double a, double b, double *p, double *e) {
+    double x = a * b;
+    *p = x;
+    *e = fma(a, b, -x); /* exact residual of the rounded product */
+}
+
+/* e := e + b, exactly */
+static void expan_add(expan *e, double b) {
+    double q = b;
+    int m = 0;
+    for (int i = 0; i < e->n; i++) {
+        double s, h;
+        two_sum(q, e->c[i], &s, &h);
+        q = s;
+        if (h != 0.0) e->c[m++] = h;
+    }
+    if (q != 0.0) e->c[m++] = q;
+    e->n = m;
+}
+
+/* e := e + sign * (product of nf factors), exactly (nf <= 3) */
+static void expan_add_product(expan *e, int sign, const double *f, int nf) {
+    if (nf == 0) {
+        expan_add(e, (double)sign);
+        return;
+    }
+    if (nf == 1) {
+        expan_add(e, sign * f[0]);
+        return;
+    }
+    double p, q;
+    two_prod(f[0], f[1], &p, &q);
+    if (nf == 2) {
+        expan_add(e, sign * p);
+        expan_add(e, sign * q);
+        return;
+    }
+    double p1, e1, p2, e2;
+    two_prod(p, f[2], &p1, &e1);
+    two_prod(q, f[2], &p2, &e2);
+    expan_add(e, sign * p1);
+    expan_add(e, sign * e1);
+    expan_add(e, sign * p2);
+    expan_add(e, sign * e2);
+}
+
+static int expan_sign(const expan *e) {
+    for (int i = e->n - 1; i >= 0; i--)
+        if (e->c[i] != 0.0) return e->c[i] > 0 ? 1 : -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* exact sign of a minor of the 4x4 matrix L whose row r is (x_r, y_r, z_r, 1)
+ * for the four points p[0..3]; rows / cols given as bit masks.  Leibniz
+ * expansion, every product accumulated exactly.                             */
+static int lambda_minor_sign(const double *const p[4], unsigned rowmask, unsigned colmask) {
+    int rows[4], cols[4], m = 0, mc = 0;
+    for (int r = 0; r < 4; r++)
+        if (rowmask & (1u << r)) rows[m++] = r;
+    for (int c = 0; c < 4; c++)
+        if (colmask & (1u << c)) cols[mc++] = c;
+    if (m != mc) abort();
+    if (m == 0) return 1;
+    expan acc;
+    acc.n = 0;
+    int perm[4] = {0, 1, 2, 3};
+    /* iterate permutations of 0..m-1 (Heap's algorithm would do; m <= 4 so
+     * plain lexicographic enumeration of all m! index tuples is fine) */
+    int idx[4];
+    int total = 1;
+    for (int i = 2; i <= m; i++) total *= i;
+    for (int t = 0; t < total; t++) {
+        /* decode t into a permutation via the factorial number system */
+        int avail[4] = {0, 1, 2, 3};
+        int na = m, tt = t;
+        int fact = total;
+        for (int i = 0; i < m; i++) {
+            fact /= (m - i);
+            int d = tt / fact;
+            tt %= fact;
+            idx[i] = avail[d];
+            for (int j = d; j < na - 1; j++) avail[j] = avail[j + 1];
+            na--;
+        }
+        /* sign = parity of inversions */
+        int inv = 0;
+        for (int i = 0; i < m; i++)
+            for (int j = i + 1; j < m; j++)
+                if (idx[i] > idx[j]) inv++;
+        double f[4];
+        int nf = 0;
+        for (int i = 0; i < m; i++) {
+            int c = cols[idx[i]];
+            if (c < 3) f[nf++] = p[rows[i]][c];
+        }
+        expan_add_product(&acc, (inv & 1) ? -1 : 1, f, nf);
+    }
+    (void)perm;
+    return expan_sign(&acc);
+}
+
+/* Exact sign of orient(a,b,c,d) := det[b-a; c-a; d-a].  It is positive when
+ * d lies on the side the normal (b-a)x(c-a) points to.  Note det L(a,b,c,d)
+ * = -orient(a,b,c,d).  A floating-point evaluation with a deliberately loose
+ * error bound is tried first; ambiguous cases are decided exactly.          */
+static long g_cnt_orient, g_cnt_exact; /* updated racily; diagnostics only */
+
+static int orient_exact(const double *a, const double *b, const double *c, const double *d) {
+    double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double v[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double w[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
+    double t0 = v[1] * w[2], t1 = v[2] * w[1];
+    double t2 = v[2] * w[0], t3 = v[0] * w[2];
+    double t4 = v[0] * w[1], t5 = v[1] * w[0];
+    double det = u[0] * (t0 - t1) + u[1] * (t2 - t3) + u[2] * (t4 - t5);
+    double perm = fabs(u[0]) * (fabs(t0) + fabs(t1)) + fabs(u[1]) * (fabs(t2) + fabs(t3)) +
+                  fabs(u[2]) * (fabs(t4) + fabs(t5));
+    /* 2^-44 is far looser than the true bound (about 8 ulp of perm) */
+    double bound = perm * 5.6843418860808015e-14;
+    g_cnt_orient++;
+    if (det > bound) return 1;
+    if (det < -bound) return -1;
+    g_cnt_exact++;
+    const double *p[4] = {a, b, c, d};
+    return -lambda_minor_sign(p, 0xF, 0xF);
+}
+
+/* Orientation under Simulation of Simplicity (Edelsbrunner & Muecke 1990):
+ * point with index i is moved by eps^(2^(3i+2-j)) along coordinate j, so the
+ * point with the lowest index moves most, and z before y before x.  The sign
+ * of the perturbed determinant is the sign of the first non-vanishing
+ * coefficient of its expansion in eps, taken in order of decreasing size.  */
+static int orient_sos(const double *const q[4], const int id[4]) {
+    int s = orient_exact(q[0], q[1], q[2], q[3]);
+    if (s != 0) return s;
+    /* sort rows by index, tracking the permutation parity */
+    int ord[4] = {0, 1, 2, 3};
+    int parity = 1;
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 3 - i; j++)
+            if (id[ord[j]] > id[ord[j + 1]]) {
+                int t = ord[j];
+                ord[j] = ord[j + 1];
+                ord[j + 1] = t;
+                parity = -parity;
+            }
+    const double *p[4] = {q[ord[0]], q[ord[1]], q[ord[2]], q[ord[3]]};
+    /* bit 3r+(2-j) <-> perturbation of row r, coordinate j (0=x,1=y,2=z) */
+    for (unsigned mask = 1; mask < 4096; mask++) {
+        int rowof[12], colof[12], ne = 0;
+        unsigned rused = 0, cused = 0;
+        int ok = 1;
+        for (int b = 0; b < 12 && ok; b++) {
+            if (!(mask & (1u << b))) continue;
+            int r = b / 3, j = 2 - (b % 3);
+            if ((rused & (1u << r)) || (cused & (1u << j))) ok = 0;
+            rused |= 1u << r;
+            cused |= 1u << j;
+            rowof[ne] = r;
+            colof[ne] = j;
+            ne++;
+        }
+        if (!ok) continue;
+        /* sign of sigma0: rows in the set map to their paired columns, the
+         * remaining rows map to the remaining columns in increasing order  */
+        int sigma[4];
+        for (int e = 0; e < ne; e++) sigma[rowof[e]] = colof[e];
+        int rc[4], nrc = 0;
+        for (int c = 0; c < 4; c++)
+            if (!(cused & (1u << c))) rc[nrc++] = c;
+        int t = 0;
+        for (int r = 0; r < 4; r++)
+            if (!(rused & (1u << r))) sigma[r] = rc[t++];
+        int inv = 0;
+        for (int i = 0; i < 4; i++)
+            for (int j = i + 1; j < 4; j++)
+                if (sigma[i] > sigma[j]) inv++;
+        int ms = lambda_minor_sign(p, (~rused) & 0xF, (~cused) & 0xF);
+        if (ms != 0) {
+            int coef = (inv & 1) ? -ms : ms; /* sign of det L_sorted(eps) */
+            return -parity * coef;          /* orient = -det L_original  */
+        }
+    }
+    abort(); /* unreachable: a 1x1 minor of the constant column is 1 */
+}
+
+/* exact sign of det[a; b; c] (rows) */
+static int det3_exact(const double *a, const double *b, const double *c) {
+    double d = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+               a[2] * (b[0] * c[1] - b[1] * c[0]);
+    double perm = fabs(a[0]) * (fabs(b[1] * c[2]) + fabs(b[2] * c[1])) +
+                  fabs(a[1]) * (fabs(b[0] * c[2]) + fabs(b[2] * c[0])) +
+                  fabs(a[2]) * (fabs(b[0] * c[1]) + fabs(b[1] * c[0]));
+    double bound = perm * 5.6843418860808015e-14;
+    if (d > bound) return 1;
+    if (d < -bound) return -1;
+    expan e;
+    e.n = 0;
+    const double *r[3] = {a, b, c};
+    static const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    static const int S[6] = {1, -1, -1, 1, 1, -1};
+    for (int t = 0; t < 6; t++) {
+        double f[3] = {r[0][P[t][0]], r[1][P[t][1]], r[2][P[t][2]]};
+        expan_add_product(&e, S[t], f, 3);
+    }
+    return expan_sign(&e);
+}
+
+/* ======================================================================== */
+/* rotation systems and the orientation-preserving canonical walk            */
+/* ======================================================================== */
+typedef struct {
+    int k;
+    int deg[KMAX];
+    int nxt[KMAX][KMAX]; /* nxt[x][y]: neighbour after y, counter-clockwise
+                            around x seen from outside; -1 if no edge xy */
+} rotsys;
+
+static int count_edges(const rotsys *g) {
+    int s = 0;
+    for (int i = 0; i < g->k; i++) s += g->deg[i];
+    return s / 2;
+}
+
+/* rotation system from outward counter-clockwise triangles */
+static int rotsys_from_tris(int k, const int (*tri)[3], int ntri, rotsys *g) {
+    g->k = k;
+    for (int i = 0; i < k; i++) {
+        g->deg[i] = 0;
+        for (int j = 0; j < k; j++) g->nxt[i][j] = -1;
+    }
+    for (int t = 0; t < ntri; t++) {
+        int a = tri[t][0], b = tri[t][1], c = tri[t][2];
+        if (g->nxt[a][b] >= 0 || g->nxt[b][c] >= 0 || g->nxt[c][a] >= 0) return 0;
+        g->nxt[a][b] = c;
+        g->nxt[b][c] = a;
+        g->nxt[c][a] = b;
+    }
+    for (int x = 0; x < k; x++) {
+        int first = -1, cnt = 0;
+        for (int y = 0; y < k; y++)
+            if (g->nxt[x][y] >= 0) {
+                cnt++;
+                if (first < 0) first = y;
+            }
+        if (cnt == 0) return 0;
+        /* the cycle through the neighbours must be a single orbit */
+        int y = first, len = 0;
+        do {
+            y = g->nxt[x][y];
+            if (y < 0) return 0;
+            len++;
+        } while (y != first && len <= k);
+        if (len != cnt) return 0;
+        g->deg[x] = cnt;
+    }
+    return 1;
+}
+
+/* Walk code from the directed start edge u->v (labels 1..k in order of first
+ * visit).  Rules: on reaching a new vertex leave by the next edge
+ * counter-clockwise after the arrival edge; on reaching a known vertex go
+ * back along the arrival edge if that direction is unused, otherwise leave
+ * by the first unused edge counter-clockwise after the arrival edge.  Every
+ * directed edge is walked once, so the code has 2E+1 entries.  Returns the
+ * length, or -1 if the walk stalls.  vlab[l] receives the vertex labelled l. */
+static int walk_code(const rotsys *g, int u, int v, int *code, int *vlab) {
+    int k = g->k;
+    int E2 = 2 * count_edges(g);
+    unsigned char used[KMAX][KMAX];
+    int lab[KMAX];
+    memset(used, 0, sizeof used);
+    for (int i = 0; i < k; i++) lab[i] = 0;
+    int nl = 0, pos = 0;
+    lab[u] = ++nl;
+    vlab[nl] = u;
+    code[pos++] = lab[u];
+    used[u][v] = 1;
+    int fresh = 1;
+    lab[v] = ++nl;
+    vlab[nl] = v;
+    code[pos++] = lab[v];
+    int from = u, x = v;
+    for (int step = 1; step < E2; step++) {
+        int y;
+        if (fresh) {
+            y = g->nxt[x][from];
+        } else if (!used[x][from]) {
+            y = from;
+        } else {
+            y = g->nxt[x][from];
+            int guard = 0;
+            while (used[x][y]) {
+                y = g->nxt[x][y];
+                if (++guard > k) return -1;
+            }
+        }
+        if (used[x][y]) return -1;
+        used[x][y] = 1;
+        fresh = (lab[y] == 0);
+        if (fresh) {
+            lab[y] = ++nl;
+            vlab[nl] = y;
+        }
+        code[pos++] = lab[y];
+        from = x;
+        x = y;
+    }
+    return pos;
+}
+
+static int code_cmp(const int *a, const int *b, int n) {
+    for (int i = 0; i < n; i++)
+        if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+    return 0;
+}
+
+#define CODE_MAX (2 * (3 * KMAX - 6) + 1)
+#define AUT_MAX 128
+
+typedef struct {
+    int len;
+    int code[CODE_MAX];
+    int naut;                  /* number of start edges reaching the minimum */
+    int vlab[AUT_MAX][KMAX + 1]; /* vertex of each label, per such start edge */
+} canon_t;
+
+/* canonical form: smallest walk code over all directed start edges */
+static int canonical(const rotsys *g, canon_t *cf) {
+    int k = g->k;
+    int code[CODE_MAX], vl[KMAX + 1];
+    cf->len = -1;
+    cf->naut = 0;
+    for (int u = 0; u < k; u++)
+        for (int v = 0; v < k; v++) {
+            if (g->nxt[u][v] < 0) continue;
+            int len = walk_code(g, u, v, code, vl);
+            if (len < 0) return 0;
+            int c = (cf->len < 0) ? -1 : code_cmp(code, cf->code, len);
+            if (c < 0) {
+                cf->len = len;
+                memcpy(cf->code, code, sizeof(int) * len);
+                cf->naut = 0;
+            }
+            if (c <= 0) {
+                if (cf->naut >= AUT_MAX) return 0;
+                memcpy(cf->vlab[cf->naut], vl, sizeof vl);
+                cf->naut++;
+            }
+        }
+    return 1;
+}
+
+/* ======================================================================== */
+/* templates                                                                 */
+/* ======================================================================== */
+typedef struct {
+    int k;
+    double w[KMAX][3];     /* ideal neighbour positions, centre at origin   */
+    double b[NMAX][3];     /* eq.(4) normalised N=k+1 points, row 0 = centre */
+    double vpinv[3][NMAX]; /* Moore-Penrose pseudoinverse of b (3 x N)       */
+    int ngroup;
+    int gperm[60][KMAX];   /* R_g w_j = w_{gperm[g][j]}                      */
+    double grot[60][9];    /* R_g row-major                                  */
+    int ntri;              /* number of triangulations                       */
+    int tri_len;
+    int *tri_code;         /* [ntri][tri_len] canonical codes                */
+    int *tri_vlab;         /* [ntri][k+1] template vertex of each label       */
+    int norbit;            /* triangulation orbits under the rotation group  */
+} templ_t;
+
+static templ_t g_T[NTEMPL];
+static pthread_once_t g_once = PTHREAD_ONCE_INIT;
+static int g_init_ok = 0;
+
+/* vertex numbering fixed by the output convention */
+static void template_coords(int t, double w[KMAX][3]) {
+    int k = TEMPL_K[t];
+    memset(w, 0, sizeof(double) * KMAX * 3);
+    if (t == T_SC) {
+        static const double s[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        memcpy(w, s, sizeof s);
+    } else if (t == T_FCC) {
+        static const double f[12][3] = {{1, 1, 0},  {1, -1, 0},  {-1, 1, 0},  {-1, -1, 0},
+                                        {1, 0, 1},  {1, 0, -1},  {-1, 0, 1},  {-1, 0, -1},
+                                        {0, 1, 1},  {0, 1, -1},  {0, -1, 1},  {0, -1, -1}};
+        memcpy(w, f, sizeof f);
+    } else if (t == T_HCP) {
+        const double pi = 3.14159265358979323846;
+        for (int m = 0; m < 6; m++) {
+            w[m][0] = cos(pi / 3.0 * m);
+            w[m][1] = sin(pi / 3.0 * m);
+            w[m][2] = 0.0;
+        }
+        double r = 1.0 / sqrt(3.0), h = sqrt(2.0 / 3.0);
+        for (int j = 0; j < 3; j++) {
+            double ang = pi / 6.0 + 2.0 * pi / 3.0 * j;
+            w[6 + j][0] = r * cos(ang);
+            w[6 + j][1] = r * sin(ang);
+            w[6 + j][2] = h;
+            w[9 + j][0] = r * cos(ang);
+            w[9 + j][1] = r * sin(ang);
+            w[9 + j][2] = -h;
+        }
+    } else if (t == T_ICO) {
+        double p = (1.0 + sqrt(5.0)) / 2.0;
+        double v[12][3] = {{0, 1, p},  {0, 1, -p},  {0, -1, p},  {0, -1, -p},
+                           {1, p, 0},  {1, -p, 0},  {-1, p, 0},  {-1, -p, 0},
+                           {p, 0, 1},  {p, 0, -1},  {-p, 0, 1},  {-p, 0, -1}};
+        memcpy(w, v, sizeof v);
+    } else {
+        static const double v[14][3] = {{1, 1, 1},   {1, 1, -1},  {1, -1, 1},  {1, -1, -1},
+                                        {-1, 1, 1},  {-1, 1, -1}, {-1, -1, 1}, {-1, -1, -1},
+                                        {2, 0, 0},   {-2, 0, 0},  {0, 2, 0},   {0, -2, 0},
+                                        {0, 0, 2},   {0, 0, -2}};
+        memcpy(w, v, sizeof v);
+    }
+    (void)k;
+}
+
+/* eq.(4): translate the N points to their barycentre and divide by the mean
+ * distance from it.  p[0] is the centre, p[1..k] the neighbours.          */
+static double normalise_points(int N, const double (*p)[3], double (*out)[3]) {
+    double c[3] = {0, 0, 0};
+    for (int i = 0; i < N; i++)
+        for (int d = 0; d < 3; d++) c[d] += p[i][d];
+    for (int d = 0; d < 3; d++) c[d] /= N;
+    double l = 0;
+    for (int i = 0; i < N; i++) {
+        double dx = p[i][0] - c[0], dy = p[i][1] - c[1], dz = p[i][2] - c[2];
+        l += sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    l /= N;
+    for (int i = 0; i < N; i++)
+        for (int d = 0; d < 3; d++) out[i][d] = (p[i][d] - c[d]) / l;
+    return l;
+}
+
+static void mat3_inverse(const double m[3][3], double inv[3][3]) {
+    double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                 m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                 m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+    inv[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / det;
+    inv[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / det;
+    inv[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / det;
+    inv[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) / det;
+    inv[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / det;
+    inv[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / det;
+    inv[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) / det;
+    inv[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) / det;
+    inv[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / det;
+}
+
+/* proper rotations mapping the neighbour set onto itself, found by trying
+ * every image of a reference pair of vertices */
+static int find_group(int k, const double (*w)[3], int perm[60][KMAX], double rot[60][9]) {
+    int i0 = 0, i1 = -1;
+    for (int j = 1; j < k; j++) {
+        double cx = w[0][1] * w[j][2] - w[0][2] * w[j][1];
+        double cy = w[0][2] * w[j][0] - w[0][0] * w[j][2];
+        double cz = w[0][0] * w[j][1] - w[0][1] * w[j][0];
+        if (cx * cx + cy * cy + cz * cz > 1e-6) {
+            i1 = j;
+            break;
+        }
+    }
+    double E[3][3], n0 = 0, n1, dot01 = 0;
+    for (int d = 0; d < 3; d++) n0 += w[i0][d] * w[i0][d];
+    n0 = sqrt(n0);
+    for (int d = 0; d < 3; d++) E[0][d] = w[i0][d] / n0;
+    for (int d = 0; d < 3; d++) dot01 += w[i1][d] * E[0][d];
+    double t[3];
+    for (int d = 0; d < 3; d++) t[d] = w[i1][d] - dot01 * E[0][d];
+    n1 = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int d = 0; d < 3; d++) E[1][d] = t[d] / n1;
+    E[2][0] = E[0][1] * E[1][2] - E[0][2] * E[1][1];
+    E[2][1] = E[0][2] * E[1][0] - E[0][0] * E[1][2];
+    E[2][2] = E[0][0] * E[1][1] - E[0][1] * E[1][0];
+    double len0 = n0, len1 = sqrt(w[i1][0] * w[i1][0] + w[i1][1] * w[i1][1] + w[i1][2] * w[i1][2]);
+    double g01 = w[i0][0] * w[i1][0] + w[i0][1] * w[i1][1] + w[i0][2] * w[i1][2];
+    int ng = 0;
+    for (int a = 0; a < k; a++)
+        for (int b = 0; b < k; b++) {
+            if (a == b) continue;
+            double la = sqrt(w[a][0] * w[a][0] + w[a][1] * w[a][1] + w[a][2] * w[a][2]);
+            double lb = sqrt(w[b][0] * w[b][0] + w[b][1] * w[b][1] + w[b][2] * w[b][2]);
+            double gab = w[a][0] * w[b][0] + w[a][1] * w[b][1] + w[a][2] * w[b][2];
+            if (fabs(la - len0) > 1e-9 || fabs(lb - len1) > 1e-9 || fabs(gab - g01) > 1e-9) continue;
+            double F[3][3], da = 0;
+            for (int d = 0; d < 3; d++) F[0][d] = w[a][d] / la;
+            for (int d = 0; d < 3; d++) da += w[b][d] * F[0][d];
+            for (int d = 0; d < 3; d++) t[d] = w[b][d] - da * F[0][d];
+            double nt = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+            for (int d = 0; d < 3; d++) F[1][d] = t[d] / nt;
+            F[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+            F[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+            F[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+            /* R = F^T E  maps E-frame onto F-frame */
+            double R[3][3];
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) {
+                    R[r][c] = 0;
+                    for (int m = 0; m < 3; m++) R[r][c] += F[m][r] * E[m][c];
+                }
+            int pm[KMAX], ok = 1;
+            for (int j = 0; j < k && ok; j++) {
+                double y[3];
+                for (int r = 0; r < 3; r++) y[r] = R[r][0] * w[j][0] + R[r][1] * w[j][1] + R[r][2] * w[j][2];
+                pm[j] = -1;
+                for (int m = 0; m < k; m++) {
+                    double dx = y[0] - w[m][0], dy = y[1] - w[m][1], dz = y[2] - w[m][2];
+                    if (dx * dx + dy * dy + dz * dz < 1e-12) {
+                        pm[j] = m;
+                        break;
+                    }
+                }
+                if (pm[j] < 0) ok = 0;
+            }
+            if (!ok) continue;
+            if (ng >= 60) return -1;
+            memcpy(perm[ng], pm, sizeof(int) * k);
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) rot[ng][r * 3 + c] = R[r][c];
+            ng++;
+        }
+    return ng;
+}
+
+/* faces of the ideal hull: coplanar vertex sets on supporting planes,
+ * ordered counter-clockwise seen from outside */
+static int template_faces(int k, const double (*w)[3], int faces[32][4], int fsize[32]) {
+    int nf = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            for (int l = j + 1; l < k; l++) {
+                double u[3], v[3], n[3];
+                for (int d = 0; d < 3; d++) {
+                    u[d] = w[j][d] - w[i][d];
+                    v[d] = w[l][d] - w[i][d];
+                }
+                n[0] = u[1] * v[2] - u[2] * v[1];
+                n[1] = u[2] * v[0] - u[0] * v[2];
+                n[2] = u[0] * v[1] - u[1] * v[0];
+                double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                if (nn < 1e-9) continue;
+                int pos = 0, neg = 0, on[KMAX], non = 0;
+                for (int m = 0; m < k; m++) {
+                    double s = (n[0] * (w[m][0] - w[i][0]) + n[1] * (w[m][1] - w[i][1]) +
+                                n[2] * (w[m][2] - w[i][2])) / nn;
+                    if (s > 1e-7) pos++;
+                    else if (s < -1e-7) neg++;
+                    else on[non++] = m;
+                }
+                if (pos && neg) continue;
+                if (non > 4) return -1;
+                /* outward normal */
+                double sgn = pos ? -1.0 : 1.0;
+                for (int d = 0; d < 3; d++) n[d] *= sgn;
+                /* dedupe */
+                int dup = 0;
+                for (int f = 0; f < nf && !dup; f++) {
+                    if (fsize[f] != non) continue;
+                    int same = 1;
+                    for (int a = 0; a < non; a++) {
+                        int found = 0;
+                        for (int b = 0; b < non; b++)
+                            if (faces[f][b] == on[a]) found = 1;
+                        if (!found) same = 0;
+                    }
+                    if (same) dup = 1;
+                }
+                if (dup) continue;
+                /* order counter-clockwise around the outward normal */
+                double c[3] = {0, 0, 0};
+                for (int a = 0; a < non; a++)
+                    for (int d = 0; d < 3; d++) c[d] += w[on[a]][d] / non;
+                double e1[3], e2[3];
+                for (int d = 0; d < 3; d++) e1[d] = w[on[0]][d] - c[d];
+                double ne1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+                for (int d = 0; d < 3; d++) e1[d] /= ne1;
+                e2[0] = n[1] * e1[2] - n[2] * e1[1];
+                e2[1] = n[2] * e1[0] - n[0] * e1[2];
+                e2[2] = n[0] * e1[1] - n[1] * e1[0];
+                double ang[4];
+                for (int a = 0; a < non; a++) {
+                    double x = 0, y = 0;
+                    for (int d = 0; d < 3; d++) {
+                        x += (w[on[a]][d] - c[d]) * e1[d];
+                        y += (w[on[a]][d] - c[d]) * e2[d];
+                    }
+                    ang[a] = atan2(y, x);
+                }
+                for (int a = 0; a < non; a++)
+                    for (int b = 0; b < non - 1 - a; b++)
+                        if (ang[b] > ang[b + 1]) {
+                            double ta = ang[b];
+                            ang[b] = ang[b + 1];
+                            ang[b + 1] = ta;
+                            int tv = on[b];
+                            on[b] = on[b + 1];
+                            on[b + 1] = tv;
+                        }
+                if (nf >= 32) return -1;
+                for (int a = 0; a < non; a++) faces[nf][a] = on[a];
+                fsize[nf] = non;
+                nf++;
+            }
+    return nf;
+}
+
+static int build_template(int t) {
+    templ_t *T = &g_T[t];
+    int k = TEMPL_K[t];
+    T->k = k;
+    template_coords(t, T->w);
+    double pts[NMAX][3];
+    memset(pts, 0, sizeof pts);
+    for (int j = 0; j < k; j++)
+        for (int d = 0; d < 3; d++) pts[j + 1][d] = T->w[j][d];
+    normalise_points(k + 1, (const double(*)[3])pts, T->b);
+    /* pseudoinverse (B^T B)^-1 B^T of the N x 3 matrix B */
+    double btb[3][3] = {{0}}, inv[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            for (int i = 0; i < k + 1; i++) btb[r][c] += T->b[i][r] * T->b[i][c];
+    mat3_inverse(btb, inv);
+    for (int r = 0; r < 3; r++)
+        for (int i = 0; i < k + 1; i++) {
+            T->vpinv[r][i] = 0;
+            for (int c = 0; c < 3; c++) T->vpinv[r][i] += inv[r][c] * T->b[i][c];
+        }
+    T->ngroup = find_group(k, (const double(*)[3])T->w, T->gperm, T->grot);
+    if (T->ngroup <= 0) return 0;
+
+    int faces[32][4], fsize[32];
+    int nf = template_faces(k, (const double(*)[3])T->w, faces, fsize);
+    if (nf <= 0) return 0;
+    int quads[32], nq = 0, ntri_fixed = 0;
+    for (int f = 0; f < nf; f++) {
+        if (fsize[f] == 4) quads[nq++] = f;
+        else if (fsize[f] == 3) ntri_fixed++;
+        else return 0;
+    }
+    T->ntri = 1 << nq;
+    int E = 3 * k - 6;
+    T->tri_len = 2 * E + 1;
+    T->tri_code = (int *)malloc(sizeof(int) * T->ntri * T->tri_len);
+    T->tri_vlab = (int *)malloc(sizeof(int) * T->ntri * (k + 1));
+    /* orbit bookkeeping: triangulation id of the image under each rotation */
+    int *orbit_of = (int *)malloc(sizeof(int) * T->ntri);
+    for (int s = 0; s < T->ntri; s++) orbit_of[s] = -1;
+    for (int s = 0; s < T->ntri; s++) {
+        int tris[2 * KMAX][3], nt = 0;
+        for (int f = 0; f < nf; f++)
+            if (fsize[f] == 3) {
+                tris[nt][0] = faces[f][0];
+                tris[nt][1] = faces[f][1];
+                tris[nt][2] = faces[f][2];
+                nt++;
+            }
+        for (int q = 0; q < nq; q++) {
+            const int *v = faces[quads[q]];
+            if (s & (1 << q)) { /* diagonal v1-v3 */
+                int a[3] = {v[1], v[2], v[3]}, b[3] = {v[1], v[3], v[0]};
+                memcpy(tris[nt++], a, sizeof a);
+                memcpy(tris[nt++], b, sizeof b);
+            } else { /* diagonal v0-v2 */
+                int a[3] = {v[0], v[1], v[2]}, b[3] = {v[0], v[2], v[3]};
+                memcpy(tris[nt++], a, sizeof a);
+                memcpy(tris[nt++], b, sizeof b);
+            }
+        }
+        if (nt != 2 * k - 4) return 0;
+        rotsys g;
+        if (!rotsys_from_tris(k, (const int(*)[3])tris, nt, &g)) return 0;
+        canon_t cf;
+        if (!canonical(&g, &cf) || cf.len != T->tri_len) return 0;
+        memcpy(T->tri_code + (size_t)s * T->tri_len, cf.code, sizeof(int) * cf.len);
+        for (int l = 1; l <= k; l++) T->tri_vlab[(size_t)s * (k + 1) + l] = cf.vlab[0][l];
+        T->tri_vlab[(size_t)s * (k + 1)] = -1;
+        /* orbit id: the image of the diagonal choice under each group element */
+        if (orbit_of[s] < 0) {
+            for (int gi = 0; gi < T->ngroup; gi++) {
+                int img = 0;
+                for (int q = 0; q < nq; q++) {
+                    const int *v = faces[quads[q]];
+                    int d0 = (s & (1 << q)) ? v[1] : v[0];
+                    int d1 = (s & (1 << q)) ? v[3] : v[2];
+                    int e0 = T->gperm[gi][d0], e1 = T->gperm[gi][d1];
+                    /* find the quad containing the image diagonal */
+                    for (int q2 = 0; q2 < nq; q2++) {
+                        const int *u = faces[quads[q2]];
+                        int h0 = 0, h1 = 0;
+                        for (int a = 0; a < 4; a++) {
+                            if (u[a] == e0) h0 = 1;
+                            if (u[a] == e1) h1 = 1;
+                        }
+                        if (h0 && h1) {
+                            int alt = (e0 == u[1] || e0 == u[3]);
+                            if (alt) img |= 1 << q2;
+                        }
+                    }
+                }
+                orbit_of[img] = s;
+            }
+        }
+    }
+    T->norbit = 0;
+    for (int s = 0; s < T->ntri; s++)
+        if (orbit_of[s] == s) T->norbit++;
+    free(orbit_of);
+    (void)ntri_fixed;
+    return 1;
+}
+
+static void init_tables(void) {
+    for (int t = 0; t < NTEMPL; t++)
+        if (!build_template(t)) return;
+    g_init_ok = 1;
+}
+
+static int ensure_init(void) {
+    pthread_once(&g_once, init_tables);
+    return g_init_ok;
+}
+
+/* ======================================================================== */
+/* superposition: eq.(2)-(4) via Horn's quaternion matrix                    */
+/* ======================================================================== */
+/* cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= 4);
+ * eigenvalues in ev, eigenvectors in the columns of V */
+static void jacobi_eigen(int n, double A[4][4], double ev[4], double V[4][4]) {
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) V[i][j] = (i == j);
+    for (int sweep = 0; sweep < 100; sweep++) {
+        double off = 0, diag = 0;
+        for (int i = 0; i < n; i++) {
+            diag += A[i][i] * A[i][i];
+            for (int j = i + 1; j < n; j++) off += A[i][j] * A[i][j];
+        }
+        if (off == 0.0 || off < 1e-34 * diag) break;
+        for (int p = 0; p < n; p++)
+            for (int q = p + 1; q < n; q++) {
+                if (A[p][q] == 0.0) continue;
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int r = 0; r < n; r++) { /* columns p,q */
+                    double arp = A[r][p], arq = A[r][q];
+                    A[r][p] = c * arp - s * arq;
+                    A[r][q] = s * arp + c * arq;
+                }
+                for (int r = 0; r < n; r++) { /* rows p,q */
+                    double apr = A[p][r], aqr = A[q][r];
+                    A[p][r] = c * apr - s * aqr;
+                    A[q][r] = s * apr + c * aqr;
+                }
+                for (int r = 0; r < n; r++) {
+                    double vrp = V[r][p], vrq = V[r][q];
+                    V[r][p] = c * vrp - s * vrq;
+                    V[r][q] = s * vrp + c * vrq;
+                }
+            }
+    }
+    for (int i = 0; i < n; i++) ev[i] = A[i][i];
+}
+
+static void quat_to_rot(const double q[4], double R[9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static void rot_to_quat(const double R[9], double q[4]) {
+    double tr = R[0] + R[4] + R[8];
+    double c[4] = {1 + tr, 1 + R[0] - R[4] - R[8], 1 - R[0] + R[4] - R[8], 1 - R[0] - R[4] + R[8]};
+    int m = 0;
+    for (int i = 1; i < 4; i++)
+        if (c[i] > c[m]) m = i;
+    double s = 2.0 * sqrt(c[m]);
+    if (m == 0) {
+        q[0] = s / 4; q[1] = (R[7] - R[5]) / s; q[2] = (R[2] - R[6]) / s; q[3] = (R[3] - R[1]) / s;
+    } else if (m == 1) {
+        q[0] = (R[7] - R[5]) / s; q[1] = s / 4; q[2] = (R[1] + R[3]) / s; q[3] = (R[2] + R[6]) / s;
+    } else if (m == 2) {
+        q[0] = (R[2] - R[6]) / s; q[1] = (R[1] + R[3]) / s; q[2] = s / 4; q[3] = (R[5] + R[7]) / s;
+    } else {
+        q[0] = (R[3] - R[1]) / s; q[1] = (R[2] + R[6]) / s; q[2] = (R[5] + R[7]) / s; q[3] = s / 4;
+    }
+    double nrm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; i++) q[i] /= nrm;
+}
+
+static void quat_canonical_sign(double q[4]) {
+    for (int i = 0; i < 4; i++) {
+        if (q[i] > 0) return;
+        if (q[i] < 0) {
+            for (int j = 0; j < 4; j++) q[j] = -q[j];
+            return;
+        }
+    }
+}
+
+/* min over s, Q of eq.(3), given rows a[i] = observed point i minus the
+ * observed barycentre and b[i] = the eq.(4)-normalised template point it is
+ * matched with.  Q maps template to sample: s a_i ~ Q b_i.                 */
+static void superpose(int N, const double (*a)[3], const double (*b)[3], double *rmsd, double *scale,
+                      double q[4], double *lambda_out) {
+    double S[3][3] = {{0}};
+    double Ga = 0;
+    for (int i = 0; i < N; i++) {
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) S[r][c] += b[i][r] * a[i][c];
+        Ga += a[i][0] * a[i][0] + a[i][1] * a[i][1] + a[i][2] * a[i][2];
+    }
+    double K[4][4] = {
+        {S[0][0] + S[1][1] + S[2][2], S[1][2] - S[2][1], S[2][0] - S[0][2], S[0][1] - S[1][0]},
+        {S[1][2] - S[2][1], S[0][0] - S[1][1] - S[2][2], S[0][1] + S[1][0], S[2][0] + S[0][2]},
+        {S[2][0] - S[0][2], S[0][1] + S[1][0], -S[0][0] + S[1][1] - S[2][2], S[1][2] + S[2][1]},
+        {S[0][1] - S[1][0], S[2][0] + S[0][2], S[1][2] + S[2][1], -S[0][0] - S[1][1] + S[2][2]}};
+    double ev[4], V[4][4];
+    jacobi_eigen(4, K, ev, V);
+    int m = 0;
+    for (int i = 1; i < 4; i++)
+        if (ev[i] > ev[m]) m = i;
+    double lam = ev[m];
+    for (int i = 0; i < 4; i++) q[i] = V[i][m];
+    double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; i++) q[i] /= nq;
+    double s = (Ga > 0) ? lam / Ga : 0.0;
+    double R[9];
+    quat_to_rot(q, R);
+    double res = 0;
+    for (int i = 0; i < N; i++) {
+        for (int r = 0; r < 3; r++) {
+            double rb = R[r * 3] * b[i][0] + R[r * 3 + 1] * b[i][1] + R[r * 3 + 2] * b[i][2];
+            double d = s * a[i][r] - rb;
+            res += d * d;
+        }
+    }
+    *rmsd = sqrt(res / N);
+    *scale = s;
+    if (lambda_out) *lambda_out = lam;
+}
+
+/* ======================================================================== */
+/* per-atom classification                                                   */
+/* ======================================================================== */
+typedef struct {
+    int tmpl;
+    int c[KMAX];   /* observed neighbour rank at each template vertex */
+    double r, s, q[4];
+} cand_t;
+
+typedef struct {
+    long n_orient, n_exact, n_hull, n_code, n_cand;
+} counters_t;
+
+/* hull of the first k neighbours by testing all triples; fills the rotation
+ * system and returns 1 when all k points are hull vertices and the central
+ * atom (the origin) is strictly inside every facet */
+static int hull_all_triples(int k, const double (*q)[3], rotsys *g) {
+    int tris[4 * KMAX][3], nt = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            for (int l = j + 1; l < k; l++) {
+                int ref = 0, ok = 1;
+                for (int m = 0; m < k && ok; m++) {
+                    if (m == i || m == j || m == l) continue;
+                    const double *P[4] = {q[i], q[j], q[l], q[m]};
+                    int id[4] = {i, j, l, m};
+                    int s = orient_sos(P, id);
+                    if (ref == 0) ref = s;
+                    else if (s != ref) ok = 0;
+                }
+                if (!ok) continue;
+                if (nt >= 4 * KMAX) return 0;
+                if (ref < 0) {
+                    tris[nt][0] = i; tris[nt][1] = j; tris[nt][2] = l;
+                } else {
+                    tris[nt][0] = i; tris[nt][1] = l; tris[nt][2] = j;
+                }
+                nt++;
+            }
+    if (nt != 2 * k - 4) return 0;
+    unsigned seen = 0;
+    for (int t = 0; t < nt; t++) seen |= (1u << tris[t][0]) | (1u << tris[t][1]) | (1u << tris[t][2]);
+    if (seen != (1u << k) - 1) return 0;
+    for (int t = 0; t < nt; t++)
+        if (det3_exact(q[tris[t][0]], q[tris[t][1]], q[tris[t][2]]) <= 0) return 0;
+    return rotsys_from_tris(k, (const int(*)[3])tris, nt, g);
+}
+
+/* brute-force neighbour list ordered by (d^2, index); minimum image with
+ * s = rint(d * (1/L)), d -= s*L per periodic axis; d^2 = (dx^2+dy^2)+dz^2 */
+static int knn_brute(const double *pos, int64_t n, const double box[3], int64_t i, int K,
+                     int32_t *ids, double (*rel)[3], double *d2out) {
+    double inv[3];
+    for (int d = 0; d < 3; d++) inv[d] = box[d] > 0 ? 1.0 / box[d] : 0.0;
+    int cnt = 0;
+    double kd2[KMAX + 1];
+    int32_t kid[KMAX + 1];
+    double kr[KMAX + 1][3];
+    for (int64_t j = 0; j < n; j++) {
+        if (j == i) continue;
+        double v[3];
+        for (int d = 0; d < 3; d++) {
+            double x = pos[3 * j + d] - pos[3 * i + d];
+            if (box[d] > 0) {
+                double s = rint(x * inv[d]);
+                x = x - s * box[d];
+            }
+            v[d] = x;
+        }
+        double xx = v[0] * v[0], yy = v[1] * v[1], zz = v[2] * v[2];
+        double dd = (xx + yy) + zz;
+        if (cnt == K && !(dd < kd2[K - 1] || (dd == kd2[K - 1] && j < kid[K - 1]))) continue;
+        int p = (cnt < K) ? cnt++ : K - 1;
+        while (p > 0 && (dd < kd2[p - 1] || (dd == kd2[p - 1] && j < kid[p - 1]))) {
+            kd2[p] = kd2[p - 1];
+            kid[p] = kid[p - 1];
+            memcpy(kr[p], kr[p - 1], sizeof kr[p]);
+            p--;
+        }
+        kd2[p] = dd;
+        kid[p] = (int32_t)j;
+        memcpy(kr[p], v, sizeof v);
+    }
+    for (int r = 0; r < cnt; r++) {
+        ids[r] = kid[r];
+        memcpy(rel[r], kr[r], sizeof kr[r]);
+        if (d2out) d2out[r] = kd2[r];
+    }
+    return cnt;
+}
+
+/* lexicographically smallest rank vector over the template's rotation group
+ * (the orientation representative); returns the group element used */
+static int representative(int t, const int *c, int *out) {
+    const templ_t *T = &g_T[t];
+    int k = T->k, best = -1;
+    int cur[KMAX], inv[KMAX];
+    for (int g = 0; g < T->ngroup; g++) {
+        for (int j = 0; j < k; j++) inv[T->gperm[g][j]] = j;
+        for (int m = 0; m < k; m++) cur[m] = c[inv[m]];
+        if (best < 0 || code_cmp(cur, out, k) < 0) {
+            memcpy(out, cur, sizeof(int) * k);
+            best = g;
+        }
+    }
+    return best;
+}
+
+typedef struct {
+    int8_t type, alloy;
+    double rmsd, scale, quat[4], strain[9], margin;
+    int32_t nbr[KMAX], knn[KMAX];
+    int32_t ncand;
+} atom_out_t;
+
+static void classify_atom(const double *pos, const int8_t *species, const double box[3], int64_t n,
+                          int64_t i, uint32_t mask, double cutoff, atom_out_t *o, counters_t *cnt) {
+    int32_t ids[KMAX];
+    double rel[KMAX][3];
+    int nn = knn_brute(pos, n, box, i, KMAX, ids, rel, NULL);
+    for (int r = 0; r < KMAX; r++) o->knn[r] = r < nn ? ids[r] : -1;
+
+    static const int group_k[3] = {6, 12, 14};
+    cand_t *cands = NULL;
+    int nc = 0, capc = 0;
+    for (int gk = 0; gk < 3; gk++) {
+        int k = group_k[gk];
+        unsigned need = (k == 6) ? 1u : (k == 12 ? 0xEu : 0x10u);
+        if (!(mask & need) || nn < k) continue;
+        rotsys g;
+        cnt->n_hull++;
+        if (!hull_all_triples(k, (const double(*)[3])rel, &g)) continue;
+        canon_t cf;
+        cnt->n_code++;
+        if (!canonical(&g, &cf)) continue;
+        /* observed points, eq.(2): centre first, then neighbours by rank */
+        double obs[NMAX][3], cen[3] = {0, 0, 0};
+        memset(obs[0], 0, sizeof obs[0]);
+        for (int r = 0; r < k; r++) memcpy(obs[r + 1], rel[r], sizeof rel[r]);
+        for (int r = 0; r < k + 1; r++)
+            for (int d = 0; d < 3; d++) cen[d] += obs[r][d];
+        for (int d = 0; d < 3; d++) cen[d] /= (k + 1);
+        double a[NMAX][3];
+        for (int r = 0; r < k + 1; r++)
+            for (int d = 0; d < 3; d++) a[r][d] = obs[r][d] - cen[d];
+        for (int t = 0; t < NTEMPL; t++) {
+            if (TEMPL_K[t] != k || !(mask & (1u << t))) continue;
+            const templ_t *T = &g_T[t];
+            for (int s = 0; s < T->ntri; s++) {
+                if (T->tri_len != cf.len || code_cmp(T->tri_code + (size_t)s * T->tri_len, cf.code, cf.len))
+                    continue;
+                const int *tv = T->tri_vlab + (size_t)s * (k + 1);
+                for (int au = 0; au < cf.naut; au++) {
+                    cand_t C;
+                    C.tmpl = t;
+                    for (int l = 1; l <= k; l++) C.c[tv[l]] = cf.vlab[au][l];
+                    /* template rows in correspondence with observed rows */
+                    double bb[NMAX][3];
+                    memcpy(bb[0], T->b[0], sizeof bb[0]);
+                    double aa[NMAX][3];
+                    memcpy(aa[0], a[0], sizeof aa[0]);
+                    for (int j = 0; j < k; j++) {
+                        memcpy(bb[j + 1], T->b[j + 1], sizeof bb[0]);
+                        memcpy(aa[j + 1], a[C.c[j] + 1], sizeof aa[0]);
+                    }
+                    superpose(k + 1, (const double(*)[3])aa, (const double(*)[3])bb, &C.r, &C.s, C.q, NULL);
+                    cnt->n_cand++;
+                    if (nc == capc) {
+                        capc = capc ? 2 * capc : 64;
+                        cands = (cand_t *)realloc(cands, sizeof(cand_t) * capc);
+                    }
+                    cands[nc++] = C;
+                }
+            }
+        }
+    }
+    o->ncand = nc;
+    for (int r = 0; r < KMAX; r++) o->nbr[r] = -1;
+    memset(o->strain, 0, sizeof o->strain);
+    o->quat[0] = 1; o->quat[1] = o->quat[2] = o->quat[3] = 0;
+    o->rmsd = INFINITY;
+    o->scale = 0;
+    o->type = 0;
+    o->alloy = 0;
+    o->margin = INFINITY;
+    if (nc == 0) {
+        free(cands);
+        return;
+    }
+    /* Alg. 1 decision: minimum RMSD; near-equal values (within TIE_EPS) are
+     * resolved by template order, then by the smallest representative rank
+     * vector, which makes the result independent of enumeration order     */
+    double rstar = INFINITY;
+    for (int c = 0; c < nc; c++)
+        if (cands[c].r < rstar) rstar = cands[c].r;
+    int win = -1, win_rep[KMAX], win_g = -1;
+    for (int c = 0; c < nc; c++) {
+        if (!(cands[c].r <= rstar + TIE_EPS)) continue;
+        int rep[KMAX];
+        int gsel = representative(cands[c].tmpl, cands[c].c, rep);
+        int k = TEMPL_K[cands[c].tmpl];
+        int better = 0;
+        if (win < 0) better = 1;
+        else if (cands[c].tmpl != cands[win].tmpl) better = cands[c].tmpl < cands[win].tmpl;
+        else better = code_cmp(rep, win_rep, k) < 0;
+        if (better) {
+            win = c;
+            win_g = gsel;
+            memcpy(win_rep, rep, sizeof(int) * k);
+        }
+    }
+    const cand_t *W = &cands[win];
+    int t = W->tmpl, k = TEMPL_K[t];
+    const templ_t *T = &g_T[t];
+    /* margin: best RMSD of any candidate in a different template or class */
+    for (int c = 0; c < nc; c++) {
+        if (c == win) continue;
+        int rep[KMAX];
+        if (cands[c].tmpl == t) {
+            representative(t, cands[c].c, rep);
+            if (!code_cmp(rep, win_rep, k)) continue;
+        }
+        double mg = cands[c].r - W->r;
+        if (mg < o->margin) o->margin = mg;
+    }
+    o->rmsd = W->r;
+    o->scale = W->s;
+    o->type = (W->r <= cutoff) ? (int8_t)(t + 1) : 0;
+    for (int m = 0; m < k; m++) o->nbr[m] = ids[win_rep[m]];
+    /* orientation of the representative: Q' = Q R_g^T */
+    double R[9], Rg[9], Rn[9];
+    quat_to_rot(W->q, R);
+    memcpy(Rg, T->grot[win_g], sizeof Rg);
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            Rn[r * 3 + c] = 0;
+            for (int m = 0; m < 3; m++) Rn[r * 3 + c] += R[r * 3 + m] * Rg[c * 3 + m];
+        }
+    rot_to_quat(Rn, o->quat);
+    quat_canonical_sign(o->quat);
+
+    /* eq.(6): A^T = V+ W', W' = observed points in template order, centred
+     * and normalised by their own mean distance; P = (A A^T)^(1/2)        */
+    {
+        double obs[NMAX][3], wn[NMAX][3];
+        memset(obs[0], 0, sizeof obs[0]);
+        for (int j = 0; j < k; j++) memcpy(obs[j + 1], rel[W->c[j]], sizeof obs[0]);
+        normalise_points(k + 1, (const double(*)[3])obs, wn);
+        double At[3][3] = {{0}};
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++)
+                for (int m = 0; m < k + 1; m++) At[r][c] += T->vpinv[r][m] * wn[m][c];
+        double AAt[4][4] = {{0}};
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++)
+                for (int m = 0; m < 3; m++) AAt[r][c] += At[m][r] * At[m][c];
+        double ev[4], V[4][4];
+        jacobi_eigen(3, AAt, ev, V);
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) {
+                double s = 0;
+                for (int m = 0; m < 3; m++) s += V[r][m] * sqrt(ev[m] > 0 ? ev[m] : 0.0) * V[c][m];
+                o->strain[r * 3 + c] = s;
+            }
+    }
+    /* alloy type (Sec. 6, Table 3) for FCC and BCC matches within cut-off */
+    if (species && o->type) {
+        int8_t me = species[i];
+        if (t == T_FCC) {
+            int cnt3[3] = {0, 0, 0};
+            for (int j = 0; j < 12; j++)
+                if (species[ids[W->c[j]]] != me) cnt3[j / 4]++;
+            for (int x = 0; x < 3; x++)
+                for (int y = 0; y < 2 - x; y++)
+                    if (cnt3[y] > cnt3[y + 1]) {
+                        int tmp = cnt3[y]; cnt3[y] = cnt3[y + 1]; cnt3[y + 1] = tmp;
+                    }
+            if (cnt3[0] == 0 && cnt3[1] == 0 && cnt3[2] == 0) o->alloy = 1;      /* A1 */
+            else if (cnt3[0] == 0 && cnt3[1] == 4 && cnt3[2] == 4) o->alloy = 2; /* L1_0 */
+            else if (cnt3[0] == 0 && cnt3[1] == 0 && cnt3[2] == 4) o->alloy = 3; /* L1_2 majority site */
+            else if (cnt3[0] == 4 && cnt3[1] == 4 && cnt3[2] == 4) o->alloy = 4; /* L1_2 minority site */
+            else o->alloy = 5;
+        } else if (t == T_BCC) {
+            int inner_other = 0, outer_other = 0;
+            for (int j = 0; j < 14; j++) {
+                int other = species[ids[W->c[j]]] != me;
+                if (j < 8) inner_other += other;
+                else outer_other += other;
+            }
+            if (inner_other == 0 && outer_other == 0) o->alloy = 6;       /* A2 */
+            else if (inner_other == 8 && outer_other == 0) o->alloy = 7;  /* B2 */
+            else o->alloy = 8;
+        }
+    }
+    free(cands);
+}
+
+/* ======================================================================== */
+/* exported entry points (ctypes)                                           */
+/* ======================================================================== */
+typedef struct {
+    const double *pos;
+    const int8_t *species;
+    const double *box;
+    int64_t n;
+    const int64_t *sel;
+    int64_t nsel;
+    uint32_t mask;
+    double cutoff;
+    int8_t *type, *alloy;
+    double *rmsd, *scale, *quat, *strain, *margin;
+    int32_t *nbr, *knn, *ncand;
+    int64_t lo, hi;
+    counters_t cnt;
+} job_t;
+
+static void *worker(void *arg) {
+    job_t *J = (job_t *)arg;
+    memset(&J->cnt, 0, sizeof J->cnt);
+    for (int64_t s = J->lo; s < J->hi; s++) {
+        int64_t i = J->sel ? J->sel[s] : s;
+        atom_out_t o;
+        classify_atom(J->pos, J->species, J->box, J->n, i, J->mask, J->cutoff, &o, &J->cnt);
+        J->type[s] = o.type;
+        if (J->alloy) J->alloy[s] = o.alloy;
+        J->rmsd[s] = o.rmsd;
+        J->scale[s] = o.scale;
+        memcpy(J->quat + 4 * s, o.quat, sizeof o.quat);
+        memcpy(J->strain + 9 * s, o.strain, sizeof o.strain);
+        memcpy(J->nbr + KMAX * s, o.nbr, sizeof o.nbr);
+        if (J->knn) memcpy(J->knn + KMAX * s, o.knn, sizeof o.knn);
+        if (J->margin) J->margin[s] = o.margin;
+        if (J->ncand) J->ncand[s] = o.ncand;
+    }
+    return NULL;
+}
+
+/* Classify the atoms listed in sel (or all n atoms when sel == NULL); output
+ * slot s belongs to atom sel[s].  Returns 0 on success.  counters (optional,
+ * 5 entries) receives hull, code, candidate, orientation-test and
+ * exact-fallback counts. */
+int ptm_oracle_classify(const double *pos, const int8_t *species, const double *box, int64_t n,
+                        uint32_t mask, double cutoff, const int64_t *sel, int64_t nsel, int nthreads,
+                        int8_t *type, int8_t *alloy, double *rmsd, double *scale, double *quat,
+                        int32_t *nbr, double *strain, int32_t *knn, double *margin, int32_t *ncand,
+                        int64_t *counters) {
+    if (!ensure_init()) return 1;
+    if (!sel) nsel = n;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    job_t jobs[256];
+    pthread_t th[256];
+    long o0 = g_cnt_orient, e0 = g_cnt_exact;
+    for (int t = 0; t < nthreads; t++) {
+        job_t *J = &jobs[t];
+        J->pos = pos; J->species = species; J->box = box; J->n = n;
+        J->sel = sel; J->nsel = nsel; J->mask = mask; J->cutoff = cutoff;
+        J->type = type; J->alloy = alloy; J->rmsd = rmsd; J->scale = scale; J->quat = quat;
+        J->strain = strain; J->margin = margin; J->nbr = nbr; J->knn = knn; J->ncand = ncand;
+        J->lo = nsel * t / nthreads;
+        J->hi = nsel * (t + 1) / nthreads;
+    }
+    for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, worker, &jobs[t]);
+    worker(&jobs[0]);
+    for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
+    if (counters) {
+        memset(counters, 0, sizeof(int64_t) * 5);
+        for (int t = 0; t < nthreads; t++) {
+            counters[0] += jobs[t].cnt.n_hull;
+            counters[1] += jobs[t].cnt.n_code;
+            counters[2] += jobs[t].cnt.n_cand;
+        }
+        counters[3] = g_cnt_orient - o0;
+        counters[4] = g_cnt_exact - e0;
+    }
+    return 0;
+}
+
+/* ---- narrow hooks used by the oracle's own pinning tests --------------- */
+int ptm_oracle_orient(const double *p12, const int *idx4, int use_sos) {
+    const double *q[4] = {p12, p12 + 3, p12 + 6, p12 + 9};
+    if (use_sos) return orient_sos(q, idx4);
+    return orient_exact(q[0], q[1], q[2], q[3]);
+}
+
+int ptm_oracle_det3(const double *p9) { return det3_exact(p9, p9 + 3, p9 + 6); }
+
+/* hull of k points: returns 1 if valid; tris receives 2k-4 outward
+ * counter-clockwise triangles.  When the hull is not valid (returns 0) the
+ * raw facet list is still written and *ntri set, for diagnosis. */
+int ptm_oracle_hull(int k, const double *pts, int *tris, int *ntri) {
+    if (k < 4 || k > KMAX) return -1;
+    const double(*q)[3] = (const double(*)[3])pts;
+    int nt = 0;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            for (int l = j + 1; l < k; l++) {
+                int ref = 0, ok = 1;
+                for (int m = 0; m < k && ok; m++) {
+                    if (m == i || m == j || m == l) continue;
+                    const double *P[4] = {q[i], q[j], q[l], q[m]};
+                    int id[4] = {i, j, l, m};
+                    int s = orient_sos(P, id);
+                    if (ref == 0) ref = s;
+                    else if (s != ref) ok = 0;
+                }
+                if (!ok || nt >= 4 * KMAX) continue;
+                tris[3 * nt] = i;
+                tris[3 * nt + 1] = ref < 0 ? j : l;
+                tris[3 * nt + 2] = ref < 0 ? l : j;
+                nt++;
+            }
+    *ntri = nt;
+    rotsys g;
+    return hull_all_triples(k, q, &g);
+}
+
+/* canonical walk code of a triangulated sphere given as outward
+ * counter-clockwise triangles; returns the number of automorphisms (start
+ * edges reaching the minimum) or -1 */
+int ptm_oracle_canonical(int k, const int *tris, int ntri, int *code, int *len, int *vlab_first) {
+    rotsys g;
+    if (!rotsys_from_tris(k, (const int(*)[3])tris, ntri, &g)) return -1;
+    canon_t cf;
+    if (!canonical(&g, &cf)) return -1;
+    memcpy(code, cf.code, sizeof(int) * cf.len);
+    *len = cf.len;
+    if (vlab_first)
+        for (int l = 1; l <= k; l++) vlab_first[l - 1] = cf.vlab[0][l];
+    return cf.naut;
+}
+
+/* template facts: k, group order, triangulations, orbits, coordinates,
+ * normalised points and the group (perm + rotation) */
+int ptm_oracle_template(int t, int *info4, double *w, double *b, int *gperm, double *grot,
+                        double *vpinv) {
+    if (!ensure_init() || t < 0 || t >= NTEMPL) return -1;
+    const templ_t *T = &g_T[t];
+    info4[0] = T->k;
+    info4[1] = T->ngroup;
+    info4[2] = T->ntri;
+    info4[3] = T->norbit;
+    if (w) memcpy(w, T->w, sizeof(double) * 3 * T->k);
+    if (b) memcpy(b, T->b, sizeof(double) * 3 * (T->k + 1));
+    if (gperm)
+        for (int g = 0; g < T->ngroup; g++) memcpy(gperm + g * T->k, T->gperm[g], sizeof(int) * T->k);
+    if (grot) memcpy(grot, T->grot, sizeof(double) * 9 * T->ngroup);
+    if (vpinv)
+        for (int r = 0; r < 3; r++) memcpy(vpinv + r * (T->k + 1), T->vpinv[r], sizeof(double) * (T->k + 1));
+    return 0;
+}
+
+/* canonical code of triangulation s of template t (for table checks) */
+int ptm_oracle_template_code(int t, int s, int *code, int *vlab) {
+    if (!ensure_init()) return -1;
+    const templ_t *T = &g_T[t];
+    if (s < 0 || s >= T->ntri) return -1;
+    memcpy(code, T->tri_code + (size_t)s * T->tri_len, sizeof(int) * T->tri_len);
+    if (vlab)
+        for (int l = 1; l <= T->k; l++) vlab[l - 1] = T->tri_vlab[(size_t)s * (T->k + 1) + l];
+    return T->tri_len;
+}
+
+/* eq.(3) for a fixed correspondence: a = observed N x 3 (not yet centred),
+ * b = template N x 3 (not yet normalised) */
+int ptm_oracle_superpose(int N, const double *obs, const double *tpl, double *rmsd, double *scale,
+                         double *q, double *lambda) {
+    if (N < 1 || N > NMAX) return -1;
+    double a[NMAX][3], bn[NMAX][3], c[3] = {0, 0, 0};
+    for (int i = 0; i < N; i++)
+        for (int d = 0; d < 3; d++) c[d] += obs[3 * i + d];
+    for (int d = 0; d < 3; d++) c[d] /= N;
+    for (int i = 0; i < N; i++)
+        for (int d = 0; d < 3; d++) a[i][d] = obs[3 * i + d] - c[d];
+    normalise_points(N, (const double(*)[3])tpl, bn);
+    superpose(N, (const double(*)[3])a, (const double(*)[3])bn, rmsd, scale, q, lambda);
+    return 0;
+}
+
+/* neighbour list of atom i (brute force) */
+int ptm_oracle_knn(const double *pos, int64_t n, const double *box, int64_t i, int K, int32_t *ids,
+                   double *rel, double *d2) {
+    if (K > KMAX + 1) return -1;
+    return knn_brute(pos, n, box, i, K > KMAX ? KMAX : K, ids, (double(*)[3])rel, d2);
+}
