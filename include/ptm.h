@@ -1,0 +1,159 @@
+/*
+ * ptm.h -- C ABI of the MI355X Polyhedral Template Matching library
+ * (libptm.so).  Method: Larsen, Schmidt & Schiotz, "Robust Structural
+ * Identification via Polyhedral Template Matching", arXiv:1603.05143.
+ *
+ * For every atom the library finds the nearest neighbours (Sec. 3, Euclidean
+ * ordering), builds the convex hull of the innermost 6, 12 and 14 neighbours
+ * (Sec. 4; Alg. 1 requires the central atom strictly inside), reduces the
+ * hull to its orientation-preserving canonical form (Sec. 4), looks it up
+ * against the SC, FCC, HCP, ICO and BCC templates (Table 1, App. A) and
+ * minimises the scale-invariant RMSD of eqs. (3)-(4) over the candidate
+ * correspondences (Alg. 1).  It returns type, RMSD, scale, orientation,
+ * ordered neighbours, the elastic strain of eq. (6) / Sec. 8 and the alloy
+ * class of Sec. 6 / Table 3.
+ *
+ * Conventions
+ *  - Status codes only; no exception crosses this boundary.  On an error no
+ *    output is written (outputs may be partially written only by
+ *    PTM_E_DEVICE, after which their contents are unspecified).
+ *  - Pointers are device pointers (HIP, same device as the context) unless
+ *    the context was created with PTM_F_HOST_POINTERS.  The caller owns
+ *    all input and output buffers; they must stay valid until the call (or
+ *    ticket) completes.  The context owns its tables and scratch memory.
+ *  - Real outputs are float64 in both precision forms.
+ *  - One context per host thread.  Calls on one context are serialised on
+ *    its stream.
+ */
+#ifndef PTM_H
+#define PTM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptm_ctx ptm_ctx; /* opaque: device tables, scratch, stream */
+
+typedef enum {
+    PTM_OK = 0,
+    PTM_E_INVALID = 1,   /* bad argument: NULL pointer, n < 0, bad box, NaN/Inf coordinate */
+    PTM_E_NOMEM = 2,     /* device allocation failed or HBM budget exceeded */
+    PTM_E_DEVICE = 3,    /* HIP runtime error (message in ptm_last_error) */
+    PTM_E_BOX = 4,       /* reserved: box unusable for the neighbour search */
+    PTM_E_TOO_LARGE = 5, /* n > PTM_MAX_ATOMS */
+    PTM_E_BUSY = 6,      /* serving queue full */
+    PTM_E_TIMEOUT = 7    /* ptm_wait timed out; the ticket stays valid */
+} ptm_status;
+
+#define PTM_MAX_ATOMS 2147483646LL /* atom ids are int32 */
+
+typedef enum {
+    PTM_FP64 = 0,      /* every floating-point step in FP64 */
+    PTM_FP32_MIXED = 1 /* FP32 where an error bound proves the decision; FP64 otherwise */
+} ptm_precision;
+
+/* template_mask bits (Table 1 templates) */
+enum { PTM_SC = 1u << 0, PTM_FCC = 1u << 1, PTM_HCP = 1u << 2, PTM_ICO = 1u << 3, PTM_BCC = 1u << 4,
+       PTM_ALL = 0x1Fu };
+
+/* structure type output */
+enum { PTM_TYPE_NONE = 0, PTM_TYPE_SC = 1, PTM_TYPE_FCC = 2, PTM_TYPE_HCP = 3, PTM_TYPE_ICO = 4,
+       PTM_TYPE_BCC = 5 };
+
+/* alloy output (Sec. 6, Table 3; species-agnostic: "same as / other than the
+ * central atom") */
+enum { PTM_ALLOY_NONE = 0, PTM_ALLOY_A1 = 1, PTM_ALLOY_L10 = 2, PTM_ALLOY_L12_MAJ = 3,
+       PTM_ALLOY_L12_MIN = 4, PTM_ALLOY_FCC_OTHER = 5, PTM_ALLOY_A2 = 6, PTM_ALLOY_B2 = 7,
+       PTM_ALLOY_BCC_OTHER = 8 };
+
+/* context flags */
+enum { PTM_F_HOST_POINTERS = 1u << 0 };
+
+typedef struct {
+    int device;                /* HIP device ordinal */
+    ptm_precision precision;   /* PTM_FP64 or PTM_FP32_MIXED */
+    void *hip_stream;          /* hipStream_t to run on; NULL = the context's own stream */
+    uint64_t hbm_budget_bytes; /* cap on scratch + in-flight frames; 0 = no cap */
+    uint32_t flags;            /* PTM_F_* */
+} ptm_config;
+
+/* Per-atom outputs, n entries each (arrays with a second dimension are
+ * row-major [n][m]).  Every pointer except type may be NULL to skip it. */
+typedef struct {
+    int8_t *type;        /* PTM_TYPE_*: best template if its RMSD <= rmsd_cutoff, else NONE      */
+    int8_t *alloy;       /* PTM_ALLOY_*; NONE when species == NULL or type not FCC/BCC            */
+    double *rmsd;        /* minimum eq.(3) RMSD over enabled templates; +inf if no candidate        */
+    double *scale;       /* optimal s of eq.(3) (1/length); 0 if no candidate                      */
+    double *quat;        /* [n][4] (w,x,y,z) of the rotation template -> sample, w >= 0; (1,0,0,0)
+                            if no candidate                                                          */
+    int32_t *neighbours; /* [n][14] atom ids in template-vertex order; -1 past k or if no candidate */
+    double *strain;      /* [n][9] symmetric P of the left polar decomposition A = P U of eq.(6)   */
+    int32_t *knn;        /* [n][14] atom ids in Euclidean order (Sec. 3); -1 past the last neighbour */
+} ptm_outputs;
+
+/* Frame statistics returned by ptm_wait. */
+typedef struct {
+    double submit_time_us;   /* host clock at ptm_submit */
+    double start_time_us;    /* host clock when the frame's work was enqueued on the device */
+    double complete_time_us; /* host clock when completion was observed */
+    int64_t n_atoms;
+} ptm_frame_stats;
+
+/* Create a context on cfg->device: builds the template tables (all
+ * triangulations, canonical codes, rotation groups; Sec. 4, App. A) and
+ * uploads them.  *out receives the context, or NULL on error.
+ * Errors: PTM_E_INVALID (NULL arguments, bad precision), PTM_E_DEVICE (no
+ * such device / HIP failure), PTM_E_NOMEM. */
+ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out);
+
+/* Classify n_atoms atoms of one frame (Alg. 1 for every atom).
+ *   positions  [n][3] float64, any values; periodic axes are wrapped.
+ *   species    [n] int8 or NULL (alloy output then NONE).
+ *   box        host pointer to 3 doubles: > 0 periodic length of an
+ *              orthorhombic box along that axis, 0 open.  Negative, NaN or
+ *              Inf -> PTM_E_INVALID.
+ *   template_mask  PTM_* bits of the templates to consider (0 allowed).
+ *   rmsd_cutoff    keep the type iff RMSD <= cutoff (+inf = no cut-off,
+ *                  Sec. 5.1); must not be NaN.
+ * Stream-ordered on the context's stream; synchronises before returning.
+ * Errors: PTM_E_INVALID, PTM_E_TOO_LARGE, PTM_E_NOMEM, PTM_E_DEVICE.
+ * n_atoms == 0 returns PTM_OK without touching the device. */
+ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *species,
+                        const double *box, int64_t n_atoms, uint32_t template_mask,
+                        double rmsd_cutoff, const ptm_outputs *out);
+
+/* Serving: enqueue one frame without waiting (continuous batching: frames
+ * are admitted while the HBM budget allows, their work overlaps on the
+ * device).  Arguments as ptm_classify; buffers must stay valid until
+ * ptm_wait returns PTM_OK for the ticket.  Errors: as ptm_classify, plus
+ * PTM_E_BUSY when the budget cannot admit the frame now (retry after a
+ * ptm_wait). */
+ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *species,
+                      const double *box, int64_t n_atoms, uint32_t template_mask,
+                      double rmsd_cutoff, const ptm_outputs *out, uint64_t *ticket);
+
+/* Wait for a ticket (timeout_us < 0: forever; 0: poll).  PTM_E_TIMEOUT if
+ * not yet complete; PTM_E_INVALID for an unknown ticket.  stats may be NULL. */
+ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame_stats *stats);
+
+/* Destroy a context (waits for in-flight tickets).  NULL is a no-op. */
+void ptm_destroy(ptm_ctx *ctx);
+
+/* Static description of a status code. */
+const char *ptm_status_string(ptm_status s);
+
+/* Last error message of a context (empty string if none; never NULL). */
+const char *ptm_last_error(const ptm_ctx *ctx);
+
+/* Template facts of the library's own tables, for checks without a device:
+ * info[0]=k, info[1]=rotation group order, info[2]=triangulations,
+ * info[3]=distinct canonical codes, info[4]=candidates kept after symmetry
+ * reduction (App. A).  Returns PTM_E_INVALID for t outside 0..4. */
+ptm_status ptm_template_info(int t, int64_t info[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTM_H */

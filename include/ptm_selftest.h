@@ -1,0 +1,41 @@
+/*
+ * ptm_selftest.h -- self-check entry points of libptm.so.
+ *
+ * They run the library's own device arithmetic compiled for the host, so the
+ * exact orientation predicate with Simulation of Simplicity (used for the
+ * hull of Sec. 4 of arXiv:1603.05143) and the library's canonical code can
+ * be checked on a machine without a GPU.  They are not part of the
+ * classification path.  All pointers are host pointers.
+ */
+#ifndef PTM_SELFTEST_H
+#define PTM_SELFTEST_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sign (+1/-1) of det[b-a; c-a; d-a] for the rows a,b,c,d of p12[4][3],
+ * exact, with Simulation of Simplicity by the four distinct ranks (the
+ * lowest rank is perturbed most).  Returns 0 only if ranks are not distinct. */
+int ptm_selftest_orient(const double *p12, const int32_t *ranks4);
+
+/* Exact sign (-1/0/+1) of det[a; b; c] for the rows of p9[3][3]. */
+int ptm_selftest_det3(const double *p9);
+
+/* Canonical code of a triangulated sphere with k <= 14 vertices given as
+ * ntri outward counter-clockwise triangles (int32 [ntri][3]).  rows[k]
+ * receives the code, *n_auto the number of labellings reaching it.
+ * Returns 0 on success, -1 if the triangles are not a closed oriented
+ * triangulation. */
+int ptm_selftest_canonical(int k, const int32_t *tris, int ntri, uint64_t *rows, int32_t *n_auto);
+
+/* Eq. (3) superposition for a fixed correspondence with the library's QCP
+ * solver: obs and tpl are [N][3] (N <= 15, not centred / not normalised).
+ * Writes rmsd, scale and the quaternion (w,x,y,z) rotating the template
+ * onto the observation.  Returns 0, or -1 for N out of range. */
+int ptm_selftest_superpose(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,455 @@
+// ptm_api.hip -- C ABI of the PTM library (declared in include/ptm.h).
+//
+// A context owns the device copy of the template tables, one stream and the
+// scratch of the synchronous path; ptm_classify validates the arguments,
+// sizes the cell grid from the frame's density, runs the kernel pipeline
+// and synchronises.  ptm_submit / ptm_wait run frames on a pool of streams
+// with per-frame scratch, admitted against the HBM budget (see
+// ptm_serve.hip).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "../../include/ptm.h"
+#include "ptm_internal.hpp"
+#include "ptm_kernels.hpp"
+#include "ptm_tables.hpp"
+
+using namespace ptm;
+
+namespace ptm {
+
+// ------------------------------------------------------------ scratch
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
+    size_t b = 0;
+    b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
+    b += align_up(4 * (size_t)(cells + 1)) * 2;  // count, start
+    b += align_up(8 * (size_t)n) * 3;         // sorted positions
+    b += align_up(4 * (size_t)n * KMAX);      // neighbour ids
+    b += align_up(8 * (size_t)n * KMAX * 3);  // neighbour vectors
+    b += align_up(4 * (size_t)n * NGRP);      // code ids
+    b += align_up(8 * (size_t)n * NGRP);      // labellings
+    b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
+    b += align_up(scan_tmp);
+    return b;
+}
+
+bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
+    int nb = bounds_blocks(n);
+    size_t scan_tmp = 0;
+    if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
+                                         (int)(cells + 1)) != hipSuccess) {
+        err = "hipcub scan size query failed";
+        return false;
+    }
+    size_t need = frame_bytes(n, cells, nb, scan_tmp);
+    if (need > bytes) {
+        if (base) (void)hipFree(base);
+        base = nullptr;
+        bytes = 0;
+        if (hipMalloc(&base, need) != hipSuccess) {
+            (void)hipGetLastError();
+            err = "device allocation of " + std::to_string(need) + " bytes failed";
+            return false;
+        }
+        bytes = need;
+    }
+    char *p = (char *)base;
+    auto take = [&](size_t sz) {
+        char *r = p;
+        p += align_up(sz);
+        return (void *)r;
+    };
+    cell_of = (int32_t *)take(4 * (size_t)n);
+    slot_of = (int32_t *)take(4 * (size_t)n);
+    sid = (int32_t *)take(4 * (size_t)n);
+    count = (int32_t *)take(4 * (size_t)(cells + 1));
+    start = (int32_t *)take(4 * (size_t)(cells + 1));
+    sx = (double *)take(8 * (size_t)n);
+    sy = (double *)take(8 * (size_t)n);
+    sz = (double *)take(8 * (size_t)n);
+    nbr_id = (int32_t *)take(4 * (size_t)n * KMAX);
+    nbr_rel = (double *)take(8 * (size_t)n * KMAX * 3);
+    code = (int32_t *)take(4 * (size_t)n * NGRP);
+    ord = (uint64_t *)take(8 * (size_t)n * NGRP);
+    part = (double *)take(8 * 7 * (size_t)nb);
+    scan_tmp_ptr = take(scan_tmp);
+    scan_tmp_bytes = scan_tmp;
+    return true;
+}
+
+void FrameScratch::release() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    bytes = 0;
+}
+
+int bounds_blocks(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// Choose the cell grid: cell edge close to the expected distance of the
+// 15th neighbour so that the 27-cell block usually certifies the 14
+// nearest; at least 3 cells on periodic axes.
+Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n) {
+    Grid g;
+    double ext[3], vol = 1.0;
+    int flat = 0;
+    for (int a = 0; a < 3; a++) {
+        g.periodic[a] = box[a] > 0;
+        ext[a] = g.periodic[a] ? box[a] : std::fmax(mx[a] - mn[a], 0.0);
+        if (ext[a] > 0) vol *= ext[a];
+        else flat++;
+    }
+    double h;
+    if (flat == 0 && vol > 0) {
+        double rho = (double)n / vol;
+        h = std::cbrt(15.0 / (4.1887902047863905 * rho));
+    } else {
+        h = 1.0;
+        for (int a = 0; a < 3; a++) h = std::fmax(h, ext[a] / 16.0);
+    }
+    for (int iter = 0; iter < 200; iter++) {
+        double cells = 1;
+        for (int a = 0; a < 3; a++) {
+            int nc;
+            if (g.periodic[a]) nc = (int)std::fmin(std::floor(ext[a] / h), 1 << 20);
+            else nc = ext[a] > 0 ? (int)std::fmin(std::floor(ext[a] / h), 1 << 20) : 1;
+            if (g.periodic[a] && nc < 3) nc = 3;
+            if (nc < 1) nc = 1;
+            g.nc[a] = nc;
+            cells *= nc;
+        }
+        if (cells <= (double)(1 << 30) && cells <= 4.0 * (double)n + 4096.0) break;
+        h *= 1.25;
+    }
+    double hmax = 0;
+    for (int a = 0; a < 3; a++) {
+        if (g.periodic[a]) {
+            g.L[a] = box[a];
+            g.invL[a] = 1.0 / box[a];
+            g.lo[a] = 0.0;
+            g.h[a] = box[a] / g.nc[a];
+            g.inv_h[a] = g.nc[a] / box[a];
+        } else {
+            g.L[a] = 0.0;
+            g.invL[a] = 0.0;
+            g.lo[a] = mn[a];
+            g.h[a] = ext[a] > 0 ? ext[a] / g.nc[a] : 1.0;
+            g.inv_h[a] = ext[a] > 0 ? g.nc[a] / ext[a] : 1.0;
+        }
+        hmax = std::fmax(hmax, g.h[a]);
+    }
+    g.margin = 1e-9 * hmax;
+    return g;
+}
+
+// Enqueue the whole pipeline for one frame whose bounds are known.
+ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st) {
+    const int64_t n = J.n;
+    const Grid &g = J.grid;
+    int64_t cells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 1), st));
+    launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
+    size_t tmp = S.scan_tmp_bytes;
+    PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
+    launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.sx, S.sy, S.sz, S.sid, st);
+    launch_knn(n, g, J.pos, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, st);
+    const uint32_t m = J.mask;
+    const bool need[NGRP] = {(m & 0x1u) != 0, (m & 0xEu) != 0, (m & 0x10u) != 0};
+    for (int grp = 0; grp < NGRP; grp++) {
+        if (need[grp])
+            launch_topo(group_k(grp), n, S.nbr_rel, S.nbr_id, ctx->view, S.code + (int64_t)grp * n,
+                        S.ord + (int64_t)grp * n, st);
+        else
+            PTM_HIP(ctx, hipMemsetAsync(S.code + (int64_t)grp * n, 0xFF, 4 * (size_t)n, st));
+    }
+    MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
+    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, st);
+    PTM_HIP(ctx, hipGetLastError());
+    return PTM_OK;
+}
+
+// Bounds of the frame: finite check and per-axis extent (synchronous on st).
+ptm_status frame_bounds(ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_t n, double mn[3], double mx[3],
+                        bool &bad, hipStream_t st) {
+    int nb = bounds_blocks(n);
+    launch_bounds(pos, n, S.part, nb, st);
+    PTM_HIP(ctx, hipGetLastError());
+    std::vector<double> h((size_t)nb * 7);
+    PTM_HIP(ctx, hipMemcpyAsync(h.data(), S.part, h.size() * 8, hipMemcpyDeviceToHost, st));
+    PTM_HIP(ctx, hipStreamSynchronize(st));
+    bad = false;
+    for (int a = 0; a < 3; a++) {
+        mn[a] = 1e308;
+        mx[a] = -1e308;
+    }
+    for (int b = 0; b < nb; b++) {
+        for (int a = 0; a < 3; a++) {
+            mn[a] = std::fmin(mn[a], h[7 * b + a]);
+            mx[a] = std::fmax(mx[a], h[7 * b + 3 + a]);
+        }
+        if (h[7 * b + 6] != 0.0) bad = true;
+    }
+    return PTM_OK;
+}
+
+ptm_status validate(ptm_ctx *ctx, const double *positions, const double *box, int64_t n, double cutoff,
+                    const ptm_outputs *out) {
+    if (!ctx) return PTM_E_INVALID;
+    if (!box || !out || (n > 0 && !out->type)) {
+        ctx->err = "box, out and (for n > 0) out->type must not be NULL";
+        return PTM_E_INVALID;
+    }
+    if (n < 0) {
+        ctx->err = "n_atoms < 0";
+        return PTM_E_INVALID;
+    }
+    if (n > PTM_MAX_ATOMS) {
+        ctx->err = "n_atoms exceeds PTM_MAX_ATOMS";
+        return PTM_E_TOO_LARGE;
+    }
+    if (n > 0 && !positions) {
+        ctx->err = "positions must not be NULL";
+        return PTM_E_INVALID;
+    }
+    for (int a = 0; a < 3; a++)
+        if (!(box[a] >= 0.0) || std::isinf(box[a])) {
+            ctx->err = "box lengths must be finite and >= 0";
+            return PTM_E_INVALID;
+        }
+    if (std::isnan(cutoff)) {
+        ctx->err = "rmsd_cutoff is NaN";
+        return PTM_E_INVALID;
+    }
+    return PTM_OK;
+}
+
+}  // namespace ptm
+
+// ============================================================== C ABI
+extern "C" {
+
+const char *ptm_status_string(ptm_status s) {
+    switch (s) {
+        case PTM_OK: return "ok";
+        case PTM_E_INVALID: return "invalid argument";
+        case PTM_E_NOMEM: return "out of device memory or HBM budget";
+        case PTM_E_DEVICE: return "HIP runtime error";
+        case PTM_E_BOX: return "box unusable for the neighbour search";
+        case PTM_E_TOO_LARGE: return "too many atoms";
+        case PTM_E_BUSY: return "serving queue full";
+        case PTM_E_TIMEOUT: return "timed out";
+    }
+    return "unknown status";
+}
+
+const char *ptm_last_error(const ptm_ctx *ctx) {
+    if (!ctx) return "";
+    return ctx->err.c_str();
+}
+
+ptm_status ptm_template_info(int t, int64_t info[5]) {
+    if (t < 0 || t >= NT || !info) return PTM_E_INVALID;
+    static std::once_flag once;
+    static HostTables *T = nullptr;
+    static bool ok = false;
+    std::call_once(once, [] {
+        T = new (std::nothrow) HostTables();
+        std::string err;
+        ok = T && build_tables(*T, err);
+    });
+    if (!ok) return PTM_E_NOMEM;
+    info[0] = T->tpl[t].k;
+    info[1] = T->tpl[t].ngroup;
+    info[2] = T->ntri[t];
+    info[3] = T->ncodes_t[t];
+    info[4] = T->ncand_kept[t];
+    return PTM_OK;
+}
+
+ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
+    if (!cfg || !out) return PTM_E_INVALID;
+    *out = nullptr;
+    if (cfg->precision != PTM_FP64 && cfg->precision != PTM_FP32_MIXED) return PTM_E_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
+        (void)hipGetLastError();
+        return PTM_E_DEVICE;
+    }
+    ptm_ctx *ctx = new (std::nothrow) ptm_ctx();
+    if (!ctx) return PTM_E_NOMEM;
+    ctx->device = cfg->device;
+    ctx->precision = cfg->precision;
+    ctx->budget = cfg->hbm_budget_bytes;
+    ctx->flags = cfg->flags;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        delete ctx;
+        return PTM_E_DEVICE;
+    }
+    if (cfg->hip_stream) {
+        ctx->stream = (hipStream_t)cfg->hip_stream;
+        ctx->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return PTM_E_DEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    std::string err;
+    if (!build_tables(ctx->host, err)) {
+        ptm_destroy(ctx);
+        return PTM_E_NOMEM;
+    }
+    ptm_status st = upload_tables(ctx);
+    if (st != PTM_OK) {
+        ptm_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return PTM_OK;
+}
+
+void ptm_destroy(ptm_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    serve_shutdown(ctx);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    ctx->main.release();
+    ctx->staging.release();
+    for (void *p : ctx->table_buffers) (void)hipFree(p);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *species, const double *box,
+                        int64_t n_atoms, uint32_t template_mask, double rmsd_cutoff, const ptm_outputs *out) {
+    ptm_status st = validate(ctx, positions, box, n_atoms, rmsd_cutoff, out);
+    if (st != PTM_OK) return st;
+    ctx->err.clear();
+    if (n_atoms == 0) return PTM_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        ctx->err = "hipSetDevice failed";
+        return PTM_E_DEVICE;
+    }
+    FrameJob J;
+    J.n = n_atoms;
+    J.mask = template_mask & PTM_ALL;
+    J.cutoff = rmsd_cutoff;
+    HostStage H;
+    st = stage_in(ctx, positions, species, out, n_atoms, J, H);
+    if (st != PTM_OK) return st;
+    // bounds first (needs scratch for the partials): reserve with a tiny grid
+    if (!ctx->main.reserve(n_atoms, 1, ctx->err)) return PTM_E_NOMEM;
+    double mn[3], mx[3];
+    bool bad = false;
+    st = frame_bounds(ctx, ctx->main, J.pos, n_atoms, mn, mx, bad, ctx->stream);
+    if (st != PTM_OK) return st;
+    if (bad) {
+        ctx->err = "non-finite coordinate";
+        return PTM_E_INVALID;
+    }
+    J.grid = make_grid(box, mn, mx, n_atoms);
+    int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
+    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0) > ctx->budget) {
+        ctx->err = "frame scratch exceeds the HBM budget";
+        return PTM_E_NOMEM;
+    }
+    if (!ctx->main.reserve(n_atoms, cells, ctx->err)) return PTM_E_NOMEM;
+    st = enqueue_frame(ctx, ctx->main, J, ctx->stream);
+    if (st != PTM_OK) return st;
+    st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
+    if (st != PTM_OK) return st;
+    PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PTM_OK;
+}
+
+}  // extern "C"
+
+// ======================================================= self-check entry points
+#include "../../include/ptm_selftest.h"
+#include "ptm_device.hpp"
+
+extern "C" {
+
+int ptm_selftest_orient(const double *p, const int32_t *r) {
+    if (r[0] == r[1] || r[0] == r[2] || r[0] == r[3] || r[1] == r[2] || r[1] == r[3] || r[2] == r[3]) return 0;
+    return orient_sos64(p, p + 3, p + 6, p + 9, r[0], r[1], r[2], r[3]);
+}
+
+int ptm_selftest_det3(const double *p) { return det3_sign64(p, p + 3, p + 6); }
+
+int ptm_selftest_canonical(int k, const int32_t *tris, int ntri, uint64_t *rows, int32_t *n_auto) {
+    if (k < 4 || k > KMAX || ntri != 2 * k - 4) return -1;
+    uint64_t nxt[KMAX];
+    int deg[KMAX] = {0};
+    for (int x = 0; x < k; x++) nxt[x] = ~0ull;
+    for (int t = 0; t < ntri; t++)
+        for (int e = 0; e < 3; e++) {
+            int a = tris[3 * t + e], b = tris[3 * t + (e + 1) % 3], c = tris[3 * t + (e + 2) % 3];
+            if (a < 0 || a >= k || b < 0 || b >= k || c < 0 || c >= k) return -1;
+            if (((nxt[a] >> (4 * b)) & 0xF) != 0xF) return -1;
+            nxt[a] &= ~(0xFull << (4 * b));
+            nxt[a] |= (uint64_t)c << (4 * b);
+            deg[a]++;
+        }
+    std::vector<uint64_t> labs;
+    *n_auto = canonical_code_host(k, nxt, deg, rows, labs);
+    return 0;
+}
+
+int ptm_selftest_superpose(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q) {
+    if (N < 1 || N > NMAX) return -1;
+    double a[NMAX][3], b[NMAX][3], ca[3] = {0, 0, 0}, cb[3] = {0, 0, 0};
+    for (int i = 0; i < N; i++)
+        for (int d = 0; d < 3; d++) {
+            ca[d] += obs[3 * i + d] / N;
+            cb[d] += tpl[3 * i + d] / N;
+        }
+    double lb = 0, Ga = 0, Gb = 0;
+    for (int i = 0; i < N; i++) {
+        double s = 0;
+        for (int d = 0; d < 3; d++) {
+            a[i][d] = obs[3 * i + d] - ca[d];
+            b[i][d] = tpl[3 * i + d] - cb[d];
+            s += b[i][d] * b[i][d];
+        }
+        lb += sqrt(s);
+    }
+    lb /= N;
+    double S[3][3] = {{0}};
+    for (int i = 0; i < N; i++) {
+        for (int d = 0; d < 3; d++) b[i][d] /= lb;
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) S[x][y] += b[i][x] * a[i][y];
+        for (int d = 0; d < 3; d++) {
+            Ga += a[i][d] * a[i][d];
+            Gb += b[i][d] * b[i][d];
+        }
+    }
+    double lam = qcp_solve(S, Ga, Gb, q);
+    double s = Ga > 0 ? lam / Ga : 0.0, R[3][3], res = 0;
+    quat_rot(q, R);
+    for (int i = 0; i < N; i++)
+        for (int x = 0; x < 3; x++) {
+            double d = s * a[i][x] - (R[x][0] * b[i][0] + R[x][1] * b[i][1] + R[x][2] * b[i][2]);
+            res += d * d;
+        }
+    *rmsd = sqrt(res / N);
+    *scale = s;
+    return 0;
+}
+
+}  // extern "C"

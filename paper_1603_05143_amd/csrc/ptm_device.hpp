@@ -1,0 +1,362 @@
+// ptm_device.hpp -- device arithmetic of the HIP path (also compiled for
+// the host so the self-check entry points can exercise it without a GPU).
+//
+//  * orientation predicates with an FP64 (or FP32) error-bounded filter and
+//    an exact fallback on floating-point expansions (error-free sums and
+//    products, Dekker/Knuth; expansion growth after Shewchuk 1997), plus
+//    Simulation of Simplicity (Edelsbrunner & Muecke 1990) for exact zeros
+//    -- the hull of Sec. 4 is thereby a function of the input alone;
+//  * the QCP solve of the superposition of eqs. (2)-(4) (Theobald 2005; Liu
+//    et al. 2010): characteristic polynomial of Horn's 4x4 matrix, Newton
+//    from an upper bound, eigenvector from the adjugate;
+//  * cyclic Jacobi for 3x3 symmetric matrices (square root of A A^T, Sec. 8).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptm {
+
+#define PTM_HD __host__ __device__ inline
+
+// ------------------------------------------------------------------ exact
+struct Expansion {
+    int n;
+    double c[112];
+};
+
+PTM_HD void exact_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bv = s - a;
+    double av = s - bv;
+    e = (a - av) + (b - bv);
+}
+
+PTM_HD void exact_prod(double a, double b, double &p, double &e) {
+    p = a * b;
+    e = fma(a, b, -p);
+}
+
+// x += b exactly; zero components dropped
+PTM_HD void exp_grow(Expansion &x, double b) {
+    double q = b;
+    int m = 0;
+    for (int i = 0; i < x.n; i++) {
+        double s, h;
+        exact_sum(q, x.c[i], s, h);
+        q = s;
+        if (h != 0.0) x.c[m++] = h;
+    }
+    if (q != 0.0) x.c[m++] = q;
+    x.n = m;
+}
+
+PTM_HD int exp_sign(const Expansion &x) {
+    for (int i = x.n - 1; i >= 0; i--)
+        if (x.c[i] != 0.0) return x.c[i] > 0.0 ? 1 : -1;
+    return 0;
+}
+
+// x += sgn * a*b*c exactly
+PTM_HD void exp_add_prod3(Expansion &x, double a, double b, double c, double sgn) {
+    double p, e;
+    exact_prod(a, b, p, e);
+    double p1, e1, p2, e2;
+    exact_prod(p, c, p1, e1);
+    exact_prod(e, c, p2, e2);
+    exp_grow(x, sgn * p1);
+    exp_grow(x, sgn * e1);
+    exp_grow(x, sgn * p2);
+    exp_grow(x, sgn * e2);
+}
+
+PTM_HD void exp_add_prod2(Expansion &x, double a, double b, double sgn) {
+    double p, e;
+    exact_prod(a, b, p, e);
+    exp_grow(x, sgn * p);
+    exp_grow(x, sgn * e);
+}
+
+// x += sgn * det[p; q; r] (rows, raw coordinates) exactly
+PTM_HD void exp_add_det3(Expansion &x, const double *p, const double *q, const double *r, double sgn) {
+    exp_add_prod3(x, p[0], q[1], r[2], sgn);
+    exp_add_prod3(x, p[0], q[2], r[1], -sgn);
+    exp_add_prod3(x, p[1], q[0], r[2], -sgn);
+    exp_add_prod3(x, p[1], q[2], r[0], sgn);
+    exp_add_prod3(x, p[2], q[0], r[1], sgn);
+    exp_add_prod3(x, p[2], q[1], r[0], -sgn);
+}
+
+// Sign of det of the 4x4 matrix with rows (p_i, 1): Laplace expansion along
+// the constant column, each 3x3 minor evaluated exactly.
+#ifdef __HIP_DEVICE_COMPILE__
+__attribute__((noinline))
+#endif
+__host__ __device__ inline int lambda4_sign_exact(const double *a, const double *b, const double *c, const double *d) {
+    Expansion x;
+    x.n = 0;
+    exp_add_det3(x, b, c, d, -1.0);
+    exp_add_det3(x, a, c, d, 1.0);
+    exp_add_det3(x, a, b, d, -1.0);
+    exp_add_det3(x, a, b, c, 1.0);
+    return exp_sign(x);
+}
+
+// exact sign of det[[p_i, p_j, 1], [q_i, q_j, 1], [r_i, r_j, 1]] on coordinates (i, j)
+#ifdef __HIP_DEVICE_COMPILE__
+__attribute__((noinline))
+#endif
+__host__ __device__ inline int orient2_sign_exact(const double *p, const double *q, const double *r, int i, int j) {
+    Expansion x;
+    x.n = 0;
+    exp_add_prod2(x, p[i], q[j], 1.0);
+    exp_add_prod2(x, p[j], q[i], -1.0);
+    exp_add_prod2(x, p[i], r[j], -1.0);
+    exp_add_prod2(x, p[j], r[i], 1.0);
+    exp_add_prod2(x, q[i], r[j], 1.0);
+    exp_add_prod2(x, q[j], r[i], -1.0);
+    return exp_sign(x);
+}
+
+PTM_HD int sgn_diff(double a, double b) { return a > b ? 1 : (a < b ? -1 : 0); }
+
+// Simulation of Simplicity for the 4x4 orientation determinant.  Rows sorted
+// by increasing rank r0 < r1 < r2 < r3; rank r's coordinate j is perturbed by
+// eps^(2^(3r+2-j)) (j = 0,1,2 for x,y,z), so the lowest rank moves most and z
+// before y before x.  The perturbed determinant is a polynomial in eps whose
+// coefficients are signed minors; in order of decreasing size the
+// non-vanishing candidates are listed below as (sign, minor).  Returns the
+// sign of det L_sorted(eps).
+#ifdef __HIP_DEVICE_COMPILE__
+__attribute__((noinline))
+#endif
+__host__ __device__ inline int sos_lambda4_sorted(const double *p0, const double *p1, const double *p2,
+                                           const double *p3) {
+    int s;
+    // eps(r0,z): +det[x y 1] of rows 1,2,3
+    if ((s = orient2_sign_exact(p1, p2, p3, 0, 1))) return s;
+    // eps(r0,y): -det[x z 1] of rows 1,2,3
+    if ((s = orient2_sign_exact(p1, p2, p3, 0, 2))) return -s;
+    // eps(r0,x): +det[y z 1] of rows 1,2,3
+    if ((s = orient2_sign_exact(p1, p2, p3, 1, 2))) return s;
+    // eps(r1,z): -det[x y 1] of rows 0,2,3
+    if ((s = orient2_sign_exact(p0, p2, p3, 0, 1))) return -s;
+    // eps(r0,y) eps(r1,z): +(x2 - x3)
+    if ((s = sgn_diff(p2[0], p3[0]))) return s;
+    // eps(r0,x) eps(r1,z): -(y2 - y3)
+    if ((s = sgn_diff(p2[1], p3[1]))) return -s;
+    // eps(r1,y): +det[x z 1] of rows 0,2,3
+    if ((s = orient2_sign_exact(p0, p2, p3, 0, 2))) return s;
+    // eps(r0,z) eps(r1,y): -(x2 - x3)
+    if ((s = sgn_diff(p2[0], p3[0]))) return -s;
+    // eps(r0,x) eps(r1,y): +(z2 - z3)
+    if ((s = sgn_diff(p2[2], p3[2]))) return s;
+    // eps(r1,x): -det[y z 1] of rows 0,2,3
+    if ((s = orient2_sign_exact(p0, p2, p3, 1, 2))) return -s;
+    // eps(r0,z) eps(r1,x): +(y2 - y3)
+    if ((s = sgn_diff(p2[1], p3[1]))) return s;
+    // eps(r0,y) eps(r1,x): -(z2 - z3)
+    if ((s = sgn_diff(p2[2], p3[2]))) return -s;
+    // eps(r2,z): +det[x y 1] of rows 0,1,3
+    if ((s = orient2_sign_exact(p0, p1, p3, 0, 1))) return s;
+    // eps(r0,y) eps(r2,z): -(x1 - x3)
+    if ((s = sgn_diff(p1[0], p3[0]))) return -s;
+    // eps(r0,x) eps(r2,z): +(y1 - y3)
+    if ((s = sgn_diff(p1[1], p3[1]))) return s;
+    // eps(r1,y) eps(r2,z): +(x0 - x3)
+    if ((s = sgn_diff(p0[0], p3[0]))) return s;
+    // eps(r0,x) eps(r1,y) eps(r2,z): +1
+    return 1;
+}
+
+// orientation of (a,b,c,d) := det[b-a; c-a; d-a] (> 0: d on the side the
+// normal (b-a)x(c-a) points to), exactly, with SoS by the ranks ra..rd
+PTM_HD int orient_exact_sos(const double *a, const double *b, const double *c, const double *d, int ra,
+                            int rb, int rc, int rd) {
+    int s = lambda4_sign_exact(a, b, c, d);
+    if (s) return -s;
+    const double *p[4] = {a, b, c, d};
+    int r[4] = {ra, rb, rc, rd};
+    int parity = 1;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3 - i; j++)
+            if (r[j] > r[j + 1]) {
+                int tr = r[j]; r[j] = r[j + 1]; r[j + 1] = tr;
+                const double *tp = p[j]; p[j] = p[j + 1]; p[j + 1] = tp;
+                parity = -parity;
+            }
+    return -parity * sos_lambda4_sorted(p[0], p[1], p[2], p[3]);
+}
+
+// Semi-static filter for det[b-a; c-a; d-a] in FP64 with exact inputs.
+// Returns the sign, or 0 when the error bound does not decide it.  The
+// evaluation uses differences against d (det[a-d; b-d; c-d] = -orient) and
+// the bound 10 u x permanent (u = 2^-53) covers the 3 input differences, 2 products,
+// 1 subtraction, 1 product and 2 additions of each term.
+PTM_HD int orient_filter64(const double *a, const double *b, const double *c, const double *d) {
+    double adx = a[0] - d[0], ady = a[1] - d[1], adz = a[2] - d[2];
+    double bdx = b[0] - d[0], bdy = b[1] - d[1], bdz = b[2] - d[2];
+    double cdx = c[0] - d[0], cdy = c[1] - d[1], cdz = c[2] - d[2];
+    double m1 = bdx * cdy, m2 = cdx * bdy;
+    double m3 = cdx * ady, m4 = adx * cdy;
+    double m5 = adx * bdy, m6 = bdx * ady;
+    double det = adz * (m1 - m2) + bdz * (m3 - m4) + cdz * (m5 - m6);
+    double perm = (fabs(m1) + fabs(m2)) * fabs(adz) + (fabs(m3) + fabs(m4)) * fabs(bdz) +
+                  (fabs(m5) + fabs(m6)) * fabs(cdz);
+    double bound = 1.1102230246251565e-15 * perm;  // 10 unit roundoffs of perm
+    if (det > bound) return -1;
+    if (det < -bound) return 1;
+    return 0;
+}
+
+// det[a; b; c] (raw coordinates) filter; 0 if undecided
+PTM_HD int det3_filter64(const double *a, const double *b, const double *c) {
+    double m1 = b[1] * c[2], m2 = b[2] * c[1];
+    double m3 = b[2] * c[0], m4 = b[0] * c[2];
+    double m5 = b[0] * c[1], m6 = b[1] * c[0];
+    double det = a[0] * (m1 - m2) + a[1] * (m3 - m4) + a[2] * (m5 - m6);
+    double perm = fabs(a[0]) * (fabs(m1) + fabs(m2)) + fabs(a[1]) * (fabs(m3) + fabs(m4)) +
+                  fabs(a[2]) * (fabs(m5) + fabs(m6));
+    double bound = 8.8817841970012523e-16 * perm;  // 8 unit roundoffs
+    if (det > bound) return 1;
+    if (det < -bound) return -1;
+    return 0;
+}
+
+#ifdef __HIP_DEVICE_COMPILE__
+__attribute__((noinline))
+#endif
+__host__ __device__ inline int det3_sign_exact(const double *a, const double *b, const double *c) {
+    Expansion x;
+    x.n = 0;
+    exp_add_det3(x, a, b, c, 1.0);
+    return exp_sign(x);
+}
+
+PTM_HD int orient_sos64(const double *a, const double *b, const double *c, const double *d, int ra, int rb,
+                        int rc, int rd) {
+    int s = orient_filter64(a, b, c, d);
+    if (s) return s;
+    return orient_exact_sos(a, b, c, d, ra, rb, rc, rd);
+}
+
+PTM_HD int det3_sign64(const double *a, const double *b, const double *c) {
+    int s = det3_filter64(a, b, c);
+    if (s) return s;
+    return det3_sign_exact(a, b, c);
+}
+
+// ------------------------------------------------------------------- QCP
+// Largest eigenvalue and eigenvector of Horn's matrix for S_xy = sum b_x a_y
+// (template b, observation a); q (w,x,y,z) rotates b onto a.  Ga, Gb are the
+// inner products of the two sets (upper bound sqrt(Ga Gb) on lambda).
+PTM_HD double qcp_solve(const double S[3][3], double Ga, double Gb, double q[4]) {
+    const double Sxx = S[0][0], Sxy = S[0][1], Sxz = S[0][2];
+    const double Syx = S[1][0], Syy = S[1][1], Syz = S[1][2];
+    const double Szx = S[2][0], Szy = S[2][1], Szz = S[2][2];
+    double K[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+                      {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
+                      {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
+                      {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+    // characteristic polynomial lambda^4 + c2 lambda^2 + c1 lambda + c0
+    double ss = 0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) ss += S[i][j] * S[i][j];
+    double c2 = -2.0 * ss;
+    double detS = Sxx * (Syy * Szz - Syz * Szy) - Sxy * (Syx * Szz - Syz * Szx) + Sxz * (Syx * Szy - Syy * Szx);
+    double c1 = -8.0 * detS;
+    // c0 = det K by complementary 2x2 minors of rows (0,1) and (2,3)
+    double s01 = K[0][0] * K[1][1] - K[0][1] * K[1][0], s02 = K[0][0] * K[1][2] - K[0][2] * K[1][0];
+    double s03 = K[0][0] * K[1][3] - K[0][3] * K[1][0], s12 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+    double s13 = K[0][1] * K[1][3] - K[0][3] * K[1][1], s23 = K[0][2] * K[1][3] - K[0][3] * K[1][2];
+    double t01 = K[2][0] * K[3][1] - K[2][1] * K[3][0], t02 = K[2][0] * K[3][2] - K[2][2] * K[3][0];
+    double t03 = K[2][0] * K[3][3] - K[2][3] * K[3][0], t12 = K[2][1] * K[3][2] - K[2][2] * K[3][1];
+    double t13 = K[2][1] * K[3][3] - K[2][3] * K[3][1], t23 = K[2][2] * K[3][3] - K[2][3] * K[3][2];
+    double c0 = s01 * t23 - s02 * t13 + s03 * t12 + s12 * t03 - s13 * t02 + s23 * t01;
+    double lam = sqrt(Ga * Gb);
+    for (int it = 0; it < 60; it++) {
+        double l2 = lam * lam;
+        double f = (l2 + c2) * l2 + c1 * lam + c0;
+        double fp = 4.0 * l2 * lam + 2.0 * c2 * lam + c1;
+        if (fp == 0.0) break;
+        double step = f / fp;
+        lam -= step;
+        if (fabs(step) <= 1e-15 * fabs(lam) + 1e-300) break;
+    }
+    // eigenvector: the adjugate column of (K - lam I) with the largest norm
+    double A[4][4];
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) A[i][j] = K[i][j] - (i == j ? lam : 0.0);
+    double best = -1.0;
+    q[0] = 1; q[1] = q[2] = q[3] = 0;
+    for (int col = 0; col < 4; col++) {
+        // cofactors C_{col,i} = (-1)^{col+i} det(A without row col, col i)
+        double v[4];
+        for (int i = 0; i < 4; i++) {
+            int r[3], c[3], nr = 0, nc = 0;
+            for (int t = 0; t < 4; t++) {
+                if (t != col) r[nr++] = t;
+                if (t != i) c[nc++] = t;
+            }
+            double m = A[r[0]][c[0]] * (A[r[1]][c[1]] * A[r[2]][c[2]] - A[r[1]][c[2]] * A[r[2]][c[1]]) -
+                       A[r[0]][c[1]] * (A[r[1]][c[0]] * A[r[2]][c[2]] - A[r[1]][c[2]] * A[r[2]][c[0]]) +
+                       A[r[0]][c[2]] * (A[r[1]][c[0]] * A[r[2]][c[1]] - A[r[1]][c[1]] * A[r[2]][c[0]]);
+            v[i] = ((col + i) & 1) ? -m : m;
+        }
+        double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+        if (n2 > best) {
+            best = n2;
+            double inv = n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
+            for (int i = 0; i < 4; i++) q[i] = v[i] * inv;
+        }
+    }
+    if (!(best > 0)) { q[0] = 1; q[1] = q[2] = q[3] = 0; }
+    return lam;
+}
+
+PTM_HD void quat_rot(const double q[4], double R[3][3]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z);     R[0][2] = 2 * (x * z + w * y);
+    R[1][0] = 2 * (x * y + w * z);     R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+    R[2][0] = 2 * (x * z - w * y);     R[2][1] = 2 * (y * z + w * x);     R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+// cyclic Jacobi for a symmetric 3x3 matrix; returns eigenvalues in d and
+// eigenvectors in the columns of V
+PTM_HD void jacobi3(double A[3][3], double d[3], double V[3][3]) {
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 12; sweep++) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        double dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off <= 1e-36 * dg) break;
+        for (int p = 0; p < 2; p++)
+            for (int r = p + 1; r < 3; r++) {
+                double apr = A[p][r];
+                if (apr == 0.0) continue;
+                double h = A[r][r] - A[p][p];
+                double t;
+                double th = 0.5 * h / apr;
+                t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
+                if (th < 0) t = -t;
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int m = 0; m < 3; m++) {
+                    double amp = A[m][p], amr = A[m][r];
+                    A[m][p] = c * amp - s * amr;
+                    A[m][r] = s * amp + c * amr;
+                }
+                for (int m = 0; m < 3; m++) {
+                    double apm = A[p][m], arm = A[r][m];
+                    A[p][m] = c * apm - s * arm;
+                    A[r][m] = s * apm + c * arm;
+                }
+                for (int m = 0; m < 3; m++) {
+                    double vmp = V[m][p], vmr = V[m][r];
+                    V[m][p] = c * vmp - s * vmr;
+                    V[m][r] = s * vmp + c * vmr;
+                }
+            }
+    }
+    d[0] = A[0][0]; d[1] = A[1][1]; d[2] = A[2][2];
+}
+
+}  // namespace ptm

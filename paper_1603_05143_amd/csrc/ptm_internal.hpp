@@ -1,0 +1,128 @@
+// ptm_internal.hpp -- context and per-frame state shared by the ABI sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ptm.h"
+#include "ptm_kernels.hpp"
+#include "ptm_tables.hpp"
+
+#define PTM_HIP(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+            return PTM_E_DEVICE;                                                            \
+        }                                                                                   \
+    } while (0)
+
+namespace ptm {
+
+// Device scratch of one frame (one allocation, carved into arrays).
+struct FrameScratch {
+    void *base = nullptr;
+    size_t bytes = 0;
+    int32_t *cell_of = nullptr, *slot_of = nullptr, *sid = nullptr, *count = nullptr, *start = nullptr;
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    int32_t *nbr_id = nullptr;
+    double *nbr_rel = nullptr;
+    int32_t *code = nullptr;
+    uint64_t *ord = nullptr;
+    double *part = nullptr;
+    void *scan_tmp_ptr = nullptr;
+    size_t scan_tmp_bytes = 0;
+    bool reserve(int64_t n, int64_t cells, std::string &err);
+    void release();
+};
+
+// Staging buffers for host-pointer contexts.
+struct StagingBuffers {
+    void *base = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (base) (void)hipFree(base);
+        base = nullptr;
+        bytes = 0;
+    }
+};
+
+// Everything a frame's kernels need (device pointers).
+struct FrameJob {
+    int64_t n = 0;
+    const double *pos = nullptr;
+    const int8_t *species = nullptr;
+    uint32_t mask = 0;
+    double cutoff = 0;
+    Grid grid;
+    ptm_outputs out;  // device pointers
+};
+
+// Host pointers to copy back to when the context uses host pointers.
+struct HostStage {
+    bool active = false;
+    ptm_outputs host_out;
+};
+
+struct Ticket {
+    FrameScratch scratch;
+    StagingBuffers staging;
+    HostStage stage;
+    FrameJob job;
+    hipEvent_t done = nullptr;
+    int stream = 0;
+    size_t footprint = 0;
+    double t_submit = 0, t_start = 0, t_complete = 0;
+    bool complete = false;
+};
+
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp);
+int bounds_blocks(int64_t n);
+Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n);
+ptm_status enqueue_frame(struct ::ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st);
+ptm_status frame_bounds(struct ::ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_t n, double mn[3],
+                        double mx[3], bool &bad, hipStream_t st);
+ptm_status validate(struct ::ptm_ctx *ctx, const double *positions, const double *box, int64_t n, double cutoff,
+                    const ptm_outputs *out);
+ptm_status upload_tables(struct ::ptm_ctx *ctx);
+ptm_status stage_in(struct ::ptm_ctx *ctx, const double *positions, const int8_t *species, const ptm_outputs *out,
+                    int64_t n, FrameJob &J, HostStage &H);
+ptm_status stage_in_buffers(struct ::ptm_ctx *ctx, StagingBuffers &B, const double *positions,
+                            const int8_t *species, const ptm_outputs *out, int64_t n, FrameJob &J, HostStage &H,
+                            hipStream_t st);
+ptm_status stage_out(struct ::ptm_ctx *ctx, const ptm_outputs *out, int64_t n, const FrameJob &J, const HostStage &H,
+                     hipStream_t st);
+void serve_shutdown(struct ::ptm_ctx *ctx);
+
+inline double now_us() {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace ptm
+
+struct ptm_ctx {
+    int device = 0;
+    ptm_precision precision = PTM_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    uint32_t flags = 0;
+    ptm::HostTables host;
+    std::vector<void *> table_buffers;
+    ptm::TablesView view;
+    ptm::FrameScratch main;
+    ptm::StagingBuffers staging;
+    std::string err;
+    // serving state
+    std::vector<hipStream_t> serve_streams;
+    hipStream_t bounds_stream = nullptr;
+    std::map<uint64_t, ptm::Ticket *> tickets;
+    std::vector<ptm::FrameScratch> free_scratch;
+    uint64_t next_ticket = 1;
+    size_t inflight_bytes = 0;
+    int next_stream = 0;
+};

@@ -1,0 +1,843 @@
+// ptm_kernels.hip -- HIP kernels of the PTM classification pass for gfx950.
+//
+// Pipeline for one frame (Polyhedral Template Matching, arXiv:1603.05143):
+//   k_bounds      finite check + bounding box (open axes)
+//   k_bin_count   cell id + per-cell counter (counting sort, pass 1)
+//   (scan)        exclusive prefix sum of the counters
+//   k_bin_scatter sorted SoA copy of the positions (counting sort, pass 2)
+//   k_knn         14 nearest neighbours by (d^2, id), Sec. 3 Euclidean order
+//   k_topo<K>     hull of the innermost K = 6 / 12 / 14 neighbours with
+//                 exact predicates (Sec. 4; Alg. 1 requires the centre
+//                 strictly inside), canonical code, template table lookup
+//   k_match       superposition over the candidates (eqs. 2-4), decision
+//                 (Alg. 1), representative, strain (eq. 6, Sec. 8), alloy
+//                 (Sec. 6, Table 3), write-back in input order
+// One lane owns one atom in every per-atom kernel; atoms are processed in
+// cell order so the lanes of a wave read the same cells.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ptm_device.hpp"
+#include "ptm_kernels.hpp"
+#include "ptm_tables.hpp"
+
+namespace ptm {
+
+// --------------------------------------------------------------- helpers
+__device__ inline uint32_t nib(uint64_t w, int i) { return (uint32_t)((w >> (4 * i)) & 0xF); }
+__device__ inline uint64_t setnib(uint64_t w, int i, uint32_t v) {
+    return (w & ~(0xFull << (4 * i))) | ((uint64_t)v << (4 * i));
+}
+
+__device__ inline int cell_coord(double x, const Grid &g, int d) {
+    double u;
+    if (g.periodic[d]) {
+        u = x - g.L[d] * floor(x * g.invL[d]);
+    } else {
+        u = x - g.lo[d];
+    }
+    double f = floor(u * g.inv_h[d]);
+    int c = (f < 0.0) ? 0 : (f >= (double)(g.nc[d] - 1) ? g.nc[d] - 1 : (int)f);
+    return c;
+}
+
+__device__ inline double wrapped(double x, const Grid &g, int d) {
+    return g.periodic[d] ? x - g.L[d] * floor(x * g.invL[d]) : x - g.lo[d];
+}
+
+// ------------------------------------------------------------------ bounds
+// Per-block min/max of each axis and a non-finite flag.
+__global__ void k_bounds(const double *__restrict__ pos, int64_t n, double *__restrict__ part) {
+    __shared__ double smin[3][256], smax[3][256];
+    __shared__ int sbad[256];
+    double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 3; d++) {
+            double x = pos[3 * i + d];
+            if (!isfinite(x)) bad = 1;
+            mn[d] = fmin(mn[d], x);
+            mx[d] = fmax(mx[d], x);
+        }
+    }
+    int t = threadIdx.x;
+    for (int d = 0; d < 3; d++) { smin[d][t] = mn[d]; smax[d][t] = mx[d]; }
+    sbad[t] = bad;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            for (int d = 0; d < 3; d++) {
+                smin[d][t] = fmin(smin[d][t], smin[d][t + s]);
+                smax[d][t] = fmax(smax[d][t], smax[d][t + s]);
+            }
+            sbad[t] |= sbad[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double *o = part + 7 * blockIdx.x;
+        for (int d = 0; d < 3; d++) { o[d] = smin[d][0]; o[3 + d] = smax[d][0]; }
+        o[6] = (double)sbad[0];
+    }
+}
+
+// ----------------------------------------------------------------- binning
+__global__ void k_bin_count(const double *__restrict__ pos, int64_t n, Grid g, int32_t *__restrict__ cell_of,
+                            int32_t *__restrict__ slot_of, int32_t *__restrict__ count) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(pos[3 * i + 0], g, 0);
+    int cy = cell_coord(pos[3 * i + 1], g, 1);
+    int cz = cell_coord(pos[3 * i + 2], g, 2);
+    int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+    cell_of[i] = c;
+    slot_of[i] = atomicAdd(&count[c], 1);
+}
+
+__global__ void k_bin_scatter(const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ cell_of,
+                              const int32_t *__restrict__ slot_of, const int32_t *__restrict__ start,
+                              double *__restrict__ sx, double *__restrict__ sy, double *__restrict__ sz,
+                              int32_t *__restrict__ sid) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t p = (int64_t)start[cell_of[i]] + slot_of[i];
+    sx[p] = pos[3 * i + 0];
+    sy[p] = pos[3 * i + 1];
+    sz[p] = pos[3 * i + 2];
+    sid[p] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------- k-NN
+// Minimum-image difference exactly as specified: s = rint(d * (1/L)),
+// d - s*L, without contraction (the library is built with
+// -ffp-contract=off), so d^2 matches the reference bit for bit.
+__device__ inline double min_image(double d, const Grid &g, int a) {
+    if (g.periodic[a]) {
+        double s = rint(d * g.invL[a]);
+        d = d - s * g.L[a];
+    }
+    return d;
+}
+
+// insert (d2, j) into the ascending list (kd, kj) of length KN
+template <int KN>
+__device__ inline void topk_insert(double (&kd)[KN], int32_t (&kj)[KN], double d2, int32_t j) {
+    bool done = false;
+#pragma unroll
+    for (int m = KN - 1; m > 0; m--) {
+        bool lt = !done && (d2 < kd[m - 1] || (d2 == kd[m - 1] && j < kj[m - 1]));
+        if (!done) {
+            kd[m] = lt ? kd[m - 1] : d2;
+            kj[m] = lt ? kj[m - 1] : j;
+        }
+        done = done || !lt;
+    }
+    if (!done) {
+        kd[0] = d2;
+        kj[0] = j;
+    }
+}
+
+__device__ inline void shell_range(const Grid &g, int a, int s, int &lo, int &hi) {
+    if (g.periodic[a]) {
+        int half = (g.nc[a] - 1) / 2;
+        lo = -min(s, half);
+        hi = min(s, g.nc[a] - 1 - half);
+    } else {
+        lo = -s;
+        hi = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const double *__restrict__ pos,
+                                             const double *__restrict__ sx, const double *__restrict__ sy,
+                                             const double *__restrict__ sz, const int32_t *__restrict__ sid,
+                                             const int32_t *__restrict__ start, int32_t *__restrict__ nbr_id,
+                                             double *__restrict__ nbr_rel, int32_t *__restrict__ knn_out) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    constexpr int KN = KMAX;
+    const double xi = sx[p], yi = sy[p], zi = sz[p];
+    const int32_t i = sid[p];
+    const double xs[3] = {xi, yi, zi};
+    int cc[3];
+    double u[3];
+    for (int a = 0; a < 3; a++) {
+        cc[a] = cell_coord(xs[a], g, a);
+        u[a] = wrapped(xs[a], g, a);
+    }
+    double kd[KN];
+    int32_t kj[KN];
+#pragma unroll
+    for (int m = 0; m < KN; m++) { kd[m] = INFINITY; kj[m] = 0x7fffffff; }
+    int found = 0;
+    int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};  // previous (empty) block
+    for (int s = 1;; s++) {
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; a++) shell_range(g, a, s, lo[a], hi[a]);
+        for (int oz = lo[2]; oz <= hi[2]; oz++) {
+            int cz = cc[2] + oz;
+            if (g.periodic[2]) cz = (cz % g.nc[2] + g.nc[2]) % g.nc[2];
+            else if (cz < 0 || cz >= g.nc[2]) continue;
+            for (int oy = lo[1]; oy <= hi[1]; oy++) {
+                int cy = cc[1] + oy;
+                if (g.periodic[1]) cy = (cy % g.nc[1] + g.nc[1]) % g.nc[1];
+                else if (cy < 0 || cy >= g.nc[1]) continue;
+                for (int ox = lo[0]; ox <= hi[0]; ox++) {
+                    bool inner = ox >= plo[0] && ox <= phi[0] && oy >= plo[1] && oy <= phi[1] &&
+                                 oz >= plo[2] && oz <= phi[2];
+                    if (inner) continue;
+                    int cx = cc[0] + ox;
+                    if (g.periodic[0]) cx = (cx % g.nc[0] + g.nc[0]) % g.nc[0];
+                    else if (cx < 0 || cx >= g.nc[0]) continue;
+                    int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+                    int q1 = start[c + 1];
+                    for (int q = start[c]; q < q1; q++) {
+                        int32_t j = sid[q];
+                        if (j == i) continue;
+                        double dx = min_image(sx[q] - xi, g, 0);
+                        double dy = min_image(sy[q] - yi, g, 1);
+                        double dz = min_image(sz[q] - zi, g, 2);
+                        double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                        double d2 = (xx + yy) + zz;
+                        found++;
+                        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, d2, j);
+                    }
+                }
+            }
+        }
+        // certification: distance from the atom to the unsearched region
+        double dmin = INFINITY;
+        bool all = true;
+        for (int a = 0; a < 3; a++) {
+            bool sat_lo, sat_hi;
+            if (g.periodic[a]) {
+                sat_lo = sat_hi = (hi[a] - lo[a] + 1) >= g.nc[a];
+            } else {
+                sat_lo = cc[a] + lo[a] <= 0;
+                sat_hi = cc[a] + hi[a] >= g.nc[a] - 1;
+            }
+            if (!sat_lo) dmin = fmin(dmin, u[a] - (cc[a] + lo[a]) * g.h[a]);
+            if (!sat_hi) dmin = fmin(dmin, (cc[a] + hi[a] + 1) * g.h[a] - u[a]);
+            all = all && sat_lo && sat_hi;
+            plo[a] = lo[a];
+            phi[a] = hi[a];
+        }
+        if (all) break;
+        dmin -= g.margin;
+        if (found >= KN && dmin > 0 && kd[KN - 1] < dmin * dmin) break;
+    }
+    int cnt = found < KN ? found : KN;
+#pragma unroll
+    for (int m = 0; m < KN; m++) {
+        int32_t j = (m < cnt) ? kj[m] : -1;
+        nbr_id[(int64_t)m * n + p] = j;
+        double r0 = 0, r1 = 0, r2 = 0;
+        if (j >= 0) {
+            r0 = min_image(pos[3 * (int64_t)j + 0] - xi, g, 0);
+            r1 = min_image(pos[3 * (int64_t)j + 1] - yi, g, 1);
+            r2 = min_image(pos[3 * (int64_t)j + 2] - zi, g, 2);
+        }
+        nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
+        nbr_rel[((int64_t)m * 3 + 1) * n + p] = r1;
+        nbr_rel[((int64_t)m * 3 + 2) * n + p] = r2;
+        if (knn_out) knn_out[(int64_t)i * KN + m] = j;
+    }
+}
+
+// --------------------------------------------------------------- topology
+// Incremental convex hull (every point must become a vertex and stay one),
+// facets with neighbour links, then the rotation system and the canonical
+// code.  Per-lane state lives in LDS, lane-minor, so dynamic indices never
+// conflict across lanes.
+constexpr int TB = 64;  // threads per block of the topology kernel
+
+template <int K>
+struct TopoShared {
+    double P[3][K][TB];
+    uint32_t F[2 * K - 4][TB];
+    uint16_t H[K][TB];
+    uint64_t NT[K][TB];
+};
+
+// facet word: v0 | v1<<4 | v2<<8 | nb0<<12 | nb1<<17 | nb2<<22
+__device__ inline uint32_t fpack(int a, int b, int c, int n0, int n1, int n2) {
+    return (uint32_t)a | ((uint32_t)b << 4) | ((uint32_t)c << 8) | ((uint32_t)n0 << 12) | ((uint32_t)n1 << 17) |
+           ((uint32_t)n2 << 22);
+}
+__device__ inline int fv(uint32_t f, int e) { return (f >> (4 * e)) & 0xF; }
+__device__ inline int fn(uint32_t f, int e) { return (f >> (12 + 5 * e)) & 0x1F; }
+__device__ inline uint32_t fset_nb(uint32_t f, int e, int g) {
+    int sh = 12 + 5 * e;
+    return (f & ~(0x1Fu << sh)) | ((uint32_t)g << sh);
+}
+
+template <int K>
+__device__ inline int lane_orient(TopoShared<K> &S, int t, int a, int b, int c, int d) {
+    double pa[3], pb[3], pc[3], pd[3];
+    for (int k = 0; k < 3; k++) {
+        pa[k] = S.P[k][a][t];
+        pb[k] = S.P[k][b][t];
+        pc[k] = S.P[k][c][t];
+        pd[k] = S.P[k][d][t];
+    }
+    return orient_sos64(pa, pb, pc, pd, a, b, c, d);
+}
+
+// returns 1 if the hull is valid (all K points vertices, centre strictly
+// inside); the facets are left in S.F[0 .. 2K-5]
+template <int K>
+__device__ int lane_hull(TopoShared<K> &S, int t) {
+    int a = 0, b = 1, c = 2, d = 3;
+    if (lane_orient<K>(S, t, 0, 1, 2, 3) > 0) { b = 2; c = 1; }
+    S.F[0][t] = fpack(a, b, c, 1, 2, 3);
+    S.F[1][t] = fpack(b, a, d, 0, 3, 2);
+    S.F[2][t] = fpack(c, b, d, 0, 1, 3);
+    S.F[3][t] = fpack(a, c, d, 0, 2, 1);
+    int nf = 4;
+    for (int p = 4; p < K; p++) {
+        uint32_t vis = 0;
+        int nvis = 0;
+        for (int f = 0; f < nf; f++) {
+            uint32_t w = S.F[f][t];
+            if (lane_orient<K>(S, t, fv(w, 0), fv(w, 1), fv(w, 2), p) > 0) {
+                vis |= 1u << f;
+                nvis++;
+            }
+        }
+        if (nvis == 0) return 0;  // p inside: never a vertex
+        // horizon edges (a -> b) of visible facets whose neighbour is not visible
+        int nh = 0;
+        for (int f = 0; f < nf; f++) {
+            if (!((vis >> f) & 1)) continue;
+            uint32_t w = S.F[f][t];
+            for (int e = 0; e < 3; e++) {
+                int g = fn(w, e);
+                if (g >= nf) return 0;  // broken link (cannot happen with exact predicates)
+                if ((vis >> g) & 1) continue;
+                if (nh >= K) return 0;
+                S.H[nh][t] = (uint16_t)(fv(w, e) | (fv(w, (e + 1) % 3) << 4) | (g << 8));
+                nh++;
+            }
+        }
+        // a horizon of nvis+2 edges <=> no earlier vertex is swallowed
+        if (nh != nvis + 2) return 0;
+        // slots: freed visible facets first (increasing), then two new ones;
+        // pass 1 records vertex -> slot maps, pass 2 builds the facets
+        uint64_t start_lo = 0, start_hi = 0, end_lo = 0, end_hi = 0;  // 8-bit fields
+        uint32_t freed = vis;
+        int nf_new = nf;
+        for (int h = 0; h < nh; h++) {
+            int s;
+            if (freed) {
+                s = __builtin_ctz(freed);
+                freed &= freed - 1;
+            } else {
+                s = nf_new++;
+            }
+            uint32_t hw = S.H[h][t];
+            int ha = hw & 0xF, hb = (hw >> 4) & 0xF;
+            if (ha < 8) start_lo |= (uint64_t)s << (8 * ha); else start_hi |= (uint64_t)s << (8 * (ha - 8));
+            if (hb < 8) end_lo |= (uint64_t)s << (8 * hb); else end_hi |= (uint64_t)s << (8 * (hb - 8));
+        }
+        freed = vis;
+        int nf2 = nf;
+        for (int h = 0; h < nh; h++) {
+            int s;
+            if (freed) {
+                s = __builtin_ctz(freed);
+                freed &= freed - 1;
+            } else {
+                s = nf2++;
+            }
+            uint32_t hw = S.H[h][t];
+            int ha = hw & 0xF, hb = (hw >> 4) & 0xF, g = (hw >> 8) & 0x1F;
+            int s_next = (int)(((hb < 8 ? start_lo >> (8 * hb) : start_hi >> (8 * (hb - 8)))) & 0xFF);
+            int s_prev = (int)(((ha < 8 ? end_lo >> (8 * ha) : end_hi >> (8 * (ha - 8)))) & 0xFF);
+            S.F[s][t] = fpack(ha, hb, p, g, s_next, s_prev);
+            uint32_t gw = S.F[g][t];
+            for (int e = 0; e < 3; e++)
+                if (fv(gw, e) == hb && fv(gw, (e + 1) % 3) == ha) gw = fset_nb(gw, e, s);
+            S.F[g][t] = gw;
+        }
+        nf = nf_new;
+    }
+    // centre strictly inside every facet: det[a; b; c] > 0 exactly
+    for (int f = 0; f < 2 * K - 4; f++) {
+        uint32_t w = S.F[f][t];
+        double pa[3], pb[3], pc[3];
+        for (int k = 0; k < 3; k++) {
+            pa[k] = S.P[k][fv(w, 0)][t];
+            pb[k] = S.P[k][fv(w, 1)][t];
+            pc[k] = S.P[k][fv(w, 2)][t];
+        }
+        if (det3_sign64(pa, pb, pc) <= 0) return 0;
+    }
+    return 1;
+}
+
+// canonical code (see ptm_tables.cpp for the definition); best[] receives the
+// K rows, the return value the labelling (nibble l = vertex of label l)
+template <int K>
+__device__ uint64_t lane_canonical(TopoShared<K> &S, int t, uint64_t degs, uint64_t (&best)[K]) {
+    int mindeg = 15;
+    for (int x = 0; x < K; x++) mindeg = min(mindeg, (int)nib(degs, x));
+    bool have = false;
+    uint64_t best_ord = 0;
+    for (int u = 0; u < K; u++) {
+        if ((int)nib(degs, u) != mindeg) continue;
+        uint64_t ntu = S.NT[u][t];
+        for (int v = 0; v < K; v++) {
+            if (nib(ntu, v) == 0xF) continue;
+            uint64_t lab = ~0ull, ord = 0, par = 0;
+            lab = setnib(lab, u, 0);
+            lab = setnib(lab, v, 1);
+            ord = (uint64_t)u | ((uint64_t)v << 4);
+            par = setnib(par, v, u);
+            uint32_t nl = 2;
+            int state = have ? 0 : -1;  // 0 equal so far, -1 smaller, +1 larger
+#pragma unroll
+            for (int i = 0; i < K; i++) {
+                if (state <= 0) {
+                    int x = min((int)nib(ord, i), K - 1);
+                    int y = (i == 0) ? v : (int)nib(par, x);
+                    uint64_t ntx = S.NT[x][t];
+                    int dx = (int)nib(degs, x);
+                    uint64_t row = (uint64_t)dx << 60;
+                    for (int j = 0; j < dx; j++) {
+                        uint32_t ly = nib(lab, y);
+                        if (ly == 0xF) {
+                            ly = nl;
+                            lab = setnib(lab, y, nl);
+                            ord = setnib(ord, nl, y);
+                            par = setnib(par, y, x);
+                            nl++;
+                        }
+                        row |= (uint64_t)ly << (56 - 4 * j);
+                        y = min((int)nib(ntx, y), K - 1);
+                    }
+                    if (state == 0) state = (row < best[i]) ? -1 : (row > best[i] ? 1 : 0);
+                    if (state < 0) best[i] = row;
+                }
+            }
+            if (state < 0) {
+                best_ord = ord;
+                have = true;
+            }
+        }
+    }
+    return best_ord;
+}
+
+template <int K>
+__global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
+                                              const int32_t *__restrict__ nbr_id, TablesView T,
+                                              int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
+    __shared__ TopoShared<K> S;
+    const int t = threadIdx.x;
+    const int64_t p = blockIdx.x * (int64_t)TB + t;
+    if (p >= n) return;
+    constexpr int grp = (K == 6) ? 0 : (K == 12 ? 1 : 2);
+    int32_t cid = -1;
+    uint64_t ordw = 0;
+    if (nbr_id[(int64_t)(K - 1) * n + p] >= 0) {
+        for (int r = 0; r < K; r++)
+            for (int d = 0; d < 3; d++) S.P[d][r][t] = nbr_rel[((int64_t)r * 3 + d) * n + p];
+        if (lane_hull<K>(S, t)) {
+            for (int x = 0; x < K; x++) S.NT[x][t] = ~0ull;
+            uint64_t degs = 0;
+            for (int f = 0; f < 2 * K - 4; f++) {
+                uint32_t w = S.F[f][t];
+                int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
+                S.NT[a][t] = setnib(S.NT[a][t], b, c);
+                S.NT[b][t] = setnib(S.NT[b][t], c, a);
+                S.NT[c][t] = setnib(S.NT[c][t], a, b);
+                degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
+            }
+            uint64_t best[K];
+#pragma unroll
+            for (int i = 0; i < K; i++) best[i] = ~0ull;
+            uint64_t ord = lane_canonical<K>(S, t, degs, best);
+            // table lookup with full-code verification
+            uint64_t h = code_hash(best, K);
+            int mask = T.hmask[grp];
+            int s = (int)(h & (uint64_t)mask);
+            for (int probe = 0; probe <= mask; probe++) {
+                int c = T.slots[grp][s];
+                if (c < 0) break;
+                const uint64_t *cw = T.codes[grp] + (int64_t)c * K;
+                bool eq = true;
+#pragma unroll
+                for (int i = 0; i < K; i++) eq = eq && (cw[i] == best[i]);
+                if (eq) {
+                    cid = c;
+                    ordw = ord;
+                    break;
+                }
+                s = (s + 1) & mask;
+            }
+        }
+    }
+    code_out[p] = cid;
+    ord_out[p] = ordw;
+}
+
+// ------------------------------------------------------------------ match
+constexpr int MB = 128;  // threads per block of the match kernel
+
+struct MatchShared {
+    TemplateDev tpl[NT];
+};
+
+// rank vector of the representative: min over g of (c(g^-1(m)))_m, packed
+// with m = 0 in the most significant nibble
+__device__ inline uint64_t rep_vector(const TemplateDev &D, uint64_t cmap, int &gbest) {
+    uint64_t best = ~0ull;
+    gbest = 0;
+    for (int g = 0; g < D.ngroup; g++) {
+        uint64_t gi = D.ginv[g];
+        uint64_t v = 0;
+        for (int m = 0; m < D.k; m++) v |= (uint64_t)nib(cmap, (int)nib(gi, m)) << (4 * (15 - m));
+        if (v < best) {
+            best = v;
+            gbest = g;
+        }
+    }
+    return best;
+}
+
+struct CandEval {
+    double r, s, q[4];
+};
+
+// eq.(3) for one candidate: observed rank r <-> template vertex tv(r)
+template <int K>
+__device__ inline void eval_candidate(const double (&a)[NMAX][3], double Ga, const TemplateDev &D, uint64_t tv_of_rank,
+                                      CandEval &out) {
+    double S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double Gb = 0;
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) S[x][y] += D.b[0][x] * a[0][y];
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+        const double *bb = D.b[nib(tv_of_rank, r) + 1];
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[r + 1][y];
+    }
+    for (int i = 0; i <= K; i++) Gb += D.b[i][0] * D.b[i][0] + D.b[i][1] * D.b[i][1] + D.b[i][2] * D.b[i][2];
+    double lam = qcp_solve(S, Ga, Gb, out.q);
+    double s = Ga > 0 ? lam / Ga : 0.0;
+    double R[3][3];
+    quat_rot(out.q, R);
+    double res = 0;
+    {
+        const double *bb = D.b[0];
+        for (int x = 0; x < 3; x++) {
+            double d = s * a[0][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
+            res += d * d;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+        const double *bb = D.b[nib(tv_of_rank, r) + 1];
+        for (int x = 0; x < 3; x++) {
+            double d = s * a[r + 1][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
+            res += d * d;
+        }
+    }
+    out.r = sqrt(res / (K + 1));
+    out.s = s;
+}
+
+// observed points of one hull group: centre (row 0) and the innermost K
+// neighbours, minus their barycentre (eq. 2); Ga = sum of squared norms
+template <int K>
+__device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t n, int64_t p, double (&a)[NMAX][3],
+                                    double &Ga) {
+    double c[3] = {0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < K; r++)
+        for (int d = 0; d < 3; d++) {
+            a[r + 1][d] = nbr_rel[((int64_t)r * 3 + d) * n + p];
+            c[d] += a[r + 1][d];
+        }
+    for (int d = 0; d < 3; d++) c[d] /= (K + 1);
+    Ga = 0;
+    for (int d = 0; d < 3; d++) {
+        a[0][d] = -c[d];
+        Ga += c[d] * c[d];
+    }
+#pragma unroll
+    for (int r = 0; r < K; r++)
+        for (int d = 0; d < 3; d++) {
+            a[r + 1][d] -= c[d];
+            Ga += a[r + 1][d] * a[r + 1][d];
+        }
+}
+
+// template vertex of each observed rank for candidate perm (label -> vertex)
+// and labelling ord (label -> rank)
+__device__ inline uint64_t tv_of_rank(uint64_t perm, uint64_t ord, int k) {
+    uint64_t tv = 0;
+    for (int l = 0; l < k; l++) tv |= (uint64_t)nib(perm, l) << (4 * nib(ord, l));
+    return tv;
+}
+
+// observed rank at each template vertex
+__device__ inline uint64_t rank_of_tv(uint64_t perm, uint64_t ord, int k) {
+    uint64_t c = 0;
+    for (int l = 0; l < k; l++) c |= (uint64_t)nib(ord, l) << (4 * nib(perm, l));
+    return c;
+}
+
+template <int K>
+__device__ inline void scan_group(const MatchShared &M, const TablesView &T, int grp, int32_t cid, uint64_t ord,
+                                  uint32_t mask, const double *__restrict__ nbr_rel, int64_t n, int64_t p, double &m1,
+                                  double &m2, int &arg_grp, int &arg_c) {
+    double a[NMAX][3], Ga;
+    load_centred<K>(nbr_rel, n, p, a, Ga);
+    int c0 = T.cstart[grp][cid], c1 = T.cstart[grp][cid + 1];
+    for (int c = c0; c < c1; c++) {
+        Candidate cd = T.cand[grp][c];
+        if (!((mask >> cd.tmpl) & 1)) continue;
+        CandEval ev;
+        eval_candidate<K>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
+        if (ev.r < m1) {
+            m2 = m1;
+            m1 = ev.r;
+            arg_grp = grp;
+            arg_c = c;
+        } else if (ev.r < m2) {
+            m2 = ev.r;
+        }
+    }
+}
+
+// full tie rule: among candidates within TIE of the minimum, earliest
+// template, then the smallest representative vector
+template <int K>
+__device__ inline void tie_group(const MatchShared &M, const TablesView &T, int grp, int32_t cid, uint64_t ord,
+                                 uint32_t mask, const double *__restrict__ nbr_rel, int64_t n, int64_t p, double rstar,
+                                 int &win_grp, int &win_c, int &win_t, uint64_t &win_rep) {
+    double a[NMAX][3], Ga;
+    load_centred<K>(nbr_rel, n, p, a, Ga);
+    int c0 = T.cstart[grp][cid], c1 = T.cstart[grp][cid + 1];
+    for (int c = c0; c < c1; c++) {
+        Candidate cd = T.cand[grp][c];
+        if (!((mask >> cd.tmpl) & 1)) continue;
+        CandEval ev;
+        eval_candidate<K>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
+        if (!(ev.r <= rstar + 1e-12)) continue;
+        int gsel;
+        uint64_t rep = rep_vector(M.tpl[cd.tmpl], rank_of_tv(cd.perm, ord, K), gsel);
+        bool better = (win_c < 0) || (cd.tmpl < win_t) || (cd.tmpl == win_t && rep < win_rep);
+        if (better) {
+            win_grp = grp;
+            win_c = c;
+            win_t = cd.tmpl;
+            win_rep = rep;
+        }
+    }
+}
+
+template <int K>
+__device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
+                              const double *__restrict__ nbr_rel, double cutoff, int64_t p, int64_t n, int32_t i,
+                              const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
+                              const MatchOut &O) {
+    double a[NMAX][3], Ga;
+    load_centred<K>(nbr_rel, n, p, a, Ga);
+    Candidate cd = T.cand[grp][c];
+    const TemplateDev &D = M.tpl[cd.tmpl];
+    uint64_t tv = tv_of_rank(cd.perm, ord, K);
+    CandEval ev;
+    eval_candidate<K>(a, Ga, D, tv, ev);
+    int type = (ev.r <= cutoff) ? cd.tmpl + 1 : 0;
+    uint64_t cmap = rank_of_tv(cd.perm, ord, K);
+    int g;
+    uint64_t rep = rep_vector(D, cmap, g);
+    // q' = q * conj(q_g)
+    const double *qg = D.gq[g];
+    double w1 = ev.q[0], x1 = ev.q[1], y1 = ev.q[2], z1 = ev.q[3];
+    double w2 = qg[0], x2 = -qg[1], y2 = -qg[2], z2 = -qg[3];
+    double q[4] = {w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                   w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2};
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    int flip = 0;
+    for (int k = 0; k < 4; k++) {
+        if (q[k] > 0) { flip = 1; break; }
+        if (q[k] < 0) { flip = -1; break; }
+    }
+    double sc = (flip < 0 ? -1.0 : 1.0) / qn;
+    for (int k = 0; k < 4; k++) q[k] *= sc;
+    // strain: A^T = V+ W', W' = a / l(a) in template order; P = sqrt(A A^T)
+    double l = 0;
+    for (int r = 0; r <= K; r++) l += sqrt(a[r][0] * a[r][0] + a[r][1] * a[r][1] + a[r][2] * a[r][2]);
+    l /= (K + 1);
+    double At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) At[x][y] += D.vpinv[x][0] * a[0][y];
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+        int col = (int)nib(tv, r) + 1;
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) At[x][y] += D.vpinv[x][col] * a[r + 1][y];
+    }
+    double AA[3][3];
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) {
+            double s = 0;
+            for (int m = 0; m < 3; m++) s += At[m][x] * At[m][y];
+            AA[x][y] = s / (l * l);
+        }
+    double ev3[3], V[3][3];
+    jacobi3(AA, ev3, V);
+    double P[9];
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) {
+            double s = 0;
+            for (int m = 0; m < 3; m++) s += V[x][m] * sqrt(fmax(ev3[m], 0.0)) * V[y][m];
+            P[3 * x + y] = s;
+        }
+    // alloy (Sec. 6, Table 3)
+    int alloy = 0;
+    if (species && type) {
+        int8_t me = species[i];
+        if (cd.tmpl == 1 || cd.tmpl == 4) {
+            uint32_t cnt = 0;  // 8-bit counters: FCC groups 0..2, BCC inner/outer
+            for (int r = 0; r < K; r++) {
+                int32_t j = nbr_id[(int64_t)r * n + p];
+                int other = species[j] != me;
+                int tvx = (int)nib(tv, r);
+                int grp2 = (cd.tmpl == 1) ? (tvx >> 2) : (tvx < 8 ? 0 : 1);
+                cnt += (uint32_t)other << (8 * grp2);
+            }
+            if (cd.tmpl == 1) {
+                int c0 = cnt & 0xFF, c1 = (cnt >> 8) & 0xFF, c2 = (cnt >> 16) & 0xFF;
+                int lo = min(c0, min(c1, c2)), hi = max(c0, max(c1, c2)), mid = c0 + c1 + c2 - lo - hi;
+                if (lo == 0 && mid == 0 && hi == 0) alloy = 1;
+                else if (lo == 0 && mid == 4 && hi == 4) alloy = 2;
+                else if (lo == 0 && mid == 0 && hi == 4) alloy = 3;
+                else if (lo == 4 && mid == 4 && hi == 4) alloy = 4;
+                else alloy = 5;
+            } else {
+                int inner = cnt & 0xFF, outer = (cnt >> 8) & 0xFF;
+                if (inner == 0 && outer == 0) alloy = 6;
+                else if (inner == 8 && outer == 0) alloy = 7;
+                else alloy = 8;
+            }
+        }
+    }
+    O.type[i] = (int8_t)type;
+    if (O.alloy) O.alloy[i] = (int8_t)alloy;
+    if (O.rmsd) O.rmsd[i] = ev.r;
+    if (O.scale) O.scale[i] = ev.s;
+    if (O.quat)
+        for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = q[k];
+    if (O.strain)
+        for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = P[k];
+    if (O.neighbours) {
+        for (int m = 0; m < KMAX; m++) {
+            int32_t id = -1;
+            if (m < K) {
+                int rank = (int)((rep >> (4 * (15 - m))) & 0xF);
+                id = nbr_id[(int64_t)rank * n + p];
+            }
+            O.neighbours[(int64_t)i * KMAX + m] = id;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(MB) k_match(int64_t n, const double *__restrict__ nbr_rel,
+                                               const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
+                                               const int8_t *__restrict__ species, TablesView T,
+                                               const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
+                                               uint32_t mask, double cutoff, MatchOut O) {
+    __shared__ MatchShared M;
+    {
+        const uint32_t *src = (const uint32_t *)T.tpl;
+        uint32_t *dst = (uint32_t *)M.tpl;
+        for (int w = threadIdx.x; w < (int)(sizeof(TemplateDev) * NT / 4); w += MB) dst[w] = src[w];
+    }
+    __syncthreads();
+    const int64_t p = blockIdx.x * (int64_t)MB + threadIdx.x;
+    if (p >= n) return;
+    const int32_t i = sid[p];
+    int32_t cid[NGRP];
+    uint64_t ord[NGRP];
+    for (int g = 0; g < NGRP; g++) {
+        cid[g] = code[(int64_t)g * n + p];
+        ord[g] = ords[(int64_t)g * n + p];
+    }
+    double m1 = INFINITY, m2 = INFINITY;
+    int arg_grp = -1, arg_c = -1;
+    if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+    if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+    if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+    if (arg_c < 0) {
+        O.type[i] = 0;
+        if (O.alloy) O.alloy[i] = 0;
+        if (O.rmsd) O.rmsd[i] = INFINITY;
+        if (O.scale) O.scale[i] = 0.0;
+        if (O.quat) {
+            O.quat[4 * (int64_t)i] = 1.0;
+            for (int k = 1; k < 4; k++) O.quat[4 * (int64_t)i + k] = 0.0;
+        }
+        if (O.strain)
+            for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = 0.0;
+        if (O.neighbours)
+            for (int m = 0; m < KMAX; m++) O.neighbours[(int64_t)i * KMAX + m] = -1;
+        return;
+    }
+    if (m2 <= m1 + 1e-12) {
+        // near tie: apply the full rule over every candidate
+        int wg = -1, wc = -1, wt = 99;
+        uint64_t wrep = ~0ull;
+        if (cid[0] >= 0) tie_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
+        if (cid[1] >= 0) tie_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
+        if (cid[2] >= 0) tie_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
+        if (wc >= 0) {
+            arg_grp = wg;
+            arg_c = wc;
+        }
+    }
+    if (arg_grp == 0) finish<6>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+    else if (arg_grp == 1) finish<12>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+    else finish<14>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+}
+
+// --------------------------------------------------------------- launches
+void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_bounds, dim3(nblocks), dim3(256), 0, st, pos, n, part);
+}
+void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
+                      int32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, g, cell_of, slot_of,
+                       count);
+}
+void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
+                        const int32_t *start, double *sx, double *sy, double *sz, int32_t *sid, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, cell_of, slot_of,
+                       start, sx, sy, sz, sid);
+}
+void launch_knn(int64_t n, const Grid &g, const double *pos, const double *sx, const double *sy, const double *sz,
+                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_knn, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, g, pos, sx, sy, sz, sid, start,
+                       nbr_id, nbr_rel, knn_out);
+}
+void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
+                 uint64_t *ord, hipStream_t st) {
+    dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
+    if (K == 6) hipLaunchKernelGGL(k_topo<6>, grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+    else if (K == 12) hipLaunchKernelGGL(k_topo<12>, grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+    else hipLaunchKernelGGL(k_topo<14>, grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+}
+void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
+                  const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
+                  const MatchOut &O, hipStream_t st) {
+    hipLaunchKernelGGL(k_match, dim3((unsigned)((n + MB - 1) / MB)), dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species,
+                       T, code, ord, mask, cutoff, O);
+}
+
+}  // namespace ptm

@@ -1,0 +1,46 @@
+// ptm_kernels.hpp -- host-visible launch wrappers of the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ptm_tables.hpp"
+
+namespace ptm {
+
+// Cell grid of one frame (counting-sort binning; see k_bin_count).
+struct Grid {
+    int nc[3];        // cells per axis
+    int periodic[3];  // 1 if the axis is periodic
+    double L[3];      // periodic box length (0 on open axes)
+    double invL[3];   // 1/L, correctly rounded (minimum image uses d*(1/L))
+    double lo[3];     // grid origin on open axes
+    double h[3];      // cell edge
+    double inv_h[3];  // cells per unit length
+    double margin;    // safety margin of the neighbour-search certificate
+};
+
+struct MatchOut {
+    int8_t *type;
+    int8_t *alloy;
+    double *rmsd;
+    double *scale;
+    double *quat;
+    int32_t *neighbours;
+    double *strain;
+};
+
+void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st);
+void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
+                      int32_t *count, hipStream_t st);
+void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
+                        const int32_t *start, double *sx, double *sy, double *sz, int32_t *sid, hipStream_t st);
+void launch_knn(int64_t n, const Grid &g, const double *pos, const double *sx, const double *sy, const double *sz,
+                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
+                hipStream_t st);
+void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
+                 uint64_t *ord, hipStream_t st);
+void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
+                  const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
+                  const MatchOut &O, hipStream_t st);
+
+}  // namespace ptm

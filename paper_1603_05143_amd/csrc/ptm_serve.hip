@@ -1,0 +1,304 @@
+// ptm_serve.hip -- table upload, host-pointer staging and the serving loop
+// (ptm_submit / ptm_wait).
+//
+// Serving is continuous batching over a pool of HIP streams (default
+// priority): each admitted frame gets its own scratch and runs its whole
+// pipeline on the next stream of the pool, so frames that arrive while
+// others are on the device overlap with them.  Admission is by bytes: a
+// frame is admitted when the scratch of all in-flight frames plus its own
+// stays within the context's HBM budget; otherwise ptm_submit returns
+// PTM_E_BUSY and the caller retries after a ptm_wait.  Finished frames
+// return their scratch to a free list for reuse.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "ptm_internal.hpp"
+
+using namespace ptm;
+
+namespace ptm {
+
+static constexpr int SERVE_STREAMS = 4;
+
+ptm_status upload_tables(ptm_ctx *ctx) {
+    auto up = [&](const void *src, size_t bytes, void **dst) -> ptm_status {
+        if (bytes == 0) bytes = 8;
+        PTM_HIP(ctx, hipMalloc(dst, bytes));
+        ctx->table_buffers.push_back(*dst);
+        if (src) PTM_HIP(ctx, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return PTM_OK;
+    };
+    void *p;
+    ptm_status st;
+    if ((st = up(ctx->host.tpl, sizeof(TemplateDev) * NT, &p)) != PTM_OK) return st;
+    ctx->view.tpl = (const TemplateDev *)p;
+    for (int g = 0; g < NGRP; g++) {
+        HostTables &H = ctx->host;
+        if ((st = up(H.codes[g].data(), H.codes[g].size() * 8, &p)) != PTM_OK) return st;
+        ctx->view.codes[g] = (const uint64_t *)p;
+        if ((st = up(H.slots[g].data(), H.slots[g].size() * 4, &p)) != PTM_OK) return st;
+        ctx->view.slots[g] = (const int32_t *)p;
+        if ((st = up(H.cstart[g].data(), H.cstart[g].size() * 4, &p)) != PTM_OK) return st;
+        ctx->view.cstart[g] = (const int32_t *)p;
+        if ((st = up(H.cand[g].data(), H.cand[g].size() * sizeof(Candidate), &p)) != PTM_OK) return st;
+        ctx->view.cand[g] = (const Candidate *)p;
+        ctx->view.hmask[g] = H.hmask[g];
+        ctx->view.ncodes[g] = H.ncodes[g];
+    }
+    return PTM_OK;
+}
+
+static size_t staging_bytes(int64_t n) {
+    size_t a = 0;
+    auto add = [&](size_t s) { a += (s + 255) & ~(size_t)255; };
+    add(24 * (size_t)n);   // positions
+    add((size_t)n);        // species
+    add((size_t)n);        // type
+    add((size_t)n);        // alloy
+    add(8 * (size_t)n);    // rmsd
+    add(8 * (size_t)n);    // scale
+    add(32 * (size_t)n);   // quat
+    add(56 * (size_t)n);   // neighbours
+    add(72 * (size_t)n);   // strain
+    add(56 * (size_t)n);   // knn
+    return a;
+}
+
+ptm_status stage_in_buffers(ptm_ctx *ctx, StagingBuffers &B, const double *positions, const int8_t *species,
+                            const ptm_outputs *out, int64_t n, FrameJob &J, HostStage &H, hipStream_t st) {
+    if (!(ctx->flags & PTM_F_HOST_POINTERS)) {
+        J.pos = positions;
+        J.species = species;
+        J.out = *out;
+        H.active = false;
+        return PTM_OK;
+    }
+    size_t need = staging_bytes(n);
+    if (need > B.bytes) {
+        B.release();
+        if (hipMalloc(&B.base, need) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->err = "staging allocation failed";
+            return PTM_E_NOMEM;
+        }
+        B.bytes = need;
+    }
+    char *p = (char *)B.base;
+    auto take = [&](size_t s) {
+        char *r = p;
+        p += (s + 255) & ~(size_t)255;
+        return (void *)r;
+    };
+    double *dpos = (double *)take(24 * (size_t)n);
+    int8_t *dspc = (int8_t *)take((size_t)n);
+    ptm_outputs d;
+    d.type = (int8_t *)take((size_t)n);
+    d.alloy = (int8_t *)take((size_t)n);
+    d.rmsd = (double *)take(8 * (size_t)n);
+    d.scale = (double *)take(8 * (size_t)n);
+    d.quat = (double *)take(32 * (size_t)n);
+    d.neighbours = (int32_t *)take(56 * (size_t)n);
+    d.strain = (double *)take(72 * (size_t)n);
+    d.knn = (int32_t *)take(56 * (size_t)n);
+    if (!out->alloy) d.alloy = nullptr;
+    if (!out->rmsd) d.rmsd = nullptr;
+    if (!out->scale) d.scale = nullptr;
+    if (!out->quat) d.quat = nullptr;
+    if (!out->neighbours) d.neighbours = nullptr;
+    if (!out->strain) d.strain = nullptr;
+    if (!out->knn) d.knn = nullptr;
+    PTM_HIP(ctx, hipMemcpyAsync(dpos, positions, 24 * (size_t)n, hipMemcpyHostToDevice, st));
+    if (species) PTM_HIP(ctx, hipMemcpyAsync(dspc, species, (size_t)n, hipMemcpyHostToDevice, st));
+    J.pos = dpos;
+    J.species = species ? dspc : nullptr;
+    J.out = d;
+    H.active = true;
+    H.host_out = *out;
+    return PTM_OK;
+}
+
+ptm_status stage_in(ptm_ctx *ctx, const double *positions, const int8_t *species, const ptm_outputs *out, int64_t n,
+                    FrameJob &J, HostStage &H) {
+    return stage_in_buffers(ctx, ctx->staging, positions, species, out, n, J, H, ctx->stream);
+}
+
+ptm_status stage_out(ptm_ctx *ctx, const ptm_outputs *out, int64_t n, const FrameJob &J, const HostStage &H,
+                     hipStream_t st) {
+    (void)out;
+    if (!H.active) return PTM_OK;
+    const ptm_outputs &h = H.host_out, &d = J.out;
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> ptm_status {
+        if (dst && src) PTM_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        return PTM_OK;
+    };
+    ptm_status s;
+    if ((s = cp(h.type, d.type, (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.alloy, d.alloy, (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.rmsd, d.rmsd, 8 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.scale, d.scale, 8 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.quat, d.quat, 32 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.neighbours, d.neighbours, 56 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.strain, d.strain, 72 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.knn, d.knn, 56 * (size_t)n)) != PTM_OK) return s;
+    return PTM_OK;
+}
+
+static ptm_status serve_init(ptm_ctx *ctx) {
+    if (!ctx->serve_streams.empty()) return PTM_OK;
+    for (int s = 0; s < SERVE_STREAMS; s++) {
+        hipStream_t h;
+        PTM_HIP(ctx, hipStreamCreateWithFlags(&h, hipStreamNonBlocking));
+        ctx->serve_streams.push_back(h);
+    }
+    PTM_HIP(ctx, hipStreamCreateWithFlags(&ctx->bounds_stream, hipStreamNonBlocking));
+    return PTM_OK;
+}
+
+static void retire(ptm_ctx *ctx, Ticket *T) {
+    ctx->inflight_bytes -= T->footprint;
+    if (T->done) (void)hipEventDestroy(T->done);
+    T->done = nullptr;
+    ctx->free_scratch.push_back(T->scratch);
+    T->scratch = FrameScratch();
+    T->staging.release();
+}
+
+void serve_shutdown(ptm_ctx *ctx) {
+    for (auto &kv : ctx->tickets) {
+        if (kv.second->done) (void)hipEventSynchronize(kv.second->done);
+        retire(ctx, kv.second);
+        delete kv.second;
+    }
+    ctx->tickets.clear();
+    for (auto &s : ctx->free_scratch) s.release();
+    ctx->free_scratch.clear();
+    for (auto s : ctx->serve_streams) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    ctx->serve_streams.clear();
+    if (ctx->bounds_stream) (void)hipStreamDestroy(ctx->bounds_stream);
+    ctx->bounds_stream = nullptr;
+}
+
+}  // namespace ptm
+
+extern "C" {
+
+ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *species, const double *box,
+                      int64_t n_atoms, uint32_t template_mask, double rmsd_cutoff, const ptm_outputs *out,
+                      uint64_t *ticket) {
+    ptm_status st = validate(ctx, positions, box, n_atoms, rmsd_cutoff, out);
+    if (st != PTM_OK) return st;
+    if (!ticket) {
+        ctx->err = "ticket must not be NULL";
+        return PTM_E_INVALID;
+    }
+    ctx->err.clear();
+    PTM_HIP(ctx, hipSetDevice(ctx->device));
+    if ((st = serve_init(ctx)) != PTM_OK) return st;
+    double t_submit = now_us();
+    Ticket *T = new Ticket();
+    T->t_submit = t_submit;
+    T->job.n = n_atoms;
+    T->job.mask = template_mask & PTM_ALL;
+    T->job.cutoff = rmsd_cutoff;
+    if (n_atoms > 0) {
+        // take the smallest free scratch that fits later; first the bounds
+        int best = -1;
+        for (size_t i = 0; i < ctx->free_scratch.size(); i++)
+            if (best < 0 || ctx->free_scratch[i].bytes > ctx->free_scratch[best].bytes) best = (int)i;
+        if (best >= 0) {
+            T->scratch = ctx->free_scratch[best];
+            ctx->free_scratch.erase(ctx->free_scratch.begin() + best);
+        }
+        hipStream_t bst = ctx->bounds_stream;
+        st = stage_in_buffers(ctx, T->staging, positions, species, out, n_atoms, T->job, T->stage, bst);
+        if (st == PTM_OK && !T->scratch.reserve(n_atoms, 1, ctx->err)) st = PTM_E_NOMEM;
+        double mn[3], mx[3];
+        bool bad = false;
+        if (st == PTM_OK) st = frame_bounds(ctx, T->scratch, T->job.pos, n_atoms, mn, mx, bad, bst);
+        if (st == PTM_OK && bad) {
+            ctx->err = "non-finite coordinate";
+            st = PTM_E_INVALID;
+        }
+        int64_t cells = 1;
+        if (st == PTM_OK) {
+            T->job.grid = make_grid(box, mn, mx, n_atoms);
+            cells = (int64_t)T->job.grid.nc[0] * T->job.grid.nc[1] * T->job.grid.nc[2];
+            T->footprint = frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0);
+            if (ctx->budget && ctx->inflight_bytes + T->footprint > ctx->budget) {
+                ctx->err = "HBM budget full";
+                st = (T->footprint > ctx->budget) ? PTM_E_NOMEM : PTM_E_BUSY;
+            }
+        }
+        if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, ctx->err)) st = PTM_E_NOMEM;
+        if (st != PTM_OK) {
+            if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);
+            T->staging.release();
+            delete T;
+            return st;
+        }
+        ctx->inflight_bytes += T->footprint;
+        T->stream = ctx->next_stream;
+        ctx->next_stream = (ctx->next_stream + 1) % (int)ctx->serve_streams.size();
+        hipStream_t s = ctx->serve_streams[T->stream];
+        T->t_start = now_us();
+        st = enqueue_frame(ctx, T->scratch, T->job, s);
+        if (st == PTM_OK) st = stage_out(ctx, out, n_atoms, T->job, T->stage, s);
+        if (st == PTM_OK && hipEventCreateWithFlags(&T->done, hipEventDisableTiming) != hipSuccess) st = PTM_E_DEVICE;
+        if (st == PTM_OK && hipEventRecord(T->done, s) != hipSuccess) st = PTM_E_DEVICE;
+        if (st != PTM_OK) {
+            (void)hipStreamSynchronize(s);
+            retire(ctx, T);
+            delete T;
+            return st;
+        }
+    } else {
+        T->t_start = T->t_complete = now_us();
+        T->complete = true;
+    }
+    uint64_t id = ctx->next_ticket++;
+    ctx->tickets[id] = T;
+    *ticket = id;
+    return PTM_OK;
+}
+
+ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame_stats *stats) {
+    if (!ctx) return PTM_E_INVALID;
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) {
+        ctx->err = "unknown ticket";
+        return PTM_E_INVALID;
+    }
+    Ticket *T = it->second;
+    if (!T->complete) {
+        PTM_HIP(ctx, hipSetDevice(ctx->device));
+        double t0 = now_us();
+        for (;;) {
+            hipError_t q = hipEventQuery(T->done);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) {
+                ctx->err = std::string("frame failed: ") + hipGetErrorString(q);
+                return PTM_E_DEVICE;
+            }
+            if (timeout_us >= 0 && now_us() - t0 >= (double)timeout_us) return PTM_E_TIMEOUT;
+        }
+        T->t_complete = now_us();
+        T->complete = true;
+    }
+    if (stats) {
+        stats->submit_time_us = T->t_submit;
+        stats->start_time_us = T->t_start;
+        stats->complete_time_us = T->t_complete;
+        stats->n_atoms = T->job.n;
+    }
+    retire(ctx, T);
+    delete T;
+    ctx->tickets.erase(it);
+    return PTM_OK;
+}
+
+}  // extern "C"

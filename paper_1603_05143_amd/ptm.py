@@ -1,0 +1,188 @@
+"""Thin ctypes binding of ``libptm.so`` (C ABI in include/ptm.h).
+
+Names follow the C functions.  This module only marshals arguments: every
+step of the classification runs in the library's HIP kernels.  PyTorch is
+used for device memory (``Classifier`` allocates output tensors and passes
+their ``data_ptr()``).  If the library is missing the import of the
+library fails loudly; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptm.so")
+
+PTM_OK, PTM_E_INVALID, PTM_E_NOMEM, PTM_E_DEVICE, PTM_E_BOX, PTM_E_TOO_LARGE, PTM_E_BUSY, PTM_E_TIMEOUT = range(8)
+PTM_FP64, PTM_FP32_MIXED = 0, 1
+PTM_SC, PTM_FCC, PTM_HCP, PTM_ICO, PTM_BCC = 1, 2, 4, 8, 16
+PTM_ALL = 0x1F
+PTM_F_HOST_POINTERS = 1
+TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
+ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")
+
+
+class ptm_config(C.Structure):
+    _fields_ = [("device", C.c_int), ("precision", C.c_int), ("hip_stream", C.c_void_p),
+                ("hbm_budget_bytes", C.c_uint64), ("flags", C.c_uint32)]
+
+
+class ptm_outputs(C.Structure):
+    _fields_ = [("type", C.c_void_p), ("alloy", C.c_void_p), ("rmsd", C.c_void_p), ("scale", C.c_void_p),
+                ("quat", C.c_void_p), ("neighbours", C.c_void_p), ("strain", C.c_void_p), ("knn", C.c_void_p)]
+
+
+class ptm_frame_stats(C.Structure):
+    _fields_ = [("submit_time_us", C.c_double), ("start_time_us", C.c_double),
+                ("complete_time_us", C.c_double), ("n_atoms", C.c_int64)]
+
+
+class PTMError(RuntimeError):
+    def __init__(self, status, message=""):
+        self.status = status
+        super().__init__(f"{ptm_status_string(status)} ({status}): {message}")
+
+
+_lib = None
+
+
+def lib():
+    """Load libptm.so (built by paper_1603_05143_amd.build_lib)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.ptm_create.argtypes = [C.POINTER(ptm_config), C.POINTER(vp)]
+        L.ptm_create.restype = C.c_int
+        L.ptm_classify.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_double, C.POINTER(ptm_outputs)]
+        L.ptm_classify.restype = C.c_int
+        L.ptm_submit.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_double, C.POINTER(ptm_outputs),
+                                 C.POINTER(C.c_uint64)]
+        L.ptm_submit.restype = C.c_int
+        L.ptm_wait.argtypes = [vp, C.c_uint64, C.c_int64, C.POINTER(ptm_frame_stats)]
+        L.ptm_wait.restype = C.c_int
+        L.ptm_destroy.argtypes = [vp]
+        L.ptm_destroy.restype = None
+        L.ptm_status_string.argtypes = [C.c_int]
+        L.ptm_status_string.restype = C.c_char_p
+        L.ptm_last_error.argtypes = [vp]
+        L.ptm_last_error.restype = C.c_char_p
+        L.ptm_template_info.argtypes = [C.c_int, C.POINTER(C.c_int64)]
+        L.ptm_template_info.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+# ---- same names as the C ABI --------------------------------------------
+def ptm_status_string(status: int) -> str:
+    return lib().ptm_status_string(status).decode()
+
+
+def ptm_last_error(ctx) -> str:
+    return lib().ptm_last_error(ctx).decode()
+
+
+def ptm_create(device=0, precision=PTM_FP64, hip_stream=None, hbm_budget_bytes=0, flags=0):
+    cfg = ptm_config(device, precision, hip_stream, hbm_budget_bytes, flags)
+    ctx = C.c_void_p()
+    st = lib().ptm_create(C.byref(cfg), C.byref(ctx))
+    if st != PTM_OK:
+        raise PTMError(st, "ptm_create")
+    return ctx
+
+
+def ptm_destroy(ctx) -> None:
+    lib().ptm_destroy(ctx)
+
+
+def ptm_classify(ctx, positions_ptr, species_ptr, box, n_atoms, template_mask, rmsd_cutoff, outputs):
+    bx = (C.c_double * 3)(*[float(b) for b in box])
+    return lib().ptm_classify(ctx, positions_ptr, species_ptr, bx, int(n_atoms), int(template_mask),
+                              float(rmsd_cutoff), C.byref(outputs))
+
+
+def ptm_submit(ctx, positions_ptr, species_ptr, box, n_atoms, template_mask, rmsd_cutoff, outputs):
+    bx = (C.c_double * 3)(*[float(b) for b in box])
+    t = C.c_uint64()
+    st = lib().ptm_submit(ctx, positions_ptr, species_ptr, bx, int(n_atoms), int(template_mask),
+                          float(rmsd_cutoff), C.byref(outputs), C.byref(t))
+    return st, t.value
+
+
+def ptm_wait(ctx, ticket, timeout_us=-1):
+    s = ptm_frame_stats()
+    st = lib().ptm_wait(ctx, C.c_uint64(ticket), int(timeout_us), C.byref(s))
+    return st, s
+
+
+def ptm_template_info(t: int):
+    info = (C.c_int64 * 5)()
+    st = lib().ptm_template_info(t, info)
+    if st != PTM_OK:
+        raise PTMError(st, "ptm_template_info")
+    return {"k": info[0], "group_order": info[1], "triangulations": info[2], "codes": info[3],
+            "candidates": info[4]}
+
+
+# ---- convenience wrapper over torch device tensors ------------------------
+class Classifier:
+    """Owns a context; classifies torch tensors resident on the GPU."""
+
+    def __init__(self, device: int = 0, precision: int = PTM_FP64, hbm_budget_bytes: int = 0):
+        import torch  # noqa: F401  (loads the HIP runtime the library shares)
+        self.device = device
+        self.ctx = ptm_create(device, precision, None, hbm_budget_bytes, 0)
+
+    def close(self):
+        if self.ctx is not None:
+            ptm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def alloc_outputs(n: int, device: str, knn: bool = False):
+        import torch
+        out = {
+            "type": torch.empty(n, dtype=torch.int8, device=device),
+            "alloy": torch.empty(n, dtype=torch.int8, device=device),
+            "rmsd": torch.empty(n, dtype=torch.float64, device=device),
+            "scale": torch.empty(n, dtype=torch.float64, device=device),
+            "quat": torch.empty((n, 4), dtype=torch.float64, device=device),
+            "neighbours": torch.empty((n, 14), dtype=torch.int32, device=device),
+            "strain": torch.empty((n, 9), dtype=torch.float64, device=device),
+        }
+        if knn:
+            out["knn"] = torch.empty((n, 14), dtype=torch.int32, device=device)
+        return out
+
+    @staticmethod
+    def outputs_struct(out) -> ptm_outputs:
+        def p(k):
+            t = out.get(k)
+            return None if t is None else t.data_ptr()
+        return ptm_outputs(p("type"), p("alloy"), p("rmsd"), p("scale"), p("quat"), p("neighbours"),
+                           p("strain"), p("knn"))
+
+    def classify(self, positions, box, species=None, mask=PTM_ALL, cutoff=float("inf"), out=None, knn=False):
+        """positions: (n,3) float64 CUDA tensor; returns dict of output tensors."""
+        import torch
+        assert positions.is_cuda and positions.dtype == torch.float64 and positions.is_contiguous()
+        n = positions.shape[0]
+        if out is None:
+            out = self.alloc_outputs(n, positions.device, knn)
+        sp = None
+        if species is not None:
+            assert species.is_cuda and species.dtype == torch.int8 and species.is_contiguous()
+            sp = species.data_ptr()
+        st = ptm_classify(self.ctx, positions.data_ptr() if n else None, sp, box, n, mask, cutoff,
+                          self.outputs_struct(out))
+        if st != PTM_OK:
+            raise PTMError(st, ptm_last_error(self.ctx))
+        return out

@@ -1,0 +1,166 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+headers declare, reports its template tables, and its host-compiled device
+predicates and canonical code agree with the independent oracle."""
+import ctypes as C
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("ptm.h", "ptm_selftest.h")]
+
+
+@pytest.fixture(scope="module")
+def ptm():
+    from paper_1603_05143_amd import ptm as P
+    P.lib()
+    return P
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(ptm_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_function(ptm):
+    names = declared_functions()
+    assert "ptm_classify" in names and "ptm_create" in names and "ptm_submit" in names
+    L = ptm.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_template_info_matches_paper(ptm):
+    import json
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_facts.json")))
+    names = ("SC", "FCC", "HCP", "ICO", "BCC")
+    for t, nm in enumerate(names):
+        d = ptm.ptm_template_info(t)
+        assert d["k"] == gold["neighbours_required"][nm]
+        assert d["group_order"] == gold["symmetry_order"][nm]
+        assert d["triangulations"] == gold["triangulations"][nm]
+    # App. A: the automorphisms of the unique SC and ICO triangulations are all
+    # symmetrically equivalent -> one candidate each
+    assert ptm.ptm_template_info(0)["candidates"] == 1
+    assert ptm.ptm_template_info(3)["candidates"] == 1
+    with pytest.raises(ptm.PTMError):
+        ptm.ptm_template_info(5)
+
+
+def test_status_strings_and_errors_without_device(ptm):
+    for s in range(8):
+        assert ptm.ptm_status_string(s)
+    assert ptm.lib().ptm_last_error(None) == b""
+    out = ptm.ptm_outputs()
+    st = ptm.lib().ptm_classify(None, None, None, None, 0, 0, 0.0, C.byref(out))
+    assert st == ptm.PTM_E_INVALID
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        with pytest.raises(ptm.PTMError) as e:
+            ptm.ptm_create()
+        assert e.value.status == ptm.PTM_E_DEVICE
+
+
+def frac_det3(p):
+    a, b, c = [[Fraction(x) for x in r] for r in p]
+    d = (a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0])
+         + a[2] * (b[0] * c[1] - b[1] * c[0]))
+    return (d > 0) - (d < 0)
+
+
+def test_selftest_orient_agrees_with_oracle(ptm, oracle_lib):
+    L = ptm.lib()
+    rng = np.random.default_rng(0)
+    for trial in range(4000):
+        kind = trial % 4
+        if kind == 0:
+            q = rng.normal(size=(4, 3))
+        else:
+            q = rng.integers(-2, 3, size=(4, 3)).astype(float) * rng.choice([1.0, 0.5, 3.615])
+            if kind == 2:
+                q[3] = q[0] + rng.integers(-2, 3) * (q[1] - q[0]) + rng.integers(-2, 3) * (q[2] - q[0])
+            if kind == 3:
+                q[2] = q[0] + 2 * (q[1] - q[0])
+        r = rng.permutation(14)[:4].astype(np.int32)
+        got = L.ptm_selftest_orient(q.ctypes.data_as(C.c_void_p), r.ctypes.data_as(C.c_void_p))
+        assert got == oracle_lib.orient(q, r, sos=True)
+
+
+def test_selftest_det3_exact(ptm):
+    L = ptm.lib()
+    rng = np.random.default_rng(1)
+    for _ in range(2000):
+        p = rng.normal(size=(3, 3))
+        if rng.random() < 0.4:
+            p[2] = p[0] * rng.integers(-2, 3) + p[1] * rng.integers(-2, 3)
+        p = np.ascontiguousarray(p)
+        assert L.ptm_selftest_det3(p.ctypes.data_as(C.c_void_p)) == frac_det3(p)
+
+
+def lib_code(ptm, k, tris):
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    rows = np.zeros(14, np.uint64)
+    na = C.c_int32()
+    rc = ptm.lib().ptm_selftest_canonical(k, t.ctypes.data_as(C.c_void_p), len(t),
+                                          rows.ctypes.data_as(C.c_void_p), C.byref(na))
+    assert rc == 0
+    return tuple(rows[:k].tolist()), na.value
+
+
+def test_selftest_canonical_agrees_with_oracle(ptm, oracle_lib):
+    """Two independent complete codes must induce the same partition."""
+    rng = np.random.default_rng(2)
+    for t in range(5):
+        w = oracle_lib.template(t)["w"]
+        k = len(w)
+        graphs = []
+        while len(graphs) < 25:
+            ok, tris = oracle_lib.hull(w + rng.normal(scale=0.06, size=w.shape))
+            if ok:
+                graphs.append(tris)
+        lc = [lib_code(ptm, k, g) for g in graphs]
+        oc = [oracle_lib.canonical(k, g) for g in graphs]
+        for i in range(len(graphs)):
+            assert lc[i][1] == oc[i][1]          # automorphism counts
+            perm = rng.permutation(k)
+            assert lib_code(ptm, k, perm[graphs[i]])[0] == lc[i][0]
+            for j in range(i + 1, len(graphs)):
+                assert (lc[i][0] == lc[j][0]) == (oc[i][0] == oc[j][0])
+
+
+def test_selftest_superpose_agrees_with_oracle(ptm, oracle_lib):
+    """The library's QCP solve (Newton on the characteristic polynomial,
+    adjugate eigenvector) vs the oracle's Jacobi on Horn's matrix."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from parity_util import quat_angle
+    from paper_1603_05143_amd.synthetic import random_rotations
+    L = ptm.lib()
+    rng = np.random.default_rng(5)
+    for t in range(5):
+        w = oracle_lib.template(t)["w"]
+        tpl = np.ascontiguousarray(np.vstack([np.zeros(3), w]))
+        for sig in (0.0, 0.05, 0.3, 1.0):
+            for _ in range(50):
+                R = random_rotations(rng, 1)[0]
+                obs = np.ascontiguousarray(np.vstack([np.zeros(3), w @ R.T * 1.8
+                                                      + rng.normal(scale=sig, size=w.shape)]))
+                r, s, q = C.c_double(), C.c_double(), np.zeros(4)
+                assert L.ptm_selftest_superpose(len(obs), obs.ctypes.data_as(C.c_void_p),
+                                                tpl.ctypes.data_as(C.c_void_p), C.byref(r), C.byref(s),
+                                                q.ctypes.data_as(C.c_void_p)) == 0
+                r1, s1, q1, _ = oracle_lib.superpose(obs, tpl)
+                assert abs(r.value - r1) < 1e-13
+                assert abs(s.value - s1) < 1e-13 * s1
+                assert quat_angle(q, q1) < 1e-12

@@ -1,0 +1,190 @@
+"""GPU parity of the FP64 HIP path against the FP64 oracle, through the C
+ABI: decisions (type, neighbour orders, alloy) bit-exact, reals within the
+algorithmic tolerances of parity_util.TOL64."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1603_05143_amd import ptm, synthetic as S
+from parity_util import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def clf(torch_cuda):
+    c = ptm.Classifier(device=0, precision=ptm.PTM_FP64)
+    yield c
+    c.close()
+
+
+def run_gpu(torch, clf, frame, mask=ptm.PTM_ALL, cutoff=math.inf):
+    print(f"[gpu] n={frame.n} box={frame.box.tolist()} mask={mask}", flush=True)
+    pos = torch.from_numpy(np.ascontiguousarray(frame.positions)).to("cuda:0")
+    sp = None if frame.species is None else torch.from_numpy(frame.species).to("cuda:0")
+    out = clf.classify(pos, frame.box, species=sp, mask=mask, cutoff=cutoff, knn=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def run_ref(oracle, frame, mask=ptm.PTM_ALL, cutoff=math.inf, atoms=None):
+    return oracle.classify(frame.positions, frame.box, species=frame.species, mask=mask, cutoff=cutoff,
+                           atoms=atoms)
+
+
+def test_config0(torch_cuda, clf, oracle_lib):
+    f = S.config0()
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    st = compare(got, ref)
+    assert np.all(got["type"] == 2)
+    print("config0", st)
+
+
+@pytest.mark.parametrize("kind,a", [("fcc", 3.615), ("bcc", 2.87), ("sc", 2.6), ("hcp", 2.51),
+                                    ("fcc", 2.0), ("bcc", 2.0)])
+def test_perfect_lattices_degenerate(torch_cuda, clf, oracle_lib, kind, a):
+    """Exactly or nearly coplanar facets everywhere: exact predicates + SoS."""
+    f = S.perfect_crystal(kind, (4, 4, 4), a=a)
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+
+
+@pytest.mark.parametrize("kind", ["l12", "l10", "b2", "a1", "a2"])
+def test_alloys(torch_cuda, clf, oracle_lib, kind):
+    a = 2.88 if kind in ("b2", "a2") else 3.6
+    f = S.perfect_crystal(kind, (3, 3, 3), a=a)
+    rng = np.random.default_rng(3)
+    f.positions = S.wrap(f.positions + rng.normal(scale=0.05, size=f.positions.shape), f.box)
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+
+
+def test_small_polycrystal(torch_cuda, clf, oracle_lib):
+    f = S.polycrystal(L=40.0, n_grains=4, sigma=0.1, seed=11)
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    st = compare(got, ref)
+    print("polycrystal", f.n, np.bincount(got["type"], minlength=6), st)
+
+
+def test_small_alloy_slabs(torch_cuda, clf, oracle_lib):
+    f = S.alloy_slabs(n_cells=12, seed=12)
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+
+
+@pytest.mark.parametrize("mask,cutoff", [(ptm.PTM_FCC | ptm.PTM_HCP, math.inf), (ptm.PTM_BCC, math.inf),
+                                         (ptm.PTM_SC | ptm.PTM_ICO, 0.3), (ptm.PTM_ALL, 0.06), (0, math.inf)])
+def test_mask_and_cutoff(torch_cuda, clf, oracle_lib, mask, cutoff):
+    f = S.polycrystal(L=30.0, n_grains=3, sigma=0.15, seed=13)
+    got = run_gpu(torch_cuda, clf, f, mask=mask, cutoff=cutoff)
+    ref = run_ref(oracle_lib, f, mask=mask, cutoff=cutoff)
+    compare(got, ref)
+
+
+def test_open_boundaries_icosahedron(torch_cuda, clf, oracle_lib):
+    p = S.mackay_icosahedron(3, nn=2.55)
+    rng = np.random.default_rng(5)
+    p = p + rng.normal(scale=0.02, size=p.shape)
+    f = S.Frame(positions=p, box=np.zeros(3))
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+    assert got["type"][0] == 4
+
+
+def test_mixed_periodic_open_axes(torch_cuda, clf, oracle_lib):
+    f = S.polycrystal(L=30.0, n_grains=2, sigma=0.1, seed=14)
+    f.box = np.array([f.box[0], 0.0, f.box[2]])
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 13, 15])
+def test_tiny_systems(torch_cuda, clf, oracle_lib, n):
+    rng = np.random.default_rng(n)
+    f = S.Frame(positions=rng.random((n, 3)) * 6.0, box=np.array([6.0, 6.0, 6.0]))
+    got = run_gpu(torch_cuda, clf, f)
+    ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+
+
+def test_empty_frame(torch_cuda, clf):
+    pos = torch_cuda.zeros((0, 3), dtype=torch_cuda.float64, device="cuda:0")
+    out = clf.classify(pos, [10.0, 10.0, 10.0])
+    assert out["type"].numel() == 0
+
+
+def test_invalid_inputs(torch_cuda, clf):
+    f = S.config0()
+    p = f.positions.copy()
+    p[7, 1] = np.nan
+    pos = torch_cuda.from_numpy(p).to("cuda:0")
+    with pytest.raises(ptm.PTMError) as e:
+        clf.classify(pos, f.box)
+    assert e.value.status == ptm.PTM_E_INVALID
+    pos = torch_cuda.from_numpy(f.positions).to("cuda:0")
+    for box in ([-1.0, 10, 10], [math.inf, 10, 10], [math.nan, 10, 10]):
+        with pytest.raises(ptm.PTMError) as e:
+            clf.classify(pos, box)
+        assert e.value.status == ptm.PTM_E_INVALID
+    with pytest.raises(ptm.PTMError):
+        clf.classify(pos, f.box, cutoff=math.nan)
+
+
+def test_deterministic_and_translation_invariant(torch_cuda, clf):
+    f = S.polycrystal(L=30.0, n_grains=3, sigma=0.1, seed=15)
+    a = run_gpu(torch_cuda, clf, f)
+    b = run_gpu(torch_cuda, clf, f)
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    g = S.Frame(positions=f.positions + f.box * np.array([2.0, -3.0, 1.0]), box=f.box)
+    c = run_gpu(torch_cuda, clf, g)
+    for k in ("type", "knn", "neighbours"):
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_config1_sampled(torch_cuda, clf, oracle_lib):
+    """Full ~0.92 M-atom polycrystal on the GPU; a seeded sample of atoms
+    recomputed one by one by the oracle."""
+    f = S.polycrystal()
+    got = run_gpu(torch_cuda, clf, f)
+    rng = np.random.default_rng(0)
+    atoms = np.sort(rng.choice(f.n, 1500, replace=False))
+    ref = run_ref(oracle_lib, f, atoms=atoms)
+    sub = {k: v[atoms] for k, v in got.items()}
+    st = compare(sub, ref)
+    print("config1", f.n, np.bincount(got["type"], minlength=6).tolist(), st)
+
+
+def test_host_pointer_context(torch_cuda, oracle_lib):
+    import ctypes as C
+    f = S.config0()
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, ptm.PTM_F_HOST_POINTERS)
+    try:
+        n = f.n
+        pos = np.ascontiguousarray(f.positions)
+        out = {"type": np.zeros(n, np.int8), "alloy": np.zeros(n, np.int8), "rmsd": np.zeros(n),
+               "scale": np.zeros(n), "quat": np.zeros((n, 4)), "neighbours": np.zeros((n, 14), np.int32),
+               "strain": np.zeros((n, 9)), "knn": np.zeros((n, 14), np.int32)}
+        o = ptm.ptm_outputs(*[out[k].ctypes.data for k in ("type", "alloy", "rmsd", "scale", "quat",
+                                                         "neighbours", "strain", "knn")])
+        st = ptm.ptm_classify(ctx, pos.ctypes.data, None, f.box, n, ptm.PTM_ALL, math.inf, o)
+        assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+        compare(out, oracle_lib.classify(f.positions, f.box))
+    finally:
+        ptm.ptm_destroy(ctx)
