@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the PTM classification pass on one MI355X.
+
+One step = one ptm_classify call over the whole frame (bounds, binning,
+k-NN, three hulls + canonical codes, candidate superposition, decision,
+strain, alloy, write-back) with inputs and outputs resident in HBM.  The
+workload is the ~0.92 M-atom periodic Voronoi polycrystal (L = 220 A, 16
+grains of FCC/BCC/HCP, sigma = 0.10 A), all five templates enabled.
+
+Prints one JSON line.  ``roofline`` covers the dominant kernel, timed with
+HIP events on the stream its kernels run on; ``cpu_baseline`` times the FP64
+reference implementation on a bounded sample of the same frame.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atoms/s (PTM, all templates) FP32-mixed vs FP64 plain; p50/p99 frame latency"
+STAGES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "match")
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def work_model(stage: str, n: int) -> tuple[str, float, str]:
+    """Algorithmic work of one launch of a stage: (bound, amount, unit).
+
+    Per-atom figures are derived in the design doc section 7: HBM bytes for the
+    memory-bound stages, FP64 floating-point operations for the arithmetic
+    stages (orientation-filter and superposition arithmetic only; integer
+    work of the canonical code is not counted, so the fraction is a lower
+    bound on VALU use).
+    """
+    K = {"topo6": 6, "topo12": 12, "topo14": 14}.get(stage)
+    if stage == "bin":
+        return "hbm", 92.0 * n, "bytes"
+    if stage == "bounds":
+        return "hbm", 24.0 * n, "bytes"
+    if stage == "knn":
+        # 27-cell search at ~8 atoms per cell: ~216 candidate distances of 20 FLOP
+        return "fp64", 216 * 20.0 * n, "flop"
+    if K is not None:
+        tests = 1 + (K - 1) * (K - 4)
+        return "fp64", (29.0 * tests + 20.0 * (2 * K - 4)) * n, "flop"
+    if stage == "match":
+        # ~4 candidates (paper's profile: 3.93 QCP solves per atom) of
+        # (9N covariance FMA + ~400 QCP + 21N residual) FLOP with N ~ 13
+        per_cand = 2 * 9 * 13 + 400 + 21 * 13
+        return "fp64", 4 * per_cand * n, "flop"
+    raise KeyError(stage)
+
+
+def build_frame(args):
+    from paper_1603_05143_amd import synthetic as S
+    t = time.time()
+    f = S.polycrystal()
+    return f, time.time() - t
+
+
+def run_gpu(frame, precision, steps, warmup):
+    import torch
+    from paper_1603_05143_amd import ptm
+    pos = torch.from_numpy(frame.positions).to("cuda:0")
+    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE)
+    out = ptm.Classifier.alloc_outputs(frame.n, "cuda:0")
+    o = ptm.Classifier.outputs_struct(out)
+
+    def step():
+        st = ptm.ptm_classify(ctx, pos.data_ptr(), None, frame.box, frame.n, ptm.PTM_ALL, math.inf, o)
+        if st != ptm.PTM_OK:
+            raise RuntimeError(ptm.ptm_last_error(ctx))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    acc = [0.0] * 7
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        st_ms = ptm.ptm_stage_times(ctx)
+        for i, s in enumerate(STAGES):
+            acc[i] += st_ms[s]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    types = torch.bincount(out["type"].long(), minlength=6).cpu().tolist()
+    ptm.ptm_destroy(ctx)
+    ms = (t1 - t0) * 1e3 / steps
+    return {"ms_per_step": ms, "atoms_per_s": frame.n / (ms / 1e3),
+            "stage_ms": {s: acc[i] / steps for i, s in enumerate(STAGES)}, "types": types}
+
+
+def cpu_baseline(frame, sample):
+    import numpy as np
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    rng = np.random.default_rng(2024)
+    atoms = np.sort(rng.choice(frame.n, sample, replace=False))
+    oracle.lib()
+    t = time.perf_counter()
+    oracle.classify(frame.positions, frame.box, atoms=atoms, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": sample / dt, "unit": "atoms/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample} seeded atoms of the {frame.n}-atom polycrystal, each classified "
+                      f"with brute-force neighbours over all atoms ({dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch  # noqa: F401  (loads the HIP runtime shared with libptm)
+    from paper_1603_05143_amd import ptm
+
+    frame, gen_s = build_frame(args)
+    print(f"[bench] frame n={frame.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    r64 = run_gpu(frame, ptm.PTM_FP64, args.steps, args.warmup)
+    print(f"[bench] fp64 {r64['ms_per_step']:.2f} ms/step {r64['stage_ms']}", file=sys.stderr, flush=True)
+    main_run = r64
+    dtype = "f64"
+
+    stage_ms = main_run["stage_ms"]
+    dom = max((s for s in STAGES if s != "bounds"), key=lambda s: stage_ms[s])
+    bound, work, unit = work_model(dom, frame.n)
+    t = stage_ms[dom] / 1e3
+    if bound == "hbm":
+        achieved = work / t / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        achieved = work / t / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["kernel_ms"] = stage_ms[dom]
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(frame, args.cpu_sample)
+        print(f"[bench] cpu oracle {cpu['value']:.0f} atoms/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+
+    line = {
+        "metric": METRIC, "value": main_run["atoms_per_s"], "unit": "atoms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": "periodic Voronoi polycrystal, L=220 A, 16 grains FCC 3.615/BCC 2.87/HCP 2.51 "
+                               "(c/a 1.633), sigma 0.10 A, all templates",
+                   "n_atoms": frame.n, "template_mask": "SC|FCC|HCP|ICO|BCC", "rmsd_cutoff": "inf"},
+        "fp64_atoms_per_s": r64["atoms_per_s"],
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "types": dict(zip(ptm.TYPE_NAMES, main_run["types"])),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

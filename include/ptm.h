@@ -69,7 +69,12 @@ enum { PTM_ALLOY_NONE = 0, PTM_ALLOY_A1 = 1, PTM_ALLOY_L10 = 2, PTM_ALLOY_L12_MA
        PTM_ALLOY_BCC_OTHER = 8 };
 
 /* context flags */
-enum { PTM_F_HOST_POINTERS = 1u << 0 };
+enum { PTM_F_HOST_POINTERS = 1u << 0, /* inputs/outputs are host pointers (staged through HBM) */
+       PTM_F_PROFILE = 1u << 1 };     /* record HIP events between pipeline stages */
+
+/* pipeline stages reported by ptm_stage_times */
+enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2, PTM_STAGE_TOPO6 = 3, PTM_STAGE_TOPO12 = 4,
+       PTM_STAGE_TOPO14 = 5, PTM_STAGE_MATCH = 6, PTM_NSTAGES = 7 };
 
 typedef struct {
     int device;                /* HIP device ordinal */
@@ -80,7 +85,8 @@ typedef struct {
 } ptm_config;
 
 /* Per-atom outputs, n entries each (arrays with a second dimension are
- * row-major [n][m]).  Every pointer except type may be NULL to skip it. */
+ * row-major [n][m]).  Every pointer except type may be NULL to skip it
+ * (type too when n == 0). */
 typedef struct {
     int8_t *type;        /* PTM_TYPE_*: best template if its RMSD <= rmsd_cutoff, else NONE      */
     int8_t *alloy;       /* PTM_ALLOY_*; NONE when species == NULL or type not FCC/BCC            */
@@ -146,6 +152,13 @@ const char *ptm_status_string(ptm_status s);
 
 /* Last error message of a context (empty string if none; never NULL). */
 const char *ptm_last_error(const ptm_ctx *ctx);
+
+/* Device time in milliseconds of each pipeline stage of the most recent
+ * ptm_classify on a context created with PTM_F_PROFILE, measured with HIP
+ * events on the stream the kernels run on: ms[PTM_STAGE_*] for
+ * min(n, PTM_NSTAGES) entries (0 for a stage that did not run).
+ * PTM_E_INVALID if the context was not created with PTM_F_PROFILE. */
+ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n);
 
 /* Template facts of the library's own tables, for checks without a device:
  * info[0]=k, info[1]=rotation group order, info[2]=triangulations,

@@ -156,16 +156,24 @@ Grid make_grid(const double box[3], const double mn[3], const double mx[3], int6
 }
 
 // Enqueue the whole pipeline for one frame whose bounds are known.
-ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st) {
+ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st, bool prof) {
     const int64_t n = J.n;
+    auto mark = [&](int e) -> ptm_status {
+        if (prof) PTM_HIP(ctx, hipEventRecord(ctx->prof_ev[e], st));
+        return PTM_OK;
+    };
+    ptm_status ps;
     const Grid &g = J.grid;
+    if ((ps = mark(PTM_STAGE_BIN)) != PTM_OK) return ps;
     int64_t cells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 1), st));
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
     size_t tmp = S.scan_tmp_bytes;
     PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
     launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.sx, S.sy, S.sz, S.sid, st);
+    if ((ps = mark(PTM_STAGE_KNN)) != PTM_OK) return ps;
     launch_knn(n, g, J.pos, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, st);
+    if ((ps = mark(PTM_STAGE_TOPO6)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
     const bool need[NGRP] = {(m & 0x1u) != 0, (m & 0xEu) != 0, (m & 0x10u) != 0};
     for (int grp = 0; grp < NGRP; grp++) {
@@ -174,9 +182,12 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
                         S.ord + (int64_t)grp * n, st);
         else
             PTM_HIP(ctx, hipMemsetAsync(S.code + (int64_t)grp * n, 0xFF, 4 * (size_t)n, st));
+        if (prof) ctx->prof_ran[PTM_STAGE_TOPO6 + grp] = need[grp];
+        if ((ps = mark(PTM_STAGE_TOPO6 + grp + 1)) != PTM_OK) return ps;
     }
     MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
     launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, st);
+    if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;
 }
@@ -308,6 +319,12 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
         }
         ctx->own_stream = true;
     }
+    if (ctx->flags & PTM_F_PROFILE)
+        for (int e = 0; e <= PTM_NSTAGES; e++)
+            if (hipEventCreate(&ctx->prof_ev[e]) != hipSuccess) {
+                ptm_destroy(ctx);
+                return PTM_E_DEVICE;
+            }
     std::string err;
     if (!build_tables(ctx->host, err)) {
         ptm_destroy(ctx);
@@ -330,6 +347,8 @@ void ptm_destroy(ptm_ctx *ctx) {
     ctx->main.release();
     ctx->staging.release();
     for (void *p : ctx->table_buffers) (void)hipFree(p);
+    for (int e = 0; e <= PTM_NSTAGES; e++)
+        if (ctx->prof_ev[e]) (void)hipEventDestroy(ctx->prof_ev[e]);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -355,6 +374,9 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
     if (!ctx->main.reserve(n_atoms, 1, ctx->err)) return PTM_E_NOMEM;
     double mn[3], mx[3];
     bool bad = false;
+    const bool prof = (ctx->flags & PTM_F_PROFILE) != 0;
+    ctx->prof_valid = false;
+    if (prof) PTM_HIP(ctx, hipEventRecord(ctx->prof_ev[PTM_STAGE_BOUNDS], ctx->stream));
     st = frame_bounds(ctx, ctx->main, J.pos, n_atoms, mn, mx, bad, ctx->stream);
     if (st != PTM_OK) return st;
     if (bad) {
@@ -368,11 +390,28 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
         return PTM_E_NOMEM;
     }
     if (!ctx->main.reserve(n_atoms, cells, ctx->err)) return PTM_E_NOMEM;
-    st = enqueue_frame(ctx, ctx->main, J, ctx->stream);
+    st = enqueue_frame(ctx, ctx->main, J, ctx->stream, prof);
     if (st != PTM_OK) return st;
     st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
     if (st != PTM_OK) return st;
     PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->prof_valid = prof;
+    return PTM_OK;
+}
+
+ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n) {
+    if (!ctx || !ms || n < 0 || !(ctx->flags & PTM_F_PROFILE)) return PTM_E_INVALID;
+    for (int i = 0; i < n && i < PTM_NSTAGES; i++) {
+        ms[i] = 0.0;
+        if (!ctx->prof_valid) continue;
+        if (i >= PTM_STAGE_TOPO6 && i <= PTM_STAGE_TOPO14 && !ctx->prof_ran[i]) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ctx->prof_ev[i], ctx->prof_ev[i + 1]) != hipSuccess) {
+            (void)hipGetLastError();
+            return PTM_E_DEVICE;
+        }
+        ms[i] = t;
+    }
     return PTM_OK;
 }
 

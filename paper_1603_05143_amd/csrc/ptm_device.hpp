@@ -170,7 +170,10 @@ __host__ __device__ inline int sos_lambda4_sorted(const double *p0, const double
 
 // orientation of (a,b,c,d) := det[b-a; c-a; d-a] (> 0: d on the side the
 // normal (b-a)x(c-a) points to), exactly, with SoS by the ranks ra..rd
-PTM_HD int orient_exact_sos(const double *a, const double *b, const double *c, const double *d, int ra,
+#ifdef __HIP_DEVICE_COMPILE__
+__attribute__((noinline))
+#endif
+__host__ __device__ inline int orient_exact_sos(const double *a, const double *b, const double *c, const double *d, int ra,
                             int rb, int rc, int rd) {
     int s = lambda4_sign_exact(a, b, c, d);
     if (s) return -s;

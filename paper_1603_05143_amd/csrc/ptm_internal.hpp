@@ -83,7 +83,8 @@ struct Ticket {
 size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp);
 int bounds_blocks(int64_t n);
 Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n);
-ptm_status enqueue_frame(struct ::ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st);
+ptm_status enqueue_frame(struct ::ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st,
+                         bool prof = false);
 ptm_status frame_bounds(struct ::ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_t n, double mn[3],
                         double mx[3], bool &bad, hipStream_t st);
 ptm_status validate(struct ::ptm_ctx *ctx, const double *positions, const double *box, int64_t n, double cutoff,
@@ -125,4 +126,8 @@ struct ptm_ctx {
     uint64_t next_ticket = 1;
     size_t inflight_bytes = 0;
     int next_stream = 0;
+    // stage profiling (PTM_F_PROFILE)
+    hipEvent_t prof_ev[PTM_NSTAGES + 1] = {};
+    bool prof_valid = false;
+    bool prof_ran[PTM_NSTAGES] = {};
 };

@@ -254,10 +254,12 @@ constexpr int TB = 64;  // threads per block of the topology kernel
 
 template <int K>
 struct TopoShared {
-    double P[3][K][TB];
+    union {
+        double P[3][K][TB];   // neighbour vectors (hull phase)
+        uint64_t NT[K][TB];   // rotation system (code phase)
+    };
     uint32_t F[2 * K - 4][TB];
     uint16_t H[K][TB];
-    uint64_t NT[K][TB];
 };
 
 // facet word: v0 | v1<<4 | v2<<8 | nb0<<12 | nb1<<17 | nb2<<22
@@ -284,6 +286,18 @@ __device__ inline int lane_orient(TopoShared<K> &S, int t, int a, int b, int c, 
     return orient_sos64(pa, pb, pc, pd, a, b, c, d);
 }
 
+// orientation of facet (a,b,c) against the point p held in registers
+template <int K>
+__device__ inline int lane_orient_p(TopoShared<K> &S, int t, int a, int b, int c, const double (&pp)[3], int p) {
+    double pa[3], pb[3], pc[3];
+    for (int k = 0; k < 3; k++) {
+        pa[k] = S.P[k][a][t];
+        pb[k] = S.P[k][b][t];
+        pc[k] = S.P[k][c][t];
+    }
+    return orient_sos64(pa, pb, pc, pp, a, b, c, p);
+}
+
 // returns 1 if the hull is valid (all K points vertices, centre strictly
 // inside); the facets are left in S.F[0 .. 2K-5]
 template <int K>
@@ -298,9 +312,10 @@ __device__ int lane_hull(TopoShared<K> &S, int t) {
     for (int p = 4; p < K; p++) {
         uint32_t vis = 0;
         int nvis = 0;
+        const double pp[3] = {S.P[0][p][t], S.P[1][p][t], S.P[2][p][t]};
         for (int f = 0; f < nf; f++) {
             uint32_t w = S.F[f][t];
-            if (lane_orient<K>(S, t, fv(w, 0), fv(w, 1), fv(w, 2), p) > 0) {
+            if (lane_orient_p<K>(S, t, fv(w, 0), fv(w, 1), fv(w, 2), pp, p) > 0) {
                 vis |= 1u << f;
                 nvis++;
             }
@@ -376,45 +391,89 @@ __device__ int lane_hull(TopoShared<K> &S, int t) {
     return 1;
 }
 
-// canonical code (see ptm_tables.cpp for the definition); best[] receives the
-// K rows, the return value the labelling (nibble l = vertex of label l)
+// canonical code (definition in ptm_tables.cpp): signature word of every
+// start edge from a minimum-degree vertex, then the BFS rows only for the
+// start edges of minimum signature.  best[] receives the K words; the return
+// value is the labelling (nibble l = vertex of label l).  Each lane walks a
+// compact list of its own start edges, so the wave does not iterate over
+// vertex pairs that no lane needs.
 template <int K>
 __device__ uint64_t lane_canonical(TopoShared<K> &S, int t, uint64_t degs, uint64_t (&best)[K]) {
     int mindeg = 15;
+#pragma unroll
     for (int x = 0; x < K; x++) mindeg = min(mindeg, (int)nib(degs, x));
+    uint32_t mdmask = 0;
+#pragma unroll
+    for (int x = 0; x < K; x++) mdmask |= (uint32_t)(nib(degs, x) == (uint32_t)mindeg) << x;
+    // pass 1: minimum signature over start edges (u, v), deg(u) = mindeg
+    uint64_t minsig = ~0ull;
+    for (uint32_t m = mdmask; m; m &= m - 1) {
+        int u = __builtin_ctz(m);
+        uint64_t ntu = S.NT[u][t];
+        int v0 = 0;
+        while (nib(ntu, v0) == 0xF) v0++;
+        uint64_t dg = 0;  // degrees of u's neighbours, counter-clockwise from v0
+        int w = v0;
+        for (int j = 0; j < mindeg; j++) {
+            dg |= (uint64_t)nib(degs, w) << (4 * j);
+            w = (int)nib(ntu, w);
+        }
+        for (int r = 0; r < mindeg; r++) {
+            uint64_t sig = (uint64_t)mindeg << 60;
+            for (int j = 0; j < mindeg; j++) sig |= (uint64_t)nib(dg, (r + j) % mindeg) << (56 - 4 * j);
+            minsig = min(minsig, sig);
+        }
+    }
+    best[0] = minsig;
+    // pass 2: BFS rows of the minimum-signature start edges
     bool have = false;
     uint64_t best_ord = 0;
-    for (int u = 0; u < K; u++) {
-        if ((int)nib(degs, u) != mindeg) continue;
+    for (uint32_t m = mdmask; m; m &= m - 1) {
+        int u = __builtin_ctz(m);
         uint64_t ntu = S.NT[u][t];
-        for (int v = 0; v < K; v++) {
-            if (nib(ntu, v) == 0xF) continue;
-            uint64_t lab = ~0ull, ord = 0, par = 0;
+        int v0 = 0;
+        while (nib(ntu, v0) == 0xF) v0++;
+        uint64_t dg = 0;
+        int w = v0;
+        for (int j = 0; j < mindeg; j++) {
+            dg |= (uint64_t)nib(degs, w) << (4 * j);
+            w = (int)nib(ntu, w);
+        }
+        int v = v0;
+        for (int r = 0; r < mindeg; r++, v = (int)nib(ntu, v)) {
+            uint64_t sig = (uint64_t)mindeg << 60;
+            for (int j = 0; j < mindeg; j++) sig |= (uint64_t)nib(dg, (r + j) % mindeg) << (56 - 4 * j);
+            if (sig != minsig) continue;
+            uint64_t lab = ~0ull, ord = (uint64_t)u, par = 0;
             lab = setnib(lab, u, 0);
-            lab = setnib(lab, v, 1);
-            ord = (uint64_t)u | ((uint64_t)v << 4);
-            par = setnib(par, v, u);
-            uint32_t nl = 2;
+            int y = v;
+            for (int j = 0; j < mindeg; j++) {
+                lab = setnib(lab, y, j + 1);
+                ord = setnib(ord, j + 1, y);
+                par = setnib(par, y, u);
+                y = (int)nib(ntu, y);
+            }
+            uint32_t nl = mindeg + 1;
             int state = have ? 0 : -1;  // 0 equal so far, -1 smaller, +1 larger
 #pragma unroll
-            for (int i = 0; i < K; i++) {
+            for (int i = 1; i < K; i++) {
                 if (state <= 0) {
                     int x = min((int)nib(ord, i), K - 1);
-                    int y = (i == 0) ? v : (int)nib(par, x);
+                    int yy = (int)nib(par, x);
                     uint64_t ntx = S.NT[x][t];
                     int dx = (int)nib(degs, x);
                     uint64_t row = (uint64_t)dx << 60;
                     for (int j = 0; j < dx; j++) {
-                        uint32_t ly = nib(lab, y);
+                        uint32_t ly = nib(lab, yy);
                         if (ly == 0xF) {
                             ly = nl;
-                            lab = setnib(lab, y, nl);
-                            ord = setnib(ord, nl, y);
-                            par = setnib(par, y, x);
+                            lab = setnib(lab, yy, nl);
+                            ord = setnib(ord, nl, yy);
+                            par = setnib(par, yy, x);
                             nl++;
                         }
                         row |= (uint64_t)ly << (56 - 4 * j);
-                        y = min((int)nib(ntx, y), K - 1);
+                        yy = min((int)nib(ntx, yy), K - 1);
                     }
                     if (state == 0) state = (row < best[i]) ? -1 : (row > best[i] ? 1 : 0);
                     if (state < 0) best[i] = row;

@@ -197,28 +197,46 @@ std::vector<std::vector<int>> shell_faces(const std::vector<V3> &w) {
 
 }  // namespace
 
-// BFS-row canonical code.  From the directed start edge u->v: u gets label
-// 0, v label 1; vertices are processed in label order; vertex x emits one
-// 64-bit row: its degree in the top nibble, then the labels of its
-// neighbours in counter-clockwise order starting from its reference
-// neighbour (v for u, else the vertex that labelled x), assigning new labels
-// in that order.  The code is the sequence of k rows; the canonical code is
-// the lexicographic minimum over all start edges (only start vertices of
-// minimum degree can reach it).  Rows determine the labelled rotation
-// system, so equal codes <=> orientation-preserving isomorphism.
-static void bfs_code(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_t *rows,
-                     uint64_t *ordp) {
+// Canonical code of a triangulated sphere, from a directed start edge u->v.
+//   word 0 (signature): deg(u) in the top nibble, then deg(v), then the
+//     degrees of u's other neighbours in counter-clockwise order after v;
+//   words 1..k-1 (BFS rows): u gets label 0 and its neighbours labels
+//     1..deg(u) counter-clockwise from v; vertices are then processed in
+//     label order and vertex x (label i >= 1) emits one row: deg(x) in the
+//     top nibble, then the labels of its neighbours counter-clockwise from
+//     the vertex that labelled x, new vertices being labelled in that order.
+// The canonical code is the lexicographic minimum over all start edges;
+// only start edges of minimum signature need their rows.  The words
+// determine the labelled rotation system, so equal codes <=>
+// orientation-preserving isomorphism.
+static uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u, int v) {
+    (void)k;
+    uint64_t sig = ((uint64_t)deg[u] << 60) | ((uint64_t)deg[v] << 56);
+    int w = v;
+    for (int j = 1; j < deg[u]; j++) {
+        w = (int)((nxt[u] >> (4 * w)) & 0xF);
+        sig |= (uint64_t)deg[w] << (56 - 4 * j);
+    }
+    return sig;
+}
+
+static void bfs_rows(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_t *rows, uint64_t *ordp) {
     int lab[KMAX], ord[KMAX], par[KMAX];
     for (int i = 0; i < k; i++) lab[i] = -1;
     lab[u] = 0;
-    lab[v] = 1;
     ord[0] = u;
-    ord[1] = v;
-    par[v] = u;
-    int nl = 2;
-    for (int i = 0; i < k; i++) {
+    int nl = 1, y = v;
+    for (int j = 0; j < deg[u]; j++) {
+        lab[y] = nl;
+        ord[nl] = y;
+        par[y] = u;
+        nl++;
+        y = (int)((nxt[u] >> (4 * y)) & 0xF);
+    }
+    rows[0] = dart_signature(k, nxt, deg, u, v);
+    for (int i = 1; i < k; i++) {
         int x = ord[i];
-        int y = (i == 0) ? v : par[x];
+        y = par[x];
         uint64_t row = (uint64_t)deg[x] << 60;
         for (int j = 0; j < deg[x]; j++) {
             if (lab[y] < 0) {
@@ -239,16 +257,19 @@ static void bfs_code(int k, const uint64_t *nxt, const int *deg, int u, int v, u
 
 int canonical_code_host(int k, const uint64_t *nxt, const int *deg, uint64_t *rows,
                         std::vector<uint64_t> &labellings) {
-    int mindeg = 99;
-    for (int x = 0; x < k; x++) mindeg = std::min(mindeg, deg[x]);
+    uint64_t minsig = ~0ull;
+    for (int u = 0; u < k; u++)
+        for (int v = 0; v < k; v++)
+            if (v != u && ((nxt[u] >> (4 * v)) & 0xF) != 0xF)
+                minsig = std::min(minsig, dart_signature(k, nxt, deg, u, v));
     bool have = false;
     uint64_t cur[KMAX], ordw;
     labellings.clear();
-    for (int u = 0; u < k; u++) {
-        if (deg[u] != mindeg) continue;
+    for (int u = 0; u < k; u++)
         for (int v = 0; v < k; v++) {
             if (v == u || ((nxt[u] >> (4 * v)) & 0xF) == 0xF) continue;
-            bfs_code(k, nxt, deg, u, v, cur, &ordw);
+            if (dart_signature(k, nxt, deg, u, v) != minsig) continue;
+            bfs_rows(k, nxt, deg, u, v, cur, &ordw);
             int c = 0;
             if (have)
                 for (int i = 0; i < k && c == 0; i++)
@@ -261,7 +282,6 @@ int canonical_code_host(int k, const uint64_t *nxt, const int *deg, uint64_t *ro
             }
             if (c == 0) labellings.push_back(ordw);
         }
-    }
     return (int)labellings.size();
 }
 

@@ -18,6 +18,8 @@ PTM_FP64, PTM_FP32_MIXED = 0, 1
 PTM_SC, PTM_FCC, PTM_HCP, PTM_ICO, PTM_BCC = 1, 2, 4, 8, 16
 PTM_ALL = 0x1F
 PTM_F_HOST_POINTERS = 1
+PTM_F_PROFILE = 2
+STAGE_NAMES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "match")
 TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
 ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")
 
@@ -71,6 +73,8 @@ def lib():
         L.ptm_last_error.restype = C.c_char_p
         L.ptm_template_info.argtypes = [C.c_int, C.POINTER(C.c_int64)]
         L.ptm_template_info.restype = C.c_int
+        L.ptm_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.c_int]
+        L.ptm_stage_times.restype = C.c_int
         _lib = L
     return _lib
 
@@ -115,6 +119,15 @@ def ptm_wait(ctx, ticket, timeout_us=-1):
     s = ptm_frame_stats()
     st = lib().ptm_wait(ctx, C.c_uint64(ticket), int(timeout_us), C.byref(s))
     return st, s
+
+
+def ptm_stage_times(ctx):
+    """Stage times (ms) of the last ptm_classify on a PTM_F_PROFILE context."""
+    ms = (C.c_double * len(STAGE_NAMES))()
+    st = lib().ptm_stage_times(ctx, ms, len(STAGE_NAMES))
+    if st != PTM_OK:
+        raise PTMError(st, "ptm_stage_times")
+    return dict(zip(STAGE_NAMES, list(ms)))
 
 
 def ptm_template_info(t: int):
