@@ -162,8 +162,9 @@ ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n);
 
 /* Template facts of the library's own tables, for checks without a device:
  * info[0]=k, info[1]=rotation group order, info[2]=triangulations,
- * info[3]=distinct canonical codes, info[4]=candidates kept after symmetry
- * reduction (App. A).  Returns PTM_E_INVALID for t outside 0..4. */
+ * info[3]=distinct table keys (orientation-preserving start-edge codes of
+ * the triangulations), info[4]=candidate correspondences kept after the
+ * reduction by the template's rotation group (App. A).  Returns PTM_E_INVALID for t outside 0..4. */
 ptm_status ptm_template_info(int t, int64_t info[5]);
 
 #ifdef __cplusplus

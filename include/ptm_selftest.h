@@ -22,12 +22,16 @@ int ptm_selftest_orient(const double *p12, const int32_t *ranks4);
 /* Exact sign (-1/0/+1) of det[a; b; c] for the rows of p9[3][3]. */
 int ptm_selftest_det3(const double *p9);
 
-/* Canonical code of a triangulated sphere with k <= 14 vertices given as
- * ntri outward counter-clockwise triangles (int32 [ntri][3]).  rows[k]
- * receives the code, *n_auto the number of labellings reaching it.
- * Returns 0 on success, -1 if the triangles are not a closed oriented
+/* Key set of a triangulated sphere with k <= 14 vertices given as ntri
+ * outward counter-clockwise triangles (int32 [ntri][3]): the start-edge
+ * codes (k words each) of its start edges of minimum signature, in the
+ * order the topology kernel scans them (the first is the one the kernel
+ * looks up).  Writes up to max_codes codes to codes[max_codes][k] and their
+ * number to *n_codes.  Isomorphic graphs have equal key sets and the first
+ * code of a graph lies in the key set of exactly the graphs isomorphic to
+ * it.  Returns 0, or -1 if the triangles are not a closed oriented
  * triangulation. */
-int ptm_selftest_canonical(int k, const int32_t *tris, int ntri, uint64_t *rows, int32_t *n_auto);
+int ptm_selftest_codes(int k, const int32_t *tris, int ntri, uint64_t *codes, int max_codes, int32_t *n_codes);
 
 /* Eq. (3) superposition for a fixed correspondence with the library's QCP
  * solver: obs and tpl are [N][3] (N <= 15, not centred / not normalised).

@@ -430,7 +430,7 @@ int ptm_selftest_orient(const double *p, const int32_t *r) {
 
 int ptm_selftest_det3(const double *p) { return det3_sign64(p, p + 3, p + 6); }
 
-int ptm_selftest_canonical(int k, const int32_t *tris, int ntri, uint64_t *rows, int32_t *n_auto) {
+int ptm_selftest_codes(int k, const int32_t *tris, int ntri, uint64_t *codes, int max_codes, int32_t *n_codes) {
     if (k < 4 || k > KMAX || ntri != 2 * k - 4) return -1;
     uint64_t nxt[KMAX];
     int deg[KMAX] = {0};
@@ -444,8 +444,15 @@ int ptm_selftest_canonical(int k, const int32_t *tris, int ntri, uint64_t *rows,
             nxt[a] |= (uint64_t)c << (4 * b);
             deg[a]++;
         }
-    std::vector<uint64_t> labs;
-    *n_auto = canonical_code_host(k, nxt, deg, rows, labs);
+    auto darts = min_signature_darts(k, nxt, deg);
+    int m = 0;
+    for (auto &d : darts) {
+        if (m >= max_codes) break;
+        uint64_t ord;
+        dart_code(k, nxt, deg, d.first, d.second, codes + (size_t)m * k, &ord);
+        m++;
+    }
+    *n_codes = (int32_t)darts.size();
     return 0;
 }
 

@@ -8,7 +8,7 @@
 //   k_knn         14 nearest neighbours by (d^2, id), Sec. 3 Euclidean order
 //   k_topo<K>     hull of the innermost K = 6 / 12 / 14 neighbours with
 //                 exact predicates (Sec. 4; Alg. 1 requires the centre
-//                 strictly inside), canonical code, template table lookup
+//                 strictly inside), start-edge code, template table lookup
 //   k_match       superposition over the candidates (eqs. 2-4), decision
 //                 (Alg. 1), representative, strain (eq. 6, Sec. 8), alloy
 //                 (Sec. 6, Table 3), write-back in input order
@@ -391,22 +391,22 @@ __device__ int lane_hull(TopoShared<K> &S, int t) {
     return 1;
 }
 
-// canonical code (definition in ptm_tables.cpp): signature word of every
-// start edge from a minimum-degree vertex, then the BFS rows only for the
-// start edges of minimum signature.  best[] receives the K words; the return
-// value is the labelling (nibble l = vertex of label l).  Each lane walks a
-// compact list of its own start edges, so the wave does not iterate over
-// vertex pairs that no lane needs.
+// Start-edge code (definition in ptm_tables.cpp) of the first start edge
+// of minimum signature in scan order (u ascending over the minimum-degree
+// vertices, v counter-clockwise from u's lowest-numbered neighbour).
+// code[] receives the K words; the return value is the labelling (nibble
+// l = vertex of label l).  One code per hull: the tables hold every
+// minimum-signature start edge of every template triangulation.
 template <int K>
-__device__ uint64_t lane_canonical(TopoShared<K> &S, int t, uint64_t degs, uint64_t (&best)[K]) {
+__device__ uint64_t lane_start_edge_code(TopoShared<K> &S, int t, uint64_t degs, uint64_t (&code)[K]) {
     int mindeg = 15;
 #pragma unroll
     for (int x = 0; x < K; x++) mindeg = min(mindeg, (int)nib(degs, x));
     uint32_t mdmask = 0;
 #pragma unroll
     for (int x = 0; x < K; x++) mdmask |= (uint32_t)(nib(degs, x) == (uint32_t)mindeg) << x;
-    // pass 1: minimum signature over start edges (u, v), deg(u) = mindeg
     uint64_t minsig = ~0ull;
+    int bu = 0, bv = 0;
     for (uint32_t m = mdmask; m; m &= m - 1) {
         int u = __builtin_ctz(m);
         uint64_t ntu = S.NT[u][t];
@@ -418,74 +418,51 @@ __device__ uint64_t lane_canonical(TopoShared<K> &S, int t, uint64_t degs, uint6
             dg |= (uint64_t)nib(degs, w) << (4 * j);
             w = (int)nib(ntu, w);
         }
-        for (int r = 0; r < mindeg; r++) {
-            uint64_t sig = (uint64_t)mindeg << 60;
-            for (int j = 0; j < mindeg; j++) sig |= (uint64_t)nib(dg, (r + j) % mindeg) << (56 - 4 * j);
-            minsig = min(minsig, sig);
-        }
-    }
-    best[0] = minsig;
-    // pass 2: BFS rows of the minimum-signature start edges
-    bool have = false;
-    uint64_t best_ord = 0;
-    for (uint32_t m = mdmask; m; m &= m - 1) {
-        int u = __builtin_ctz(m);
-        uint64_t ntu = S.NT[u][t];
-        int v0 = 0;
-        while (nib(ntu, v0) == 0xF) v0++;
-        uint64_t dg = 0;
-        int w = v0;
-        for (int j = 0; j < mindeg; j++) {
-            dg |= (uint64_t)nib(degs, w) << (4 * j);
-            w = (int)nib(ntu, w);
-        }
         int v = v0;
         for (int r = 0; r < mindeg; r++, v = (int)nib(ntu, v)) {
             uint64_t sig = (uint64_t)mindeg << 60;
             for (int j = 0; j < mindeg; j++) sig |= (uint64_t)nib(dg, (r + j) % mindeg) << (56 - 4 * j);
-            if (sig != minsig) continue;
-            uint64_t lab = ~0ull, ord = (uint64_t)u, par = 0;
-            lab = setnib(lab, u, 0);
-            int y = v;
-            for (int j = 0; j < mindeg; j++) {
-                lab = setnib(lab, y, j + 1);
-                ord = setnib(ord, j + 1, y);
-                par = setnib(par, y, u);
-                y = (int)nib(ntu, y);
-            }
-            uint32_t nl = mindeg + 1;
-            int state = have ? 0 : -1;  // 0 equal so far, -1 smaller, +1 larger
-#pragma unroll
-            for (int i = 1; i < K; i++) {
-                if (state <= 0) {
-                    int x = min((int)nib(ord, i), K - 1);
-                    int yy = (int)nib(par, x);
-                    uint64_t ntx = S.NT[x][t];
-                    int dx = (int)nib(degs, x);
-                    uint64_t row = (uint64_t)dx << 60;
-                    for (int j = 0; j < dx; j++) {
-                        uint32_t ly = nib(lab, yy);
-                        if (ly == 0xF) {
-                            ly = nl;
-                            lab = setnib(lab, yy, nl);
-                            ord = setnib(ord, nl, yy);
-                            par = setnib(par, yy, x);
-                            nl++;
-                        }
-                        row |= (uint64_t)ly << (56 - 4 * j);
-                        yy = min((int)nib(ntx, yy), K - 1);
-                    }
-                    if (state == 0) state = (row < best[i]) ? -1 : (row > best[i] ? 1 : 0);
-                    if (state < 0) best[i] = row;
-                }
-            }
-            if (state < 0) {
-                best_ord = ord;
-                have = true;
+            if (sig < minsig) {
+                minsig = sig;
+                bu = u;
+                bv = v;
             }
         }
     }
-    return best_ord;
+    code[0] = minsig;
+    uint64_t ntu = S.NT[bu][t];
+    uint64_t lab = ~0ull, ord = (uint64_t)bu, par = 0;
+    lab = setnib(lab, bu, 0);
+    int y = bv;
+    for (int j = 0; j < mindeg; j++) {
+        lab = setnib(lab, y, j + 1);
+        ord = setnib(ord, j + 1, y);
+        par = setnib(par, y, bu);
+        y = (int)nib(ntu, y);
+    }
+    uint32_t nl = mindeg + 1;
+#pragma unroll
+    for (int i = 1; i < K; i++) {
+        int x = min((int)nib(ord, i), K - 1);
+        int yy = (int)nib(par, x);
+        uint64_t ntx = S.NT[x][t];
+        int dx = (int)nib(degs, x);
+        uint64_t row = (uint64_t)dx << 60;
+        for (int j = 0; j < dx; j++) {
+            uint32_t ly = nib(lab, yy);
+            if (ly == 0xF) {
+                ly = nl;
+                lab = setnib(lab, yy, nl);
+                ord = setnib(ord, nl, yy);
+                par = setnib(par, yy, x);
+                nl++;
+            }
+            row |= (uint64_t)ly << (56 - 4 * j);
+            yy = min((int)nib(ntx, yy), K - 1);
+        }
+        code[i] = row;
+    }
+    return ord;
 }
 
 template <int K>
@@ -514,9 +491,7 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
                 degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
             }
             uint64_t best[K];
-#pragma unroll
-            for (int i = 0; i < K; i++) best[i] = ~0ull;
-            uint64_t ord = lane_canonical<K>(S, t, degs, best);
+            uint64_t ord = lane_start_edge_code<K>(S, t, degs, best);
             // table lookup with full-code verification
             uint64_t h = code_hash(best, K);
             int mask = T.hmask[grp];

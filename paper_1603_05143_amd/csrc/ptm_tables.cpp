@@ -197,7 +197,7 @@ std::vector<std::vector<int>> shell_faces(const std::vector<V3> &w) {
 
 }  // namespace
 
-// Canonical code of a triangulated sphere, from a directed start edge u->v.
+// Start-edge code of a triangulated sphere, from a directed edge u->v.
 //   word 0 (signature): deg(u) in the top nibble, then deg(v), then the
 //     degrees of u's other neighbours in counter-clockwise order after v;
 //   words 1..k-1 (BFS rows): u gets label 0 and its neighbours labels
@@ -205,11 +205,14 @@ std::vector<std::vector<int>> shell_faces(const std::vector<V3> &w) {
 //     label order and vertex x (label i >= 1) emits one row: deg(x) in the
 //     top nibble, then the labels of its neighbours counter-clockwise from
 //     the vertex that labelled x, new vertices being labelled in that order.
-// The canonical code is the lexicographic minimum over all start edges;
-// only start edges of minimum signature need their rows.  The words
-// determine the labelled rotation system, so equal codes <=>
-// orientation-preserving isomorphism.
-static uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u, int v) {
+// The words determine the labelled rotation system.  A graph's key set is
+// the set of codes of its start edges of minimum signature; isomorphisms
+// map such start edges onto each other, so the code of any one of them is
+// found in the key set of every graph it is isomorphic to (and in no
+// other), and pairing the labellings of the two start edges gives the
+// isomorphism.  The tables hold the key sets of all template
+// triangulations; a hull needs the code of a single start edge.
+uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u, int v) {
     (void)k;
     uint64_t sig = ((uint64_t)deg[u] << 60) | ((uint64_t)deg[v] << 56);
     int w = v;
@@ -220,7 +223,7 @@ static uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u
     return sig;
 }
 
-static void bfs_rows(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_t *rows, uint64_t *ordp) {
+void dart_code(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_t *rows, uint64_t *ordp) {
     int lab[KMAX], ord[KMAX], par[KMAX];
     for (int i = 0; i < k; i++) lab[i] = -1;
     lab[u] = 0;
@@ -255,34 +258,27 @@ static void bfs_rows(int k, const uint64_t *nxt, const int *deg, int u, int v, u
     *ordp = o;
 }
 
-int canonical_code_host(int k, const uint64_t *nxt, const int *deg, uint64_t *rows,
-                        std::vector<uint64_t> &labellings) {
+// Start edges of minimum signature, in the order the kernel scans them:
+// u ascending, then v counter-clockwise around u from its lowest-numbered
+// neighbour.  The first one is the start edge the kernel uses.
+std::vector<std::pair<int, int>> min_signature_darts(int k, const uint64_t *nxt, const int *deg) {
     uint64_t minsig = ~0ull;
-    for (int u = 0; u < k; u++)
-        for (int v = 0; v < k; v++)
-            if (v != u && ((nxt[u] >> (4 * v)) & 0xF) != 0xF)
-                minsig = std::min(minsig, dart_signature(k, nxt, deg, u, v));
-    bool have = false;
-    uint64_t cur[KMAX], ordw;
-    labellings.clear();
-    for (int u = 0; u < k; u++)
-        for (int v = 0; v < k; v++) {
-            if (v == u || ((nxt[u] >> (4 * v)) & 0xF) == 0xF) continue;
-            if (dart_signature(k, nxt, deg, u, v) != minsig) continue;
-            bfs_rows(k, nxt, deg, u, v, cur, &ordw);
-            int c = 0;
-            if (have)
-                for (int i = 0; i < k && c == 0; i++)
-                    if (cur[i] != rows[i]) c = cur[i] < rows[i] ? -1 : 1;
-            if (!have || c < 0) {
-                std::memcpy(rows, cur, sizeof(uint64_t) * k);
-                labellings.clear();
-                have = true;
-                c = 0;
+    std::vector<std::pair<int, int>> out;
+    for (int u = 0; u < k; u++) {
+        int v0 = 0;
+        while (v0 < k && ((nxt[u] >> (4 * v0)) & 0xF) == 0xF) v0++;
+        if (v0 >= k) continue;
+        int v = v0;
+        for (int r = 0; r < deg[u]; r++, v = (int)((nxt[u] >> (4 * v)) & 0xF)) {
+            uint64_t sg = dart_signature(k, nxt, deg, u, v);
+            if (sg < minsig) {
+                minsig = sg;
+                out.clear();
             }
-            if (c == 0) labellings.push_back(ordw);
+            if (sg == minsig) out.push_back({u, v});
         }
-    return (int)labellings.size();
+    }
+    return out;
 }
 
 bool build_tables(HostTables &T, std::string &err) {
@@ -378,13 +374,11 @@ bool build_tables(HostTables &T, std::string &err) {
                     nxt[a] |= (uint64_t)cc << (4 * bb);
                     deg[a]++;
                 }
-            uint64_t rows[KMAX];
-            std::vector<uint64_t> labs;
-            canonical_code_host(k, nxt, deg, rows, labs);
-            std::vector<uint64_t> key(rows, rows + k);
-            codes_t.insert(key);
-            auto &lst = bucket[group_of_template(t)][key];
-            for (uint64_t perm : labs) {
+            for (auto &d : min_signature_darts(k, nxt, deg)) {
+                uint64_t rows[KMAX], perm;
+                dart_code(k, nxt, deg, d.first, d.second, rows, &perm);
+                std::vector<uint64_t> key(rows, rows + k);
+                codes_t.insert(key);
                 full++;
                 // canonical orbit representative: smallest g o perm
                 uint64_t best = ~0ull;
@@ -393,7 +387,7 @@ bool build_tables(HostTables &T, std::string &err) {
                     for (int lb = 0; lb < k; lb++) img |= (uint64_t)pm[(perm >> (4 * lb)) & 0xF] << (4 * lb);
                     best = std::min(best, img);
                 }
-                lst.push_back({t, best});
+                bucket[group_of_template(t)][key].push_back({t, best});
             }
         }
         T.ncand_full[t] = full;

@@ -1,13 +1,14 @@
 // ptm_tables.hpp -- template tables of the HIP library (host-built, device
 // read-only).  Polyhedral Template Matching, arXiv:1603.05143: the ideal
 // templates of Table 1, their hull triangulations (Sec. 4, App. A), the
-// orientation-preserving canonical codes of those triangulations and the
-// candidate correspondences, one per orbit of the template's proper
-// rotation group (App. A: symmetrically equivalent correspondences give the
-// same RMSD).
+// orientation-preserving start-edge codes of those triangulations (the
+// graph-isomorphism keys of Sec. 4) and the candidate correspondences, one
+// per orbit of the template's proper rotation group (App. A: symmetrically
+// equivalent correspondences give the same RMSD).
 #pragma once
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace ptm {
@@ -60,9 +61,9 @@ struct HostTables {
     int32_t hmask[NGRP];
     int32_t ncodes[NGRP];
     int64_t ntri[NT];        // triangulations per template
-    int64_t ncand_full[NT];  // correspondences before symmetry reduction
+    int64_t ncand_full[NT];  // table correspondences before symmetry reduction
     int64_t ncand_kept[NT];  // after
-    int64_t ncodes_t[NT];    // distinct codes per template
+    int64_t ncodes_t[NT];    // distinct table keys (start-edge codes) per template
     int max_cand_per_code[NGRP];
 };
 
@@ -80,12 +81,12 @@ __host__ __device__ inline uint64_t code_hash(const uint64_t *rows, int k) {
 // Build all tables; returns false and sets err on failure.
 bool build_tables(HostTables &T, std::string &err);
 
-// Canonical code (BFS rows, see ptm_tables.cpp) of a rotation system given
-// by nxt[x] (nibble y = vertex after y counter-clockwise around x, 0xF =
-// none) and deg; writes the k row words and every minimising labelling
-// (nibble l = vertex of label l).  Host version used by the generator and
-// by the self-check entry points.
-int canonical_code_host(int k, const uint64_t *nxt, const int *deg, uint64_t *rows,
-                        std::vector<uint64_t> &labellings);
+// Start-edge codes (definition in ptm_tables.cpp) of a rotation system
+// given by nxt[x] (nibble y = vertex after y counter-clockwise around x,
+// 0xF = none) and deg.  Host versions used by the generator and by the
+// self-check entry points.
+uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u, int v);
+void dart_code(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_t *rows, uint64_t *ordp);
+std::vector<std::pair<int, int>> min_signature_darts(int k, const uint64_t *nxt, const int *deg);
 
 } // namespace ptm

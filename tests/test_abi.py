@@ -108,18 +108,22 @@ def test_selftest_det3_exact(ptm):
         assert L.ptm_selftest_det3(p.ctypes.data_as(C.c_void_p)) == frac_det3(p)
 
 
-def lib_code(ptm, k, tris):
+def lib_keys(ptm, k, tris):
+    """(first code, key set) of the library's start-edge codes."""
     t = np.ascontiguousarray(tris, dtype=np.int32)
-    rows = np.zeros(14, np.uint64)
-    na = C.c_int32()
-    rc = ptm.lib().ptm_selftest_canonical(k, t.ctypes.data_as(C.c_void_p), len(t),
-                                          rows.ctypes.data_as(C.c_void_p), C.byref(na))
-    assert rc == 0
-    return tuple(rows[:k].tolist()), na.value
+    codes = np.zeros(128 * k, np.uint64)      # [max_codes][k]
+    n = C.c_int32()
+    rc = ptm.lib().ptm_selftest_codes(k, t.ctypes.data_as(C.c_void_p), len(t),
+                                      codes.ctypes.data_as(C.c_void_p), 128, C.byref(n))
+    assert rc == 0 and 0 < n.value <= 128
+    rows = codes.reshape(128, k)
+    keys = {tuple(rows[i].tolist()) for i in range(n.value)}
+    return tuple(rows[0].tolist()), keys
 
 
-def test_selftest_canonical_agrees_with_oracle(ptm, oracle_lib):
-    """Two independent complete codes must induce the same partition."""
+def test_selftest_codes_agree_with_oracle(ptm, oracle_lib):
+    """The library's single start-edge code finds exactly the isomorphic
+    graphs (same partition as the oracle's canonical form)."""
     rng = np.random.default_rng(2)
     for t in range(5):
         w = oracle_lib.template(t)["w"]
@@ -129,14 +133,13 @@ def test_selftest_canonical_agrees_with_oracle(ptm, oracle_lib):
             ok, tris = oracle_lib.hull(w + rng.normal(scale=0.06, size=w.shape))
             if ok:
                 graphs.append(tris)
-        lc = [lib_code(ptm, k, g) for g in graphs]
-        oc = [oracle_lib.canonical(k, g) for g in graphs]
+        lk = [lib_keys(ptm, k, g) for g in graphs]
+        oc = [oracle_lib.canonical(k, g)[0] for g in graphs]
         for i in range(len(graphs)):
-            assert lc[i][1] == oc[i][1]          # automorphism counts
             perm = rng.permutation(k)
-            assert lib_code(ptm, k, perm[graphs[i]])[0] == lc[i][0]
-            for j in range(i + 1, len(graphs)):
-                assert (lc[i][0] == lc[j][0]) == (oc[i][0] == oc[j][0])
+            assert lib_keys(ptm, k, perm[graphs[i]])[1] == lk[i][1]   # key set is invariant
+            for j in range(len(graphs)):
+                assert (lk[i][0] in lk[j][1]) == (oc[i] == oc[j])
 
 
 def test_selftest_superpose_agrees_with_oracle(ptm, oracle_lib):
