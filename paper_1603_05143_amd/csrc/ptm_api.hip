@@ -28,6 +28,10 @@ namespace ptm {
 // ------------------------------------------------------------ scratch
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// capacity of the flat candidate-pair list (typical atoms have 1-3 pairs;
+// atoms beyond the capacity are evaluated directly by k_decide)
+static int64_t pair_capacity(int64_t n) { return 6 * n + 64; }
+
 size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
@@ -38,18 +42,23 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
     b += align_up(4 * (size_t)n * NGRP);      // code ids
     b += align_up(8 * (size_t)n * NGRP);      // labellings
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
+    b += align_up(8 * (size_t)(n + 1)) * 2;   // candidate counts and offsets
+    b += align_up(16 * (size_t)pair_capacity(n));  // pairs and their RMSD
     b += align_up(scan_tmp);
     return b;
 }
 
 bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
     int nb = bounds_blocks(n);
-    size_t scan_tmp = 0;
+    size_t scan_tmp = 0, scan_tmp2 = 0;
     if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
-                                         (int)(cells + 1)) != hipSuccess) {
+                                         (int)(cells + 1)) != hipSuccess ||
+        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp2, (int64_t *)nullptr, (int64_t *)nullptr,
+                                         (int)(n + 1)) != hipSuccess) {
         err = "hipcub scan size query failed";
         return false;
     }
+    if (scan_tmp2 > scan_tmp) scan_tmp = scan_tmp2;
     size_t need = frame_bytes(n, cells, nb, scan_tmp);
     if (need > bytes) {
         if (base) (void)hipFree(base);
@@ -81,8 +90,15 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
     code = (int32_t *)take(4 * (size_t)n * NGRP);
     ord = (uint64_t *)take(8 * (size_t)n * NGRP);
     part = (double *)take(8 * 7 * (size_t)nb);
+    match.cap = pair_capacity(n);
+    match.cnt = (int64_t *)take(8 * (size_t)(n + 1));
+    match.off = (int64_t *)take(8 * (size_t)(n + 1));
+    match.pairs = (uint2 *)take(8 * (size_t)match.cap);
+    match.r = (double *)take(8 * (size_t)match.cap);
     scan_tmp_ptr = take(scan_tmp);
     scan_tmp_bytes = scan_tmp;
+    match.scan_tmp = scan_tmp_ptr;
+    match.scan_tmp_bytes = scan_tmp;
     return true;
 }
 
@@ -99,9 +115,10 @@ int bounds_blocks(int64_t n) {
     return (int)b;
 }
 
-// Choose the cell grid: cell edge close to the expected distance of the
-// 15th neighbour so that the 27-cell block usually certifies the 14
-// nearest; at least 3 cells on periodic axes.
+// Choose the cell grid: cell edge 0.6 x the expected distance of the 14th
+// neighbour, so that shells 0..2 of cells around an atom (5x5x5 block)
+// usually certify its 14 nearest neighbours; at least 3 cells on periodic
+// axes.  The grid affects only speed: the search is certified exact.
 Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n) {
     Grid g;
     double ext[3], vol = 1.0;
@@ -115,7 +132,7 @@ Grid make_grid(const double box[3], const double mn[3], const double mx[3], int6
     double h;
     if (flat == 0 && vol > 0) {
         double rho = (double)n / vol;
-        h = std::cbrt(15.0 / (4.1887902047863905 * rho));
+        h = 0.6 * std::cbrt(14.0 / (4.1887902047863905 * rho));
     } else {
         h = 1.0;
         for (int a = 0; a < 3; a++) h = std::fmax(h, ext[a] / 16.0);
@@ -172,7 +189,8 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
     launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.sx, S.sy, S.sz, S.sid, st);
     if ((ps = mark(PTM_STAGE_KNN)) != PTM_OK) return ps;
-    launch_knn(n, g, J.pos, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, st);
+    launch_knn(n, g, ctx->view.stencil, J.pos, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn,
+               st);
     if ((ps = mark(PTM_STAGE_TOPO6)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
     const bool need[NGRP] = {(m & 0x1u) != 0, (m & 0xEu) != 0, (m & 0x10u) != 0};
@@ -186,7 +204,7 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
         if ((ps = mark(PTM_STAGE_TOPO6 + grp + 1)) != PTM_OK) return ps;
     }
     MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
-    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, st);
+    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match, st);
     if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;

@@ -36,6 +36,7 @@ struct FrameScratch {
     double *part = nullptr;
     void *scan_tmp_ptr = nullptr;
     size_t scan_tmp_bytes = 0;
+    MatchScratch match = {};
     bool reserve(int64_t n, int64_t cells, std::string &err);
     void release();
 };

@@ -15,6 +15,7 @@
 // One lane owns one atom in every per-atom kernel; atoms are processed in
 // cell order so the lanes of a wave read the same cells.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 #include <stdint.h>
 
 #include "ptm_device.hpp"
@@ -149,11 +150,55 @@ __device__ inline void shell_range(const Grid &g, int a, int s, int &lo, int &hi
     }
 }
 
-__global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const double *__restrict__ pos,
-                                             const double *__restrict__ sx, const double *__restrict__ sy,
-                                             const double *__restrict__ sz, const int32_t *__restrict__ sid,
-                                             const int32_t *__restrict__ start, int32_t *__restrict__ nbr_id,
-                                             double *__restrict__ nbr_rel, int32_t *__restrict__ knn_out) {
+// scan the atoms of cell c into the top-K list
+template <int KN>
+__device__ inline void scan_cell(int c, const Grid &g, double xi, double yi, double zi, int32_t i,
+                                 const double *__restrict__ sx, const double *__restrict__ sy,
+                                 const double *__restrict__ sz, const int32_t *__restrict__ sid,
+                                 const int32_t *__restrict__ start, double (&kd)[KN], int32_t (&kj)[KN], int &found) {
+    int q1 = start[c + 1];
+    for (int q = start[c]; q < q1; q++) {
+        int32_t j = sid[q];
+        if (j == i) continue;
+        double dx = min_image(sx[q] - xi, g, 0);
+        double dy = min_image(sy[q] - yi, g, 1);
+        double dz = min_image(sz[q] - zi, g, 2);
+        double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        double d2 = (xx + yy) + zz;
+        found++;
+        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, d2, j);
+    }
+}
+
+// Is the block of offsets [lo, hi] per axis a certificate for the current
+// K-th distance?  all = the block covers every cell.
+__device__ inline bool certified(const Grid &g, const int (&cc)[3], const double (&u)[3], const int (&lo)[3],
+                                 const int (&hi)[3], int found, int KN, double kth, bool &all) {
+    double dmin = INFINITY;
+    all = true;
+    for (int a = 0; a < 3; a++) {
+        bool sat_lo, sat_hi;
+        if (g.periodic[a]) {
+            sat_lo = sat_hi = (hi[a] - lo[a] + 1) >= g.nc[a];
+        } else {
+            sat_lo = cc[a] + lo[a] <= 0;
+            sat_hi = cc[a] + hi[a] >= g.nc[a] - 1;
+        }
+        if (!sat_lo) dmin = fmin(dmin, u[a] - (cc[a] + lo[a]) * g.h[a]);
+        if (!sat_hi) dmin = fmin(dmin, (cc[a] + hi[a] + 1) * g.h[a] - u[a]);
+        all = all && sat_lo && sat_hi;
+    }
+    if (all) return true;
+    dmin -= g.margin;
+    return found >= KN && dmin > 0 && kth < dmin * dmin;
+}
+
+__global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const int32_t *__restrict__ stencil,
+                                             const double *__restrict__ pos, const double *__restrict__ sx,
+                                             const double *__restrict__ sy, const double *__restrict__ sz,
+                                             const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                                             int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                                             int32_t *__restrict__ knn_out) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     constexpr int KN = KMAX;
@@ -171,8 +216,42 @@ __global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const double *__
 #pragma unroll
     for (int m = 0; m < KN; m++) { kd[m] = INFINITY; kj[m] = 0x7fffffff; }
     int found = 0;
-    int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};  // previous (empty) block
-    for (int s = 1;; s++) {
+    int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};  // block already searched (empty)
+    int s_next = 1;
+    bool done = false;
+    // fast path: stencil shells 0..3 in a uniform order (every lane walks the
+    // same offsets), valid when no periodic axis wraps onto itself
+    bool fast = true;
+    for (int a = 0; a < 3; a++) fast = fast && (!g.periodic[a] || g.nc[a] >= 2 * STENCIL_SHELLS + 1);
+    if (fast) {
+        for (int s = 0; s <= STENCIL_SHELLS && !done; s++) {
+            for (int idx = stencil_start(s); idx < stencil_start(s + 1); idx++) {
+                int32_t o = stencil[idx];
+                int c3[3] = {cc[0] + (o & 0xFF) - 8, cc[1] + ((o >> 8) & 0xFF) - 8, cc[2] + ((o >> 16) & 0xFF) - 8};
+                bool skip = false;
+                for (int a = 0; a < 3; a++) {
+                    if (g.periodic[a]) {
+                        if (c3[a] < 0) c3[a] += g.nc[a];
+                        else if (c3[a] >= g.nc[a]) c3[a] -= g.nc[a];
+                    } else if (c3[a] < 0 || c3[a] >= g.nc[a]) {
+                        skip = true;
+                    }
+                }
+                if (skip) continue;
+                int c = (c3[2] * g.nc[1] + c3[1]) * g.nc[0] + c3[0];
+                scan_cell<KN>(c, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj, found);
+            }
+            if (s >= 1) {
+                int lo[3] = {-s, -s, -s}, hi[3] = {s, s, s};
+                bool all;
+                done = certified(g, cc, u, lo, hi, found, KN, kd[KN - 1], all);
+                for (int a = 0; a < 3; a++) { plo[a] = lo[a]; phi[a] = hi[a]; }
+                s_next = s + 1;
+            }
+        }
+    }
+    // general path: shells of cells with per-axis clamping to the grid
+    for (int s = s_next; !done; s++) {
         int lo[3], hi[3];
         for (int a = 0; a < 3; a++) shell_range(g, a, s, lo[a], hi[a]);
         for (int oz = lo[2]; oz <= hi[2]; oz++) {
@@ -191,41 +270,13 @@ __global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const double *__
                     if (g.periodic[0]) cx = (cx % g.nc[0] + g.nc[0]) % g.nc[0];
                     else if (cx < 0 || cx >= g.nc[0]) continue;
                     int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
-                    int q1 = start[c + 1];
-                    for (int q = start[c]; q < q1; q++) {
-                        int32_t j = sid[q];
-                        if (j == i) continue;
-                        double dx = min_image(sx[q] - xi, g, 0);
-                        double dy = min_image(sy[q] - yi, g, 1);
-                        double dz = min_image(sz[q] - zi, g, 2);
-                        double xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                        double d2 = (xx + yy) + zz;
-                        found++;
-                        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, d2, j);
-                    }
+                    scan_cell<KN>(c, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj, found);
                 }
             }
         }
-        // certification: distance from the atom to the unsearched region
-        double dmin = INFINITY;
-        bool all = true;
-        for (int a = 0; a < 3; a++) {
-            bool sat_lo, sat_hi;
-            if (g.periodic[a]) {
-                sat_lo = sat_hi = (hi[a] - lo[a] + 1) >= g.nc[a];
-            } else {
-                sat_lo = cc[a] + lo[a] <= 0;
-                sat_hi = cc[a] + hi[a] >= g.nc[a] - 1;
-            }
-            if (!sat_lo) dmin = fmin(dmin, u[a] - (cc[a] + lo[a]) * g.h[a]);
-            if (!sat_hi) dmin = fmin(dmin, (cc[a] + hi[a] + 1) * g.h[a] - u[a]);
-            all = all && sat_lo && sat_hi;
-            plo[a] = lo[a];
-            phi[a] = hi[a];
-        }
-        if (all) break;
-        dmin -= g.margin;
-        if (found >= KN && dmin > 0 && kd[KN - 1] < dmin * dmin) break;
+        bool all;
+        done = certified(g, cc, u, lo, hi, found, KN, kd[KN - 1], all);
+        for (int a = 0; a < 3; a++) { plo[a] = lo[a]; phi[a] = hi[a]; }
     }
     int cnt = found < KN ? found : KN;
 #pragma unroll
@@ -782,18 +833,107 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
     }
 }
 
-__global__ void __launch_bounds__(MB) k_match(int64_t n, const double *__restrict__ nbr_rel,
+__device__ inline void write_none(const MatchOut &O, int32_t i) {
+    O.type[i] = 0;
+    if (O.alloy) O.alloy[i] = 0;
+    if (O.rmsd) O.rmsd[i] = INFINITY;
+    if (O.scale) O.scale[i] = 0.0;
+    if (O.quat) {
+        O.quat[4 * (int64_t)i] = 1.0;
+        for (int k = 1; k < 4; k++) O.quat[4 * (int64_t)i + k] = 0.0;
+    }
+    if (O.strain)
+        for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = 0.0;
+    if (O.neighbours)
+        for (int m = 0; m < KMAX; m++) O.neighbours[(int64_t)i * KMAX + m] = -1;
+}
+
+__device__ inline void load_templates(MatchShared &M, const TablesView &T) {
+    const uint32_t *src = (const uint32_t *)T.tpl;
+    uint32_t *dst = (uint32_t *)M.tpl;
+    for (int w = threadIdx.x; w < (int)(sizeof(TemplateDev) * NT / 4); w += blockDim.x) dst[w] = src[w];
+    __syncthreads();
+}
+
+// Candidates of one atom: pass 1 counts them (mask applied), pass 2 lists
+// them as (atom, group, candidate) pairs at the atom's offset.
+__global__ void __launch_bounds__(256) k_cand_count(int64_t n, TablesView T, const int32_t *__restrict__ code,
+                                                    uint32_t mask, int64_t *__restrict__ cnt) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p > n) return;
+    int c = 0;
+    if (p < n)
+        for (int g = 0; g < NGRP; g++) {
+            int32_t cid = code[(int64_t)g * n + p];
+            if (cid < 0) continue;
+            for (int k = T.cstart[g][cid]; k < T.cstart[g][cid + 1]; k++) c += (mask >> T.cand[g][k].tmpl) & 1;
+        }
+    cnt[p] = c;  // cnt[n] = 0 so that the scan yields the total
+}
+
+__global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, const int32_t *__restrict__ code,
+                                                   uint32_t mask, const int64_t *__restrict__ off, int64_t cap,
+                                                   uint2 *__restrict__ pairs) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int64_t q = off[p];
+    if (off[p + 1] > cap) {
+        // evaluated directly by the decision kernel; mark its slots below cap
+        for (; q < cap; q++) pairs[q] = make_uint2(0xFFFFFFFFu, 0u);
+        return;
+    }
+    for (int g = 0; g < NGRP; g++) {
+        int32_t cid = code[(int64_t)g * n + p];
+        if (cid < 0) continue;
+        for (int k = T.cstart[g][cid]; k < T.cstart[g][cid + 1]; k++)
+            if ((mask >> T.cand[g][k].tmpl) & 1) pairs[q++] = make_uint2((uint32_t)p, ((uint32_t)g << 28) | (uint32_t)k);
+    }
+}
+
+// One superposition per lane over the flat pair list (grid-stride).
+__global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
+                                                  const uint64_t *__restrict__ ords, const int64_t *__restrict__ off,
+                                                  int64_t cap, const uint2 *__restrict__ pairs,
+                                                  double *__restrict__ rout) {
+    __shared__ MatchShared M;
+    load_templates(M, T);
+    int64_t total = off[n];
+    if (total > cap) total = cap;
+    for (int64_t q = blockIdx.x * (int64_t)MB + threadIdx.x; q < total; q += (int64_t)gridDim.x * MB) {
+        uint2 pr = pairs[q];
+        if (pr.x == 0xFFFFFFFFu) continue;  // atom handled by k_decide
+        int64_t p = pr.x;
+        int g = pr.y >> 28, k = pr.y & 0x0FFFFFFF;
+        Candidate cd = T.cand[g][k];
+        uint64_t ord = ords[(int64_t)g * n + p];
+        double a[NMAX][3], Ga;
+        CandEval ev;
+        if (g == 0) {
+            load_centred<6>(nbr_rel, n, p, a, Ga);
+            eval_candidate<6>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
+        } else if (g == 1) {
+            load_centred<12>(nbr_rel, n, p, a, Ga);
+            eval_candidate<12>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
+        } else {
+            load_centred<14>(nbr_rel, n, p, a, Ga);
+            eval_candidate<14>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
+        }
+        rout[q] = ev.r;
+    }
+}
+
+// Per-atom decision over the evaluated pairs (Alg. 1 minimum with the tie
+// rule), then the outputs of the winner.  Atoms whose pairs did not fit the
+// pair buffer are evaluated here directly.
+__global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restrict__ nbr_rel,
                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
                                                const int8_t *__restrict__ species, TablesView T,
                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
+                                               const int64_t *__restrict__ off, int64_t cap,
+                                               const uint2 *__restrict__ pairs, const double *__restrict__ rr,
                                                uint32_t mask, double cutoff, MatchOut O) {
     __shared__ MatchShared M;
-    {
-        const uint32_t *src = (const uint32_t *)T.tpl;
-        uint32_t *dst = (uint32_t *)M.tpl;
-        for (int w = threadIdx.x; w < (int)(sizeof(TemplateDev) * NT / 4); w += MB) dst[w] = src[w];
-    }
-    __syncthreads();
+    load_templates(M, T);
     const int64_t p = blockIdx.x * (int64_t)MB + threadIdx.x;
     if (p >= n) return;
     const int32_t i = sid[p];
@@ -805,22 +945,26 @@ __global__ void __launch_bounds__(MB) k_match(int64_t n, const double *__restric
     }
     double m1 = INFINITY, m2 = INFINITY;
     int arg_grp = -1, arg_c = -1;
-    if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-    if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-    if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-    if (arg_c < 0) {
-        O.type[i] = 0;
-        if (O.alloy) O.alloy[i] = 0;
-        if (O.rmsd) O.rmsd[i] = INFINITY;
-        if (O.scale) O.scale[i] = 0.0;
-        if (O.quat) {
-            O.quat[4 * (int64_t)i] = 1.0;
-            for (int k = 1; k < 4; k++) O.quat[4 * (int64_t)i + k] = 0.0;
+    const int64_t q0 = off[p], q1 = off[p + 1];
+    if (q1 <= cap) {
+        for (int64_t q = q0; q < q1; q++) {
+            double r = rr[q];
+            if (r < m1) {
+                m2 = m1;
+                m1 = r;
+                arg_grp = pairs[q].y >> 28;
+                arg_c = pairs[q].y & 0x0FFFFFFF;
+            } else if (r < m2) {
+                m2 = r;
+            }
         }
-        if (O.strain)
-            for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = 0.0;
-        if (O.neighbours)
-            for (int m = 0; m < KMAX; m++) O.neighbours[(int64_t)i * KMAX + m] = -1;
+    } else {
+        if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+        if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+        if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+    }
+    if (arg_c < 0) {
+        write_none(O, i);
         return;
     }
     if (m2 <= m1 + 1e-12) {
@@ -854,11 +998,11 @@ void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, co
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, cell_of, slot_of,
                        start, sx, sy, sz, sid);
 }
-void launch_knn(int64_t n, const Grid &g, const double *pos, const double *sx, const double *sy, const double *sz,
-                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
-                hipStream_t st) {
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, g, pos, sx, sy, sz, sid, start,
-                       nbr_id, nbr_rel, knn_out);
+void launch_knn(int64_t n, const Grid &g, const int32_t *stencil, const double *pos, const double *sx,
+                const double *sy, const double *sz, const int32_t *sid, const int32_t *start, int32_t *nbr_id,
+                double *nbr_rel, int32_t *knn_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_knn, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, g, stencil, pos, sx, sy, sz,
+                       sid, start, nbr_id, nbr_rel, knn_out);
 }
 void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
                  uint64_t *ord, hipStream_t st) {
@@ -869,9 +1013,16 @@ void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id,
 }
 void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
                   const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
-                  const MatchOut &O, hipStream_t st) {
-    hipLaunchKernelGGL(k_match, dim3((unsigned)((n + MB - 1) / MB)), dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species,
-                       T, code, ord, mask, cutoff, O);
+                  const MatchOut &O, const MatchScratch &W, hipStream_t st) {
+    unsigned nb = (unsigned)((n + 1 + 255) / 256);
+    hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt);
+    size_t tmp = W.scan_tmp_bytes;
+    (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, (int)(n + 1), st);
+    hipLaunchKernelGGL(k_cand_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, code, mask, W.off,
+                       W.cap, W.pairs);
+    hipLaunchKernelGGL(k_cand_eval, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs, W.r);
+    hipLaunchKernelGGL(k_decide, dim3((unsigned)((n + MB - 1) / MB)), dim3(MB), 0, st, n, nbr_rel, nbr_id, sid,
+                       species, T, code, ord, W.off, W.cap, W.pairs, W.r, mask, cutoff, O);
 }
 
 }  // namespace ptm

@@ -29,18 +29,29 @@ struct MatchOut {
     double *strain;
 };
 
+// Flat (atom, candidate) pair list of the match stage.
+struct MatchScratch {
+    int64_t *cnt;        // [n+1] candidates per atom
+    int64_t *off;        // [n+1] exclusive prefix sum (off[n] = total)
+    uint2 *pairs;        // [cap] (atom, group << 28 | candidate)
+    double *r;           // [cap] RMSD of each pair
+    int64_t cap;         // pair capacity
+    void *scan_tmp;
+    size_t scan_tmp_bytes;
+};
+
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st);
 void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
                       int32_t *count, hipStream_t st);
 void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
                         const int32_t *start, double *sx, double *sy, double *sz, int32_t *sid, hipStream_t st);
-void launch_knn(int64_t n, const Grid &g, const double *pos, const double *sx, const double *sy, const double *sz,
+void launch_knn(int64_t n, const Grid &g, const int32_t *stencil, const double *pos, const double *sx, const double *sy, const double *sz,
                 const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
                 hipStream_t st);
 void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
                  uint64_t *ord, hipStream_t st);
 void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
                   const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
-                  const MatchOut &O, hipStream_t st);
+                  const MatchOut &O, const MatchScratch &W, hipStream_t st);
 
 }  // namespace ptm
