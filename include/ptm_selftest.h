@@ -39,6 +39,19 @@ int ptm_selftest_codes(int k, const int32_t *tris, int ntri, uint64_t *codes, in
  * onto the observation.  Returns 0, or -1 for N out of range. */
 int ptm_selftest_superpose(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q);
 
+/* Decision (+1/-1, or 0 if undecided) of the FP32-storage orientation filter
+ * of the FP32-mixed form on the FP32 roundings of p12[4][3]; a decided
+ * sign must equal the exact sign of det[b-a; c-a; d-a] on the FP64 inputs. */
+int ptm_selftest_orient_f32filter(const double *p12);
+
+/* Same for det[a; b; c] (p9[3][3]). */
+int ptm_selftest_det3_f32filter(const double *p9);
+
+/* ptm_selftest_superpose evaluated in FP32 the way the FP32-mixed form
+ * evaluates a candidate (centring in FP64, covariance, QCP and residual in
+ * FP32). */
+int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q);
+
 #ifdef __cplusplus
 }
 #endif

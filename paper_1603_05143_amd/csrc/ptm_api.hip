@@ -196,15 +196,16 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     const bool need[NGRP] = {(m & 0x1u) != 0, (m & 0xEu) != 0, (m & 0x10u) != 0};
     for (int grp = 0; grp < NGRP; grp++) {
         if (need[grp])
-            launch_topo(group_k(grp), n, S.nbr_rel, S.nbr_id, ctx->view, S.code + (int64_t)grp * n,
-                        S.ord + (int64_t)grp * n, st);
+            launch_topo(group_k(grp), ctx->precision == PTM_FP32_MIXED, n, S.nbr_rel, S.nbr_id, ctx->view,
+                        S.code + (int64_t)grp * n, S.ord + (int64_t)grp * n, st);
         else
             PTM_HIP(ctx, hipMemsetAsync(S.code + (int64_t)grp * n, 0xFF, 4 * (size_t)n, st));
         if (prof) ctx->prof_ran[PTM_STAGE_TOPO6 + grp] = need[grp];
         if ((ps = mark(PTM_STAGE_TOPO6 + grp + 1)) != PTM_OK) return ps;
     }
     MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
-    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match, st);
+    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match,
+                 ctx->precision == PTM_FP32_MIXED, st);
     if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;
@@ -513,6 +514,63 @@ int ptm_selftest_superpose(int N, const double *obs, const double *tpl, double *
         }
     *rmsd = sqrt(res / N);
     *scale = s;
+    return 0;
+}
+
+int ptm_selftest_orient_f32filter(const double *p) {
+    float f[12];
+    for (int i = 0; i < 12; i++) f[i] = (float)p[i];
+    return orient_filter_f32in(f, f + 3, f + 6, f + 9);
+}
+
+int ptm_selftest_det3_f32filter(const double *p) {
+    float f[9];
+    for (int i = 0; i < 9; i++) f[i] = (float)p[i];
+    return det3_filter_f32in(f, f + 3, f + 6);
+}
+
+int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q) {
+    if (N < 1 || N > NMAX) return -1;
+    double ca[3] = {0, 0, 0}, cb[3] = {0, 0, 0};
+    for (int i = 0; i < N; i++)
+        for (int d = 0; d < 3; d++) {
+            ca[d] += obs[3 * i + d] / N;
+            cb[d] += tpl[3 * i + d] / N;
+        }
+    double lb = 0, Ga64 = 0;
+    float a[NMAX][3], b[NMAX][3];
+    double b64[NMAX][3];
+    for (int i = 0; i < N; i++) {
+        double s = 0;
+        for (int d = 0; d < 3; d++) {
+            double x = obs[3 * i + d] - ca[d];
+            a[i][d] = (float)x;
+            Ga64 += x * x;
+            b64[i][d] = tpl[3 * i + d] - cb[d];
+            s += b64[i][d] * b64[i][d];
+        }
+        lb += sqrt(s);
+    }
+    lb /= N;
+    float S[3][3] = {{0}}, Gb = 0, Ga = (float)Ga64;
+    for (int i = 0; i < N; i++) {
+        for (int d = 0; d < 3; d++) b[i][d] = (float)(b64[i][d] / lb);
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) S[x][y] += b[i][x] * a[i][y];
+        for (int d = 0; d < 3; d++) Gb += b[i][d] * b[i][d];
+    }
+    float qf[4];
+    float lam = qcp_solve<float>(S, Ga, Gb, qf);
+    float s = Ga > 0 ? lam / Ga : 0.f, R[3][3], res = 0;
+    quat_rot<float>(qf, R);
+    for (int i = 0; i < N; i++)
+        for (int x = 0; x < 3; x++) {
+            float d = s * a[i][x] - (R[x][0] * b[i][0] + R[x][1] * b[i][1] + R[x][2] * b[i][2]);
+            res += d * d;
+        }
+    *rmsd = sqrtf(res / N);
+    *scale = s;
+    for (int i = 0; i < 4; i++) q[i] = qf[i];
     return 0;
 }
 

@@ -225,6 +225,40 @@ PTM_HD int det3_filter64(const double *a, const double *b, const double *c) {
     return 0;
 }
 
+// Filters on points stored in FP32 (each coordinate the FP32 rounding of the
+// exact FP64 input, |x32 - x64| <= 2^-24 |x64|).  The arithmetic runs in
+// FP64 on the widened values; the bound covers the input rounding -- three
+// rounded differences per term, each off by at most 2^-24 (|a| + |d|) --
+// i.e. 3.01 x 2^-24 x P, with P the permanent built from |a| + |d| sums,
+// plus the FP64 arithmetic (1e-15 x P).  A decided sign is therefore the
+// exact sign of the predicate on the FP64 inputs.
+PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d) {
+    double adx = (double)a[0] - d[0], ady = (double)a[1] - d[1], adz = (double)a[2] - d[2];
+    double bdx = (double)b[0] - d[0], bdy = (double)b[1] - d[1], bdz = (double)b[2] - d[2];
+    double cdx = (double)c[0] - d[0], cdy = (double)c[1] - d[1], cdz = (double)c[2] - d[2];
+    double sdx = fabs((double)d[0]), sdy = fabs((double)d[1]), sdz = fabs((double)d[2]);
+    double sax = fabs((double)a[0]) + sdx, say = fabs((double)a[1]) + sdy, saz = fabs((double)a[2]) + sdz;
+    double sbx = fabs((double)b[0]) + sdx, sby = fabs((double)b[1]) + sdy, sbz = fabs((double)b[2]) + sdz;
+    double scx = fabs((double)c[0]) + sdx, scy = fabs((double)c[1]) + sdy, scz = fabs((double)c[2]) + sdz;
+    double det = adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
+    double P = saz * (sbx * scy + scx * sby) + sbz * (scx * say + sax * scy) + scz * (sax * sby + sbx * say);
+    double bound = 1.8e-7 * P;
+    if (det > bound) return -1;
+    if (det < -bound) return 1;
+    return 0;
+}
+
+PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c) {
+    double ax = a[0], ay = a[1], az = a[2], bx = b[0], by = b[1], bz = b[2], cx = c[0], cy = c[1], cz = c[2];
+    double m1 = by * cz, m2 = bz * cy, m3 = bz * cx, m4 = bx * cz, m5 = bx * cy, m6 = by * cx;
+    double det = ax * (m1 - m2) + ay * (m3 - m4) + az * (m5 - m6);
+    double P = fabs(ax) * (fabs(m1) + fabs(m2)) + fabs(ay) * (fabs(m3) + fabs(m4)) + fabs(az) * (fabs(m5) + fabs(m6));
+    double bound = 1.8e-7 * P;
+    if (det > bound) return 1;
+    if (det < -bound) return -1;
+    return 0;
+}
+
 #ifdef __HIP_DEVICE_COMPILE__
 __attribute__((noinline))
 #endif
@@ -249,75 +283,90 @@ PTM_HD int det3_sign64(const double *a, const double *b, const double *c) {
 }
 
 // ------------------------------------------------------------------- QCP
+template <typename T>
+struct RealTraits;
+template <>
+struct RealTraits<double> {
+    static constexpr double newton_tol = 1e-15;
+    static constexpr double jacobi_off = 1e-36;
+};
+template <>
+struct RealTraits<float> {
+    static constexpr float newton_tol = 2e-7f;
+    static constexpr float jacobi_off = 1e-14f;
+};
+
 // Largest eigenvalue and eigenvector of Horn's matrix for S_xy = sum b_x a_y
 // (template b, observation a); q (w,x,y,z) rotates b onto a.  Ga, Gb are the
 // inner products of the two sets (upper bound sqrt(Ga Gb) on lambda).
-PTM_HD double qcp_solve(const double S[3][3], double Ga, double Gb, double q[4]) {
-    const double Sxx = S[0][0], Sxy = S[0][1], Sxz = S[0][2];
-    const double Syx = S[1][0], Syy = S[1][1], Syz = S[1][2];
-    const double Szx = S[2][0], Szy = S[2][1], Szz = S[2][2];
-    double K[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
-                      {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
-                      {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
-                      {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+template <typename T>
+__host__ __device__ inline T qcp_solve(const T S[3][3], T Ga, T Gb, T q[4]) {
+    const T Sxx = S[0][0], Sxy = S[0][1], Sxz = S[0][2];
+    const T Syx = S[1][0], Syy = S[1][1], Syz = S[1][2];
+    const T Szx = S[2][0], Szy = S[2][1], Szz = S[2][2];
+    T K[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+                 {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
+                 {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
+                 {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
     // characteristic polynomial lambda^4 + c2 lambda^2 + c1 lambda + c0
-    double ss = 0;
+    T ss = 0;
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) ss += S[i][j] * S[i][j];
-    double c2 = -2.0 * ss;
-    double detS = Sxx * (Syy * Szz - Syz * Szy) - Sxy * (Syx * Szz - Syz * Szx) + Sxz * (Syx * Szy - Syy * Szx);
-    double c1 = -8.0 * detS;
+    T c2 = T(-2) * ss;
+    T detS = Sxx * (Syy * Szz - Syz * Szy) - Sxy * (Syx * Szz - Syz * Szx) + Sxz * (Syx * Szy - Syy * Szx);
+    T c1 = T(-8) * detS;
     // c0 = det K by complementary 2x2 minors of rows (0,1) and (2,3)
-    double s01 = K[0][0] * K[1][1] - K[0][1] * K[1][0], s02 = K[0][0] * K[1][2] - K[0][2] * K[1][0];
-    double s03 = K[0][0] * K[1][3] - K[0][3] * K[1][0], s12 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-    double s13 = K[0][1] * K[1][3] - K[0][3] * K[1][1], s23 = K[0][2] * K[1][3] - K[0][3] * K[1][2];
-    double t01 = K[2][0] * K[3][1] - K[2][1] * K[3][0], t02 = K[2][0] * K[3][2] - K[2][2] * K[3][0];
-    double t03 = K[2][0] * K[3][3] - K[2][3] * K[3][0], t12 = K[2][1] * K[3][2] - K[2][2] * K[3][1];
-    double t13 = K[2][1] * K[3][3] - K[2][3] * K[3][1], t23 = K[2][2] * K[3][3] - K[2][3] * K[3][2];
-    double c0 = s01 * t23 - s02 * t13 + s03 * t12 + s12 * t03 - s13 * t02 + s23 * t01;
-    double lam = sqrt(Ga * Gb);
+    T s01 = K[0][0] * K[1][1] - K[0][1] * K[1][0], s02 = K[0][0] * K[1][2] - K[0][2] * K[1][0];
+    T s03 = K[0][0] * K[1][3] - K[0][3] * K[1][0], s12 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+    T s13 = K[0][1] * K[1][3] - K[0][3] * K[1][1], s23 = K[0][2] * K[1][3] - K[0][3] * K[1][2];
+    T t01 = K[2][0] * K[3][1] - K[2][1] * K[3][0], t02 = K[2][0] * K[3][2] - K[2][2] * K[3][0];
+    T t03 = K[2][0] * K[3][3] - K[2][3] * K[3][0], t12 = K[2][1] * K[3][2] - K[2][2] * K[3][1];
+    T t13 = K[2][1] * K[3][3] - K[2][3] * K[3][1], t23 = K[2][2] * K[3][3] - K[2][3] * K[3][2];
+    T c0 = s01 * t23 - s02 * t13 + s03 * t12 + s12 * t03 - s13 * t02 + s23 * t01;
+    T lam = sqrt(Ga * Gb);
     for (int it = 0; it < 60; it++) {
-        double l2 = lam * lam;
-        double f = (l2 + c2) * l2 + c1 * lam + c0;
-        double fp = 4.0 * l2 * lam + 2.0 * c2 * lam + c1;
-        if (fp == 0.0) break;
-        double step = f / fp;
+        T l2 = lam * lam;
+        T f = (l2 + c2) * l2 + c1 * lam + c0;
+        T fp = T(4) * l2 * lam + T(2) * c2 * lam + c1;
+        if (fp == T(0)) break;
+        T step = f / fp;
         lam -= step;
-        if (fabs(step) <= 1e-15 * fabs(lam) + 1e-300) break;
+        if (fabs(step) <= RealTraits<T>::newton_tol * fabs(lam) + T(1e-30)) break;
     }
     // eigenvector: the adjugate column of (K - lam I) with the largest norm
-    double A[4][4];
+    T A[4][4];
     for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) A[i][j] = K[i][j] - (i == j ? lam : 0.0);
-    double best = -1.0;
+        for (int j = 0; j < 4; j++) A[i][j] = K[i][j] - (i == j ? lam : T(0));
+    T best = -1;
     q[0] = 1; q[1] = q[2] = q[3] = 0;
     for (int col = 0; col < 4; col++) {
         // cofactors C_{col,i} = (-1)^{col+i} det(A without row col, col i)
-        double v[4];
+        T v[4];
         for (int i = 0; i < 4; i++) {
             int r[3], c[3], nr = 0, nc = 0;
             for (int t = 0; t < 4; t++) {
                 if (t != col) r[nr++] = t;
                 if (t != i) c[nc++] = t;
             }
-            double m = A[r[0]][c[0]] * (A[r[1]][c[1]] * A[r[2]][c[2]] - A[r[1]][c[2]] * A[r[2]][c[1]]) -
-                       A[r[0]][c[1]] * (A[r[1]][c[0]] * A[r[2]][c[2]] - A[r[1]][c[2]] * A[r[2]][c[0]]) +
-                       A[r[0]][c[2]] * (A[r[1]][c[0]] * A[r[2]][c[1]] - A[r[1]][c[1]] * A[r[2]][c[0]]);
+            T m = A[r[0]][c[0]] * (A[r[1]][c[1]] * A[r[2]][c[2]] - A[r[1]][c[2]] * A[r[2]][c[1]]) -
+                  A[r[0]][c[1]] * (A[r[1]][c[0]] * A[r[2]][c[2]] - A[r[1]][c[2]] * A[r[2]][c[0]]) +
+                  A[r[0]][c[2]] * (A[r[1]][c[0]] * A[r[2]][c[1]] - A[r[1]][c[1]] * A[r[2]][c[0]]);
             v[i] = ((col + i) & 1) ? -m : m;
         }
-        double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+        T n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
         if (n2 > best) {
             best = n2;
-            double inv = n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
+            T inv = n2 > T(0) ? T(1) / sqrt(n2) : T(0);
             for (int i = 0; i < 4; i++) q[i] = v[i] * inv;
         }
     }
-    if (!(best > 0)) { q[0] = 1; q[1] = q[2] = q[3] = 0; }
+    if (!(best > T(0))) { q[0] = 1; q[1] = q[2] = q[3] = 0; }
     return lam;
 }
 
-PTM_HD void quat_rot(const double q[4], double R[3][3]) {
-    double w = q[0], x = q[1], y = q[2], z = q[3];
+template <typename T>
+__host__ __device__ inline void quat_rot(const T q[4], T R[3][3]) {
+    T w = q[0], x = q[1], y = q[2], z = q[3];
     R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z);     R[0][2] = 2 * (x * z + w * y);
     R[1][0] = 2 * (x * y + w * z);     R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
     R[2][0] = 2 * (x * z - w * y);     R[2][1] = 2 * (y * z + w * x);     R[2][2] = 1 - 2 * (x * x + y * y);
@@ -325,35 +374,35 @@ PTM_HD void quat_rot(const double q[4], double R[3][3]) {
 
 // cyclic Jacobi for a symmetric 3x3 matrix; returns eigenvalues in d and
 // eigenvectors in the columns of V
-PTM_HD void jacobi3(double A[3][3], double d[3], double V[3][3]) {
+template <typename T>
+__host__ __device__ inline void jacobi3(T A[3][3], T d[3], T V[3][3]) {
     for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) V[i][j] = (i == j) ? 1.0 : 0.0;
+        for (int j = 0; j < 3; j++) V[i][j] = (i == j) ? T(1) : T(0);
     for (int sweep = 0; sweep < 12; sweep++) {
-        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
-        double dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-        if (off <= 1e-36 * dg) break;
+        T off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        T dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off <= RealTraits<T>::jacobi_off * dg) break;
         for (int p = 0; p < 2; p++)
             for (int r = p + 1; r < 3; r++) {
-                double apr = A[p][r];
-                if (apr == 0.0) continue;
-                double h = A[r][r] - A[p][p];
-                double t;
-                double th = 0.5 * h / apr;
-                t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
-                if (th < 0) t = -t;
-                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                T apr = A[p][r];
+                if (apr == T(0)) continue;
+                T h = A[r][r] - A[p][p];
+                T th = T(0.5) * h / apr;
+                T t = T(1) / (fabs(th) + sqrt(th * th + T(1)));
+                if (th < T(0)) t = -t;
+                T c = T(1) / sqrt(t * t + T(1)), s = t * c;
                 for (int m = 0; m < 3; m++) {
-                    double amp = A[m][p], amr = A[m][r];
+                    T amp = A[m][p], amr = A[m][r];
                     A[m][p] = c * amp - s * amr;
                     A[m][r] = s * amp + c * amr;
                 }
                 for (int m = 0; m < 3; m++) {
-                    double apm = A[p][m], arm = A[r][m];
+                    T apm = A[p][m], arm = A[r][m];
                     A[p][m] = c * apm - s * arm;
                     A[r][m] = s * apm + c * arm;
                 }
                 for (int m = 0; m < 3; m++) {
-                    double vmp = V[m][p], vmr = V[m][r];
+                    T vmp = V[m][p], vmr = V[m][r];
                     V[m][p] = c * vmp - s * vmr;
                     V[m][r] = s * vmp + c * vmr;
                 }

@@ -303,14 +303,31 @@ __global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const int32_t *_
 // conflict across lanes.
 constexpr int TB = 64;  // threads per block of the topology kernel
 
-template <int K>
+// The rotation system reuses the point storage after the hull is built.
+// Entries are kept in words of the point type so that every lane's rotation
+// system overlays only its own points (column t): 64-bit words over FP64
+// points, pairs of 32-bit words over FP32 points.
+template <int K, typename R>
 struct TopoShared {
     union {
-        double P[3][K][TB];   // neighbour vectors (hull phase)
-        uint64_t NT[K][TB];   // rotation system (code phase)
+        R P[3][K][TB];            // neighbour vectors (hull phase), FP64 or FP32
+        uint64_t NT64[K][TB];     // rotation system over FP64 points
+        uint32_t NT32[2 * K][TB]; // rotation system over FP32 points (lo, hi)
     };
     uint32_t F[2 * K - 4][TB];
     uint16_t H[K][TB];
+    __device__ uint64_t nt(int x, int t) const {
+        if constexpr (sizeof(R) == 8) return NT64[x][t];
+        else return (uint64_t)NT32[2 * x][t] | ((uint64_t)NT32[2 * x + 1][t] << 32);
+    }
+    __device__ void set_nt(int x, int t, uint64_t v) {
+        if constexpr (sizeof(R) == 8) {
+            NT64[x][t] = v;
+        } else {
+            NT32[2 * x][t] = (uint32_t)v;
+            NT32[2 * x + 1][t] = (uint32_t)(v >> 32);
+        }
+    }
 };
 
 // facet word: v0 | v1<<4 | v2<<8 | nb0<<12 | nb1<<17 | nb2<<22
@@ -325,36 +342,74 @@ __device__ inline uint32_t fset_nb(uint32_t f, int e, int g) {
     return (f & ~(0x1Fu << sh)) | ((uint32_t)g << sh);
 }
 
-template <int K>
-__device__ inline int lane_orient(TopoShared<K> &S, int t, int a, int b, int c, int d) {
-    double pa[3], pb[3], pc[3], pd[3];
-    for (int k = 0; k < 3; k++) {
-        pa[k] = S.P[k][a][t];
-        pb[k] = S.P[k][b][t];
-        pc[k] = S.P[k][c][t];
-        pd[k] = S.P[k][d][t];
+// Per-lane view of the hull inputs: LDS points plus the FP64 originals in
+// global memory (used when an FP32 filter cannot decide).
+template <int K, typename R>
+struct Lane {
+    TopoShared<K, R> &S;
+    int t;
+    const double *__restrict__ rel;
+    int64_t n, p;
+    __device__ void load64(int r, double (&x)[3]) const {
+        for (int d = 0; d < 3; d++) x[d] = rel[((int64_t)r * 3 + d) * n + p];
     }
-    return orient_sos64(pa, pb, pc, pd, a, b, c, d);
+    __device__ void load(int r, R (&x)[3]) const {
+        for (int d = 0; d < 3; d++) x[d] = S.P[d][r][t];
+    }
+};
+
+// orientation of facet (a,b,c) against point q (held in registers)
+template <int K, typename R>
+__device__ inline int lane_orient(const Lane<K, R> &L, int a, int b, int c, const R (&pq)[3], int q) {
+    R pa[3], pb[3], pc[3];
+    L.load(a, pa);
+    L.load(b, pb);
+    L.load(c, pc);
+    if constexpr (sizeof(R) == 8) {
+        return orient_sos64(pa, pb, pc, pq, a, b, c, q);
+    } else {
+        int s = orient_filter_f32in(pa, pb, pc, pq);
+        if (s) return s;
+        double da[3], db[3], dc[3], dq[3];
+        L.load64(a, da);
+        L.load64(b, db);
+        L.load64(c, dc);
+        L.load64(q, dq);
+        return orient_sos64(da, db, dc, dq, a, b, c, q);
+    }
 }
 
-// orientation of facet (a,b,c) against the point p held in registers
-template <int K>
-__device__ inline int lane_orient_p(TopoShared<K> &S, int t, int a, int b, int c, const double (&pp)[3], int p) {
-    double pa[3], pb[3], pc[3];
-    for (int k = 0; k < 3; k++) {
-        pa[k] = S.P[k][a][t];
-        pb[k] = S.P[k][b][t];
-        pc[k] = S.P[k][c][t];
+template <int K, typename R>
+__device__ inline int lane_det3(const Lane<K, R> &L, int a, int b, int c) {
+    R pa[3], pb[3], pc[3];
+    L.load(a, pa);
+    L.load(b, pb);
+    L.load(c, pc);
+    if constexpr (sizeof(R) == 8) {
+        return det3_sign64(pa, pb, pc);
+    } else {
+        int s = det3_filter_f32in(pa, pb, pc);
+        if (s) return s;
+        double da[3], db[3], dc[3];
+        L.load64(a, da);
+        L.load64(b, db);
+        L.load64(c, dc);
+        return det3_sign64(da, db, dc);
     }
-    return orient_sos64(pa, pb, pc, pp, a, b, c, p);
 }
 
 // returns 1 if the hull is valid (all K points vertices, centre strictly
 // inside); the facets are left in S.F[0 .. 2K-5]
-template <int K>
-__device__ int lane_hull(TopoShared<K> &S, int t) {
+template <int K, typename R>
+__device__ int lane_hull(const Lane<K, R> &L) {
+    TopoShared<K, R> &S = L.S;
+    const int t = L.t;
     int a = 0, b = 1, c = 2, d = 3;
-    if (lane_orient<K>(S, t, 0, 1, 2, 3) > 0) { b = 2; c = 1; }
+    {
+        R p3[3];
+        L.load(3, p3);
+        if (lane_orient<K, R>(L, 0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
+    }
     S.F[0][t] = fpack(a, b, c, 1, 2, 3);
     S.F[1][t] = fpack(b, a, d, 0, 3, 2);
     S.F[2][t] = fpack(c, b, d, 0, 1, 3);
@@ -363,10 +418,11 @@ __device__ int lane_hull(TopoShared<K> &S, int t) {
     for (int p = 4; p < K; p++) {
         uint32_t vis = 0;
         int nvis = 0;
-        const double pp[3] = {S.P[0][p][t], S.P[1][p][t], S.P[2][p][t]};
+        R pp[3];
+        L.load(p, pp);
         for (int f = 0; f < nf; f++) {
             uint32_t w = S.F[f][t];
-            if (lane_orient_p<K>(S, t, fv(w, 0), fv(w, 1), fv(w, 2), pp, p) > 0) {
+            if (lane_orient<K, R>(L, fv(w, 0), fv(w, 1), fv(w, 2), pp, p) > 0) {
                 vis |= 1u << f;
                 nvis++;
             }
@@ -431,13 +487,7 @@ __device__ int lane_hull(TopoShared<K> &S, int t) {
     // centre strictly inside every facet: det[a; b; c] > 0 exactly
     for (int f = 0; f < 2 * K - 4; f++) {
         uint32_t w = S.F[f][t];
-        double pa[3], pb[3], pc[3];
-        for (int k = 0; k < 3; k++) {
-            pa[k] = S.P[k][fv(w, 0)][t];
-            pb[k] = S.P[k][fv(w, 1)][t];
-            pc[k] = S.P[k][fv(w, 2)][t];
-        }
-        if (det3_sign64(pa, pb, pc) <= 0) return 0;
+        if (lane_det3<K, R>(L, fv(w, 0), fv(w, 1), fv(w, 2)) <= 0) return 0;
     }
     return 1;
 }
@@ -448,8 +498,8 @@ __device__ int lane_hull(TopoShared<K> &S, int t) {
 // code[] receives the K words; the return value is the labelling (nibble
 // l = vertex of label l).  One code per hull: the tables hold every
 // minimum-signature start edge of every template triangulation.
-template <int K>
-__device__ uint64_t lane_start_edge_code(TopoShared<K> &S, int t, uint64_t degs, uint64_t (&code)[K]) {
+template <int K, typename R>
+__device__ uint64_t lane_start_edge_code(TopoShared<K, R> &S, int t, uint64_t degs, uint64_t (&code)[K]) {
     int mindeg = 15;
 #pragma unroll
     for (int x = 0; x < K; x++) mindeg = min(mindeg, (int)nib(degs, x));
@@ -460,7 +510,7 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K> &S, int t, uint64_t degs,
     int bu = 0, bv = 0;
     for (uint32_t m = mdmask; m; m &= m - 1) {
         int u = __builtin_ctz(m);
-        uint64_t ntu = S.NT[u][t];
+        uint64_t ntu = S.nt(u, t);
         int v0 = 0;
         while (nib(ntu, v0) == 0xF) v0++;
         uint64_t dg = 0;  // degrees of u's neighbours, counter-clockwise from v0
@@ -481,7 +531,7 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K> &S, int t, uint64_t degs,
         }
     }
     code[0] = minsig;
-    uint64_t ntu = S.NT[bu][t];
+    uint64_t ntu = S.nt(bu, t);
     uint64_t lab = ~0ull, ord = (uint64_t)bu, par = 0;
     lab = setnib(lab, bu, 0);
     int y = bv;
@@ -496,7 +546,7 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K> &S, int t, uint64_t degs,
     for (int i = 1; i < K; i++) {
         int x = min((int)nib(ord, i), K - 1);
         int yy = (int)nib(par, x);
-        uint64_t ntx = S.NT[x][t];
+        uint64_t ntx = S.nt(x, t);
         int dx = (int)nib(degs, x);
         uint64_t row = (uint64_t)dx << 60;
         for (int j = 0; j < dx; j++) {
@@ -516,11 +566,11 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K> &S, int t, uint64_t degs,
     return ord;
 }
 
-template <int K>
+template <int K, typename R>
 __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
                                               const int32_t *__restrict__ nbr_id, TablesView T,
                                               int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
-    __shared__ TopoShared<K> S;
+    __shared__ TopoShared<K, R> S;
     const int t = threadIdx.x;
     const int64_t p = blockIdx.x * (int64_t)TB + t;
     if (p >= n) return;
@@ -529,20 +579,21 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
     uint64_t ordw = 0;
     if (nbr_id[(int64_t)(K - 1) * n + p] >= 0) {
         for (int r = 0; r < K; r++)
-            for (int d = 0; d < 3; d++) S.P[d][r][t] = nbr_rel[((int64_t)r * 3 + d) * n + p];
-        if (lane_hull<K>(S, t)) {
-            for (int x = 0; x < K; x++) S.NT[x][t] = ~0ull;
+            for (int d = 0; d < 3; d++) S.P[d][r][t] = (R)nbr_rel[((int64_t)r * 3 + d) * n + p];
+        Lane<K, R> L{S, t, nbr_rel, n, p};
+        if (lane_hull<K, R>(L)) {
             uint64_t degs = 0;
+            for (int x = 0; x < K; x++) S.set_nt(x, t, ~0ull);  // overwrites this lane's points
             for (int f = 0; f < 2 * K - 4; f++) {
                 uint32_t w = S.F[f][t];
                 int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
-                S.NT[a][t] = setnib(S.NT[a][t], b, c);
-                S.NT[b][t] = setnib(S.NT[b][t], c, a);
-                S.NT[c][t] = setnib(S.NT[c][t], a, b);
+                S.set_nt(a, t, setnib(S.nt(a, t), b, c));
+                S.set_nt(b, t, setnib(S.nt(b, t), c, a));
+                S.set_nt(c, t, setnib(S.nt(c, t), a, b));
                 degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
             }
             uint64_t best[K];
-            uint64_t ord = lane_start_edge_code<K>(S, t, degs, best);
+            uint64_t ord = lane_start_edge_code<K, R>(S, t, degs, best);
             // table lookup with full-code verification
             uint64_t h = code_hash(best, K);
             int mask = T.hmask[grp];
@@ -591,73 +642,85 @@ __device__ inline uint64_t rep_vector(const TemplateDev &D, uint64_t cmap, int &
     return best;
 }
 
+template <typename T>
 struct CandEval {
-    double r, s, q[4];
+    T r, s, q[4];
 };
 
-// eq.(3) for one candidate: observed rank r <-> template vertex tv(r)
-template <int K>
-__device__ inline void eval_candidate(const double (&a)[NMAX][3], double Ga, const TemplateDev &D, uint64_t tv_of_rank,
-                                      CandEval &out) {
-    double S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double Gb = 0;
-    for (int x = 0; x < 3; x++)
-        for (int y = 0; y < 3; y++) S[x][y] += D.b[0][x] * a[0][y];
+// eq.(3) for one candidate: observed rank r <-> template vertex tv(r).
+// a[] are the centred observed points (row 0 = centre), in the working
+// precision T; the template comes from the FP64 table.
+template <int K, typename T>
+__device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const TemplateDev &D, uint64_t tv_of_rank,
+                                      CandEval<T> &out) {
+    T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    T Gb = 0;
+    {
+        const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[0][y];
+        Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+    }
 #pragma unroll
     for (int r = 0; r < K; r++) {
-        const double *bb = D.b[nib(tv_of_rank, r) + 1];
+        const double *b64 = D.b[nib(tv_of_rank, r) + 1];
+        const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
         for (int x = 0; x < 3; x++)
             for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[r + 1][y];
+        Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
     }
-    for (int i = 0; i <= K; i++) Gb += D.b[i][0] * D.b[i][0] + D.b[i][1] * D.b[i][1] + D.b[i][2] * D.b[i][2];
-    double lam = qcp_solve(S, Ga, Gb, out.q);
-    double s = Ga > 0 ? lam / Ga : 0.0;
-    double R[3][3];
-    quat_rot(out.q, R);
-    double res = 0;
+    T lam = qcp_solve<T>(S, Ga, Gb, out.q);
+    T s = Ga > T(0) ? lam / Ga : T(0);
+    T R[3][3];
+    quat_rot<T>(out.q, R);
+    T res = 0;
     {
-        const double *bb = D.b[0];
+        const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
         for (int x = 0; x < 3; x++) {
-            double d = s * a[0][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
+            T d = s * a[0][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
             res += d * d;
         }
     }
 #pragma unroll
     for (int r = 0; r < K; r++) {
-        const double *bb = D.b[nib(tv_of_rank, r) + 1];
+        const double *b64 = D.b[nib(tv_of_rank, r) + 1];
+        const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
         for (int x = 0; x < 3; x++) {
-            double d = s * a[r + 1][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
+            T d = s * a[r + 1][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
             res += d * d;
         }
     }
-    out.r = sqrt(res / (K + 1));
+    out.r = sqrt(res / T(K + 1));
     out.s = s;
 }
 
 // observed points of one hull group: centre (row 0) and the innermost K
 // neighbours, minus their barycentre (eq. 2); Ga = sum of squared norms
-template <int K>
-__device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t n, int64_t p, double (&a)[NMAX][3],
-                                    double &Ga) {
+template <int K, typename T>
+__device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t n, int64_t p, T (&a)[NMAX][3],
+                                    T &Ga) {
+    double v[KMAX][3];
     double c[3] = {0, 0, 0};
 #pragma unroll
     for (int r = 0; r < K; r++)
         for (int d = 0; d < 3; d++) {
-            a[r + 1][d] = nbr_rel[((int64_t)r * 3 + d) * n + p];
-            c[d] += a[r + 1][d];
+            v[r][d] = nbr_rel[((int64_t)r * 3 + d) * n + p];
+            c[d] += v[r][d];
         }
     for (int d = 0; d < 3; d++) c[d] /= (K + 1);
-    Ga = 0;
+    double g = 0;
     for (int d = 0; d < 3; d++) {
-        a[0][d] = -c[d];
-        Ga += c[d] * c[d];
+        a[0][d] = (T)(-c[d]);
+        g += c[d] * c[d];
     }
 #pragma unroll
     for (int r = 0; r < K; r++)
         for (int d = 0; d < 3; d++) {
-            a[r + 1][d] -= c[d];
-            Ga += a[r + 1][d] * a[r + 1][d];
+            double x = v[r][d] - c[d];
+            a[r + 1][d] = (T)x;
+            g += x * x;
         }
+    Ga = (T)g;
 }
 
 // template vertex of each observed rank for candidate perm (label -> vertex)
@@ -680,13 +743,13 @@ __device__ inline void scan_group(const MatchShared &M, const TablesView &T, int
                                   uint32_t mask, const double *__restrict__ nbr_rel, int64_t n, int64_t p, double &m1,
                                   double &m2, int &arg_grp, int &arg_c) {
     double a[NMAX][3], Ga;
-    load_centred<K>(nbr_rel, n, p, a, Ga);
+    load_centred<K, double>(nbr_rel, n, p, a, Ga);
     int c0 = T.cstart[grp][cid], c1 = T.cstart[grp][cid + 1];
     for (int c = c0; c < c1; c++) {
         Candidate cd = T.cand[grp][c];
         if (!((mask >> cd.tmpl) & 1)) continue;
-        CandEval ev;
-        eval_candidate<K>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
+        CandEval<double> ev;
+        eval_candidate<K, double>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
         if (ev.r < m1) {
             m2 = m1;
             m1 = ev.r;
@@ -705,13 +768,13 @@ __device__ inline void tie_group(const MatchShared &M, const TablesView &T, int 
                                  uint32_t mask, const double *__restrict__ nbr_rel, int64_t n, int64_t p, double rstar,
                                  int &win_grp, int &win_c, int &win_t, uint64_t &win_rep) {
     double a[NMAX][3], Ga;
-    load_centred<K>(nbr_rel, n, p, a, Ga);
+    load_centred<K, double>(nbr_rel, n, p, a, Ga);
     int c0 = T.cstart[grp][cid], c1 = T.cstart[grp][cid + 1];
     for (int c = c0; c < c1; c++) {
         Candidate cd = T.cand[grp][c];
         if (!((mask >> cd.tmpl) & 1)) continue;
-        CandEval ev;
-        eval_candidate<K>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
+        CandEval<double> ev;
+        eval_candidate<K, double>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
         if (!(ev.r <= rstar + 1e-12)) continue;
         int gsel;
         uint64_t rep = rep_vector(M.tpl[cd.tmpl], rank_of_tv(cd.perm, ord, K), gsel);
@@ -725,63 +788,63 @@ __device__ inline void tie_group(const MatchShared &M, const TablesView &T, int 
     }
 }
 
-template <int K>
+template <int K, typename RT>
 __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
                               const double *__restrict__ nbr_rel, double cutoff, int64_t p, int64_t n, int32_t i,
                               const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
                               const MatchOut &O) {
-    double a[NMAX][3], Ga;
-    load_centred<K>(nbr_rel, n, p, a, Ga);
+    RT a[NMAX][3], Ga;
+    load_centred<K, RT>(nbr_rel, n, p, a, Ga);
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
     uint64_t tv = tv_of_rank(cd.perm, ord, K);
-    CandEval ev;
-    eval_candidate<K>(a, Ga, D, tv, ev);
-    int type = (ev.r <= cutoff) ? cd.tmpl + 1 : 0;
+    CandEval<RT> ev;
+    eval_candidate<K, RT>(a, Ga, D, tv, ev);
+    int type = ((double)ev.r <= cutoff) ? cd.tmpl + 1 : 0;
     uint64_t cmap = rank_of_tv(cd.perm, ord, K);
     int g;
     uint64_t rep = rep_vector(D, cmap, g);
     // q' = q * conj(q_g)
     const double *qg = D.gq[g];
-    double w1 = ev.q[0], x1 = ev.q[1], y1 = ev.q[2], z1 = ev.q[3];
-    double w2 = qg[0], x2 = -qg[1], y2 = -qg[2], z2 = -qg[3];
-    double q[4] = {w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+    RT w1 = ev.q[0], x1 = ev.q[1], y1 = ev.q[2], z1 = ev.q[3];
+    RT w2 = (RT)qg[0], x2 = -(RT)qg[1], y2 = -(RT)qg[2], z2 = -(RT)qg[3];
+    RT q[4] = {w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
                    w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2};
-    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    RT qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     int flip = 0;
     for (int k = 0; k < 4; k++) {
         if (q[k] > 0) { flip = 1; break; }
         if (q[k] < 0) { flip = -1; break; }
     }
-    double sc = (flip < 0 ? -1.0 : 1.0) / qn;
+    RT sc = RT(flip < 0 ? -1 : 1) / qn;
     for (int k = 0; k < 4; k++) q[k] *= sc;
     // strain: A^T = V+ W', W' = a / l(a) in template order; P = sqrt(A A^T)
-    double l = 0;
+    RT l = 0;
     for (int r = 0; r <= K; r++) l += sqrt(a[r][0] * a[r][0] + a[r][1] * a[r][1] + a[r][2] * a[r][2]);
-    l /= (K + 1);
-    double At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    l /= RT(K + 1);
+    RT At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int x = 0; x < 3; x++)
-        for (int y = 0; y < 3; y++) At[x][y] += D.vpinv[x][0] * a[0][y];
+        for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][0] * a[0][y];
 #pragma unroll
     for (int r = 0; r < K; r++) {
         int col = (int)nib(tv, r) + 1;
         for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) At[x][y] += D.vpinv[x][col] * a[r + 1][y];
+            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * a[r + 1][y];
     }
-    double AA[3][3];
+    RT AA[3][3];
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) {
-            double s = 0;
+            RT s = 0;
             for (int m = 0; m < 3; m++) s += At[m][x] * At[m][y];
             AA[x][y] = s / (l * l);
         }
-    double ev3[3], V[3][3];
-    jacobi3(AA, ev3, V);
-    double P[9];
+    RT ev3[3], V[3][3];
+    jacobi3<RT>(AA, ev3, V);
+    RT P[9];
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) {
-            double s = 0;
-            for (int m = 0; m < 3; m++) s += V[x][m] * sqrt(fmax(ev3[m], 0.0)) * V[y][m];
+            RT s = 0;
+            for (int m = 0; m < 3; m++) s += V[x][m] * sqrt(fmax(ev3[m], RT(0))) * V[y][m];
             P[3 * x + y] = s;
         }
     // alloy (Sec. 6, Table 3)
@@ -815,12 +878,12 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
     }
     O.type[i] = (int8_t)type;
     if (O.alloy) O.alloy[i] = (int8_t)alloy;
-    if (O.rmsd) O.rmsd[i] = ev.r;
-    if (O.scale) O.scale[i] = ev.s;
+    if (O.rmsd) O.rmsd[i] = (double)ev.r;
+    if (O.scale) O.scale[i] = (double)ev.s;
     if (O.quat)
-        for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = q[k];
+        for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = (double)q[k];
     if (O.strain)
-        for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = P[k];
+        for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = (double)P[k];
     if (O.neighbours) {
         for (int m = 0; m < KMAX; m++) {
             int32_t id = -1;
@@ -891,6 +954,7 @@ __global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, cons
 }
 
 // One superposition per lane over the flat pair list (grid-stride).
+template <typename RT>
 __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
                                                   const uint64_t *__restrict__ ords, const int64_t *__restrict__ off,
                                                   int64_t cap, const uint2 *__restrict__ pairs,
@@ -906,25 +970,35 @@ __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__res
         int g = pr.y >> 28, k = pr.y & 0x0FFFFFFF;
         Candidate cd = T.cand[g][k];
         uint64_t ord = ords[(int64_t)g * n + p];
-        double a[NMAX][3], Ga;
-        CandEval ev;
+        RT a[NMAX][3], Ga;
+        CandEval<RT> ev;
         if (g == 0) {
-            load_centred<6>(nbr_rel, n, p, a, Ga);
-            eval_candidate<6>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
+            load_centred<6, RT>(nbr_rel, n, p, a, Ga);
+            eval_candidate<6, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
         } else if (g == 1) {
-            load_centred<12>(nbr_rel, n, p, a, Ga);
-            eval_candidate<12>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
+            load_centred<12, RT>(nbr_rel, n, p, a, Ga);
+            eval_candidate<12, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
         } else {
-            load_centred<14>(nbr_rel, n, p, a, Ga);
-            eval_candidate<14>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
+            load_centred<14, RT>(nbr_rel, n, p, a, Ga);
+            eval_candidate<14, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
         }
-        rout[q] = ev.r;
+        rout[q] = (double)ev.r;
     }
 }
 
+// Bound on |RMSD_FP32 - RMSD_FP64| of one candidate evaluated in FP32 from
+// FP64-centred points (derivation in the design notes: input rounding and
+// residual arithmetic contribute ~5e-7; the rotation error enters at second
+// order).  Decisions whose FP32 margins are below it are redone in FP64.
+constexpr double RMSD_F32_BOUND = 4e-6;
+
 // Per-atom decision over the evaluated pairs (Alg. 1 minimum with the tie
 // rule), then the outputs of the winner.  Atoms whose pairs did not fit the
-// pair buffer are evaluated here directly.
+// pair buffer are evaluated here directly.  With RT = float the pair RMSDs
+// are FP32; the decision is kept only when the best candidate beats every
+// other by more than twice the FP32 bound and lies clear of the cut-off,
+// otherwise the atom is decided in FP64.
+template <typename RT>
 __global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restrict__ nbr_rel,
                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
                                                const int8_t *__restrict__ species, TablesView T,
@@ -958,7 +1032,15 @@ __global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restri
                 m2 = r;
             }
         }
-    } else {
+    }
+    bool fp64 = q1 > cap;
+    if (sizeof(RT) == 4 && !fp64 && arg_c >= 0) {
+        bool clear = (m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) && !(fabs(m1 - cutoff) <= RMSD_F32_BOUND);
+        fp64 = !clear;
+    }
+    if (fp64) {
+        m1 = m2 = INFINITY;
+        arg_grp = arg_c = -1;
         if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
         if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
         if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
@@ -979,9 +1061,15 @@ __global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restri
             arg_c = wc;
         }
     }
-    if (arg_grp == 0) finish<6>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-    else if (arg_grp == 1) finish<12>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-    else finish<14>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+    if (fp64) {
+        if (arg_grp == 0) finish<6, double>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else if (arg_grp == 1) finish<12, double>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else finish<14, double>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+    } else {
+        if (arg_grp == 0) finish<6, RT>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else if (arg_grp == 1) finish<12, RT>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else finish<14, RT>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+    }
 }
 
 // --------------------------------------------------------------- launches
@@ -1004,25 +1092,40 @@ void launch_knn(int64_t n, const Grid &g, const int32_t *stencil, const double *
     hipLaunchKernelGGL(k_knn, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, g, stencil, pos, sx, sy, sz,
                        sid, start, nbr_id, nbr_rel, knn_out);
 }
-void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
-                 uint64_t *ord, hipStream_t st) {
+void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
+                 int32_t *code, uint64_t *ord, hipStream_t st) {
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
-    if (K == 6) hipLaunchKernelGGL(k_topo<6>, grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-    else if (K == 12) hipLaunchKernelGGL(k_topo<12>, grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-    else hipLaunchKernelGGL(k_topo<14>, grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+    if (f32) {
+        if (K == 6) hipLaunchKernelGGL((k_topo<6, float>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+        else if (K == 12) hipLaunchKernelGGL((k_topo<12, float>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+        else hipLaunchKernelGGL((k_topo<14, float>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+    } else {
+        if (K == 6) hipLaunchKernelGGL((k_topo<6, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+        else if (K == 12) hipLaunchKernelGGL((k_topo<12, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+        else hipLaunchKernelGGL((k_topo<14, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
+    }
 }
 void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
                   const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
-                  const MatchOut &O, const MatchScratch &W, hipStream_t st) {
+                  const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st) {
     unsigned nb = (unsigned)((n + 1 + 255) / 256);
     hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt);
     size_t tmp = W.scan_tmp_bytes;
     (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, (int)(n + 1), st);
     hipLaunchKernelGGL(k_cand_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, code, mask, W.off,
                        W.cap, W.pairs);
-    hipLaunchKernelGGL(k_cand_eval, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs, W.r);
-    hipLaunchKernelGGL(k_decide, dim3((unsigned)((n + MB - 1) / MB)), dim3(MB), 0, st, n, nbr_rel, nbr_id, sid,
-                       species, T, code, ord, W.off, W.cap, W.pairs, W.r, mask, cutoff, O);
+    dim3 gd((unsigned)((n + MB - 1) / MB));
+    if (f32) {
+        hipLaunchKernelGGL(k_cand_eval<float>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs,
+                           W.r);
+        hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
+                           W.cap, W.pairs, W.r, mask, cutoff, O);
+    } else {
+        hipLaunchKernelGGL(k_cand_eval<double>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap,
+                           W.pairs, W.r);
+        hipLaunchKernelGGL(k_decide<double>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
+                           W.off, W.cap, W.pairs, W.r, mask, cutoff, O);
+    }
 }
 
 }  // namespace ptm

@@ -48,10 +48,10 @@ void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, co
 void launch_knn(int64_t n, const Grid &g, const int32_t *stencil, const double *pos, const double *sx, const double *sy, const double *sz,
                 const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
                 hipStream_t st);
-void launch_topo(int K, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
+void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
                  uint64_t *ord, hipStream_t st);
 void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
                   const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
-                  const MatchOut &O, const MatchScratch &W, hipStream_t st);
+                  const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st);
 
 }  // namespace ptm

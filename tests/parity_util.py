@@ -6,6 +6,8 @@ import numpy as np
 # FP64 plain path vs the FP64 oracle: decisions bit-exact; reals differ only
 # by algorithm (QCP Newton/adjugate vs Jacobi; explicit residuals)
 TOL64 = {"rmsd": 1e-12, "scale_rel": 1e-12, "angle": 1e-9, "strain": 1e-10}
+# FP32-mixed path: decisions bit-exact; reals within the stated tolerances
+TOL32 = {"rmsd": 1e-5, "scale_rel": 1e-6, "angle": 1e-4, "strain": 1e-5}
 
 
 def quat_angle(q1, q2):

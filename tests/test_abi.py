@@ -167,3 +167,70 @@ def test_selftest_superpose_agrees_with_oracle(ptm, oracle_lib):
                 assert abs(r.value - r1) < 1e-13
                 assert abs(s.value - s1) < 1e-13 * s1
                 assert quat_angle(q, q1) < 1e-12
+
+
+def frac_orient(p):
+    a, b, c, d = [[Fraction(x) for x in r] for r in p]
+    u = [b[i] - a[i] for i in range(3)]
+    v = [c[i] - a[i] for i in range(3)]
+    w = [d[i] - a[i] for i in range(3)]
+    det = (u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0])
+           + u[2] * (v[0] * w[1] - v[1] * w[0]))
+    return (det > 0) - (det < 0)
+
+
+def test_f32_filters_never_decide_wrongly(ptm):
+    """The FP32-storage filters of the FP32-mixed form: a decided sign is the
+    exact sign on the FP64 inputs (adversarial near-coplanar sets included)."""
+    L = ptm.lib()
+    rng = np.random.default_rng(11)
+    decided = 0
+    for trial in range(6000):
+        kind = trial % 3
+        p = rng.normal(size=(4, 3)) * 2.5
+        if kind == 1:   # nearly coplanar: d in the plane of a, b, c plus a tiny offset
+            s, t = rng.random(2)
+            p[3] = p[0] + s * (p[1] - p[0]) + t * (p[2] - p[0]) + rng.normal(size=3) * 10.0 ** rng.uniform(-9, -4)
+        elif kind == 2:  # lattice-like exact coplanarity in FP64, broken by FP32 rounding
+            q = rng.integers(-2, 3, size=(4, 3)) * 1.8075
+            q[3] = q[0] + (q[1] - q[0]) - (q[2] - q[0])
+            p = q + 1e-9 * rng.normal(size=(4, 3))
+        p = np.ascontiguousarray(p)
+        got = L.ptm_selftest_orient_f32filter(p.ctypes.data_as(C.c_void_p))
+        if got:
+            decided += kind == 0
+            assert got == frac_orient(p)
+        p3 = np.ascontiguousarray(p[:3])
+        g3 = L.ptm_selftest_det3_f32filter(p3.ctypes.data_as(C.c_void_p))
+        if g3:
+            assert g3 == frac_det3(p3)
+    assert decided > 0.95 * 2000  # generic inputs are decided by the filter
+
+
+def test_superpose_f32_within_stated_tolerances(ptm, oracle_lib):
+    """FP32 candidate evaluation vs the FP64 oracle: well inside the decision
+    bound (4e-6) and the output tolerances (scale 1e-6 rel, angle 1e-4)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from parity_util import quat_angle
+    from paper_1603_05143_amd.synthetic import random_rotations
+    L = ptm.lib()
+    rng = np.random.default_rng(6)
+    for t in range(5):
+        w = oracle_lib.template(t)["w"]
+        tpl = np.ascontiguousarray(np.vstack([np.zeros(3), w]))
+        for sig in (0.0, 0.01, 0.1, 0.5, 2.0):
+            for _ in range(60):
+                R = random_rotations(rng, 1)[0]
+                obs = np.vstack([np.zeros(3), w @ R.T * (2.5 / np.linalg.norm(w[0]))
+                                 + rng.normal(scale=sig, size=w.shape)])
+                obs = np.ascontiguousarray(obs)
+                r, s, q = C.c_double(), C.c_double(), np.zeros(4)
+                L.ptm_selftest_superpose_f32(len(obs), obs.ctypes.data_as(C.c_void_p),
+                                             tpl.ctypes.data_as(C.c_void_p), C.byref(r), C.byref(s),
+                                             q.ctypes.data_as(C.c_void_p))
+                r1, s1, q1, _ = oracle_lib.superpose(obs, tpl)
+                assert abs(r.value - r1) < 1e-6
+                assert abs(s.value - s1) < 1e-6 * s1
+                if sig < 1.0:
+                    assert quat_angle(q, q1) < 1e-5

@@ -1,6 +1,6 @@
-"""GPU parity of the FP64 HIP path against the FP64 oracle, through the C
-ABI: decisions (type, neighbour orders, alloy) bit-exact, reals within the
-algorithmic tolerances of parity_util.TOL64."""
+"""GPU parity of both HIP forms against the FP64 oracle, through the C ABI:
+decisions (type, neighbour orders, alloy) bit-exact; reals within
+parity_util.TOL64 (FP64 plain) or TOL32 (FP32-mixed)."""
 import math
 import sys
 
@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_1603_05143_amd import ptm, synthetic as S
-from parity_util import compare
+from parity_util import TOL32, TOL64, compare as _compare
 
 pytestmark = pytest.mark.gpu
 
@@ -20,14 +20,23 @@ def torch_cuda():
     return torch
 
 
-@pytest.fixture(scope="module")
-def clf(torch_cuda):
-    c = ptm.Classifier(device=0, precision=ptm.PTM_FP64)
+@pytest.fixture(scope="module", params=[ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def clf(torch_cuda, request):
+    c = ptm.Classifier(device=0, precision=request.param)
+    c.tol = TOL64 if request.param == ptm.PTM_FP64 else TOL32
     yield c
     c.close()
 
 
+_current_tol = [TOL64]
+
+
+def compare(got, ref, **kw):
+    return _compare(got, ref, tol=_current_tol[0], **kw)
+
+
 def run_gpu(torch, clf, frame, mask=ptm.PTM_ALL, cutoff=math.inf):
+    _current_tol[0] = clf.tol
     print(f"[gpu] n={frame.n} box={frame.box.tolist()} mask={mask}", flush=True)
     pos = torch.from_numpy(np.ascontiguousarray(frame.positions)).to("cuda:0")
     sp = None if frame.species is None else torch.from_numpy(frame.species).to("cuda:0")
