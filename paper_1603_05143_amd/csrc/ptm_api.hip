@@ -169,6 +169,9 @@ Grid make_grid(const double box[3], const double mn[3], const double mx[3], int6
         hmax = std::fmax(hmax, g.h[a]);
     }
     g.margin = 1e-9 * hmax;
+    g.canonical = 1;
+    for (int a = 0; a < 3; a++)
+        if (g.periodic[a] && !(mn[a] >= 0.0 && mx[a] < box[a])) g.canonical = 0;
     return g;
 }
 

@@ -170,6 +170,30 @@ __device__ inline void scan_cell(int c, const Grid &g, double xi, double yi, dou
     }
 }
 
+// scan cell c whose atoms need the known minimum-image shift (sh = s*L with
+// s in {-1, 0, 1}): d - s*L is bit-identical to the general formula because
+// rint(d/L) = s for every atom of a stencil cell when positions lie in
+// [0, L) and the grid has at least 8 cells per periodic axis.
+template <int KN>
+__device__ inline void scan_cell_shift(int c, double xi, double yi, double zi, double shx, double shy, double shz,
+                                       int32_t i, const double *__restrict__ sx, const double *__restrict__ sy,
+                                       const double *__restrict__ sz, const int32_t *__restrict__ sid,
+                                       const int32_t *__restrict__ start, double (&kd)[KN], int32_t (&kj)[KN],
+                                       int &found) {
+    int q1 = start[c + 1];
+    for (int q = start[c]; q < q1; q++) {
+        int32_t j = sid[q];
+        if (j == i) continue;
+        double dx = (sx[q] - xi) - shx;
+        double dy = (sy[q] - yi) - shy;
+        double dz = (sz[q] - zi) - shz;
+        double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+        double d2 = (xx + yy) + zz;
+        found++;
+        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, d2, j);
+    }
+}
+
 // Is the block of offsets [lo, hi] per axis a certificate for the current
 // K-th distance?  all = the block covers every cell.
 __device__ inline bool certified(const Grid &g, const int (&cc)[3], const double (&u)[3], const int (&lo)[3],
@@ -220,26 +244,44 @@ __global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const int32_t *_
     int s_next = 1;
     bool done = false;
     // fast path: stencil shells 0..3 in a uniform order (every lane walks the
-    // same offsets), valid when no periodic axis wraps onto itself
-    bool fast = true;
-    for (int a = 0; a < 3; a++) fast = fast && (!g.periodic[a] || g.nc[a] >= 2 * STENCIL_SHELLS + 1);
+    // same offsets), valid when no periodic axis wraps onto itself.  Once K
+    // neighbours are known, cells farther than the current K-th distance
+    // are skipped (their atoms could not enter the list).
+    bool fast = true, shifted = g.canonical != 0;
+    for (int a = 0; a < 3; a++) {
+        fast = fast && (!g.periodic[a] || g.nc[a] >= 2 * STENCIL_SHELLS + 1);
+        shifted = shifted && (!g.periodic[a] || g.nc[a] >= 2 * STENCIL_SHELLS + 2);
+    }
     if (fast) {
         for (int s = 0; s <= STENCIL_SHELLS && !done; s++) {
             for (int idx = stencil_start(s); idx < stencil_start(s + 1); idx++) {
                 int32_t o = stencil[idx];
-                int c3[3] = {cc[0] + (o & 0xFF) - 8, cc[1] + ((o >> 8) & 0xFF) - 8, cc[2] + ((o >> 16) & 0xFF) - 8};
+                int off3[3] = {(o & 0xFF) - 8, ((o >> 8) & 0xFF) - 8, ((o >> 16) & 0xFF) - 8};
+                int c3[3];
+                double sh[3] = {0.0, 0.0, 0.0}, gap2 = 0.0;
                 bool skip = false;
                 for (int a = 0; a < 3; a++) {
+                    c3[a] = cc[a] + off3[a];
+                    // distance from the atom to the cell's slab along this axis
+                    double lo = (cc[a] + off3[a]) * g.h[a] - u[a], hi = lo + g.h[a];
+                    double gap = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
+                    gap = gap > g.margin ? gap - g.margin : 0.0;
+                    gap2 += gap * gap;
                     if (g.periodic[a]) {
-                        if (c3[a] < 0) c3[a] += g.nc[a];
-                        else if (c3[a] >= g.nc[a]) c3[a] -= g.nc[a];
+                        // a cell below 0 wraps to the top of the box: its atoms lie
+                        // about one box length above, so d - L is the minimum image
+                        if (c3[a] < 0) { c3[a] += g.nc[a]; sh[a] = g.L[a]; }
+                        else if (c3[a] >= g.nc[a]) { c3[a] -= g.nc[a]; sh[a] = -g.L[a]; }
                     } else if (c3[a] < 0 || c3[a] >= g.nc[a]) {
                         skip = true;
                     }
                 }
-                if (skip) continue;
+                if (skip || (found >= KN && gap2 > kd[KN - 1])) continue;
                 int c = (c3[2] * g.nc[1] + c3[1]) * g.nc[0] + c3[0];
-                scan_cell<KN>(c, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj, found);
+                if (shifted)
+                    scan_cell_shift<KN>(c, xi, yi, zi, sh[0], sh[1], sh[2], i, sx, sy, sz, sid, start, kd, kj, found);
+                else
+                    scan_cell<KN>(c, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj, found);
             }
             if (s >= 1) {
                 int lo[3] = {-s, -s, -s}, hi[3] = {s, s, s};

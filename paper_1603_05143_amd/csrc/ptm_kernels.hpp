@@ -17,6 +17,7 @@ struct Grid {
     double h[3];      // cell edge
     double inv_h[3];  // cells per unit length
     double margin;    // safety margin of the neighbour-search certificate
+    int canonical;    // every periodic coordinate already lies in [0, L)
 };
 
 struct MatchOut {
