@@ -35,7 +35,7 @@ static int64_t pair_capacity(int64_t n) { return 6 * n + 64; }
 size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
-    b += align_up(4 * (size_t)(cells + 1)) * 2;  // count, start
+    b += align_up(4 * (size_t)(cells + 2)) * 2;  // count (+ k-NN leftover counter), start
     b += align_up(8 * (size_t)n) * 3;         // sorted positions
     b += align_up(4 * (size_t)n * KMAX);      // neighbour ids
     b += align_up(8 * (size_t)n * KMAX * 3);  // neighbour vectors
@@ -80,8 +80,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
     cell_of = (int32_t *)take(4 * (size_t)n);
     slot_of = (int32_t *)take(4 * (size_t)n);
     sid = (int32_t *)take(4 * (size_t)n);
-    count = (int32_t *)take(4 * (size_t)(cells + 1));
-    start = (int32_t *)take(4 * (size_t)(cells + 1));
+    count = (int32_t *)take(4 * (size_t)(cells + 2));
+    start = (int32_t *)take(4 * (size_t)(cells + 2));
     sx = (double *)take(8 * (size_t)n);
     sy = (double *)take(8 * (size_t)n);
     sz = (double *)take(8 * (size_t)n);
@@ -186,14 +186,16 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     const Grid &g = J.grid;
     if ((ps = mark(PTM_STAGE_BIN)) != PTM_OK) return ps;
     int64_t cells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
-    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 1), st));
+    // count[cells + 1] counts the atoms the fast k-NN search leaves over
+    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 2), st));
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
     size_t tmp = S.scan_tmp_bytes;
     PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
     launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.sx, S.sy, S.sz, S.sid, st);
     if ((ps = mark(PTM_STAGE_KNN)) != PTM_OK) return ps;
-    launch_knn(n, g, ctx->view.stencil, J.pos, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn,
-               st);
+    // slot_of is free once the atoms are scattered: it holds the leftover list
+    launch_knn(n, g, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, S.slot_of,
+               S.count + cells + 1, st);
     if ((ps = mark(PTM_STAGE_TOPO6)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
     const bool need[NGRP] = {(m & 0x1u) != 0, (m & 0xEu) != 0, (m & 0x10u) != 0};

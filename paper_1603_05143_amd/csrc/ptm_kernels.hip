@@ -120,9 +120,11 @@ __device__ inline double min_image(double d, const Grid &g, int a) {
     return d;
 }
 
-// insert (d2, j) into the ascending list (kd, kj) of length KN
+// insert (d2, j) -- with j's position q in the sorted arrays -- into the
+// list (kd, kj, kq) of length KN, ascending by (d2, j)
 template <int KN>
-__device__ inline void topk_insert(double (&kd)[KN], int32_t (&kj)[KN], double d2, int32_t j) {
+__device__ inline void topk_insert(double (&kd)[KN], int32_t (&kj)[KN], int32_t (&kq)[KN], double d2, int32_t j,
+                                   int32_t q) {
     bool done = false;
 #pragma unroll
     for (int m = KN - 1; m > 0; m--) {
@@ -130,12 +132,14 @@ __device__ inline void topk_insert(double (&kd)[KN], int32_t (&kj)[KN], double d
         if (!done) {
             kd[m] = lt ? kd[m - 1] : d2;
             kj[m] = lt ? kj[m - 1] : j;
+            kq[m] = lt ? kq[m - 1] : q;
         }
         done = done || !lt;
     }
     if (!done) {
         kd[0] = d2;
         kj[0] = j;
+        kq[0] = q;
     }
 }
 
@@ -155,7 +159,8 @@ template <int KN>
 __device__ inline void scan_cell(int c, const Grid &g, double xi, double yi, double zi, int32_t i,
                                  const double *__restrict__ sx, const double *__restrict__ sy,
                                  const double *__restrict__ sz, const int32_t *__restrict__ sid,
-                                 const int32_t *__restrict__ start, double (&kd)[KN], int32_t (&kj)[KN], int &found) {
+                                 const int32_t *__restrict__ start, double (&kd)[KN], int32_t (&kj)[KN],
+                                 int32_t (&kq)[KN], int &found) {
     int q1 = start[c + 1];
     for (int q = start[c]; q < q1; q++) {
         int32_t j = sid[q];
@@ -166,31 +171,7 @@ __device__ inline void scan_cell(int c, const Grid &g, double xi, double yi, dou
         double xx = dx * dx, yy = dy * dy, zz = dz * dz;
         double d2 = (xx + yy) + zz;
         found++;
-        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, d2, j);
-    }
-}
-
-// scan cell c whose atoms need the known minimum-image shift (sh = s*L with
-// s in {-1, 0, 1}): d - s*L is bit-identical to the general formula because
-// rint(d/L) = s for every atom of a stencil cell when positions lie in
-// [0, L) and the grid has at least 8 cells per periodic axis.
-template <int KN>
-__device__ inline void scan_cell_shift(int c, double xi, double yi, double zi, double shx, double shy, double shz,
-                                       int32_t i, const double *__restrict__ sx, const double *__restrict__ sy,
-                                       const double *__restrict__ sz, const int32_t *__restrict__ sid,
-                                       const int32_t *__restrict__ start, double (&kd)[KN], int32_t (&kj)[KN],
-                                       int &found) {
-    int q1 = start[c + 1];
-    for (int q = start[c]; q < q1; q++) {
-        int32_t j = sid[q];
-        if (j == i) continue;
-        double dx = (sx[q] - xi) - shx;
-        double dy = (sy[q] - yi) - shy;
-        double dz = (sz[q] - zi) - shz;
-        double xx = dx * dx, yy = dy * dy, zz = dz * dz;
-        double d2 = (xx + yy) + zz;
-        found++;
-        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, d2, j);
+        if (d2 < kd[KN - 1] || (d2 == kd[KN - 1] && j < kj[KN - 1])) topk_insert<KN>(kd, kj, kq, d2, j, q);
     }
 }
 
@@ -217,17 +198,87 @@ __device__ inline bool certified(const Grid &g, const int (&cc)[3], const double
     return found >= KN && dmin > 0 && kth < dmin * dmin;
 }
 
-__global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const int32_t *__restrict__ stencil,
-                                             const double *__restrict__ pos, const double *__restrict__ sx,
-                                             const double *__restrict__ sy, const double *__restrict__ sz,
-                                             const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
-                                             int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
-                                             int32_t *__restrict__ knn_out) {
+// Write the K nearest neighbours of sorted atom p (original id i): ids and
+// minimum-image vectors in the component-major layout the hull kernels read.
+// sx[q] is a copy of pos[3 sid[q]], so the vectors are those of the input.
+template <int KN>
+__device__ inline void write_knn(int64_t n, int64_t p, int32_t i, int cnt, const int32_t (&kq)[KN], const Grid &g,
+                                 double xi, double yi, double zi, const double *__restrict__ sx,
+                                 const double *__restrict__ sy, const double *__restrict__ sz,
+                                 const int32_t *__restrict__ sid, int32_t *__restrict__ nbr_id,
+                                 double *__restrict__ nbr_rel, int32_t *__restrict__ knn_out) {
+#pragma unroll
+    for (int m = 0; m < KN; m++) {
+        int32_t j = -1;
+        double r0 = 0, r1 = 0, r2 = 0;
+        if (m < cnt) {
+            int32_t q = kq[m];
+            j = sid[q];
+            r0 = min_image(sx[q] - xi, g, 0);
+            r1 = min_image(sy[q] - yi, g, 1);
+            r2 = min_image(sz[q] - zi, g, 2);
+        }
+        nbr_id[(int64_t)m * n + p] = j;
+        nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
+        nbr_rel[((int64_t)m * 3 + 1) * n + p] = r1;
+        nbr_rel[((int64_t)m * 3 + 2) * n + p] = r2;
+        if (knn_out) knn_out[(int64_t)i * KN + m] = j;
+    }
+}
+
+// Packed search key of a candidate: high word = FP32 rounding of d^2 (its
+// bit pattern, offset by 2^20 so that the word read as the high half of an
+// FP64 number is a normal, finite value), low word = sorted index q.  Keys
+// compare as FP64 numbers in the order (round(d^2), q); rounding to nearest
+// is monotone, so round(a) < round(b) implies a < b.
+__device__ inline double pack_key(double d2, int32_t q) {
+    uint32_t hi = __float_as_uint(__double2float_rn(d2)) + 0x00100000u;
+    return __hiloint2double((int)hi, q);
+}
+__device__ inline uint32_t key_hi(double k) { return (uint32_t)__double2hiint(k); }
+__device__ inline int32_t key_q(double k) { return __double2loint(k); }
+// upper bound of every d^2 whose rounding gives the key's high word
+// (relative error 2^-24 of a normal float, absolute 2^-150 of a subnormal)
+__device__ inline double key_d2_upper(double k) {
+    return (double)__uint_as_float(key_hi(k) - 0x00100000u) * (1.0 + 0x1p-22) + 0x1p-148;
+}
+
+// One step of the insertion: (a, t) <- (min(a, t), max(a, t)).  Written as
+// two VALU instructions that update a in place: the keys are finite, normal
+// FP64 numbers (no NaN, no denormal), for which the instructions return one
+// of their operands unchanged, and keeping each list entry in one register
+// avoids copies of the whole list on every loop iteration.
+__device__ inline void minmax_step(double &a, double &t) {
+    double hi;
+    asm("v_max_f64 %0, %1, %2\n\tv_min_f64 %1, %1, %2" : "=&v"(hi), "+v"(a) : "v"(t));
+    t = hi;
+}
+
+constexpr int KNN_FAST_LIST = KMAX + 1;  // the 15th entry certifies the boundary
+
+// Fast search: the 5x5x5 block of cells around the atom, walked as 25
+// x-rows nearest-first.  A row of cells is one contiguous range of the
+// sorted atoms (two if it wraps), and each lane walks its ranges in one flat
+// loop, so a wave pays about the per-lane candidate count rather than the
+// per-cell maximum.  The running list holds the 15 smallest packed keys,
+// kept by a branch-free min/max insertion.  Once 14 keys are known, rows and
+// the x-extent of each row are trimmed to an upper bound of the current 14th
+// distance.  The result is accepted when it is provably the exact ordered
+// (d^2, id) list: the high words of the 15 keys strictly increase (then the
+// rounded order is the exact order and no atom outside ties with the 14th)
+// and the exact 14th distance is certified by the block.  Other atoms are
+// appended to a list for k_knn_exact.  Requires every periodic axis to have
+// at least 5 cells (no axis wraps onto itself within the block).
+__global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ sx,
+                                                  const double *__restrict__ sy, const double *__restrict__ sz,
+                                                  const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                                                  int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                                                  int32_t *__restrict__ knn_out, int32_t *__restrict__ todo,
+                                                  int32_t *__restrict__ todo_count) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
-    constexpr int KN = KMAX;
+    constexpr int KN = KNN_FAST_LIST;
     const double xi = sx[p], yi = sy[p], zi = sz[p];
-    const int32_t i = sid[p];
     const double xs[3] = {xi, yi, zi};
     int cc[3];
     double u[3];
@@ -235,106 +286,267 @@ __global__ void __launch_bounds__(256) k_knn(int64_t n, Grid g, const int32_t *_
         cc[a] = cell_coord(xs[a], g, a);
         u[a] = wrapped(xs[a], g, a);
     }
-    double kd[KN];
-    int32_t kj[KN];
+    const double INF = __longlong_as_double(0x7ff0000000000000ll);
+    double key[KN];
 #pragma unroll
-    for (int m = 0; m < KN; m++) { kd[m] = INFINITY; kj[m] = 0x7fffffff; }
-    int found = 0;
-    int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};  // block already searched (empty)
-    int s_next = 1;
-    bool done = false;
-    // fast path: stencil shells 0..3 in a uniform order (every lane walks the
-    // same offsets), valid when no periodic axis wraps onto itself.  Once K
-    // neighbours are known, cells farther than the current K-th distance
-    // are skipped (their atoms could not enter the list).
-    bool fast = true, shifted = g.canonical != 0;
-    for (int a = 0; a < 3; a++) {
-        fast = fast && (!g.periodic[a] || g.nc[a] >= 2 * STENCIL_SHELLS + 1);
-        shifted = shifted && (!g.periodic[a] || g.nc[a] >= 2 * STENCIL_SHELLS + 2);
-    }
-    if (fast) {
-        for (int s = 0; s <= STENCIL_SHELLS && !done; s++) {
-            for (int idx = stencil_start(s); idx < stencil_start(s + 1); idx++) {
-                int32_t o = stencil[idx];
-                int off3[3] = {(o & 0xFF) - 8, ((o >> 8) & 0xFF) - 8, ((o >> 16) & 0xFF) - 8};
-                int c3[3];
-                double sh[3] = {0.0, 0.0, 0.0}, gap2 = 0.0;
+    for (int m = 0; m < KN; m++) key[m] = INF;
+    // known minimum-image shifts: every periodic coordinate in [0, L) and at
+    // least 7 cells per periodic axis, so a wrapped row is exactly one box
+    // length away and the shifted difference equals the minimum image
+    bool shifted = g.canonical != 0;
+    for (int a = 0; a < 3; a++) shifted = shifted && (!g.periodic[a] || g.nc[a] >= 7);
+    // (dy + 2) + 5 (dz + 2) of the 25 rows by increasing dy^2 + dz^2, 5 bits each
+    const uint64_t rows_lo = 0x013952440D13B56Cull;  // rows 0..11
+    const uint64_t rows_hi = 0x0250171D4334BCB6ull;  // rows 12..23
+    const int row_last = 24;                          // row 24: (dy, dz) = (2, 2)
+    const int nx = g.nc[0];
+    int r = 0, q = 0, qend = 0, seg2_lo = 0, seg2_hi = -1;
+    double shx = 0, shy = 0, shz = 0, shx2 = 0;
+    int cyz = 0;
+    // Each iteration first moves to the next segment if the current one is
+    // exhausted, then takes at most one candidate; the insertion runs on
+    // every iteration (an empty step inserts +inf), and the loop exits only
+    // after it, so the list stays in the same registers across the loop.
+    bool more = true;
+    do {
+        if (q >= qend) {
+            if (seg2_lo <= seg2_hi) {  // second (wrapped) part of the row
+                q = start[cyz + seg2_lo];
+                qend = start[cyz + seg2_hi + 1];
+                shx = shx2;
+                seg2_hi = -1;
+            } else if (r < 25) {
+                int code = r < 12 ? (int)((rows_lo >> (5 * r)) & 31)
+                                  : (r < 24 ? (int)((rows_hi >> (5 * (r - 12))) & 31) : row_last);
+                r++;
+                int dz = code / 5 - 2, dy = code - 5 * (code / 5) - 2;
+                int cy = cc[1] + dy, cz = cc[2] + dz;
                 bool skip = false;
-                for (int a = 0; a < 3; a++) {
-                    c3[a] = cc[a] + off3[a];
-                    // distance from the atom to the cell's slab along this axis
-                    double lo = (cc[a] + off3[a]) * g.h[a] - u[a], hi = lo + g.h[a];
-                    double gap = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
-                    gap = gap > g.margin ? gap - g.margin : 0.0;
-                    gap2 += gap * gap;
-                    if (g.periodic[a]) {
-                        // a cell below 0 wraps to the top of the box: its atoms lie
-                        // about one box length above, so d - L is the minimum image
-                        if (c3[a] < 0) { c3[a] += g.nc[a]; sh[a] = g.L[a]; }
-                        else if (c3[a] >= g.nc[a]) { c3[a] -= g.nc[a]; sh[a] = -g.L[a]; }
-                    } else if (c3[a] < 0 || c3[a] >= g.nc[a]) {
+                shy = shz = 0;
+                if (g.periodic[1]) {
+                    if (cy < 0) { cy += g.nc[1]; shy = g.L[1]; }
+                    else if (cy >= g.nc[1]) { cy -= g.nc[1]; shy = -g.L[1]; }
+                } else {
+                    skip = cy < 0 || cy >= g.nc[1];
+                }
+                if (g.periodic[2]) {
+                    if (cz < 0) { cz += g.nc[2]; shz = g.L[2]; }
+                    else if (cz >= g.nc[2]) { cz -= g.nc[2]; shz = -g.L[2]; }
+                } else {
+                    skip = skip || cz < 0 || cz >= g.nc[2];
+                }
+                int xlo = -2, xhi = 2;
+                if (!skip && key[KMAX - 1] != INF) {
+                    double ly = (cc[1] + dy) * g.h[1] - u[1], hy = ly + g.h[1];
+                    double lz = (cc[2] + dz) * g.h[2] - u[2], hz = lz + g.h[2];
+                    double gy = ly > 0 ? ly : (hy < 0 ? -hy : 0.0);
+                    double gz = lz > 0 ? lz : (hz < 0 ? -hz : 0.0);
+                    gy = gy > g.margin ? gy - g.margin : 0.0;
+                    gz = gz > g.margin ? gz - g.margin : 0.0;
+                    double rem = key_d2_upper(key[KMAX - 1]) - (gy * gy + gz * gz);
+                    if (rem < 0) {
                         skip = true;
+                    } else {
+                        // cells whose x-gap exceeds sqrt(rem) cannot hold a better neighbour
+                        double reach = sqrt(rem) + g.margin;
+                        double x0 = u[0] - cc[0] * g.h[0];  // offset of the atom inside its cell
+                        while (xlo < 0 && (-xlo - 1) * g.h[0] + x0 > reach) xlo++;
+                        while (xhi > 0 && (xhi - 1) * g.h[0] + (g.h[0] - x0) > reach) xhi--;
                     }
                 }
-                if (skip || (found >= KN && gap2 > kd[KN - 1])) continue;
-                int c = (c3[2] * g.nc[1] + c3[1]) * g.nc[0] + c3[0];
-                if (shifted)
-                    scan_cell_shift<KN>(c, xi, yi, zi, sh[0], sh[1], sh[2], i, sx, sy, sz, sid, start, kd, kj, found);
-                else
-                    scan_cell<KN>(c, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj, found);
-            }
-            if (s >= 1) {
-                int lo[3] = {-s, -s, -s}, hi[3] = {s, s, s};
-                bool all;
-                done = certified(g, cc, u, lo, hi, found, KN, kd[KN - 1], all);
-                for (int a = 0; a < 3; a++) { plo[a] = lo[a]; phi[a] = hi[a]; }
-                s_next = s + 1;
+                cyz = (cz * g.nc[1] + cy) * nx;
+                int a0 = cc[0] + xlo, a1 = cc[0] + xhi;
+                seg2_hi = -1;
+                if (g.periodic[0]) {
+                    if (a0 < 0) {  // wrapped part [a0 + nx, nx - 1] lies one box length up
+                        seg2_lo = a0 + nx;
+                        seg2_hi = nx - 1;
+                        shx2 = g.L[0];
+                        a0 = 0;
+                    } else if (a1 >= nx) {
+                        seg2_lo = 0;
+                        seg2_hi = a1 - nx;
+                        shx2 = -g.L[0];
+                        a1 = nx - 1;
+                    }
+                } else {
+                    a0 = max(a0, 0);
+                    a1 = min(a1, nx - 1);
+                    skip = skip || a0 > a1;
+                }
+                if (skip) {
+                    q = qend = 0;
+                    seg2_hi = -1;
+                } else {
+                    q = start[cyz + a0];
+                    qend = start[cyz + a1 + 1];
+                }
+                shx = 0;
+            } else {
+                more = false;
             }
         }
+        double t = INF;
+        if (q < qend) {
+            double dx, dy, dz;
+            if (shifted) {
+                dx = (sx[q] - xi) - shx;
+                dy = (sy[q] - yi) - shy;
+                dz = (sz[q] - zi) - shz;
+            } else {
+                dx = min_image(sx[q] - xi, g, 0);
+                dy = min_image(sy[q] - yi, g, 1);
+                dz = min_image(sz[q] - zi, g, 2);
+            }
+            double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            double d2 = (xx + yy) + zz;
+            if (q != (int)p) t = pack_key(d2, q);
+            q++;
+        }
+#pragma unroll
+        for (int m = 0; m < KN; m++) minmax_step(key[m], t);
+    } while (more);
+    bool ok = key[KMAX - 1] != INF;
+#pragma unroll
+    for (int m = 0; m < KN - 1; m++) ok = ok && key_hi(key[m]) < key_hi(key[m + 1]);
+    int32_t kq[KMAX];
+#pragma unroll
+    for (int m = 0; m < KMAX; m++) kq[m] = key_q(key[m]);
+    if (ok) {
+        int32_t q13 = kq[KMAX - 1];
+        double ex = min_image(sx[q13] - xi, g, 0);
+        double ey = min_image(sy[q13] - yi, g, 1);
+        double ez = min_image(sz[q13] - zi, g, 2);
+        double kth = (ex * ex + ey * ey) + ez * ez;
+        int lo[3] = {-2, -2, -2}, hi[3] = {2, 2, 2};
+        bool all;
+        ok = certified(g, cc, u, lo, hi, KMAX, KMAX, kth, all);
     }
-    // general path: shells of cells with per-axis clamping to the grid
-    for (int s = s_next; !done; s++) {
-        int lo[3], hi[3];
-        for (int a = 0; a < 3; a++) shell_range(g, a, s, lo[a], hi[a]);
-        for (int oz = lo[2]; oz <= hi[2]; oz++) {
-            int cz = cc[2] + oz;
-            if (g.periodic[2]) cz = (cz % g.nc[2] + g.nc[2]) % g.nc[2];
-            else if (cz < 0 || cz >= g.nc[2]) continue;
-            for (int oy = lo[1]; oy <= hi[1]; oy++) {
-                int cy = cc[1] + oy;
+    if (!ok) {
+        todo[atomicAdd(todo_count, 1)] = (int32_t)p;
+        return;
+    }
+    write_knn<KMAX>(n, p, sid[p], KMAX, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel, knn_out);
+}
+
+// Exact search for the atoms the fast search left (or all atoms when todo
+// is NULL), one wavefront per atom.  The lanes share the cells of the block
+// of shells 0..2 (then of each further shell) and keep private lists
+// ordered by the exact key (d^2, id); a 14-round wave-wide merge of the list
+// heads gives the atom's ordered neighbours, and the shells grow until the
+// searched block certifies the 14th distance.  A wave per atom keeps the
+// latency of a few left-over atoms short: each lane scans one or two cells.
+__global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const double *__restrict__ sx,
+                                                   const double *__restrict__ sy, const double *__restrict__ sz,
+                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                                                   int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                                                   int32_t *__restrict__ knn_out, const int32_t *__restrict__ todo,
+                                                   const int32_t *__restrict__ todo_count) {
+    constexpr int KN = KMAX;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t cnt_todo = todo ? (int64_t)*todo_count : n;
+    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); w < cnt_todo; w += nwaves) {
+        const int64_t p = todo ? (int64_t)todo[w] : w;
+        const double xi = sx[p], yi = sy[p], zi = sz[p];
+        const int32_t i = sid[p];
+        const double xs[3] = {xi, yi, zi};
+        int cc[3];
+        double u[3];
+        for (int a = 0; a < 3; a++) {
+            cc[a] = cell_coord(xs[a], g, a);
+            u[a] = wrapped(xs[a], g, a);
+        }
+        double kd[KN];
+        int32_t kj[KN], kq[KN];
+#pragma unroll
+        for (int m = 0; m < KN; m++) { kd[m] = INFINITY; kj[m] = 0x7fffffff; kq[m] = 0; }
+        int found = 0;
+        // merged result: lane m < KN holds entry m
+        double rd = INFINITY;
+        int32_t rj = -1, rq = 0;
+        int total = 0;
+        int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};  // block already searched (empty)
+        for (int s = 2;; s++) {
+            int lo[3], hi[3], ext[3];
+            for (int a = 0; a < 3; a++) {
+                shell_range(g, a, s, lo[a], hi[a]);
+                ext[a] = hi[a] - lo[a] + 1;
+            }
+            const int ncell = ext[0] * ext[1] * ext[2];
+            for (int c = lane; c < ncell; c += 64) {
+                int ox = lo[0] + c % ext[0];
+                int oy = lo[1] + (c / ext[0]) % ext[1];
+                int oz = lo[2] + c / (ext[0] * ext[1]);
+                bool inner = ox >= plo[0] && ox <= phi[0] && oy >= plo[1] && oy <= phi[1] && oz >= plo[2] &&
+                             oz <= phi[2];
+                if (inner) continue;
+                int cx = cc[0] + ox, cy = cc[1] + oy, cz = cc[2] + oz;
+                if (g.periodic[0]) cx = (cx % g.nc[0] + g.nc[0]) % g.nc[0];
+                else if (cx < 0 || cx >= g.nc[0]) continue;
                 if (g.periodic[1]) cy = (cy % g.nc[1] + g.nc[1]) % g.nc[1];
                 else if (cy < 0 || cy >= g.nc[1]) continue;
-                for (int ox = lo[0]; ox <= hi[0]; ox++) {
-                    bool inner = ox >= plo[0] && ox <= phi[0] && oy >= plo[1] && oy <= phi[1] &&
-                                 oz >= plo[2] && oz <= phi[2];
-                    if (inner) continue;
-                    int cx = cc[0] + ox;
-                    if (g.periodic[0]) cx = (cx % g.nc[0] + g.nc[0]) % g.nc[0];
-                    else if (cx < 0 || cx >= g.nc[0]) continue;
-                    int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
-                    scan_cell<KN>(c, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj, found);
+                if (g.periodic[2]) cz = (cz % g.nc[2] + g.nc[2]) % g.nc[2];
+                else if (cz < 0 || cz >= g.nc[2]) continue;
+                scan_cell<KN>((cz * g.nc[1] + cy) * g.nc[0] + cx, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj,
+                              kq, found);
+            }
+            // wave-wide merge of the list heads, smallest (d^2, id) first
+            total = found;
+            for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off);
+#pragma unroll 1
+            for (int m = 0; m < KN; m++) {
+                double bd = kd[0];
+                int32_t bj = kj[0];
+                for (int off = 32; off > 0; off >>= 1) {
+                    double od = __shfl_xor(bd, off);
+                    int32_t oj = __shfl_xor(bj, off);
+                    if (od < bd || (od == bd && oj < bj)) { bd = od; bj = oj; }
+                }
+                if (bd == INFINITY) break;  // every list is empty
+                bool mine = kd[0] == bd && kj[0] == bj;
+                uint64_t who = __ballot(mine);
+                int src = __ffsll((unsigned long long)who) - 1;
+                int32_t bq = __shfl(kq[0], src);
+                if (lane == m) { rd = bd; rj = bj; rq = bq; }
+                if (mine) {  // pop the head
+#pragma unroll
+                    for (int t = 0; t < KN - 1; t++) { kd[t] = kd[t + 1]; kj[t] = kj[t + 1]; kq[t] = kq[t + 1]; }
+                    kd[KN - 1] = INFINITY;
+                    kj[KN - 1] = 0x7fffffff;
                 }
             }
-        }
-        bool all;
-        done = certified(g, cc, u, lo, hi, found, KN, kd[KN - 1], all);
-        for (int a = 0; a < 3; a++) { plo[a] = lo[a]; phi[a] = hi[a]; }
-    }
-    int cnt = found < KN ? found : KN;
+            double kth = __shfl(rd, KN - 1);
+            bool all;
+            bool done = certified(g, cc, u, lo, hi, total, KN, kth, all);
+            for (int a = 0; a < 3; a++) { plo[a] = lo[a]; phi[a] = hi[a]; }
+            if (done) break;
+            // the merged entries seed lane 0's list for the next shell
 #pragma unroll
-    for (int m = 0; m < KN; m++) {
-        int32_t j = (m < cnt) ? kj[m] : -1;
-        nbr_id[(int64_t)m * n + p] = j;
-        double r0 = 0, r1 = 0, r2 = 0;
-        if (j >= 0) {
-            r0 = min_image(pos[3 * (int64_t)j + 0] - xi, g, 0);
-            r1 = min_image(pos[3 * (int64_t)j + 1] - yi, g, 1);
-            r2 = min_image(pos[3 * (int64_t)j + 2] - zi, g, 2);
+            for (int m = 0; m < KN; m++) {
+                double d = __shfl(rd, m);
+                int32_t j = __shfl(rj, m), q = __shfl(rq, m);
+                kd[m] = lane == 0 && j >= 0 ? d : INFINITY;
+                kj[m] = lane == 0 && j >= 0 ? j : 0x7fffffff;
+                kq[m] = q;
+            }
+            found = lane == 0 ? total : 0;
         }
-        nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
-        nbr_rel[((int64_t)m * 3 + 1) * n + p] = r1;
-        nbr_rel[((int64_t)m * 3 + 2) * n + p] = r2;
-        if (knn_out) knn_out[(int64_t)i * KN + m] = j;
+        const int cnt = total < KN ? total : KN;
+        if (lane < KN) {
+            int32_t j = lane < cnt ? rj : -1;
+            double r0 = 0, r1 = 0, r2 = 0;
+            if (lane < cnt) {
+                r0 = min_image(sx[rq] - xi, g, 0);
+                r1 = min_image(sy[rq] - yi, g, 1);
+                r2 = min_image(sz[rq] - zi, g, 2);
+            }
+            nbr_id[(int64_t)lane * n + p] = j;
+            nbr_rel[((int64_t)lane * 3 + 0) * n + p] = r0;
+            nbr_rel[((int64_t)lane * 3 + 1) * n + p] = r1;
+            nbr_rel[((int64_t)lane * 3 + 2) * n + p] = r2;
+            if (knn_out) knn_out[(int64_t)i * KN + lane] = j;
+        }
     }
 }
 
@@ -1128,11 +1340,27 @@ void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, co
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, cell_of, slot_of,
                        start, sx, sy, sz, sid);
 }
-void launch_knn(int64_t n, const Grid &g, const int32_t *stencil, const double *pos, const double *sx,
-                const double *sy, const double *sz, const int32_t *sid, const int32_t *start, int32_t *nbr_id,
-                double *nbr_rel, int32_t *knn_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_knn, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, g, stencil, pos, sx, sy, sz,
-                       sid, start, nbr_id, nbr_rel, knn_out);
+bool knn_fast_applies(const Grid &g) {
+    for (int a = 0; a < 3; a++)
+        if (g.periodic[a] && g.nc[a] < 5) return false;
+    return true;
+}
+void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz, const int32_t *sid,
+                const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out, int32_t *todo,
+                int32_t *todo_count, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (knn_fast_applies(g)) {
+        hipLaunchKernelGGL(k_knn_fast, dim3((unsigned)blocks), dim3(256), 0, st, n, g, sx, sy, sz, sid, start, nbr_id,
+                           nbr_rel, knn_out, todo, todo_count);
+        // the atoms left over are few; 1024 blocks of four waves stride over them
+        hipLaunchKernelGGL(k_knn_exact, dim3((unsigned)std::min<int64_t>(blocks, 1024)), dim3(256), 0, st, n, g, sx,
+                           sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)todo,
+                           (const int32_t *)todo_count);
+    } else {
+        hipLaunchKernelGGL(k_knn_exact, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 16384)), dim3(256), 0, st, n, g, sx,
+                           sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)nullptr,
+                           (const int32_t *)nullptr);
+    }
 }
 void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
                  int32_t *code, uint64_t *ord, hipStream_t st) {

@@ -46,9 +46,12 @@ void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell
                       int32_t *count, hipStream_t st);
 void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
                         const int32_t *start, double *sx, double *sy, double *sz, int32_t *sid, hipStream_t st);
-void launch_knn(int64_t n, const Grid &g, const int32_t *stencil, const double *pos, const double *sx, const double *sy, const double *sz,
-                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
-                hipStream_t st);
+// k-NN: fast block search, then the exact shell search for the atoms it
+// leaves in todo (n entries) / *todo_count (zeroed by the caller).
+bool knn_fast_applies(const Grid &g);
+void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz, const int32_t *sid,
+                const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out, int32_t *todo,
+                int32_t *todo_count, hipStream_t st);
 void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
                  uint64_t *ord, hipStream_t st);
 void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,

@@ -34,8 +34,6 @@ ptm_status upload_tables(ptm_ctx *ctx) {
     ptm_status st;
     if ((st = up(ctx->host.tpl, sizeof(TemplateDev) * NT, &p)) != PTM_OK) return st;
     ctx->view.tpl = (const TemplateDev *)p;
-    if ((st = up(ctx->host.stencil.data(), ctx->host.stencil.size() * 4, &p)) != PTM_OK) return st;
-    ctx->view.stencil = (const int32_t *)p;
     for (int g = 0; g < NGRP; g++) {
         HostTables &H = ctx->host;
         if ((st = up(H.codes[g].data(), H.codes[g].size() * 8, &p)) != PTM_OK) return st;

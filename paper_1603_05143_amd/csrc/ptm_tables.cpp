@@ -281,22 +281,7 @@ std::vector<std::pair<int, int>> min_signature_darts(int k, const uint64_t *nxt,
     return out;
 }
 
-static std::vector<int32_t> make_stencil() {
-    std::vector<std::array<int, 5>> v;
-    for (int dz = -STENCIL_SHELLS; dz <= STENCIL_SHELLS; dz++)
-        for (int dy = -STENCIL_SHELLS; dy <= STENCIL_SHELLS; dy++)
-            for (int dx = -STENCIL_SHELLS; dx <= STENCIL_SHELLS; dx++) {
-                int sh = std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz)));
-                v.push_back({sh, dx * dx + dy * dy + dz * dz, dx, dy, dz});
-            }
-    std::sort(v.begin(), v.end());
-    std::vector<int32_t> out;
-    for (auto &e : v) out.push_back((e[2] + 8) | ((e[3] + 8) << 8) | ((e[4] + 8) << 16));
-    return out;
-}
-
 bool build_tables(HostTables &T, std::string &err) {
-    T.stencil = make_stencil();
     // per hull group: code (as vector) -> list of (template, perm)
     std::map<std::vector<uint64_t>, std::vector<std::pair<int, uint64_t>>> bucket[NGRP];
     for (int t = 0; t < NT; t++) {

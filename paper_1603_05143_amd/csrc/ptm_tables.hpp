@@ -49,15 +49,7 @@ struct TablesView {
     const Candidate *cand[NGRP];          // candidates
     int32_t hmask[NGRP];
     int32_t ncodes[NGRP];
-    const int32_t *stencil;  // k-NN cell offsets, shells 0..3 of the 7x7x7 block, nearest first
 };
-
-// k-NN stencil: cell offsets (dx+8) | (dy+8) << 8 | (dz+8) << 16 sorted by
-// Chebyshev shell, then by squared length; shell s occupies
-// [STENCIL_START[s], STENCIL_START[s+1]).
-constexpr int STENCIL_SHELLS = 3;
-constexpr int STENCIL_N = 343;
-__host__ __device__ constexpr int stencil_start(int s) { return s == 0 ? 0 : (2 * s - 1) * (2 * s - 1) * (2 * s - 1); }
 
 // Host-side tables.
 struct HostTables {
@@ -73,7 +65,6 @@ struct HostTables {
     int64_t ncand_kept[NT];  // after
     int64_t ncodes_t[NT];    // distinct table keys (start-edge codes) per template
     int max_cand_per_code[NGRP];
-    std::vector<int32_t> stencil;
 };
 
 // Hash of a code (k row words); used identically by host and device.
