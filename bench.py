@@ -9,7 +9,10 @@ grains of FCC/BCC/HCP, sigma = 0.10 A), all five templates enabled.
 
 Prints one JSON line.  ``roofline`` covers the dominant kernel, timed with
 HIP events on the stream its kernels run on; ``cpu_baseline`` times the FP64
-reference implementation on a bounded sample of the same frame.
+reference implementation on a bounded sample of the same frame; ``serving``
+reports the serving loop (ptm_submit / ptm_wait) on a stream of frames of
+uneven size: throughput when saturated and p50/p99 frame latency under
+Poisson arrivals at 0.7 x the FP64 plain capacity.
 """
 from __future__ import annotations
 
@@ -98,6 +101,118 @@ def run_gpu(frame, precision, steps, warmup):
             "stage_ms": {s: acc[i] / steps for i, s in enumerate(STAGES)}, "types": types}
 
 
+def _mono_us():
+    return time.clock_gettime(time.CLOCK_MONOTONIC) * 1e6  # the clock of ptm_frame_stats
+
+
+def serving_bench(n_frames, pool_levels, ring, budget_gb, seed_shift=0):
+    """Serving loop on a stream of frames with log-uniform sizes in [1e3, 2e6].
+
+    Frames are drawn from a pool of ``pool_levels`` generated frames with
+    log-spaced sizes (each stream frame takes the pool frame nearest to its
+    size in log scale), so that generating the stream stays cheap; the pool
+    is resident on the device.  ``ring`` output sets bound the frames in
+    flight on the client side; admission on the library side is by the HBM
+    budget.  Latency = device completion time - scheduled arrival time.
+    """
+    import collections
+
+    import numpy as np
+    import torch
+    from paper_1603_05143_amd import ptm, synthetic as S
+
+    sizes, _ = S.serving_stream(n_frames)
+    levels = np.exp(np.linspace(math.log(1e3), math.log(2e6), pool_levels))
+    t = time.time()
+    pool = [S.serving_frame(int(round(n)), seed=S.BASE_SEED + 300 + k) for k, n in enumerate(levels)]
+    print(f"[serve] pool of {len(pool)} frames ({sum(f.n for f in pool)} atoms) in {time.time() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    pick = np.argmin(np.abs(np.log(sizes)[:, None] - np.log([f.n for f in pool])[None, :]), axis=1)
+    dev = [(torch.from_numpy(f.positions).to("cuda:0"), torch.from_numpy(f.species).to("cuda:0"), f)
+           for f in pool]
+    nmax = max(f.n for f in pool)
+    outs = [ptm.Classifier.alloc_outputs(nmax, "cuda:0") for _ in range(ring)]
+    structs = [ptm.Classifier.outputs_struct(o) for o in outs]
+    rng = np.random.default_rng(S.BASE_SEED + 3 + seed_shift)
+    gaps = rng.exponential(1.0, n_frames)  # unit-rate Poisson process, scaled below
+    atoms = np.array([pool[i].n for i in pick], dtype=np.float64)
+
+    def run(ctx, rate_hz):
+        free = collections.deque(range(ring))
+        pending = collections.deque()
+        done = np.zeros(n_frames)
+
+        def reap(block):
+            while pending:
+                tk, k, slot = pending[0]
+                st, s = ptm.ptm_wait(ctx, tk, -1 if block else 0)
+                if st == ptm.PTM_E_TIMEOUT:
+                    return
+                if st != ptm.PTM_OK:
+                    raise RuntimeError(ptm.ptm_last_error(ctx))
+                pending.popleft()
+                free.append(slot)
+                done[k] = s.complete_time_us
+                if block:
+                    return
+
+        arrive = None if rate_hz is None else np.cumsum(gaps) / rate_hz * 1e6
+        t0 = _mono_us()
+        for k in range(n_frames):
+            if arrive is not None:
+                while _mono_us() < t0 + arrive[k]:
+                    reap(False)
+            while not free:
+                reap(True)
+            slot = free.popleft()
+            pos, spc, f = dev[pick[k]]
+            while True:
+                st, tk = ptm.ptm_submit(ctx, pos.data_ptr(), spc.data_ptr(), f.box, f.n, ptm.PTM_ALL, math.inf,
+                                        structs[slot])
+                if st != ptm.PTM_E_BUSY:
+                    break
+                reap(True)
+            if st != ptm.PTM_OK:
+                raise RuntimeError(ptm.ptm_last_error(ctx))
+            pending.append((tk, k, slot))
+        while pending:
+            reap(True)
+        return t0, arrive, done
+
+    res = {}
+    rate = None
+    for name, prec in (("fp64", ptm.PTM_FP64), ("fp32_mixed", ptm.PTM_FP32_MIXED)):
+        ctx = ptm.ptm_create(0, prec, None, int(budget_gb * 1e9), 0)
+        # warm the scratch pool: every pool frame twice, in flight together
+        keep = []
+        for rep in range(2):
+            for j, (pos, spc, f) in enumerate(dev):
+                st, tk = ptm.ptm_submit(ctx, pos.data_ptr(), spc.data_ptr(), f.box, f.n, ptm.PTM_ALL, math.inf,
+                                        structs[(rep * len(dev) + j) % ring])
+                keep.append(tk)
+        for tk in keep:
+            ptm.ptm_wait(ctx, tk, -1)
+        t0, _, done = run(ctx, None)
+        span_s = (done.max() - t0) / 1e6
+        r = {"atoms_per_s": atoms.sum() / span_s, "frames_per_s": n_frames / span_s}
+        if rate is None:
+            rate = 0.7 * r["frames_per_s"]  # same arrival rate for both forms
+        t0, arrive, done = run(ctx, rate)
+        lat_ms = (done - (t0 + arrive)) / 1e3
+        lat = lat_ms[50:] if n_frames > 100 else lat_ms
+        r.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                  "mean_ms": float(lat.mean())})
+        ptm.ptm_destroy(ctx)
+        print(f"[serve] {name}: {r}", file=sys.stderr, flush=True)
+        res[name] = r
+    del outs, dev
+    return {"frames": n_frames, "sizes": "log-uniform in [1e3, 2e6] atoms",
+            "pool_frames": len(pool), "pool_atoms": int(sum(f.n for f in pool)),
+            "rate_hz": rate, "budget_gb": budget_gb, "client_ring": ring,
+            "latency_over": f"frames 51-{n_frames}" if n_frames > 100 else "all frames",
+            "fp64": res["fp64"], "fp32_mixed": res["fp32_mixed"]}
+
+
 def cpu_baseline(frame, sample):
     import numpy as np
     import oracle
@@ -118,8 +233,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--cpu-sample", type=int, default=30000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-frames", type=int, default=2000)
+    ap.add_argument("--serve-pool", type=int, default=12)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -154,6 +272,10 @@ def main():
     roof["kernel"] = dom
     roof["kernel_ms"] = stage_ms[dom]
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_bench(args.serve_frames, args.serve_pool, ring=24, budget_gb=200.0)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(frame, args.cpu_sample)
@@ -175,6 +297,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "types": dict(zip(ptm.TYPE_NAMES, main_run["types"])),
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -103,8 +103,9 @@ typedef struct {
 typedef struct {
     double submit_time_us;   /* host clock at ptm_submit */
     double start_time_us;    /* host clock when the frame's work was enqueued on the device */
-    double complete_time_us; /* host clock when completion was observed */
+    double complete_time_us; /* host-clock time of the frame's completion on the device */
     int64_t n_atoms;
+    uint64_t scratch_bytes;  /* pooled device scratch the frame held (counted against the budget) */
 } ptm_frame_stats;
 
 /* Create a context on cfg->device: builds the template tables (all

@@ -125,8 +125,12 @@ struct ptm_ctx {
     std::map<uint64_t, ptm::Ticket *> tickets;
     std::vector<ptm::FrameScratch> free_scratch;
     uint64_t next_ticket = 1;
-    size_t inflight_bytes = 0;
+    size_t inflight_bytes = 0;  // scratch held by in-flight frames
+    size_t pool_bytes = 0;      // scratch allocated by the pool (in flight + free)
     int next_stream = 0;
+    double *bounds_part = nullptr;      // per-block bounds of the frame being admitted
+    hipEvent_t ref_event = nullptr;     // device-timeline reference ...
+    double ref_time_us = 0;             // ... and its host-clock time
     // stage profiling (PTM_F_PROFILE)
     hipEvent_t prof_ev[PTM_NSTAGES + 1] = {};
     bool prof_valid = false;

@@ -4,15 +4,19 @@
 // Serving is continuous batching over a pool of HIP streams (default
 // priority): each admitted frame gets its own scratch and runs its whole
 // pipeline on the next stream of the pool, so frames that arrive while
-// others are on the device overlap with them.  Admission is by bytes: a
-// frame is admitted when the scratch of all in-flight frames plus its own
-// stays within the context's HBM budget; otherwise ptm_submit returns
-// PTM_E_BUSY and the caller retries after a ptm_wait.  Finished frames
-// return their scratch to a free list for reuse.
+// others are on the device overlap with them.  Scratch comes from a
+// grow-only pool of power-of-two size classes (no device free, hence no
+// implicit device synchronisation, while serving).  Admission is by bytes:
+// a frame is admitted when the pool memory it needs fits within the
+// context's HBM budget next to that of all in-flight frames; otherwise
+// ptm_submit returns PTM_E_BUSY and the caller retries after a ptm_wait.
+// Completion times are read from timing events on the device timeline.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
+#include <string>
 
 #include "ptm_internal.hpp"
 
@@ -153,6 +157,62 @@ static ptm_status serve_init(ptm_ctx *ctx) {
         ctx->serve_streams.push_back(h);
     }
     PTM_HIP(ctx, hipStreamCreateWithFlags(&ctx->bounds_stream, hipStreamNonBlocking));
+    PTM_HIP(ctx, hipMalloc(&ctx->bounds_part, 8 * 7 * (size_t)bounds_blocks(PTM_MAX_ATOMS)));
+    // reference point of the device timeline on the host clock
+    PTM_HIP(ctx, hipEventCreate(&ctx->ref_event));
+    PTM_HIP(ctx, hipEventRecord(ctx->ref_event, ctx->bounds_stream));
+    PTM_HIP(ctx, hipEventSynchronize(ctx->ref_event));
+    ctx->ref_time_us = now_us();
+    return PTM_OK;
+}
+
+// Size class of a frame's scratch: the next power of two (at least 1 MiB)
+// of an upper bound of its bytes that holds for any cell grid make_grid
+// may choose (at most 4n + 4096 cells).
+static size_t scratch_class(int64_t n) {
+    int64_t cells = 4 * n + 4096;
+    size_t tmp = 0, tmp2 = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int32_t *)nullptr, (int32_t *)nullptr, (int)(cells + 1));
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2, (int64_t *)nullptr, (int64_t *)nullptr, (int)(n + 1));
+    size_t need = frame_bytes(n, cells, bounds_blocks(n), std::max(tmp, tmp2));
+    size_t c = (size_t)1 << 20;
+    while (c < need) c <<= 1;
+    return c;
+}
+
+// Take a pooled scratch of class c (allocating one if none is free and the
+// budget allows).  Returns PTM_E_BUSY / PTM_E_NOMEM when it does not fit.
+static ptm_status take_scratch(ptm_ctx *ctx, size_t c, FrameScratch &out) {
+    for (size_t i = 0; i < ctx->free_scratch.size(); i++)
+        if (ctx->free_scratch[i].bytes == c) {
+            out = ctx->free_scratch[i];
+            ctx->free_scratch.erase(ctx->free_scratch.begin() + i);
+            return PTM_OK;
+        }
+    if (ctx->budget) {
+        if (c > ctx->budget) {
+            ctx->err = "frame larger than the HBM budget";
+            return PTM_E_NOMEM;
+        }
+        // idle buffers of other classes give their memory back first
+        while (ctx->pool_bytes + c > ctx->budget && !ctx->free_scratch.empty()) {
+            ctx->pool_bytes -= ctx->free_scratch.back().bytes;
+            ctx->free_scratch.back().release();
+            ctx->free_scratch.pop_back();
+        }
+        if (ctx->pool_bytes + c > ctx->budget) {
+            ctx->err = "HBM budget full";
+            return PTM_E_BUSY;
+        }
+    }
+    if (hipMalloc(&out.base, c) != hipSuccess) {
+        (void)hipGetLastError();
+        out.base = nullptr;
+        ctx->err = "device allocation of " + std::to_string(c) + " bytes failed";
+        return PTM_E_NOMEM;
+    }
+    out.bytes = c;
+    ctx->pool_bytes += c;
     return PTM_OK;
 }
 
@@ -160,7 +220,7 @@ static void retire(ptm_ctx *ctx, Ticket *T) {
     ctx->inflight_bytes -= T->footprint;
     if (T->done) (void)hipEventDestroy(T->done);
     T->done = nullptr;
-    ctx->free_scratch.push_back(T->scratch);
+    if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);
     T->scratch = FrameScratch();
     T->staging.release();
 }
@@ -174,6 +234,11 @@ void serve_shutdown(ptm_ctx *ctx) {
     ctx->tickets.clear();
     for (auto &s : ctx->free_scratch) s.release();
     ctx->free_scratch.clear();
+    ctx->pool_bytes = 0;
+    if (ctx->bounds_part) (void)hipFree(ctx->bounds_part);
+    ctx->bounds_part = nullptr;
+    if (ctx->ref_event) (void)hipEventDestroy(ctx->ref_event);
+    ctx->ref_event = nullptr;
     for (auto s : ctx->serve_streams) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
@@ -206,20 +271,14 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
     T->job.mask = template_mask & PTM_ALL;
     T->job.cutoff = rmsd_cutoff;
     if (n_atoms > 0) {
-        // take the smallest free scratch that fits later; first the bounds
-        int best = -1;
-        for (size_t i = 0; i < ctx->free_scratch.size(); i++)
-            if (best < 0 || ctx->free_scratch[i].bytes > ctx->free_scratch[best].bytes) best = (int)i;
-        if (best >= 0) {
-            T->scratch = ctx->free_scratch[best];
-            ctx->free_scratch.erase(ctx->free_scratch.begin() + best);
-        }
         hipStream_t bst = ctx->bounds_stream;
+        // bounds first (synchronous on the bounds stream): the grid depends on them
         st = stage_in_buffers(ctx, T->staging, positions, species, out, n_atoms, T->job, T->stage, bst);
-        if (st == PTM_OK && !T->scratch.reserve(n_atoms, 1, ctx->err)) st = PTM_E_NOMEM;
         double mn[3], mx[3];
         bool bad = false;
-        if (st == PTM_OK) st = frame_bounds(ctx, T->scratch, T->job.pos, n_atoms, mn, mx, bad, bst);
+        FrameScratch bs;
+        bs.part = ctx->bounds_part;
+        if (st == PTM_OK) st = frame_bounds(ctx, bs, T->job.pos, n_atoms, mn, mx, bad, bst);
         if (st == PTM_OK && bad) {
             ctx->err = "non-finite coordinate";
             st = PTM_E_INVALID;
@@ -228,11 +287,8 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
         if (st == PTM_OK) {
             T->job.grid = make_grid(box, mn, mx, n_atoms);
             cells = (int64_t)T->job.grid.nc[0] * T->job.grid.nc[1] * T->job.grid.nc[2];
-            T->footprint = frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0);
-            if (ctx->budget && ctx->inflight_bytes + T->footprint > ctx->budget) {
-                ctx->err = "HBM budget full";
-                st = (T->footprint > ctx->budget) ? PTM_E_NOMEM : PTM_E_BUSY;
-            }
+            T->footprint = scratch_class(n_atoms);
+            st = take_scratch(ctx, T->footprint, T->scratch);
         }
         if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, ctx->err)) st = PTM_E_NOMEM;
         if (st != PTM_OK) {
@@ -248,7 +304,7 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
         T->t_start = now_us();
         st = enqueue_frame(ctx, T->scratch, T->job, s);
         if (st == PTM_OK) st = stage_out(ctx, out, n_atoms, T->job, T->stage, s);
-        if (st == PTM_OK && hipEventCreateWithFlags(&T->done, hipEventDisableTiming) != hipSuccess) st = PTM_E_DEVICE;
+        if (st == PTM_OK && hipEventCreate(&T->done) != hipSuccess) st = PTM_E_DEVICE;
         if (st == PTM_OK && hipEventRecord(T->done, s) != hipSuccess) st = PTM_E_DEVICE;
         if (st != PTM_OK) {
             (void)hipStreamSynchronize(s);
@@ -286,7 +342,12 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
             }
             if (timeout_us >= 0 && now_us() - t0 >= (double)timeout_us) return PTM_E_TIMEOUT;
         }
-        T->t_complete = now_us();
+        // completion on the device timeline, mapped to the host clock
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->ref_event, T->done) == hipSuccess)
+            T->t_complete = ctx->ref_time_us + 1e3 * (double)ms;
+        else
+            T->t_complete = now_us();
         T->complete = true;
     }
     if (stats) {
@@ -294,6 +355,7 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
         stats->start_time_us = T->t_start;
         stats->complete_time_us = T->t_complete;
         stats->n_atoms = T->job.n;
+        stats->scratch_bytes = T->footprint;
     }
     retire(ctx, T);
     delete T;

@@ -36,7 +36,7 @@ class ptm_outputs(C.Structure):
 
 class ptm_frame_stats(C.Structure):
     _fields_ = [("submit_time_us", C.c_double), ("start_time_us", C.c_double),
-                ("complete_time_us", C.c_double), ("n_atoms", C.c_int64)]
+                ("complete_time_us", C.c_double), ("n_atoms", C.c_int64), ("scratch_bytes", C.c_uint64)]
 
 
 class PTMError(RuntimeError):

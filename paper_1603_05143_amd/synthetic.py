@@ -189,18 +189,28 @@ def config0(seed: int | None = None) -> Frame:
     return Frame(positions=wrap(pos, f.box), box=f.box, labels={"config": 0})
 
 
+# phase -> (motif, lattice constant, c/a, species of the motif sites or None
+# for a pure element, fraction of B atoms drawn at random or None)
 _PHASES = {
-    "fcc": (FCC_MOTIF, 3.615, None),
-    "bcc": (BCC_MOTIF, 2.87, None),
-    "hcp": (None, 2.51, 1.633),
+    "fcc": (FCC_MOTIF, 3.615, None, None, None),
+    "bcc": (BCC_MOTIF, 2.87, None, None, None),
+    "hcp": (None, 2.51, 1.633, None, None),
+    # ordered alloys of the alloy-slab workload (species 1 = B)
+    "l12": (FCC_MOTIF, 3.57, None, np.array([1, 0, 0, 0], np.int8), None),
+    "l10": (FCC_MOTIF, 3.85, 0.97, np.array([0, 0, 1, 1], np.int8), None),
+    "b2": (BCC_MOTIF, 2.88, None, np.array([0, 1], np.int8), None),
+    "a1": (FCC_MOTIF, 3.57, None, None, 0.25),
 }
 
 
 def _phase_cell(phase: str):
-    motif, a, coa = _PHASES[phase]
+    motif, a, coa, _, _ = _PHASES[phase]
     if phase == "hcp":
         return hcp_cell(a, coa)
-    return motif, np.eye(3) * a
+    cell = np.eye(3) * a
+    if coa is not None:
+        cell[2, 2] = a * coa
+    return motif, cell
 
 
 def _min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:
@@ -221,6 +231,8 @@ def polycrystal(L: float = 220.0, n_grains: int = 16, sigma: float = 0.10,
     belongs to the grain whose centre is nearest under the minimum image.
     Of each cross-grain pair closer than ``min_dist`` the atom with the
     higher (grain, index) is deleted.  Gaussian noise ``sigma`` is added last.
+    If any phase is an alloy (``l12``, ``l10``, ``b2``, ``a1``) the frame
+    carries species (0 on the sites of pure phases).
     """
     from scipy.spatial import cKDTree
 
@@ -240,7 +252,8 @@ def polycrystal(L: float = 220.0, n_grains: int = 16, sigma: float = 0.10,
     np.maximum.at(cover, owner, dist)
     cover += math.sqrt(3) * L / g + 4.0
 
-    all_pos, all_grain = [], []
+    with_species = any(_PHASES[ph][3] is not None or _PHASES[ph][4] is not None for ph in phases)
+    all_pos, all_grain, all_spc = [], [], []
     for gi in range(n_grains):
         motif, cell = _phase_cell(phases[phase_idx[gi]])
         r = cover[gi]
@@ -249,22 +262,35 @@ def polycrystal(L: float = 220.0, n_grains: int = 16, sigma: float = 0.10,
         rng_cells = np.arange(-reach, reach + 1)
         ijk = np.stack(np.meshgrid(rng_cells, rng_cells, rng_cells, indexing="ij"), -1).reshape(-1, 3)
         sites = ((ijk[:, None, :] + motif[None]) .reshape(-1, 3)) @ cell
-        sites = sites[np.einsum("ij,ij->i", sites, sites) <= r * r]
-        p = sites @ rots[gi].T + centres[gi]
-        p = wrap(p, box)
+        inside = np.einsum("ij,ij->i", sites, sites) <= r * r
+        sites = sites[inside]
+        d = sites @ rots[gi].T
+        p = wrap(d + centres[gi], box)
         _, own = ctree.query(p)
-        keep = own == gi
+        # each point of space once: the site's offset from the centre must be
+        # its own minimum image (matters when a grain spans most of the box)
+        keep = (own == gi) & np.all(np.abs(d) < 0.5 * L, axis=1)
         all_pos.append(p[keep])
         all_grain.append(np.full(int(keep.sum()), gi, dtype=np.int32))
+        if with_species:
+            _, _, _, smotif, bfrac = _PHASES[phases[phase_idx[gi]]]
+            if smotif is not None:
+                spc = np.tile(smotif, len(ijk))[inside][keep]
+            elif bfrac is not None:
+                spc = (rng.random(int(keep.sum())) < bfrac).astype(np.int8)
+            else:
+                spc = np.zeros(int(keep.sum()), np.int8)
+            all_spc.append(spc)
     pos = np.concatenate(all_pos)
     grain = np.concatenate(all_grain)
+    species = np.concatenate(all_spc) if with_species else None
 
-    # delete the higher (grain, index) atom of each too-close cross-grain pair
+    # delete the higher (grain, index) atom of each too-close pair: pairs
+    # across grain boundaries, and across the periodic seam of a grain that
+    # meets its own image (lattice neighbours are never this close)
     tree = cKDTree(pos, boxsize=L)
     pairs = tree.query_pairs(min_dist, output_type="ndarray")
     if len(pairs):
-        cross = grain[pairs[:, 0]] != grain[pairs[:, 1]]
-        pairs = pairs[cross]
         a_, b_ = pairs[:, 0], pairs[:, 1]
         key_a = grain[a_].astype(np.int64) * (1 << 32) + a_
         key_b = grain[b_].astype(np.int64) * (1 << 32) + b_
@@ -272,9 +298,11 @@ def polycrystal(L: float = 220.0, n_grains: int = 16, sigma: float = 0.10,
         alive = np.ones(len(pos), bool)
         alive[victim] = False
         pos, grain = pos[alive], grain[alive]
+        if species is not None:
+            species = species[alive]
 
     pos = pos + rng.normal(0.0, sigma, size=pos.shape)
-    return Frame(positions=wrap(pos, box), box=box,
+    return Frame(positions=wrap(pos, box), box=box, species=species,
                  labels={"grain": grain, "phases": [phases[i] for i in phase_idx],
                          "rotations": rots, "centres": centres})
 
@@ -341,12 +369,17 @@ def alloy_slabs(n_cells: int = 102, a_l12: float = 3.57, a_l10: float = 3.85,
     return Frame(positions=wrap(pos, box), box=box, species=spc, labels={"slab": slab})
 
 
+SERVING_PHASES = ("fcc", "bcc", "hcp", "l12", "l10", "b2", "a1")
+
+
 def serving_frame(n: int, seed: int, sigma: float | None = None) -> Frame:
     """One frame of the serving stream: a small periodic polycrystal of ~n atoms.
 
-    Lattice types are drawn from the polycrystal phases; the grain count is
-    max(1, n / 60000) and the cubic box is sized for ~n atoms at the mean
-    density of the phases (at least 22 A).  ``sigma`` defaults to U[0.02, 0.3].
+    Grain lattices are drawn from the phases of the polycrystal and of the
+    alloy-slab workloads (FCC, BCC, HCP, L1_2, L1_0, B2, random FCC), so
+    frames carry species; the grain count is max(1, n / 60000) and the cubic
+    box is sized for ~n atoms at the mean density of the phases (at least
+    22 A).  ``sigma`` defaults to U[0.02, 0.3].
     """
     rng = rng_for(seed)
     if sigma is None:
@@ -354,7 +387,8 @@ def serving_frame(n: int, seed: int, sigma: float | None = None) -> Frame:
     rho = 0.0862
     L = max(22.0, (n / rho) ** (1.0 / 3.0))
     n_grains = max(1, int(n // 60000))
-    f = polycrystal(L=L, n_grains=n_grains, sigma=sigma, seed=int(rng.integers(1 << 31)))
+    f = polycrystal(L=L, n_grains=n_grains, sigma=sigma, seed=int(rng.integers(1 << 31)),
+                    phases=SERVING_PHASES)
     f.labels["sigma"] = sigma
     return f
 
