@@ -27,39 +27,84 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "atoms/s (PTM, all templates) FP32-mixed vs FP64 plain; p50/p99 frame latency"
-STAGES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "match")
+STAGES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "cand", "eval", "decide")
 
-# MI355X published peaks
+# MI355X published peaks: HBM3E bandwidth; vector FP64, which equals vector
+# FP32 without packed instructions (the library is built without them)
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_TFLOPS = 78.6
+PEAK_VALU_TFLOPS = 78.6
+
+# kernel(s) behind each single-kernel stage, for the roofline line
+STAGE_KERNEL = {"knn": "k_knn_fast + k_knn_exact", "topo6": "k_topo<6>", "topo12": "k_topo<12>",
+                "topo14": "k_topo<14>", "eval": "k_cand_eval", "decide": "k_decide"}
 
 
-def work_model(stage: str, n: int) -> tuple[str, float, str]:
+def orient_tests(K: int) -> int:
+    """Orientation tests of the incremental hull of K points: the first
+    tetrahedron, every facet of the current hull against each later point
+    (2m - 4 facets when m points are in), and the centre against the 2K - 4
+    final facets (counted separately)."""
+    return 1 + sum(2 * m - 4 for m in range(4, K))
+
+
+def work_model(stage: str, n: int, info: dict) -> tuple[str, float, str]:
     """Algorithmic work of one launch of a stage: (bound, amount, unit).
 
-    Per-atom figures are derived in the design doc section 7: HBM bytes for the
-    memory-bound stages, FP64 floating-point operations for the arithmetic
-    stages (orientation-filter and superposition arithmetic only; integer
-    work of the canonical code is not counted, so the fraction is a lower
-    bound on VALU use).
+    Counted from the method, not from the kernels' instruction mix: FP
+    operations for the arithmetic stages, HBM bytes for binning.
+      knn     18 in-sphere distances per atom (the minimum any search must
+              evaluate) x 11 FLOP (difference, minimum image, squared norm)
+      topoK   orient3d from differences = 23 FLOP per test, 14 FLOP per
+              centre-inside test (the centre is the origin)
+      eval    per superposed pair with N = 13 points: covariance 18N, G_b 6N,
+              residual 27N, key matrix + characteristic polynomial + Newton +
+              adjugate eigenvector + rotation ~290 FLOP
+      decide  winner re-evaluation (953) + quaternion (30) + strain (A^T =
+              V+ W' 234, A A^T 54, Jacobi 540, P 90) ~ 1.9 kFLOP per atom
+      bin     104 B per atom (positions read twice, cell/slot/sorted writes)
+              + 8 B per cell (histogram scan)
     """
     K = {"topo6": 6, "topo12": 12, "topo14": 14}.get(stage)
     if stage == "bin":
-        return "hbm", 92.0 * n, "bytes"
-    if stage == "bounds":
-        return "hbm", 24.0 * n, "bytes"
+        return "hbm", 104.0 * n + 8.0 * info.get("cells", 0), "bytes"
     if stage == "knn":
-        # 27-cell search at ~8 atoms per cell: ~216 candidate distances of 20 FLOP
-        return "fp64", 216 * 20.0 * n, "flop"
+        return "alu", 18 * 11.0 * n, "flop"
     if K is not None:
-        tests = 1 + (K - 1) * (K - 4)
-        return "fp64", (29.0 * tests + 20.0 * (2 * K - 4)) * n, "flop"
-    if stage == "match":
-        # ~4 candidates (paper's profile: 3.93 QCP solves per atom) of
-        # (9N covariance FMA + ~400 QCP + 21N residual) FLOP with N ~ 13
-        per_cand = 2 * 9 * 13 + 400 + 21 * 13
-        return "fp64", 4 * per_cand * n, "flop"
+        return "alu", (23.0 * orient_tests(K) + 14.0 * (2 * K - 4)) * n, "flop"
+    if stage == "eval":
+        N = 13
+        return "alu", (51.0 * N + 290.0) * info.get("pairs", 0), "flop"
+    if stage == "decide":
+        return "alu", 1900.0 * n, "flop"
     raise KeyError(stage)
+
+
+def kernel_source_digest() -> str:
+    """Digest of the kernel sources; HBM traffic measured on other sources is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ptm_kernels.hip", "ptm_device.hpp", "ptm_kernels.hpp", "ptm_tables.hpp"):
+        with open(os.path.join(ROOT, "paper_1603_05143_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage: str, precision: str):
+    """HBM bytes per launch of a stage's kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary under profiles/ (scaled by the copy-kernel
+    calibration recorded there), or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_polycrystal_919k.md")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_source_digest()
+    for line in open(path):
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cols) >= 6 and cols[0] == stage and cols[1] == precision and cols[5] == digest:
+            try:
+                return float(cols[2]) + float(cols[3])
+            except ValueError:
+                return None
+    return None
 
 
 def build_frame(args):
@@ -85,7 +130,7 @@ def run_gpu(frame, precision, steps, warmup):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    acc = [0.0] * 7
+    acc = [0.0] * len(STAGES)
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
@@ -94,11 +139,12 @@ def run_gpu(frame, precision, steps, warmup):
             acc[i] += st_ms[s]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    info = ptm.ptm_frame_info(ctx)
     types = torch.bincount(out["type"].long(), minlength=6).cpu().tolist()
     ptm.ptm_destroy(ctx)
     ms = (t1 - t0) * 1e3 / steps
     return {"ms_per_step": ms, "atoms_per_s": frame.n / (ms / 1e3),
-            "stage_ms": {s: acc[i] / steps for i, s in enumerate(STAGES)}, "types": types}
+            "stage_ms": {s: acc[i] / steps for i, s in enumerate(STAGES)}, "types": types, "info": info}
 
 
 def _mono_us():
@@ -238,14 +284,23 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=2000)
     ap.add_argument("--serve-pool", type=int, default=12)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy a 256 MiB device buffer (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
-    import torch  # noqa: F401  (loads the HIP runtime shared with libptm)
+    import torch  # (loads the HIP runtime shared with libptm)
     from paper_1603_05143_amd import ptm
 
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     frame, gen_s = build_frame(args)
     print(f"[bench] frame n={frame.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
     r64 = run_gpu(frame, ptm.PTM_FP64, args.steps, args.warmup)
@@ -258,19 +313,19 @@ def main():
     dtype = "f32-mixed"
 
     stage_ms = main_run["stage_ms"]
-    dom = max((s for s in STAGES if s != "bounds"), key=lambda s: stage_ms[s])
-    bound, work, unit = work_model(dom, frame.n)
+    dom = max(STAGE_KERNEL, key=lambda st: stage_ms[st])
+    bound, work, unit = work_model(dom, frame.n, main_run["info"])
     t = stage_ms[dom] / 1e3
     if bound == "hbm":
-        achieved = work / t / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        roof = {"bound": "hbm", "achieved": work / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     else:
-        achieved = work / t / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "achieved": work / t / 1e12, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom, "fp32_mixed")
+    roof["kernel"] = STAGE_KERNEL[dom] + " (FP32-mixed)"
     roof["kernel_ms"] = stage_ms[dom]
+    roof["work_per_launch"] = work
+    roof["work_unit"] = unit
 
     serving = None
     if not args.no_serve:
@@ -294,6 +349,7 @@ def main():
         "fp32_mixed_atoms_per_s": r32["atoms_per_s"],
         "fp32_mixed_over_fp64": r32["atoms_per_s"] / r64["atoms_per_s"],
         "fp64_stage_ms": {k: round(v, 4) for k, v in r64["stage_ms"].items()},
+        "work_counts": main_run["info"],
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "types": dict(zip(ptm.TYPE_NAMES, main_run["types"])),
         "roofline": roof,

@@ -74,7 +74,9 @@ enum { PTM_F_HOST_POINTERS = 1u << 0, /* inputs/outputs are host pointers (stage
 
 /* pipeline stages reported by ptm_stage_times */
 enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2, PTM_STAGE_TOPO6 = 3, PTM_STAGE_TOPO12 = 4,
-       PTM_STAGE_TOPO14 = 5, PTM_STAGE_MATCH = 6, PTM_NSTAGES = 7 };
+       PTM_STAGE_TOPO14 = 5, PTM_STAGE_CAND = 6 /* candidate pair list */,
+       PTM_STAGE_EVAL = 7 /* superposition of every pair */,
+       PTM_STAGE_DECIDE = 8 /* decision, orientation, strain, alloy, write-back */, PTM_NSTAGES = 9 };
 
 typedef struct {
     int device;                /* HIP device ordinal */
@@ -160,6 +162,15 @@ const char *ptm_last_error(const ptm_ctx *ctx);
  * min(n, PTM_NSTAGES) entries (0 for a stage that did not run).
  * PTM_E_INVALID if the context was not created with PTM_F_PROFILE. */
 ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n);
+
+/* Work counts of the most recent ptm_classify on a PTM_F_PROFILE context:
+ * info[PTM_INFO_*] for min(n, PTM_NINFO) entries.  Same errors as
+ * ptm_stage_times. */
+enum { PTM_INFO_CELLS = 0,      /* cells of the binning grid */
+       PTM_INFO_KNN_EXACT = 1,  /* atoms whose neighbours the exact (whole-wave) search found */
+       PTM_INFO_PAIRS = 2,      /* (atom, candidate correspondence) pairs superposed */
+       PTM_NINFO = 3 };
+ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n);
 
 /* Template facts of the library's own tables, for checks without a device:
  * info[0]=k, info[1]=rotation group order, info[2]=triangulations,

@@ -209,8 +209,13 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
         if ((ps = mark(PTM_STAGE_TOPO6 + grp + 1)) != PTM_OK) return ps;
     }
     MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
-    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match,
-                 ctx->precision == PTM_FP32_MIXED, st);
+    const bool f32 = ctx->precision == PTM_FP32_MIXED;
+    launch_cand(n, ctx->view, S.code, m, S.match, st);
+    if ((ps = mark(PTM_STAGE_EVAL)) != PTM_OK) return ps;
+    launch_eval(n, S.nbr_rel, ctx->view, S.ord, S.match, f32, st);
+    if ((ps = mark(PTM_STAGE_DECIDE)) != PTM_OK) return ps;
+    launch_decide(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match, f32,
+                  st);
     if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;
@@ -419,6 +424,15 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
     st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
     if (st != PTM_OK) return st;
     PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (prof) {
+        int32_t left = 0;
+        int64_t pairs = 0;
+        PTM_HIP(ctx, hipMemcpy(&left, ctx->main.count + cells + 1, 4, hipMemcpyDeviceToHost));
+        PTM_HIP(ctx, hipMemcpy(&pairs, ctx->main.match.off + n_atoms, 8, hipMemcpyDeviceToHost));
+        ctx->prof_info[PTM_INFO_CELLS] = cells;
+        ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left : n_atoms;
+        ctx->prof_info[PTM_INFO_PAIRS] = pairs;
+    }
     ctx->prof_valid = prof;
     return PTM_OK;
 }
@@ -436,6 +450,12 @@ ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n) {
         }
         ms[i] = t;
     }
+    return PTM_OK;
+}
+
+ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n) {
+    if (!ctx || !info || n < 0 || !(ctx->flags & PTM_F_PROFILE)) return PTM_E_INVALID;
+    for (int i = 0; i < n && i < PTM_NINFO; i++) info[i] = ctx->prof_valid ? ctx->prof_info[i] : 0;
     return PTM_OK;
 }
 

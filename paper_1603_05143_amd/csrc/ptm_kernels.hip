@@ -1375,27 +1375,34 @@ void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_
         else hipLaunchKernelGGL((k_topo<14, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
     }
 }
-void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
-                  const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
-                  const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st) {
+void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
+                 hipStream_t st) {
     unsigned nb = (unsigned)((n + 1 + 255) / 256);
     hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt);
     size_t tmp = W.scan_tmp_bytes;
     (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, (int)(n + 1), st);
     hipLaunchKernelGGL(k_cand_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, code, mask, W.off,
                        W.cap, W.pairs);
-    dim3 gd((unsigned)((n + MB - 1) / MB));
-    if (f32) {
+}
+void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
+                 bool f32, hipStream_t st) {
+    if (f32)
         hipLaunchKernelGGL(k_cand_eval<float>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs,
                            W.r);
-        hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
-                           W.cap, W.pairs, W.r, mask, cutoff, O);
-    } else {
+    else
         hipLaunchKernelGGL(k_cand_eval<double>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap,
                            W.pairs, W.r);
+}
+void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
+                   const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
+                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st) {
+    dim3 gd((unsigned)((n + MB - 1) / MB));
+    if (f32)
+        hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
+                           W.cap, W.pairs, W.r, mask, cutoff, O);
+    else
         hipLaunchKernelGGL(k_decide<double>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
                            W.off, W.cap, W.pairs, W.r, mask, cutoff, O);
-    }
 }
 
 }  // namespace ptm

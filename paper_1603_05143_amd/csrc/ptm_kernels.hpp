@@ -54,8 +54,13 @@ void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, co
                 int32_t *todo_count, hipStream_t st);
 void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
                  uint64_t *ord, hipStream_t st);
-void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid, const int8_t *species,
-                  const TablesView &T, const int32_t *code, const uint64_t *ord, uint32_t mask, double cutoff,
-                  const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st);
+// match stage: candidate pair list, superposition of every pair, decision
+void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
+                 hipStream_t st);
+void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
+                 bool f32, hipStream_t st);
+void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
+                   const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
+                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st);
 
 }  // namespace ptm

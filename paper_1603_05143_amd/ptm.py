@@ -19,7 +19,7 @@ PTM_SC, PTM_FCC, PTM_HCP, PTM_ICO, PTM_BCC = 1, 2, 4, 8, 16
 PTM_ALL = 0x1F
 PTM_F_HOST_POINTERS = 1
 PTM_F_PROFILE = 2
-STAGE_NAMES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "match")
+STAGE_NAMES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "cand", "eval", "decide")
 TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
 ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")
 
@@ -75,6 +75,8 @@ def lib():
         L.ptm_template_info.restype = C.c_int
         L.ptm_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.c_int]
         L.ptm_stage_times.restype = C.c_int
+        L.ptm_frame_info.argtypes = [vp, C.POINTER(C.c_int64), C.c_int]
+        L.ptm_frame_info.restype = C.c_int
         _lib = L
     return _lib
 
@@ -128,6 +130,18 @@ def ptm_stage_times(ctx):
     if st != PTM_OK:
         raise PTMError(st, "ptm_stage_times")
     return dict(zip(STAGE_NAMES, list(ms)))
+
+
+INFO_NAMES = ("cells", "knn_exact", "pairs")
+
+
+def ptm_frame_info(ctx):
+    """Work counts of the last ptm_classify on a PTM_F_PROFILE context."""
+    info = (C.c_int64 * len(INFO_NAMES))()
+    st = lib().ptm_frame_info(ctx, info, len(INFO_NAMES))
+    if st != PTM_OK:
+        raise PTMError(st, "ptm_frame_info")
+    return dict(zip(INFO_NAMES, list(info)))
 
 
 def ptm_template_info(t: int):
