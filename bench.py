@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "atoms/s (PTM, all templates) FP32-mixed vs FP64 plain; p50/p99 frame latency"
-STAGES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "cand", "eval", "decide")
+STAGES = ("bounds", "bin", "knn", "topo", "cand", "eval", "decide")
 
 # MI355X published peaks: HBM3E bandwidth; vector FP64, which equals vector
 # FP32 without packed instructions (the library is built without them)
@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
 
 # kernel(s) behind each single-kernel stage, for the roofline line
-STAGE_KERNEL = {"knn": "k_knn_fast + k_knn_exact", "topo6": "k_topo<6>", "topo12": "k_topo<12>",
-                "topo14": "k_topo<14>", "eval": "k_cand_eval", "decide": "k_decide"}
+STAGE_KERNEL = {"knn": "k_knn_fast + k_knn_exact", "topo": "k_topo", "eval": "k_cand_eval",
+                "decide": "k_decide + k_decide_full"}
 
 
 def orient_tests(K: int) -> int:
@@ -54,8 +54,10 @@ def work_model(stage: str, n: int, info: dict) -> tuple[str, float, str]:
     operations for the arithmetic stages, HBM bytes for binning.
       knn     18 in-sphere distances per atom (the minimum any search must
               evaluate) x 11 FLOP (difference, minimum image, squared norm)
-      topoK   orient3d from differences = 23 FLOP per test, 14 FLOP per
-              centre-inside test (the centre is the origin)
+      topo    one incremental hull of the 14 neighbours (orient3d from
+              differences = 23 FLOP per test) read off at 6, 12 and 14 points,
+              each checked for the centre (14 FLOP per facet: the centre is
+              the origin)
       eval    per superposed pair with N = 13 points: covariance 18N, G_b 6N,
               residual 27N, key matrix + characteristic polynomial + Newton +
               adjugate eigenvector + rotation ~290 FLOP
@@ -64,13 +66,13 @@ def work_model(stage: str, n: int, info: dict) -> tuple[str, float, str]:
       bin     104 B per atom (positions read twice, cell/slot/sorted writes)
               + 8 B per cell (histogram scan)
     """
-    K = {"topo6": 6, "topo12": 12, "topo14": 14}.get(stage)
     if stage == "bin":
         return "hbm", 104.0 * n + 8.0 * info.get("cells", 0), "bytes"
     if stage == "knn":
         return "alu", 18 * 11.0 * n, "flop"
-    if K is not None:
-        return "alu", (23.0 * orient_tests(K) + 14.0 * (2 * K - 4)) * n, "flop"
+    if stage == "topo":
+        inside = sum(2 * K - 4 for K in (6, 12, 14))
+        return "alu", (23.0 * orient_tests(14) + 14.0 * inside) * n, "flop"
     if stage == "eval":
         N = 13
         return "alu", (51.0 * N + 290.0) * info.get("pairs", 0), "flop"

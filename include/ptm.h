@@ -73,10 +73,10 @@ enum { PTM_F_HOST_POINTERS = 1u << 0, /* inputs/outputs are host pointers (stage
        PTM_F_PROFILE = 1u << 1 };     /* record HIP events between pipeline stages */
 
 /* pipeline stages reported by ptm_stage_times */
-enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2, PTM_STAGE_TOPO6 = 3, PTM_STAGE_TOPO12 = 4,
-       PTM_STAGE_TOPO14 = 5, PTM_STAGE_CAND = 6 /* candidate pair list */,
-       PTM_STAGE_EVAL = 7 /* superposition of every pair */,
-       PTM_STAGE_DECIDE = 8 /* decision, orientation, strain, alloy, write-back */, PTM_NSTAGES = 9 };
+enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2,
+       PTM_STAGE_TOPO = 3 /* hulls of 6, 12, 14 neighbours, codes, lookup */,
+       PTM_STAGE_CAND = 4 /* candidate pair list */, PTM_STAGE_EVAL = 5 /* superposition of every pair */,
+       PTM_STAGE_DECIDE = 6 /* decision, orientation, strain, alloy, write-back */, PTM_NSTAGES = 7 };
 
 typedef struct {
     int device;                /* HIP device ordinal */
@@ -169,7 +169,8 @@ ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n);
 enum { PTM_INFO_CELLS = 0,      /* cells of the binning grid */
        PTM_INFO_KNN_EXACT = 1,  /* atoms whose neighbours the exact (whole-wave) search found */
        PTM_INFO_PAIRS = 2,      /* (atom, candidate correspondence) pairs superposed */
-       PTM_NINFO = 3 };
+       PTM_INFO_DECIDE_FULL = 3, /* atoms decided by the full rule (near tie, FP32 margin, overflow) */
+       PTM_NINFO = 4 };
 ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n);
 
 /* Template facts of the library's own tables, for checks without a device:

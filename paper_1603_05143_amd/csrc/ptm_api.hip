@@ -35,7 +35,7 @@ static int64_t pair_capacity(int64_t n) { return 6 * n + 64; }
 size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
-    b += align_up(4 * (size_t)(cells + 2)) * 2;  // count (+ k-NN leftover counter), start
+    b += align_up(4 * (size_t)(cells + 3)) * 2;  // count (+ k-NN and decision leftover counters), start
     b += align_up(8 * (size_t)n) * 3;         // sorted positions
     b += align_up(4 * (size_t)n * KMAX);      // neighbour ids
     b += align_up(8 * (size_t)n * KMAX * 3);  // neighbour vectors
@@ -44,6 +44,7 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
     b += align_up(8 * (size_t)(n + 1)) * 2;   // candidate counts and offsets
     b += align_up(16 * (size_t)pair_capacity(n));  // pairs and their RMSD
+    b += align_up(40 * (size_t)pair_capacity(n));  // their quaternion and scale
     b += align_up(scan_tmp);
     return b;
 }
@@ -80,8 +81,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
     cell_of = (int32_t *)take(4 * (size_t)n);
     slot_of = (int32_t *)take(4 * (size_t)n);
     sid = (int32_t *)take(4 * (size_t)n);
-    count = (int32_t *)take(4 * (size_t)(cells + 2));
-    start = (int32_t *)take(4 * (size_t)(cells + 2));
+    count = (int32_t *)take(4 * (size_t)(cells + 3));
+    start = (int32_t *)take(4 * (size_t)(cells + 3));
     sx = (double *)take(8 * (size_t)n);
     sy = (double *)take(8 * (size_t)n);
     sz = (double *)take(8 * (size_t)n);
@@ -95,6 +96,7 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
     match.off = (int64_t *)take(8 * (size_t)(n + 1));
     match.pairs = (uint2 *)take(8 * (size_t)match.cap);
     match.r = (double *)take(8 * (size_t)match.cap);
+    match.qs = take(40 * (size_t)match.cap);
     scan_tmp_ptr = take(scan_tmp);
     scan_tmp_bytes = scan_tmp;
     match.scan_tmp = scan_tmp_ptr;
@@ -186,8 +188,9 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     const Grid &g = J.grid;
     if ((ps = mark(PTM_STAGE_BIN)) != PTM_OK) return ps;
     int64_t cells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
-    // count[cells + 1] counts the atoms the fast k-NN search leaves over
-    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 2), st));
+    // count[cells + 1] and count[cells + 2] count the atoms the fast k-NN
+    // search and the common-case decision leave over
+    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 3), st));
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
     size_t tmp = S.scan_tmp_bytes;
     PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
@@ -196,26 +199,20 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     // slot_of is free once the atoms are scattered: it holds the leftover list
     launch_knn(n, g, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, S.slot_of,
                S.count + cells + 1, st);
-    if ((ps = mark(PTM_STAGE_TOPO6)) != PTM_OK) return ps;
+    if ((ps = mark(PTM_STAGE_TOPO)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
-    const bool need[NGRP] = {(m & 0x1u) != 0, (m & 0xEu) != 0, (m & 0x10u) != 0};
-    for (int grp = 0; grp < NGRP; grp++) {
-        if (need[grp])
-            launch_topo(group_k(grp), ctx->precision == PTM_FP32_MIXED, n, S.nbr_rel, S.nbr_id, ctx->view,
-                        S.code + (int64_t)grp * n, S.ord + (int64_t)grp * n, st);
-        else
-            PTM_HIP(ctx, hipMemsetAsync(S.code + (int64_t)grp * n, 0xFF, 4 * (size_t)n, st));
-        if (prof) ctx->prof_ran[PTM_STAGE_TOPO6 + grp] = need[grp];
-        if ((ps = mark(PTM_STAGE_TOPO6 + grp + 1)) != PTM_OK) return ps;
-    }
+    const uint32_t need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
+    launch_topo(ctx->precision == PTM_FP32_MIXED, n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, st);
+    if ((ps = mark(PTM_STAGE_CAND)) != PTM_OK) return ps;
     MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
     const bool f32 = ctx->precision == PTM_FP32_MIXED;
     launch_cand(n, ctx->view, S.code, m, S.match, st);
     if ((ps = mark(PTM_STAGE_EVAL)) != PTM_OK) return ps;
     launch_eval(n, S.nbr_rel, ctx->view, S.ord, S.match, f32, st);
     if ((ps = mark(PTM_STAGE_DECIDE)) != PTM_OK) return ps;
-    launch_decide(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match, f32,
-                  st);
+    // slot_of (free since the scatter) holds the decision's leftover list
+    launch_decide(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match,
+                  S.slot_of, S.count + cells + 2, f32, st);
     if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;
@@ -425,13 +422,14 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
     if (st != PTM_OK) return st;
     PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (prof) {
-        int32_t left = 0;
+        int32_t left[2] = {0, 0};
         int64_t pairs = 0;
-        PTM_HIP(ctx, hipMemcpy(&left, ctx->main.count + cells + 1, 4, hipMemcpyDeviceToHost));
+        PTM_HIP(ctx, hipMemcpy(left, ctx->main.count + cells + 1, 8, hipMemcpyDeviceToHost));
         PTM_HIP(ctx, hipMemcpy(&pairs, ctx->main.match.off + n_atoms, 8, hipMemcpyDeviceToHost));
         ctx->prof_info[PTM_INFO_CELLS] = cells;
-        ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left : n_atoms;
+        ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left[0] : n_atoms;
         ctx->prof_info[PTM_INFO_PAIRS] = pairs;
+        ctx->prof_info[PTM_INFO_DECIDE_FULL] = left[1];
     }
     ctx->prof_valid = prof;
     return PTM_OK;
@@ -442,7 +440,6 @@ ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n) {
     for (int i = 0; i < n && i < PTM_NSTAGES; i++) {
         ms[i] = 0.0;
         if (!ctx->prof_valid) continue;
-        if (i >= PTM_STAGE_TOPO6 && i <= PTM_STAGE_TOPO14 && !ctx->prof_ran[i]) continue;
         float t = 0.f;
         if (hipEventElapsedTime(&t, ctx->prof_ev[i], ctx->prof_ev[i + 1]) != hipSuccess) {
             (void)hipGetLastError();

@@ -134,6 +134,5 @@ struct ptm_ctx {
     // stage profiling (PTM_F_PROFILE)
     hipEvent_t prof_ev[PTM_NSTAGES + 1] = {};
     bool prof_valid = false;
-    bool prof_ran[PTM_NSTAGES] = {};
     int64_t prof_info[PTM_NINFO] = {};
 };

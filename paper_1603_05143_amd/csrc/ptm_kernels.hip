@@ -551,36 +551,44 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
 }
 
 // --------------------------------------------------------------- topology
-// Incremental convex hull (every point must become a vertex and stay one),
-// facets with neighbour links, then the rotation system and the canonical
-// code.  Per-lane state lives in LDS, lane-minor, so dynamic indices never
-// conflict across lanes.
+// One incremental convex hull per atom over its 14 nearest neighbours in
+// rank order (every point must become a vertex and stay one), with facets
+// and neighbour links.  The hull of the first k points is a state of that
+// same construction, so the 6-, 12- and 14-point hulls are read off it
+// after inserting points 5, 11 and 13: for each, the centre must lie
+// strictly inside, then the rotation system and the canonical start-edge
+// code are built and looked up.  Per-lane state lives in LDS, lane-minor,
+// so dynamic indices never conflict across lanes.
 constexpr int TB = 64;  // threads per block of the topology kernel
+constexpr int NT_SNAP = 12;  // rotation-system rows kept beside the points
 
-// The rotation system reuses the point storage after the hull is built.
-// Entries are kept in words of the point type so that every lane's rotation
-// system overlays only its own points (column t): 64-bit words over FP64
-// points, pairs of 32-bit words over FP32 points.
-template <int K, typename R>
+// LDS of one block.  P: neighbour vectors (FP64 or FP32 words); F: facets;
+// H: the horizon of the current insertion, which shares its rows with the
+// rotation system of the 6- and 12-point hulls (built between insertions).
+// The rotation system of the last hull overlays P, which is then free.
+template <typename R>
 struct TopoShared {
     union {
-        R P[3][K][TB];            // neighbour vectors (hull phase), FP64 or FP32
-        uint64_t NT64[K][TB];     // rotation system over FP64 points
-        uint32_t NT32[2 * K][TB]; // rotation system over FP32 points (lo, hi)
+        R P[3][KMAX][TB];
+        uint32_t PW[3 * KMAX * sizeof(R) / 4][TB];
     };
-    uint32_t F[2 * K - 4][TB];
-    uint16_t H[K][TB];
-    __device__ uint64_t nt(int x, int t) const {
-        if constexpr (sizeof(R) == 8) return NT64[x][t];
-        else return (uint64_t)NT32[2 * x][t] | ((uint64_t)NT32[2 * x + 1][t] << 32);
-    }
-    __device__ void set_nt(int x, int t, uint64_t v) {
-        if constexpr (sizeof(R) == 8) {
-            NT64[x][t] = v;
-        } else {
-            NT32[2 * x][t] = (uint32_t)v;
-            NT32[2 * x + 1][t] = (uint32_t)(v >> 32);
-        }
+    uint32_t F[2 * KMAX - 4][TB];
+    union {
+        uint16_t H[KMAX][TB];
+        uint32_t NW[2 * NT_SNAP][TB];
+    };
+};
+
+// A lane's rotation system: row x = 64-bit word whose nibble y is the
+// vertex after y counter-clockwise around x (0xF: not a neighbour), stored
+// as two 32-bit LDS words in the lane's column.
+struct RotSys {
+    uint32_t (*w)[TB];
+    int t;
+    __device__ uint64_t get(int x) const { return (uint64_t)w[2 * x][t] | ((uint64_t)w[2 * x + 1][t] << 32); }
+    __device__ void set(int x, uint64_t v) const {
+        w[2 * x][t] = (uint32_t)v;
+        w[2 * x + 1][t] = (uint32_t)(v >> 32);
     }
 };
 
@@ -598,9 +606,9 @@ __device__ inline uint32_t fset_nb(uint32_t f, int e, int g) {
 
 // Per-lane view of the hull inputs: LDS points plus the FP64 originals in
 // global memory (used when an FP32 filter cannot decide).
-template <int K, typename R>
+template <typename R>
 struct Lane {
-    TopoShared<K, R> &S;
+    TopoShared<R> &S;
     int t;
     const double *__restrict__ rel;
     int64_t n, p;
@@ -613,8 +621,8 @@ struct Lane {
 };
 
 // orientation of facet (a,b,c) against point q (held in registers)
-template <int K, typename R>
-__device__ inline int lane_orient(const Lane<K, R> &L, int a, int b, int c, const R (&pq)[3], int q) {
+template <typename R>
+__device__ inline int lane_orient(const Lane<R> &L, int a, int b, int c, const R (&pq)[3], int q) {
     R pa[3], pb[3], pc[3];
     L.load(a, pa);
     L.load(b, pb);
@@ -633,8 +641,8 @@ __device__ inline int lane_orient(const Lane<K, R> &L, int a, int b, int c, cons
     }
 }
 
-template <int K, typename R>
-__device__ inline int lane_det3(const Lane<K, R> &L, int a, int b, int c) {
+template <typename R>
+__device__ inline int lane_det3(const Lane<R> &L, int a, int b, int c) {
     R pa[3], pb[3], pc[3];
     L.load(a, pa);
     L.load(b, pb);
@@ -652,96 +660,105 @@ __device__ inline int lane_det3(const Lane<K, R> &L, int a, int b, int c) {
     }
 }
 
-// returns 1 if the hull is valid (all K points vertices, centre strictly
-// inside); the facets are left in S.F[0 .. 2K-5]
-template <int K, typename R>
-__device__ int lane_hull(const Lane<K, R> &L) {
-    TopoShared<K, R> &S = L.S;
+// first tetrahedron of points 0..3, positively oriented; facets 0..3
+template <typename R>
+__device__ inline void lane_hull_start(const Lane<R> &L) {
+    TopoShared<R> &S = L.S;
     const int t = L.t;
     int a = 0, b = 1, c = 2, d = 3;
-    {
-        R p3[3];
-        L.load(3, p3);
-        if (lane_orient<K, R>(L, 0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
-    }
+    R p3[3];
+    L.load(3, p3);
+    if (lane_orient<R>(L, 0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
     S.F[0][t] = fpack(a, b, c, 1, 2, 3);
     S.F[1][t] = fpack(b, a, d, 0, 3, 2);
     S.F[2][t] = fpack(c, b, d, 0, 1, 3);
     S.F[3][t] = fpack(a, c, d, 0, 2, 1);
-    int nf = 4;
-    for (int p = 4; p < K; p++) {
-        uint32_t vis = 0;
-        int nvis = 0;
-        R pp[3];
-        L.load(p, pp);
-        for (int f = 0; f < nf; f++) {
-            uint32_t w = S.F[f][t];
-            if (lane_orient<K, R>(L, fv(w, 0), fv(w, 1), fv(w, 2), pp, p) > 0) {
-                vis |= 1u << f;
-                nvis++;
-            }
-        }
-        if (nvis == 0) return 0;  // p inside: never a vertex
-        // horizon edges (a -> b) of visible facets whose neighbour is not visible
-        int nh = 0;
-        for (int f = 0; f < nf; f++) {
-            if (!((vis >> f) & 1)) continue;
-            uint32_t w = S.F[f][t];
-            for (int e = 0; e < 3; e++) {
-                int g = fn(w, e);
-                if (g >= nf) return 0;  // broken link (cannot happen with exact predicates)
-                if ((vis >> g) & 1) continue;
-                if (nh >= K) return 0;
-                S.H[nh][t] = (uint16_t)(fv(w, e) | (fv(w, (e + 1) % 3) << 4) | (g << 8));
-                nh++;
-            }
-        }
-        // a horizon of nvis+2 edges <=> no earlier vertex is swallowed
-        if (nh != nvis + 2) return 0;
-        // slots: freed visible facets first (increasing), then two new ones;
-        // pass 1 records vertex -> slot maps, pass 2 builds the facets
-        uint64_t start_lo = 0, start_hi = 0, end_lo = 0, end_hi = 0;  // 8-bit fields
-        uint32_t freed = vis;
-        int nf_new = nf;
-        for (int h = 0; h < nh; h++) {
-            int s;
-            if (freed) {
-                s = __builtin_ctz(freed);
-                freed &= freed - 1;
-            } else {
-                s = nf_new++;
-            }
-            uint32_t hw = S.H[h][t];
-            int ha = hw & 0xF, hb = (hw >> 4) & 0xF;
-            if (ha < 8) start_lo |= (uint64_t)s << (8 * ha); else start_hi |= (uint64_t)s << (8 * (ha - 8));
-            if (hb < 8) end_lo |= (uint64_t)s << (8 * hb); else end_hi |= (uint64_t)s << (8 * (hb - 8));
-        }
-        freed = vis;
-        int nf2 = nf;
-        for (int h = 0; h < nh; h++) {
-            int s;
-            if (freed) {
-                s = __builtin_ctz(freed);
-                freed &= freed - 1;
-            } else {
-                s = nf2++;
-            }
-            uint32_t hw = S.H[h][t];
-            int ha = hw & 0xF, hb = (hw >> 4) & 0xF, g = (hw >> 8) & 0x1F;
-            int s_next = (int)(((hb < 8 ? start_lo >> (8 * hb) : start_hi >> (8 * (hb - 8)))) & 0xFF);
-            int s_prev = (int)(((ha < 8 ? end_lo >> (8 * ha) : end_hi >> (8 * (ha - 8)))) & 0xFF);
-            S.F[s][t] = fpack(ha, hb, p, g, s_next, s_prev);
-            uint32_t gw = S.F[g][t];
-            for (int e = 0; e < 3; e++)
-                if (fv(gw, e) == hb && fv(gw, (e + 1) % 3) == ha) gw = fset_nb(gw, e, s);
-            S.F[g][t] = gw;
-        }
-        nf = nf_new;
-    }
-    // centre strictly inside every facet: det[a; b; c] > 0 exactly
-    for (int f = 0; f < 2 * K - 4; f++) {
+}
+
+// Insert point p into the hull of points 0..p-1 (nf = 2p - 4 facets).
+// Returns 0 if p lies inside (it never becomes a vertex) or swallows an
+// earlier vertex: then no hull of p or more points is valid.
+template <typename R>
+__device__ int lane_insert(const Lane<R> &L, int p) {
+    TopoShared<R> &S = L.S;
+    const int t = L.t;
+    const int nf = 2 * p - 4;
+    uint32_t vis = 0;
+    int nvis = 0;
+    R pp[3];
+    L.load(p, pp);
+    for (int f = 0; f < nf; f++) {
         uint32_t w = S.F[f][t];
-        if (lane_det3<K, R>(L, fv(w, 0), fv(w, 1), fv(w, 2)) <= 0) return 0;
+        if (lane_orient<R>(L, fv(w, 0), fv(w, 1), fv(w, 2), pp, p) > 0) {
+            vis |= 1u << f;
+            nvis++;
+        }
+    }
+    if (nvis == 0) return 0;  // p inside: never a vertex
+    // horizon edges (a -> b) of visible facets whose neighbour is not visible
+    int nh = 0;
+    for (int f = 0; f < nf; f++) {
+        if (!((vis >> f) & 1)) continue;
+        uint32_t w = S.F[f][t];
+        for (int e = 0; e < 3; e++) {
+            int g = fn(w, e);
+            if (g >= nf) return 0;  // broken link (cannot happen with exact predicates)
+            if ((vis >> g) & 1) continue;
+            if (nh >= KMAX) return 0;
+            S.H[nh][t] = (uint16_t)(fv(w, e) | (fv(w, (e + 1) % 3) << 4) | (g << 8));
+            nh++;
+        }
+    }
+    // a horizon of nvis+2 edges <=> no earlier vertex is swallowed
+    if (nh != nvis + 2) return 0;
+    // slots: freed visible facets first (increasing), then two new ones;
+    // pass 1 records vertex -> slot maps, pass 2 builds the facets
+    uint64_t start_lo = 0, start_hi = 0, end_lo = 0, end_hi = 0;  // 8-bit fields
+    uint32_t freed = vis;
+    int nf_new = nf;
+    for (int h = 0; h < nh; h++) {
+        int s;
+        if (freed) {
+            s = __builtin_ctz(freed);
+            freed &= freed - 1;
+        } else {
+            s = nf_new++;
+        }
+        uint32_t hw = S.H[h][t];
+        int ha = hw & 0xF, hb = (hw >> 4) & 0xF;
+        if (ha < 8) start_lo |= (uint64_t)s << (8 * ha); else start_hi |= (uint64_t)s << (8 * (ha - 8));
+        if (hb < 8) end_lo |= (uint64_t)s << (8 * hb); else end_hi |= (uint64_t)s << (8 * (hb - 8));
+    }
+    freed = vis;
+    int nf2 = nf;
+    for (int h = 0; h < nh; h++) {
+        int s;
+        if (freed) {
+            s = __builtin_ctz(freed);
+            freed &= freed - 1;
+        } else {
+            s = nf2++;
+        }
+        uint32_t hw = S.H[h][t];
+        int ha = hw & 0xF, hb = (hw >> 4) & 0xF, g = (hw >> 8) & 0x1F;
+        int s_next = (int)(((hb < 8 ? start_lo >> (8 * hb) : start_hi >> (8 * (hb - 8)))) & 0xFF);
+        int s_prev = (int)(((ha < 8 ? end_lo >> (8 * ha) : end_hi >> (8 * (ha - 8)))) & 0xFF);
+        S.F[s][t] = fpack(ha, hb, p, g, s_next, s_prev);
+        uint32_t gw = S.F[g][t];
+        for (int e = 0; e < 3; e++)
+            if (fv(gw, e) == hb && fv(gw, (e + 1) % 3) == ha) gw = fset_nb(gw, e, s);
+        S.F[g][t] = gw;
+    }
+    return 1;
+}
+
+// the centre lies strictly inside every facet of the K-point hull:
+// det[a; b; c] > 0 exactly
+template <typename R>
+__device__ inline int lane_centre_inside(const Lane<R> &L, int K) {
+    for (int f = 0; f < 2 * K - 4; f++) {
+        uint32_t w = L.S.F[f][L.t];
+        if (lane_det3<R>(L, fv(w, 0), fv(w, 1), fv(w, 2)) <= 0) return 0;
     }
     return 1;
 }
@@ -752,8 +769,8 @@ __device__ int lane_hull(const Lane<K, R> &L) {
 // code[] receives the K words; the return value is the labelling (nibble
 // l = vertex of label l).  One code per hull: the tables hold every
 // minimum-signature start edge of every template triangulation.
-template <int K, typename R>
-__device__ uint64_t lane_start_edge_code(TopoShared<K, R> &S, int t, uint64_t degs, uint64_t (&code)[K]) {
+template <int K>
+__device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64_t (&code)[K]) {
     int mindeg = 15;
 #pragma unroll
     for (int x = 0; x < K; x++) mindeg = min(mindeg, (int)nib(degs, x));
@@ -764,7 +781,7 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K, R> &S, int t, uint64_t de
     int bu = 0, bv = 0;
     for (uint32_t m = mdmask; m; m &= m - 1) {
         int u = __builtin_ctz(m);
-        uint64_t ntu = S.nt(u, t);
+        uint64_t ntu = NT.get(u);
         int v0 = 0;
         while (nib(ntu, v0) == 0xF) v0++;
         uint64_t dg = 0;  // degrees of u's neighbours, counter-clockwise from v0
@@ -785,7 +802,7 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K, R> &S, int t, uint64_t de
         }
     }
     code[0] = minsig;
-    uint64_t ntu = S.nt(bu, t);
+    uint64_t ntu = NT.get(bu);
     uint64_t lab = ~0ull, ord = (uint64_t)bu, par = 0;
     lab = setnib(lab, bu, 0);
     int y = bv;
@@ -800,7 +817,7 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K, R> &S, int t, uint64_t de
     for (int i = 1; i < K; i++) {
         int x = min((int)nib(ord, i), K - 1);
         int yy = (int)nib(par, x);
-        uint64_t ntx = S.nt(x, t);
+        uint64_t ntx = NT.get(x);
         int dx = (int)nib(degs, x);
         uint64_t row = (uint64_t)dx << 60;
         for (int j = 0; j < dx; j++) {
@@ -820,71 +837,115 @@ __device__ uint64_t lane_start_edge_code(TopoShared<K, R> &S, int t, uint64_t de
     return ord;
 }
 
-template <int K, typename R>
+// Rotation system, canonical code and table lookup of the K-point hull now
+// held in F; returns the code id (-1: no template triangulation has this
+// code) and the labelling in ordw.
+template <int K>
+__device__ int32_t lane_lookup(const uint32_t (*F)[TB], const RotSys &NT, const TablesView &T, uint64_t &ordw) {
+    constexpr int grp = (K == 6) ? 0 : (K == 12 ? 1 : 2);
+    const int t = NT.t;
+    uint64_t degs = 0;
+    for (int x = 0; x < K; x++) NT.set(x, ~0ull);
+    for (int f = 0; f < 2 * K - 4; f++) {
+        uint32_t w = F[f][t];
+        int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
+        NT.set(a, setnib(NT.get(a), b, c));
+        NT.set(b, setnib(NT.get(b), c, a));
+        NT.set(c, setnib(NT.get(c), a, b));
+        degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
+    }
+    uint64_t best[K];
+    uint64_t ord = lane_start_edge_code<K>(NT, degs, best);
+    // table lookup with full-code verification
+    uint64_t h = code_hash(best, K);
+    int mask = T.hmask[grp];
+    int s = (int)(h & (uint64_t)mask);
+    for (int probe = 0; probe <= mask; probe++) {
+        int c = T.slots[grp][s];
+        if (c < 0) break;
+        const uint64_t *cw = T.codes[grp] + (int64_t)c * K;
+        bool eq = true;
+#pragma unroll
+        for (int i = 0; i < K; i++) eq = eq && (cw[i] == best[i]);
+        if (eq) {
+            ordw = ord;
+            return c;
+        }
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
+
+// One lane per atom: the hulls of the first 6, 12 and 14 neighbours (those
+// enabled by need: bit g for hull group g), code ids and labellings into
+// code_out / ord_out [group][n] (-1 / 0 for a group without a valid hull or
+// not needed).
+template <typename R>
 __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
-                                              const int32_t *__restrict__ nbr_id, TablesView T,
+                                              const int32_t *__restrict__ nbr_id, TablesView T, uint32_t need,
                                               int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
-    __shared__ TopoShared<K, R> S;
+    __shared__ TopoShared<R> S;
     const int t = threadIdx.x;
     const int64_t p = blockIdx.x * (int64_t)TB + t;
     if (p >= n) return;
-    constexpr int grp = (K == 6) ? 0 : (K == 12 ? 1 : 2);
-    int32_t cid = -1;
-    uint64_t ordw = 0;
-    if (nbr_id[(int64_t)(K - 1) * n + p] >= 0) {
-        for (int r = 0; r < K; r++)
+    // hulls wanted and possible (the K-th neighbour exists)
+    uint32_t want = 0;
+    for (int g = 0; g < NGRP; g++)
+        if (((need >> g) & 1) && nbr_id[(int64_t)(group_k(g) - 1) * n + p] >= 0) want |= 1u << g;
+    int32_t cid[NGRP] = {-1, -1, -1};
+    uint64_t ordw[NGRP] = {0, 0, 0};
+    if (want) {
+        const int kl = (want & 4) ? 14 : ((want & 2) ? 12 : 6);  // last point to insert
+        for (int r = 0; r < kl; r++)
             for (int d = 0; d < 3; d++) S.P[d][r][t] = (R)nbr_rel[((int64_t)r * 3 + d) * n + p];
-        Lane<K, R> L{S, t, nbr_rel, n, p};
-        if (lane_hull<K, R>(L)) {
-            uint64_t degs = 0;
-            for (int x = 0; x < K; x++) S.set_nt(x, t, ~0ull);  // overwrites this lane's points
-            for (int f = 0; f < 2 * K - 4; f++) {
-                uint32_t w = S.F[f][t];
-                int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
-                S.set_nt(a, t, setnib(S.nt(a, t), b, c));
-                S.set_nt(b, t, setnib(S.nt(b, t), c, a));
-                S.set_nt(c, t, setnib(S.nt(c, t), a, b));
-                degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
-            }
-            uint64_t best[K];
-            uint64_t ord = lane_start_edge_code<K, R>(S, t, degs, best);
-            // table lookup with full-code verification
-            uint64_t h = code_hash(best, K);
-            int mask = T.hmask[grp];
-            int s = (int)(h & (uint64_t)mask);
-            for (int probe = 0; probe <= mask; probe++) {
-                int c = T.slots[grp][s];
-                if (c < 0) break;
-                const uint64_t *cw = T.codes[grp] + (int64_t)c * K;
-                bool eq = true;
-#pragma unroll
-                for (int i = 0; i < K; i++) eq = eq && (cw[i] == best[i]);
-                if (eq) {
-                    cid = c;
-                    ordw = ord;
-                    break;
-                }
-                s = (s + 1) & mask;
+        Lane<R> L{S, t, nbr_rel, n, p};
+        lane_hull_start<R>(L);
+        const RotSys snap{S.NW, t}, last{S.PW, t};
+        for (int q = 4; q < kl; q++) {
+            if (!lane_insert<R>(L, q)) break;
+            const int K = q + 1;
+            if (K == 6 && (want & 1)) {
+                if (lane_centre_inside<R>(L, 6)) cid[0] = lane_lookup<6>(S.F, snap, T, ordw[0]);
+            } else if (K == 12 && (want & 2)) {
+                if (lane_centre_inside<R>(L, 12)) cid[1] = lane_lookup<12>(S.F, snap, T, ordw[1]);
+            } else if (K == 14) {
+                // last hull: its rotation system may overlay the points
+                if (lane_centre_inside<R>(L, 14)) cid[2] = lane_lookup<14>(S.F, last, T, ordw[2]);
             }
         }
     }
-    code_out[p] = cid;
-    ord_out[p] = ordw;
+    for (int g = 0; g < NGRP; g++) {
+        code_out[(int64_t)g * n + p] = cid[g];
+        ord_out[(int64_t)g * n + p] = cid[g] >= 0 ? ordw[g] : 0;
+    }
 }
 
 // ------------------------------------------------------------------ match
-constexpr int MB = 128;  // threads per block of the match kernel
+constexpr int MB = 256;  // threads per block of the match kernels
 
 struct MatchShared {
     TemplateDev tpl[NT];
 };
 
 // rank vector of the representative: min over g of (c(g^-1(m)))_m, packed
-// with m = 0 in the most significant nibble
+// with m = 0 in the most significant nibble.  Only the group elements whose
+// first entry is minimal can win, so the full vectors are built for those
+// alone (a vertex lies in the image of g^-1(0) for |G| / orbit elements).
 __device__ inline uint64_t rep_vector(const TemplateDev &D, uint64_t cmap, int &gbest) {
+    uint32_t first = 16;
+    uint64_t cand = 0;  // bit g: g attains the minimal first entry
+    for (int g = 0; g < D.ngroup; g++) {
+        uint32_t f = nib(cmap, (int)nib(D.ginv[g], 0));
+        if (f < first) {
+            first = f;
+            cand = 0;
+        }
+        if (f == first) cand |= 1ull << g;
+    }
     uint64_t best = ~0ull;
     gbest = 0;
-    for (int g = 0; g < D.ngroup; g++) {
+    for (; cand; cand &= cand - 1) {
+        int g = __builtin_ctzll(cand);
         uint64_t gi = D.ginv[g];
         uint64_t v = 0;
         for (int m = 0; m < D.k; m++) v |= (uint64_t)nib(cmap, (int)nib(gi, m)) << (4 * (15 - m));
@@ -948,19 +1009,82 @@ __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const Templat
     out.s = s;
 }
 
+// eq.(3) for one candidate with the observed points streamed from the
+// (cached) neighbour vectors instead of held in registers: the barycentre,
+// then covariance and G_a / G_b, then the residual, each pass recomputing
+// the centred points.  The arithmetic and its order are those of
+// load_centred followed by eval_candidate, so the results are identical.
+template <int K, typename T>
+__device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t n, int64_t p,
+                                     const TemplateDev &D, uint64_t tv, CandEval<T> &out) {
+    double c[3] = {0, 0, 0};
+#pragma unroll 2
+    for (int r = 0; r < K; r++)
+        for (int d = 0; d < 3; d++) c[d] += nbr_rel[((int64_t)r * 3 + d) * n + p];
+    for (int d = 0; d < 3; d++) c[d] /= (K + 1);
+    T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    T Gb = 0;
+    double g = 0;
+    const T a0[3] = {(T)(-c[0]), (T)(-c[1]), (T)(-c[2])};
+    for (int d = 0; d < 3; d++) g += c[d] * c[d];
+    {
+        const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a0[y];
+        Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+    }
+#pragma unroll 2
+    for (int r = 0; r < K; r++) {
+        T a[3];
+        for (int d = 0; d < 3; d++) {
+            double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d];
+            a[d] = (T)x;
+            g += x * x;
+        }
+        const double *b64 = D.b[nib(tv, r) + 1];
+        const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[y];
+        Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+    }
+    const T Ga = (T)g;
+    T lam = qcp_solve<T>(S, Ga, Gb, out.q);
+    T s = Ga > T(0) ? lam / Ga : T(0);
+    T R[3][3];
+    quat_rot<T>(out.q, R);
+    T res = 0;
+    {
+        const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
+        for (int x = 0; x < 3; x++) {
+            T d = s * a0[x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
+            res += d * d;
+        }
+    }
+#pragma unroll 2
+    for (int r = 0; r < K; r++) {
+        T a[3];
+        for (int d = 0; d < 3; d++) a[d] = (T)(nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d]);
+        const double *b64 = D.b[nib(tv, r) + 1];
+        const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
+        for (int x = 0; x < 3; x++) {
+            T d = s * a[x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
+            res += d * d;
+        }
+    }
+    out.r = sqrt(res / T(K + 1));
+    out.s = s;
+}
+
 // observed points of one hull group: centre (row 0) and the innermost K
 // neighbours, minus their barycentre (eq. 2); Ga = sum of squared norms
 template <int K, typename T>
 __device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t n, int64_t p, T (&a)[NMAX][3],
                                     T &Ga) {
-    double v[KMAX][3];
+    // two passes over the (cached) neighbour vectors: the barycentre, then
+    // the centred points, so that the FP64 inputs are never all held at once
     double c[3] = {0, 0, 0};
-#pragma unroll
     for (int r = 0; r < K; r++)
-        for (int d = 0; d < 3; d++) {
-            v[r][d] = nbr_rel[((int64_t)r * 3 + d) * n + p];
-            c[d] += v[r][d];
-        }
+        for (int d = 0; d < 3; d++) c[d] += nbr_rel[((int64_t)r * 3 + d) * n + p];
     for (int d = 0; d < 3; d++) c[d] /= (K + 1);
     double g = 0;
     for (int d = 0; d < 3; d++) {
@@ -970,7 +1094,7 @@ __device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t 
 #pragma unroll
     for (int r = 0; r < K; r++)
         for (int d = 0; d < 3; d++) {
-            double x = v[r][d] - c[d];
+            double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d];
             a[r + 1][d] = (T)x;
             g += x * x;
         }
@@ -1042,71 +1166,77 @@ __device__ inline void tie_group(const MatchShared &M, const TablesView &T, int 
     }
 }
 
+// Outputs of the winning candidate from its superposition ev and the
+// strain inputs A^T (sum over points of V+ columns times centred points, in
+// template order) and l (mean point norm).
 template <int K, typename RT>
-__device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
-                              const double *__restrict__ nbr_rel, double cutoff, int64_t p, int64_t n, int32_t i,
-                              const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
-                              const MatchOut &O) {
-    RT a[NMAX][3], Ga;
-    load_centred<K, RT>(nbr_rel, n, p, a, Ga);
+__device__ inline void finish_outputs(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
+                                      const CandEval<RT> &ev, RT l, const RT (&At)[3][3], double cutoff, int64_t p,
+                                      int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
+                                      const int8_t *__restrict__ species, const MatchOut &O) {
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
-    uint64_t tv = tv_of_rank(cd.perm, ord, K);
-    CandEval<RT> ev;
-    eval_candidate<K, RT>(a, Ga, D, tv, ev);
-    int type = ((double)ev.r <= cutoff) ? cd.tmpl + 1 : 0;
-    uint64_t cmap = rank_of_tv(cd.perm, ord, K);
+    const uint64_t tv = tv_of_rank(cd.perm, ord, K);
+    const int type = ((double)ev.r <= cutoff) ? cd.tmpl + 1 : 0;
     int g;
-    uint64_t rep = rep_vector(D, cmap, g);
-    // q' = q * conj(q_g)
-    const double *qg = D.gq[g];
-    RT w1 = ev.q[0], x1 = ev.q[1], y1 = ev.q[2], z1 = ev.q[3];
-    RT w2 = (RT)qg[0], x2 = -(RT)qg[1], y2 = -(RT)qg[2], z2 = -(RT)qg[3];
-    RT q[4] = {w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+    const uint64_t rep = rep_vector(D, rank_of_tv(cd.perm, ord, K), g);
+    {
+        // q' = q * conj(q_g), sign fixed so that the first non-zero component is positive
+        const double *qg = D.gq[g];
+        RT w1 = ev.q[0], x1 = ev.q[1], y1 = ev.q[2], z1 = ev.q[3];
+        RT w2 = (RT)qg[0], x2 = -(RT)qg[1], y2 = -(RT)qg[2], z2 = -(RT)qg[3];
+        RT q[4] = {w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
                    w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2};
-    RT qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    int flip = 0;
-    for (int k = 0; k < 4; k++) {
-        if (q[k] > 0) { flip = 1; break; }
-        if (q[k] < 0) { flip = -1; break; }
+        RT qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        int flip = 0;
+        for (int k = 0; k < 4; k++) {
+            if (q[k] > 0) { flip = 1; break; }
+            if (q[k] < 0) { flip = -1; break; }
+        }
+        RT sc = RT(flip < 0 ? -1 : 1) / qn;
+        O.type[i] = (int8_t)type;
+        if (O.rmsd) O.rmsd[i] = (double)ev.r;
+        if (O.scale) O.scale[i] = (double)ev.s;
+        if (O.quat)
+            for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = (double)(q[k] * sc);
     }
-    RT sc = RT(flip < 0 ? -1 : 1) / qn;
-    for (int k = 0; k < 4; k++) q[k] *= sc;
-    // strain: A^T = V+ W', W' = a / l(a) in template order; P = sqrt(A A^T)
-    RT l = 0;
-    for (int r = 0; r <= K; r++) l += sqrt(a[r][0] * a[r][0] + a[r][1] * a[r][1] + a[r][2] * a[r][2]);
-    l /= RT(K + 1);
-    RT At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int x = 0; x < 3; x++)
-        for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][0] * a[0][y];
-#pragma unroll
-    for (int r = 0; r < K; r++) {
-        int col = (int)nib(tv, r) + 1;
+    if (O.neighbours) {
+#pragma unroll 1
+        for (int m = 0; m < KMAX; m++) {
+            int32_t id = -1;
+            if (m < K) {
+                int rank = (int)((rep >> (4 * (15 - m))) & 0xF);
+                id = nbr_id[(int64_t)rank * n + p];
+            }
+            O.neighbours[(int64_t)i * KMAX + m] = id;
+        }
+    }
+    if (O.strain) {
+        // P = sqrt(A A^T) by the eigen-decomposition of the symmetric A A^T
+        RT AA[3][3];
         for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * a[r + 1][y];
+            for (int y = 0; y < 3; y++) {
+                RT s = 0;
+                for (int m = 0; m < 3; m++) s += At[m][x] * At[m][y];
+                AA[x][y] = s / (l * l);
+            }
+        RT ev3[3], V[3][3];
+        jacobi3<RT>(AA, ev3, V);
+        for (int m = 0; m < 3; m++) ev3[m] = sqrt(fmax(ev3[m], RT(0)));
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) {
+                RT s = 0;
+                for (int m = 0; m < 3; m++) s += V[x][m] * ev3[m] * V[y][m];
+                O.strain[9 * (int64_t)i + 3 * x + y] = (double)s;
+            }
     }
-    RT AA[3][3];
-    for (int x = 0; x < 3; x++)
-        for (int y = 0; y < 3; y++) {
-            RT s = 0;
-            for (int m = 0; m < 3; m++) s += At[m][x] * At[m][y];
-            AA[x][y] = s / (l * l);
-        }
-    RT ev3[3], V[3][3];
-    jacobi3<RT>(AA, ev3, V);
-    RT P[9];
-    for (int x = 0; x < 3; x++)
-        for (int y = 0; y < 3; y++) {
-            RT s = 0;
-            for (int m = 0; m < 3; m++) s += V[x][m] * sqrt(fmax(ev3[m], RT(0))) * V[y][m];
-            P[3 * x + y] = s;
-        }
-    // alloy (Sec. 6, Table 3)
-    int alloy = 0;
-    if (species && type) {
-        int8_t me = species[i];
-        if (cd.tmpl == 1 || cd.tmpl == 4) {
+    if (O.alloy) {
+        // alloy (Sec. 6, Table 3)
+        int alloy = 0;
+        if (species && type && (cd.tmpl == 1 || cd.tmpl == 4)) {
+            const int8_t me = species[i];
             uint32_t cnt = 0;  // 8-bit counters: FCC groups 0..2, BCC inner/outer
+#pragma unroll 1
             for (int r = 0; r < K; r++) {
                 int32_t j = nbr_id[(int64_t)r * n + p];
                 int other = species[j] != me;
@@ -1129,25 +1259,78 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
                 else alloy = 8;
             }
         }
+        O.alloy[i] = (int8_t)alloy;
     }
-    O.type[i] = (int8_t)type;
-    if (O.alloy) O.alloy[i] = (int8_t)alloy;
-    if (O.rmsd) O.rmsd[i] = (double)ev.r;
-    if (O.scale) O.scale[i] = (double)ev.s;
-    if (O.quat)
-        for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = (double)q[k];
-    if (O.strain)
-        for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = (double)P[k];
-    if (O.neighbours) {
-        for (int m = 0; m < KMAX; m++) {
-            int32_t id = -1;
-            if (m < K) {
-                int rank = (int)((rep >> (4 * (15 - m))) & 0xF);
-                id = nbr_id[(int64_t)rank * n + p];
-            }
-            O.neighbours[(int64_t)i * KMAX + m] = id;
+}
+
+
+// Winner outputs with the superposition recomputed from the points.
+template <int K, typename RT>
+__device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
+                              const double *__restrict__ nbr_rel, double cutoff, int64_t p, int64_t n, int32_t i,
+                              const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
+                              const MatchOut &O) {
+    Candidate cd = T.cand[grp][c];
+    const TemplateDev &D = M.tpl[cd.tmpl];
+    const uint64_t tv = tv_of_rank(cd.perm, ord, K);
+    CandEval<RT> ev;
+    RT l = 0;
+    RT At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    {
+        RT a[NMAX][3], Ga;
+        load_centred<K, RT>(nbr_rel, n, p, a, Ga);
+        eval_candidate<K, RT>(a, Ga, D, tv, ev);
+        for (int r = 0; r <= K; r++) l += sqrt(a[r][0] * a[r][0] + a[r][1] * a[r][1] + a[r][2] * a[r][2]);
+        l /= RT(K + 1);
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][0] * a[0][y];
+#pragma unroll
+        for (int r = 0; r < K; r++) {
+            int col = (int)nib(tv, r) + 1;
+            for (int x = 0; x < 3; x++)
+                for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * a[r + 1][y];
         }
     }
+    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, cutoff, p, n, i, nbr_id, species, O);
+}
+
+// Winner outputs from the superposition stored by k_cand_eval (q, s) and
+// its RMSD r: only the strain inputs are gathered from the points, in two
+// passes (barycentre, then centred points) without holding them.
+template <int K, typename RT>
+__device__ inline void finish_stored(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
+                                     const double *__restrict__ nbr_rel, double r, const RT *__restrict__ qs,
+                                     double cutoff, int64_t p, int64_t n, int32_t i,
+                                     const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
+                                     const MatchOut &O) {
+    Candidate cd = T.cand[grp][c];
+    const TemplateDev &D = M.tpl[cd.tmpl];
+    const uint64_t tv = tv_of_rank(cd.perm, ord, K);
+    CandEval<RT> ev;
+    ev.r = (RT)r;
+    for (int k = 0; k < 4; k++) ev.q[k] = qs[k];
+    ev.s = qs[4];
+    double cb[3] = {0, 0, 0};
+#pragma unroll 1
+    for (int rr = 0; rr < K; rr++)
+        for (int d = 0; d < 3; d++) cb[d] += nbr_rel[((int64_t)rr * 3 + d) * n + p];
+    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
+    RT a0[3] = {(RT)(-cb[0]), (RT)(-cb[1]), (RT)(-cb[2])};
+    RT l = sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
+    RT At[3][3];
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) At[x][y] = (RT)D.vpinv[x][0] * a0[y];
+#pragma unroll 1
+    for (int rr = 0; rr < K; rr++) {
+        RT ar[3];
+        for (int d = 0; d < 3; d++) ar[d] = (RT)(nbr_rel[((int64_t)rr * 3 + d) * n + p] - cb[d]);
+        l += sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
+        int col = (int)nib(tv, rr) + 1;
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * ar[y];
+    }
+    l /= RT(K + 1);
+    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, cutoff, p, n, i, nbr_id, species, O);
 }
 
 __device__ inline void write_none(const MatchOut &O, int32_t i) {
@@ -1212,7 +1395,7 @@ template <typename RT>
 __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
                                                   const uint64_t *__restrict__ ords, const int64_t *__restrict__ off,
                                                   int64_t cap, const uint2 *__restrict__ pairs,
-                                                  double *__restrict__ rout) {
+                                                  double *__restrict__ rout, RT *__restrict__ qsout) {
     __shared__ MatchShared M;
     load_templates(M, T);
     int64_t total = off[n];
@@ -1224,19 +1407,33 @@ __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__res
         int g = pr.y >> 28, k = pr.y & 0x0FFFFFFF;
         Candidate cd = T.cand[g][k];
         uint64_t ord = ords[(int64_t)g * n + p];
-        RT a[NMAX][3], Ga;
         CandEval<RT> ev;
-        if (g == 0) {
-            load_centred<6, RT>(nbr_rel, n, p, a, Ga);
-            eval_candidate<6, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
-        } else if (g == 1) {
-            load_centred<12, RT>(nbr_rel, n, p, a, Ga);
-            eval_candidate<12, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
+        if constexpr (sizeof(RT) == 4) {
+            // FP32 points fit in registers: load once, evaluate
+            RT a[NMAX][3], Ga;
+            if (g == 0) {
+                load_centred<6, RT>(nbr_rel, n, p, a, Ga);
+                eval_candidate<6, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
+            } else if (g == 1) {
+                load_centred<12, RT>(nbr_rel, n, p, a, Ga);
+                eval_candidate<12, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
+            } else {
+                load_centred<14, RT>(nbr_rel, n, p, a, Ga);
+                eval_candidate<14, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
+            }
         } else {
-            load_centred<14, RT>(nbr_rel, n, p, a, Ga);
-            eval_candidate<14, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
+            // FP64 points would take ~90 registers: stream them instead
+            if (g == 0) eval_streamed<6, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
+            else if (g == 1) eval_streamed<12, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
+            else eval_streamed<14, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
         }
         rout[q] = (double)ev.r;
+        RT *o = qsout + 5 * q;
+        o[0] = ev.q[0];
+        o[1] = ev.q[1];
+        o[2] = ev.q[2];
+        o[3] = ev.q[3];
+        o[4] = ev.s;
     }
 }
 
@@ -1246,12 +1443,36 @@ __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__res
 // order).  Decisions whose FP32 margins are below it are redone in FP64.
 constexpr double RMSD_F32_BOUND = 4e-6;
 
+// Minimum over an atom's evaluated pairs: best and second-best RMSD and the
+// winning (group, candidate).  q1 > cap: the pairs did not fit the buffer.
+__device__ inline void pair_minimum(int64_t q0, int64_t q1, int64_t cap, const uint2 *__restrict__ pairs,
+                                    const double *__restrict__ rr, double &m1, double &m2, int &arg_grp,
+                                    int &arg_c, int64_t &arg_q) {
+    m1 = m2 = INFINITY;
+    arg_grp = arg_c = -1;
+    arg_q = -1;
+    if (q1 > cap) return;
+    for (int64_t q = q0; q < q1; q++) {
+        double r = rr[q];
+        if (r < m1) {
+            m2 = m1;
+            m1 = r;
+            arg_grp = pairs[q].y >> 28;
+            arg_c = pairs[q].y & 0x0FFFFFFF;
+            arg_q = q;
+        } else if (r < m2) {
+            m2 = r;
+        }
+    }
+}
+
 // Per-atom decision over the evaluated pairs (Alg. 1 minimum with the tie
-// rule), then the outputs of the winner.  Atoms whose pairs did not fit the
-// pair buffer are evaluated here directly.  With RT = float the pair RMSDs
-// are FP32; the decision is kept only when the best candidate beats every
-// other by more than twice the FP32 bound and lies clear of the cut-off,
-// otherwise the atom is decided in FP64.
+// rule), then the outputs of the winner.  The common case -- a unique
+// winner by more than the tie tolerance (for FP32 pair RMSDs: by more than
+// twice the FP32 bound, and clear of the cut-off) -- is finished here in
+// the working precision; every other atom (a near tie, an FP32 margin too
+// small to trust, pairs that did not fit the buffer) is appended to todo for
+// k_decide_full, so that this kernel stays small enough for full occupancy.
 template <typename RT>
 __global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restrict__ nbr_rel,
                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
@@ -1259,70 +1480,107 @@ __global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restri
                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
                                                const int64_t *__restrict__ off, int64_t cap,
                                                const uint2 *__restrict__ pairs, const double *__restrict__ rr,
-                                               uint32_t mask, double cutoff, MatchOut O) {
+                                               const RT *__restrict__ qs, double cutoff, MatchOut O,
+                                               int32_t *__restrict__ todo, int32_t *__restrict__ todo_count) {
     __shared__ MatchShared M;
     load_templates(M, T);
     const int64_t p = blockIdx.x * (int64_t)MB + threadIdx.x;
     if (p >= n) return;
     const int32_t i = sid[p];
-    int32_t cid[NGRP];
-    uint64_t ord[NGRP];
-    for (int g = 0; g < NGRP; g++) {
-        cid[g] = code[(int64_t)g * n + p];
-        ord[g] = ords[(int64_t)g * n + p];
-    }
-    double m1 = INFINITY, m2 = INFINITY;
-    int arg_grp = -1, arg_c = -1;
-    const int64_t q0 = off[p], q1 = off[p + 1];
-    if (q1 <= cap) {
-        for (int64_t q = q0; q < q1; q++) {
-            double r = rr[q];
-            if (r < m1) {
-                m2 = m1;
-                m1 = r;
-                arg_grp = pairs[q].y >> 28;
-                arg_c = pairs[q].y & 0x0FFFFFFF;
-            } else if (r < m2) {
-                m2 = r;
-            }
-        }
-    }
-    bool fp64 = q1 > cap;
-    if (sizeof(RT) == 4 && !fp64 && arg_c >= 0) {
-        bool clear = (m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) && !(fabs(m1 - cutoff) <= RMSD_F32_BOUND);
-        fp64 = !clear;
-    }
-    if (fp64) {
-        m1 = m2 = INFINITY;
-        arg_grp = arg_c = -1;
-        if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-        if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-        if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+    double m1, m2;
+    int arg_grp, arg_c;
+    int64_t arg_q;
+    const int64_t q1 = off[p + 1];
+    pair_minimum(off[p], q1, cap, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
+    bool full = q1 > cap || (arg_c >= 0 && !(m2 > m1 + 1e-12));
+    if (sizeof(RT) == 4 && arg_c >= 0)
+        full = full || !(m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) || fabs(m1 - cutoff) <= RMSD_F32_BOUND;
+    if (full) {
+        todo[atomicAdd(todo_count, 1)] = (int32_t)p;
+        return;
     }
     if (arg_c < 0) {
         write_none(O, i);
         return;
     }
-    if (m2 <= m1 + 1e-12) {
-        // near tie: apply the full rule over every candidate
-        int wg = -1, wc = -1, wt = 99;
-        uint64_t wrep = ~0ull;
-        if (cid[0] >= 0) tie_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
-        if (cid[1] >= 0) tie_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
-        if (cid[2] >= 0) tie_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
-        if (wc >= 0) {
-            arg_grp = wg;
-            arg_c = wc;
+    const uint64_t ord = ords[(int64_t)arg_grp * n + p];
+    const RT *w = qs + 5 * arg_q;
+    if (arg_grp == 0) finish_stored<6, RT>(M, T, 0, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
+    else if (arg_grp == 1)
+        finish_stored<12, RT>(M, T, 1, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
+    else finish_stored<14, RT>(M, T, 2, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
+}
+
+// The atoms k_decide left: the minimum is recomputed in FP64 when the FP32
+// margins could not decide it or the pairs did not fit, the full tie rule is
+// applied to near ties, and the winner is finished in FP64 when the decision
+// was taken in FP64 (else in the working precision).  Grid-stride over todo.
+template <typename RT>
+__global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__restrict__ nbr_rel,
+                                                    const int32_t *__restrict__ nbr_id,
+                                                    const int32_t *__restrict__ sid,
+                                                    const int8_t *__restrict__ species, TablesView T,
+                                                    const int32_t *__restrict__ code,
+                                                    const uint64_t *__restrict__ ords,
+                                                    const int64_t *__restrict__ off, int64_t cap,
+                                                    const uint2 *__restrict__ pairs, const double *__restrict__ rr,
+                                                    uint32_t mask, double cutoff, MatchOut O,
+                                                    const int32_t *__restrict__ todo,
+                                                    const int32_t *__restrict__ todo_count) {
+    __shared__ MatchShared M;
+    load_templates(M, T);
+    const int64_t cnt = *todo_count;
+    for (int64_t w = blockIdx.x * (int64_t)MB + threadIdx.x; w < cnt; w += (int64_t)gridDim.x * MB) {
+        const int64_t p = todo[w];
+        const int32_t i = sid[p];
+        int32_t cid[NGRP];
+        uint64_t ord[NGRP];
+        for (int g = 0; g < NGRP; g++) {
+            cid[g] = code[(int64_t)g * n + p];
+            ord[g] = ords[(int64_t)g * n + p];
         }
-    }
-    if (fp64) {
-        if (arg_grp == 0) finish<6, double>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        else if (arg_grp == 1) finish<12, double>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        else finish<14, double>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-    } else {
-        if (arg_grp == 0) finish<6, RT>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        else if (arg_grp == 1) finish<12, RT>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        else finish<14, RT>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        double m1, m2;
+        int arg_grp, arg_c;
+        int64_t arg_q;
+        const int64_t q1 = off[p + 1];
+        pair_minimum(off[p], q1, cap, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
+        bool fp64 = q1 > cap;
+        if (sizeof(RT) == 4 && !fp64 && arg_c >= 0) {
+            bool clear = (m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) && !(fabs(m1 - cutoff) <= RMSD_F32_BOUND);
+            fp64 = !clear;
+        }
+        if (fp64) {
+            m1 = m2 = INFINITY;
+            arg_grp = arg_c = -1;
+            if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+            if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+            if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
+        }
+        if (arg_c < 0) {
+            write_none(O, i);
+            continue;
+        }
+        if (m2 <= m1 + 1e-12) {
+            // near tie: apply the full rule over every candidate
+            int wg = -1, wc = -1, wt = 99;
+            uint64_t wrep = ~0ull;
+            if (cid[0] >= 0) tie_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
+            if (cid[1] >= 0) tie_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
+            if (cid[2] >= 0) tie_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
+            if (wc >= 0) {
+                arg_grp = wg;
+                arg_c = wc;
+            }
+        }
+        if (fp64) {
+            if (arg_grp == 0) finish<6, double>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else if (arg_grp == 1) finish<12, double>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else finish<14, double>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        } else {
+            if (arg_grp == 0) finish<6, RT>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else if (arg_grp == 1) finish<12, RT>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else finish<14, RT>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        }
     }
 }
 
@@ -1362,18 +1620,11 @@ void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, co
                            (const int32_t *)nullptr);
     }
 }
-void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
-                 int32_t *code, uint64_t *ord, hipStream_t st) {
+void launch_topo(bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
+                 uint32_t need, int32_t *code, uint64_t *ord, hipStream_t st) {
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
-    if (f32) {
-        if (K == 6) hipLaunchKernelGGL((k_topo<6, float>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-        else if (K == 12) hipLaunchKernelGGL((k_topo<12, float>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-        else hipLaunchKernelGGL((k_topo<14, float>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-    } else {
-        if (K == 6) hipLaunchKernelGGL((k_topo<6, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-        else if (K == 12) hipLaunchKernelGGL((k_topo<12, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-        else hipLaunchKernelGGL((k_topo<14, double>), grid, block, 0, st, n, nbr_rel, nbr_id, T, code, ord);
-    }
+    if (f32) hipLaunchKernelGGL(k_topo<float>, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
+    else hipLaunchKernelGGL(k_topo<double>, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
 }
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
                  hipStream_t st) {
@@ -1388,21 +1639,30 @@ void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const ui
                  bool f32, hipStream_t st) {
     if (f32)
         hipLaunchKernelGGL(k_cand_eval<float>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs,
-                           W.r);
+                           W.r, (float *)W.qs);
     else
         hipLaunchKernelGGL(k_cand_eval<double>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap,
-                           W.pairs, W.r);
+                           W.pairs, W.r, (double *)W.qs);
 }
 void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
                    const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
-                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st) {
+                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
+                   int32_t *todo_count, bool f32, hipStream_t st) {
     dim3 gd((unsigned)((n + MB - 1) / MB));
-    if (f32)
+    dim3 gf((unsigned)std::min<int64_t>((n + MB - 1) / MB, 2048));
+    if (f32) {
         hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
-                           W.cap, W.pairs, W.r, mask, cutoff, O);
-    else
+                           W.cap, W.pairs, W.r, (const float *)W.qs, cutoff, O, todo, todo_count);
+        hipLaunchKernelGGL(k_decide_full<float>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
+                           W.off, W.cap, W.pairs, W.r, mask, cutoff, O, (const int32_t *)todo,
+                           (const int32_t *)todo_count);
+    } else {
         hipLaunchKernelGGL(k_decide<double>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
-                           W.off, W.cap, W.pairs, W.r, mask, cutoff, O);
+                           W.off, W.cap, W.pairs, W.r, (const double *)W.qs, cutoff, O, todo, todo_count);
+        hipLaunchKernelGGL(k_decide_full<double>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code,
+                           ord, W.off, W.cap, W.pairs, W.r, mask, cutoff, O, (const int32_t *)todo,
+                           (const int32_t *)todo_count);
+    }
 }
 
 }  // namespace ptm

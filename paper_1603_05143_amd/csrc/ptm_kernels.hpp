@@ -36,6 +36,7 @@ struct MatchScratch {
     int64_t *off;        // [n+1] exclusive prefix sum (off[n] = total)
     uint2 *pairs;        // [cap] (atom, group << 28 | candidate)
     double *r;           // [cap] RMSD of each pair
+    void *qs;            // [cap][5] quaternion and scale of each pair, working precision
     int64_t cap;         // pair capacity
     void *scan_tmp;
     size_t scan_tmp_bytes;
@@ -52,15 +53,20 @@ bool knn_fast_applies(const Grid &g);
 void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz, const int32_t *sid,
                 const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out, int32_t *todo,
                 int32_t *todo_count, hipStream_t st);
-void launch_topo(int K, bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, int32_t *code,
-                 uint64_t *ord, hipStream_t st);
+// hulls of the first 6 / 12 / 14 neighbours (need: bit g for group g);
+// code ids and labellings into code / ord [group][n]
+void launch_topo(bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
+                 uint32_t need, int32_t *code, uint64_t *ord, hipStream_t st);
 // match stage: candidate pair list, superposition of every pair, decision
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
                  hipStream_t st);
 void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
                  bool f32, hipStream_t st);
+// decision: common atoms, then those left in todo / *todo_count (zeroed by
+// the caller) by the full rule
 void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
                    const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
-                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, bool f32, hipStream_t st);
+                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
+                   int32_t *todo_count, bool f32, hipStream_t st);
 
 }  // namespace ptm

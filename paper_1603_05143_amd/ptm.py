@@ -19,7 +19,7 @@ PTM_SC, PTM_FCC, PTM_HCP, PTM_ICO, PTM_BCC = 1, 2, 4, 8, 16
 PTM_ALL = 0x1F
 PTM_F_HOST_POINTERS = 1
 PTM_F_PROFILE = 2
-STAGE_NAMES = ("bounds", "bin", "knn", "topo6", "topo12", "topo14", "cand", "eval", "decide")
+STAGE_NAMES = ("bounds", "bin", "knn", "topo", "cand", "eval", "decide")
 TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
 ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")
 
@@ -132,7 +132,7 @@ def ptm_stage_times(ctx):
     return dict(zip(STAGE_NAMES, list(ms)))
 
 
-INFO_NAMES = ("cells", "knn_exact", "pairs")
+INFO_NAMES = ("cells", "knn_exact", "pairs", "decide_full")
 
 
 def ptm_frame_info(ctx):
