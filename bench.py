@@ -291,7 +291,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     import torch  # (loads the HIP runtime shared with libptm)
     from paper_1603_05143_amd import ptm

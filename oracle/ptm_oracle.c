@@ -33,7 +33,8 @@
  *   alloy       -- Table 3 (FCC coplanar groups) and the A1/A2/B2 rules of
  *                  Sec. 6.
  *
- * Readings where the paper is silent are listed in DESIGN.md ("readings").
+ * Where the paper is silent, the reading taken is stated at the function
+ * that depends on it.
  */
 #include <math.h>
 #include <pthread.h>
@@ -442,7 +443,10 @@ static templ_t g_T[NTEMPL];
 static pthread_once_t g_once = PTHREAD_ONCE_INIT;
 static int g_init_ok = 0;
 
-/* vertex numbering fixed by the output convention */
+/* Template vertices in the order that numbers the ordered-neighbour output:
+ * SC +-x, +-y, +-z; FCC the z=0, y=0, x=0 coplanar groups; HCP the basal
+ * hexagon then the upper and lower triangles; ICO the cyclic (0, +-1, +-phi)
+ * family; BCC the 8 cube corners then the 6 second neighbours. */
 static void template_coords(int t, double w[KMAX][3]) {
     int k = TEMPL_K[t];
     memset(w, 0, sizeof(double) * KMAX * 3);

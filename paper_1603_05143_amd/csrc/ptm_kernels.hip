@@ -1438,9 +1438,13 @@ __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__res
 }
 
 // Bound on |RMSD_FP32 - RMSD_FP64| of one candidate evaluated in FP32 from
-// FP64-centred points (derivation in the design notes: input rounding and
-// residual arithmetic contribute ~5e-7; the rotation error enters at second
-// order).  Decisions whose FP32 margins are below it are redone in FP64.
+// FP64-centred points.  The residual terms s a - R b are O(1) after the
+// normalisation of eq.(4); rounding the inputs and the residual arithmetic
+// to FP32 moves them by a few 2^-24, i.e. the RMSD by ~5e-7, while the
+// rotation and scale errors of the FP32 solve enter only at second order
+// (the RMSD is stationary in both at the optimum).  The bound keeps a factor
+// of eight over that estimate; decisions whose FP32 margins are below it
+// are redone in FP64.
 constexpr double RMSD_F32_BOUND = 4e-6;
 
 // Minimum over an atom's evaluated pairs: best and second-best RMSD and the

@@ -12,8 +12,10 @@ int8 (0 = majority "A" atom, 1 = minority "B" atom).
 
 The workloads stand in for the paper's benchmark systems (a quenched
 Cu-precipitate-in-Fe sample and a 2.8 M-atom Cu3Pt polycrystal, Sec. 5),
-which are not available; sizes, densities and lattice types follow the
-configurations listed in the design doc.
+which are not available: a ~0.92 M-atom periodic polycrystal of FCC, BCC
+and HCP grains, a ~4 M-atom box of ordered-alloy slabs with species, a
+stream of polycrystal frames of uneven size, and small perfect or noisy
+crystals and clusters for tests.
 """
 from __future__ import annotations
 
