@@ -412,3 +412,152 @@ def subsample_box(frame: Frame, frac: float, seed: int = 0) -> Frame:
     m = np.all(frame.positions < cut, axis=1)
     return Frame(positions=frame.positions[m].copy(), box=np.zeros(3),
                  species=None if frame.species is None else frame.species[m].copy())
+
+
+def _rsa_tile(dims, dmin: float, rng: np.random.Generator,
+              rounds=(0.15, 0.3, 0.6, 1.0, 2.0, 3.0, 5.0)) -> np.ndarray:
+    """Random sequential adsorption in a periodic box: points arrive as
+    Poisson batches of the given densities (per A^3); a point is kept iff it
+    lies at least ``dmin`` from every point kept before it (arrival order is
+    a uniform random priority within each batch)."""
+    from scipy.spatial import cKDTree
+
+    dims = np.asarray(dims, dtype=np.float64)
+    vol = float(np.prod(dims))
+    pts = np.zeros((0, 3))
+    for rho in rounds:
+        p = rng.random((int(rng.poisson(rho * vol)), 3)) * dims
+        if len(pts):
+            d, _ = cKDTree(pts, boxsize=dims).query(p, distance_upper_bound=dmin)
+            p = p[~np.isfinite(d)]
+        if not len(p):
+            continue
+        pairs = cKDTree(p, boxsize=dims).query_pairs(dmin, output_type="ndarray")
+        prio = rng.random(len(p))
+        alive = np.ones(len(p), bool)
+        keep = np.zeros(len(p), bool)
+        a_, b_ = (pairs[:, 0], pairs[:, 1]) if len(pairs) else (np.zeros(0, int), np.zeros(0, int))
+        # the points kept by sequential arrival in priority order: repeatedly
+        # keep every live point that arrives before all its live neighbours
+        while alive.any():
+            live = alive[a_] & alive[b_]
+            aa, bb = a_[live], b_[live]
+            first = alive.copy()
+            first[np.where(prio[aa] < prio[bb], bb, aa)] = False
+            keep |= first
+            alive &= ~first
+            alive[np.concatenate([bb[first[aa]], aa[first[bb]]])] = False
+        pts = np.concatenate([pts, p[keep]])
+    return pts
+
+
+def mixed_frame(n_cells: int = 256, a_bcc: float = 2.87, vacancy: float = 0.01, n_ico: int = 200,
+                ico_nn: float = 2.55, n_sc: int = 10, a_sc: float = 2.6, sc_edge: float = 40.0,
+                clearance: float = 1.2, slab_frac: float = 0.15, rsa_dmin: float = 2.2,
+                sigma: float = 0.15, seed: int | None = None) -> Frame:
+    """The ~32 M-atom mixed frame: a periodic BCC matrix (a = 2.87 A, L =
+    n_cells a, ``vacancy`` of the sites removed) holding ``n_ico`` Mackay
+    icosahedra (half of 55 atoms, half of 147; first-shell radius ``ico_nn``;
+    random orientations), ``n_sc`` simple-cubic cubes (a = 2.6 A, edge ~40 A,
+    random orientations) and a slab of ``slab_frac`` of the volume (all y, z)
+    filled by random sequential adsorption with minimum distance ``rsa_dmin``
+    (liquid-like; jammed near 0.06 per A^3).  Inclusions replace the matrix
+    inside their outer radius (cubes: their extent) plus ``clearance``; of
+    each pair closer than ``clearance`` across a slab face the slab atom is
+    removed.  The slab is tiled from one periodic adsorption block of 1/288
+    of its volume.  Gaussian noise ``sigma`` is added last.  labels["kind"]:
+    0 matrix, 1 icosahedron, 2 simple cubic, 3 slab.
+    """
+    from scipy.spatial import cKDTree
+
+    seed = BASE_SEED + 4 if seed is None else seed
+    rng = rng_for(seed)
+    n, a = n_cells, a_bcc
+    L = n * a
+    box = np.array([L, L, L])
+    w = slab_frac * L  # slab: x in [0, w)
+    # inclusions: centres outside the slab, no two closer than their radii + 2 clearances
+    ico_shells = np.array([2] * (n_ico // 2) + [3] * (n_ico - n_ico // 2))
+    m_side = int(round(sc_edge / a_sc))  # cells per cube edge (m_side + 1 points)
+    half = 0.5 * m_side * a_sc
+    radii = np.concatenate([ico_shells * ico_nn, np.full(n_sc, half * math.sqrt(3.0))])
+    kinds = np.concatenate([np.ones(n_ico, int), np.full(n_sc, 2)])
+    order = np.argsort(-radii, kind="stable")
+    centres = np.zeros((len(radii), 3))
+    placed = []
+    for idx in order:
+        r = radii[idx] + clearance
+        for _ in range(10000):
+            c = np.array([w + r + rng.random() * (L - w - 2 * r), rng.random() * L, rng.random() * L])
+            ok = True
+            for j in placed:
+                d = _min_image(c - centres[j], box)
+                if np.linalg.norm(d) < r + radii[j] + 3 * clearance:
+                    ok = False
+                    break
+            if ok:
+                break
+        centres[idx] = c
+        placed.append(idx)
+    rots = random_rotations(rng, len(radii))
+
+    # matrix: BCC site (s, i, j, k) at a (i, j, k) + a s (1/2, 1/2, 1/2)
+    keep = rng.random(2 * n * n * n) >= vacancy
+    keep = keep.reshape(2, n, n, n)
+    lo_cell = int(math.ceil(w / a))  # cells with x >= w: sublattice 0 from i = lo_cell
+    keep[0, :lo_cell] = False
+    keep[1, :int(math.ceil(w / a - 0.5))] = False
+    inc_pos, inc_kind = [], []
+    for idx in range(len(radii)):
+        c, R = centres[idx], rots[idx]
+        if kinds[idx] == 1:
+            pts = mackay_icosahedron(int(ico_shells[idx]), ico_nn) @ R.T
+            rad = ico_shells[idx] * ico_nn + clearance
+        else:
+            g = np.arange(m_side + 1) * a_sc - half
+            pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) @ R.T
+            rad = half * math.sqrt(3.0) + clearance
+        inc_pos.append(pts + c)
+        inc_kind.append(np.full(len(pts), kinds[idx], np.int8))
+        # matrix sites near the centre (periodic index window)
+        for s in (0, 1):
+            lo = np.floor((c - rad) / a - 0.5 * s).astype(int)
+            hi = np.ceil((c + rad) / a - 0.5 * s).astype(int)
+            ii = [np.arange(lo[d], hi[d] + 1) for d in range(3)]
+            I, J, K = np.meshgrid(*ii, indexing="ij")
+            sp = (np.stack([I, J, K], -1) + 0.5 * s) * a - c
+            sp = _min_image(sp, box)
+            if kinds[idx] == 1:
+                inside = np.einsum("...d,...d->...", sp, sp) <= rad * rad
+            else:
+                loc = sp @ R  # cube frame
+                inside = np.all(np.abs(loc) <= half + clearance, axis=-1)
+            keep[s, I[inside] % n, J[inside] % n, K[inside] % n] = False
+    s_idx, i_idx, j_idx, k_idx = np.nonzero(keep)
+    del keep
+    mat = (np.stack([i_idx, j_idx, k_idx], -1).astype(np.float64) + 0.5 * s_idx[:, None]) * a
+    del s_idx, i_idx, j_idx, k_idx
+
+    # slab: one periodic adsorption block tiled 2 x 12 x 12
+    tiles = (2, 12, 12)
+    tdims = np.array([w / tiles[0], L / tiles[1], L / tiles[2]])
+    tile = _rsa_tile(tdims, rsa_dmin, rng)
+    off = np.stack(np.meshgrid(*[np.arange(t) for t in tiles], indexing="ij"), -1).reshape(-1, 1, 3) * tdims
+    slab = (tile[None] + off).reshape(-1, 3)
+    # slab atoms too close to the matrix across the two slab faces
+    near_m = mat[(mat[:, 0] < w + 2 * clearance) | (mat[:, 0] > L - 2 * clearance)]
+    near_s = (slab[:, 0] < 2 * clearance) | (slab[:, 0] > w - 2 * clearance)
+    if len(near_m) and near_s.any():
+        d, _ = cKDTree(near_m, boxsize=L).query(wrap(slab[near_s], box), distance_upper_bound=clearance)
+        drop = np.zeros(len(slab), bool)
+        drop[np.nonzero(near_s)[0][np.isfinite(d)]] = True
+        slab = slab[~drop]
+
+    pos = np.concatenate([mat, np.concatenate(inc_pos), slab])
+    kind = np.concatenate([np.zeros(len(mat), np.int8), np.concatenate(inc_kind),
+                           np.full(len(slab), 3, np.int8)])
+    del mat
+    pos += rng.normal(0.0, sigma, size=pos.shape)
+    return Frame(positions=wrap(pos, box), box=box,
+                 labels={"kind": kind, "centres": centres, "inclusion_kind": kinds,
+                         "slab_density": len(slab) / (w * L * L)})

@@ -1,0 +1,106 @@
+"""GPU parity at full size on the two large workloads, through the C ABI:
+the ~4 M-atom ordered-alloy slabs (with species) and the ~32 M-atom mixed
+frame (BCC matrix, Mackay icosahedra, simple-cubic cubes, adsorbed liquid
+slab).  The whole frame runs on the GPU in the launch configuration the
+benchmark uses; a seeded sample of atoms -- uniform plus every kind of
+region -- is recomputed one by one by the FP64 oracle (brute-force
+neighbours over all atoms).  Decisions bit-exact, reals within the form's
+tolerance."""
+import numpy as np
+import pytest
+
+from paper_1603_05143_amd import ptm, synthetic as S
+from parity_util import TOL32, TOL64, compare
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn")
+_oracle_cache = {}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu_sample(torch, precision, f, atoms):
+    """Classify the whole frame on the GPU; return the outputs of the sample."""
+    print(f"[full] n={f.n} precision={precision} sample={len(atoms)}", flush=True)
+    c = ptm.Classifier(device=0, precision=precision)
+    try:
+        pos = torch.from_numpy(np.ascontiguousarray(f.positions)).to("cuda:0")
+        sp = None if f.species is None else torch.from_numpy(f.species).to("cuda:0")
+        out = c.classify(pos, f.box, species=sp, knn=True)
+        idx = torch.from_numpy(np.asarray(atoms, dtype=np.int64)).to("cuda:0")
+        res = {k: out[k].index_select(0, idx).cpu().numpy() for k in FIELDS}
+        types = torch.bincount(out["type"].long(), minlength=6).cpu().numpy()
+        del out, pos, sp
+        torch.cuda.synchronize()
+    finally:
+        c.close()
+    return res, types
+
+
+def _oracle(oracle_lib, key, f, atoms):
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle_lib.classify(f.positions, f.box, species=f.species, atoms=atoms)
+    return _oracle_cache[key]
+
+
+@pytest.fixture(scope="module")
+def alloy_frame():
+    f = S.alloy_slabs()
+    rng = np.random.default_rng(11)
+    slab = f.labels["slab"]
+    picks = [rng.choice(f.n, 1000, replace=False)]
+    for s in range(4):  # every slab, whatever its share
+        picks.append(rng.choice(np.nonzero(slab == s)[0], 150, replace=False))
+    return f, np.unique(np.concatenate(picks))
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    f = S.mixed_frame()
+    rng = np.random.default_rng(12)
+    kind = f.labels["kind"]
+    # inclusions follow the matrix, one after another: the icosahedra (first
+    # half 55 atoms, second half 147), then the cubes; each cluster starts
+    # with its centre atom
+    n_ico = int(np.sum(f.labels["inclusion_kind"] == 1))
+    sizes = np.array([55] * (n_ico // 2) + [147] * (n_ico - n_ico // 2))
+    centres = int(np.nonzero(kind == 1)[0][0]) + np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    assert np.all(kind[centres] == 1)
+    picks = [rng.choice(f.n, 600, replace=False), centres]
+    for k in (1, 2, 3):
+        picks.append(rng.choice(np.nonzero(kind == k)[0], 150, replace=False))
+    return f, np.unique(np.concatenate(picks)), centres
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_alloy_slabs_full_sampled(torch_cuda, oracle_lib, alloy_frame, precision):
+    f, atoms = alloy_frame
+    got, types = _gpu_sample(torch_cuda, precision, f, atoms)
+    ref = _oracle(oracle_lib, "alloy", f, atoms)
+    tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
+    st = compare(got, ref, tol=tol, label="alloy-slabs ")
+    # the slabs hold L1_0, both L1_2 sites and B2: each class occurs in the sample
+    assert set(np.unique(ref["alloy"])) >= {2, 3, 4, 7}, np.unique(ref["alloy"])
+    print("alloy slabs", f.n, types.tolist(), st)
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_mixed_frame_full_sampled(torch_cuda, oracle_lib, mixed, precision):
+    f, atoms, centres = mixed
+    got, types = _gpu_sample(torch_cuda, precision, f, atoms)
+    ref = _oracle(oracle_lib, "mixed", f, atoms)
+    tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
+    st = compare(got, ref, tol=tol, check_alloy=False, label="mixed ")
+    # every structure of the frame is found: BCC matrix, SC cubes,
+    # icosahedral centres, and disorder in the slab
+    kind = f.labels["kind"]
+    assert types[5] > 0.7 * np.sum(kind == 0) and types[1] > 0 and types[4] > 0 and types[0] > 0, types
+    at_centres = ref["type"][np.searchsorted(atoms, centres)]
+    assert np.mean(at_centres == 4) > 0.9, np.bincount(at_centres, minlength=6)
+    print("mixed frame", f.n, types.tolist(), st)
