@@ -269,13 +269,24 @@ constexpr int KNN_FAST_LIST = KMAX + 1;  // the 15th entry certifies the boundar
 // and the exact 14th distance is certified by the block.  Other atoms are
 // appended to a list for k_knn_exact.  Requires every periodic axis to have
 // at least 5 cells (no axis wraps onto itself within the block).
+// Workgroups are dispatched to the 8 XCDs round-robin, and each XCD has its
+// own L2.  With a grid padded to a multiple of 8, this bijection gives every
+// XCD one contiguous range of blocks, so that blocks sharing cells (and
+// their atoms) run behind the same L2.
+constexpr int NXCD = 8;
+__device__ inline int64_t xcd_block(int64_t i, int64_t nblocks_padded) {
+    const int64_t per = nblocks_padded / NXCD;
+    return (i % NXCD) * per + i / NXCD;
+}
+inline int64_t xcd_pad(int64_t nblocks) { return (nblocks + NXCD - 1) / NXCD * NXCD; }
+
 __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ sx,
                                                   const double *__restrict__ sy, const double *__restrict__ sz,
                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                                   int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                                   int32_t *__restrict__ knn_out, int32_t *__restrict__ todo,
                                                   int32_t *__restrict__ todo_count) {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
     constexpr int KN = KNN_FAST_LIST;
     const double xi = sx[p], yi = sy[p], zi = sz[p];
@@ -1077,14 +1088,21 @@ __device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t
 
 // observed points of one hull group: centre (row 0) and the innermost K
 // neighbours, minus their barycentre (eq. 2); Ga = sum of squared norms
-template <int K, typename T>
+template <int K, typename T, bool OnePass = false>
 __device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t n, int64_t p, T (&a)[NMAX][3],
                                     T &Ga) {
-    // two passes over the (cached) neighbour vectors: the barycentre, then
-    // the centred points, so that the FP64 inputs are never all held at once
+    // OnePass: every FP64 input loaded at once (more loads in flight, more
+    // registers); otherwise two passes over the (cached) neighbour vectors,
+    // the barycentre and then the centred points.  Same arithmetic either way.
+    double v[OnePass ? KMAX : 1][3];
     double c[3] = {0, 0, 0};
+#pragma unroll
     for (int r = 0; r < K; r++)
-        for (int d = 0; d < 3; d++) c[d] += nbr_rel[((int64_t)r * 3 + d) * n + p];
+        for (int d = 0; d < 3; d++) {
+            double x = nbr_rel[((int64_t)r * 3 + d) * n + p];
+            if constexpr (OnePass) v[r][d] = x;
+            c[d] += x;
+        }
     for (int d = 0; d < 3; d++) c[d] /= (K + 1);
     double g = 0;
     for (int d = 0; d < 3; d++) {
@@ -1094,7 +1112,9 @@ __device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t 
 #pragma unroll
     for (int r = 0; r < K; r++)
         for (int d = 0; d < 3; d++) {
-            double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d];
+            double x;
+            if constexpr (OnePass) x = v[r][d] - c[d];
+            else x = nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d];
             a[r + 1][d] = (T)x;
             g += x * x;
         }
@@ -1201,7 +1221,7 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
             for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = (double)(q[k] * sc);
     }
     if (O.neighbours) {
-#pragma unroll 1
+#pragma unroll
         for (int m = 0; m < KMAX; m++) {
             int32_t id = -1;
             if (m < K) {
@@ -1236,7 +1256,7 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
         if (species && type && (cd.tmpl == 1 || cd.tmpl == 4)) {
             const int8_t me = species[i];
             uint32_t cnt = 0;  // 8-bit counters: FCC groups 0..2, BCC inner/outer
-#pragma unroll 1
+#pragma unroll
             for (int r = 0; r < K; r++) {
                 int32_t j = nbr_id[(int64_t)r * n + p];
                 int other = species[j] != me;
@@ -1310,8 +1330,11 @@ __device__ inline void finish_stored(const MatchShared &M, const TablesView &T, 
     ev.r = (RT)r;
     for (int k = 0; k < 4; k++) ev.q[k] = qs[k];
     ev.s = qs[4];
+    // loads are issued K/2 ranks at a time: enough in flight to hide the
+    // memory latency without holding every point in registers
+    constexpr int HALF = K / 2;
     double cb[3] = {0, 0, 0};
-#pragma unroll 1
+#pragma unroll HALF
     for (int rr = 0; rr < K; rr++)
         for (int d = 0; d < 3; d++) cb[d] += nbr_rel[((int64_t)rr * 3 + d) * n + p];
     for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
@@ -1320,7 +1343,7 @@ __device__ inline void finish_stored(const MatchShared &M, const TablesView &T, 
     RT At[3][3];
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) At[x][y] = (RT)D.vpinv[x][0] * a0[y];
-#pragma unroll 1
+#pragma unroll HALF
     for (int rr = 0; rr < K; rr++) {
         RT ar[3];
         for (int d = 0; d < 3; d++) ar[d] = (RT)(nbr_rel[((int64_t)rr * 3 + d) * n + p] - cb[d]);
@@ -1412,13 +1435,13 @@ __global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__res
             // FP32 points fit in registers: load once, evaluate
             RT a[NMAX][3], Ga;
             if (g == 0) {
-                load_centred<6, RT>(nbr_rel, n, p, a, Ga);
+                load_centred<6, RT, true>(nbr_rel, n, p, a, Ga);
                 eval_candidate<6, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
             } else if (g == 1) {
-                load_centred<12, RT>(nbr_rel, n, p, a, Ga);
+                load_centred<12, RT, true>(nbr_rel, n, p, a, Ga);
                 eval_candidate<12, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
             } else {
-                load_centred<14, RT>(nbr_rel, n, p, a, Ga);
+                load_centred<14, RT, true>(nbr_rel, n, p, a, Ga);
                 eval_candidate<14, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
             }
         } else {
@@ -1612,8 +1635,8 @@ void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, co
                 int32_t *todo_count, hipStream_t st) {
     int64_t blocks = (n + 255) / 256;
     if (knn_fast_applies(g)) {
-        hipLaunchKernelGGL(k_knn_fast, dim3((unsigned)blocks), dim3(256), 0, st, n, g, sx, sy, sz, sid, start, nbr_id,
-                           nbr_rel, knn_out, todo, todo_count);
+        hipLaunchKernelGGL(k_knn_fast, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, sx, sy, sz, sid, start,
+                           nbr_id, nbr_rel, knn_out, todo, todo_count);
         // the atoms left over are few; 1024 blocks of four waves stride over them
         hipLaunchKernelGGL(k_knn_exact, dim3((unsigned)std::min<int64_t>(blocks, 1024)), dim3(256), 0, st, n, g, sx,
                            sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)todo,
