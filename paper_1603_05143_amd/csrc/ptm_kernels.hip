@@ -571,36 +571,27 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
 // code are built and looked up.  Per-lane state lives in LDS, lane-minor,
 // so dynamic indices never conflict across lanes.
 constexpr int TB = 64;  // threads per block of the topology kernel
-constexpr int NT_SNAP = 12;  // rotation-system rows kept beside the points
 
-// LDS of one block.  P: neighbour vectors (FP64 or FP32 words); F: facets;
-// H: the horizon of the current insertion, which shares its rows with the
-// rotation system of the 6- and 12-point hulls (built between insertions).
-// The rotation system of the last hull overlays P, which is then free.
+// LDS of one block.  P: neighbour vectors (FP64 or FP32); F: facets; H: the
+// horizon of the current insertion, which shares its space with the
+// rotation system of a finished hull (built between insertions).
 template <typename R>
 struct TopoShared {
-    union {
-        R P[3][KMAX][TB];
-        uint32_t PW[3 * KMAX * sizeof(R) / 4][TB];
-    };
+    R P[3][KMAX][TB];
     uint32_t F[2 * KMAX - 4][TB];
     union {
         uint16_t H[KMAX][TB];
-        uint32_t NW[2 * NT_SNAP][TB];
+        uint64_t NT[KMAX][TB];
     };
 };
 
 // A lane's rotation system: row x = 64-bit word whose nibble y is the
-// vertex after y counter-clockwise around x (0xF: not a neighbour), stored
-// as two 32-bit LDS words in the lane's column.
+// vertex after y counter-clockwise around x (0xF: not a neighbour).
 struct RotSys {
-    uint32_t (*w)[TB];
+    uint64_t (*w)[TB];
     int t;
-    __device__ uint64_t get(int x) const { return (uint64_t)w[2 * x][t] | ((uint64_t)w[2 * x + 1][t] << 32); }
-    __device__ void set(int x, uint64_t v) const {
-        w[2 * x][t] = (uint32_t)v;
-        w[2 * x + 1][t] = (uint32_t)(v >> 32);
-    }
+    __device__ uint64_t get(int x) const { return w[x][t]; }
+    __device__ void set(int x, uint64_t v) const { w[x][t] = v; }
 };
 
 // facet word: v0 | v1<<4 | v2<<8 | nb0<<12 | nb1<<17 | nb2<<22
@@ -790,26 +781,34 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
     for (int x = 0; x < K; x++) mdmask |= (uint32_t)(nib(degs, x) == (uint32_t)mindeg) << x;
     uint64_t minsig = ~0ull;
     int bu = 0, bv = 0;
+    // signature fields below the degree: mindeg nibbles from bit 56 down
+    const int low = 60 - 4 * mindeg;
+    const uint64_t field = (~0ull >> (4 + low)) << low;  // bits low .. 59
     for (uint32_t m = mdmask; m; m &= m - 1) {
         int u = __builtin_ctz(m);
         uint64_t ntu = NT.get(u);
-        int v0 = 0;
-        while (nib(ntu, v0) == 0xF) v0++;
-        uint64_t dg = 0;  // degrees of u's neighbours, counter-clockwise from v0
+        // lowest-numbered neighbour: first nibble of ntu that is not 0xF
+        uint64_t z = ~ntu;
+        z = (z | (z >> 1) | (z >> 2) | (z >> 3)) & 0x1111111111111111ull;
+        int v0 = __builtin_ctzll(z) >> 2;
+        // degrees of u's neighbours counter-clockwise from v0, first in the
+        // most significant field
+        uint64_t seq = 0;
         int w = v0;
         for (int j = 0; j < mindeg; j++) {
-            dg |= (uint64_t)nib(degs, w) << (4 * j);
+            seq |= (uint64_t)nib(degs, w) << (56 - 4 * j);
             w = (int)nib(ntu, w);
         }
         int v = v0;
         for (int r = 0; r < mindeg; r++, v = (int)nib(ntu, v)) {
-            uint64_t sig = (uint64_t)mindeg << 60;
-            for (int j = 0; j < mindeg; j++) sig |= (uint64_t)nib(dg, (r + j) % mindeg) << (56 - 4 * j);
+            uint64_t sig = ((uint64_t)mindeg << 60) | seq;
             if (sig < minsig) {
                 minsig = sig;
                 bu = u;
                 bv = v;
             }
+            // next start: rotate the sequence by one neighbour
+            seq = ((seq << 4) & field) | ((seq >> 56) << low);
         }
     }
     code[0] = minsig;
@@ -911,17 +910,16 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
             for (int d = 0; d < 3; d++) S.P[d][r][t] = (R)nbr_rel[((int64_t)r * 3 + d) * n + p];
         Lane<R> L{S, t, nbr_rel, n, p};
         lane_hull_start<R>(L);
-        const RotSys snap{S.NW, t}, last{S.PW, t};
+        const RotSys nt{S.NT, t};
         for (int q = 4; q < kl; q++) {
             if (!lane_insert<R>(L, q)) break;
             const int K = q + 1;
             if (K == 6 && (want & 1)) {
-                if (lane_centre_inside<R>(L, 6)) cid[0] = lane_lookup<6>(S.F, snap, T, ordw[0]);
+                if (lane_centre_inside<R>(L, 6)) cid[0] = lane_lookup<6>(S.F, nt, T, ordw[0]);
             } else if (K == 12 && (want & 2)) {
-                if (lane_centre_inside<R>(L, 12)) cid[1] = lane_lookup<12>(S.F, snap, T, ordw[1]);
+                if (lane_centre_inside<R>(L, 12)) cid[1] = lane_lookup<12>(S.F, nt, T, ordw[1]);
             } else if (K == 14) {
-                // last hull: its rotation system may overlay the points
-                if (lane_centre_inside<R>(L, 14)) cid[2] = lane_lookup<14>(S.F, last, T, ordw[2]);
+                if (lane_centre_inside<R>(L, 14)) cid[2] = lane_lookup<14>(S.F, nt, T, ordw[2]);
             }
         }
     }
