@@ -466,10 +466,16 @@ extern "C" {
 
 int ptm_selftest_orient(const double *p, const int32_t *r) {
     if (r[0] == r[1] || r[0] == r[2] || r[0] == r[3] || r[1] == r[2] || r[1] == r[3] || r[2] == r[3]) return 0;
-    return orient_sos64(p, p + 3, p + 6, p + 9, r[0], r[1], r[2], r[3]);
+    double m = 0;
+    for (int i = 0; i < 12; i++) m = fmax(m, fabs(p[i]));
+    return orient_sos64b(p, p + 3, p + 6, p + 9, r[0], r[1], r[2], r[3], f64_orient_bound(m));
 }
 
-int ptm_selftest_det3(const double *p) { return det3_sign64(p, p + 3, p + 6); }
+int ptm_selftest_det3(const double *p) {
+    double m = 0;
+    for (int i = 0; i < 9; i++) m = fmax(m, fabs(p[i]));
+    return det3_sign64b(p, p + 3, p + 6, f64_det3_bound(m));
+}
 
 int ptm_selftest_codes(int k, const int32_t *tris, int ntri, uint64_t *codes, int max_codes, int32_t *n_codes) {
     if (k < 4 || k > KMAX || ntri != 2 * k - 4) return -1;
@@ -541,14 +547,22 @@ int ptm_selftest_superpose(int N, const double *obs, const double *tpl, double *
 
 int ptm_selftest_orient_f32filter(const double *p) {
     float f[12];
-    for (int i = 0; i < 12; i++) f[i] = (float)p[i];
-    return orient_filter_f32in(f, f + 3, f + 6, f + 9);
+    float m = 0;
+    for (int i = 0; i < 12; i++) {
+        f[i] = (float)p[i];
+        m = fmaxf(m, fabsf(f[i]));
+    }
+    return orient_filter_f32in(f, f + 3, f + 6, f + 9, f32_orient_bound(m));
 }
 
 int ptm_selftest_det3_f32filter(const double *p) {
     float f[9];
-    for (int i = 0; i < 9; i++) f[i] = (float)p[i];
-    return det3_filter_f32in(f, f + 3, f + 6);
+    float m = 0;
+    for (int i = 0; i < 9; i++) {
+        f[i] = (float)p[i];
+        m = fmaxf(m, fabsf(f[i]));
+    }
+    return det3_filter_f32in(f, f + 3, f + 6, f32_det3_bound(m));
 }
 
 int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q) {

@@ -225,35 +225,72 @@ PTM_HD int det3_filter64(const double *a, const double *b, const double *c) {
     return 0;
 }
 
-// Filters on points stored in FP32 (each coordinate the FP32 rounding of the
-// exact FP64 input, |x32 - x64| <= 2^-24 |x64|).  The arithmetic runs in
-// FP64 on the widened values; the bound covers the input rounding -- three
-// rounded differences per term, each off by at most 2^-24 (|a| + |d|) --
-// i.e. 3.01 x 2^-24 x P, with P the permanent built from |a| + |d| sums,
-// plus the FP64 arithmetic (1e-15 x P).  A decided sign is therefore the
+// Static error bounds.  For a point set whose coordinates are at most m in
+// magnitude every entry of the difference matrix of an orientation test is
+// at most 2m, and a perturbation of at most e per entry moves each of the six
+// products of the 3x3 determinant by at most 3 (2m)^2 e (first order), so the
+// determinant by at most 18 (2m)^2 e; for det[a; b; c] on the raw points the
+// same argument gives 18 m^2 e.  The bounds below are fixed per atom (m = the
+// largest coordinate of its neighbour vectors), so a test costs the
+// determinant alone.  Tiny sets (bound below 1e-290) are never decided.
+//
+// FP32 storage: each coordinate x32 is the FP32 rounding of the exact FP64
+// input (|x32 - x| <= 2^-24 |x|, and m is taken from the x32 with a factor
+// 1 + 2^-22); the determinant is evaluated in FP64 on the widened values, so
+// e = 2^-24 (|a| + |d|) <= 2^-23 m plus the FP64 difference rounding, and the
+// FP64 evaluation adds < 1e-13 m^3: orient 144 m^3 (2^-24 + 2^-53) <= 8.6e-6
+// m^3 -> 8.7e-6 m^3; det3 18 m^3 2^-24 -> 1.1e-6 m^3.  A decided sign is the
 // exact sign of the predicate on the FP64 inputs.
-PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d) {
+PTM_HD double f32_orient_bound(double m) {
+    double M = m * (1.0 + 0x1p-22);
+    return fmax(8.7e-6 * M * M * M, 1e-290);
+}
+PTM_HD double f32_det3_bound(double m) {
+    double M = m * (1.0 + 0x1p-22);
+    return fmax(1.1e-6 * M * M * M, 1e-290);
+}
+// FP64 inputs: the rounding of the differences (e = 2^-53 2m) and 10 unit
+// roundoffs of the evaluation on a permanent of at most 6 (2m)^3 give
+// (144 + 480) 2^-53 m^3 = 6.9e-14 m^3 -> 7e-14 m^3; det3: 8 unit roundoffs
+// of at most 6 m^3 -> 5.4e-15 m^3.
+PTM_HD double f64_orient_bound(double m) { return fmax(7e-14 * m * m * m, 1e-290); }
+PTM_HD double f64_det3_bound(double m) { return fmax(5.4e-15 * m * m * m, 1e-290); }
+
+// det[b-a; c-a; d-a] sign from FP32 points widened to FP64 (evaluated as
+// -det[a-d; b-d; c-d]); 0 when |det| <= bound.
+PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d, double bound) {
     double adx = (double)a[0] - d[0], ady = (double)a[1] - d[1], adz = (double)a[2] - d[2];
     double bdx = (double)b[0] - d[0], bdy = (double)b[1] - d[1], bdz = (double)b[2] - d[2];
     double cdx = (double)c[0] - d[0], cdy = (double)c[1] - d[1], cdz = (double)c[2] - d[2];
-    double sdx = fabs((double)d[0]), sdy = fabs((double)d[1]), sdz = fabs((double)d[2]);
-    double sax = fabs((double)a[0]) + sdx, say = fabs((double)a[1]) + sdy, saz = fabs((double)a[2]) + sdz;
-    double sbx = fabs((double)b[0]) + sdx, sby = fabs((double)b[1]) + sdy, sbz = fabs((double)b[2]) + sdz;
-    double scx = fabs((double)c[0]) + sdx, scy = fabs((double)c[1]) + sdy, scz = fabs((double)c[2]) + sdz;
     double det = adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
-    double P = saz * (sbx * scy + scx * sby) + sbz * (scx * say + sax * scy) + scz * (sax * sby + sbx * say);
-    double bound = 1.8e-7 * P;
     if (det > bound) return -1;
     if (det < -bound) return 1;
     return 0;
 }
 
-PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c) {
+PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c, double bound) {
     double ax = a[0], ay = a[1], az = a[2], bx = b[0], by = b[1], bz = b[2], cx = c[0], cy = c[1], cz = c[2];
-    double m1 = by * cz, m2 = bz * cy, m3 = bz * cx, m4 = bx * cz, m5 = bx * cy, m6 = by * cx;
-    double det = ax * (m1 - m2) + ay * (m3 - m4) + az * (m5 - m6);
-    double P = fabs(ax) * (fabs(m1) + fabs(m2)) + fabs(ay) * (fabs(m3) + fabs(m4)) + fabs(az) * (fabs(m5) + fabs(m6));
-    double bound = 1.8e-7 * P;
+    double det = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+    if (det > bound) return 1;
+    if (det < -bound) return -1;
+    return 0;
+}
+
+// FP64 filters with a static bound (same evaluation as orient_filter64 /
+// det3_filter64, without the per-test permanent)
+PTM_HD int orient_filter64b(const double *a, const double *b, const double *c, const double *d, double bound) {
+    double adx = a[0] - d[0], ady = a[1] - d[1], adz = a[2] - d[2];
+    double bdx = b[0] - d[0], bdy = b[1] - d[1], bdz = b[2] - d[2];
+    double cdx = c[0] - d[0], cdy = c[1] - d[1], cdz = c[2] - d[2];
+    double det = adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
+    if (det > bound) return -1;
+    if (det < -bound) return 1;
+    return 0;
+}
+
+PTM_HD int det3_filter64b(const double *a, const double *b, const double *c, double bound) {
+    double det = a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+                 a[2] * (b[0] * c[1] - b[1] * c[0]);
     if (det > bound) return 1;
     if (det < -bound) return -1;
     return 0;
@@ -278,6 +315,20 @@ PTM_HD int orient_sos64(const double *a, const double *b, const double *c, const
 
 PTM_HD int det3_sign64(const double *a, const double *b, const double *c) {
     int s = det3_filter64(a, b, c);
+    if (s) return s;
+    return det3_sign_exact(a, b, c);
+}
+
+// the same with a static filter bound (f64_orient_bound / f64_det3_bound)
+PTM_HD int orient_sos64b(const double *a, const double *b, const double *c, const double *d, int ra, int rb,
+                         int rc, int rd, double bound) {
+    int s = orient_filter64b(a, b, c, d, bound);
+    if (s) return s;
+    return orient_exact_sos(a, b, c, d, ra, rb, rc, rd);
+}
+
+PTM_HD int det3_sign64b(const double *a, const double *b, const double *c, double bound) {
+    int s = det3_filter64b(a, b, c, bound);
     if (s) return s;
     return det3_sign_exact(a, b, c);
 }

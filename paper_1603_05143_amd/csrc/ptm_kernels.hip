@@ -607,13 +607,16 @@ __device__ inline uint32_t fset_nb(uint32_t f, int e, int g) {
 }
 
 // Per-lane view of the hull inputs: LDS points plus the FP64 originals in
-// global memory (used when an FP32 filter cannot decide).
+// global memory (used when an FP32 filter cannot decide), and the static
+// filter bounds of the atom (from its largest neighbour coordinate).
 template <typename R>
 struct Lane {
     TopoShared<R> &S;
     int t;
     const double *__restrict__ rel;
     int64_t n, p;
+    double bo, bd;        // filter bounds of orient and det3 in the working form
+    double bo64, bd64;    // FP64 filter bounds (FP32 form's fallback)
     __device__ void load64(int r, double (&x)[3]) const {
         for (int d = 0; d < 3; d++) x[d] = rel[((int64_t)r * 3 + d) * n + p];
     }
@@ -630,16 +633,16 @@ __device__ inline int lane_orient(const Lane<R> &L, int a, int b, int c, const R
     L.load(b, pb);
     L.load(c, pc);
     if constexpr (sizeof(R) == 8) {
-        return orient_sos64(pa, pb, pc, pq, a, b, c, q);
+        return orient_sos64b(pa, pb, pc, pq, a, b, c, q, L.bo);
     } else {
-        int s = orient_filter_f32in(pa, pb, pc, pq);
+        int s = orient_filter_f32in(pa, pb, pc, pq, L.bo);
         if (s) return s;
         double da[3], db[3], dc[3], dq[3];
         L.load64(a, da);
         L.load64(b, db);
         L.load64(c, dc);
         L.load64(q, dq);
-        return orient_sos64(da, db, dc, dq, a, b, c, q);
+        return orient_sos64b(da, db, dc, dq, a, b, c, q, L.bo64);
     }
 }
 
@@ -650,15 +653,15 @@ __device__ inline int lane_det3(const Lane<R> &L, int a, int b, int c) {
     L.load(b, pb);
     L.load(c, pc);
     if constexpr (sizeof(R) == 8) {
-        return det3_sign64(pa, pb, pc);
+        return det3_sign64b(pa, pb, pc, L.bd);
     } else {
-        int s = det3_filter_f32in(pa, pb, pc);
+        int s = det3_filter_f32in(pa, pb, pc, L.bd);
         if (s) return s;
         double da[3], db[3], dc[3];
         L.load64(a, da);
         L.load64(b, db);
         L.load64(c, dc);
-        return det3_sign64(da, db, dc);
+        return det3_sign64b(da, db, dc, L.bd64);
     }
 }
 
@@ -906,9 +909,23 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
     uint64_t ordw[NGRP] = {0, 0, 0};
     if (want) {
         const int kl = (want & 4) ? 14 : ((want & 2) ? 12 : 6);  // last point to insert
+        double m64 = 0;  // largest coordinate (FP64) and of its stored form
+        float m32 = 0;
         for (int r = 0; r < kl; r++)
-            for (int d = 0; d < 3; d++) S.P[d][r][t] = (R)nbr_rel[((int64_t)r * 3 + d) * n + p];
-        Lane<R> L{S, t, nbr_rel, n, p};
+            for (int d = 0; d < 3; d++) {
+                double x = nbr_rel[((int64_t)r * 3 + d) * n + p];
+                S.P[d][r][t] = (R)x;
+                m64 = fmax(m64, fabs(x));
+                m32 = fmaxf(m32, fabsf((float)x));
+            }
+        Lane<R> L{S, t, nbr_rel, n, p, 0, 0, f64_orient_bound(m64), f64_det3_bound(m64)};
+        if constexpr (sizeof(R) == 8) {
+            L.bo = L.bo64;
+            L.bd = L.bd64;
+        } else {
+            L.bo = f32_orient_bound(m32);
+            L.bd = f32_det3_bound(m32);
+        }
         lane_hull_start<R>(L);
         const RotSys nt{S.NT, t};
         for (int q = 4; q < kl; q++) {
