@@ -586,11 +586,12 @@ struct TopoShared {
 };
 
 // A lane's rotation system: row x = 64-bit word whose nibble y is the
-// vertex after y counter-clockwise around x (0xF: not a neighbour).
+// vertex after y counter-clockwise around x (0xF: not a neighbour), kept in
+// LDS complemented.
 struct RotSys {
     uint64_t (*w)[TB];
     int t;
-    __device__ uint64_t get(int x) const { return w[x][t]; }
+    __device__ uint64_t get(int x) const { return ~w[x][t]; }  // rows are stored complemented
     __device__ void set(int x, uint64_t v) const { w[x][t] = v; }
 };
 
@@ -702,8 +703,8 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
     if (nvis == 0) return 0;  // p inside: never a vertex
     // horizon edges (a -> b) of visible facets whose neighbour is not visible
     int nh = 0;
-    for (int f = 0; f < nf; f++) {
-        if (!((vis >> f) & 1)) continue;
+    for (uint32_t vm = vis; vm; vm &= vm - 1) {  // visible facets only
+        const int f = __builtin_ctz(vm);
         uint32_t w = S.F[f][t];
         for (int e = 0; e < 3; e++) {
             int g = fn(w, e);
@@ -857,14 +858,17 @@ template <int K>
 __device__ int32_t lane_lookup(const uint32_t (*F)[TB], const RotSys &NT, const TablesView &T, uint64_t &ordw) {
     constexpr int grp = (K == 6) ? 0 : (K == 12 ? 1 : 2);
     const int t = NT.t;
+    // rows are built complemented (0 = no neighbour) by LDS atomic ORs, so
+    // the 3 (2K - 4) updates need no read-modify-write round trips; every
+    // (x, y) nibble is written once
     uint64_t degs = 0;
-    for (int x = 0; x < K; x++) NT.set(x, ~0ull);
+    for (int x = 0; x < K; x++) NT.w[x][t] = 0;
     for (int f = 0; f < 2 * K - 4; f++) {
         uint32_t w = F[f][t];
         int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
-        NT.set(a, setnib(NT.get(a), b, c));
-        NT.set(b, setnib(NT.get(b), c, a));
-        NT.set(c, setnib(NT.get(c), a, b));
+        atomicOr((unsigned long long *)&NT.w[a][t], (unsigned long long)(c ^ 0xF) << (4 * b));
+        atomicOr((unsigned long long *)&NT.w[b][t], (unsigned long long)(a ^ 0xF) << (4 * c));
+        atomicOr((unsigned long long *)&NT.w[c][t], (unsigned long long)(b ^ 0xF) << (4 * a));
         degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
     }
     uint64_t best[K];
