@@ -580,7 +580,7 @@ struct TopoShared {
     R P[3][KMAX][TB];
     uint32_t F[2 * KMAX - 4][TB];
     union {
-        uint16_t H[KMAX][TB];
+        uint32_t H[KMAX][TB];
         uint64_t NT[KMAX][TB];
     };
 };
@@ -626,13 +626,10 @@ struct Lane {
     }
 };
 
-// orientation of facet (a,b,c) against point q (held in registers)
+// orientation of facet (a,b,c), its points given, against point q
 template <typename R>
-__device__ inline int lane_orient(const Lane<R> &L, int a, int b, int c, const R (&pq)[3], int q) {
-    R pa[3], pb[3], pc[3];
-    L.load(a, pa);
-    L.load(b, pb);
-    L.load(c, pc);
+__device__ inline int lane_orient_pts(const Lane<R> &L, int a, int b, int c, const R (&pa)[3], const R (&pb)[3],
+                                      const R (&pc)[3], const R (&pq)[3], int q) {
     if constexpr (sizeof(R) == 8) {
         return orient_sos64b(pa, pb, pc, pq, a, b, c, q, L.bo);
     } else {
@@ -645,6 +642,16 @@ __device__ inline int lane_orient(const Lane<R> &L, int a, int b, int c, const R
         L.load64(q, dq);
         return orient_sos64b(da, db, dc, dq, a, b, c, q, L.bo64);
     }
+}
+
+// orientation of facet (a,b,c) against point q (held in registers)
+template <typename R>
+__device__ inline int lane_orient(const Lane<R> &L, int a, int b, int c, const R (&pq)[3], int q) {
+    R pa[3], pb[3], pc[3];
+    L.load(a, pa);
+    L.load(b, pb);
+    L.load(c, pc);
+    return lane_orient_pts<R>(L, a, b, c, pa, pb, pc, pq, q);
 }
 
 template <typename R>
@@ -701,7 +708,9 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
         }
     }
     if (nvis == 0) return 0;  // p inside: never a vertex
-    // horizon edges (a -> b) of visible facets whose neighbour is not visible
+    // horizon edges (a -> b) of visible facets f whose neighbour g is not
+    // visible: entries a | b << 4 | g << 8 | f << 13 | eg << 18, eg = the
+    // index of the edge b -> a in g
     int nh = 0;
     for (uint32_t vm = vis; vm; vm &= vm - 1) {  // visible facets only
         const int f = __builtin_ctz(vm);
@@ -711,14 +720,20 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
             if (g >= nf) return 0;  // broken link (cannot happen with exact predicates)
             if ((vis >> g) & 1) continue;
             if (nh >= KMAX) return 0;
-            S.H[nh][t] = (uint16_t)(fv(w, e) | (fv(w, (e + 1) % 3) << 4) | (g << 8));
+            const int ha = fv(w, e), hb = fv(w, e == 2 ? 0 : e + 1);
+            const uint32_t gw = S.F[g][t];
+            const int eg = (fv(gw, 0) == hb) ? 0 : ((fv(gw, 1) == hb) ? 1 : 2);
+            S.H[nh][t] = (uint32_t)ha | ((uint32_t)hb << 4) | ((uint32_t)g << 8) | ((uint32_t)f << 13) |
+                         ((uint32_t)eg << 18);
             nh++;
         }
     }
     // a horizon of nvis+2 edges <=> no earlier vertex is swallowed
     if (nh != nvis + 2) return 0;
     // slots: freed visible facets first (increasing), then two new ones;
-    // pass 1 records vertex -> slot maps, pass 2 builds the facets
+    // pass 1 records vertex -> slot maps, pass 2 builds the facets and turns
+    // each neighbour's link from the visible facet to the new one (an XOR:
+    // every link changes at most once, so no read-modify-write is needed)
     uint64_t start_lo = 0, start_hi = 0, end_lo = 0, end_hi = 0;  // 8-bit fields
     uint32_t freed = vis;
     int nf_new = nf;
@@ -746,14 +761,11 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
             s = nf2++;
         }
         uint32_t hw = S.H[h][t];
-        int ha = hw & 0xF, hb = (hw >> 4) & 0xF, g = (hw >> 8) & 0x1F;
+        int ha = hw & 0xF, hb = (hw >> 4) & 0xF, g = (hw >> 8) & 0x1F, f = (hw >> 13) & 0x1F, eg = (hw >> 18) & 3;
         int s_next = (int)(((hb < 8 ? start_lo >> (8 * hb) : start_hi >> (8 * (hb - 8)))) & 0xFF);
         int s_prev = (int)(((ha < 8 ? end_lo >> (8 * ha) : end_hi >> (8 * (ha - 8)))) & 0xFF);
         S.F[s][t] = fpack(ha, hb, p, g, s_next, s_prev);
-        uint32_t gw = S.F[g][t];
-        for (int e = 0; e < 3; e++)
-            if (fv(gw, e) == hb && fv(gw, (e + 1) % 3) == ha) gw = fset_nb(gw, e, s);
-        S.F[g][t] = gw;
+        atomicXor(&S.F[g][t], (uint32_t)(f ^ s) << (12 + 5 * eg));
     }
     return 1;
 }
