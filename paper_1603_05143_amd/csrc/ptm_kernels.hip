@@ -1167,56 +1167,6 @@ __device__ inline uint64_t rank_of_tv(uint64_t perm, uint64_t ord, int k) {
     return c;
 }
 
-template <int K>
-__device__ inline void scan_group(const MatchShared &M, const TablesView &T, int grp, int32_t cid, uint64_t ord,
-                                  uint32_t mask, const double *__restrict__ nbr_rel, int64_t n, int64_t p, double &m1,
-                                  double &m2, int &arg_grp, int &arg_c) {
-    double a[NMAX][3], Ga;
-    load_centred<K, double>(nbr_rel, n, p, a, Ga);
-    int c0 = T.cstart[grp][cid], c1 = T.cstart[grp][cid + 1];
-    for (int c = c0; c < c1; c++) {
-        Candidate cd = T.cand[grp][c];
-        if (!((mask >> cd.tmpl) & 1)) continue;
-        CandEval<double> ev;
-        eval_candidate<K, double>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
-        if (ev.r < m1) {
-            m2 = m1;
-            m1 = ev.r;
-            arg_grp = grp;
-            arg_c = c;
-        } else if (ev.r < m2) {
-            m2 = ev.r;
-        }
-    }
-}
-
-// full tie rule: among candidates within TIE of the minimum, earliest
-// template, then the smallest representative vector
-template <int K>
-__device__ inline void tie_group(const MatchShared &M, const TablesView &T, int grp, int32_t cid, uint64_t ord,
-                                 uint32_t mask, const double *__restrict__ nbr_rel, int64_t n, int64_t p, double rstar,
-                                 int &win_grp, int &win_c, int &win_t, uint64_t &win_rep) {
-    double a[NMAX][3], Ga;
-    load_centred<K, double>(nbr_rel, n, p, a, Ga);
-    int c0 = T.cstart[grp][cid], c1 = T.cstart[grp][cid + 1];
-    for (int c = c0; c < c1; c++) {
-        Candidate cd = T.cand[grp][c];
-        if (!((mask >> cd.tmpl) & 1)) continue;
-        CandEval<double> ev;
-        eval_candidate<K, double>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
-        if (!(ev.r <= rstar + 1e-12)) continue;
-        int gsel;
-        uint64_t rep = rep_vector(M.tpl[cd.tmpl], rank_of_tv(cd.perm, ord, K), gsel);
-        bool better = (win_c < 0) || (cd.tmpl < win_t) || (cd.tmpl == win_t && rep < win_rep);
-        if (better) {
-            win_grp = grp;
-            win_c = c;
-            win_t = cd.tmpl;
-            win_rep = rep;
-        }
-    }
-}
-
 // Outputs of the winning candidate from its superposition ev and the
 // strain inputs A^T (sum over points of V+ columns times centred points, in
 // template order) and l (mean point norm).
@@ -1569,75 +1519,97 @@ __global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restri
     else finish_stored<14, RT>(M, T, 2, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
 }
 
-// The atoms k_decide left: the minimum is recomputed in FP64 when the FP32
-// margins could not decide it or the pairs did not fit, the full tie rule is
-// applied to near ties, and the winner is finished in FP64 when the decision
-// was taken in FP64 (else in the working precision).  Grid-stride over todo.
+// The atoms k_decide left (near ties, FP32 margins too small to trust, pairs
+// that did not fit the buffer), decided by the full rule in FP64 with one
+// wavefront per atom: each lane superposes one candidate of the atom's code
+// lists (at most 26 + 26 + 7), the minimum r* is reduced over the wave, every
+// candidate within the tie tolerance computes its representative vector, the
+// (template, representative) minimum is reduced, and one lane finishes the
+// winner in FP64.  Grid-stride over todo.
 template <typename RT>
 __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__restrict__ nbr_rel,
                                                     const int32_t *__restrict__ nbr_id,
                                                     const int32_t *__restrict__ sid,
                                                     const int8_t *__restrict__ species, TablesView T,
                                                     const int32_t *__restrict__ code,
-                                                    const uint64_t *__restrict__ ords,
-                                                    const int64_t *__restrict__ off, int64_t cap,
-                                                    const uint2 *__restrict__ pairs, const double *__restrict__ rr,
-                                                    uint32_t mask, double cutoff, MatchOut O,
-                                                    const int32_t *__restrict__ todo,
+                                                    const uint64_t *__restrict__ ords, uint32_t mask, double cutoff,
+                                                    MatchOut O, const int32_t *__restrict__ todo,
                                                     const int32_t *__restrict__ todo_count) {
     __shared__ MatchShared M;
     load_templates(M, T);
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (MB / 64);
     const int64_t cnt = *todo_count;
-    for (int64_t w = blockIdx.x * (int64_t)MB + threadIdx.x; w < cnt; w += (int64_t)gridDim.x * MB) {
+    for (int64_t w = blockIdx.x * (int64_t)(MB / 64) + (threadIdx.x >> 6); w < cnt; w += nwaves) {
         const int64_t p = todo[w];
         const int32_t i = sid[p];
-        int32_t cid[NGRP];
+        int32_t c0[NGRP], nc[NGRP];
         uint64_t ord[NGRP];
         for (int g = 0; g < NGRP; g++) {
-            cid[g] = code[(int64_t)g * n + p];
+            const int32_t cid = code[(int64_t)g * n + p];
             ord[g] = ords[(int64_t)g * n + p];
+            c0[g] = cid >= 0 ? T.cstart[g][cid] : 0;
+            nc[g] = cid >= 0 ? T.cstart[g][cid + 1] - c0[g] : 0;
         }
-        double m1, m2;
-        int arg_grp, arg_c;
-        int64_t arg_q;
-        const int64_t q1 = off[p + 1];
-        pair_minimum(off[p], q1, cap, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
-        bool fp64 = q1 > cap;
-        if (sizeof(RT) == 4 && !fp64 && arg_c >= 0) {
-            bool clear = (m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) && !(fabs(m1 - cutoff) <= RMSD_F32_BOUND);
-            fp64 = !clear;
-        }
-        if (fp64) {
-            m1 = m2 = INFINITY;
-            arg_grp = arg_c = -1;
-            if (cid[0] >= 0) scan_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-            if (cid[1] >= 0) scan_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-            if (cid[2] >= 0) scan_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, m2, arg_grp, arg_c);
-        }
-        if (arg_c < 0) {
-            write_none(O, i);
-            continue;
-        }
-        if (m2 <= m1 + 1e-12) {
-            // near tie: apply the full rule over every candidate
-            int wg = -1, wc = -1, wt = 99;
-            uint64_t wrep = ~0ull;
-            if (cid[0] >= 0) tie_group<6>(M, T, 0, cid[0], ord[0], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
-            if (cid[1] >= 0) tie_group<12>(M, T, 1, cid[1], ord[1], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
-            if (cid[2] >= 0) tie_group<14>(M, T, 2, cid[2], ord[2], mask, nbr_rel, n, p, m1, wg, wc, wt, wrep);
-            if (wc >= 0) {
-                arg_grp = wg;
-                arg_c = wc;
+        // this lane's candidate
+        int g = -1, c = -1, tmpl = 99;
+        double r = INFINITY;
+        {
+            int j = lane;
+            for (int gg = 0; gg < NGRP && g < 0; gg++) {
+                if (j < nc[gg]) {
+                    g = gg;
+                    c = c0[gg] + j;
+                } else {
+                    j -= nc[gg];
+                }
             }
         }
-        if (fp64) {
-            if (arg_grp == 0) finish<6, double>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else if (arg_grp == 1) finish<12, double>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else finish<14, double>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        } else {
-            if (arg_grp == 0) finish<6, RT>(M, T, 0, arg_c, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else if (arg_grp == 1) finish<12, RT>(M, T, 1, arg_c, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else finish<14, RT>(M, T, 2, arg_c, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        Candidate cd = {0, 0, 0};
+        if (g >= 0) {
+            cd = T.cand[g][c];
+            if ((mask >> cd.tmpl) & 1) {
+                tmpl = cd.tmpl;
+                CandEval<double> ev;
+                const TemplateDev &D = M.tpl[cd.tmpl];
+                if (g == 0) eval_streamed<6, double>(nbr_rel, n, p, D, tv_of_rank(cd.perm, ord[0], 6), ev);
+                else if (g == 1) eval_streamed<12, double>(nbr_rel, n, p, D, tv_of_rank(cd.perm, ord[1], 12), ev);
+                else eval_streamed<14, double>(nbr_rel, n, p, D, tv_of_rank(cd.perm, ord[2], 14), ev);
+                r = ev.r;
+            }
+        }
+        double m1 = r;
+        for (int off = 32; off > 0; off >>= 1) m1 = fmin(m1, __shfl_xor(m1, off));
+        if (m1 == INFINITY) {  // no candidate of an enabled template
+            if (lane == 0) write_none(O, i);
+            continue;
+        }
+        // tie rule: earliest template, then the smallest representative vector
+        int kt = 99;
+        uint64_t krep = ~0ull;
+        if (r <= m1 + 1e-12) {
+            int gsel;
+            const int K = group_k(g);
+            kt = tmpl;
+            krep = rep_vector(M.tpl[tmpl], rank_of_tv(cd.perm, ord[g], K), gsel);
+        }
+        int bt = kt, bl = lane;
+        uint64_t brep = krep;
+        for (int off = 32; off > 0; off >>= 1) {
+            int ot = __shfl_xor(bt, off), ol = __shfl_xor(bl, off);
+            uint64_t orep = __shfl_xor(brep, off);
+            bool take = ot < bt || (ot == bt && (orep < brep || (orep == brep && ol < bl)));
+            if (take) {
+                bt = ot;
+                brep = orep;
+                bl = ol;
+            }
+        }
+        const int wg = __shfl(g, bl), wc = __shfl(c, bl);
+        if (lane == 0) {
+            if (wg == 0) finish<6, double>(M, T, 0, wc, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else if (wg == 1) finish<12, double>(M, T, 1, wc, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else finish<14, double>(M, T, 2, wc, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
         }
     }
 }
@@ -1707,19 +1679,17 @@ void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, cons
                    uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
                    int32_t *todo_count, bool f32, hipStream_t st) {
     dim3 gd((unsigned)((n + MB - 1) / MB));
-    dim3 gf((unsigned)std::min<int64_t>((n + MB - 1) / MB, 2048));
+    dim3 gf((unsigned)std::min<int64_t>((n + MB / 64 - 1) / (MB / 64), 2048));
     if (f32) {
         hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
                            W.cap, W.pairs, W.r, (const float *)W.qs, cutoff, O, todo, todo_count);
         hipLaunchKernelGGL(k_decide_full<float>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
-                           W.off, W.cap, W.pairs, W.r, mask, cutoff, O, (const int32_t *)todo,
-                           (const int32_t *)todo_count);
+                           mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count);
     } else {
         hipLaunchKernelGGL(k_decide<double>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
                            W.off, W.cap, W.pairs, W.r, (const double *)W.qs, cutoff, O, todo, todo_count);
         hipLaunchKernelGGL(k_decide_full<double>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code,
-                           ord, W.off, W.cap, W.pairs, W.r, mask, cutoff, O, (const int32_t *)todo,
-                           (const int32_t *)todo_count);
+                           ord, mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count);
     }
 }
 

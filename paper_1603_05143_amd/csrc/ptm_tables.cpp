@@ -425,6 +425,12 @@ bool build_tables(HostTables &T, std::string &err) {
             T.slots[g][s] = c;
         }
     }
+    // the full decision superposes all candidates of an atom's three codes
+    // with one lane each of a 64-lane wavefront
+    if (T.max_cand_per_code[0] + T.max_cand_per_code[1] + T.max_cand_per_code[2] > 64) {
+        err = "more than 64 candidate correspondences per atom";
+        return false;
+    }
     return true;
 }
 
