@@ -197,3 +197,29 @@ def test_host_pointer_context(torch_cuda, oracle_lib):
         compare(out, oracle_lib.classify(f.positions, f.box))
     finally:
         ptm.ptm_destroy(ctx)
+
+
+def test_config1_fp32_decisions_equal_fp64(torch_cuda):
+    """Whole 0.92 M-atom polycrystal: every decision of the FP32-mixed form
+    (type, alloy, ordered neighbours) equals the FP64 form's, and the reals
+    agree within the FP32 tolerances.  The atoms whose FP32 margins were too
+    small are decided by the full rule (checked to occur)."""
+    torch = torch_cuda
+    f = S.polycrystal()
+    pos = torch.from_numpy(f.positions).to("cuda:0")
+    res, full = {}, {}
+    for prec in (ptm.PTM_FP64, ptm.PTM_FP32_MIXED):
+        ctx = ptm.ptm_create(0, prec, None, 0, ptm.PTM_F_PROFILE)
+        try:
+            out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
+            st = ptm.ptm_classify(ctx, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, math.inf,
+                                  ptm.Classifier.outputs_struct(out))
+            assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+            torch.cuda.synchronize()
+            res[prec] = {k: v.cpu().numpy() for k, v in out.items()}
+            full[prec] = ptm.ptm_frame_info(ctx)["decide_full"]
+        finally:
+            ptm.ptm_destroy(ctx)
+    st = _compare(res[ptm.PTM_FP32_MIXED], res[ptm.PTM_FP64], tol=TOL32, label="fp32 vs fp64 ")
+    print("fp32 vs fp64 on", f.n, "atoms:", st, "full-rule atoms:", full)
+    assert full[ptm.PTM_FP32_MIXED] > 0
