@@ -99,6 +99,16 @@ typedef struct {
     int32_t *neighbours; /* [n][14] atom ids in template-vertex order; -1 past k or if no candidate */
     double *strain;      /* [n][9] symmetric P of the left polar decomposition A = P U of eq.(6)   */
     int32_t *knn;        /* [n][14] atom ids in Euclidean order (Sec. 3); -1 past the last neighbour */
+    /* derived from the best match (0, or (1,0,0,0), if there is no candidate) */
+    double *vm_strain;       /* von Mises shear strain of P, sqrt(3/2 sum P_ij^2 - 1/2 (tr P)^2) (Sec. 8)  */
+    double *strain_residual; /* residual of the least-squares fit of eq.(6): sum of squares over the N
+                                normalised points (Falk-Langer D^2_min, Sec. 8)                            */
+    double *nn_distance;     /* nearest-neighbour distance the fit implies: the distance of template
+                                vertex 0 from the centre in eq.(4) units divided by s (the hydrostatic
+                                part recovered from the scale, Sec. 8)                                  */
+    double *quat_fz;         /* [n][4] the orientation in the fundamental zone (Sec. 7): of the
+                                equivalent q x conj(q_h), h in the template's proper rotation group,
+                                the one of largest w (the first in group order on ties), w >= 0       */
 } ptm_outputs;
 
 /* Frame statistics returned by ptm_wait. */

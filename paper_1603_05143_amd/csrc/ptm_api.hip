@@ -204,7 +204,10 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     const uint32_t need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
     launch_topo(ctx->precision == PTM_FP32_MIXED, n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, st);
     if ((ps = mark(PTM_STAGE_CAND)) != PTM_OK) return ps;
-    MatchOut O = {J.out.type, J.out.alloy, J.out.rmsd, J.out.scale, J.out.quat, J.out.neighbours, J.out.strain};
+    MatchOut O = {J.out.type,       J.out.alloy,     J.out.rmsd,
+                  J.out.scale,      J.out.quat,      J.out.neighbours,
+                  J.out.strain,     J.out.vm_strain, J.out.strain_residual,
+                  J.out.nn_distance, J.out.quat_fz};
     const bool f32 = ctx->precision == PTM_FP32_MIXED;
     launch_cand(n, ctx->view, S.code, m, S.match, st);
     if ((ps = mark(PTM_STAGE_EVAL)) != PTM_OK) return ps;

@@ -1172,8 +1172,8 @@ __device__ inline uint64_t rank_of_tv(uint64_t perm, uint64_t ord, int k) {
 // template order) and l (mean point norm).
 template <int K, typename RT>
 __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
-                                      const CandEval<RT> &ev, RT l, const RT (&At)[3][3], double cutoff, int64_t p,
-                                      int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
+                                      const CandEval<RT> &ev, RT l, const RT (&At)[3][3], RT resid, double cutoff,
+                                      int64_t p, int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
                                       const int8_t *__restrict__ species, const MatchOut &O) {
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
@@ -1200,6 +1200,39 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
         if (O.scale) O.scale[i] = (double)ev.s;
         if (O.quat)
             for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = (double)(q[k] * sc);
+        if (O.quat_fz) {
+            // Sec. 7: of the equivalent orientations q' x conj(q_h), the one
+            // closest to the identity (largest |w|; the first on ties)
+            const RT a0 = q[0] * sc, a1 = q[1] * sc, a2 = q[2] * sc, a3 = q[3] * sc;
+            RT best[4] = {a0, a1, a2, a3};
+            RT bw = RT(-1);
+            for (int h = 0; h < D.ngroup; h++) {
+                const double *qh = D.gq[h];
+                const RT w2 = (RT)qh[0], x2 = -(RT)qh[1], y2 = -(RT)qh[2], z2 = -(RT)qh[3];
+                const RT c0 = a0 * w2 - a1 * x2 - a2 * y2 - a3 * z2;
+                if (fabs(c0) > bw) {
+                    bw = fabs(c0);
+                    best[0] = c0;
+                    best[1] = a0 * x2 + a1 * w2 + a2 * z2 - a3 * y2;
+                    best[2] = a0 * y2 - a1 * z2 + a2 * w2 + a3 * x2;
+                    best[3] = a0 * z2 + a1 * y2 - a2 * x2 + a3 * w2;
+                }
+            }
+            RT sg = best[0] < RT(0) ? RT(-1) : RT(1);
+            if (best[0] == RT(0))
+                for (int k = 1; k < 4; k++)
+                    if (best[k] != RT(0)) {
+                        sg = best[k] < RT(0) ? RT(-1) : RT(1);
+                        break;
+                    }
+            for (int k = 0; k < 4; k++) O.quat_fz[4 * (int64_t)i + k] = (double)(sg * best[k]);
+        }
+        if (O.nn_distance) {
+            // hydrostatic part (Sec. 8): template vertex 0 lies at |b_1| in eq.(4) units
+            const double *b1 = D.b[1];
+            O.nn_distance[i] = ev.s > RT(0) ? sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]) / (double)ev.s : 0.0;
+        }
+        if (O.strain_residual) O.strain_residual[i] = (double)resid;
     }
     if (O.neighbours) {
 #pragma unroll
@@ -1212,7 +1245,7 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
             O.neighbours[(int64_t)i * KMAX + m] = id;
         }
     }
-    if (O.strain) {
+    if (O.strain || O.vm_strain) {
         // P = sqrt(A A^T) by the eigen-decomposition of the symmetric A A^T
         RT AA[3][3];
         for (int x = 0; x < 3; x++)
@@ -1224,12 +1257,17 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
         RT ev3[3], V[3][3];
         jacobi3<RT>(AA, ev3, V);
         for (int m = 0; m < 3; m++) ev3[m] = sqrt(fmax(ev3[m], RT(0)));
+        RT sq = 0, tr = 0;
         for (int x = 0; x < 3; x++)
             for (int y = 0; y < 3; y++) {
                 RT s = 0;
                 for (int m = 0; m < 3; m++) s += V[x][m] * ev3[m] * V[y][m];
-                O.strain[9 * (int64_t)i + 3 * x + y] = (double)s;
+                if (O.strain) O.strain[9 * (int64_t)i + 3 * x + y] = (double)s;
+                sq += s * s;
+                if (x == y) tr += s;
             }
+        // Sec. 8: von Mises shear strain of P
+        if (O.vm_strain) O.vm_strain[i] = (double)sqrt(fmax(RT(1.5) * sq - RT(0.5) * tr * tr, RT(0)));
     }
     if (O.alloy) {
         // alloy (Sec. 6, Table 3)
@@ -1275,7 +1313,7 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
     const TemplateDev &D = M.tpl[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
     CandEval<RT> ev;
-    RT l = 0;
+    RT l = 0, resid = 0;
     RT At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     {
         RT a[NMAX][3], Ga;
@@ -1291,8 +1329,19 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
             for (int x = 0; x < 3; x++)
                 for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * a[r + 1][y];
         }
+        if (O.strain_residual) {
+            // eq.(6) residual: sum over points of |V_i A^T - W'_i|^2 (W' = a / l)
+            for (int r = 0; r <= K; r++) {
+                const double *v = D.b[r == 0 ? 0 : (int)nib(tv, r - 1) + 1];
+                for (int y = 0; y < 3; y++) {
+                    RT d = (RT)v[0] * At[0][y] + (RT)v[1] * At[1][y] + (RT)v[2] * At[2][y] - a[r][y];
+                    resid += d * d;
+                }
+            }
+            resid /= l * l;
+        }
     }
-    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, cutoff, p, n, i, nbr_id, species, O);
+    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, resid, cutoff, p, n, i, nbr_id, species, O);
 }
 
 // Winner outputs from the superposition stored by k_cand_eval (q, s) and
@@ -1334,7 +1383,25 @@ __device__ inline void finish_stored(const MatchShared &M, const TablesView &T, 
             for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * ar[y];
     }
     l /= RT(K + 1);
-    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, cutoff, p, n, i, nbr_id, species, O);
+    RT resid = 0;
+    if (O.strain_residual) {
+        // eq.(6) residual, a third pass over the points: sum of |V_i A^T - a_i|^2 / l^2
+        for (int y = 0; y < 3; y++) {
+            RT d = (RT)D.b[0][0] * At[0][y] + (RT)D.b[0][1] * At[1][y] + (RT)D.b[0][2] * At[2][y] - a0[y];
+            resid += d * d;
+        }
+#pragma unroll HALF
+        for (int rr = 0; rr < K; rr++) {
+            const double *v = D.b[(int)nib(tv, rr) + 1];
+            for (int y = 0; y < 3; y++) {
+                RT ay = (RT)(nbr_rel[((int64_t)rr * 3 + y) * n + p] - cb[y]);
+                RT d = (RT)v[0] * At[0][y] + (RT)v[1] * At[1][y] + (RT)v[2] * At[2][y] - ay;
+                resid += d * d;
+            }
+        }
+        resid /= l * l;
+    }
+    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, resid, cutoff, p, n, i, nbr_id, species, O);
 }
 
 __device__ inline void write_none(const MatchOut &O, int32_t i) {
@@ -1350,6 +1417,13 @@ __device__ inline void write_none(const MatchOut &O, int32_t i) {
         for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = 0.0;
     if (O.neighbours)
         for (int m = 0; m < KMAX; m++) O.neighbours[(int64_t)i * KMAX + m] = -1;
+    if (O.vm_strain) O.vm_strain[i] = 0.0;
+    if (O.strain_residual) O.strain_residual[i] = 0.0;
+    if (O.nn_distance) O.nn_distance[i] = 0.0;
+    if (O.quat_fz) {
+        O.quat_fz[4 * (int64_t)i] = 1.0;
+        for (int k = 1; k < 4; k++) O.quat_fz[4 * (int64_t)i + k] = 0.0;
+    }
 }
 
 __device__ inline void load_templates(MatchShared &M, const TablesView &T) {

@@ -28,6 +28,10 @@ struct MatchOut {
     double *quat;
     int32_t *neighbours;
     double *strain;
+    double *vm_strain;
+    double *strain_residual;
+    double *nn_distance;
+    double *quat_fz;
 };
 
 // Flat (atom, candidate) pair list of the match stage.

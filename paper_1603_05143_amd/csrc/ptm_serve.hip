@@ -67,6 +67,10 @@ static size_t staging_bytes(int64_t n) {
     add(56 * (size_t)n);   // neighbours
     add(72 * (size_t)n);   // strain
     add(56 * (size_t)n);   // knn
+    add(8 * (size_t)n);    // vm_strain
+    add(8 * (size_t)n);    // strain_residual
+    add(8 * (size_t)n);    // nn_distance
+    add(32 * (size_t)n);   // quat_fz
     return a;
 }
 
@@ -106,6 +110,10 @@ ptm_status stage_in_buffers(ptm_ctx *ctx, StagingBuffers &B, const double *posit
     d.neighbours = (int32_t *)take(56 * (size_t)n);
     d.strain = (double *)take(72 * (size_t)n);
     d.knn = (int32_t *)take(56 * (size_t)n);
+    d.vm_strain = (double *)take(8 * (size_t)n);
+    d.strain_residual = (double *)take(8 * (size_t)n);
+    d.nn_distance = (double *)take(8 * (size_t)n);
+    d.quat_fz = (double *)take(32 * (size_t)n);
     if (!out->alloy) d.alloy = nullptr;
     if (!out->rmsd) d.rmsd = nullptr;
     if (!out->scale) d.scale = nullptr;
@@ -113,6 +121,10 @@ ptm_status stage_in_buffers(ptm_ctx *ctx, StagingBuffers &B, const double *posit
     if (!out->neighbours) d.neighbours = nullptr;
     if (!out->strain) d.strain = nullptr;
     if (!out->knn) d.knn = nullptr;
+    if (!out->vm_strain) d.vm_strain = nullptr;
+    if (!out->strain_residual) d.strain_residual = nullptr;
+    if (!out->nn_distance) d.nn_distance = nullptr;
+    if (!out->quat_fz) d.quat_fz = nullptr;
     PTM_HIP(ctx, hipMemcpyAsync(dpos, positions, 24 * (size_t)n, hipMemcpyHostToDevice, st));
     if (species) PTM_HIP(ctx, hipMemcpyAsync(dspc, species, (size_t)n, hipMemcpyHostToDevice, st));
     J.pos = dpos;
@@ -146,6 +158,10 @@ ptm_status stage_out(ptm_ctx *ctx, const ptm_outputs *out, int64_t n, const Fram
     if ((s = cp(h.neighbours, d.neighbours, 56 * (size_t)n)) != PTM_OK) return s;
     if ((s = cp(h.strain, d.strain, 72 * (size_t)n)) != PTM_OK) return s;
     if ((s = cp(h.knn, d.knn, 56 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.vm_strain, d.vm_strain, 8 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.strain_residual, d.strain_residual, 8 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.nn_distance, d.nn_distance, 8 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.quat_fz, d.quat_fz, 32 * (size_t)n)) != PTM_OK) return s;
     return PTM_OK;
 }
 

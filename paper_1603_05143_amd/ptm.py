@@ -29,9 +29,12 @@ class ptm_config(C.Structure):
                 ("hbm_budget_bytes", C.c_uint64), ("flags", C.c_uint32)]
 
 
+OUTPUT_FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn",
+                 "vm_strain", "strain_residual", "nn_distance", "quat_fz")
+
+
 class ptm_outputs(C.Structure):
-    _fields_ = [("type", C.c_void_p), ("alloy", C.c_void_p), ("rmsd", C.c_void_p), ("scale", C.c_void_p),
-                ("quat", C.c_void_p), ("neighbours", C.c_void_p), ("strain", C.c_void_p), ("knn", C.c_void_p)]
+    _fields_ = [(k, C.c_void_p) for k in OUTPUT_FIELDS]
 
 
 class ptm_frame_stats(C.Structure):
@@ -174,7 +177,7 @@ class Classifier:
             pass
 
     @staticmethod
-    def alloc_outputs(n: int, device: str, knn: bool = False):
+    def alloc_outputs(n: int, device: str, knn: bool = False, derived: bool = False):
         import torch
         out = {
             "type": torch.empty(n, dtype=torch.int8, device=device),
@@ -187,6 +190,10 @@ class Classifier:
         }
         if knn:
             out["knn"] = torch.empty((n, 14), dtype=torch.int32, device=device)
+        if derived:
+            for k in ("vm_strain", "strain_residual", "nn_distance"):
+                out[k] = torch.empty(n, dtype=torch.float64, device=device)
+            out["quat_fz"] = torch.empty((n, 4), dtype=torch.float64, device=device)
         return out
 
     @staticmethod
@@ -194,16 +201,16 @@ class Classifier:
         def p(k):
             t = out.get(k)
             return None if t is None else t.data_ptr()
-        return ptm_outputs(p("type"), p("alloy"), p("rmsd"), p("scale"), p("quat"), p("neighbours"),
-                           p("strain"), p("knn"))
+        return ptm_outputs(*[p(k) for k in OUTPUT_FIELDS])
 
-    def classify(self, positions, box, species=None, mask=PTM_ALL, cutoff=float("inf"), out=None, knn=False):
+    def classify(self, positions, box, species=None, mask=PTM_ALL, cutoff=float("inf"), out=None, knn=False,
+                 derived=False):
         """positions: (n,3) float64 CUDA tensor; returns dict of output tensors."""
         import torch
         assert positions.is_cuda and positions.dtype == torch.float64 and positions.is_contiguous()
         n = positions.shape[0]
         if out is None:
-            out = self.alloc_outputs(n, positions.device, knn)
+            out = self.alloc_outputs(n, positions.device, knn, derived)
         sp = None
         if species is not None:
             assert species.is_cuda and species.dtype == torch.int8 and species.is_contiguous()

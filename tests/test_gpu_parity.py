@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_1603_05143_amd import ptm, synthetic as S
-from parity_util import TOL32, TOL64, compare as _compare
+from parity_util import TOL32, TOL64, compare as _compare, quat_angle
 
 pytestmark = pytest.mark.gpu
 
@@ -223,3 +223,44 @@ def test_config1_fp32_decisions_equal_fp64(torch_cuda):
     st = _compare(res[ptm.PTM_FP32_MIXED], res[ptm.PTM_FP64], tol=TOL32, label="fp32 vs fp64 ")
     print("fp32 vs fp64 on", f.n, "atoms:", st, "full-rule atoms:", full)
     assert full[ptm.PTM_FP32_MIXED] > 0
+
+
+@pytest.mark.parametrize("case", ["config0", "fcc", "bcc", "sc", "hcp", "polycrystal"])
+def test_derived_outputs(torch_cuda, clf, oracle_lib, case):
+    """von Mises strain, eq.(6) residual, nearest-neighbour distance and the
+    fundamental-zone orientation (Sec. 7, Sec. 8) against oracle/derived.py."""
+    from oracle import derived as OD
+    torch = torch_cuda
+    if case == "config0":
+        f = S.config0()
+    elif case == "polycrystal":
+        f = S.polycrystal(L=40.0, n_grains=3, sigma=0.1, seed=77)
+    else:
+        a = {"fcc": 3.615, "bcc": 2.87, "sc": 2.6, "hcp": 2.51}[case]
+        f = S.perfect_crystal(case, reps=(4, 4, 4) if case != "hcp" else (4, 3, 3), a=a)
+        f.positions = f.positions + np.random.default_rng(1).normal(0, 0.04, f.positions.shape)
+        f.positions = np.mod(f.positions, f.box)
+    pos = torch.from_numpy(np.ascontiguousarray(f.positions)).to("cuda:0")
+    out = clf.classify(pos, f.box, derived=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    atoms = np.arange(f.n) if f.n <= 600 else np.sort(np.random.default_rng(2).choice(f.n, 600, replace=False))
+    ref = oracle_lib.classify(f.positions, f.box, atoms=atoms)
+    d = OD.derived(f.positions, f.box, ref, atoms=atoms)
+    tol = clf.tol
+    fin = np.isfinite(ref["rmsd"])
+    assert np.array_equal(got["type"][atoms], ref["type"])
+    for k, t in (("vm_strain", tol["strain"] * 10), ("strain_residual", tol["strain"])):
+        err = np.max(np.abs(got[k][atoms][fin] - d[k][fin]), initial=0.0)
+        assert err <= t, (k, err)
+    rel = np.max(np.abs(got["nn_distance"][atoms][fin] / d["nn_distance"][fin] - 1), initial=0.0)
+    assert rel <= tol["scale_rel"] * 10, rel
+    # the fundamental-zone representative is unique where its |w| leads by a margin
+    uniq = fin & (d["fz_gap"] > 1e-6)
+    ang = quat_angle(got["quat_fz"][atoms][uniq], d["quat_fz"][uniq])
+    assert np.max(ang, initial=0.0) <= tol["angle"], np.max(ang)
+    dw = np.abs(got["quat_fz"][atoms][fin][:, 0] - d["quat_fz"][fin][:, 0])
+    assert np.max(dw, initial=0.0) <= tol["angle"]
+    nf = ~fin
+    assert np.all(got["vm_strain"][atoms][nf] == 0) and np.all(got["nn_distance"][atoms][nf] == 0)
+    print(case, f.n, "vm", float(np.max(got["vm_strain"])), "nn", float(np.median(got["nn_distance"][atoms][fin])))
