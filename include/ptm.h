@@ -183,6 +183,19 @@ enum { PTM_INFO_CELLS = 0,      /* cells of the binning grid */
        PTM_NINFO = 4 };
 ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n);
 
+/* Misorientation angles (Sec. 7): for i < n, angle[i] = the smallest
+ * rotation angle (radians, in [0, pi]) of conj(q1_i) x q2_i x q_h over the
+ * proper rotation group of template type[i] (PTM_TYPE_*; NONE: no symmetry,
+ * the plain angle between the two orientations).  q1, q2: [n][4] unit
+ * quaternions (w,x,y,z) as written to ptm_outputs.quat; type: [n] int8;
+ * angle: [n] double.  Device pointers (host pointers on a PTM_F_HOST_POINTERS
+ * context), caller-owned; runs on the context's stream and synchronises.
+ * A type outside 0..5 gives NaN (device pointers) or PTM_E_INVALID before
+ * any work (host pointers); PTM_E_INVALID also for NULL arrays with n > 0
+ * or n < 0. */
+ptm_status ptm_misorientation(ptm_ctx *ctx, const int8_t *type, const double *q1, const double *q2, int64_t n,
+                              double *angle);
+
 /* Template facts of the library's own tables, for checks without a device:
  * info[0]=k, info[1]=rotation group order, info[2]=triangulations,
  * info[3]=distinct table keys (orientation-preserving start-edge codes of

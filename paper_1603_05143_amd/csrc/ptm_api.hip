@@ -459,6 +459,59 @@ ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n) {
     return PTM_OK;
 }
 
+ptm_status ptm_misorientation(ptm_ctx *ctx, const int8_t *type, const double *q1, const double *q2, int64_t n,
+                              double *angle) {
+    if (!ctx) return PTM_E_INVALID;
+    if (n < 0 || (n > 0 && (!type || !q1 || !q2 || !angle))) {
+        ctx->err = "ptm_misorientation: NULL array or n < 0";
+        return PTM_E_INVALID;
+    }
+    ctx->err.clear();
+    if (n == 0) return PTM_OK;
+    PTM_HIP(ctx, hipSetDevice(ctx->device));
+    const int8_t *dt = type;
+    const double *d1 = q1, *d2 = q2;
+    double *da = angle;
+    void *buf = nullptr;
+    const bool host = (ctx->flags & PTM_F_HOST_POINTERS) != 0;
+    if (host) {
+        // types first: reject invalid ones before any device work
+        for (int64_t i = 0; i < n; i++)
+            if (type[i] < 0 || type[i] > 5) {
+                ctx->err = "ptm_misorientation: type outside 0..5";
+                return PTM_E_INVALID;
+            }
+        size_t bytes = (size_t)n * (1 + 32 + 32 + 8) + 256;
+        if (hipMalloc(&buf, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->err = "ptm_misorientation: staging allocation failed";
+            return PTM_E_NOMEM;
+        }
+        char *b = (char *)buf;
+        double *h1 = (double *)b, *h2 = h1 + 4 * n, *ha = h2 + 4 * n;
+        int8_t *ht = (int8_t *)(ha + n);
+        ptm_status st = PTM_OK;
+        if (hipMemcpyAsync(h1, q1, 32 * (size_t)n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(h2, q2, 32 * (size_t)n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(ht, type, (size_t)n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+            st = PTM_E_DEVICE;
+        if (st == PTM_OK) {
+            launch_misorientation(n, ctx->view, ht, h1, h2, ha, ctx->stream);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(angle, ha, 8 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess)
+                st = PTM_E_DEVICE;
+        }
+        (void)hipFree(buf);
+        if (st != PTM_OK) ctx->err = "ptm_misorientation: HIP error";
+        return st;
+    }
+    launch_misorientation(n, ctx->view, dt, d1, d2, da, ctx->stream);
+    PTM_HIP(ctx, hipGetLastError());
+    PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PTM_OK;
+}
+
 }  // extern "C"
 
 // ======================================================= self-check entry points

@@ -1688,6 +1688,48 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
     }
 }
 
+// ------------------------------------------------------- misorientation
+// Sec. 7: smallest rotation angle of conj(q1) q2 q_h over the template's
+// proper rotations (identity only for type NONE), as 2 atan2(|v|, |w|) of
+// the best product, which stays accurate near zero.  Invalid types give NaN.
+__global__ void __launch_bounds__(256) k_misorientation(int64_t n, TablesView T, const int8_t *__restrict__ type,
+                                                        const double *__restrict__ q1, const double *__restrict__ q2,
+                                                        double *__restrict__ angle) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ty = type[i];
+    const double a0 = q1[4 * i], a1 = -q1[4 * i + 1], a2 = -q1[4 * i + 2], a3 = -q1[4 * i + 3];  // conj(q1)
+    const double b0 = q2[4 * i], b1 = q2[4 * i + 1], b2 = q2[4 * i + 2], b3 = q2[4 * i + 3];
+    const double m0 = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3, m1 = a0 * b1 + a1 * b0 + a2 * b3 - a3 * b2;
+    const double m2 = a0 * b2 - a1 * b3 + a2 * b0 + a3 * b1, m3 = a0 * b3 + a1 * b2 - a2 * b1 + a3 * b0;
+    if (ty < 0 || ty > NT) {
+        angle[i] = NAN;
+        return;
+    }
+    double bw = fabs(m0), bv = sqrt(m1 * m1 + m2 * m2 + m3 * m3);
+    if (ty > 0) {
+        const TemplateDev &D = T.tpl[ty - 1];
+        for (int h = 0; h < D.ngroup; h++) {
+            const double *g = D.gq[h];
+            const double c0 = m0 * g[0] - m1 * g[1] - m2 * g[2] - m3 * g[3];
+            if (fabs(c0) > bw) {
+                const double c1 = m0 * g[1] + m1 * g[0] + m2 * g[3] - m3 * g[2];
+                const double c2 = m0 * g[2] - m1 * g[3] + m2 * g[0] + m3 * g[1];
+                const double c3 = m0 * g[3] + m1 * g[2] - m2 * g[1] + m3 * g[0];
+                bw = fabs(c0);
+                bv = sqrt(c1 * c1 + c2 * c2 + c3 * c3);
+            }
+        }
+    }
+    angle[i] = 2.0 * atan2(bv, bw);
+}
+
+void launch_misorientation(int64_t n, const TablesView &T, const int8_t *type, const double *q1, const double *q2,
+                           double *angle, hipStream_t st) {
+    hipLaunchKernelGGL(k_misorientation, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, type, q1, q2,
+                       angle);
+}
+
 // --------------------------------------------------------------- launches
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(nblocks), dim3(256), 0, st, pos, n, part);

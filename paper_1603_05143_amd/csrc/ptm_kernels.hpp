@@ -73,4 +73,8 @@ void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, cons
                    uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
                    int32_t *todo_count, bool f32, hipStream_t st);
 
+// misorientation angles of orientation pairs under each template's symmetry
+void launch_misorientation(int64_t n, const TablesView &T, const int8_t *type, const double *q1, const double *q2,
+                           double *angle, hipStream_t st);
+
 }  // namespace ptm

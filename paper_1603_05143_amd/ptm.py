@@ -80,6 +80,8 @@ def lib():
         L.ptm_stage_times.restype = C.c_int
         L.ptm_frame_info.argtypes = [vp, C.POINTER(C.c_int64), C.c_int]
         L.ptm_frame_info.restype = C.c_int
+        L.ptm_misorientation.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
+        L.ptm_misorientation.restype = C.c_int
         _lib = L
     return _lib
 
@@ -145,6 +147,10 @@ def ptm_frame_info(ctx):
     if st != PTM_OK:
         raise PTMError(st, "ptm_frame_info")
     return dict(zip(INFO_NAMES, list(info)))
+
+
+def ptm_misorientation(ctx, type_ptr, q1_ptr, q2_ptr, n, angle_ptr):
+    return lib().ptm_misorientation(ctx, type_ptr, q1_ptr, q2_ptr, int(n), angle_ptr)
 
 
 def ptm_template_info(t: int):

@@ -61,6 +61,8 @@ def test_status_strings_and_errors_without_device(ptm):
     out = ptm.ptm_outputs()
     st = ptm.lib().ptm_classify(None, None, None, None, 0, 0, 0.0, C.byref(out))
     assert st == ptm.PTM_E_INVALID
+    assert ptm.ptm_misorientation(None, None, None, None, 1, None) == ptm.PTM_E_INVALID
+    assert ptm.lib().ptm_frame_info(None, None, 0) == ptm.PTM_E_INVALID
     try:
         import torch
         has_gpu = torch.cuda.is_available()

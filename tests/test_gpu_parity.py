@@ -264,3 +264,57 @@ def test_derived_outputs(torch_cuda, clf, oracle_lib, case):
     nf = ~fin
     assert np.all(got["vm_strain"][atoms][nf] == 0) and np.all(got["nn_distance"][atoms][nf] == 0)
     print(case, f.n, "vm", float(np.max(got["vm_strain"])), "nn", float(np.median(got["nn_distance"][atoms][fin])))
+
+
+def test_misorientation(torch_cuda, oracle_lib):
+    """ptm_misorientation against oracle/derived.py: random orientation pairs
+    of every type (NONE: no symmetry), device and host pointers."""
+    import ctypes as C
+    from oracle import derived as OD
+    torch = torch_cuda
+    rng = np.random.default_rng(21)
+    n = 600
+    q = rng.normal(size=(2, n, 4))
+    q /= np.linalg.norm(q, axis=-1, keepdims=True)
+    # include equivalent pairs (zero misorientation) and near-identical ones
+    for t in range(1, 6):
+        G = OD.group_quaternions(t - 1)
+        q[1, t * 10] = OD.quat_mul(q[0, t * 10], G[len(G) // 2])
+    q[1, 5] = q[0, 5] + 1e-9
+    q[1, 5] /= np.linalg.norm(q[1, 5])
+    types = (np.arange(n) % 6).astype(np.int8)
+    want = np.array([OD.misorientation(q[0, i], q[1, i], t - 1) if t > 0 else
+                     2 * np.arccos(min(1.0, abs(OD.quat_mul(OD.conj(q[0, i]), q[1, i])[0])))
+                     for i, t in enumerate(types)])
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    try:
+        dq1 = torch.from_numpy(np.ascontiguousarray(q[0])).to("cuda:0")
+        dq2 = torch.from_numpy(np.ascontiguousarray(q[1])).to("cuda:0")
+        dt = torch.from_numpy(types).to("cuda:0")
+        da = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        st = ptm.ptm_misorientation(ctx, dt.data_ptr(), dq1.data_ptr(), dq2.data_ptr(), n, da.data_ptr())
+        assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+        got = da.cpu().numpy()
+        # the oracle's arccos loses accuracy only near zero angle
+        assert np.max(np.abs(got - want)) < 1e-7
+        for t in range(1, 6):
+            assert got[t * 10] < 1e-7
+        cubic = types[:] == 2
+        assert np.max(got[cubic]) <= np.radians(62.81)
+        bad = torch.tensor([7], dtype=torch.int8, device="cuda:0")
+        st = ptm.ptm_misorientation(ctx, bad.data_ptr(), dq1.data_ptr(), dq2.data_ptr(), 1, da.data_ptr())
+        assert st == ptm.PTM_OK and np.isnan(da[0].item())
+    finally:
+        ptm.ptm_destroy(ctx)
+    hctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, ptm.PTM_F_HOST_POINTERS)
+    try:
+        h1, h2 = np.ascontiguousarray(q[0]), np.ascontiguousarray(q[1])
+        ha = np.zeros(n)
+        st = ptm.ptm_misorientation(hctx, types.ctypes.data, h1.ctypes.data, h2.ctypes.data, n, ha.ctypes.data)
+        assert st == ptm.PTM_OK
+        assert np.array_equal(ha, got)
+        bt = np.full(n, 9, np.int8)
+        assert ptm.ptm_misorientation(hctx, bt.ctypes.data, h1.ctypes.data, h2.ctypes.data, n,
+                                      ha.ctypes.data) == ptm.PTM_E_INVALID
+    finally:
+        ptm.ptm_destroy(hctx)
