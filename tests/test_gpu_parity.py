@@ -277,12 +277,12 @@ def test_misorientation(torch_cuda, oracle_lib):
     q = rng.normal(size=(2, n, 4))
     q /= np.linalg.norm(q, axis=-1, keepdims=True)
     # include equivalent pairs (zero misorientation) and near-identical ones
-    for t in range(1, 6):
+    types = (np.arange(n) % 6).astype(np.int8)
+    for t in range(1, 6):  # atom 60 + t has type t
         G = OD.group_quaternions(t - 1)
-        q[1, t * 10] = OD.quat_mul(q[0, t * 10], G[len(G) // 2])
+        q[1, 60 + t] = OD.quat_mul(q[0, 60 + t], G[len(G) // 2])
     q[1, 5] = q[0, 5] + 1e-9
     q[1, 5] /= np.linalg.norm(q[1, 5])
-    types = (np.arange(n) % 6).astype(np.int8)
     want = np.array([OD.misorientation(q[0, i], q[1, i], t - 1) if t > 0 else
                      2 * np.arccos(min(1.0, abs(OD.quat_mul(OD.conj(q[0, i]), q[1, i])[0])))
                      for i, t in enumerate(types)])
@@ -298,7 +298,7 @@ def test_misorientation(torch_cuda, oracle_lib):
         # the oracle's arccos loses accuracy only near zero angle
         assert np.max(np.abs(got - want)) < 1e-7
         for t in range(1, 6):
-            assert got[t * 10] < 1e-7
+            assert got[60 + t] < 1e-7
         cubic = types[:] == 2
         assert np.max(got[cubic]) <= np.radians(62.81)
         bad = torch.tensor([7], dtype=torch.int8, device="cuda:0")
