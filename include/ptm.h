@@ -109,6 +109,10 @@ typedef struct {
     double *quat_fz;         /* [n][4] the orientation in the fundamental zone (Sec. 7): of the
                                 equivalent q x conj(q_h), h in the template's proper rotation group,
                                 the one of largest w (the first in group order on ties), w >= 0       */
+    int8_t *best_type;       /* the template of the minimum-RMSD match whatever rmsd_cutoff (NONE only
+                                without a candidate): with rmsd, the input of ptm_apply_cutoff and
+                                ptm_rmsd_histogram, so that the cut-off can be chosen after the
+                                analysis (Sec. 5.1)                                                      */
 } ptm_outputs;
 
 /* Frame statistics returned by ptm_wait. */
@@ -195,6 +199,23 @@ ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n);
  * or n < 0. */
 ptm_status ptm_misorientation(ptm_ctx *ctx, const int8_t *type, const double *q1, const double *q2, int64_t n,
                               double *angle);
+
+/* Post-hoc cut-off (Sec. 5.1: RMSD_max can be chosen after the analysis):
+ * type[i] = best_type[i] if rmsd[i] <= rmsd_cutoff, else PTM_TYPE_NONE, for
+ * i < n.  Arrays as written by ptm_classify (device pointers, or host ones
+ * on a PTM_F_HOST_POINTERS context), caller-owned; the context's stream,
+ * synchronised.  PTM_E_INVALID for NULL arrays with n > 0 or n < 0. */
+ptm_status ptm_apply_cutoff(ptm_ctx *ctx, const int8_t *best_type, const double *rmsd, int64_t n,
+                            double rmsd_cutoff, int8_t *type);
+
+/* RMSD histograms per structure type (Sec. 5.1, Fig. 4: the way to pick
+ * RMSD_max): counts[t * nbins + b] (host array of 6 * nbins int64,
+ * overwritten) = number of atoms with best_type t and rmsd in bin b of
+ * nbins equal bins over [0, rmax); an RMSD >= rmax (or +inf) counts in the
+ * last bin.  best_type, rmsd as for ptm_apply_cutoff.  PTM_E_INVALID for
+ * NULL arrays with n > 0, n < 0, nbins outside 1..65536 or rmax <= 0. */
+ptm_status ptm_rmsd_histogram(ptm_ctx *ctx, const int8_t *best_type, const double *rmsd, int64_t n, int nbins,
+                              double rmax, int64_t *counts);
 
 /* Template facts of the library's own tables, for checks without a device:
  * info[0]=k, info[1]=rotation group order, info[2]=triangulations,

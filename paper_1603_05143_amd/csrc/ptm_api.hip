@@ -207,7 +207,7 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     MatchOut O = {J.out.type,       J.out.alloy,     J.out.rmsd,
                   J.out.scale,      J.out.quat,      J.out.neighbours,
                   J.out.strain,     J.out.vm_strain, J.out.strain_residual,
-                  J.out.nn_distance, J.out.quat_fz};
+                  J.out.nn_distance, J.out.quat_fz, J.out.best_type};
     const bool f32 = ctx->precision == PTM_FP32_MIXED;
     launch_cand(n, ctx->view, S.code, m, S.match, st);
     if ((ps = mark(PTM_STAGE_EVAL)) != PTM_OK) return ps;
@@ -510,6 +510,100 @@ ptm_status ptm_misorientation(ptm_ctx *ctx, const int8_t *type, const double *q1
     PTM_HIP(ctx, hipGetLastError());
     PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PTM_OK;
+}
+
+// Copies host arrays to device scratch for the post-hoc entry points of a
+// PTM_F_HOST_POINTERS context (one allocation, freed by the caller).
+static ptm_status stage_pair(ptm_ctx *ctx, const int8_t *t, const double *r, int64_t n, void **buf, int8_t **dt,
+                             double **dr, size_t extra) {
+    size_t bytes = 8 * (size_t)n + (size_t)n + extra + 512;
+    if (hipMalloc(buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->err = "staging allocation failed";
+        return PTM_E_NOMEM;
+    }
+    *dr = (double *)*buf;
+    *dt = (int8_t *)(*dr + n);
+    if (hipMemcpyAsync(*dr, r, 8 * (size_t)n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(*dt, t, (size_t)n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+        ctx->err = "staging copy failed";
+        return PTM_E_DEVICE;
+    }
+    return PTM_OK;
+}
+
+ptm_status ptm_apply_cutoff(ptm_ctx *ctx, const int8_t *best_type, const double *rmsd, int64_t n,
+                            double rmsd_cutoff, int8_t *type) {
+    if (!ctx) return PTM_E_INVALID;
+    if (n < 0 || (n > 0 && (!best_type || !rmsd || !type))) {
+        ctx->err = "ptm_apply_cutoff: NULL array or n < 0";
+        return PTM_E_INVALID;
+    }
+    ctx->err.clear();
+    if (n == 0) return PTM_OK;
+    PTM_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->flags & PTM_F_HOST_POINTERS) {
+        void *buf = nullptr;
+        int8_t *dt;
+        double *dr;
+        ptm_status st = stage_pair(ctx, best_type, rmsd, n, &buf, &dt, &dr, (size_t)n + 256);
+        if (st == PTM_OK) {
+            int8_t *dout = (int8_t *)(((uintptr_t)(dt + n) + 255) & ~(uintptr_t)255);
+            launch_apply_cutoff(n, dt, dr, rmsd_cutoff, dout, ctx->stream);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(type, dout, (size_t)n, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                ctx->err = "ptm_apply_cutoff: HIP error";
+                st = PTM_E_DEVICE;
+            }
+        }
+        if (buf) (void)hipFree(buf);
+        return st;
+    }
+    launch_apply_cutoff(n, best_type, rmsd, rmsd_cutoff, type, ctx->stream);
+    PTM_HIP(ctx, hipGetLastError());
+    PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PTM_OK;
+}
+
+ptm_status ptm_rmsd_histogram(ptm_ctx *ctx, const int8_t *best_type, const double *rmsd, int64_t n, int nbins,
+                              double rmax, int64_t *counts) {
+    if (!ctx) return PTM_E_INVALID;
+    if (n < 0 || (n > 0 && (!best_type || !rmsd)) || !counts || nbins < 1 || nbins > 65536 || !(rmax > 0)) {
+        ctx->err = "ptm_rmsd_histogram: invalid argument";
+        return PTM_E_INVALID;
+    }
+    ctx->err.clear();
+    std::memset(counts, 0, sizeof(int64_t) * 6 * (size_t)nbins);
+    if (n == 0) return PTM_OK;
+    PTM_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t cbytes = 8 * 6 * (size_t)nbins;
+    void *buf = nullptr;
+    int8_t *dt = const_cast<int8_t *>(best_type);
+    double *dr = const_cast<double *>(rmsd);
+    unsigned long long *dc = nullptr;
+    ptm_status st = PTM_OK;
+    if (ctx->flags & PTM_F_HOST_POINTERS) {
+        st = stage_pair(ctx, best_type, rmsd, n, &buf, &dt, &dr, cbytes + 256);
+        if (st == PTM_OK) dc = (unsigned long long *)(((uintptr_t)(dt + n) + 255) & ~(uintptr_t)255);
+    } else if (hipMalloc(&buf, cbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->err = "ptm_rmsd_histogram: allocation failed";
+        st = PTM_E_NOMEM;
+    } else {
+        dc = (unsigned long long *)buf;
+    }
+    if (st == PTM_OK) {
+        if (hipMemsetAsync(dc, 0, cbytes, ctx->stream) != hipSuccess) st = PTM_E_DEVICE;
+        if (st == PTM_OK) launch_rmsd_histogram(n, dt, dr, nbins, rmax, dc, ctx->stream);
+        if (st == PTM_OK && (hipGetLastError() != hipSuccess ||
+                             hipMemcpyAsync(counts, dc, cbytes, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+                             hipStreamSynchronize(ctx->stream) != hipSuccess))
+            st = PTM_E_DEVICE;
+        if (st != PTM_OK && ctx->err.empty()) ctx->err = "ptm_rmsd_histogram: HIP error";
+    }
+    if (buf) (void)hipFree(buf);
+    return st;
 }
 
 }  // extern "C"

@@ -1179,6 +1179,7 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
     const TemplateDev &D = M.tpl[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
     const int type = ((double)ev.r <= cutoff) ? cd.tmpl + 1 : 0;
+    if (O.best_type) O.best_type[i] = (int8_t)(cd.tmpl + 1);
     int g;
     const uint64_t rep = rep_vector(D, rank_of_tv(cd.perm, ord, K), g);
     {
@@ -1417,6 +1418,7 @@ __device__ inline void write_none(const MatchOut &O, int32_t i) {
         for (int k = 0; k < 9; k++) O.strain[9 * (int64_t)i + k] = 0.0;
     if (O.neighbours)
         for (int m = 0; m < KMAX; m++) O.neighbours[(int64_t)i * KMAX + m] = -1;
+    if (O.best_type) O.best_type[i] = 0;
     if (O.vm_strain) O.vm_strain[i] = 0.0;
     if (O.strain_residual) O.strain_residual[i] = 0.0;
     if (O.nn_distance) O.nn_distance[i] = 0.0;
@@ -1686,6 +1688,53 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
             else finish<14, double>(M, T, 2, wc, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
         }
     }
+}
+
+// ------------------------------------------------- post-hoc cut-off (Sec. 5.1)
+__global__ void __launch_bounds__(256) k_apply_cutoff(int64_t n, const int8_t *__restrict__ best_type,
+                                                      const double *__restrict__ rmsd, double cutoff,
+                                                      int8_t *__restrict__ type) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) type[i] = rmsd[i] <= cutoff ? best_type[i] : (int8_t)0;
+}
+
+// per-type histograms: a block-private copy in LDS, then one atomic add per
+// non-zero bin into the global counts
+constexpr int HIST_LDS_BINS = 6 * 1024;
+__global__ void __launch_bounds__(256) k_rmsd_histogram(int64_t n, const int8_t *__restrict__ best_type,
+                                                        const double *__restrict__ rmsd, int nbins, double rmax,
+                                                        double inv, unsigned long long *__restrict__ counts) {
+    __shared__ unsigned int h[HIST_LDS_BINS];
+    const bool lds = 6 * nbins <= HIST_LDS_BINS;
+    if (lds)
+        for (int b = threadIdx.x; b < 6 * nbins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int t = best_type[i];
+        if (t < 0 || t > 5) continue;
+        const double r = rmsd[i];
+        int b = nbins - 1;
+        if (r < rmax) b = min(nbins - 1, max(0, (int)(r * inv)));
+        if (lds) atomicAdd(&h[t * nbins + b], 1u);
+        else atomicAdd(&counts[t * nbins + b], 1ull);
+    }
+    __syncthreads();
+    if (lds)
+        for (int b = threadIdx.x; b < 6 * nbins; b += blockDim.x)
+            if (h[b]) atomicAdd(&counts[b], (unsigned long long)h[b]);
+}
+
+void launch_apply_cutoff(int64_t n, const int8_t *best_type, const double *rmsd, double cutoff, int8_t *type,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_cutoff, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, best_type, rmsd,
+                       cutoff, type);
+}
+void launch_rmsd_histogram(int64_t n, const int8_t *best_type, const double *rmsd, int nbins, double rmax,
+                           unsigned long long *counts, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    const double inv = (double)nbins / rmax;  // the bin of r is floor(r * inv), inv rounded once on the host
+    hipLaunchKernelGGL(k_rmsd_histogram, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, best_type,
+                       rmsd, nbins, rmax, inv, counts);
 }
 
 // ------------------------------------------------------- misorientation

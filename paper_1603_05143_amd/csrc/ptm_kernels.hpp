@@ -32,6 +32,7 @@ struct MatchOut {
     double *strain_residual;
     double *nn_distance;
     double *quat_fz;
+    int8_t *best_type;
 };
 
 // Flat (atom, candidate) pair list of the match stage.
@@ -73,6 +74,11 @@ void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, cons
                    uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
                    int32_t *todo_count, bool f32, hipStream_t st);
 
+// post-hoc cut-off and RMSD histograms (counts: device, 6 * nbins, zeroed by the caller)
+void launch_apply_cutoff(int64_t n, const int8_t *best_type, const double *rmsd, double cutoff, int8_t *type,
+                         hipStream_t st);
+void launch_rmsd_histogram(int64_t n, const int8_t *best_type, const double *rmsd, int nbins, double rmax,
+                           unsigned long long *counts, hipStream_t st);
 // misorientation angles of orientation pairs under each template's symmetry
 void launch_misorientation(int64_t n, const TablesView &T, const int8_t *type, const double *q1, const double *q2,
                            double *angle, hipStream_t st);

@@ -71,6 +71,7 @@ static size_t staging_bytes(int64_t n) {
     add(8 * (size_t)n);    // strain_residual
     add(8 * (size_t)n);    // nn_distance
     add(32 * (size_t)n);   // quat_fz
+    add((size_t)n);        // best_type
     return a;
 }
 
@@ -114,6 +115,7 @@ ptm_status stage_in_buffers(ptm_ctx *ctx, StagingBuffers &B, const double *posit
     d.strain_residual = (double *)take(8 * (size_t)n);
     d.nn_distance = (double *)take(8 * (size_t)n);
     d.quat_fz = (double *)take(32 * (size_t)n);
+    d.best_type = (int8_t *)take((size_t)n);
     if (!out->alloy) d.alloy = nullptr;
     if (!out->rmsd) d.rmsd = nullptr;
     if (!out->scale) d.scale = nullptr;
@@ -125,6 +127,7 @@ ptm_status stage_in_buffers(ptm_ctx *ctx, StagingBuffers &B, const double *posit
     if (!out->strain_residual) d.strain_residual = nullptr;
     if (!out->nn_distance) d.nn_distance = nullptr;
     if (!out->quat_fz) d.quat_fz = nullptr;
+    if (!out->best_type) d.best_type = nullptr;
     PTM_HIP(ctx, hipMemcpyAsync(dpos, positions, 24 * (size_t)n, hipMemcpyHostToDevice, st));
     if (species) PTM_HIP(ctx, hipMemcpyAsync(dspc, species, (size_t)n, hipMemcpyHostToDevice, st));
     J.pos = dpos;
@@ -162,6 +165,7 @@ ptm_status stage_out(ptm_ctx *ctx, const ptm_outputs *out, int64_t n, const Fram
     if ((s = cp(h.strain_residual, d.strain_residual, 8 * (size_t)n)) != PTM_OK) return s;
     if ((s = cp(h.nn_distance, d.nn_distance, 8 * (size_t)n)) != PTM_OK) return s;
     if ((s = cp(h.quat_fz, d.quat_fz, 32 * (size_t)n)) != PTM_OK) return s;
+    if ((s = cp(h.best_type, d.best_type, (size_t)n)) != PTM_OK) return s;
     return PTM_OK;
 }
 

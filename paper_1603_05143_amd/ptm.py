@@ -30,7 +30,7 @@ class ptm_config(C.Structure):
 
 
 OUTPUT_FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn",
-                 "vm_strain", "strain_residual", "nn_distance", "quat_fz")
+                 "vm_strain", "strain_residual", "nn_distance", "quat_fz", "best_type")
 
 
 class ptm_outputs(C.Structure):
@@ -82,6 +82,10 @@ def lib():
         L.ptm_frame_info.restype = C.c_int
         L.ptm_misorientation.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
         L.ptm_misorientation.restype = C.c_int
+        L.ptm_apply_cutoff.argtypes = [vp, vp, vp, C.c_int64, C.c_double, vp]
+        L.ptm_apply_cutoff.restype = C.c_int
+        L.ptm_rmsd_histogram.argtypes = [vp, vp, vp, C.c_int64, C.c_int, C.c_double, C.POINTER(C.c_int64)]
+        L.ptm_rmsd_histogram.restype = C.c_int
         _lib = L
     return _lib
 
@@ -153,6 +157,17 @@ def ptm_misorientation(ctx, type_ptr, q1_ptr, q2_ptr, n, angle_ptr):
     return lib().ptm_misorientation(ctx, type_ptr, q1_ptr, q2_ptr, int(n), angle_ptr)
 
 
+def ptm_apply_cutoff(ctx, best_type_ptr, rmsd_ptr, n, cutoff, type_ptr):
+    return lib().ptm_apply_cutoff(ctx, best_type_ptr, rmsd_ptr, int(n), float(cutoff), type_ptr)
+
+
+def ptm_rmsd_histogram(ctx, best_type_ptr, rmsd_ptr, n, nbins, rmax):
+    """Returns (status, counts[6][nbins] as a list of lists)."""
+    counts = (C.c_int64 * (6 * int(nbins)))()
+    st = lib().ptm_rmsd_histogram(ctx, best_type_ptr, rmsd_ptr, int(n), int(nbins), float(rmax), counts)
+    return st, [list(counts[t * nbins:(t + 1) * nbins]) for t in range(6)]
+
+
 def ptm_template_info(t: int):
     info = (C.c_int64 * 5)()
     st = lib().ptm_template_info(t, info)
@@ -183,7 +198,7 @@ class Classifier:
             pass
 
     @staticmethod
-    def alloc_outputs(n: int, device: str, knn: bool = False, derived: bool = False):
+    def alloc_outputs(n: int, device: str, knn: bool = False, derived: bool = False, best_type: bool = False):
         import torch
         out = {
             "type": torch.empty(n, dtype=torch.int8, device=device),
@@ -200,6 +215,8 @@ class Classifier:
             for k in ("vm_strain", "strain_residual", "nn_distance"):
                 out[k] = torch.empty(n, dtype=torch.float64, device=device)
             out["quat_fz"] = torch.empty((n, 4), dtype=torch.float64, device=device)
+        if derived or best_type:
+            out["best_type"] = torch.empty(n, dtype=torch.int8, device=device)
         return out
 
     @staticmethod
@@ -210,13 +227,13 @@ class Classifier:
         return ptm_outputs(*[p(k) for k in OUTPUT_FIELDS])
 
     def classify(self, positions, box, species=None, mask=PTM_ALL, cutoff=float("inf"), out=None, knn=False,
-                 derived=False):
+                 derived=False, best_type=False):
         """positions: (n,3) float64 CUDA tensor; returns dict of output tensors."""
         import torch
         assert positions.is_cuda and positions.dtype == torch.float64 and positions.is_contiguous()
         n = positions.shape[0]
         if out is None:
-            out = self.alloc_outputs(n, positions.device, knn, derived)
+            out = self.alloc_outputs(n, positions.device, knn, derived, best_type)
         sp = None
         if species is not None:
             assert species.is_cuda and species.dtype == torch.int8 and species.is_contiguous()
@@ -226,3 +243,25 @@ class Classifier:
         if st != PTM_OK:
             raise PTMError(st, ptm_last_error(self.ctx))
         return out
+
+    def apply_cutoff(self, out, cutoff):
+        """Types under a new RMSD cut-off from the outputs of a classify call
+        that kept best_type; returns a new int8 tensor."""
+        import torch
+        n = out["rmsd"].shape[0]
+        t = torch.empty(n, dtype=torch.int8, device=out["rmsd"].device)
+        st = ptm_apply_cutoff(self.ctx, out["best_type"].data_ptr() if n else None,
+                              out["rmsd"].data_ptr() if n else None, n, cutoff, t.data_ptr() if n else None)
+        if st != PTM_OK:
+            raise PTMError(st, ptm_last_error(self.ctx))
+        return t
+
+    def rmsd_histogram(self, out, nbins, rmax):
+        """Per-type RMSD histograms (6 x nbins int64 numpy array)."""
+        import numpy as np
+        n = out["rmsd"].shape[0]
+        st, counts = ptm_rmsd_histogram(self.ctx, out["best_type"].data_ptr() if n else None,
+                                        out["rmsd"].data_ptr() if n else None, n, nbins, rmax)
+        if st != PTM_OK:
+            raise PTMError(st, ptm_last_error(self.ctx))
+        return np.array(counts, dtype=np.int64)

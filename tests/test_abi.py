@@ -63,6 +63,8 @@ def test_status_strings_and_errors_without_device(ptm):
     assert st == ptm.PTM_E_INVALID
     assert ptm.ptm_misorientation(None, None, None, None, 1, None) == ptm.PTM_E_INVALID
     assert ptm.lib().ptm_frame_info(None, None, 0) == ptm.PTM_E_INVALID
+    assert ptm.ptm_apply_cutoff(None, None, None, 1, 0.1, None) == ptm.PTM_E_INVALID
+    assert ptm.ptm_rmsd_histogram(None, None, None, 1, 10, 0.3)[0] == ptm.PTM_E_INVALID
     try:
         import torch
         has_gpu = torch.cuda.is_available()

@@ -32,10 +32,18 @@ def _gpu_sample(torch, precision, f, atoms):
     try:
         pos = torch.from_numpy(np.ascontiguousarray(f.positions)).to("cuda:0")
         sp = None if f.species is None else torch.from_numpy(f.species).to("cuda:0")
-        out = c.classify(pos, f.box, species=sp, knn=True)
+        out = c.classify(pos, f.box, species=sp, knn=True, best_type=True)
         idx = torch.from_numpy(np.asarray(atoms, dtype=np.int64)).to("cuda:0")
         res = {k: out[k].index_select(0, idx).cpu().numpy() for k in FIELDS}
         types = torch.bincount(out["type"].long(), minlength=6).cpu().numpy()
+        # post-hoc outputs over the whole frame (properties that hold at any
+        # size): without a cut-off the best match is the type, and the RMSD
+        # histograms hold every atom under its type
+        assert torch.equal(out["best_type"], out["type"])
+        hist = c.rmsd_histogram(out, 200, 0.5)
+        assert np.array_equal(hist.sum(axis=1), types), (hist.sum(axis=1), types)
+        half = c.apply_cutoff(out, 0.1)
+        assert torch.equal(half, torch.where(out["rmsd"] <= 0.1, out["type"], torch.zeros_like(half)))
         del out, pos, sp
         torch.cuda.synchronize()
     finally:

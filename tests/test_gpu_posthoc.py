@@ -1,0 +1,182 @@
+"""GPU parity of the post-hoc cut-off and the per-type RMSD histograms
+(Sec. 5.1) against oracle/posthoc.py, through the C ABI.
+
+* best_type from a classify call equals the oracle's best match, bit-exact,
+  whatever cut-off the call used;
+* ptm_apply_cutoff on the stored best matches equals the oracle's rule on
+  the oracle's matches (pinned on the CPU against the oracle pipeline run
+  with that cut-off); atoms whose RMSD lies within the form's RMSD tolerance
+  of the cut-off may go either way and are checked to be valid instead;
+* ptm_rmsd_histogram is bit-exact against the oracle on seeded synthetic
+  (best_type, rmsd) arrays that hold values on bin edges, overflow and
+  non-finite values, for bin counts on both the LDS and the global-memory
+  path; end to end, a frame's histograms differ from the oracle's only by
+  atoms within the tolerance of a bin edge;
+* device and host-pointer contexts agree; empty input; argument errors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1603_05143_amd import ptm, synthetic as S
+from parity_util import TOL32, TOL64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P(oracle_lib):
+    from oracle import posthoc
+    return posthoc
+
+
+@pytest.fixture(scope="module")
+def noisy(oracle_lib):
+    """A thermally disordered FCC/BCC bicrystal with free surfaces: RMSD
+    values spread over a range, with some atoms matched to other templates."""
+    rng = np.random.default_rng(31)
+    a = S.perfect_crystal("fcc", reps=(8, 8, 4), a=3.615)
+    b = S.perfect_crystal("bcc", reps=(10, 10, 5), a=2.87)
+    pos = np.vstack([a.positions, b.positions + [0, 0, a.box[2] + 1.6]])
+    pos = pos + rng.normal(scale=0.1, size=pos.shape)
+    box = np.zeros(3)  # open boundaries: surface atoms add NONE and stray matches
+    ref = oracle_lib.classify(pos, box)
+    return pos, box, ref
+
+
+def _classify(torch, precision, pos, box, cutoff=math.inf):
+    print(f"[posthoc] n={len(pos)} precision={precision} cutoff={cutoff}", flush=True)
+    c = ptm.Classifier(device=0, precision=precision)
+    dpos = torch.from_numpy(np.ascontiguousarray(pos)).to("cuda:0")
+    out = c.classify(dpos, box, cutoff=cutoff, best_type=True)
+    torch.cuda.synchronize()
+    return c, out
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_best_type_and_cutoff_afterwards(torch_cuda, P, noisy, precision):
+    pos, box, ref = noisy
+    tol = (TOL64 if precision == ptm.PTM_FP64 else TOL32)["rmsd"]
+    r = ref["rmsd"]
+    finite = np.sort(r[np.isfinite(r)])
+    assert np.unique(ref["type"]).size >= 3, np.bincount(ref["type"])
+    c, out = _classify(torch_cuda, precision, pos, box)
+    try:
+        bt = out["best_type"].cpu().numpy()
+        assert np.array_equal(bt, ref["type"])
+        assert np.array_equal(out["type"].cpu().numpy(), ref["type"])
+        got_r = out["rmsd"].cpu().numpy()
+        fin = np.isfinite(r)
+        assert np.array_equal(fin, np.isfinite(got_r)) and np.max(np.abs(got_r[fin] - r[fin])) <= tol
+        cuts = [float(np.quantile(finite, q)) for q in (0.05, 0.3, 0.6, 0.95)] + [float(finite[101]), 0.0,
+                                                                                   math.inf]
+        for cut in cuts:
+            got = c.apply_cutoff(out, cut).cpu().numpy()
+            want = P.apply_cutoff(ref["type"], r, cut)
+            band = np.abs(r - cut) <= tol if math.isfinite(cut) else np.zeros(len(r), bool)
+            assert np.array_equal(got[~band], want[~band]), cut
+            assert np.all((got[band] == 0) | (got[band] == ref["type"][band]))
+        # classify with a cut-off keeps the best match in best_type
+        cut = float(np.quantile(finite, 0.5))
+        c2, out2 = _classify(torch_cuda, precision, pos, box, cutoff=cut)
+        try:
+            assert np.array_equal(out2["best_type"].cpu().numpy(), ref["type"])
+            t2 = out2["type"].cpu().numpy()
+            band = np.abs(r - cut) <= tol
+            assert np.array_equal(t2[~band], P.apply_cutoff(ref["type"], r, cut)[~band])
+            assert np.sum(t2 == 0) > 0.3 * len(t2)
+        finally:
+            c2.close()
+    finally:
+        c.close()
+
+
+def _synthetic_pairs(seed, n, nbins, rmax):
+    rng = np.random.default_rng(seed)
+    t = rng.integers(0, 6, n).astype(np.int8)
+    r = rng.uniform(0, 1.2 * rmax, n)
+    k = rng.integers(0, nbins + 1, n // 10)
+    r[: n // 10] = k * (rmax / nbins)  # bin edges, as the host forms them
+    r[n // 10: n // 10 + 50] = np.inf
+    r[n // 10 + 50: n // 10 + 80] = np.nan
+    r[n // 10 + 80: n // 10 + 100] = rmax
+    r[n // 10 + 100: n // 10 + 120] = np.nextafter(rmax, 0.0)
+    return t, r
+
+
+@pytest.mark.parametrize("nbins", [1, 50, 1024, 1025, 40000])
+def test_histogram_exact_synthetic(torch_cuda, P, nbins):
+    torch = torch_cuda
+    n, rmax = 300_000, 0.37
+    t, r = _synthetic_pairs(nbins, n, nbins, rmax)
+    want = P.rmsd_histograms(t, r, nbins, rmax)
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    try:
+        dt = torch.from_numpy(t).to("cuda:0")
+        dr = torch.from_numpy(r).to("cuda:0")
+        print(f"[hist] nbins={nbins} n={n}", flush=True)
+        st, got = ptm.ptm_rmsd_histogram(ctx, dt.data_ptr(), dr.data_ptr(), n, nbins, rmax)
+        assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+        assert np.array_equal(np.array(got), want)
+        assert np.array(got).sum() == n
+    finally:
+        ptm.ptm_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_histogram_end_to_end(torch_cuda, P, noisy, precision):
+    pos, box, ref = noisy
+    tol = (TOL64 if precision == ptm.PTM_FP64 else TOL32)["rmsd"]
+    nbins, rmax = 64, 0.3
+    want = P.rmsd_histograms(ref["type"], ref["rmsd"], nbins, rmax)
+    c, out = _classify(torch_cuda, precision, pos, box)
+    try:
+        got = c.rmsd_histogram(out, nbins, rmax)
+    finally:
+        c.close()
+    r = ref["rmsd"]
+    frac = np.where(np.isfinite(r), r, 0.0) * (nbins / rmax)
+    near = np.isfinite(r) & (np.abs(frac - np.round(frac)) <= tol * (nbins / rmax))
+    assert np.array_equal(got.sum(axis=1), want.sum(axis=1))
+    assert np.abs(got - want).sum() <= 2 * int(near.sum())
+    assert want[2].sum() > 0 and want[5].sum() > 0  # FCC and BCC rows are populated
+
+
+def test_host_pointers_empty_and_errors(torch_cuda, P):
+    torch = torch_cuda
+    n, nbins, rmax = 50_000, 30, 0.2
+    t, r = _synthetic_pairs(77, n, nbins, rmax)
+    want_h = P.rmsd_histograms(t, r, nbins, rmax)
+    want_c = P.apply_cutoff(t, r, 0.1)
+    hctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, ptm.PTM_F_HOST_POINTERS)
+    ctx = ptm.ptm_create(0, ptm.PTM_FP32_MIXED, None, 0, 0)
+    try:
+        out = np.zeros(n, np.int8)
+        st = ptm.ptm_apply_cutoff(hctx, t.ctypes.data, r.ctypes.data, n, 0.1, out.ctypes.data)
+        assert st == ptm.PTM_OK, ptm.ptm_last_error(hctx)
+        assert np.array_equal(out, want_c)
+        st, h = ptm.ptm_rmsd_histogram(hctx, t.ctypes.data, r.ctypes.data, n, nbins, rmax)
+        assert st == ptm.PTM_OK and np.array_equal(np.array(h), want_h)
+        # empty input: zero counts, nothing written
+        st, h = ptm.ptm_rmsd_histogram(ctx, None, None, 0, nbins, rmax)
+        assert st == ptm.PTM_OK and np.array(h).sum() == 0
+        assert ptm.ptm_apply_cutoff(ctx, None, None, 0, 0.1, None) == ptm.PTM_OK
+        # argument errors
+        dt = torch.from_numpy(t).to("cuda:0")
+        dr = torch.from_numpy(r).to("cuda:0")
+        for nb, rm in ((0, rmax), (65537, rmax), (nbins, 0.0), (nbins, -1.0), (nbins, math.nan)):
+            assert ptm.ptm_rmsd_histogram(ctx, dt.data_ptr(), dr.data_ptr(), n, nb, rm)[0] == ptm.PTM_E_INVALID
+        assert ptm.ptm_rmsd_histogram(ctx, None, dr.data_ptr(), n, nbins, rmax)[0] == ptm.PTM_E_INVALID
+        assert ptm.ptm_apply_cutoff(ctx, dt.data_ptr(), None, n, 0.1, dt.data_ptr()) == ptm.PTM_E_INVALID
+        assert ptm.ptm_apply_cutoff(ctx, dt.data_ptr(), dr.data_ptr(), -1, 0.1, dt.data_ptr()) == ptm.PTM_E_INVALID
+    finally:
+        ptm.ptm_destroy(hctx)
+        ptm.ptm_destroy(ctx)

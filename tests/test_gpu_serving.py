@@ -42,7 +42,7 @@ def _alone(torch, precision, frames):
     res = []
     for f in frames:
         pos, sp = _device_frame(torch, f)
-        out = c.classify(pos, f.box, species=sp, knn=True)
+        out = c.classify(pos, f.box, species=sp, knn=True, derived=True)
         torch.cuda.synchronize()
         res.append({k: v.cpu().numpy() for k, v in out.items()})
     c.close()
@@ -53,7 +53,7 @@ def _submit_all(torch, ctx, frames):
     keep, tickets = [], []
     for f in frames:
         pos, sp = _device_frame(torch, f)
-        out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
+        out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True, derived=True)
         o = ptm.Classifier.outputs_struct(out)
         st, t = ptm.ptm_submit(ctx, pos.data_ptr(), None if sp is None else sp.data_ptr(), f.box, f.n,
                                ptm.PTM_ALL, math.inf, o)
@@ -78,7 +78,9 @@ def test_mixed_equals_alone(torch_cuda, frames, precision):
                 stats.append((s.submit_time_us, s.start_time_us, s.complete_time_us, s.n_atoms))
             for (pos, sp, out, o), r, f in zip(keep, ref, frames):
                 got = {k: v.cpu().numpy() for k, v in out.items()}
-                for k in FIELDS:
+                assert set(got) == set(FIELDS) | {"vm_strain", "strain_residual", "nn_distance", "quat_fz",
+                                                  "best_type"}
+                for k in got:
                     assert np.array_equal(got[k], r[k], equal_nan=True), (rep, f.n, k)
             for sub, start, done, n in stats:
                 assert sub <= start <= done + 1e3, (sub, start, done)
