@@ -149,6 +149,91 @@ def run_gpu(frame, precision, steps, warmup):
             "stage_ms": {s: acc[i] / steps for i, s in enumerate(STAGES)}, "types": types, "info": info}
 
 
+def derived_overhead(frame, steps, warmup):
+    """FP32-mixed frame time with every output of the widened rows requested
+    (von Mises strain, eq.(6) residual, implied nearest-neighbour distance,
+    fundamental-zone orientation, best match for the post-hoc cut-off)."""
+    import torch
+    from paper_1603_05143_amd import ptm
+    pos = torch.from_numpy(frame.positions).to("cuda:0")
+    ctx = ptm.ptm_create(0, ptm.PTM_FP32_MIXED, None, 0, 0)
+    out = ptm.Classifier.alloc_outputs(frame.n, "cuda:0", derived=True)
+    o = ptm.Classifier.outputs_struct(out)
+    try:
+        for k in range(warmup + steps):
+            if k == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            st = ptm.ptm_classify(ctx, pos.data_ptr(), None, frame.box, frame.n, ptm.PTM_ALL, math.inf, o)
+            if st != ptm.PTM_OK:
+                raise RuntimeError(ptm.ptm_last_error(ctx))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+    finally:
+        ptm.ptm_destroy(ctx)
+    return ms
+
+
+def posthoc_bench(n, reps=10):
+    """Device time of the post-hoc entry points (HIP events on the stream the
+    library launches on) over n seeded synthetic best matches with RMSDs
+    spread like a thermal frame, and of ptm_misorientation over n / 4 pairs.
+    All three are HBM-bound: bytes are the arrays read and written once."""
+    import torch
+    from paper_1603_05143_amd import ptm
+    stream = torch.cuda.Stream()  # default priority; the library launches on it
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, stream.cuda_stream, 0, 0)
+    res = {}
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def entry(name, ms, nbytes, count):
+        gbs = nbytes / (ms / 1e3) / 1e9
+        res[name] = {"n": count, "ms": round(ms, 4), "GB_s": round(gbs, 1),
+                     "frac_of_hbm": round(gbs / PEAK_HBM_GBS, 3)}
+
+    try:
+        with torch.cuda.stream(stream):
+            g = torch.Generator(device="cuda:0")
+            g.manual_seed(160305143)
+            bt = torch.randint(0, 6, (n,), dtype=torch.int8, device="cuda:0", generator=g)
+            r = 0.02 + 0.08 * torch.rand(n, dtype=torch.float64, device="cuda:0", generator=g)
+            ty = torch.empty(n, dtype=torch.int8, device="cuda:0")
+            stream.synchronize()
+            entry("apply_cutoff", timed(lambda: _ok(ptm.ptm_apply_cutoff(ctx, bt.data_ptr(), r.data_ptr(), n, 0.06,
+                                                                         ty.data_ptr()))), 10 * n, n)
+            entry("rmsd_histogram", timed(lambda: _ok(ptm.ptm_rmsd_histogram(ctx, bt.data_ptr(), r.data_ptr(), n,
+                                                                             100, 0.3)[0])), 9 * n, n)
+            del bt, r, ty
+            m = n // 4
+            q = torch.randn((2, m, 4), dtype=torch.float64, device="cuda:0", generator=g)
+            q = q / q.norm(dim=-1, keepdim=True)
+            q1, q2 = q[0].contiguous(), q[1].contiguous()
+            tm = torch.randint(1, 6, (m,), dtype=torch.int8, device="cuda:0", generator=g)
+            ang = torch.empty(m, dtype=torch.float64, device="cuda:0")
+            stream.synchronize()
+            entry("misorientation", timed(lambda: _ok(ptm.ptm_misorientation(ctx, tm.data_ptr(), q1.data_ptr(),
+                                                                             q2.data_ptr(), m, ang.data_ptr()))),
+                  73 * m, m)
+    finally:
+        stream.synchronize()
+        ptm.ptm_destroy(ctx)
+    return res
+
+
+def _ok(status):
+    if status != 0:
+        raise RuntimeError(f"post-hoc entry point failed with status {status}")
+
+
 def _mono_us():
     return time.clock_gettime(time.CLOCK_MONOTONIC) * 1e6  # the clock of ptm_frame_stats
 
@@ -329,6 +414,10 @@ def main():
     roof["work_per_launch"] = work
     roof["work_unit"] = unit
 
+    derived_ms = derived_overhead(frame, args.steps, args.warmup)
+    posthoc = posthoc_bench(1 << 27)
+    print(f"[bench] derived outputs {derived_ms:.2f} ms/step; post-hoc {posthoc}", file=sys.stderr, flush=True)
+
     serving = None
     if not args.no_serve:
         serving = serving_bench(args.serve_frames, args.serve_pool, ring=24, budget_gb=200.0)
@@ -355,6 +444,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "types": dict(zip(ptm.TYPE_NAMES, main_run["types"])),
         "roofline": roof,
+        "derived_outputs_ms_per_step": round(derived_ms, 4),
+        "posthoc": posthoc,
         "serving": serving,
         "cpu_baseline": cpu,
     }

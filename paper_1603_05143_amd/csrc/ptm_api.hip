@@ -376,6 +376,7 @@ void ptm_destroy(ptm_ctx *ctx) {
     ctx->main.release();
     ctx->staging.release();
     for (void *p : ctx->table_buffers) (void)hipFree(p);
+    if (ctx->aux) (void)hipFree(ctx->aux);
     for (int e = 0; e <= PTM_NSTAGES; e++)
         if (ctx->prof_ev[e]) (void)hipEventDestroy(ctx->prof_ev[e]);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -586,12 +587,22 @@ ptm_status ptm_rmsd_histogram(ptm_ctx *ctx, const int8_t *best_type, const doubl
     if (ctx->flags & PTM_F_HOST_POINTERS) {
         st = stage_pair(ctx, best_type, rmsd, n, &buf, &dt, &dr, cbytes + 256);
         if (st == PTM_OK) dc = (unsigned long long *)(((uintptr_t)(dt + n) + 255) & ~(uintptr_t)255);
-    } else if (hipMalloc(&buf, cbytes) != hipSuccess) {
-        (void)hipGetLastError();
-        ctx->err = "ptm_rmsd_histogram: allocation failed";
-        st = PTM_E_NOMEM;
     } else {
-        dc = (unsigned long long *)buf;
+        if (ctx->aux_bytes < cbytes) {
+            // grow-only: later calls of this size allocate nothing
+            if (ctx->aux) (void)hipFree(ctx->aux);
+            ctx->aux = nullptr;
+            ctx->aux_bytes = 0;
+            if (hipMalloc(&ctx->aux, cbytes) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->aux = nullptr;
+                ctx->err = "ptm_rmsd_histogram: allocation failed";
+                st = PTM_E_NOMEM;
+            } else {
+                ctx->aux_bytes = cbytes;
+            }
+        }
+        dc = (unsigned long long *)ctx->aux;
     }
     if (st == PTM_OK) {
         if (hipMemsetAsync(dc, 0, cbytes, ctx->stream) != hipSuccess) st = PTM_E_DEVICE;

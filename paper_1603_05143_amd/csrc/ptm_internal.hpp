@@ -135,4 +135,7 @@ struct ptm_ctx {
     hipEvent_t prof_ev[PTM_NSTAGES + 1] = {};
     bool prof_valid = false;
     int64_t prof_info[PTM_NINFO] = {};
+    // grow-only device buffer of the small per-call outputs (histogram counts)
+    void *aux = nullptr;
+    size_t aux_bytes = 0;
 };

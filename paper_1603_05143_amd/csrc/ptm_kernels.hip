@@ -1691,17 +1691,45 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
 }
 
 // ------------------------------------------------- post-hoc cut-off (Sec. 5.1)
-__global__ void __launch_bounds__(256) k_apply_cutoff(int64_t n, const int8_t *__restrict__ best_type,
+// Both kernels are HBM streams.  Lanes take eight atoms each (one 8-byte
+// load of types, four 16-byte loads of RMSDs) when the arrays are aligned
+// for it; atoms past the last full group of eight, or misaligned arrays, go
+// one per lane.
+__device__ inline int8_t cut_one(int8_t t, double r, double cutoff) { return r <= cutoff ? t : (int8_t)0; }
+
+__global__ void __launch_bounds__(256) k_apply_cutoff(int64_t n, int64_t n8, const int8_t *__restrict__ best_type,
                                                       const double *__restrict__ rmsd, double cutoff,
                                                       int8_t *__restrict__ type) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) type[i] = rmsd[i] <= cutoff ? best_type[i] : (int8_t)0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n8; g += stride) {
+        const uint64_t t8 = ((const uint64_t *)best_type)[g];
+        const double2 *r2 = (const double2 *)rmsd + 4 * g;
+        uint64_t o = 0;
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+            const double2 r = r2[h];
+            o |= (uint64_t)(uint8_t)cut_one((int8_t)(t8 >> (16 * h)), r.x, cutoff) << (16 * h);
+            o |= (uint64_t)(uint8_t)cut_one((int8_t)(t8 >> (16 * h + 8)), r.y, cutoff) << (16 * h + 8);
+        }
+        ((uint64_t *)type)[g] = o;
+    }
+    for (int64_t i = 8 * n8 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+        type[i] = cut_one(best_type[i], rmsd[i], cutoff);
 }
 
-// per-type histograms: a block-private copy in LDS, then one atomic add per
-// non-zero bin into the global counts
+// per-type histograms: a block-private copy in LDS (when 6 * nbins fits),
+// then one atomic add per non-zero bin into the global counts
 constexpr int HIST_LDS_BINS = 6 * 1024;
-__global__ void __launch_bounds__(256) k_rmsd_histogram(int64_t n, const int8_t *__restrict__ best_type,
+__device__ inline void hist_add(unsigned int *h, unsigned long long *counts, bool lds, int t, double r, int nbins,
+                                double rmax, double inv) {
+    if (t < 0 || t > 5) return;
+    int b = nbins - 1;
+    if (r < rmax) b = min(nbins - 1, max(0, (int)(r * inv)));
+    if (lds) atomicAdd(&h[t * nbins + b], 1u);
+    else atomicAdd(&counts[t * nbins + b], 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_rmsd_histogram(int64_t n, int64_t n8, const int8_t *__restrict__ best_type,
                                                         const double *__restrict__ rmsd, int nbins, double rmax,
                                                         double inv, unsigned long long *__restrict__ counts) {
     __shared__ unsigned int h[HIST_LDS_BINS];
@@ -1709,74 +1737,129 @@ __global__ void __launch_bounds__(256) k_rmsd_histogram(int64_t n, const int8_t 
     if (lds)
         for (int b = threadIdx.x; b < 6 * nbins; b += blockDim.x) h[b] = 0;
     __syncthreads();
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int t = best_type[i];
-        if (t < 0 || t > 5) continue;
-        const double r = rmsd[i];
-        int b = nbins - 1;
-        if (r < rmax) b = min(nbins - 1, max(0, (int)(r * inv)));
-        if (lds) atomicAdd(&h[t * nbins + b], 1u);
-        else atomicAdd(&counts[t * nbins + b], 1ull);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n8; g += stride) {
+        const uint64_t t8 = ((const uint64_t *)best_type)[g];
+        const double2 *r2 = (const double2 *)rmsd + 4 * g;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const double2 r = r2[q];
+            hist_add(h, counts, lds, (int8_t)(t8 >> (16 * q)), r.x, nbins, rmax, inv);
+            hist_add(h, counts, lds, (int8_t)(t8 >> (16 * q + 8)), r.y, nbins, rmax, inv);
+        }
     }
+    for (int64_t i = 8 * n8 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+        hist_add(h, counts, lds, best_type[i], rmsd[i], nbins, rmax, inv);
     __syncthreads();
     if (lds)
         for (int b = threadIdx.x; b < 6 * nbins; b += blockDim.x)
             if (h[b]) atomicAdd(&counts[b], (unsigned long long)h[b]);
 }
 
+// groups of eight atoms a lane can load as one 8-byte word of types and four
+// 16-byte words of RMSDs (0 if the arrays are not aligned for that)
+static int64_t groups_of_eight(int64_t n, const void *t, const void *r, const void *out) {
+    const bool ok = ((uintptr_t)t % 8 == 0) && ((uintptr_t)r % 16 == 0) && (!out || (uintptr_t)out % 8 == 0);
+    return ok ? n / 8 : 0;
+}
+static unsigned stream_blocks(int64_t n) {
+    // about eight resident blocks per CU of 256 lanes, each lane striding
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256 * 8));
+}
+
 void launch_apply_cutoff(int64_t n, const int8_t *best_type, const double *rmsd, double cutoff, int8_t *type,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_apply_cutoff, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, best_type, rmsd,
+    const int64_t n8 = groups_of_eight(n, best_type, rmsd, type);
+    hipLaunchKernelGGL(k_apply_cutoff, dim3(stream_blocks(n8 > 0 ? n8 : n)), dim3(256), 0, st, n, n8, best_type, rmsd,
                        cutoff, type);
 }
 void launch_rmsd_histogram(int64_t n, const int8_t *best_type, const double *rmsd, int nbins, double rmax,
                            unsigned long long *counts, hipStream_t st) {
+    const int64_t n8 = groups_of_eight(n, best_type, rmsd, nullptr);
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
     const double inv = (double)nbins / rmax;  // the bin of r is floor(r * inv), inv rounded once on the host
-    hipLaunchKernelGGL(k_rmsd_histogram, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, best_type,
-                       rmsd, nbins, rmax, inv, counts);
+    hipLaunchKernelGGL(k_rmsd_histogram, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, n, n8,
+                       best_type, rmsd, nbins, rmax, inv, counts);
 }
 
 // ------------------------------------------------------- misorientation
 // Sec. 7: smallest rotation angle of conj(q1) q2 q_h over the template's
 // proper rotations (identity only for type NONE), as 2 atan2(|v|, |w|) of
 // the best product, which stays accurate near zero.  Invalid types give NaN.
+template <bool Vec>
 __global__ void __launch_bounds__(256) k_misorientation(int64_t n, TablesView T, const int8_t *__restrict__ type,
                                                         const double *__restrict__ q1, const double *__restrict__ q2,
                                                         double *__restrict__ angle) {
+    // every template's rotation group, staged in LDS: lanes of one type read
+    // the same word (a broadcast)
+    __shared__ double4 G[NT * GMAX];
+    __shared__ int gbase[NT + 1];
+    if (threadIdx.x == 0) {
+        int b = 0;
+        for (int t = 0; t < NT; t++) {
+            gbase[t] = b;
+            b += T.tpl[t].ngroup;
+        }
+        gbase[NT] = b;
+    }
+    __syncthreads();
+    for (int t = 0; t < NT; t++)
+        for (int h = threadIdx.x; h < T.tpl[t].ngroup; h += blockDim.x) {
+            const double *g = T.tpl[t].gq[h];
+            G[gbase[t] + h] = make_double4(g[0], g[1], g[2], g[3]);
+        }
+    __syncthreads();
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int ty = type[i];
-    const double a0 = q1[4 * i], a1 = -q1[4 * i + 1], a2 = -q1[4 * i + 2], a3 = -q1[4 * i + 3];  // conj(q1)
-    const double b0 = q2[4 * i], b1 = q2[4 * i + 1], b2 = q2[4 * i + 2], b3 = q2[4 * i + 3];
+    double a0, a1, a2, a3, b0, b1, b2, b3;
+    if (Vec) {  // 16-byte aligned quaternion arrays
+        const double2 *p1 = (const double2 *)(q1 + 4 * i), *p2 = (const double2 *)(q2 + 4 * i);
+        const double2 u0 = p1[0], u1 = p1[1], v0 = p2[0], v1 = p2[1];
+        a0 = u0.x, a1 = -u0.y, a2 = -u1.x, a3 = -u1.y;  // conj(q1)
+        b0 = v0.x, b1 = v0.y, b2 = v1.x, b3 = v1.y;
+    } else {
+        a0 = q1[4 * i], a1 = -q1[4 * i + 1], a2 = -q1[4 * i + 2], a3 = -q1[4 * i + 3];
+        b0 = q2[4 * i], b1 = q2[4 * i + 1], b2 = q2[4 * i + 2], b3 = q2[4 * i + 3];
+    }
     const double m0 = a0 * b0 - a1 * b1 - a2 * b2 - a3 * b3, m1 = a0 * b1 + a1 * b0 + a2 * b3 - a3 * b2;
     const double m2 = a0 * b2 - a1 * b3 + a2 * b0 + a3 * b1, m3 = a0 * b3 + a1 * b2 - a2 * b1 + a3 * b0;
     if (ty < 0 || ty > NT) {
         angle[i] = NAN;
         return;
     }
-    double bw = fabs(m0), bv = sqrt(m1 * m1 + m2 * m2 + m3 * m3);
+    // the w of m q_h is a dot product: scan the group for the largest |w|,
+    // then form the vector part of that one product only
+    double bw = fabs(m0);
+    int best = -1;
     if (ty > 0) {
-        const TemplateDev &D = T.tpl[ty - 1];
-        for (int h = 0; h < D.ngroup; h++) {
-            const double *g = D.gq[h];
-            const double c0 = m0 * g[0] - m1 * g[1] - m2 * g[2] - m3 * g[3];
-            if (fabs(c0) > bw) {
-                const double c1 = m0 * g[1] + m1 * g[0] + m2 * g[3] - m3 * g[2];
-                const double c2 = m0 * g[2] - m1 * g[3] + m2 * g[0] + m3 * g[1];
-                const double c3 = m0 * g[3] + m1 * g[2] - m2 * g[1] + m3 * g[0];
-                bw = fabs(c0);
-                bv = sqrt(c1 * c1 + c2 * c2 + c3 * c3);
+        const int h0 = gbase[ty - 1], h1 = gbase[ty];
+        for (int h = h0; h < h1; h++) {
+            const double4 g = G[h];
+            const double c0 = fabs(m0 * g.x - m1 * g.y - m2 * g.z - m3 * g.w);
+            if (c0 > bw) {
+                bw = c0;
+                best = h;
             }
         }
     }
-    angle[i] = 2.0 * atan2(bv, bw);
+    double c1 = m1, c2 = m2, c3 = m3;
+    if (best >= 0) {
+        const double4 g = G[best];
+        c1 = m0 * g.y + m1 * g.x + m2 * g.w - m3 * g.z;
+        c2 = m0 * g.z - m1 * g.w + m2 * g.x + m3 * g.y;
+        c3 = m0 * g.w + m1 * g.z - m2 * g.y + m3 * g.x;
+    }
+    angle[i] = 2.0 * atan2(sqrt(c1 * c1 + c2 * c2 + c3 * c3), bw);
 }
 
 void launch_misorientation(int64_t n, const TablesView &T, const int8_t *type, const double *q1, const double *q2,
                            double *angle, hipStream_t st) {
-    hipLaunchKernelGGL(k_misorientation, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, type, q1, q2,
-                       angle);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if ((uintptr_t)q1 % 16 == 0 && (uintptr_t)q2 % 16 == 0)
+        hipLaunchKernelGGL(k_misorientation<true>, grid, dim3(256), 0, st, n, T, type, q1, q2, angle);
+    else
+        hipLaunchKernelGGL(k_misorientation<false>, grid, dim3(256), 0, st, n, T, type, q1, q2, angle);
 }
 
 // --------------------------------------------------------------- launches

@@ -112,10 +112,10 @@ def _synthetic_pairs(seed, n, nbins, rmax):
     return t, r
 
 
-@pytest.mark.parametrize("nbins", [1, 50, 1024, 1025, 40000])
-def test_histogram_exact_synthetic(torch_cuda, P, nbins):
+@pytest.mark.parametrize("nbins,n", [(1, 300_000), (50, 300_005), (1024, 300_000), (1025, 299_999), (40000, 300_000)])
+def test_histogram_exact_synthetic(torch_cuda, P, nbins, n):
     torch = torch_cuda
-    n, rmax = 300_000, 0.37
+    rmax = 0.37
     t, r = _synthetic_pairs(nbins, n, nbins, rmax)
     want = P.rmsd_histograms(t, r, nbins, rmax)
     ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
@@ -179,4 +179,48 @@ def test_host_pointers_empty_and_errors(torch_cuda, P):
         assert ptm.ptm_apply_cutoff(ctx, dt.data_ptr(), dr.data_ptr(), -1, 0.1, dt.data_ptr()) == ptm.PTM_E_INVALID
     finally:
         ptm.ptm_destroy(hctx)
+        ptm.ptm_destroy(ctx)
+
+
+def test_misaligned_and_ragged(torch_cuda, P):
+    """Arrays at offsets that rule out the eight-atom loads, and lengths that
+    leave a tail, through all three post-hoc entry points."""
+    import ctypes as C
+    from oracle import derived as OD
+    torch = torch_cuda
+    n, nbins, rmax = 100_003, 40, 0.25
+    t, r = _synthetic_pairs(5, n + 1, nbins, rmax)
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    try:
+        dt = torch.from_numpy(t).to("cuda:0")
+        dr = torch.from_numpy(r).to("cuda:0")
+        out = torch.zeros(n + 1, dtype=torch.int8, device="cuda:0")
+        for off in (0, 1):  # off = 1: types at +1 byte, RMSDs at +8 bytes
+            m = n - off
+            print(f"[posthoc] misaligned off={off} n={m}", flush=True)
+            tp, rp, op = dt.data_ptr() + off, dr.data_ptr() + 8 * off, out.data_ptr() + off
+            assert ptm.ptm_apply_cutoff(ctx, tp, rp, m, 0.1, op) == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+            got = out.cpu().numpy()[off:off + m]
+            assert np.array_equal(got, P.apply_cutoff(t[off:off + m], r[off:off + m], 0.1))
+            st, h = ptm.ptm_rmsd_histogram(ctx, tp, rp, m, nbins, rmax)
+            assert st == ptm.PTM_OK and np.array_equal(np.array(h),
+                                                       P.rmsd_histograms(t[off:off + m], r[off:off + m], nbins, rmax))
+        # quaternions at an 8-byte offset (no 16-byte loads) and a ragged count
+        rng = np.random.default_rng(9)
+        k = 1001
+        q = rng.normal(size=(2, k, 4))
+        q /= np.linalg.norm(q, axis=-1, keepdims=True)
+        ty = rng.integers(0, 6, k).astype(np.int8)
+        want = np.array([OD.misorientation(q[0, i], q[1, i], ty[i] - 1) if ty[i] > 0 else
+                         2 * np.arccos(min(1.0, abs(OD.quat_mul(OD.conj(q[0, i]), q[1, i])[0]))) for i in range(k)])
+        flat = torch.zeros((2, 4 * k + 1), dtype=torch.float64, device="cuda:0")
+        flat[0, 1:] = torch.from_numpy(q[0].ravel())
+        flat[1, 1:] = torch.from_numpy(q[1].ravel())
+        dty = torch.from_numpy(ty).to("cuda:0")
+        ang = torch.empty(k, dtype=torch.float64, device="cuda:0")
+        st = ptm.ptm_misorientation(ctx, dty.data_ptr(), flat[0].data_ptr() + 8, flat[1].data_ptr() + 8, k,
+                                    ang.data_ptr())
+        assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+        assert np.max(np.abs(ang.cpu().numpy() - want)) < 1e-7
+    finally:
         ptm.ptm_destroy(ctx)
