@@ -26,6 +26,7 @@ LIB = os.path.join(HERE, "libptm_oracle.so")
 TEMPLATES = ("SC", "FCC", "HCP", "ICO", "BCC")
 TEMPLATE_K = (6, 12, 12, 12, 14)
 MASK_ALL = 0x1F
+ORDER_TOPOLOGICAL = 0x100  # mask bit of the C oracle: topological neighbour ordering (Sec. 3)
 
 
 def build(force: bool = True) -> str:
@@ -50,7 +51,10 @@ def lib():
         p = C.c_void_p
         L.ptm_oracle_classify.restype = C.c_int
         L.ptm_oracle_classify.argtypes = [p, p, p, C.c_int64, C.c_uint32, C.c_double, p, C.c_int64,
-                                          C.c_int, p, p, p, p, p, p, p, p, p, p, p]
+                                          C.c_int, p, p, p, p, p, p, p, p, p, p, p, p]
+        L.ptm_oracle_voronoi.restype = C.c_int
+        L.ptm_oracle_voronoi.argtypes = [p, p, p, p]
+        L.ptm_oracle_voronoi_areas.argtypes = [C.c_int, p, p]
         L.ptm_oracle_orient.argtypes = [p, p, C.c_int]
         L.ptm_oracle_det3.argtypes = [p]
         L.ptm_oracle_hull.argtypes = [C.c_int, p, p, p]
@@ -68,11 +72,17 @@ def _ptr(a):
 
 
 def classify(positions, box, species=None, mask=MASK_ALL, cutoff=float("inf"), atoms=None,
-             threads=None, counters=False):
+             threads=None, counters=False, ordering="euclidean"):
     """Classify atoms (all, or the indices in ``atoms``).  Returns a dict of
     numpy arrays: type, alloy, rmsd, scale, quat (w,x,y,z), neighbours
     (template-vertex order), strain (3x3 row-major P), knn (distance order),
-    margin, ncand; plus ``counters`` when requested."""
+    margin, ncand, tmargin (topological ordering: distance of the nearest
+    area grid value to a rounding boundary); plus ``counters`` when
+    requested.  ``ordering``: "euclidean" or "topological" (Sec. 3)."""
+    if ordering not in ("euclidean", "topological"):
+        raise ValueError(ordering)
+    if ordering == "topological":
+        mask = mask | ORDER_TOPOLOGICAL
     pos = np.ascontiguousarray(positions, dtype=np.float64)
     n = pos.shape[0]
     bx = np.ascontiguousarray(box, dtype=np.float64)
@@ -84,6 +94,7 @@ def classify(positions, box, species=None, mask=MASK_ALL, cutoff=float("inf"), a
         "rmsd": np.zeros(m), "scale": np.zeros(m), "quat": np.zeros((m, 4)),
         "neighbours": np.zeros((m, 14), np.int32), "strain": np.zeros((m, 9)),
         "knn": np.zeros((m, 14), np.int32), "margin": np.zeros(m), "ncand": np.zeros(m, np.int32),
+        "tmargin": np.zeros(m),
     }
     cnt = np.zeros(5, np.int64)
     if threads is None:
@@ -92,7 +103,7 @@ def classify(positions, box, species=None, mask=MASK_ALL, cutoff=float("inf"), a
                                    m, threads, _ptr(out["type"]), _ptr(out["alloy"]),
                                    _ptr(out["rmsd"]), _ptr(out["scale"]), _ptr(out["quat"]),
                                    _ptr(out["neighbours"]), _ptr(out["strain"]), _ptr(out["knn"]),
-                                   _ptr(out["margin"]), _ptr(out["ncand"]), _ptr(cnt))
+                                   _ptr(out["margin"]), _ptr(out["ncand"]), _ptr(out["tmargin"]), _ptr(cnt))
     if rc != 0:
         raise RuntimeError("oracle initialisation failed")
     if counters:
@@ -181,3 +192,23 @@ def knn(positions, box, i, K=14):
     d2 = np.zeros(K)
     cnt = lib().ptm_oracle_knn(_ptr(pos), pos.shape[0], _ptr(bx), i, K, _ptr(ids), _ptr(rel), _ptr(d2))
     return ids[:cnt], rel[:cnt], d2[:cnt]
+
+
+def voronoi(rel18):
+    """(bounded, areas[18], order[18], tmargin) of the Voronoi cell of the
+    origin with 18 neighbour vectors in Euclidean order (Sec. 3)."""
+    r = np.ascontiguousarray(rel18, dtype=np.float64).reshape(18, 3)
+    area = np.zeros(18)
+    order = np.zeros(18, np.int32)
+    tm = np.zeros(1)
+    ok = lib().ptm_oracle_voronoi(_ptr(r), _ptr(area), _ptr(order), _ptr(tm))
+    return ok == 1, area, order, float(tm[0])
+
+
+def voronoi_areas(rel):
+    """Interface areas of the (bounded) Voronoi cell of the origin with the
+    k <= 18 neighbour vectors ``rel``."""
+    r = np.ascontiguousarray(rel, dtype=np.float64)
+    area = np.zeros(r.shape[0])
+    lib().ptm_oracle_voronoi_areas(r.shape[0], _ptr(r), _ptr(area))
+    return area

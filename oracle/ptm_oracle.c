@@ -9,7 +9,11 @@
  *
  * Every step is written for clarity, not speed, and follows the paper:
  *   neighbours  -- brute force over all atoms, ordered by distance
- *                  (Sec. 3; Alg. 1 takes A sorted by distance)
+ *                  (Sec. 3; Alg. 1 takes A sorted by distance), or in the
+ *                  topological order (Sec. 3): Voronoi interface areas of
+ *                  the cell of the centre and its 18 nearest neighbours
+ *                  (Sec. 9), every cell vertex found as an intersection of
+ *                  three bisector planes
  *   hull        -- every triple tested against every other point with exact
  *                  orientation predicates and symbolic perturbation
  *                  (Sec. 4: convex hull of the innermost |W| atoms; Alg. 1
@@ -44,6 +48,9 @@
 
 #define KMAX 14
 #define NMAX (KMAX + 1)
+#define TOPO_K 18                 /* Sec. 9: Voronoi cell from the centre and its 18 nearest neighbours */
+#define ORDER_TOPOLOGICAL 0x100u  /* mask bit: topological neighbour ordering (Sec. 3) */
+#define AREA_GRID 1048576.0       /* areas compared on a grid of 2^-20 of the cell surface */
 #define TIE_EPS 1e-12
 
 enum { T_SC = 0, T_FCC = 1, T_HCP = 2, T_ICO = 3, T_BCC = 4, NTEMPL = 5 };
@@ -972,9 +979,9 @@ static int knn_brute(const double *pos, int64_t n, const double box[3], int64_t 
     double inv[3];
     for (int d = 0; d < 3; d++) inv[d] = box[d] > 0 ? 1.0 / box[d] : 0.0;
     int cnt = 0;
-    double kd2[KMAX + 1];
-    int32_t kid[KMAX + 1];
-    double kr[KMAX + 1][3];
+    double kd2[TOPO_K + 1];
+    int32_t kid[TOPO_K + 1];
+    double kr[TOPO_K + 1][3];
     for (int64_t j = 0; j < n; j++) {
         if (j == i) continue;
         double v[3];
@@ -1008,6 +1015,160 @@ static int knn_brute(const double *pos, int64_t n, const double box[3], int64_t 
     return cnt;
 }
 
+/* ======================================================================== */
+/* topological neighbour ordering (Sec. 3)                                   */
+/* ======================================================================== */
+static const double ORIGIN[3] = {0.0, 0.0, 0.0};
+
+/* Is the origin strictly inside the convex hull of the k points q?  The
+ * hull is the intersection of the half-spaces of its supporting planes:
+ * every triple whose plane has no point strictly on one of its sides (exact
+ * orientation, no perturbation).  The origin must lie strictly on the inner
+ * side of each; a flat point set has no such plane and fails. */
+static int origin_strictly_inside(int k, const double (*q)[3]) {
+    int planes = 0;
+    for (int a = 0; a < k; a++)
+        for (int b = a + 1; b < k; b++)
+            for (int c = b + 1; c < k; c++) {
+                int pos = 0, neg = 0;
+                for (int m = 0; m < k && !(pos && neg); m++) {
+                    if (m == a || m == b || m == c) continue;
+                    int sg = orient_exact(q[a], q[b], q[c], q[m]);
+                    pos |= sg > 0;
+                    neg |= sg < 0;
+                }
+                if (pos == neg) continue; /* both sides, or every point on the plane */
+                int so = orient_exact(q[a], q[b], q[c], ORIGIN);
+                if (so == 0 || (so > 0) != (pos != 0)) return 0;
+                planes++;
+            }
+    return planes > 0;
+}
+
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Sec. 3: A_j, the area of the interface between the Voronoi cell of the
+ * centre (the origin) and that of neighbour j, the cell taken with respect
+ * to the centre and these k neighbours only; 0 when they do not touch.
+ * Written from the definition.  The cell is {x : x.d_m <= |d_m|^2 / 2 for
+ * every m}.  Its vertices are the points where three bisector planes meet
+ * and no constraint is violated (all triples tried; a relative slack of
+ * 1e-9 absorbs the rounding of the solve).  Face j is the convex polygon of
+ * the vertices found on plane j, taken in angular order about their mean;
+ * its area follows from the shoelace formula in an orthonormal basis of the
+ * plane.  The cell must be bounded. */
+static void voronoi_areas(int k, const double (*d)[3], double *area) {
+    static __thread double fv[TOPO_K][(TOPO_K - 1) * (TOPO_K - 2) / 2][3];
+    int nv[TOPO_K] = {0};
+    double h[TOPO_K];
+    for (int m = 0; m < k; m++) h[m] = 0.5 * dot3(d[m], d[m]);
+    for (int a = 0; a < k; a++)
+        for (int b = a + 1; b < k; b++)
+            for (int c = b + 1; c < k; c++) {
+                double bc[3], ca[3], ab[3];
+                cross3(d[b], d[c], bc);
+                cross3(d[c], d[a], ca);
+                cross3(d[a], d[b], ab);
+                double det = dot3(d[a], bc);
+                double scale = sqrt(dot3(d[a], d[a]) * dot3(d[b], d[b]) * dot3(d[c], d[c]));
+                if (!(fabs(det) > 1e-12 * scale)) continue; /* (nearly) parallel planes */
+                double x[3];
+                for (int e = 0; e < 3; e++) x[e] = (h[a] * bc[e] + h[b] * ca[e] + h[c] * ab[e]) / det;
+                int ok = 1;
+                for (int m = 0; m < k && ok; m++)
+                    if (dot3(x, d[m]) > h[m] * (1.0 + 1e-9)) ok = 0;
+                if (!ok) continue;
+                const int f[3] = {a, b, c};
+                for (int e = 0; e < 3; e++) memcpy(fv[f[e]][nv[f[e]]++], x, sizeof x);
+            }
+    for (int j = 0; j < k; j++) {
+        area[j] = 0.0;
+        int m = nv[j];
+        if (m < 3) continue;
+        /* orthonormal basis (u, v) of plane j */
+        double nrm = sqrt(dot3(d[j], d[j])), nh[3] = {d[j][0] / nrm, d[j][1] / nrm, d[j][2] / nrm};
+        double t[3] = {0, 0, 0};
+        int ax = fabs(nh[0]) <= fabs(nh[1]) ? (fabs(nh[0]) <= fabs(nh[2]) ? 0 : 2) : (fabs(nh[1]) <= fabs(nh[2]) ? 1 : 2);
+        t[ax] = 1.0;
+        double u[3], v[3];
+        cross3(nh, t, u);
+        double un = sqrt(dot3(u, u));
+        for (int e = 0; e < 3; e++) u[e] /= un;
+        cross3(nh, u, v);
+        double cen[3] = {0, 0, 0};
+        for (int q = 0; q < m; q++)
+            for (int e = 0; e < 3; e++) cen[e] += fv[j][q][e] / m;
+        double px[(TOPO_K - 1) * (TOPO_K - 2) / 2], py[(TOPO_K - 1) * (TOPO_K - 2) / 2],
+            th[(TOPO_K - 1) * (TOPO_K - 2) / 2];
+        for (int q = 0; q < m; q++) {
+            double r[3] = {fv[j][q][0] - cen[0], fv[j][q][1] - cen[1], fv[j][q][2] - cen[2]};
+            px[q] = dot3(r, u);
+            py[q] = dot3(r, v);
+            th[q] = atan2(py[q], px[q]);
+        }
+        for (int q = 1; q < m; q++) /* insertion sort by angle */
+            for (int p = q; p > 0 && th[p] < th[p - 1]; p--) {
+                double s0 = th[p]; th[p] = th[p - 1]; th[p - 1] = s0;
+                s0 = px[p]; px[p] = px[p - 1]; px[p - 1] = s0;
+                s0 = py[p]; py[p] = py[p - 1]; py[p - 1] = s0;
+            }
+        double s2 = 0;
+        for (int q = 0; q < m; q++) {
+            int r = (q + 1) % m;
+            s2 += px[q] * py[r] - px[r] * py[q];
+        }
+        area[j] = 0.5 * fabs(s2);
+    }
+}
+
+/* Sec. 3: the topological order of the k = TOPO_K nearest neighbours (ids,
+ * rel in Euclidean order on entry, permuted in place): lexicographically by
+ * (A_j, 1/d_j), larger first.  Reading: areas are compared on a grid, the
+ * grid value floor(2^20 A_j / sum A) (equal grid values tie, and ties fall
+ * to 1/d, i.e. to the Euclidean rank, which also orders exactly equal
+ * distances by index).  When the cell is unbounded (the origin not strictly
+ * inside the hull of the neighbours) the Euclidean order is kept: no hull of
+ * any subset can then hold the centre.  *tmargin receives the distance of
+ * the closest grid value >= 0.5 to an integer (how far the order is from a
+ * different rounding), +inf when the order is Euclidean. */
+static void topological_order(int32_t *ids, double (*rel)[3], double *area_out, double *tmargin) {
+    const int k = TOPO_K;
+    *tmargin = INFINITY;
+    for (int j = 0; j < k; j++) area_out[j] = -1.0;
+    if (!origin_strictly_inside(k, (const double(*)[3])rel)) return;
+    double A[TOPO_K], tot = 0;
+    voronoi_areas(k, (const double(*)[3])rel, A);
+    for (int j = 0; j < k; j++) tot += A[j];
+    if (!(tot > 0)) return;
+    int64_t key[TOPO_K];
+    for (int j = 0; j < k; j++) {
+        double x = A[j] / tot * AREA_GRID;
+        if (x >= 0.5 && fabs(x - rint(x)) < *tmargin) *tmargin = fabs(x - rint(x));
+        int64_t q = (int64_t)floor(x);
+        key[j] = ((int64_t)AREA_GRID - q) * 64 + j; /* smaller key first */
+        area_out[j] = A[j];
+    }
+    int perm[TOPO_K];
+    for (int j = 0; j < k; j++) perm[j] = j;
+    for (int q = 1; q < k; q++)
+        for (int p = q; p > 0 && key[perm[p]] < key[perm[p - 1]]; p--) {
+            int t = perm[p]; perm[p] = perm[p - 1]; perm[p - 1] = t;
+        }
+    int32_t id2[TOPO_K];
+    double rel2[TOPO_K][3];
+    for (int r = 0; r < k; r++) {
+        id2[r] = ids[perm[r]];
+        memcpy(rel2[r], rel[perm[r]], sizeof rel2[r]);
+    }
+    memcpy(ids, id2, sizeof id2);
+    memcpy(rel, rel2, sizeof rel2);
+}
+
 /* lexicographically smallest rank vector over the template's rotation group
  * (the orientation representative); returns the group element used */
 static int representative(int t, const int *c, int *out) {
@@ -1027,17 +1188,24 @@ static int representative(int t, const int *c, int *out) {
 
 typedef struct {
     int8_t type, alloy;
-    double rmsd, scale, quat[4], strain[9], margin;
+    double rmsd, scale, quat[4], strain[9], margin, tmargin;
     int32_t nbr[KMAX], knn[KMAX];
     int32_t ncand;
 } atom_out_t;
 
 static void classify_atom(const double *pos, const int8_t *species, const double box[3], int64_t n,
                           int64_t i, uint32_t mask, double cutoff, atom_out_t *o, counters_t *cnt) {
-    int32_t ids[KMAX];
-    double rel[KMAX][3];
-    int nn = knn_brute(pos, n, box, i, KMAX, ids, rel, NULL);
+    int32_t ids[TOPO_K];
+    double rel[TOPO_K][3];
+    const int topo = (mask & ORDER_TOPOLOGICAL) != 0;
+    int nn = knn_brute(pos, n, box, i, topo ? TOPO_K : KMAX, ids, rel, NULL);
     for (int r = 0; r < KMAX; r++) o->knn[r] = r < nn ? ids[r] : -1;
+    o->tmargin = INFINITY;
+    if (topo && nn == TOPO_K) { /* fewer than 18 neighbours: Euclidean order */
+        double area[TOPO_K];
+        topological_order(ids, rel, area, &o->tmargin);
+    }
+    if (nn > KMAX) nn = KMAX;
 
     static const int group_k[3] = {6, 12, 14};
     cand_t *cands = NULL;
@@ -1227,7 +1395,7 @@ typedef struct {
     uint32_t mask;
     double cutoff;
     int8_t *type, *alloy;
-    double *rmsd, *scale, *quat, *strain, *margin;
+    double *rmsd, *scale, *quat, *strain, *margin, *tmargin;
     int32_t *nbr, *knn, *ncand;
     int64_t lo, hi;
     counters_t cnt;
@@ -1249,6 +1417,7 @@ static void *worker(void *arg) {
         memcpy(J->nbr + KMAX * s, o.nbr, sizeof o.nbr);
         if (J->knn) memcpy(J->knn + KMAX * s, o.knn, sizeof o.knn);
         if (J->margin) J->margin[s] = o.margin;
+        if (J->tmargin) J->tmargin[s] = o.tmargin;
         if (J->ncand) J->ncand[s] = o.ncand;
     }
     return NULL;
@@ -1262,7 +1431,7 @@ int ptm_oracle_classify(const double *pos, const int8_t *species, const double *
                         uint32_t mask, double cutoff, const int64_t *sel, int64_t nsel, int nthreads,
                         int8_t *type, int8_t *alloy, double *rmsd, double *scale, double *quat,
                         int32_t *nbr, double *strain, int32_t *knn, double *margin, int32_t *ncand,
-                        int64_t *counters) {
+                        double *tmargin, int64_t *counters) {
     if (!ensure_init()) return 1;
     if (!sel) nsel = n;
     if (nthreads < 1) nthreads = 1;
@@ -1276,6 +1445,7 @@ int ptm_oracle_classify(const double *pos, const int8_t *species, const double *
         J->sel = sel; J->nsel = nsel; J->mask = mask; J->cutoff = cutoff;
         J->type = type; J->alloy = alloy; J->rmsd = rmsd; J->scale = scale; J->quat = quat;
         J->strain = strain; J->margin = margin; J->nbr = nbr; J->knn = knn; J->ncand = ncand;
+        J->tmargin = tmargin;
         J->lo = nsel * t / nthreads;
         J->hi = nsel * (t + 1) / nthreads;
     }
@@ -1399,6 +1569,26 @@ int ptm_oracle_superpose(int N, const double *obs, const double *tpl, double *rm
 /* neighbour list of atom i (brute force) */
 int ptm_oracle_knn(const double *pos, int64_t n, const double *box, int64_t i, int K, int32_t *ids,
                    double *rel, double *d2) {
-    if (K > KMAX + 1) return -1;
-    return knn_brute(pos, n, box, i, K > KMAX ? KMAX : K, ids, (double(*)[3])rel, d2);
+    if (K > TOPO_K || K < 1) return -1;
+    return knn_brute(pos, n, box, i, K, ids, (double(*)[3])rel, d2);
+}
+
+/* Voronoi interface areas of the origin with 18 neighbour vectors (rows of
+ * rel18, Euclidean order) and the topological order: order[r] = index of
+ * the neighbour at rank r.  Returns 1 if the cell is bounded (areas and
+ * order filled, tmargin as in the classification), 0 otherwise (areas -1,
+ * identity order). */
+int ptm_oracle_voronoi(const double *rel18, double *area, int32_t *order, double *tmargin) {
+    int32_t ids[TOPO_K];
+    double rel[TOPO_K][3];
+    for (int j = 0; j < TOPO_K; j++) ids[j] = j;
+    memcpy(rel, rel18, sizeof rel);
+    topological_order(ids, rel, area, tmargin);
+    memcpy(order, ids, sizeof ids);
+    return area[0] >= 0;
+}
+
+/* areas alone, for any k <= 18 neighbour vectors of a bounded cell */
+void ptm_oracle_voronoi_areas(int k, const double *rel, double *area) {
+    voronoi_areas(k, (const double(*)[3])rel, area);
 }
