@@ -116,11 +116,11 @@ def build_frame(args):
     return f, time.time() - t
 
 
-def run_gpu(frame, precision, steps, warmup):
+def run_gpu(frame, precision, steps, warmup, flags=0):
     import torch
     from paper_1603_05143_amd import ptm
     pos = torch.from_numpy(frame.positions).to("cuda:0")
-    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE)
+    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE | flags)
     out = ptm.Classifier.alloc_outputs(frame.n, "cuda:0")
     o = ptm.Classifier.outputs_struct(out)
 
@@ -414,6 +414,19 @@ def main():
     roof["work_per_launch"] = work
     roof["work_unit"] = unit
 
+    # topological neighbour ordering (Sec. 3): the same frame, both forms;
+    # its Voronoi kernel runs inside the k-NN stage
+    t64 = run_gpu(frame, ptm.PTM_FP64, args.steps, args.warmup, ptm.PTM_F_TOPOLOGICAL)
+    t32 = run_gpu(frame, ptm.PTM_FP32_MIXED, args.steps, args.warmup, ptm.PTM_F_TOPOLOGICAL)
+    print(f"[bench] topological fp32-mixed {t32['ms_per_step']:.2f} ms/step, fp64 {t64['ms_per_step']:.2f}",
+          file=sys.stderr, flush=True)
+    topological = {
+        "fp32_mixed_atoms_per_s": t32["atoms_per_s"], "fp64_atoms_per_s": t64["atoms_per_s"],
+        "fp32_mixed_ms_per_step": round(t32["ms_per_step"], 4), "fp64_ms_per_step": round(t64["ms_per_step"], 4),
+        "fp32_mixed_stage_ms": {k: round(v, 4) for k, v in t32["stage_ms"].items()},
+        "cost_over_euclidean": round(t32["ms_per_step"] / r32["ms_per_step"], 3),
+        "types": dict(zip(ptm.TYPE_NAMES, t32["types"])),
+    }
     derived_ms = derived_overhead(frame, args.steps, args.warmup)
     posthoc = posthoc_bench(1 << 27)
     print(f"[bench] derived outputs {derived_ms:.2f} ms/step; post-hoc {posthoc}", file=sys.stderr, flush=True)
@@ -444,6 +457,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "types": dict(zip(ptm.TYPE_NAMES, main_run["types"])),
         "roofline": roof,
+        "topological": topological,
         "derived_outputs_ms_per_step": round(derived_ms, 4),
         "posthoc": posthoc,
         "serving": serving,

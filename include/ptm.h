@@ -70,7 +70,17 @@ enum { PTM_ALLOY_NONE = 0, PTM_ALLOY_A1 = 1, PTM_ALLOY_L10 = 2, PTM_ALLOY_L12_MA
 
 /* context flags */
 enum { PTM_F_HOST_POINTERS = 1u << 0, /* inputs/outputs are host pointers (staged through HBM) */
-       PTM_F_PROFILE = 1u << 1 };     /* record HIP events between pipeline stages */
+       PTM_F_PROFILE = 1u << 1,       /* record HIP events between pipeline stages */
+       /* Topological neighbour ordering (Sec. 3) instead of the Euclidean one:
+        * the 18 nearest neighbours (Sec. 9) are ordered by the area of the
+        * interface between the Voronoi cell of the centre (taken with respect
+        * to these 18) and theirs, larger first, then by 1/d; areas are compared
+        * on a grid of 2^-20 of the cell surface, so equal areas tie and fall to
+        * the Euclidean rank.  The first 6 / 12 / 14 of this order form the
+        * hulls.  Atoms with fewer than 18 neighbours in the frame, or whose
+        * cell is unbounded, keep the Euclidean order.  The knn output stays
+        * Euclidean.  Costs 504 more bytes of scratch per atom. */
+       PTM_F_TOPOLOGICAL = 1u << 2 };
 
 /* pipeline stages reported by ptm_stage_times */
 enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2,

@@ -32,7 +32,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // atoms beyond the capacity are evaluated directly by k_decide)
 static int64_t pair_capacity(int64_t n) { return 6 * n + 64; }
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
     b += align_up(4 * (size_t)(cells + 3)) * 2;  // count (+ k-NN and decision leftover counters), start
@@ -46,10 +46,14 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp) {
     b += align_up(16 * (size_t)pair_capacity(n));  // pairs and their RMSD
     b += align_up(40 * (size_t)pair_capacity(n));  // their quaternion and scale
     b += align_up(scan_tmp);
+    if (topo) {
+        b += align_up(4 * (size_t)n * VK);      // the 18 Euclidean neighbours' ids
+        b += align_up(8 * (size_t)n * VK * 3);  // and vectors
+    }
     return b;
 }
 
-bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
+bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err) {
     int nb = bounds_blocks(n);
     size_t scan_tmp = 0, scan_tmp2 = 0;
     if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
@@ -60,7 +64,7 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
         return false;
     }
     if (scan_tmp2 > scan_tmp) scan_tmp = scan_tmp2;
-    size_t need = frame_bytes(n, cells, nb, scan_tmp);
+    size_t need = frame_bytes(n, cells, nb, scan_tmp, topo);
     if (need > bytes) {
         if (base) (void)hipFree(base);
         base = nullptr;
@@ -101,6 +105,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, std::string &err) {
     scan_tmp_bytes = scan_tmp;
     match.scan_tmp = scan_tmp_ptr;
     match.scan_tmp_bytes = scan_tmp;
+    id18 = topo ? (int32_t *)take(4 * (size_t)n * VK) : nullptr;
+    rel18 = topo ? (double *)take(8 * (size_t)n * VK * 3) : nullptr;
     return true;
 }
 
@@ -117,11 +123,12 @@ int bounds_blocks(int64_t n) {
     return (int)b;
 }
 
-// Choose the cell grid: cell edge 0.6 x the expected distance of the 14th
-// neighbour, so that shells 0..2 of cells around an atom (5x5x5 block)
-// usually certify its 14 nearest neighbours; at least 3 cells on periodic
-// axes.  The grid affects only speed: the search is certified exact.
-Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n) {
+// Choose the cell grid: cell edge 0.6 x the expected distance of the kn-th
+// neighbour (kn = 14, or 18 for the topological ordering), so that shells
+// 0..2 of cells around an atom (5x5x5 block) usually certify its kn nearest
+// neighbours; at least 3 cells on periodic axes.  The grid affects only
+// speed: the search is certified exact.
+Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n, int kn) {
     Grid g;
     double ext[3], vol = 1.0;
     int flat = 0;
@@ -134,7 +141,7 @@ Grid make_grid(const double box[3], const double mn[3], const double mx[3], int6
     double h;
     if (flat == 0 && vol > 0) {
         double rho = (double)n / vol;
-        h = 0.6 * std::cbrt(14.0 / (4.1887902047863905 * rho));
+        h = 0.6 * std::cbrt((double)kn / (4.1887902047863905 * rho));
     } else {
         h = 1.0;
         for (int a = 0; a < 3; a++) h = std::fmax(h, ext[a] / 16.0);
@@ -197,8 +204,15 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.sx, S.sy, S.sz, S.sid, st);
     if ((ps = mark(PTM_STAGE_KNN)) != PTM_OK) return ps;
     // slot_of is free once the atoms are scattered: it holds the leftover list
-    launch_knn(n, g, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, S.slot_of,
-               S.count + cells + 1, st);
+    if (J.topo) {
+        // the 18 Euclidean neighbours, then their topological order (Sec. 3)
+        launch_knn(n, g, VK, S.sx, S.sy, S.sz, S.sid, S.start, S.id18, S.rel18, J.out.knn, S.slot_of,
+                   S.count + cells + 1, st);
+        launch_voronoi(n, S.rel18, S.id18, S.nbr_rel, S.nbr_id, st);
+    } else {
+        launch_knn(n, g, KMAX, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, S.slot_of,
+                   S.count + cells + 1, st);
+    }
     if ((ps = mark(PTM_STAGE_TOPO)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
     const uint32_t need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
@@ -397,11 +411,12 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
     J.n = n_atoms;
     J.mask = template_mask & PTM_ALL;
     J.cutoff = rmsd_cutoff;
+    J.topo = (ctx->flags & PTM_F_TOPOLOGICAL) != 0;
     HostStage H;
     st = stage_in(ctx, positions, species, out, n_atoms, J, H);
     if (st != PTM_OK) return st;
     // bounds first (needs scratch for the partials): reserve with a tiny grid
-    if (!ctx->main.reserve(n_atoms, 1, ctx->err)) return PTM_E_NOMEM;
+    if (!ctx->main.reserve(n_atoms, 1, J.topo, ctx->err)) return PTM_E_NOMEM;
     double mn[3], mx[3];
     bool bad = false;
     const bool prof = (ctx->flags & PTM_F_PROFILE) != 0;
@@ -413,13 +428,13 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
         ctx->err = "non-finite coordinate";
         return PTM_E_INVALID;
     }
-    J.grid = make_grid(box, mn, mx, n_atoms);
+    J.grid = make_grid(box, mn, mx, n_atoms, J.topo ? VK : KMAX);
     int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
-    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0) > ctx->budget) {
+    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo) > ctx->budget) {
         ctx->err = "frame scratch exceeds the HBM budget";
         return PTM_E_NOMEM;
     }
-    if (!ctx->main.reserve(n_atoms, cells, ctx->err)) return PTM_E_NOMEM;
+    if (!ctx->main.reserve(n_atoms, cells, J.topo, ctx->err)) return PTM_E_NOMEM;
     st = enqueue_frame(ctx, ctx->main, J, ctx->stream, prof);
     if (st != PTM_OK) return st;
     st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);

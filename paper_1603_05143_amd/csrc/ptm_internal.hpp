@@ -31,13 +31,15 @@ struct FrameScratch {
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     int32_t *nbr_id = nullptr;
     double *nbr_rel = nullptr;
+    int32_t *id18 = nullptr;    // topological ordering: the 18 Euclidean neighbours
+    double *rel18 = nullptr;
     int32_t *code = nullptr;
     uint64_t *ord = nullptr;
     double *part = nullptr;
     void *scan_tmp_ptr = nullptr;
     size_t scan_tmp_bytes = 0;
     MatchScratch match = {};
-    bool reserve(int64_t n, int64_t cells, std::string &err);
+    bool reserve(int64_t n, int64_t cells, bool topo, std::string &err);
     void release();
 };
 
@@ -58,6 +60,7 @@ struct FrameJob {
     const double *pos = nullptr;
     const int8_t *species = nullptr;
     uint32_t mask = 0;
+    bool topo = false;  // topological neighbour ordering
     double cutoff = 0;
     Grid grid;
     ptm_outputs out;  // device pointers
@@ -81,9 +84,9 @@ struct Ticket {
     bool complete = false;
 };
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp);
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo);
 int bounds_blocks(int64_t n);
-Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n);
+Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n, int kn);
 ptm_status enqueue_frame(struct ::ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st,
                          bool prof = false);
 ptm_status frame_bounds(struct ::ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_t n, double mn[3],

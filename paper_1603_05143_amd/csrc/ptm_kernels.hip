@@ -222,7 +222,7 @@ __device__ inline void write_knn(int64_t n, int64_t p, int32_t i, int cnt, const
         nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
         nbr_rel[((int64_t)m * 3 + 1) * n + p] = r1;
         nbr_rel[((int64_t)m * 3 + 2) * n + p] = r2;
-        if (knn_out) knn_out[(int64_t)i * KN + m] = j;
+        if (knn_out && m < KMAX) knn_out[(int64_t)i * KMAX + m] = j;
     }
 }
 
@@ -254,7 +254,6 @@ __device__ inline void minmax_step(double &a, double &t) {
     t = hi;
 }
 
-constexpr int KNN_FAST_LIST = KMAX + 1;  // the 15th entry certifies the boundary
 
 // Fast search: the 5x5x5 block of cells around the atom, walked as 25
 // x-rows nearest-first.  A row of cells is one contiguous range of the
@@ -280,6 +279,10 @@ __device__ inline int64_t xcd_block(int64_t i, int64_t nblocks_padded) {
 }
 inline int64_t xcd_pad(int64_t nblocks) { return (nblocks + NXCD - 1) / NXCD * NXCD; }
 
+// NK = 14 neighbours (Euclidean ordering), or 18 (the input of the
+// topological ordering); the list holds NK + 1 keys, the last one certifies
+// the boundary.
+template <int NK>
 __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ sx,
                                                   const double *__restrict__ sy, const double *__restrict__ sz,
                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
@@ -288,7 +291,7 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
                                                   int32_t *__restrict__ todo_count) {
     int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    constexpr int KN = KNN_FAST_LIST;
+    constexpr int KN = NK + 1;
     const double xi = sx[p], yi = sy[p], zi = sz[p];
     const double xs[3] = {xi, yi, zi};
     int cc[3];
@@ -347,14 +350,14 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
                     skip = skip || cz < 0 || cz >= g.nc[2];
                 }
                 int xlo = -2, xhi = 2;
-                if (!skip && key[KMAX - 1] != INF) {
+                if (!skip && key[NK - 1] != INF) {
                     double ly = (cc[1] + dy) * g.h[1] - u[1], hy = ly + g.h[1];
                     double lz = (cc[2] + dz) * g.h[2] - u[2], hz = lz + g.h[2];
                     double gy = ly > 0 ? ly : (hy < 0 ? -hy : 0.0);
                     double gz = lz > 0 ? lz : (hz < 0 ? -hz : 0.0);
                     gy = gy > g.margin ? gy - g.margin : 0.0;
                     gz = gz > g.margin ? gz - g.margin : 0.0;
-                    double rem = key_d2_upper(key[KMAX - 1]) - (gy * gy + gz * gz);
+                    double rem = key_d2_upper(key[NK - 1]) - (gy * gy + gz * gz);
                     if (rem < 0) {
                         skip = true;
                     } else {
@@ -417,27 +420,27 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
 #pragma unroll
         for (int m = 0; m < KN; m++) minmax_step(key[m], t);
     } while (more);
-    bool ok = key[KMAX - 1] != INF;
+    bool ok = key[NK - 1] != INF;
 #pragma unroll
     for (int m = 0; m < KN - 1; m++) ok = ok && key_hi(key[m]) < key_hi(key[m + 1]);
-    int32_t kq[KMAX];
+    int32_t kq[NK];
 #pragma unroll
-    for (int m = 0; m < KMAX; m++) kq[m] = key_q(key[m]);
+    for (int m = 0; m < NK; m++) kq[m] = key_q(key[m]);
     if (ok) {
-        int32_t q13 = kq[KMAX - 1];
+        int32_t q13 = kq[NK - 1];
         double ex = min_image(sx[q13] - xi, g, 0);
         double ey = min_image(sy[q13] - yi, g, 1);
         double ez = min_image(sz[q13] - zi, g, 2);
         double kth = (ex * ex + ey * ey) + ez * ez;
         int lo[3] = {-2, -2, -2}, hi[3] = {2, 2, 2};
         bool all;
-        ok = certified(g, cc, u, lo, hi, KMAX, KMAX, kth, all);
+        ok = certified(g, cc, u, lo, hi, NK, NK, kth, all);
     }
     if (!ok) {
         todo[atomicAdd(todo_count, 1)] = (int32_t)p;
         return;
     }
-    write_knn<KMAX>(n, p, sid[p], KMAX, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel, knn_out);
+    write_knn<NK>(n, p, sid[p], NK, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel, knn_out);
 }
 
 // Exact search for the atoms the fast search left (or all atoms when todo
@@ -447,13 +450,14 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
 // heads gives the atom's ordered neighbours, and the shells grow until the
 // searched block certifies the 14th distance.  A wave per atom keeps the
 // latency of a few left-over atoms short: each lane scans one or two cells.
+template <int NK>
 __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const double *__restrict__ sx,
                                                    const double *__restrict__ sy, const double *__restrict__ sz,
                                                    const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                                    int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                                    int32_t *__restrict__ knn_out, const int32_t *__restrict__ todo,
                                                    const int32_t *__restrict__ todo_count) {
-    constexpr int KN = KMAX;
+    constexpr int KN = NK;
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t cnt_todo = todo ? (int64_t)*todo_count : n;
@@ -556,7 +560,244 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
             nbr_rel[((int64_t)lane * 3 + 0) * n + p] = r0;
             nbr_rel[((int64_t)lane * 3 + 1) * n + p] = r1;
             nbr_rel[((int64_t)lane * 3 + 2) * n + p] = r2;
-            if (knn_out) knn_out[(int64_t)i * KN + lane] = j;
+            if (knn_out && lane < KMAX) knn_out[(int64_t)i * KMAX + lane] = j;
+        }
+    }
+}
+
+// ------------------------------------------------- topological ordering
+// Sec. 3: neighbours ordered by the area of the interface between the
+// Voronoi cell of the centre and theirs, larger first, then by 1/d; the cell
+// is that of the centre and its 18 nearest neighbours (Sec. 9).  One lane
+// per atom.  The cell {x : x.n_j <= 1}, n_j = 2 d_j / |d_j|^2, is the polar
+// of the convex hull of the points n_j: hull vertices are the cell's faces,
+// each hull facet (a, b, c) is a cell vertex w (w.n_a = w.n_b = w.n_c = 1)
+// and hull edges are cell edges.  The hull is built incrementally with
+// exact predicates and Simulation of Simplicity by Euclidean rank (points
+// inside the current hull are skipped; vertices that a later point swallows
+// drop out of every facet), then the area of face v is
+// |sum over the facets f at v of (w_f x w_g) . n_v| / (2 |n_v|), g being the
+// facet across f's edge that starts at v: consecutive vertices of the face
+// polygon, in one consistent direction.  Areas are compared on a grid of
+// 2^-20 of the cell's surface, so that equal areas tie whatever their
+// rounding; ties fall to the Euclidean rank, i.e. to 1/d.  Atoms with fewer
+// than 18 neighbours, or an unbounded cell (the centre not strictly inside
+// the hull), keep the Euclidean order: no hull of any subset of their
+// neighbours can then hold the centre.
+constexpr int VF = 2 * VK - 4;  // facets of a triangulated sphere on 18 vertices
+constexpr int VB = 64;          // lanes per block
+constexpr double AREA_GRID = 1048576.0;
+
+struct VoronoiShared {
+    double P[3][VK][VB];  // the points n_j, component-major, lane-minor
+    uint32_t F[VF][VB];   // facets: vertices a | b << 5 | c << 10, link e at 15 + 5 e
+    union {
+        uint32_t H[VK][VB];  // horizon of the insertion in progress
+        double A[VK][VB];    // vector-area sums projected on n_v
+    };
+};
+
+__device__ inline uint32_t vpack(int a, int b, int c, int g0, int g1, int g2) {
+    return (uint32_t)a | ((uint32_t)b << 5) | ((uint32_t)c << 10) | ((uint32_t)g0 << 15) | ((uint32_t)g1 << 20) |
+           ((uint32_t)g2 << 25);
+}
+__device__ inline int vv(uint32_t f, int e) { return (f >> (5 * e)) & 31; }
+__device__ inline int vl(uint32_t f, int e) { return (f >> (15 + 5 * e)) & 31; }
+__device__ inline int field5(uint64_t lo, uint64_t hi, int v) {
+    return (int)((v < 12 ? lo >> (5 * v) : hi >> (5 * (v - 12))) & 31);
+}
+__device__ inline void set5(uint64_t &lo, uint64_t &hi, int v, int s) {
+    if (v < 12) lo |= (uint64_t)s << (5 * v);
+    else hi |= (uint64_t)s << (5 * (v - 12));
+}
+
+struct VLane {
+    VoronoiShared &S;
+    int t;
+    double bo, bd;  // static filter bounds of this lane's points
+    __device__ void load(int j, double (&x)[3]) const {
+        x[0] = S.P[0][j][t];
+        x[1] = S.P[1][j][t];
+        x[2] = S.P[2][j][t];
+    }
+    __device__ int orient(int a, int b, int c, int q) const {
+        double pa[3], pb[3], pc[3], pq[3];
+        load(a, pa);
+        load(b, pb);
+        load(c, pc);
+        load(q, pq);
+        return orient_sos64b(pa, pb, pc, pq, a, b, c, q, bo);
+    }
+    __device__ int det3(uint32_t f) const {
+        double pa[3], pb[3], pc[3];
+        load(vv(f, 0), pa);
+        load(vv(f, 1), pb);
+        load(vv(f, 2), pc);
+        return det3_sign64b(pa, pb, pc, bd);
+    }
+    // the cell vertex of facet f: (n_b x n_c + n_c x n_a + n_a x n_b) / det[n_a; n_b; n_c]
+    __device__ void cell_vertex(uint32_t f, double (&w)[3]) const {
+        double a[3], b[3], c[3];
+        load(vv(f, 0), a);
+        load(vv(f, 1), b);
+        load(vv(f, 2), c);
+        const double bc0 = b[1] * c[2] - b[2] * c[1], bc1 = b[2] * c[0] - b[0] * c[2], bc2 = b[0] * c[1] - b[1] * c[0];
+        const double ca0 = c[1] * a[2] - c[2] * a[1], ca1 = c[2] * a[0] - c[0] * a[2], ca2 = c[0] * a[1] - c[1] * a[0];
+        const double ab0 = a[1] * b[2] - a[2] * b[1], ab1 = a[2] * b[0] - a[0] * b[2], ab2 = a[0] * b[1] - a[1] * b[0];
+        const double inv = 1.0 / (a[0] * bc0 + a[1] * bc1 + a[2] * bc2);
+        w[0] = (bc0 + ca0 + ab0) * inv;
+        w[1] = (bc1 + ca1 + ab1) * inv;
+        w[2] = (bc2 + ca2 + ab2) * inv;
+    }
+};
+
+// first tetrahedron of points 0..3, positively oriented; facets 0..3
+__device__ inline void vhull_start(const VLane &L) {
+    int a = 0, b = 1, c = 2;
+    const int d = 3;
+    if (L.orient(0, 1, 2, 3) > 0) { b = 2; c = 1; }
+    L.S.F[0][L.t] = vpack(a, b, c, 1, 2, 3);
+    L.S.F[1][L.t] = vpack(b, a, d, 0, 3, 2);
+    L.S.F[2][L.t] = vpack(c, b, d, 0, 1, 3);
+    L.S.F[3][L.t] = vpack(a, c, d, 0, 2, 1);
+}
+
+// Insert point p into the hull whose facets are the slots in `live`.  A
+// point inside leaves the hull as it is.  New facets take the lowest free
+// slots (the visible facets' included).  Returns false on an inconsistent
+// hull, which exact predicates never produce.
+__device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
+    VoronoiShared &S = L.S;
+    const int t = L.t;
+    uint32_t vis = 0;
+    for (uint32_t m = live; m; m &= m - 1) {
+        const int f = __builtin_ctz(m);
+        const uint32_t w = S.F[f][t];
+        if (L.orient(vv(w, 0), vv(w, 1), vv(w, 2), p) > 0) vis |= 1u << f;
+    }
+    if (!vis) return true;
+    // horizon edges (a -> b) of visible facets whose neighbour g is not
+    // visible: a | b << 5 | g << 10 | eg << 15, eg = the edge b -> a of g
+    int nh = 0;
+    for (uint32_t m = vis; m; m &= m - 1) {
+        const int f = __builtin_ctz(m);
+        const uint32_t w = S.F[f][t];
+        for (int e = 0; e < 3; e++) {
+            const int g = vl(w, e);
+            if (!((live >> g) & 1)) return false;
+            if ((vis >> g) & 1) continue;
+            if (nh >= VK) return false;
+            const int ha = vv(w, e), hb = vv(w, e == 2 ? 0 : e + 1);
+            const uint32_t gw = S.F[g][t];
+            const int eg = (vv(gw, 0) == hb) ? 0 : ((vv(gw, 1) == hb) ? 1 : 2);
+            S.H[nh][t] = (uint32_t)ha | ((uint32_t)hb << 5) | ((uint32_t)g << 10) | ((uint32_t)eg << 15);
+            nh++;
+        }
+    }
+    const uint32_t freeset = ~(live & ~vis);
+    uint64_t st_lo = 0, st_hi = 0, en_lo = 0, en_hi = 0;  // vertex -> slot of the horizon edge it starts / ends
+    uint32_t fr = freeset, added = 0;
+    for (int h = 0; h < nh; h++) {
+        if (!fr) return false;
+        const int s = __builtin_ctz(fr);
+        fr &= fr - 1;
+        added |= 1u << s;
+        const uint32_t hw = S.H[h][t];
+        set5(st_lo, st_hi, hw & 31, s);
+        set5(en_lo, en_hi, (hw >> 5) & 31, s);
+    }
+    fr = freeset;
+    for (int h = 0; h < nh; h++) {
+        const int s = __builtin_ctz(fr);
+        fr &= fr - 1;
+        const uint32_t hw = S.H[h][t];
+        const int ha = hw & 31, hb = (hw >> 5) & 31, g = (hw >> 10) & 31, eg = (hw >> 15) & 3;
+        S.F[s][t] = vpack(ha, hb, p, g, field5(st_lo, st_hi, hb), field5(en_lo, en_hi, ha));
+        const uint32_t gw = S.F[g][t];
+        S.F[g][t] = (gw & ~(31u << (15 + 5 * eg))) | ((uint32_t)s << (15 + 5 * eg));
+    }
+    live = (live & ~vis) | added;
+    return true;
+}
+
+__global__ void __launch_bounds__(VB) k_voronoi(int64_t n, const double *__restrict__ rel18,
+                                                const int32_t *__restrict__ id18, double *__restrict__ nbr_rel,
+                                                int32_t *__restrict__ nbr_id) {
+    __shared__ VoronoiShared S;
+    const int t = threadIdx.x;
+    const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)VB + t;
+    if (p >= n) return;
+    // Euclidean rank v goes to row pos(v); keys order (grid area descending, rank)
+    uint32_t key[VK];
+#pragma unroll
+    for (int v = 0; v < VK; v++) key[v] = (uint32_t)v;
+    bool topo = id18[(int64_t)(VK - 1) * n + p] >= 0;
+    double m = 0;
+#pragma unroll
+    for (int v = 0; v < VK; v++) {
+        const double x = rel18[((int64_t)v * 3 + 0) * n + p], y = rel18[((int64_t)v * 3 + 1) * n + p],
+                     z = rel18[((int64_t)v * 3 + 2) * n + p];
+        const double d2 = (x * x + y * y) + z * z;
+        topo = topo && d2 > 0;
+        const double sc = 2.0 / d2;
+        const double nx = x * sc, ny = y * sc, nz = z * sc;
+        S.P[0][v][t] = nx;
+        S.P[1][v][t] = ny;
+        S.P[2][v][t] = nz;
+        m = fmax(m, fmax(fabs(nx), fmax(fabs(ny), fabs(nz))));
+    }
+    if (topo) {
+        VLane L{S, t, f64_orient_bound(m), f64_det3_bound(m)};
+        vhull_start(L);
+        uint32_t live = 0xFu;
+        for (int q = 4; q < VK && topo; q++) topo = vhull_insert(L, q, live);
+        // the centre strictly inside every facet
+        for (uint32_t mm = live; mm && topo; mm &= mm - 1) topo = L.det3(S.F[__builtin_ctz(mm)][t]) > 0;
+        if (topo) {
+#pragma unroll
+            for (int v = 0; v < VK; v++) S.A[v][t] = 0.0;
+            for (uint32_t mm = live; mm; mm &= mm - 1) {
+                const uint32_t w = S.F[__builtin_ctz(mm)][t];
+                double wf[3];
+                L.cell_vertex(w, wf);
+                for (int e = 0; e < 3; e++) {
+                    double wg[3], nv[3];
+                    L.cell_vertex(S.F[vl(w, e)][t], wg);
+                    const int v = vv(w, e);
+                    L.load(v, nv);
+                    const double cx = wf[1] * wg[2] - wf[2] * wg[1], cy = wf[2] * wg[0] - wf[0] * wg[2],
+                                 cz = wf[0] * wg[1] - wf[1] * wg[0];
+                    S.A[v][t] += cx * nv[0] + cy * nv[1] + cz * nv[2];
+                }
+            }
+            double area[VK], tot = 0;
+#pragma unroll
+            for (int v = 0; v < VK; v++) {
+                double nv[3];
+                L.load(v, nv);
+                area[v] = fabs(S.A[v][t]) / (2.0 * sqrt((nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2]));
+                tot += area[v];
+            }
+            if (tot > 0) {
+#pragma unroll
+                for (int v = 0; v < VK; v++) {
+                    const double x = area[v] / tot * AREA_GRID;
+                    const uint32_t q = (uint32_t)fmin(fmax(floor(x), 0.0), AREA_GRID);
+                    key[v] = (((uint32_t)AREA_GRID - q) << 5) | (uint32_t)v;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < VK; v++) {
+        int pos = 0;
+#pragma unroll
+        for (int u = 0; u < VK; u++) pos += key[u] < key[v];
+        if (pos < KMAX) {
+            nbr_id[(int64_t)pos * n + p] = id18[(int64_t)v * n + p];
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                nbr_rel[((int64_t)pos * 3 + c) * n + p] = rel18[((int64_t)v * 3 + c) * n + p];
         }
     }
 }
@@ -1881,22 +2122,36 @@ bool knn_fast_applies(const Grid &g) {
         if (g.periodic[a] && g.nc[a] < 5) return false;
     return true;
 }
-void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz, const int32_t *sid,
-                const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out, int32_t *todo,
-                int32_t *todo_count, hipStream_t st) {
+template <int NK>
+static void launch_knn_nk(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz,
+                          const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel,
+                          int32_t *knn_out, int32_t *todo, int32_t *todo_count, hipStream_t st) {
     int64_t blocks = (n + 255) / 256;
     if (knn_fast_applies(g)) {
-        hipLaunchKernelGGL(k_knn_fast, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, sx, sy, sz, sid, start,
-                           nbr_id, nbr_rel, knn_out, todo, todo_count);
+        hipLaunchKernelGGL(k_knn_fast<NK>, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, sx, sy, sz, sid,
+                           start, nbr_id, nbr_rel, knn_out, todo, todo_count);
         // the atoms left over are few; 1024 blocks of four waves stride over them
-        hipLaunchKernelGGL(k_knn_exact, dim3((unsigned)std::min<int64_t>(blocks, 1024)), dim3(256), 0, st, n, g, sx,
-                           sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)todo,
+        hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>(blocks, 1024)), dim3(256), 0, st, n, g,
+                           sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)todo,
                            (const int32_t *)todo_count);
     } else {
-        hipLaunchKernelGGL(k_knn_exact, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 16384)), dim3(256), 0, st, n, g, sx,
-                           sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)nullptr,
+        hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 16384)), dim3(256), 0, st, n,
+                           g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)nullptr,
                            (const int32_t *)nullptr);
     }
+}
+void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double *sy, const double *sz,
+                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
+                int32_t *todo, int32_t *todo_count, hipStream_t st) {
+    if (nk == VK)
+        launch_knn_nk<VK>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, todo, todo_count, st);
+    else
+        launch_knn_nk<KMAX>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, todo, todo_count, st);
+}
+void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, double *nbr_rel, int32_t *nbr_id,
+                    hipStream_t st) {
+    const int64_t blocks = (n + VB - 1) / VB;
+    hipLaunchKernelGGL(k_voronoi, dim3((unsigned)xcd_pad(blocks)), dim3(VB), 0, st, n, rel18, id18, nbr_rel, nbr_id);
 }
 void launch_topo(bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
                  uint32_t need, int32_t *code, uint64_t *ord, hipStream_t st) {

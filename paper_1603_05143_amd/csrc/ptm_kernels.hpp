@@ -7,6 +7,8 @@
 
 namespace ptm {
 
+constexpr int VK = 18;  // neighbours of the Voronoi cell of the topological ordering (Sec. 9)
+
 // Cell grid of one frame (counting-sort binning; see k_bin_count).
 struct Grid {
     int nc[3];        // cells per axis
@@ -55,9 +57,16 @@ void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, co
 // k-NN: fast block search, then the exact shell search for the atoms it
 // leaves in todo (n entries) / *todo_count (zeroed by the caller).
 bool knn_fast_applies(const Grid &g);
-void launch_knn(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz, const int32_t *sid,
-                const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out, int32_t *todo,
-                int32_t *todo_count, hipStream_t st);
+// nk = 14 (Euclidean ordering) or VK = 18 (input of the topological
+// ordering) nearest neighbours, rank-major [nk][n] / [nk][3][n]; knn_out
+// receives the first 14 ([n][14])
+void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double *sy, const double *sz,
+                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
+                int32_t *todo, int32_t *todo_count, hipStream_t st);
+// topological order (Sec. 3) of the 18 neighbours in rel18 / id18: the first
+// 14 go to nbr_rel / nbr_id
+void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, double *nbr_rel, int32_t *nbr_id,
+                    hipStream_t st);
 // hulls of the first 6 / 12 / 14 neighbours (need: bit g for group g);
 // code ids and labellings into code / ord [group][n]
 void launch_topo(bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,

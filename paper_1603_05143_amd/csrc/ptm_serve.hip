@@ -189,12 +189,12 @@ static ptm_status serve_init(ptm_ctx *ctx) {
 // Size class of a frame's scratch: the next power of two (at least 1 MiB)
 // of an upper bound of its bytes that holds for any cell grid make_grid
 // may choose (at most 4n + 4096 cells).
-static size_t scratch_class(int64_t n) {
+static size_t scratch_class(int64_t n, bool topo) {
     int64_t cells = 4 * n + 4096;
     size_t tmp = 0, tmp2 = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int32_t *)nullptr, (int32_t *)nullptr, (int)(cells + 1));
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2, (int64_t *)nullptr, (int64_t *)nullptr, (int)(n + 1));
-    size_t need = frame_bytes(n, cells, bounds_blocks(n), std::max(tmp, tmp2));
+    size_t need = frame_bytes(n, cells, bounds_blocks(n), std::max(tmp, tmp2), topo);
     size_t c = (size_t)1 << 20;
     while (c < need) c <<= 1;
     return c;
@@ -290,6 +290,7 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
     T->job.n = n_atoms;
     T->job.mask = template_mask & PTM_ALL;
     T->job.cutoff = rmsd_cutoff;
+    T->job.topo = (ctx->flags & PTM_F_TOPOLOGICAL) != 0;
     if (n_atoms > 0) {
         hipStream_t bst = ctx->bounds_stream;
         // bounds first (synchronous on the bounds stream): the grid depends on them
@@ -305,12 +306,12 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
         }
         int64_t cells = 1;
         if (st == PTM_OK) {
-            T->job.grid = make_grid(box, mn, mx, n_atoms);
+            T->job.grid = make_grid(box, mn, mx, n_atoms, T->job.topo ? VK : KMAX);
             cells = (int64_t)T->job.grid.nc[0] * T->job.grid.nc[1] * T->job.grid.nc[2];
-            T->footprint = scratch_class(n_atoms);
+            T->footprint = scratch_class(n_atoms, T->job.topo);
             st = take_scratch(ctx, T->footprint, T->scratch);
         }
-        if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, ctx->err)) st = PTM_E_NOMEM;
+        if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, T->job.topo, ctx->err)) st = PTM_E_NOMEM;
         if (st != PTM_OK) {
             if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);
             T->staging.release();

@@ -19,6 +19,7 @@ PTM_SC, PTM_FCC, PTM_HCP, PTM_ICO, PTM_BCC = 1, 2, 4, 8, 16
 PTM_ALL = 0x1F
 PTM_F_HOST_POINTERS = 1
 PTM_F_PROFILE = 2
+PTM_F_TOPOLOGICAL = 4
 STAGE_NAMES = ("bounds", "bin", "knn", "topo", "cand", "eval", "decide")
 TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
 ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")
@@ -181,10 +182,13 @@ def ptm_template_info(t: int):
 class Classifier:
     """Owns a context; classifies torch tensors resident on the GPU."""
 
-    def __init__(self, device: int = 0, precision: int = PTM_FP64, hbm_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, precision: int = PTM_FP64, hbm_budget_bytes: int = 0,
+                 topological: bool = False):
         import torch  # noqa: F401  (loads the HIP runtime the library shares)
         self.device = device
-        self.ctx = ptm_create(device, precision, None, hbm_budget_bytes, 0)
+        self.precision = precision
+        self.topological = topological
+        self.ctx = ptm_create(device, precision, None, hbm_budget_bytes, PTM_F_TOPOLOGICAL if topological else 0)
 
     def close(self):
         if self.ctx is not None:

@@ -25,10 +25,10 @@ def torch_cuda():
     return torch
 
 
-def _gpu_sample(torch, precision, f, atoms):
+def _gpu_sample(torch, precision, f, atoms, topological=False):
     """Classify the whole frame on the GPU; return the outputs of the sample."""
-    print(f"[full] n={f.n} precision={precision} sample={len(atoms)}", flush=True)
-    c = ptm.Classifier(device=0, precision=precision)
+    print(f"[full] n={f.n} precision={precision} sample={len(atoms)} topological={topological}", flush=True)
+    c = ptm.Classifier(device=0, precision=precision, topological=topological)
     try:
         pos = torch.from_numpy(np.ascontiguousarray(f.positions)).to("cuda:0")
         sp = None if f.species is None else torch.from_numpy(f.species).to("cuda:0")
@@ -51,9 +51,10 @@ def _gpu_sample(torch, precision, f, atoms):
     return res, types
 
 
-def _oracle(oracle_lib, key, f, atoms):
+def _oracle(oracle_lib, key, f, atoms, ordering="euclidean"):
     if key not in _oracle_cache:
-        _oracle_cache[key] = oracle_lib.classify(f.positions, f.box, species=f.species, atoms=atoms)
+        _oracle_cache[key] = oracle_lib.classify(f.positions, f.box, species=f.species, atoms=atoms,
+                                                 ordering=ordering)
     return _oracle_cache[key]
 
 
@@ -112,3 +113,39 @@ def test_mixed_frame_full_sampled(torch_cuda, oracle_lib, mixed, precision):
     at_centres = ref["type"][np.searchsorted(atoms, centres)]
     assert np.mean(at_centres == 4) > 0.9, np.bincount(at_centres, minlength=6)
     print("mixed frame", f.n, types.tolist(), st)
+
+
+@pytest.fixture(scope="module")
+def poly():
+    f = S.polycrystal()
+    rng = np.random.default_rng(13)
+    return f, np.unique(rng.choice(f.n, 1200, replace=False))
+
+
+def _sure(ref, got):
+    """Atoms whose topological order cannot round differently (tmargin)."""
+    sure = ~(ref["tmargin"] < 1e-6)
+    assert np.sum(~sure) <= 2, np.sum(~sure)
+    return ({k: v[sure] for k, v in got.items()}, {k: v[sure] for k, v in ref.items() if k in got})
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_polycrystal_topological_full_sampled(torch_cuda, oracle_lib, poly, precision):
+    """The 918,996-atom polycrystal with topological ordering (Sec. 3)."""
+    f, atoms = poly
+    got, types = _gpu_sample(torch_cuda, precision, f, atoms, topological=True)
+    ref = _oracle(oracle_lib, "poly-topo", f, atoms, ordering="topological")
+    g, r = _sure(ref, got)
+    st = compare(g, r, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32, check_alloy=False, label="poly topo ")
+    print("polycrystal topological", f.n, types.tolist(), st)
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP32_MIXED], ids=["fp32mixed"])
+def test_mixed_frame_topological_full_sampled(torch_cuda, oracle_lib, mixed, precision):
+    """The ~32 M-atom mixed frame with topological ordering."""
+    f, atoms, centres = mixed
+    got, types = _gpu_sample(torch_cuda, precision, f, atoms, topological=True)
+    ref = _oracle(oracle_lib, "mixed-topo", f, atoms, ordering="topological")
+    g, r = _sure(ref, got)
+    st = compare(g, r, tol=TOL32, check_alloy=False, label="mixed topo ")
+    print("mixed frame topological", f.n, types.tolist(), st)
