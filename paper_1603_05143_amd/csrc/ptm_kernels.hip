@@ -588,13 +588,11 @@ constexpr int VF = 2 * VK - 4;  // facets of a triangulated sphere on 18 vertice
 constexpr int VB = 64;          // lanes per block
 constexpr double AREA_GRID = 1048576.0;
 
+// 38 KB per 64-lane block: four blocks per CU
 struct VoronoiShared {
     double P[3][VK][VB];  // the points n_j, component-major, lane-minor
     uint32_t F[VF][VB];   // facets: vertices a | b << 5 | c << 10, link e at 15 + 5 e
-    union {
-        uint32_t H[VK][VB];  // horizon of the insertion in progress
-        double A[VK][VB];    // vector-area sums projected on n_v
-    };
+    uint16_t H[VK][VB];   // horizon edges of the insertion in progress: a | b << 5 | g << 10
 };
 
 __device__ inline uint32_t vpack(int a, int b, int c, int g0, int g1, int g2) {
@@ -603,6 +601,8 @@ __device__ inline uint32_t vpack(int a, int b, int c, int g0, int g1, int g2) {
 }
 __device__ inline int vv(uint32_t f, int e) { return (f >> (5 * e)) & 31; }
 __device__ inline int vl(uint32_t f, int e) { return (f >> (15 + 5 * e)) & 31; }
+// position of vertex x in facet f (f must hold x)
+__device__ inline int vpos(uint32_t f, int x) { return vv(f, 0) == x ? 0 : (vv(f, 1) == x ? 1 : 2); }
 __device__ inline int field5(uint64_t lo, uint64_t hi, int v) {
     return (int)((v < 12 ? lo >> (5 * v) : hi >> (5 * (v - 12))) & 31);
 }
@@ -620,12 +620,11 @@ struct VLane {
         x[1] = S.P[1][j][t];
         x[2] = S.P[2][j][t];
     }
-    __device__ int orient(int a, int b, int c, int q) const {
-        double pa[3], pb[3], pc[3], pq[3];
+    __device__ int orient(int a, int b, int c, const double (&pq)[3], int q) const {
+        double pa[3], pb[3], pc[3];
         load(a, pa);
         load(b, pb);
         load(c, pc);
-        load(q, pq);
         return orient_sos64b(pa, pb, pc, pq, a, b, c, q, bo);
     }
     __device__ int det3(uint32_t f) const {
@@ -635,27 +634,27 @@ struct VLane {
         load(vv(f, 2), pc);
         return det3_sign64b(pa, pb, pc, bd);
     }
-    // the cell vertex of facet f: (n_b x n_c + n_c x n_a + n_a x n_b) / det[n_a; n_b; n_c]
-    __device__ void cell_vertex(uint32_t f, double (&w)[3]) const {
-        double a[3], b[3], c[3];
-        load(vv(f, 0), a);
-        load(vv(f, 1), b);
-        load(vv(f, 2), c);
-        const double bc0 = b[1] * c[2] - b[2] * c[1], bc1 = b[2] * c[0] - b[0] * c[2], bc2 = b[0] * c[1] - b[1] * c[0];
-        const double ca0 = c[1] * a[2] - c[2] * a[1], ca1 = c[2] * a[0] - c[0] * a[2], ca2 = c[0] * a[1] - c[1] * a[0];
-        const double ab0 = a[1] * b[2] - a[2] * b[1], ab1 = a[2] * b[0] - a[0] * b[2], ab2 = a[0] * b[1] - a[1] * b[0];
-        const double inv = 1.0 / (a[0] * bc0 + a[1] * bc1 + a[2] * bc2);
-        w[0] = (bc0 + ca0 + ab0) * inv;
-        w[1] = (bc1 + ca1 + ab1) * inv;
-        w[2] = (bc2 + ca2 + ab2) * inv;
-    }
 };
+
+// the cell vertex of the facet (a, b, c): w.n_a = w.n_b = w.n_c = 1, i.e.
+// (n_b x n_c + n_c x n_a + n_a x n_b) / det[n_a; n_b; n_c]
+__device__ inline void cell_vertex(const double (&a)[3], const double (&b)[3], const double (&c)[3], double (&w)[3]) {
+    const double bc0 = b[1] * c[2] - b[2] * c[1], bc1 = b[2] * c[0] - b[0] * c[2], bc2 = b[0] * c[1] - b[1] * c[0];
+    const double ca0 = c[1] * a[2] - c[2] * a[1], ca1 = c[2] * a[0] - c[0] * a[2], ca2 = c[0] * a[1] - c[1] * a[0];
+    const double ab0 = a[1] * b[2] - a[2] * b[1], ab1 = a[2] * b[0] - a[0] * b[2], ab2 = a[0] * b[1] - a[1] * b[0];
+    const double inv = 1.0 / (a[0] * bc0 + a[1] * bc1 + a[2] * bc2);
+    w[0] = (bc0 + ca0 + ab0) * inv;
+    w[1] = (bc1 + ca1 + ab1) * inv;
+    w[2] = (bc2 + ca2 + ab2) * inv;
+}
 
 // first tetrahedron of points 0..3, positively oriented; facets 0..3
 __device__ inline void vhull_start(const VLane &L) {
     int a = 0, b = 1, c = 2;
     const int d = 3;
-    if (L.orient(0, 1, 2, 3) > 0) { b = 2; c = 1; }
+    double p3[3];
+    L.load(3, p3);
+    if (L.orient(0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
     L.S.F[0][L.t] = vpack(a, b, c, 1, 2, 3);
     L.S.F[1][L.t] = vpack(b, a, d, 0, 3, 2);
     L.S.F[2][L.t] = vpack(c, b, d, 0, 1, 3);
@@ -669,15 +668,16 @@ __device__ inline void vhull_start(const VLane &L) {
 __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
     VoronoiShared &S = L.S;
     const int t = L.t;
+    double pp[3];
+    L.load(p, pp);
     uint32_t vis = 0;
     for (uint32_t m = live; m; m &= m - 1) {
         const int f = __builtin_ctz(m);
         const uint32_t w = S.F[f][t];
-        if (L.orient(vv(w, 0), vv(w, 1), vv(w, 2), p) > 0) vis |= 1u << f;
+        if (L.orient(vv(w, 0), vv(w, 1), vv(w, 2), pp, p) > 0) vis |= 1u << f;
     }
     if (!vis) return true;
-    // horizon edges (a -> b) of visible facets whose neighbour g is not
-    // visible: a | b << 5 | g << 10 | eg << 15, eg = the edge b -> a of g
+    // horizon edges (a -> b) of visible facets whose neighbour g is not visible
     int nh = 0;
     for (uint32_t m = vis; m; m &= m - 1) {
         const int f = __builtin_ctz(m);
@@ -687,10 +687,7 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
             if (!((live >> g) & 1)) return false;
             if ((vis >> g) & 1) continue;
             if (nh >= VK) return false;
-            const int ha = vv(w, e), hb = vv(w, e == 2 ? 0 : e + 1);
-            const uint32_t gw = S.F[g][t];
-            const int eg = (vv(gw, 0) == hb) ? 0 : ((vv(gw, 1) == hb) ? 1 : 2);
-            S.H[nh][t] = (uint32_t)ha | ((uint32_t)hb << 5) | ((uint32_t)g << 10) | ((uint32_t)eg << 15);
+            S.H[nh][t] = (uint16_t)(vv(w, e) | (vv(w, e == 2 ? 0 : e + 1) << 5) | (g << 10));
             nh++;
         }
     }
@@ -711,13 +708,38 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
         const int s = __builtin_ctz(fr);
         fr &= fr - 1;
         const uint32_t hw = S.H[h][t];
-        const int ha = hw & 31, hb = (hw >> 5) & 31, g = (hw >> 10) & 31, eg = (hw >> 15) & 3;
+        const int ha = hw & 31, hb = (hw >> 5) & 31, g = (hw >> 10) & 31;
         S.F[s][t] = vpack(ha, hb, p, g, field5(st_lo, st_hi, hb), field5(en_lo, en_hi, ha));
+        // g holds the edge hb -> ha; its link there now points to s
         const uint32_t gw = S.F[g][t];
+        const int eg = vpos(gw, hb);
         S.F[g][t] = (gw & ~(31u << (15 + 5 * eg))) | ((uint32_t)s << (15 + 5 * eg));
     }
     live = (live & ~vis) | added;
     return true;
+}
+
+// Squared distance from the origin of the closest facet plane of a hull
+// that holds the origin, lowered by a relative 1e-6 (far above the rounding
+// of the evaluation): a point closer to the origin than this is strictly
+// inside the hull, and so inside every later (larger) hull.  -1 when the
+// origin is not inside.
+__device__ inline double vhull_inradius2(const VLane &L, uint32_t live) {
+    double r2 = INFINITY;
+    for (uint32_t m = live; m; m &= m - 1) {
+        const uint32_t w = L.S.F[__builtin_ctz(m)][L.t];
+        double a[3], b[3], c[3];
+        L.load(vv(w, 0), a);
+        L.load(vv(w, 1), b);
+        L.load(vv(w, 2), c);
+        const double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
+        const double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
+        const double n0 = u1 * v2 - u2 * v1, n1 = u2 * v0 - u0 * v2, n2 = u0 * v1 - u1 * v0;
+        const double h = n0 * a[0] + n1 * a[1] + n2 * a[2];
+        if (!(h > 0)) return -1.0;  // the origin is not inside: no bound
+        r2 = fmin(r2, h * h / ((n0 * n0 + n1 * n1) + n2 * n2));
+    }
+    return r2 * (1.0 - 1e-6);
 }
 
 __global__ void __launch_bounds__(VB) k_voronoi(int64_t n, const double *__restrict__ rel18,
@@ -750,32 +772,73 @@ __global__ void __launch_bounds__(VB) k_voronoi(int64_t n, const double *__restr
         VLane L{S, t, f64_orient_bound(m), f64_det3_bound(m)};
         vhull_start(L);
         uint32_t live = 0xFu;
-        for (int q = 4; q < VK && topo; q++) topo = vhull_insert(L, q, live);
+        double rin2 = -1.0;  // inradius bound of the 12-point hull
+        for (int q = 4; q < VK && topo; q++) {
+            if (q == 12) rin2 = vhull_inradius2(L, live);
+            if (q >= 12) {
+                double pq[3];
+                L.load(q, pq);
+                if ((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2] < rin2) continue;  // strictly inside
+            }
+            topo = vhull_insert(L, q, live);
+        }
         // the centre strictly inside every facet
         for (uint32_t mm = live; mm && topo; mm &= mm - 1) topo = L.det3(S.F[__builtin_ctz(mm)][t]) > 0;
         if (topo) {
-#pragma unroll
-            for (int v = 0; v < VK; v++) S.A[v][t] = 0.0;
-            for (uint32_t mm = live; mm; mm &= mm - 1) {
-                const uint32_t w = S.F[__builtin_ctz(mm)][t];
-                double wf[3];
-                L.cell_vertex(w, wf);
+            // one facet at each vertex: 5-bit fields, 31 = not a vertex (a
+            // vertex has at least three facets, so slot 31 is never needed)
+            uint64_t at_lo = ~0ull, at_hi = ~0ull;
+            for (uint32_t mm = live & 0x7FFFFFFFu; mm; mm &= mm - 1) {
+                const int f = __builtin_ctz(mm);
+                const uint32_t w = S.F[f][t];
                 for (int e = 0; e < 3; e++) {
-                    double wg[3], nv[3];
-                    L.cell_vertex(S.F[vl(w, e)][t], wg);
-                    const int v = vv(w, e);
-                    L.load(v, nv);
-                    const double cx = wf[1] * wg[2] - wf[2] * wg[1], cy = wf[2] * wg[0] - wf[0] * wg[2],
-                                 cz = wf[0] * wg[1] - wf[1] * wg[0];
-                    S.A[v][t] += cx * nv[0] + cy * nv[1] + cz * nv[2];
+                    const int x = vv(w, e);
+                    if (x < 12) at_lo = (at_lo & ~(31ull << (5 * x))) | ((uint64_t)f << (5 * x));
+                    else at_hi = (at_hi & ~(31ull << (5 * (x - 12)))) | ((uint64_t)f << (5 * (x - 12)));
                 }
             }
+            // face v: walk the facets around v (each next one across the
+            // edge that starts at v), summing w_f x w_next; every step
+            // brings one new point, the facet's vertex after v's successor
             double area[VK], tot = 0;
 #pragma unroll
             for (int v = 0; v < VK; v++) {
-                double nv[3];
+                area[v] = 0;
+                const int f0 = field5(at_lo, at_hi, v);
+                if (f0 == 31) continue;
+                double nv[3], a[3], b[3], w0[3], wp[3];
                 L.load(v, nv);
-                area[v] = fabs(S.A[v][t]) / (2.0 * sqrt((nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2]));
+                uint32_t w = S.F[f0][t];
+                int e = vpos(w, v);
+                L.load(vv(w, e == 2 ? 0 : e + 1), a);
+                L.load(vv(w, e == 0 ? 2 : e - 1), b);
+                cell_vertex(nv, a, b, w0);
+                wp[0] = w0[0]; wp[1] = w0[1]; wp[2] = w0[2];
+                double sx = 0, sy = 0, sz = 0;
+                for (int step = 0; step < VF; step++) {
+                    const int g = vl(w, e);
+                    double wn[3];
+                    if (g == f0) {
+                        wn[0] = w0[0]; wn[1] = w0[1]; wn[2] = w0[2];
+                    } else {
+                        const uint32_t gw = S.F[g][t];
+                        const int eg = vpos(gw, v);
+                        // in g the edge v -> (previous successor) is reversed: the new point follows it
+                        double c[3];
+                        L.load(vv(gw, eg == 2 ? 0 : eg + 1), c);
+                        cell_vertex(nv, c, a, wn);
+                        a[0] = c[0]; a[1] = c[1]; a[2] = c[2];
+                        w = gw;
+                        e = eg;
+                    }
+                    sx += wp[1] * wn[2] - wp[2] * wn[1];
+                    sy += wp[2] * wn[0] - wp[0] * wn[2];
+                    sz += wp[0] * wn[1] - wp[1] * wn[0];
+                    wp[0] = wn[0]; wp[1] = wn[1]; wp[2] = wn[2];
+                    if (g == f0) break;
+                }
+                area[v] = fabs(sx * nv[0] + sy * nv[1] + sz * nv[2]) /
+                          (2.0 * sqrt((nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2]));
                 tot += area[v];
             }
             if (tot > 0) {
