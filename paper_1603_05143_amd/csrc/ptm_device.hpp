@@ -352,6 +352,9 @@ struct RealTraits<float> {
 // inner products of the two sets (upper bound sqrt(Ga Gb) on lambda).
 template <typename T>
 __host__ __device__ inline T qcp_solve(const T S[3][3], T Ga, T Gb, T q[4]) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     const T Sxx = S[0][0], Sxy = S[0][1], Sxz = S[0][2];
     const T Syx = S[1][0], Syy = S[1][1], Syz = S[1][2];
     const T Szx = S[2][0], Szy = S[2][1], Szz = S[2][2];
@@ -417,6 +420,9 @@ __host__ __device__ inline T qcp_solve(const T S[3][3], T Ga, T Gb, T q[4]) {
 
 template <typename T>
 __host__ __device__ inline void quat_rot(const T q[4], T R[3][3]) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     T w = q[0], x = q[1], y = q[2], z = q[3];
     R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z);     R[0][2] = 2 * (x * z + w * y);
     R[1][0] = 2 * (x * y + w * z);     R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
@@ -427,6 +433,9 @@ __host__ __device__ inline void quat_rot(const T q[4], T R[3][3]) {
 // eigenvectors in the columns of V
 template <typename T>
 __host__ __device__ inline void jacobi3(T A[3][3], T d[3], T V[3][3]) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) V[i][j] = (i == j) ? T(1) : T(0);
     for (int sweep = 0; sweep < 12; sweep++) {

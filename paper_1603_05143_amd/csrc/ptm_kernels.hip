@@ -1314,6 +1314,9 @@ struct CandEval {
 template <int K, typename T>
 __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const TemplateDev &D, uint64_t tv_of_rank,
                                       CandEval<T> &out) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     T Gb = 0;
     {
@@ -1363,6 +1366,9 @@ __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const Templat
 template <int K, typename T>
 __device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t n, int64_t p,
                                      const TemplateDev &D, uint64_t tv, CandEval<T> &out) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     double c[3] = {0, 0, 0};
 #pragma unroll 2
     for (int r = 0; r < K; r++)
@@ -1479,6 +1485,9 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
                                       const CandEval<RT> &ev, RT l, const RT (&At)[3][3], RT resid, double cutoff,
                                       int64_t p, int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
                                       const int8_t *__restrict__ species, const MatchOut &O) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
@@ -1614,6 +1623,9 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
                               const double *__restrict__ nbr_rel, double cutoff, int64_t p, int64_t n, int32_t i,
                               const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
                               const MatchOut &O) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
@@ -1658,6 +1670,9 @@ __device__ inline void finish_stored(const MatchShared &M, const TablesView &T, 
                                      double cutoff, int64_t p, int64_t n, int32_t i,
                                      const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
                                      const MatchOut &O) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
