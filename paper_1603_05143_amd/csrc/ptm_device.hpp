@@ -259,6 +259,9 @@ PTM_HD double f64_det3_bound(double m) { return fmax(5.4e-15 * m * m * m, 1e-290
 // det[b-a; c-a; d-a] sign from FP32 points widened to FP64 (evaluated as
 // -det[a-d; b-d; c-d]); 0 when |det| <= bound.
 PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d, double bound) {
+    // fused multiply-adds round once where a product and a sum round twice,
+    // so the error bound of the unfused evaluation covers them
+#pragma clang fp contract(fast)
     double adx = (double)a[0] - d[0], ady = (double)a[1] - d[1], adz = (double)a[2] - d[2];
     double bdx = (double)b[0] - d[0], bdy = (double)b[1] - d[1], bdz = (double)b[2] - d[2];
     double cdx = (double)c[0] - d[0], cdy = (double)c[1] - d[1], cdz = (double)c[2] - d[2];
@@ -269,6 +272,9 @@ PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, c
 }
 
 PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c, double bound) {
+    // fused multiply-adds round once where a product and a sum round twice,
+    // so the error bound of the unfused evaluation covers them
+#pragma clang fp contract(fast)
     double ax = a[0], ay = a[1], az = a[2], bx = b[0], by = b[1], bz = b[2], cx = c[0], cy = c[1], cz = c[2];
     double det = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
     if (det > bound) return 1;
@@ -279,6 +285,9 @@ PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c, dou
 // FP64 filters with a static bound (same evaluation as orient_filter64 /
 // det3_filter64, without the per-test permanent)
 PTM_HD int orient_filter64b(const double *a, const double *b, const double *c, const double *d, double bound) {
+    // fused multiply-adds round once where a product and a sum round twice,
+    // so the error bound of the unfused evaluation covers them
+#pragma clang fp contract(fast)
     double adx = a[0] - d[0], ady = a[1] - d[1], adz = a[2] - d[2];
     double bdx = b[0] - d[0], bdy = b[1] - d[1], bdz = b[2] - d[2];
     double cdx = c[0] - d[0], cdy = c[1] - d[1], cdz = c[2] - d[2];
@@ -289,6 +298,9 @@ PTM_HD int orient_filter64b(const double *a, const double *b, const double *c, c
 }
 
 PTM_HD int det3_filter64b(const double *a, const double *b, const double *c, double bound) {
+    // fused multiply-adds round once where a product and a sum round twice,
+    // so the error bound of the unfused evaluation covers them
+#pragma clang fp contract(fast)
     double det = a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
                  a[2] * (b[0] * c[1] - b[1] * c[0]);
     if (det > bound) return 1;

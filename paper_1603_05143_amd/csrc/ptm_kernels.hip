@@ -639,6 +639,7 @@ struct VLane {
 // the cell vertex of the facet (a, b, c): w.n_a = w.n_b = w.n_c = 1, i.e.
 // (n_b x n_c + n_c x n_a + n_a x n_b) / det[n_a; n_b; n_c]
 __device__ inline void cell_vertex(const double (&a)[3], const double (&b)[3], const double (&c)[3], double (&w)[3]) {
+#pragma clang fp contract(fast)
     const double bc0 = b[1] * c[2] - b[2] * c[1], bc1 = b[2] * c[0] - b[0] * c[2], bc2 = b[0] * c[1] - b[1] * c[0];
     const double ca0 = c[1] * a[2] - c[2] * a[1], ca1 = c[2] * a[0] - c[0] * a[2], ca2 = c[0] * a[1] - c[1] * a[0];
     const double ab0 = a[1] * b[2] - a[2] * b[1], ab1 = a[2] * b[0] - a[0] * b[2], ab2 = a[0] * b[1] - a[1] * b[0];
