@@ -879,16 +879,20 @@ constexpr int TB = 64;  // threads per block of the topology kernel
 
 // LDS of one block.  P: neighbour vectors (FP64 or FP32); F: facets; H: the
 // horizon of the current insertion, which shares its space with the
-// rotation system of a finished hull (built between insertions).
+// rotation system of a finished 6- or 12-point hull (built between
+// insertions).  The 14-point hull is the last: its rotation system takes the
+// space of P, which is no longer read.  FP32 form: 23,040 bytes, seven
+// blocks per CU.
 template <typename R>
 struct TopoShared {
     R P[3][KMAX][TB];
     uint32_t F[2 * KMAX - 4][TB];
     union {
         uint32_t H[KMAX][TB];
-        uint64_t NT[KMAX][TB];
+        uint64_t NT[KMAX - 2][TB];
     };
 };
+static_assert(sizeof(float) * 3 * KMAX >= sizeof(uint64_t) * KMAX, "a 14-row rotation system fits in P");
 
 // A lane's rotation system: row x = 64-bit word whose nibble y is the
 // vertex after y counter-clockwise around x (0xF: not a neighbour), kept in
@@ -1249,6 +1253,7 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
         }
         lane_hull_start<R>(L);
         const RotSys nt{S.NT, t};
+        const RotSys nt14{reinterpret_cast<uint64_t (*)[TB]>(&S.P[0][0][0]), t};
         for (int q = 4; q < kl; q++) {
             if (!lane_insert<R>(L, q)) break;
             const int K = q + 1;
@@ -1257,7 +1262,7 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
             } else if (K == 12 && (want & 2)) {
                 if (lane_centre_inside<R>(L, 12)) cid[1] = lane_lookup<12>(S.F, nt, T, ordw[1]);
             } else if (K == 14) {
-                if (lane_centre_inside<R>(L, 14)) cid[2] = lane_lookup<14>(S.F, nt, T, ordw[2]);
+                if (lane_centre_inside<R>(L, 14)) cid[2] = lane_lookup<14>(S.F, nt14, T, ordw[2]);
             }
         }
     }
