@@ -216,7 +216,7 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     if ((ps = mark(PTM_STAGE_TOPO)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
     const uint32_t need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
-    launch_topo(ctx->precision == PTM_FP32_MIXED, n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, st);
+    launch_topo(n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, st);
     if ((ps = mark(PTM_STAGE_CAND)) != PTM_OK) return ps;
     MatchOut O = {J.out.type,       J.out.alloy,     J.out.rmsd,
                   J.out.scale,      J.out.quat,      J.out.neighbours,

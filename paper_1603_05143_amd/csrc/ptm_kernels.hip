@@ -2237,11 +2237,15 @@ void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, double 
     const int64_t blocks = (n + VB - 1) / VB;
     hipLaunchKernelGGL(k_voronoi, dim3((unsigned)xcd_pad(blocks)), dim3(VB), 0, st, n, rel18, id18, nbr_rel, nbr_id);
 }
-void launch_topo(bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
-                 uint32_t need, int32_t *code, uint64_t *ord, hipStream_t st) {
+// Both precision forms use the FP32-storage hull kernel: every predicate is
+// exact (a filter on the FP32 copies decides only when its bound proves the
+// sign of the predicate on the FP64 inputs, otherwise the FP64 filter and
+// the exact path run on the originals), so the hulls, codes and labellings
+// are those of the FP64 kernel, with half the LDS per lane.
+void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
+                 int32_t *code, uint64_t *ord, hipStream_t st) {
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
-    if (f32) hipLaunchKernelGGL(k_topo<float>, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
-    else hipLaunchKernelGGL(k_topo<double>, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
+    hipLaunchKernelGGL(k_topo<float>, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
 }
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
                  hipStream_t st) {

@@ -69,8 +69,8 @@ void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, double 
                     hipStream_t st);
 // hulls of the first 6 / 12 / 14 neighbours (need: bit g for group g);
 // code ids and labellings into code / ord [group][n]
-void launch_topo(bool f32, int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T,
-                 uint32_t need, int32_t *code, uint64_t *ord, hipStream_t st);
+void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
+                 int32_t *code, uint64_t *ord, hipStream_t st);
 // match stage: candidate pair list, superposition of every pair, decision
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
                  hipStream_t st);
