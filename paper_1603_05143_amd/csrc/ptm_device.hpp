@@ -234,20 +234,26 @@ PTM_HD int det3_filter64(const double *a, const double *b, const double *c) {
 // largest coordinate of its neighbour vectors), so a test costs the
 // determinant alone.  Tiny sets (bound below 1e-290) are never decided.
 //
-// FP32 storage: each coordinate x32 is the FP32 rounding of the exact FP64
-// input (|x32 - x| <= 2^-24 |x|, and m is taken from the x32 with a factor
-// 1 + 2^-22); the determinant is evaluated in FP64 on the widened values, so
-// e = 2^-24 (|a| + |d|) <= 2^-23 m plus the FP64 difference rounding, and the
-// FP64 evaluation adds < 1e-13 m^3: orient 144 m^3 (2^-24 + 2^-53) <= 8.6e-6
-// m^3 -> 8.7e-6 m^3; det3 18 m^3 2^-24 -> 1.1e-6 m^3.  A decided sign is the
-// exact sign of the predicate on the FP64 inputs.
+// FP32 storage and FP32 arithmetic: each coordinate x32 is the FP32
+// rounding of the exact FP64 input (|x32 - x| <= 2^-24 |x|; m is taken from
+// the x32 with a factor 1 + 2^-22).  Orientation: a difference computed in
+// FP32 is off the exact one by at most 2^-24 (|a| + |d|) + 2^-24 |a32 - d32|
+// <= 2^-22 m, which moves the determinant by at most 18 (2m)^2 2^-22 m =
+// 288 2^-24 m^3; the FP32 evaluation (three roundings inside each of the six
+// triple products, two in the sums) adds at most 5 2^-24 times the
+// permanent, <= 6 (2m)^3 = 48 m^3: 528 2^-24 m^3 = 3.15e-5 m^3 -> 3.3e-5 m^3.
+// det[a; b; c]: 18 m^3 2^-24 for the inputs, 5 2^-24 6 m^3 for the
+// evaluation: 48 2^-24 m^3 = 2.9e-6 m^3 -> 3.0e-6 m^3.  Outside 1e-9 < M <
+// 1e12 (FP32 underflow or overflow of the products) the filter never
+// decides.  A decided sign is the exact sign of the predicate on the FP64
+// inputs.
 PTM_HD double f32_orient_bound(double m) {
     double M = m * (1.0 + 0x1p-22);
-    return fmax(8.7e-6 * M * M * M, 1e-290);
+    return (M > 1e-9 && M < 1e12) ? 3.3e-5 * M * M * M : INFINITY;
 }
 PTM_HD double f32_det3_bound(double m) {
     double M = m * (1.0 + 0x1p-22);
-    return fmax(1.1e-6 * M * M * M, 1e-290);
+    return (M > 1e-9 && M < 1e12) ? 3.0e-6 * M * M * M : INFINITY;
 }
 // FP64 inputs: the rounding of the differences (e = 2^-53 2m) and 10 unit
 // roundoffs of the evaluation on a permanent of at most 6 (2m)^3 give
@@ -256,29 +262,33 @@ PTM_HD double f32_det3_bound(double m) {
 PTM_HD double f64_orient_bound(double m) { return fmax(7e-14 * m * m * m, 1e-290); }
 PTM_HD double f64_det3_bound(double m) { return fmax(5.4e-15 * m * m * m, 1e-290); }
 
-// det[b-a; c-a; d-a] sign from FP32 points widened to FP64 (evaluated as
-// -det[a-d; b-d; c-d]); 0 when |det| <= bound.
+// det[b-a; c-a; d-a] sign from FP32 points in FP32 arithmetic (evaluated as
+// -det[a-d; b-d; c-d]); 0 when |det| <= bound (f32_orient_bound).
 PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d, double bound) {
     // fused multiply-adds round once where a product and a sum round twice,
     // so the error bound of the unfused evaluation covers them
 #pragma clang fp contract(fast)
-    double adx = (double)a[0] - d[0], ady = (double)a[1] - d[1], adz = (double)a[2] - d[2];
-    double bdx = (double)b[0] - d[0], bdy = (double)b[1] - d[1], bdz = (double)b[2] - d[2];
-    double cdx = (double)c[0] - d[0], cdy = (double)c[1] - d[1], cdz = (double)c[2] - d[2];
-    double det = adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
-    if (det > bound) return -1;
-    if (det < -bound) return 1;
+    const float adx = a[0] - d[0], ady = a[1] - d[1], adz = a[2] - d[2];
+    const float bdx = b[0] - d[0], bdy = b[1] - d[1], bdz = b[2] - d[2];
+    const float cdx = c[0] - d[0], cdy = c[1] - d[1], cdz = c[2] - d[2];
+    const float det = adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
+    const float bf = (float)bound;
+    if (det > bf) return -1;
+    if (det < -bf) return 1;
     return 0;
 }
 
+// det[a; b; c] sign from FP32 points in FP32 arithmetic; 0 when |det| <=
+// bound (f32_det3_bound)
 PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c, double bound) {
     // fused multiply-adds round once where a product and a sum round twice,
     // so the error bound of the unfused evaluation covers them
 #pragma clang fp contract(fast)
-    double ax = a[0], ay = a[1], az = a[2], bx = b[0], by = b[1], bz = b[2], cx = c[0], cy = c[1], cz = c[2];
-    double det = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
-    if (det > bound) return 1;
-    if (det < -bound) return -1;
+    const float det = a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+                      a[2] * (b[0] * c[1] - b[1] * c[0]);
+    const float bf = (float)bound;
+    if (det > bf) return 1;
+    if (det < -bf) return -1;
     return 0;
 }
 

@@ -194,7 +194,7 @@ def test_f32_filters_never_decide_wrongly(ptm):
         p = rng.normal(size=(4, 3)) * 2.5
         if kind == 1:   # nearly coplanar: d in the plane of a, b, c plus a tiny offset
             s, t = rng.random(2)
-            p[3] = p[0] + s * (p[1] - p[0]) + t * (p[2] - p[0]) + rng.normal(size=3) * 10.0 ** rng.uniform(-9, -4)
+            p[3] = p[0] + s * (p[1] - p[0]) + t * (p[2] - p[0]) + rng.normal(size=3) * 10.0 ** rng.uniform(-9, -1)
         elif kind == 2:  # lattice-like exact coplanarity in FP64, broken by FP32 rounding
             q = rng.integers(-2, 3, size=(4, 3)) * 1.8075
             q[3] = q[0] + (q[1] - q[0]) - (q[2] - q[0])
