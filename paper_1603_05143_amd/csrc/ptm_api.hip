@@ -49,6 +49,8 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     if (topo) {
         b += align_up(4 * (size_t)n * VK);      // the 18 Euclidean neighbours' ids
         b += align_up(8 * (size_t)n * VK * 3);  // and vectors
+        b += align_up(4 * (size_t)n * (2 * VK - 4));  // facets of their Voronoi hull
+        b += align_up(4 * (size_t)n);                 // and its facet masks
     }
     return b;
 }
@@ -107,6 +109,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     match.scan_tmp_bytes = scan_tmp;
     id18 = topo ? (int32_t *)take(4 * (size_t)n * VK) : nullptr;
     rel18 = topo ? (double *)take(8 * (size_t)n * VK * 3) : nullptr;
+    vf = topo ? (uint32_t *)take(4 * (size_t)n * (2 * VK - 4)) : nullptr;
+    vlive = topo ? (uint32_t *)take(4 * (size_t)n) : nullptr;
     return true;
 }
 
@@ -208,7 +212,7 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
         // the 18 Euclidean neighbours, then their topological order (Sec. 3)
         launch_knn(n, g, VK, S.sx, S.sy, S.sz, S.sid, S.start, S.id18, S.rel18, J.out.knn, S.slot_of,
                    S.count + cells + 1, st);
-        launch_voronoi(n, S.rel18, S.id18, S.nbr_rel, S.nbr_id, st);
+        launch_voronoi(n, S.rel18, S.id18, S.vf, S.vlive, S.nbr_rel, S.nbr_id, st);
     } else {
         launch_knn(n, g, KMAX, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, S.slot_of,
                    S.count + cells + 1, st);

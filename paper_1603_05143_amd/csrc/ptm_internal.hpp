@@ -33,6 +33,8 @@ struct FrameScratch {
     double *nbr_rel = nullptr;
     int32_t *id18 = nullptr;    // topological ordering: the 18 Euclidean neighbours
     double *rel18 = nullptr;
+    uint32_t *vf = nullptr;     // and the facets of their Voronoi hull, [32][n] + live masks [n]
+    uint32_t *vlive = nullptr;
     int32_t *code = nullptr;
     uint64_t *ord = nullptr;
     double *part = nullptr;

@@ -568,31 +568,45 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
 // ------------------------------------------------- topological ordering
 // Sec. 3: neighbours ordered by the area of the interface between the
 // Voronoi cell of the centre and theirs, larger first, then by 1/d; the cell
-// is that of the centre and its 18 nearest neighbours (Sec. 9).  One lane
-// per atom.  The cell {x : x.n_j <= 1}, n_j = 2 d_j / |d_j|^2, is the polar
-// of the convex hull of the points n_j: hull vertices are the cell's faces,
-// each hull facet (a, b, c) is a cell vertex w (w.n_a = w.n_b = w.n_c = 1)
-// and hull edges are cell edges.  The hull is built incrementally with
-// exact predicates and Simulation of Simplicity by Euclidean rank (points
-// inside the current hull are skipped; vertices that a later point swallows
-// drop out of every facet), then the area of face v is
-// |sum over the facets f at v of (w_f x w_g) . n_v| / (2 |n_v|), g being the
-// facet across f's edge that starts at v: consecutive vertices of the face
-// polygon, in one consistent direction.  Areas are compared on a grid of
-// 2^-20 of the cell's surface, so that equal areas tie whatever their
-// rounding; ties fall to the Euclidean rank, i.e. to 1/d.  Atoms with fewer
-// than 18 neighbours, or an unbounded cell (the centre not strictly inside
-// the hull), keep the Euclidean order: no hull of any subset of their
-// neighbours can then hold the centre.
+// is that of the centre and its 18 nearest neighbours (Sec. 9).  The cell
+// {x : x.n_j <= 1}, n_j = 2 d_j / |d_j|^2, is the polar of the convex hull
+// of the points n_j: hull vertices are the cell's faces, each hull facet
+// (a, b, c) is a cell vertex w (w.n_a = w.n_b = w.n_c = 1) and hull edges
+// are cell edges.  Two kernels, one lane per atom in each:
+//   k_voronoi_hull   builds the hull incrementally with exact predicates and
+//                    Simulation of Simplicity by Euclidean rank (points
+//                    inside the current hull are skipped; vertices that a
+//                    later point swallows drop out of every facet) and
+//                    writes its facets;
+//   k_voronoi_order  reads them back, computes the area of face v as
+//                    |sum over the facets f at v of (w_f x w_g) . n_v| /
+//                    (2 |n_v|), g being the facet across f's edge that starts
+//                    at v (consecutive vertices of the face polygon, in one
+//                    direction), and writes the first 14 neighbours in the
+//                    topological order.
+// The hull keeps FP32 copies of the points in LDS (an exact filter, with the
+// FP64 points recomputed from the neighbour vectors when it cannot decide),
+// the areas need the FP64 points: splitting the two lets each kernel hold
+// only what it reads.  Areas are compared on a grid of 2^-20 of the cell's
+// surface, so that equal areas tie whatever their rounding; ties fall to the
+// Euclidean rank, i.e. to 1/d.  Atoms with fewer than 18 neighbours, or an
+// unbounded cell (the centre not strictly inside the hull), keep the
+// Euclidean order: no hull of any subset of their neighbours can then hold
+// the centre.
 constexpr int VF = 2 * VK - 4;  // facets of a triangulated sphere on 18 vertices
 constexpr int VB = 64;          // lanes per block
 constexpr double AREA_GRID = 1048576.0;
 
-// 38 KB per 64-lane block: four blocks per CU
-struct VoronoiShared {
-    double P[3][VK][VB];  // the points n_j, component-major, lane-minor
-    uint32_t F[VF][VB];   // facets: vertices a | b << 5 | c << 10, link e at 15 + 5 e
-    uint16_t H[VK][VB];   // horizon edges of the insertion in progress: a | b << 5 | g << 10
+// 24,320 bytes per 64-lane block: six blocks per CU
+struct VHullShared {
+    float P[3][VK][VB];  // the points n_j rounded to FP32, component-major, lane-minor
+    uint32_t F[VF][VB];  // facets: vertices a | b << 5 | c << 10, link e at 15 + 5 e
+    uint16_t H[VK][VB];  // horizon edges of the insertion in progress: a | b << 5 | g << 10
+};
+// 35,840 bytes per 64-lane block
+struct VAreaShared {
+    double P[3][VK][VB];  // the points n_j
+    uint32_t F[VF][VB];
 };
 
 __device__ inline uint32_t vpack(int a, int b, int c, int g0, int g1, int g2) {
@@ -611,28 +625,55 @@ __device__ inline void set5(uint64_t &lo, uint64_t &hi, int v, int s) {
     else hi |= (uint64_t)s << (5 * (v - 12));
 }
 
+// n_j = d_j * (2 / |d_j|^2) from the neighbour vectors: the one definition
+// of the FP64 points, used by both kernels
+__device__ inline void dual_point(const double *__restrict__ rel18, int64_t n, int64_t p, int j, double (&x)[3]) {
+    const double a = rel18[((int64_t)j * 3 + 0) * n + p], b = rel18[((int64_t)j * 3 + 1) * n + p],
+                 c = rel18[((int64_t)j * 3 + 2) * n + p];
+    const double sc = 2.0 / ((a * a + b * b) + c * c);
+    x[0] = a * sc;
+    x[1] = b * sc;
+    x[2] = c * sc;
+}
+
 struct VLane {
-    VoronoiShared &S;
+    VHullShared &S;
     int t;
-    double bo, bd;  // static filter bounds of this lane's points
-    __device__ void load(int j, double (&x)[3]) const {
+    const double *__restrict__ rel18;
+    int64_t n, p;
+    double bo, bd;      // FP32 filter bounds of this lane's points
+    double bo64, bd64;  // FP64 filter bounds
+    __device__ void load(int j, float (&x)[3]) const {
         x[0] = S.P[0][j][t];
         x[1] = S.P[1][j][t];
         x[2] = S.P[2][j][t];
     }
-    __device__ int orient(int a, int b, int c, const double (&pq)[3], int q) const {
-        double pa[3], pb[3], pc[3];
+    __device__ int orient(int a, int b, int c, const float (&pq)[3], int q) const {
+        float pa[3], pb[3], pc[3];
         load(a, pa);
         load(b, pb);
         load(c, pc);
-        return orient_sos64b(pa, pb, pc, pq, a, b, c, q, bo);
+        const int s = orient_filter_f32in(pa, pb, pc, pq, bo);
+        if (s) return s;
+        double da[3], db[3], dc[3], dq[3];
+        dual_point(rel18, n, p, a, da);
+        dual_point(rel18, n, p, b, db);
+        dual_point(rel18, n, p, c, dc);
+        dual_point(rel18, n, p, q, dq);
+        return orient_sos64b(da, db, dc, dq, a, b, c, q, bo64);
     }
     __device__ int det3(uint32_t f) const {
-        double pa[3], pb[3], pc[3];
+        float pa[3], pb[3], pc[3];
         load(vv(f, 0), pa);
         load(vv(f, 1), pb);
         load(vv(f, 2), pc);
-        return det3_sign64b(pa, pb, pc, bd);
+        const int s = det3_filter_f32in(pa, pb, pc, bd);
+        if (s) return s;
+        double da[3], db[3], dc[3];
+        dual_point(rel18, n, p, vv(f, 0), da);
+        dual_point(rel18, n, p, vv(f, 1), db);
+        dual_point(rel18, n, p, vv(f, 2), dc);
+        return det3_sign64b(da, db, dc, bd64);
     }
 };
 
@@ -653,7 +694,7 @@ __device__ inline void cell_vertex(const double (&a)[3], const double (&b)[3], c
 __device__ inline void vhull_start(const VLane &L) {
     int a = 0, b = 1, c = 2;
     const int d = 3;
-    double p3[3];
+    float p3[3];
     L.load(3, p3);
     if (L.orient(0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
     L.S.F[0][L.t] = vpack(a, b, c, 1, 2, 3);
@@ -667,9 +708,9 @@ __device__ inline void vhull_start(const VLane &L) {
 // slots (the visible facets' included).  Returns false on an inconsistent
 // hull, which exact predicates never produce.
 __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
-    VoronoiShared &S = L.S;
+    VHullShared &S = L.S;
     const int t = L.t;
-    double pp[3];
+    float pp[3];
     L.load(p, pp);
     uint32_t vis = 0;
     for (uint32_t m = live; m; m &= m - 1) {
@@ -721,18 +762,18 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
 }
 
 // Squared distance from the origin of the closest facet plane of a hull
-// that holds the origin, lowered by a relative 1e-6 (far above the rounding
-// of the evaluation): a point closer to the origin than this is strictly
-// inside the hull, and so inside every later (larger) hull.  -1 when the
-// origin is not inside.
+// that holds the origin, from the FP64 points, lowered by a relative 1e-6
+// (far above the rounding of the evaluation): a point closer to the origin
+// than this is strictly inside the hull, and so inside every later (larger)
+// hull.  -1 when the origin is not inside.
 __device__ inline double vhull_inradius2(const VLane &L, uint32_t live) {
     double r2 = INFINITY;
     for (uint32_t m = live; m; m &= m - 1) {
         const uint32_t w = L.S.F[__builtin_ctz(m)][L.t];
         double a[3], b[3], c[3];
-        L.load(vv(w, 0), a);
-        L.load(vv(w, 1), b);
-        L.load(vv(w, 2), c);
+        dual_point(L.rel18, L.n, L.p, vv(w, 0), a);
+        dual_point(L.rel18, L.n, L.p, vv(w, 1), b);
+        dual_point(L.rel18, L.n, L.p, vv(w, 2), c);
         const double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
         const double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
         const double n0 = u1 * v2 - u2 * v1, n1 = u2 * v0 - u0 * v2, n2 = u0 * v1 - u1 * v0;
@@ -743,10 +784,67 @@ __device__ inline double vhull_inradius2(const VLane &L, uint32_t live) {
     return r2 * (1.0 - 1e-6);
 }
 
-__global__ void __launch_bounds__(VB) k_voronoi(int64_t n, const double *__restrict__ rel18,
-                                                const int32_t *__restrict__ id18, double *__restrict__ nbr_rel,
-                                                int32_t *__restrict__ nbr_id) {
-    __shared__ VoronoiShared S;
+// Hull of the 18 points of each atom; facets to vf[f][n] (slots in the
+// 32-bit mask vlive[n], 0 when the atom keeps its Euclidean order).
+__global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__restrict__ rel18,
+                                                     const int32_t *__restrict__ id18, uint32_t *__restrict__ vf,
+                                                     uint32_t *__restrict__ vlive) {
+    __shared__ VHullShared S;
+    const int t = threadIdx.x;
+    const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)VB + t;
+    if (p >= n) return;
+    bool topo = id18[(int64_t)(VK - 1) * n + p] >= 0;
+    float m = 0;
+    for (int v = 0; v < VK; v++) {
+        double x[3];
+        dual_point(rel18, n, p, v, x);
+        topo = topo && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+        for (int d = 0; d < 3; d++) {
+            const float xf = (float)x[d];
+            S.P[d][v][t] = xf;
+            m = fmaxf(m, fabsf(xf));
+        }
+    }
+    uint32_t live = 0;
+    if (topo) {
+        double m64 = 0;
+        for (int v = 0; v < VK; v++)
+            for (int d = 0; d < 3; d++) m64 = fmax(m64, fabs((double)S.P[d][v][t]));
+        // the FP64 bounds from the largest coordinate of the FP32 copies, widened to cover the rounding
+        m64 *= 1.0 + 0x1p-22;
+        VLane L{S, t, rel18, n, p, f32_orient_bound(m), f32_det3_bound(m), f64_orient_bound(m64),
+                f64_det3_bound(m64)};
+        vhull_start(L);
+        live = 0xFu;
+        double rin2 = -1.0;  // inradius bound of the 12-point hull
+        for (int q = 4; q < VK && topo; q++) {
+            if (q == 12) rin2 = vhull_inradius2(L, live);
+            if (q >= 12 && rin2 > 0) {
+                double pq[3];
+                dual_point(rel18, n, p, q, pq);
+                if ((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2] < rin2) continue;  // strictly inside
+            }
+            topo = vhull_insert(L, q, live);
+        }
+        // the centre strictly inside every facet
+        for (uint32_t mm = live; mm && topo; mm &= mm - 1) topo = L.det3(S.F[__builtin_ctz(mm)][t]) > 0;
+        if (!topo) live = 0;
+        for (uint32_t mm = live; mm; mm &= mm - 1) {
+            const int f = __builtin_ctz(mm);
+            vf[(int64_t)f * n + p] = S.F[f][t];
+        }
+    }
+    vlive[p] = live;
+}
+
+// Areas, keys and the topological order from the facets of k_voronoi_hull.
+__global__ void __launch_bounds__(VB) k_voronoi_order(int64_t n, const double *__restrict__ rel18,
+                                                      const int32_t *__restrict__ id18,
+                                                      const uint32_t *__restrict__ vf,
+                                                      const uint32_t *__restrict__ vlive,
+                                                      double *__restrict__ nbr_rel, int32_t *__restrict__ nbr_id) {
+#pragma clang fp contract(fast)
+    __shared__ VAreaShared S;
     const int t = threadIdx.x;
     const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)VB + t;
     if (p >= n) return;
@@ -754,101 +852,84 @@ __global__ void __launch_bounds__(VB) k_voronoi(int64_t n, const double *__restr
     uint32_t key[VK];
 #pragma unroll
     for (int v = 0; v < VK; v++) key[v] = (uint32_t)v;
-    bool topo = id18[(int64_t)(VK - 1) * n + p] >= 0;
-    double m = 0;
-#pragma unroll
-    for (int v = 0; v < VK; v++) {
-        const double x = rel18[((int64_t)v * 3 + 0) * n + p], y = rel18[((int64_t)v * 3 + 1) * n + p],
-                     z = rel18[((int64_t)v * 3 + 2) * n + p];
-        const double d2 = (x * x + y * y) + z * z;
-        topo = topo && d2 > 0;
-        const double sc = 2.0 / d2;
-        const double nx = x * sc, ny = y * sc, nz = z * sc;
-        S.P[0][v][t] = nx;
-        S.P[1][v][t] = ny;
-        S.P[2][v][t] = nz;
-        m = fmax(m, fmax(fabs(nx), fmax(fabs(ny), fabs(nz))));
-    }
-    if (topo) {
-        VLane L{S, t, f64_orient_bound(m), f64_det3_bound(m)};
-        vhull_start(L);
-        uint32_t live = 0xFu;
-        double rin2 = -1.0;  // inradius bound of the 12-point hull
-        for (int q = 4; q < VK && topo; q++) {
-            if (q == 12) rin2 = vhull_inradius2(L, live);
-            if (q >= 12) {
-                double pq[3];
-                L.load(q, pq);
-                if ((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2] < rin2) continue;  // strictly inside
-            }
-            topo = vhull_insert(L, q, live);
+    const uint32_t live = vlive[p];
+    if (live) {
+        for (int v = 0; v < VK; v++) {
+            double x[3];
+            dual_point(rel18, n, p, v, x);
+            S.P[0][v][t] = x[0];
+            S.P[1][v][t] = x[1];
+            S.P[2][v][t] = x[2];
         }
-        // the centre strictly inside every facet
-        for (uint32_t mm = live; mm && topo; mm &= mm - 1) topo = L.det3(S.F[__builtin_ctz(mm)][t]) > 0;
-        if (topo) {
-            // one facet at each vertex: 5-bit fields, 31 = not a vertex (a
-            // vertex has at least three facets, so slot 31 is never needed)
-            uint64_t at_lo = ~0ull, at_hi = ~0ull;
-            for (uint32_t mm = live & 0x7FFFFFFFu; mm; mm &= mm - 1) {
-                const int f = __builtin_ctz(mm);
-                const uint32_t w = S.F[f][t];
-                for (int e = 0; e < 3; e++) {
-                    const int x = vv(w, e);
-                    if (x < 12) at_lo = (at_lo & ~(31ull << (5 * x))) | ((uint64_t)f << (5 * x));
-                    else at_hi = (at_hi & ~(31ull << (5 * (x - 12)))) | ((uint64_t)f << (5 * (x - 12)));
-                }
+        // one facet at each vertex: 5-bit fields, 31 = not a vertex (a
+        // vertex has at least three facets, so slot 31 is never needed)
+        uint64_t at_lo = ~0ull, at_hi = ~0ull;
+        for (uint32_t mm = live; mm; mm &= mm - 1) {
+            const int f = __builtin_ctz(mm);
+            const uint32_t w = vf[(int64_t)f * n + p];
+            S.F[f][t] = w;
+            if (f == 31) continue;
+            for (int e = 0; e < 3; e++) {
+                const int x = vv(w, e);
+                if (x < 12) at_lo = (at_lo & ~(31ull << (5 * x))) | ((uint64_t)f << (5 * x));
+                else at_hi = (at_hi & ~(31ull << (5 * (x - 12)))) | ((uint64_t)f << (5 * (x - 12)));
             }
-            // face v: walk the facets around v (each next one across the
-            // edge that starts at v), summing w_f x w_next; every step
-            // brings one new point, the facet's vertex after v's successor
-            double area[VK], tot = 0;
+        }
+        auto load = [&](int j, double (&x)[3]) {
+            x[0] = S.P[0][j][t];
+            x[1] = S.P[1][j][t];
+            x[2] = S.P[2][j][t];
+        };
+        // face v: walk the facets around v (each next one across the edge
+        // that starts at v), summing w_f x w_next; every step brings one new
+        // point, the facet's vertex after v
+        double area[VK], tot = 0;
+#pragma unroll
+        for (int v = 0; v < VK; v++) {
+            area[v] = 0;
+            const int f0 = field5(at_lo, at_hi, v);
+            if (f0 == 31) continue;
+            double nv[3], a[3], b[3], w0[3], wp[3];
+            load(v, nv);
+            uint32_t w = S.F[f0][t];
+            int e = vpos(w, v);
+            load(vv(w, e == 2 ? 0 : e + 1), a);
+            load(vv(w, e == 0 ? 2 : e - 1), b);
+            cell_vertex(nv, a, b, w0);
+            wp[0] = w0[0]; wp[1] = w0[1]; wp[2] = w0[2];
+            double sx = 0, sy = 0, sz = 0;
+            for (int step = 0; step < VF; step++) {
+                const int g = vl(w, e);
+                double wn[3];
+                if (g == f0) {
+                    wn[0] = w0[0]; wn[1] = w0[1]; wn[2] = w0[2];
+                } else {
+                    const uint32_t gw = S.F[g][t];
+                    const int eg = vpos(gw, v);
+                    // in g the edge v -> (previous successor) is reversed: the new point follows v
+                    double c[3];
+                    load(vv(gw, eg == 2 ? 0 : eg + 1), c);
+                    cell_vertex(nv, c, a, wn);
+                    a[0] = c[0]; a[1] = c[1]; a[2] = c[2];
+                    w = gw;
+                    e = eg;
+                }
+                sx += wp[1] * wn[2] - wp[2] * wn[1];
+                sy += wp[2] * wn[0] - wp[0] * wn[2];
+                sz += wp[0] * wn[1] - wp[1] * wn[0];
+                wp[0] = wn[0]; wp[1] = wn[1]; wp[2] = wn[2];
+                if (g == f0) break;
+            }
+            area[v] = fabs(sx * nv[0] + sy * nv[1] + sz * nv[2]) /
+                      (2.0 * sqrt((nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2]));
+            tot += area[v];
+        }
+        if (tot > 0) {
 #pragma unroll
             for (int v = 0; v < VK; v++) {
-                area[v] = 0;
-                const int f0 = field5(at_lo, at_hi, v);
-                if (f0 == 31) continue;
-                double nv[3], a[3], b[3], w0[3], wp[3];
-                L.load(v, nv);
-                uint32_t w = S.F[f0][t];
-                int e = vpos(w, v);
-                L.load(vv(w, e == 2 ? 0 : e + 1), a);
-                L.load(vv(w, e == 0 ? 2 : e - 1), b);
-                cell_vertex(nv, a, b, w0);
-                wp[0] = w0[0]; wp[1] = w0[1]; wp[2] = w0[2];
-                double sx = 0, sy = 0, sz = 0;
-                for (int step = 0; step < VF; step++) {
-                    const int g = vl(w, e);
-                    double wn[3];
-                    if (g == f0) {
-                        wn[0] = w0[0]; wn[1] = w0[1]; wn[2] = w0[2];
-                    } else {
-                        const uint32_t gw = S.F[g][t];
-                        const int eg = vpos(gw, v);
-                        // in g the edge v -> (previous successor) is reversed: the new point follows it
-                        double c[3];
-                        L.load(vv(gw, eg == 2 ? 0 : eg + 1), c);
-                        cell_vertex(nv, c, a, wn);
-                        a[0] = c[0]; a[1] = c[1]; a[2] = c[2];
-                        w = gw;
-                        e = eg;
-                    }
-                    sx += wp[1] * wn[2] - wp[2] * wn[1];
-                    sy += wp[2] * wn[0] - wp[0] * wn[2];
-                    sz += wp[0] * wn[1] - wp[1] * wn[0];
-                    wp[0] = wn[0]; wp[1] = wn[1]; wp[2] = wn[2];
-                    if (g == f0) break;
-                }
-                area[v] = fabs(sx * nv[0] + sy * nv[1] + sz * nv[2]) /
-                          (2.0 * sqrt((nv[0] * nv[0] + nv[1] * nv[1]) + nv[2] * nv[2]));
-                tot += area[v];
-            }
-            if (tot > 0) {
-#pragma unroll
-                for (int v = 0; v < VK; v++) {
-                    const double x = area[v] / tot * AREA_GRID;
-                    const uint32_t q = (uint32_t)fmin(fmax(floor(x), 0.0), AREA_GRID);
-                    key[v] = (((uint32_t)AREA_GRID - q) << 5) | (uint32_t)v;
-                }
+                const double x = area[v] / tot * AREA_GRID;
+                const uint32_t q = (uint32_t)fmin(fmax(floor(x), 0.0), AREA_GRID);
+                key[v] = (((uint32_t)AREA_GRID - q) << 5) | (uint32_t)v;
             }
         }
     }
@@ -2232,10 +2313,12 @@ void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double
     else
         launch_knn_nk<KMAX>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, todo, todo_count, st);
 }
-void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, double *nbr_rel, int32_t *nbr_id,
-                    hipStream_t st) {
-    const int64_t blocks = (n + VB - 1) / VB;
-    hipLaunchKernelGGL(k_voronoi, dim3((unsigned)xcd_pad(blocks)), dim3(VB), 0, st, n, rel18, id18, nbr_rel, nbr_id);
+void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_t *vf, uint32_t *vlive,
+                    double *nbr_rel, int32_t *nbr_id, hipStream_t st) {
+    const unsigned grid = (unsigned)xcd_pad((n + VB - 1) / VB);
+    hipLaunchKernelGGL(k_voronoi_hull, dim3(grid), dim3(VB), 0, st, n, rel18, id18, vf, vlive);
+    hipLaunchKernelGGL(k_voronoi_order, dim3(grid), dim3(VB), 0, st, n, rel18, id18, (const uint32_t *)vf,
+                       (const uint32_t *)vlive, nbr_rel, nbr_id);
 }
 // Both precision forms use the FP32-storage hull kernel: every predicate is
 // exact (a filter on the FP32 copies decides only when its bound proves the

@@ -65,8 +65,9 @@ void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double
                 int32_t *todo, int32_t *todo_count, hipStream_t st);
 // topological order (Sec. 3) of the 18 neighbours in rel18 / id18: the first
 // 14 go to nbr_rel / nbr_id
-void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, double *nbr_rel, int32_t *nbr_id,
-                    hipStream_t st);
+// (vf: [32][n] facet words, vlive: [n] facet masks, scratch between the two kernels)
+void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_t *vf, uint32_t *vlive,
+                    double *nbr_rel, int32_t *nbr_id, hipStream_t st);
 // hulls of the first 6 / 12 / 14 neighbours (need: bit g for group g);
 // code ids and labellings into code / ord [group][n]
 void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
