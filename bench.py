@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
 
 # kernel(s) behind each single-kernel stage, for the roofline line
-STAGE_KERNEL = {"knn": "k_knn_fast + k_knn_exact", "topo": "k_topo", "eval": "k_cand_eval",
-                "decide": "k_decide + k_decide_full"}
+STAGE_KERNEL = {"knn": "k_knn_fast<14> + k_knn_exact<14>", "topo": "k_topo<float>", "eval": "k_cand_eval<float>",
+                "decide": "k_decide<float> + k_decide_full<float>"}
 
 
 def orient_tests(K: int) -> int:
@@ -409,7 +409,7 @@ def main():
         roof = {"bound": "alu", "achieved": work / t / 1e12, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(dom, "fp32_mixed")
-    roof["kernel"] = STAGE_KERNEL[dom] + " (FP32-mixed)"
+    roof["kernel"] = STAGE_KERNEL[dom] + " in the FP32-mixed frame"
     roof["kernel_ms"] = stage_ms[dom]
     roof["work_per_launch"] = work
     roof["work_unit"] = unit
