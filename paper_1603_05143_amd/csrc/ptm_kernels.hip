@@ -933,17 +933,22 @@ __global__ void __launch_bounds__(VB) k_voronoi_order(int64_t n, const double *_
             }
         }
     }
+    int pos[VK];
 #pragma unroll
     for (int v = 0; v < VK; v++) {
-        int pos = 0;
+        pos[v] = 0;
 #pragma unroll
-        for (int u = 0; u < VK; u++) pos += key[u] < key[v];
-        if (pos < KMAX) {
-            nbr_id[(int64_t)pos * n + p] = id18[(int64_t)v * n + p];
+        for (int u = 0; u < VK; u++) pos[v] += key[u] < key[v];
+    }
+    // output row by output row, so that the lanes of a wave write each row
+    // together (whole cache lines); the source row differs per lane
+    for (int m = 0; m < KMAX; m++) {
+        int src = 0;
 #pragma unroll
-            for (int c = 0; c < 3; c++)
-                nbr_rel[((int64_t)pos * 3 + c) * n + p] = rel18[((int64_t)v * 3 + c) * n + p];
-        }
+        for (int v = 0; v < VK; v++) src = pos[v] == m ? v : src;
+        nbr_id[(int64_t)m * n + p] = id18[(int64_t)src * n + p];
+#pragma unroll
+        for (int c = 0; c < 3; c++) nbr_rel[((int64_t)m * 3 + c) * n + p] = rel18[((int64_t)src * 3 + c) * n + p];
     }
 }
 
