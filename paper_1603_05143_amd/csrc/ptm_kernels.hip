@@ -400,25 +400,42 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
                 more = false;
             }
         }
-        double t = INF;
+        // up to two candidates per step: their loads are independent, so the
+        // second one's latency hides behind the first's
+        double t = INF, t2 = INF;
         if (q < qend) {
-            double dx, dy, dz;
+            const bool two = q + 1 < qend;
+            const int q2 = two ? q + 1 : q;  // (a repeated, in-bounds load when there is no second)
+            const double ax = sx[q], ay = sy[q], az = sz[q];
+            const double bx = sx[q2], by = sy[q2], bz = sz[q2];
+            double dx, dy, dz, ex, ey, ez;
             if (shifted) {
-                dx = (sx[q] - xi) - shx;
-                dy = (sy[q] - yi) - shy;
-                dz = (sz[q] - zi) - shz;
+                dx = (ax - xi) - shx;
+                dy = (ay - yi) - shy;
+                dz = (az - zi) - shz;
+                ex = (bx - xi) - shx;
+                ey = (by - yi) - shy;
+                ez = (bz - zi) - shz;
             } else {
-                dx = min_image(sx[q] - xi, g, 0);
-                dy = min_image(sy[q] - yi, g, 1);
-                dz = min_image(sz[q] - zi, g, 2);
+                dx = min_image(ax - xi, g, 0);
+                dy = min_image(ay - yi, g, 1);
+                dz = min_image(az - zi, g, 2);
+                ex = min_image(bx - xi, g, 0);
+                ey = min_image(by - yi, g, 1);
+                ez = min_image(bz - zi, g, 2);
             }
-            double xx = dx * dx, yy = dy * dy, zz = dz * dz;
-            double d2 = (xx + yy) + zz;
+            const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            const double d2 = (xx + yy) + zz;
+            const double xx2 = ex * ex, yy2 = ey * ey, zz2 = ez * ez;
+            const double e2 = (xx2 + yy2) + zz2;
             if (q != (int)p) t = pack_key(d2, q);
-            q++;
+            if (two && q2 != (int)p) t2 = pack_key(e2, q2);
+            q += two ? 2 : 1;
         }
 #pragma unroll
         for (int m = 0; m < KN; m++) minmax_step(key[m], t);
+#pragma unroll
+        for (int m = 0; m < KN; m++) minmax_step(key[m], t2);
     } while (more);
     bool ok = key[NK - 1] != INF;
 #pragma unroll
