@@ -1112,10 +1112,33 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
     int nvis = 0;
     R pp[3];
     L.load(p, pp);
-    for (int f = 0; f < nf; f++) {
-        uint32_t w = S.F[f][t];
-        if (lane_orient<R>(L, fv(w, 0), fv(w, 1), fv(w, 2), pp, p) > 0) {
+    // two facets per step (nf is even): both filters' loads are issued
+    // together; the rare undecided test falls back to the exact path
+    for (int f = 0; f < nf; f += 2) {
+        const uint32_t w0 = S.F[f][t], w1 = S.F[f + 1][t];
+        R a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
+        L.load(fv(w0, 0), a0);
+        L.load(fv(w0, 1), b0);
+        L.load(fv(w0, 2), c0);
+        L.load(fv(w1, 0), a1);
+        L.load(fv(w1, 1), b1);
+        L.load(fv(w1, 2), c1);
+        int s0, s1;
+        if constexpr (sizeof(R) == 4) {
+            s0 = orient_filter_f32in(a0, b0, c0, pp, L.bo);
+            s1 = orient_filter_f32in(a1, b1, c1, pp, L.bo);
+        } else {
+            s0 = orient_filter64b(a0, b0, c0, pp, L.bo);
+            s1 = orient_filter64b(a1, b1, c1, pp, L.bo);
+        }
+        if (!s0) s0 = lane_orient_pts<R>(L, fv(w0, 0), fv(w0, 1), fv(w0, 2), a0, b0, c0, pp, p);
+        if (!s1) s1 = lane_orient_pts<R>(L, fv(w1, 0), fv(w1, 1), fv(w1, 2), a1, b1, c1, pp, p);
+        if (s0 > 0) {
             vis |= 1u << f;
+            nvis++;
+        }
+        if (s1 > 0) {
+            vis |= 2u << f;
             nvis++;
         }
     }
