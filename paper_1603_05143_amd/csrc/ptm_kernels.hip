@@ -730,10 +730,28 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
     float pp[3];
     L.load(p, pp);
     uint32_t vis = 0;
-    for (uint32_t m = live; m; m &= m - 1) {
-        const int f = __builtin_ctz(m);
-        const uint32_t w = S.F[f][t];
-        if (L.orient(vv(w, 0), vv(w, 1), vv(w, 2), pp, p) > 0) vis |= 1u << f;
+    // two facets per step: both filters' loads are issued together; the
+    // rare undecided test falls back to the exact path
+    for (uint32_t m = live; m;) {
+        const int f0 = __builtin_ctz(m);
+        m &= m - 1;
+        const bool two = m != 0;
+        const int f1 = two ? __builtin_ctz(m) : f0;
+        if (two) m &= m - 1;
+        const uint32_t w0 = S.F[f0][t], w1 = S.F[f1][t];
+        float a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
+        L.load(vv(w0, 0), a0);
+        L.load(vv(w0, 1), b0);
+        L.load(vv(w0, 2), c0);
+        L.load(vv(w1, 0), a1);
+        L.load(vv(w1, 1), b1);
+        L.load(vv(w1, 2), c1);
+        int s0 = orient_filter_f32in(a0, b0, c0, pp, L.bo);
+        int s1 = orient_filter_f32in(a1, b1, c1, pp, L.bo);
+        if (!s0) s0 = L.orient(vv(w0, 0), vv(w0, 1), vv(w0, 2), pp, p);
+        if (two && !s1) s1 = L.orient(vv(w1, 0), vv(w1, 1), vv(w1, 2), pp, p);
+        if (s0 > 0) vis |= 1u << f0;
+        if (two && s1 > 0) vis |= 1u << f1;
     }
     if (!vis) return true;
     // horizon edges (a -> b) of visible facets whose neighbour g is not visible
