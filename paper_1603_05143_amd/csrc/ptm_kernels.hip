@@ -1227,9 +1227,27 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
 // det[a; b; c] > 0 exactly
 template <typename R>
 __device__ inline int lane_centre_inside(const Lane<R> &L, int K) {
-    for (int f = 0; f < 2 * K - 4; f++) {
-        uint32_t w = L.S.F[f][L.t];
-        if (lane_det3<R>(L, fv(w, 0), fv(w, 1), fv(w, 2)) <= 0) return 0;
+    // two facets per step (2K - 4 is even), as in the insertion
+    for (int f = 0; f < 2 * K - 4; f += 2) {
+        const uint32_t w0 = L.S.F[f][L.t], w1 = L.S.F[f + 1][L.t];
+        R a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
+        L.load(fv(w0, 0), a0);
+        L.load(fv(w0, 1), b0);
+        L.load(fv(w0, 2), c0);
+        L.load(fv(w1, 0), a1);
+        L.load(fv(w1, 1), b1);
+        L.load(fv(w1, 2), c1);
+        int s0, s1;
+        if constexpr (sizeof(R) == 4) {
+            s0 = det3_filter_f32in(a0, b0, c0, L.bd);
+            s1 = det3_filter_f32in(a1, b1, c1, L.bd);
+        } else {
+            s0 = det3_filter64b(a0, b0, c0, L.bd);
+            s1 = det3_filter64b(a1, b1, c1, L.bd);
+        }
+        if (s0 < 0 || s1 < 0) return 0;
+        if (!s0 && lane_det3<R>(L, fv(w0, 0), fv(w0, 1), fv(w0, 2)) <= 0) return 0;
+        if (!s1 && lane_det3<R>(L, fv(w1, 0), fv(w1, 1), fv(w1, 2)) <= 0) return 0;
     }
     return 1;
 }
