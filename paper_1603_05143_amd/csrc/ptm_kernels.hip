@@ -1959,7 +1959,7 @@ __global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, cons
 
 // One superposition per lane over the flat pair list (grid-stride).
 template <typename RT>
-__global__ void __launch_bounds__(MB) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
+__global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
                                                   const uint64_t *__restrict__ ords, const int64_t *__restrict__ off,
                                                   int64_t cap, const uint2 *__restrict__ pairs,
                                                   double *__restrict__ rout, RT *__restrict__ qsout) {
