@@ -2044,8 +2044,9 @@ __device__ inline void pair_minimum(int64_t q0, int64_t q1, int64_t cap, const u
 // the working precision; every other atom (a near tie, an FP32 margin too
 // small to trust, pairs that did not fit the buffer) is appended to todo for
 // k_decide_full, so that this kernel stays small enough for full occupancy.
+// Registers are held to four waves per SIMD.
 template <typename RT>
-__global__ void __launch_bounds__(MB) k_decide(int64_t n, const double *__restrict__ nbr_rel,
+__global__ void __launch_bounds__(MB, 4) k_decide(int64_t n, const double *__restrict__ nbr_rel,
                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
                                                const int8_t *__restrict__ species, TablesView T,
                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
