@@ -1133,13 +1133,19 @@ static void voronoi_areas(int k, const double (*d)[3], double *area) {
  * to 1/d, i.e. to the Euclidean rank, which also orders exactly equal
  * distances by index).  When the cell is unbounded (the origin not strictly
  * inside the hull of the neighbours) the Euclidean order is kept: no hull of
- * any subset can then hold the centre.  *tmargin receives the distance of
+ * any subset can then hold the centre; so it is when two neighbours
+ * coincide.  *tmargin receives the distance of
  * the closest grid value >= 0.5 to an integer (how far the order is from a
  * different rounding), +inf when the order is Euclidean. */
 static void topological_order(int32_t *ids, double (*rel)[3], double *area_out, double *tmargin) {
     const int k = TOPO_K;
     *tmargin = INFINITY;
     for (int j = 0; j < k; j++) area_out[j] = -1.0;
+    /* Reading: two coincident neighbours share one bisector plane, so no
+     * interface belongs to either alone; the Euclidean order is kept. */
+    for (int j = 0; j < k; j++)
+        for (int m = j + 1; m < k; m++)
+            if (rel[j][0] == rel[m][0] && rel[j][1] == rel[m][1] && rel[j][2] == rel[m][2]) return;
     if (!origin_strictly_inside(k, (const double(*)[3])rel)) return;
     double A[TOPO_K], tot = 0;
     voronoi_areas(k, (const double(*)[3])rel, A);

@@ -122,3 +122,18 @@ def test_hot_crystal_more_fcc_topological(oracle_lib):
     n_e, n_t = int(np.sum(e["type"] == 2)), int(np.sum(t["type"] == 2))
     assert n_t > n_e * 1.03, (n_e, n_t)
     assert np.all(np.isfinite(t["tmargin"]) | (t["type"] == 0))
+
+
+def test_coincident_neighbours_keep_euclidean_order(oracle_lib):
+    """Two coincident neighbours share one bisector plane: the reading keeps
+    the Euclidean order (and reports no area grid margin)."""
+    rng = np.random.default_rng(4)
+    rel = _shell(oracle_lib, "bcc", 2.87) + rng.normal(scale=0.1, size=(18, 3))
+    rel[9] = rel[4]
+    rel = rel[np.argsort(np.einsum("ij,ij->i", rel, rel), kind="stable")]
+    ok, area, order, tm = oracle_lib.voronoi(rel)
+    assert not ok and order.tolist() == list(range(18)) and tm == math.inf
+    j = next(j for j in range(17) if np.array_equal(rel[j], rel[j + 1]))
+    rel[j + 1] = rel[j + 1] * (1 + 1e-9)  # no longer coincident: ordered by area
+    ok, area, order, tm = oracle_lib.voronoi(rel)
+    assert ok
