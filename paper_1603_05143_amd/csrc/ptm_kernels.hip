@@ -840,6 +840,17 @@ __global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__
             m = fmaxf(m, fabsf(xf));
         }
     }
+    // two coincident neighbours share one bisector plane: no interface
+    // belongs to either alone, and the atom keeps its Euclidean order (equal
+    // FP32 copies first, then the FP64 vectors)
+    for (int j = 0; j < VK - 1 && topo; j++)
+        for (int k = j + 1; k < VK && topo; k++)
+            if (S.P[0][j][t] == S.P[0][k][t] && S.P[1][j][t] == S.P[1][k][t] && S.P[2][j][t] == S.P[2][k][t]) {
+                bool same = true;
+                for (int d = 0; d < 3; d++)
+                    same = same && rel18[((int64_t)j * 3 + d) * n + p] == rel18[((int64_t)k * 3 + d) * n + p];
+                topo = !same;
+            }
     uint32_t live = 0;
     if (topo) {
         double m64 = 0;

@@ -1,0 +1,97 @@
+"""Seeded randomised frames through the whole GPU pipeline against the FP64
+oracle, both precision forms and both neighbour orderings: uniform gases
+(sparse surroundings, the wave-per-atom k-NN), liquid-like dense packings,
+rotated and strained crystals with vacancies, vacuum gaps, open and mixed
+periodic boxes, tiny periodic boxes, clusters, coincident atoms and
+species.  Decisions bit-exact, reals within the form's tolerance; for the
+topological ordering, atoms whose interface areas lie within 1e-6 of a
+grid boundary in the oracle (tmargin) are only checked for validity."""
+import numpy as np
+import pytest
+
+from paper_1603_05143_amd import ptm, synthetic as S
+from parity_util import TOL32, TOL64, compare
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn")
+
+
+def _frame(seed):
+    """(positions, box, species, label) of fuzz case `seed`."""
+    rng = np.random.default_rng(1000 + seed)
+    kind = seed % 8
+    if kind == 0:  # uniform gas in a periodic box
+        n = int(rng.integers(200, 1500))
+        box = rng.uniform(15, 30, 3)
+        pos = rng.uniform(0, 1, (n, 3)) * box
+    elif kind == 1:  # dense random packing, open boundaries
+        n = int(rng.integers(300, 1200))
+        pos = rng.normal(size=(n, 3)) * (n ** (1 / 3)) * 0.9
+        box = np.zeros(3)
+    elif kind == 2:  # rotated, strained crystal with vacancies, periodic along z only
+        k = ["fcc", "bcc", "hcp", "sc"][int(rng.integers(0, 4))]
+        f = S.perfect_crystal(k, reps=(4, 3, 3) if k == "hcp" else (4, 4, 4),
+                              a={"fcc": 3.615, "bcc": 2.87, "hcp": 2.51, "sc": 2.6}[k])
+        keep = rng.random(f.n) > 0.03
+        R = S.random_rotations(rng, 1)[0]
+        F = np.eye(3) + rng.normal(scale=0.02, size=(3, 3))
+        pos = (f.positions[keep] - f.box / 2) @ (F @ R).T + rng.normal(scale=0.05, size=(int(keep.sum()), 3))
+        box = np.zeros(3)
+    elif kind == 3:  # tiny periodic box (fewer than five cells per axis)
+        k = ["fcc", "bcc"][int(rng.integers(0, 2))]
+        f = S.perfect_crystal(k, reps=(2, 2, 3), a=3.615 if k == "fcc" else 2.87)
+        pos = f.positions + rng.normal(scale=0.08, size=f.positions.shape)
+        box = f.box
+    elif kind == 4:  # slab with a vacuum gap, periodic in x, y
+        f = S.perfect_crystal("fcc", reps=(5, 5, 5), a=3.615)
+        pos = f.positions[f.positions[:, 2] < 10.0] + rng.normal(scale=0.1, size=(1, 3))
+        box = np.array([f.box[0], f.box[1], 0.0])
+        pos = pos + rng.normal(scale=0.06, size=pos.shape)
+    elif kind == 5:  # Mackay cluster with noise
+        pos = S.mackay_icosahedron(int(rng.integers(2, 4))) + rng.normal(scale=0.05, size=(1, 3))
+        pos = pos + rng.normal(scale=0.03, size=pos.shape)
+        box = np.zeros(3)
+    elif kind == 6:  # coincident atoms inside a crystal
+        f = S.perfect_crystal("bcc", reps=(4, 4, 4), a=2.87)
+        pos = f.positions + rng.normal(scale=0.05, size=f.positions.shape)
+        dup = rng.choice(f.n, 3, replace=False)
+        pos = np.vstack([pos, pos[dup]])
+        box = f.box
+    else:  # alloy frame of the serving mix
+        fr = S.serving_frame(int(rng.integers(800, 4000)), seed=seed)
+        return fr.positions, fr.box, fr.species, "serving"
+    species = rng.integers(0, 2, len(pos)).astype(np.int8) if seed % 3 == 0 else None
+    return np.ascontiguousarray(pos, dtype=np.float64), np.asarray(box, dtype=np.float64), species, f"kind{kind}"
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.mark.parametrize("topological", [False, True], ids=["euclidean", "topological"])
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_fuzz(torch_cuda, oracle_lib, precision, topological):
+    torch = torch_cuda
+    tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
+    c = ptm.Classifier(device=0, precision=precision, topological=topological)
+    try:
+        for seed in range(24):
+            pos, box, species, label = _frame(seed)
+            print(f"[fuzz] seed={seed} {label} n={len(pos)} box={box.tolist()} topo={topological}", flush=True)
+            dpos = torch.from_numpy(pos).to("cuda:0")
+            sp = None if species is None else torch.from_numpy(species).to("cuda:0")
+            out = c.classify(dpos, box, species=sp, knn=True)
+            torch.cuda.synchronize()
+            got = {k: out[k].cpu().numpy() for k in FIELDS}
+            ref = oracle_lib.classify(pos, box, species=species,
+                                      ordering="topological" if topological else "euclidean")
+            sure = ~(ref["tmargin"] < 1e-6)
+            assert np.sum(~sure) <= 2, (seed, np.sum(~sure))
+            compare({k: v[sure] for k, v in got.items()}, {k: ref[k][sure] for k in FIELDS}, tol=tol,
+                    check_alloy=species is not None, label=f"seed {seed} {label} ")
+    finally:
+        c.close()
