@@ -50,8 +50,10 @@ typedef enum {
 #define PTM_MAX_ATOMS 2147483646LL /* atom ids are int32 */
 
 typedef enum {
-    PTM_FP64 = 0,      /* every floating-point step in FP64 */
-    PTM_FP32_MIXED = 1 /* FP32 where an error bound proves the decision; FP64 otherwise */
+    PTM_FP64 = 0,      /* superposition, orientation and strain in FP64; the exact steps (neighbour
+                          order, hull predicates, codes) are the same in both forms                */
+    PTM_FP32_MIXED = 1 /* superposition etc. in FP32 where an error bound proves the decision; FP64
+                          otherwise                                                                  */
 } ptm_precision;
 
 /* template_mask bits (Table 1 templates) */
