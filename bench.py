@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
 
 # kernel(s) behind each single-kernel stage, for the roofline line
-STAGE_KERNEL = {"knn": "k_knn_fast<14> + k_knn_exact<14>", "topo": "k_topo<float>", "eval": "k_cand_eval<float>",
+STAGE_KERNEL = {"knn": "k_knn_fast<14> + k_knn_exact<14>", "topo": "k_topo", "eval": "k_cand_eval<float>",
                 "decide": "k_decide<float> + k_decide_full<float>"}
 
 
@@ -101,7 +101,7 @@ def measured_traffic(stage: str, precision: str):
     digest = kernel_source_digest()
     for line in open(path):
         cols = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cols) >= 6 and cols[0] == stage and cols[1] == precision and cols[5] == digest:
+        if len(cols) >= 6 and cols[0] == stage and cols[1] in (precision, "both") and cols[5] == digest:
             try:
                 return float(cols[2]) + float(cols[3])
             except ValueError:

@@ -1009,15 +1009,15 @@ __global__ void __launch_bounds__(VB) k_voronoi_order(int64_t n, const double *_
 // so dynamic indices never conflict across lanes.
 constexpr int TB = 64;  // threads per block of the topology kernel
 
-// LDS of one block.  P: neighbour vectors (FP64 or FP32); F: facets; H: the
-// horizon of the current insertion, which shares its space with the
-// rotation system of a finished 6- or 12-point hull (built between
-// insertions).  The 14-point hull is the last: its rotation system takes the
-// space of P, which is no longer read.  FP32 form: 23,040 bytes, seven
-// blocks per CU.
-template <typename R>
+// LDS of one block.  P: the neighbour vectors rounded to FP32 (the input of
+// the predicate filters; every predicate is decided exactly, so both
+// precision forms use this kernel); F: facets; H: the horizon of the
+// current insertion, which shares its space with the rotation system of a
+// finished 6- or 12-point hull (built between insertions).  The 14-point
+// hull is the last: its rotation system takes the space of P, which is no
+// longer read.  23,040 bytes: seven blocks per CU.
 struct TopoShared {
-    R P[3][KMAX][TB];
+    float P[3][KMAX][TB];
     uint32_t F[2 * KMAX - 4][TB];
     union {
         uint32_t H[KMAX][TB];
@@ -1051,78 +1051,65 @@ __device__ inline uint32_t fset_nb(uint32_t f, int e, int g) {
 // Per-lane view of the hull inputs: LDS points plus the FP64 originals in
 // global memory (used when an FP32 filter cannot decide), and the static
 // filter bounds of the atom (from its largest neighbour coordinate).
-template <typename R>
 struct Lane {
-    TopoShared<R> &S;
+    TopoShared &S;
     int t;
     const double *__restrict__ rel;
     int64_t n, p;
-    double bo, bd;        // filter bounds of orient and det3 in the working form
-    double bo64, bd64;    // FP64 filter bounds (FP32 form's fallback)
+    double bo, bd;        // FP32 filter bounds of orient and det3
+    double bo64, bd64;    // FP64 filter bounds (the fallback)
     __device__ void load64(int r, double (&x)[3]) const {
         for (int d = 0; d < 3; d++) x[d] = rel[((int64_t)r * 3 + d) * n + p];
     }
-    __device__ void load(int r, R (&x)[3]) const {
+    __device__ void load(int r, float (&x)[3]) const {
         for (int d = 0; d < 3; d++) x[d] = S.P[d][r][t];
     }
 };
 
 // orientation of facet (a,b,c), its points given, against point q
-template <typename R>
-__device__ inline int lane_orient_pts(const Lane<R> &L, int a, int b, int c, const R (&pa)[3], const R (&pb)[3],
-                                      const R (&pc)[3], const R (&pq)[3], int q) {
-    if constexpr (sizeof(R) == 8) {
-        return orient_sos64b(pa, pb, pc, pq, a, b, c, q, L.bo);
-    } else {
-        int s = orient_filter_f32in(pa, pb, pc, pq, L.bo);
-        if (s) return s;
-        double da[3], db[3], dc[3], dq[3];
-        L.load64(a, da);
-        L.load64(b, db);
-        L.load64(c, dc);
-        L.load64(q, dq);
-        return orient_sos64b(da, db, dc, dq, a, b, c, q, L.bo64);
-    }
+__device__ inline int lane_orient_pts(const Lane &L, int a, int b, int c, const float (&pa)[3], const float (&pb)[3],
+                                      const float (&pc)[3], const float (&pq)[3], int q) {
+    int s = orient_filter_f32in(pa, pb, pc, pq, L.bo);
+    if (s) return s;
+    double da[3], db[3], dc[3], dq[3];
+    L.load64(a, da);
+    L.load64(b, db);
+    L.load64(c, dc);
+    L.load64(q, dq);
+    return orient_sos64b(da, db, dc, dq, a, b, c, q, L.bo64);
 }
 
 // orientation of facet (a,b,c) against point q (held in registers)
-template <typename R>
-__device__ inline int lane_orient(const Lane<R> &L, int a, int b, int c, const R (&pq)[3], int q) {
-    R pa[3], pb[3], pc[3];
+__device__ inline int lane_orient(const Lane &L, int a, int b, int c, const float (&pq)[3], int q) {
+    float pa[3], pb[3], pc[3];
     L.load(a, pa);
     L.load(b, pb);
     L.load(c, pc);
-    return lane_orient_pts<R>(L, a, b, c, pa, pb, pc, pq, q);
+    return lane_orient_pts(L, a, b, c, pa, pb, pc, pq, q);
 }
 
-template <typename R>
-__device__ inline int lane_det3(const Lane<R> &L, int a, int b, int c) {
-    R pa[3], pb[3], pc[3];
+__device__ inline int lane_det3(const Lane &L, int a, int b, int c) {
+    float pa[3], pb[3], pc[3];
     L.load(a, pa);
     L.load(b, pb);
     L.load(c, pc);
-    if constexpr (sizeof(R) == 8) {
-        return det3_sign64b(pa, pb, pc, L.bd);
-    } else {
-        int s = det3_filter_f32in(pa, pb, pc, L.bd);
-        if (s) return s;
-        double da[3], db[3], dc[3];
-        L.load64(a, da);
-        L.load64(b, db);
-        L.load64(c, dc);
-        return det3_sign64b(da, db, dc, L.bd64);
-    }
+    int s = det3_filter_f32in(pa, pb, pc, L.bd);
+    if (s) return s;
+    double da[3], db[3], dc[3];
+    L.load64(a, da);
+    L.load64(b, db);
+    L.load64(c, dc);
+    return det3_sign64b(da, db, dc, L.bd64);
 }
 
 // first tetrahedron of points 0..3, positively oriented; facets 0..3
-template <typename R>
-__device__ inline void lane_hull_start(const Lane<R> &L) {
-    TopoShared<R> &S = L.S;
+__device__ inline void lane_hull_start(const Lane &L) {
+    TopoShared &S = L.S;
     const int t = L.t;
     int a = 0, b = 1, c = 2, d = 3;
-    R p3[3];
+    float p3[3];
     L.load(3, p3);
-    if (lane_orient<R>(L, 0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
+    if (lane_orient(L, 0, 1, 2, p3, 3) > 0) { b = 2; c = 1; }
     S.F[0][t] = fpack(a, b, c, 1, 2, 3);
     S.F[1][t] = fpack(b, a, d, 0, 3, 2);
     S.F[2][t] = fpack(c, b, d, 0, 1, 3);
@@ -1132,36 +1119,29 @@ __device__ inline void lane_hull_start(const Lane<R> &L) {
 // Insert point p into the hull of points 0..p-1 (nf = 2p - 4 facets).
 // Returns 0 if p lies inside (it never becomes a vertex) or swallows an
 // earlier vertex: then no hull of p or more points is valid.
-template <typename R>
-__device__ int lane_insert(const Lane<R> &L, int p) {
-    TopoShared<R> &S = L.S;
+__device__ int lane_insert(const Lane &L, int p) {
+    TopoShared &S = L.S;
     const int t = L.t;
     const int nf = 2 * p - 4;
     uint32_t vis = 0;
     int nvis = 0;
-    R pp[3];
+    float pp[3];
     L.load(p, pp);
     // two facets per step (nf is even): both filters' loads are issued
     // together; the rare undecided test falls back to the exact path
     for (int f = 0; f < nf; f += 2) {
         const uint32_t w0 = S.F[f][t], w1 = S.F[f + 1][t];
-        R a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
+        float a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
         L.load(fv(w0, 0), a0);
         L.load(fv(w0, 1), b0);
         L.load(fv(w0, 2), c0);
         L.load(fv(w1, 0), a1);
         L.load(fv(w1, 1), b1);
         L.load(fv(w1, 2), c1);
-        int s0, s1;
-        if constexpr (sizeof(R) == 4) {
-            s0 = orient_filter_f32in(a0, b0, c0, pp, L.bo);
-            s1 = orient_filter_f32in(a1, b1, c1, pp, L.bo);
-        } else {
-            s0 = orient_filter64b(a0, b0, c0, pp, L.bo);
-            s1 = orient_filter64b(a1, b1, c1, pp, L.bo);
-        }
-        if (!s0) s0 = lane_orient_pts<R>(L, fv(w0, 0), fv(w0, 1), fv(w0, 2), a0, b0, c0, pp, p);
-        if (!s1) s1 = lane_orient_pts<R>(L, fv(w1, 0), fv(w1, 1), fv(w1, 2), a1, b1, c1, pp, p);
+        int s0 = orient_filter_f32in(a0, b0, c0, pp, L.bo);
+        int s1 = orient_filter_f32in(a1, b1, c1, pp, L.bo);
+        if (!s0) s0 = lane_orient_pts(L, fv(w0, 0), fv(w0, 1), fv(w0, 2), a0, b0, c0, pp, p);
+        if (!s1) s1 = lane_orient_pts(L, fv(w1, 0), fv(w1, 1), fv(w1, 2), a1, b1, c1, pp, p);
         if (s0 > 0) {
             vis |= 1u << f;
             nvis++;
@@ -1236,29 +1216,22 @@ __device__ int lane_insert(const Lane<R> &L, int p) {
 
 // the centre lies strictly inside every facet of the K-point hull:
 // det[a; b; c] > 0 exactly
-template <typename R>
-__device__ inline int lane_centre_inside(const Lane<R> &L, int K) {
+__device__ inline int lane_centre_inside(const Lane &L, int K) {
     // two facets per step (2K - 4 is even), as in the insertion
     for (int f = 0; f < 2 * K - 4; f += 2) {
         const uint32_t w0 = L.S.F[f][L.t], w1 = L.S.F[f + 1][L.t];
-        R a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
+        float a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
         L.load(fv(w0, 0), a0);
         L.load(fv(w0, 1), b0);
         L.load(fv(w0, 2), c0);
         L.load(fv(w1, 0), a1);
         L.load(fv(w1, 1), b1);
         L.load(fv(w1, 2), c1);
-        int s0, s1;
-        if constexpr (sizeof(R) == 4) {
-            s0 = det3_filter_f32in(a0, b0, c0, L.bd);
-            s1 = det3_filter_f32in(a1, b1, c1, L.bd);
-        } else {
-            s0 = det3_filter64b(a0, b0, c0, L.bd);
-            s1 = det3_filter64b(a1, b1, c1, L.bd);
-        }
+        const int s0 = det3_filter_f32in(a0, b0, c0, L.bd);
+        const int s1 = det3_filter_f32in(a1, b1, c1, L.bd);
         if (s0 < 0 || s1 < 0) return 0;
-        if (!s0 && lane_det3<R>(L, fv(w0, 0), fv(w0, 1), fv(w0, 2)) <= 0) return 0;
-        if (!s1 && lane_det3<R>(L, fv(w1, 0), fv(w1, 1), fv(w1, 2)) <= 0) return 0;
+        if (!s0 && lane_det3(L, fv(w0, 0), fv(w0, 1), fv(w0, 2)) <= 0) return 0;
+        if (!s1 && lane_det3(L, fv(w1, 0), fv(w1, 1), fv(w1, 2)) <= 0) return 0;
     }
     return 1;
 }
@@ -1391,11 +1364,10 @@ __device__ int32_t lane_lookup(const uint32_t (*F)[TB], const RotSys &NT, const 
 // enabled by need: bit g for hull group g), code ids and labellings into
 // code_out / ord_out [group][n] (-1 / 0 for a group without a valid hull or
 // not needed).
-template <typename R>
 __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
                                               const int32_t *__restrict__ nbr_id, TablesView T, uint32_t need,
                                               int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
-    __shared__ TopoShared<R> S;
+    __shared__ TopoShared S;
     const int t = threadIdx.x;
     const int64_t p = blockIdx.x * (int64_t)TB + t;
     if (p >= n) return;
@@ -1412,30 +1384,24 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
         for (int r = 0; r < kl; r++)
             for (int d = 0; d < 3; d++) {
                 double x = nbr_rel[((int64_t)r * 3 + d) * n + p];
-                S.P[d][r][t] = (R)x;
+                S.P[d][r][t] = (float)x;
                 m64 = fmax(m64, fabs(x));
                 m32 = fmaxf(m32, fabsf((float)x));
             }
-        Lane<R> L{S, t, nbr_rel, n, p, 0, 0, f64_orient_bound(m64), f64_det3_bound(m64)};
-        if constexpr (sizeof(R) == 8) {
-            L.bo = L.bo64;
-            L.bd = L.bd64;
-        } else {
-            L.bo = f32_orient_bound(m32);
-            L.bd = f32_det3_bound(m32);
-        }
-        lane_hull_start<R>(L);
+        Lane L{S, t, nbr_rel, n, p, f32_orient_bound(m32), f32_det3_bound(m32), f64_orient_bound(m64),
+               f64_det3_bound(m64)};
+        lane_hull_start(L);
         const RotSys nt{S.NT, t};
         const RotSys nt14{reinterpret_cast<uint64_t (*)[TB]>(&S.P[0][0][0]), t};
         for (int q = 4; q < kl; q++) {
-            if (!lane_insert<R>(L, q)) break;
+            if (!lane_insert(L, q)) break;
             const int K = q + 1;
             if (K == 6 && (want & 1)) {
-                if (lane_centre_inside<R>(L, 6)) cid[0] = lane_lookup<6>(S.F, nt, T, ordw[0]);
+                if (lane_centre_inside(L, 6)) cid[0] = lane_lookup<6>(S.F, nt, T, ordw[0]);
             } else if (K == 12 && (want & 2)) {
-                if (lane_centre_inside<R>(L, 12)) cid[1] = lane_lookup<12>(S.F, nt, T, ordw[1]);
+                if (lane_centre_inside(L, 12)) cid[1] = lane_lookup<12>(S.F, nt, T, ordw[1]);
             } else if (K == 14) {
-                if (lane_centre_inside<R>(L, 14)) cid[2] = lane_lookup<14>(S.F, nt14, T, ordw[2]);
+                if (lane_centre_inside(L, 14)) cid[2] = lane_lookup<14>(S.F, nt14, T, ordw[2]);
             }
         }
     }
@@ -2421,7 +2387,7 @@ void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_
 void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
                  int32_t *code, uint64_t *ord, hipStream_t st) {
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
-    hipLaunchKernelGGL(k_topo<float>, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
+    hipLaunchKernelGGL(k_topo, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
 }
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
                  hipStream_t st) {
