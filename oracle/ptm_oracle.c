@@ -1133,19 +1133,22 @@ static void voronoi_areas(int k, const double (*d)[3], double *area) {
  * to 1/d, i.e. to the Euclidean rank, which also orders exactly equal
  * distances by index).  When the cell is unbounded (the origin not strictly
  * inside the hull of the neighbours) the Euclidean order is kept: no hull of
- * any subset can then hold the centre; so it is when two neighbours
- * coincide.  *tmargin receives the distance of
+ * any subset can then hold the centre; so it is when two of the points
+ * (neighbours or centre) coincide.  *tmargin receives the distance of
  * the closest grid value >= 0.5 to an integer (how far the order is from a
  * different rounding), +inf when the order is Euclidean. */
 static void topological_order(int32_t *ids, double (*rel)[3], double *area_out, double *tmargin) {
     const int k = TOPO_K;
     *tmargin = INFINITY;
     for (int j = 0; j < k; j++) area_out[j] = -1.0;
-    /* Reading: two coincident neighbours share one bisector plane, so no
-     * interface belongs to either alone; the Euclidean order is kept. */
-    for (int j = 0; j < k; j++)
+    /* Reading: when two of the 19 points coincide (two neighbours, or a
+     * neighbour and the centre) the Voronoi cell has no well-defined face for
+     * them (one shared bisector plane, or none); the Euclidean order is kept. */
+    for (int j = 0; j < k; j++) {
+        if (rel[j][0] == 0.0 && rel[j][1] == 0.0 && rel[j][2] == 0.0) return;
         for (int m = j + 1; m < k; m++)
             if (rel[j][0] == rel[m][0] && rel[j][1] == rel[m][1] && rel[j][2] == rel[m][2]) return;
+    }
     if (!origin_strictly_inside(k, (const double(*)[3])rel)) return;
     double A[TOPO_K], tot = 0;
     voronoi_areas(k, (const double(*)[3])rel, A);

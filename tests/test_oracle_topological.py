@@ -137,3 +137,13 @@ def test_coincident_neighbours_keep_euclidean_order(oracle_lib):
     rel[j + 1] = rel[j + 1] * (1 + 1e-9)  # no longer coincident: ordered by area
     ok, area, order, tm = oracle_lib.voronoi(rel)
     assert ok
+
+
+def test_neighbour_at_the_centre_keeps_euclidean_order(oracle_lib):
+    """A neighbour coinciding with the centre has no bisector plane: the
+    Euclidean order is kept."""
+    rng = np.random.default_rng(6)
+    rel = _shell(oracle_lib, "bcc", 2.87)[:17] + rng.normal(scale=0.1, size=(17, 3))
+    rel = np.vstack([np.zeros(3), rel[np.argsort(np.einsum("ij,ij->i", rel, rel))]])
+    ok, area, order, tm = oracle_lib.voronoi(rel)
+    assert not ok and order.tolist() == list(range(18)) and tm == math.inf
