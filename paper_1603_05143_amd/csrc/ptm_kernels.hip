@@ -833,6 +833,8 @@ __global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__
     for (int v = 0; v < VK; v++) {
         double x[3];
         dual_point(rel18, n, p, v, x);
+        // a neighbour at the centre has no bisector plane (its point is not
+        // finite): the atom keeps its Euclidean order
         topo = topo && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
         for (int d = 0; d < 3; d++) {
             const float xf = (float)x[d];
