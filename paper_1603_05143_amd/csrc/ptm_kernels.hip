@@ -830,29 +830,40 @@ __global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__
     if (p >= n) return;
     bool topo = id18[(int64_t)(VK - 1) * n + p] >= 0;
     float m = 0;
+    uint32_t hk[VK];  // a mix of each point's FP32 bits: equal points have equal keys
+#pragma unroll
     for (int v = 0; v < VK; v++) {
         double x[3];
         dual_point(rel18, n, p, v, x);
         // a neighbour at the centre has no bisector plane (its point is not
         // finite): the atom keeps its Euclidean order
         topo = topo && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
+        uint32_t h = 0;
         for (int d = 0; d < 3; d++) {
             const float xf = (float)x[d];
             S.P[d][v][t] = xf;
             m = fmaxf(m, fabsf(xf));
+            h = h * 0x9E3779B1u + __float_as_uint(xf);
         }
+        hk[v] = h;
     }
     // two coincident neighbours share one bisector plane: no interface
     // belongs to either alone, and the atom keeps its Euclidean order (equal
-    // FP32 copies first, then the FP64 vectors)
-    for (int j = 0; j < VK - 1 && topo; j++)
-        for (int k = j + 1; k < VK && topo; k++)
-            if (S.P[0][j][t] == S.P[0][k][t] && S.P[1][j][t] == S.P[1][k][t] && S.P[2][j][t] == S.P[2][k][t]) {
-                bool same = true;
-                for (int d = 0; d < 3; d++)
-                    same = same && rel18[((int64_t)j * 3 + d) * n + p] == rel18[((int64_t)k * 3 + d) * n + p];
-                topo = !same;
-            }
+    // keys first, then the FP32 copies, then the FP64 vectors)
+    bool maybe = false;
+#pragma unroll
+    for (int j = 0; j < VK - 1; j++)
+#pragma unroll
+        for (int k = j + 1; k < VK; k++) maybe = maybe || hk[j] == hk[k];
+    if (maybe && topo)
+        for (int j = 0; j < VK - 1 && topo; j++)
+            for (int k = j + 1; k < VK && topo; k++)
+                if (S.P[0][j][t] == S.P[0][k][t] && S.P[1][j][t] == S.P[1][k][t] && S.P[2][j][t] == S.P[2][k][t]) {
+                    bool same = true;
+                    for (int d = 0; d < 3; d++)
+                        same = same && rel18[((int64_t)j * 3 + d) * n + p] == rel18[((int64_t)k * 3 + d) * n + p];
+                    topo = !same;
+                }
     uint32_t live = 0;
     if (topo) {
         double m64 = 0;
