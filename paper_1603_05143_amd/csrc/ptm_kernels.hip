@@ -2367,8 +2367,9 @@ static void launch_knn_nk(int64_t n, const Grid &g, const double *sx, const doub
     if (knn_fast_applies(g)) {
         hipLaunchKernelGGL(k_knn_fast<NK>, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, sx, sy, sz, sid,
                            start, nbr_id, nbr_rel, knn_out, todo, todo_count);
-        // the atoms left over are few; 1024 blocks of four waves stride over them
-        hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>(blocks, 1024)), dim3(256), 0, st, n, g,
+        // the atoms left over are few; 512 blocks of four waves (two per SIMD,
+        // what its registers allow) stride over them
+        hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>(blocks, 512)), dim3(256), 0, st, n, g,
                            sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)todo,
                            (const int32_t *)todo_count);
     } else {
@@ -2425,7 +2426,10 @@ void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, cons
                    uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
                    int32_t *todo_count, bool f32, hipStream_t st) {
     dim3 gd((unsigned)((n + MB - 1) / MB));
-    dim3 gf((unsigned)std::min<int64_t>((n + MB / 64 - 1) / (MB / 64), 2048));
+    // the full rule holds one wave per SIMD (its registers): 256 blocks of
+    // four waves fill the chip, and a few left-over atoms do not pay for a
+    // larger launch
+    dim3 gf((unsigned)std::min<int64_t>((n + MB / 64 - 1) / (MB / 64), 256));
     if (f32) {
         hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
                            W.cap, W.pairs, W.r, (const float *)W.qs, cutoff, O, todo, todo_count);
