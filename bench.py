@@ -82,12 +82,17 @@ def work_model(stage: str, n: int, info: dict) -> tuple[str, float, str]:
 
 
 def kernel_source_digest() -> str:
-    """Digest of the kernel sources; HBM traffic measured on other sources is stale."""
+    """Digest of the kernel sources without their comments and blank lines;
+    HBM traffic measured on other code is stale."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("ptm_kernels.hip", "ptm_device.hpp", "ptm_kernels.hpp", "ptm_tables.hpp"):
-        with open(os.path.join(ROOT, "paper_1603_05143_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1603_05143_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

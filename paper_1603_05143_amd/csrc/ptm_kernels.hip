@@ -1,17 +1,24 @@
 // ptm_kernels.hip -- HIP kernels of the PTM classification pass for gfx950.
 //
 // Pipeline for one frame (Polyhedral Template Matching, arXiv:1603.05143):
-//   k_bounds      finite check + bounding box (open axes)
-//   k_bin_count   cell id + per-cell counter (counting sort, pass 1)
-//   (scan)        exclusive prefix sum of the counters
-//   k_bin_scatter sorted SoA copy of the positions (counting sort, pass 2)
-//   k_knn         14 nearest neighbours by (d^2, id), Sec. 3 Euclidean order
-//   k_topo<K>     hull of the innermost K = 6 / 12 / 14 neighbours with
-//                 exact predicates (Sec. 4; Alg. 1 requires the centre
-//                 strictly inside), start-edge code, template table lookup
-//   k_match       superposition over the candidates (eqs. 2-4), decision
-//                 (Alg. 1), representative, strain (eq. 6, Sec. 8), alloy
-//                 (Sec. 6, Table 3), write-back in input order
+//   k_bounds          finite check + bounding box (open axes)
+//   k_bin_count       cell id + per-cell counter (counting sort, pass 1)
+//   (scan)            exclusive prefix sum of the counters
+//   k_bin_scatter     sorted SoA copy of the positions (counting sort, pass 2)
+//   k_knn_fast/exact  14 (or 18) nearest neighbours by (d^2, id), Sec. 3
+//                     Euclidean order
+//   k_voronoi_hull/   optional topological order (Sec. 3): Voronoi interface
+//   k_voronoi_order   areas of the centre and its 18 nearest neighbours
+//   k_topo            hulls of the innermost 6 / 12 / 14 neighbours with exact
+//                     predicates (Sec. 4; Alg. 1 requires the centre strictly
+//                     inside), start-edge codes, template table lookups
+//   k_cand_count/fill candidate correspondences of every code (App. A)
+//   k_cand_eval       superposition of every candidate (eqs. 2-4)
+//   k_decide(_full)   decision (Alg. 1), representative, orientation, strain
+//                     (eq. 6, Sec. 8), alloy (Sec. 6, Table 3), derived outputs,
+//                     write-back in input order
+//   k_apply_cutoff, k_rmsd_histogram, k_misorientation: post-hoc utilities
+//                     (Sec. 5.1, Sec. 7)
 // One lane owns one atom in every per-atom kernel; atoms are processed in
 // cell order so the lanes of a wave read the same cells.
 #include <hip/hip_runtime.h>
