@@ -1338,12 +1338,11 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
     return ord;
 }
 
-// Rotation system, canonical code and table lookup of the K-point hull now
-// held in F; returns the code id (-1: no template triangulation has this
-// code) and the labelling in ordw.
+// Rotation system and canonical code of the K-point hull now held in F: the
+// K code words into best, the labelling into ordw; returns the code's hash
+// (the table probe comes after the last insertion).
 template <int K>
-__device__ int32_t lane_lookup(const uint32_t (*F)[TB], const RotSys &NT, const TablesView &T, uint64_t &ordw) {
-    constexpr int grp = (K == 6) ? 0 : (K == 12 ? 1 : 2);
+__device__ uint64_t lane_code(const uint32_t (*F)[TB], const RotSys &NT, uint64_t (&best)[K], uint64_t &ordw) {
     const int t = NT.t;
     // rows are built complemented (0 = no neighbour) by LDS atomic ORs, so
     // the 3 (2K - 4) updates need no read-modify-write round trips; every
@@ -1358,24 +1357,31 @@ __device__ int32_t lane_lookup(const uint32_t (*F)[TB], const RotSys &NT, const 
         atomicOr((unsigned long long *)&NT.w[c][t], (unsigned long long)(b ^ 0xF) << (4 * a));
         degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
     }
-    uint64_t best[K];
-    uint64_t ord = lane_start_edge_code<K>(NT, degs, best);
-    // table lookup with full-code verification
-    uint64_t h = code_hash(best, K);
-    int mask = T.hmask[grp];
-    int s = (int)(h & (uint64_t)mask);
-    for (int probe = 0; probe <= mask; probe++) {
-        int c = T.slots[grp][s];
-        if (c < 0) break;
-        const uint64_t *cw = T.codes[grp] + (int64_t)c * K;
-        bool eq = true;
+    ordw = lane_start_edge_code<K>(NT, degs, best);
+    return code_hash(best, K);
+}
+
+// code row c of group grp equals best (all K words compared)
+template <int K>
+__device__ inline bool row_equal(const TablesView &T, int grp, int32_t c, const uint64_t (&best)[K]) {
+    const uint64_t *cw = T.codes[grp] + (int64_t)c * K;
+    uint64_t diff = 0;
 #pragma unroll
-        for (int i = 0; i < K; i++) eq = eq && (cw[i] == best[i]);
-        if (eq) {
-            ordw = ord;
-            return c;
-        }
+    for (int i = 0; i < K; i++) diff |= cw[i] ^ best[i];
+    return diff == 0;
+}
+
+// Table probe of a code of group grp whose first slot s held c: the code id
+// (full-code verification), or -1 when no template triangulation has it.
+template <int K>
+__device__ int32_t probe_rest(const TablesView &T, int grp, const uint64_t (&best)[K], int s, int32_t c, bool hit) {
+    const int mask = T.hmask[grp];
+    for (int probe = 0; probe <= mask; probe++) {
+        if (c < 0) return -1;
+        if (hit) return c;
         s = (s + 1) & mask;
+        c = T.slots[grp][s];
+        hit = c >= 0 && row_equal<K>(T, grp, c, best);
     }
     return -1;
 }
@@ -1391,39 +1397,66 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
     const int t = threadIdx.x;
     const int64_t p = blockIdx.x * (int64_t)TB + t;
     if (p >= n) return;
-    // hulls wanted and possible (the K-th neighbour exists)
+    // the neighbour ids that say which hulls are possible (the K-th neighbour
+    // exists) and all KMAX relative vectors are loaded in one round trip;
+    // rows past the last wanted one are stored but never read
+    int32_t kid[NGRP];
+    for (int g = 0; g < NGRP; g++) kid[g] = nbr_id[(int64_t)(group_k(g) - 1) * n + p];
+    double x[KMAX][3];
+    for (int r = 0; r < KMAX; r++)
+        for (int d = 0; d < 3; d++) x[r][d] = nbr_rel[((int64_t)r * 3 + d) * n + p];
     uint32_t want = 0;
     for (int g = 0; g < NGRP; g++)
-        if (((need >> g) & 1) && nbr_id[(int64_t)(group_k(g) - 1) * n + p] >= 0) want |= 1u << g;
+        if (((need >> g) & 1) && kid[g] >= 0) want |= 1u << g;
     int32_t cid[NGRP] = {-1, -1, -1};
     uint64_t ordw[NGRP] = {0, 0, 0};
     if (want) {
         const int kl = (want & 4) ? 14 : ((want & 2) ? 12 : 6);  // last point to insert
         double m64 = 0;  // largest coordinate (FP64) and of its stored form
         float m32 = 0;
-        for (int r = 0; r < kl; r++)
+        for (int r = 0; r < KMAX; r++)
             for (int d = 0; d < 3; d++) {
-                double x = nbr_rel[((int64_t)r * 3 + d) * n + p];
-                S.P[d][r][t] = (float)x;
-                m64 = fmax(m64, fabs(x));
-                m32 = fmaxf(m32, fabsf((float)x));
+                S.P[d][r][t] = (float)x[r][d];
+                if (r < kl) {
+                    m64 = fmax(m64, fabs(x[r][d]));
+                    m32 = fmaxf(m32, fabsf((float)x[r][d]));
+                }
             }
         Lane L{S, t, nbr_rel, n, p, f32_orient_bound(m32), f32_det3_bound(m32), f64_orient_bound(m64),
                f64_det3_bound(m64)};
         lane_hull_start(L);
         const RotSys nt{S.NT, t};
         const RotSys nt14{reinterpret_cast<uint64_t (*)[TB]>(&S.P[0][0][0]), t};
+        // codes of the valid hulls, probed together after the last insertion
+        uint64_t c6[6] = {}, c12[12] = {}, c14[14] = {}, h[NGRP] = {0, 0, 0};
+        bool pend[NGRP] = {false, false, false};
         for (int q = 4; q < kl; q++) {
             if (!lane_insert(L, q)) break;
             const int K = q + 1;
             if (K == 6 && (want & 1)) {
-                if (lane_centre_inside(L, 6)) cid[0] = lane_lookup<6>(S.F, nt, T, ordw[0]);
+                if ((pend[0] = lane_centre_inside(L, 6))) h[0] = lane_code<6>(S.F, nt, c6, ordw[0]);
             } else if (K == 12 && (want & 2)) {
-                if (lane_centre_inside(L, 12)) cid[1] = lane_lookup<12>(S.F, nt, T, ordw[1]);
+                if ((pend[1] = lane_centre_inside(L, 12))) h[1] = lane_code<12>(S.F, nt, c12, ordw[1]);
             } else if (K == 14) {
-                if (lane_centre_inside(L, 14)) cid[2] = lane_lookup<14>(S.F, nt14, T, ordw[2]);
+                if ((pend[2] = lane_centre_inside(L, 14))) h[2] = lane_code<14>(S.F, nt14, c14, ordw[2]);
             }
         }
+        // first slots of the three probes
+        int sl[NGRP];
+        int32_t c[NGRP];
+        for (int g = 0; g < NGRP; g++) {
+            sl[g] = (int)(h[g] & (uint64_t)T.hmask[g]);
+            c[g] = pend[g] ? T.slots[g][sl[g]] : -1;
+        }
+        // every group has a code row 0 (the tables refuse to build
+        // otherwise): it stands in for a missing hit, so the three rows load
+        // unconditionally, before any comparison waits
+        const bool hit0 = row_equal<6>(T, 0, max(c[0], 0), c6) & (c[0] >= 0);
+        const bool hit1 = row_equal<12>(T, 1, max(c[1], 0), c12) & (c[1] >= 0);
+        const bool hit2 = row_equal<14>(T, 2, max(c[2], 0), c14) & (c[2] >= 0);
+        cid[0] = probe_rest<6>(T, 0, c6, sl[0], c[0], hit0);
+        cid[1] = probe_rest<12>(T, 1, c12, sl[1], c[1], hit1);
+        cid[2] = probe_rest<14>(T, 2, c14, sl[2], c[2], hit2);
     }
     for (int g = 0; g < NGRP; g++) {
         code_out[(int64_t)g * n + p] = cid[g];

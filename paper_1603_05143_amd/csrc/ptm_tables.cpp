@@ -413,6 +413,10 @@ bool build_tables(HostTables &T, std::string &err) {
             T.codes[g].insert(T.codes[g].end(), kv.first.begin(), kv.first.end());
         }
         int nc = (int)bucket[g].size();
+        if (nc == 0) {  // the hull kernel reads code row 0 of every group
+            err = "template tables: no code for hull size " + std::to_string(k);
+            return false;
+        }
         T.ncodes[g] = nc;
         int size = 16;
         while (size < 4 * nc) size <<= 1;
