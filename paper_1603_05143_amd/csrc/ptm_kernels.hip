@@ -1172,64 +1172,62 @@ __device__ int lane_insert(const Lane &L, int p) {
         }
     }
     if (nvis == 0) return 0;  // p inside: never a vertex
-    // horizon edges (a -> b) of visible facets f whose neighbour g is not
-    // visible: entries a | b << 4 | g << 8 | f << 13 | eg << 18, eg = the
-    // index of the edge b -> a in g
+    // horizon edges (a -> b) of the visible facets f whose neighbour g is
+    // not visible, one per start vertex: H[a] = b | g << 4 | f << 9 |
+    // eg << 14, eg = the index of the edge b -> a in g.  Inner edges write
+    // to row KMAX - 1, which is no start vertex (a < p <= KMAX - 1), so the
+    // loop body has no branch.
+    uint32_t hv = 0, he = 0;  // start and end vertices of the horizon
+    uint64_t pred = 0;        // nibble b: a of the horizon edge a -> b
     int nh = 0;
+    bool bad = false;
     for (uint32_t vm = vis; vm; vm &= vm - 1) {  // visible facets only
         const int f = __builtin_ctz(vm);
-        uint32_t w = S.F[f][t];
+        const uint32_t w = S.F[f][t];
+#pragma unroll
         for (int e = 0; e < 3; e++) {
-            int g = fn(w, e);
-            if (g >= nf) return 0;  // broken link (cannot happen with exact predicates)
-            if ((vis >> g) & 1) continue;
-            if (nh >= KMAX) return 0;
+            const int g = fn(w, e);
+            bad |= g >= nf;  // broken link (cannot happen with exact predicates)
+            const bool hz = !((vis >> g) & 1);
             const int ha = fv(w, e), hb = fv(w, e == 2 ? 0 : e + 1);
-            const uint32_t gw = S.F[g][t];
+            const uint32_t gw = S.F[min(g, 2 * KMAX - 5)][t];
             const int eg = (fv(gw, 0) == hb) ? 0 : ((fv(gw, 1) == hb) ? 1 : 2);
-            S.H[nh][t] = (uint32_t)ha | ((uint32_t)hb << 4) | ((uint32_t)g << 8) | ((uint32_t)f << 13) |
-                         ((uint32_t)eg << 18);
-            nh++;
+            S.H[hz ? ha : KMAX - 1][t] = (uint32_t)hb | ((uint32_t)g << 4) | ((uint32_t)f << 9) | ((uint32_t)eg << 14);
+            hv |= (uint32_t)hz << ha;
+            he |= (uint32_t)hz << hb;
+            pred |= (uint64_t)(hz ? ha : 0) << (4 * hb);
+            nh += hz;
         }
     }
-    // a horizon of nvis+2 edges <=> no earlier vertex is swallowed
-    if (nh != nvis + 2) return 0;
-    // slots: freed visible facets first (increasing), then two new ones;
-    // pass 1 records vertex -> slot maps, pass 2 builds the facets and turns
-    // each neighbour's link from the visible facet to the new one (an XOR:
-    // every link changes at most once, so no read-modify-write is needed)
-    uint64_t start_lo = 0, start_hi = 0, end_lo = 0, end_hi = 0;  // 8-bit fields
+    // a horizon of nvis+2 edges <=> no earlier vertex is swallowed; one
+    // edge leaves and one enters every horizon vertex
+    if (bad || nh != nvis + 2 || __builtin_popcount(hv) != nh || he != hv) return 0;
+    // slots: freed visible facets first (increasing), then two new ones, in
+    // increasing order of the start vertex; then the new facet (a, b, p)
+    // links to g across a -> b, to the facet of b across b -> p and to the
+    // facet of pred(a) across p -> a, and g's link turns from the visible
+    // facet to the new one (an XOR: every link changes at most once, so no
+    // read-modify-write is needed)
+    uint64_t slo = 0, shi = 0;  // 5-bit slot per start vertex
     uint32_t freed = vis;
     int nf_new = nf;
-    for (int h = 0; h < nh; h++) {
-        int s;
+    for (uint32_t m = hv; m; m &= m - 1) {
+        int sl;
         if (freed) {
-            s = __builtin_ctz(freed);
+            sl = __builtin_ctz(freed);
             freed &= freed - 1;
         } else {
-            s = nf_new++;
+            sl = nf_new++;
         }
-        uint32_t hw = S.H[h][t];
-        int ha = hw & 0xF, hb = (hw >> 4) & 0xF;
-        if (ha < 8) start_lo |= (uint64_t)s << (8 * ha); else start_hi |= (uint64_t)s << (8 * (ha - 8));
-        if (hb < 8) end_lo |= (uint64_t)s << (8 * hb); else end_hi |= (uint64_t)s << (8 * (hb - 8));
+        set5(slo, shi, __builtin_ctz(m), sl);
     }
-    freed = vis;
-    int nf2 = nf;
-    for (int h = 0; h < nh; h++) {
-        int s;
-        if (freed) {
-            s = __builtin_ctz(freed);
-            freed &= freed - 1;
-        } else {
-            s = nf2++;
-        }
-        uint32_t hw = S.H[h][t];
-        int ha = hw & 0xF, hb = (hw >> 4) & 0xF, g = (hw >> 8) & 0x1F, f = (hw >> 13) & 0x1F, eg = (hw >> 18) & 3;
-        int s_next = (int)(((hb < 8 ? start_lo >> (8 * hb) : start_hi >> (8 * (hb - 8)))) & 0xFF);
-        int s_prev = (int)(((ha < 8 ? end_lo >> (8 * ha) : end_hi >> (8 * (ha - 8)))) & 0xFF);
-        S.F[s][t] = fpack(ha, hb, p, g, s_next, s_prev);
-        atomicXor(&S.F[g][t], (uint32_t)(f ^ s) << (12 + 5 * eg));
+    for (uint32_t m = hv; m; m &= m - 1) {
+        const int a = __builtin_ctz(m);
+        const uint32_t hw = S.H[a][t];
+        const int b = hw & 0xF, g = (hw >> 4) & 0x1F, f = (hw >> 9) & 0x1F, eg = (hw >> 14) & 3;
+        const int sa = field5(slo, shi, a);
+        S.F[sa][t] = fpack(a, b, p, g, field5(slo, shi, b), field5(slo, shi, (int)nib(pred, a)));
+        atomicXor(&S.F[g][t], (uint32_t)(f ^ sa) << (12 + 5 * eg));
     }
     return 1;
 }
