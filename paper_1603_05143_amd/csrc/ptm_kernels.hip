@@ -761,43 +761,54 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
         if (two && s1 > 0) vis |= 1u << f1;
     }
     if (!vis) return true;
-    // horizon edges (a -> b) of visible facets whose neighbour g is not visible
+    // horizon edges (a -> b) of the visible facets whose neighbour g is not
+    // visible, one per start vertex: H[a] = b | g << 5.  Inner edges write
+    // to row VK - 1, which is no start vertex (a < p <= VK - 1), so the loop
+    // body has no branch.
+    uint32_t hv = 0, he = 0;      // start and end vertices of the horizon
+    uint64_t pr_lo = 0, pr_hi = 0;  // 5-bit field b: a of the horizon edge a -> b
     int nh = 0;
+    bool bad = false;
     for (uint32_t m = vis; m; m &= m - 1) {
-        const int f = __builtin_ctz(m);
-        const uint32_t w = S.F[f][t];
+        const uint32_t w = S.F[__builtin_ctz(m)][t];
+#pragma unroll
         for (int e = 0; e < 3; e++) {
             const int g = vl(w, e);
-            if (!((live >> g) & 1)) return false;
-            if ((vis >> g) & 1) continue;
-            if (nh >= VK) return false;
-            S.H[nh][t] = (uint16_t)(vv(w, e) | (vv(w, e == 2 ? 0 : e + 1) << 5) | (g << 10));
-            nh++;
+            bad |= !((live >> g) & 1);
+            const bool hz = !((vis >> g) & 1);
+            const int ha = vv(w, e), hb = vv(w, e == 2 ? 0 : e + 1);
+            S.H[hz ? ha : VK - 1][t] = (uint16_t)(hb | (g << 5));
+            hv |= (uint32_t)hz << ha;
+            he |= (uint32_t)hz << hb;
+            set5(pr_lo, pr_hi, hb, hz ? ha : 0);
+            nh += hz;
         }
     }
+    // the horizon is one cycle: an edge leaves and one enters every vertex
+    if (bad || __builtin_popcount(hv) != nh || he != hv) return false;
+    // slots in increasing order of the start vertex; the new facet (a, b, p)
+    // links to g across a -> b, to the facet of b across b -> p and to the
+    // facet of pred(a) across p -> a
     const uint32_t freeset = ~(live & ~vis);
-    uint64_t st_lo = 0, st_hi = 0, en_lo = 0, en_hi = 0;  // vertex -> slot of the horizon edge it starts / ends
+    uint64_t sl_lo = 0, sl_hi = 0;  // 5-bit slot per start vertex
     uint32_t fr = freeset, added = 0;
-    for (int h = 0; h < nh; h++) {
+    for (uint32_t m = hv; m; m &= m - 1) {
         if (!fr) return false;
         const int s = __builtin_ctz(fr);
         fr &= fr - 1;
         added |= 1u << s;
-        const uint32_t hw = S.H[h][t];
-        set5(st_lo, st_hi, hw & 31, s);
-        set5(en_lo, en_hi, (hw >> 5) & 31, s);
+        set5(sl_lo, sl_hi, __builtin_ctz(m), s);
     }
-    fr = freeset;
-    for (int h = 0; h < nh; h++) {
-        const int s = __builtin_ctz(fr);
-        fr &= fr - 1;
-        const uint32_t hw = S.H[h][t];
-        const int ha = hw & 31, hb = (hw >> 5) & 31, g = (hw >> 10) & 31;
-        S.F[s][t] = vpack(ha, hb, p, g, field5(st_lo, st_hi, hb), field5(en_lo, en_hi, ha));
-        // g holds the edge hb -> ha; its link there now points to s
+    for (uint32_t m = hv; m; m &= m - 1) {
+        const int a = __builtin_ctz(m);
+        const uint32_t hw = S.H[a][t];
+        const int b = hw & 31, g = (hw >> 5) & 31;
+        const int sa = field5(sl_lo, sl_hi, a);
+        S.F[sa][t] = vpack(a, b, p, g, field5(sl_lo, sl_hi, b), field5(sl_lo, sl_hi, field5(pr_lo, pr_hi, a)));
+        // g holds the edge b -> a; its link there now points to sa
         const uint32_t gw = S.F[g][t];
-        const int eg = vpos(gw, hb);
-        S.F[g][t] = (gw & ~(31u << (15 + 5 * eg))) | ((uint32_t)s << (15 + 5 * eg));
+        const int eg = vpos(gw, b);
+        S.F[g][t] = (gw & ~(31u << (15 + 5 * eg))) | ((uint32_t)sa << (15 + 5 * eg));
     }
     live = (live & ~vis) | added;
     return true;
