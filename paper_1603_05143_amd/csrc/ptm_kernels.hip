@@ -1313,13 +1313,14 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
     }
     code[0] = minsig;
     uint64_t ntu = NT.get(bu);
-    uint64_t lab = ~0ull, ord = (uint64_t)bu, par = 0;
-    lab = setnib(lab, bu, 0);
+    // every nibble below is written once, from 0xF (lab) or 0 (ord, par), so
+    // a single XOR or OR sets it
+    uint64_t lab = ~0ull ^ (0xFull << (4 * bu)), ord = (uint64_t)bu, par = 0;
     int y = bv;
     for (int j = 0; j < mindeg; j++) {
-        lab = setnib(lab, y, j + 1);
-        ord = setnib(ord, j + 1, y);
-        par = setnib(par, y, bu);
+        lab ^= (uint64_t)(0xF ^ (j + 1)) << (4 * y);
+        ord |= (uint64_t)y << (4 * (j + 1));
+        par |= (uint64_t)bu << (4 * y);
         y = (int)nib(ntu, y);
     }
     uint32_t nl = mindeg + 1;
@@ -1334,9 +1335,9 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
             uint32_t ly = nib(lab, yy);
             if (ly == 0xF) {
                 ly = nl;
-                lab = setnib(lab, yy, nl);
-                ord = setnib(ord, nl, yy);
-                par = setnib(par, yy, x);
+                lab ^= (uint64_t)(0xF ^ nl) << (4 * yy);
+                ord |= (uint64_t)yy << (4 * nl);
+                par |= (uint64_t)x << (4 * yy);
                 nl++;
             }
             row |= (uint64_t)ly << (56 - 4 * j);
@@ -1887,23 +1888,31 @@ __device__ inline void finish_stored(const MatchShared &M, const TablesView &T, 
     ev.r = (RT)r;
     for (int k = 0; k < 4; k++) ev.q[k] = qs[k];
     ev.s = qs[4];
-    // loads are issued K/2 ranks at a time: enough in flight to hide the
-    // memory latency without holding every point in registers
+    // every point is loaded once and held in registers in the form's real
+    // type (a second pass over global memory misses the L2); the FP32 form
+    // centres the rounded points, an error of 2^-24 relative, far inside its
+    // strain tolerance.  The optional residual pass below reads the vectors
+    // again, so that they are dead once A^T is formed.
     constexpr int HALF = K / 2;
+    RT v[K][3];
     double cb[3] = {0, 0, 0};
-#pragma unroll HALF
+#pragma unroll
     for (int rr = 0; rr < K; rr++)
-        for (int d = 0; d < 3; d++) cb[d] += nbr_rel[((int64_t)rr * 3 + d) * n + p];
+        for (int d = 0; d < 3; d++) {
+            const double x = nbr_rel[((int64_t)rr * 3 + d) * n + p];
+            v[rr][d] = (RT)x;
+            cb[d] += x;
+        }
     for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
     RT a0[3] = {(RT)(-cb[0]), (RT)(-cb[1]), (RT)(-cb[2])};
     RT l = sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
     RT At[3][3];
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) At[x][y] = (RT)D.vpinv[x][0] * a0[y];
-#pragma unroll HALF
+#pragma unroll
     for (int rr = 0; rr < K; rr++) {
         RT ar[3];
-        for (int d = 0; d < 3; d++) ar[d] = (RT)(nbr_rel[((int64_t)rr * 3 + d) * n + p] - cb[d]);
+        for (int d = 0; d < 3; d++) ar[d] = v[rr][d] - (RT)cb[d];
         l += sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
         int col = (int)nib(tv, rr) + 1;
         for (int x = 0; x < 3; x++)
@@ -2082,10 +2091,11 @@ __device__ inline void pair_minimum(int64_t q0, int64_t q1, int64_t cap, const u
 // twice the FP32 bound, and clear of the cut-off) -- is finished here in
 // the working precision; every other atom (a near tie, an FP32 margin too
 // small to trust, pairs that did not fit the buffer) is appended to todo for
-// k_decide_full, so that this kernel stays small enough for full occupancy.
-// Registers are held to four waves per SIMD.
+// k_decide_full, so that this kernel stays small.  Registers: the bound of
+// three blocks per CU (FP32) or two (FP64) lets the winner's points stay in
+// registers without spilling (146 and 162 are used: three waves per SIMD).
 template <typename RT>
-__global__ void __launch_bounds__(MB, 4) k_decide(int64_t n, const double *__restrict__ nbr_rel,
+__global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t n, const double *__restrict__ nbr_rel,
                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
                                                const int8_t *__restrict__ species, TablesView T,
                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
