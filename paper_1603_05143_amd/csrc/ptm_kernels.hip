@@ -1149,8 +1149,9 @@ __device__ inline void lane_hull_start(const Lane &L) {
 
 // Insert point p into the hull of points 0..p-1 (nf = 2p - 4 facets).
 // Returns 0 if p lies inside (it never becomes a vertex) or swallows an
-// earlier vertex: then no hull of p or more points is valid.
-__device__ int lane_insert(const Lane &L, int p) {
+// earlier vertex: then no hull of p or more points is valid.  cv: facet
+// slots whose centre test has passed; the slots rewritten here leave it.
+__device__ int lane_insert(const Lane &L, int p, uint32_t &cv) {
     TopoShared &S = L.S;
     const int t = L.t;
     const int nf = 2 * p - 4;
@@ -1184,10 +1185,9 @@ __device__ int lane_insert(const Lane &L, int p) {
     }
     if (nvis == 0) return 0;  // p inside: never a vertex
     // horizon edges (a -> b) of the visible facets f whose neighbour g is
-    // not visible, one per start vertex: H[a] = b | g << 4 | f << 9 |
-    // eg << 14, eg = the index of the edge b -> a in g.  Inner edges write
-    // to row KMAX - 1, which is no start vertex (a < p <= KMAX - 1), so the
-    // loop body has no branch.
+    // not visible, one per start vertex: H[a] = b | g << 4 | f << 9.  Inner
+    // edges write to row KMAX - 1, which is no start vertex (a < p <=
+    // KMAX - 1), so the loop body has no branch.
     uint32_t hv = 0, he = 0;  // start and end vertices of the horizon
     uint64_t pred = 0;        // nibble b: a of the horizon edge a -> b
     int nh = 0;
@@ -1201,9 +1201,7 @@ __device__ int lane_insert(const Lane &L, int p) {
             bad |= g >= nf;  // broken link (cannot happen with exact predicates)
             const bool hz = !((vis >> g) & 1);
             const int ha = fv(w, e), hb = fv(w, e == 2 ? 0 : e + 1);
-            const uint32_t gw = S.F[min(g, 2 * KMAX - 5)][t];
-            const int eg = (fv(gw, 0) == hb) ? 0 : ((fv(gw, 1) == hb) ? 1 : 2);
-            S.H[hz ? ha : KMAX - 1][t] = (uint32_t)hb | ((uint32_t)g << 4) | ((uint32_t)f << 9) | ((uint32_t)eg << 14);
+            S.H[hz ? ha : KMAX - 1][t] = (uint32_t)hb | ((uint32_t)g << 4) | ((uint32_t)f << 9);
             hv |= (uint32_t)hz << ha;
             he |= (uint32_t)hz << hb;
             pred |= (uint64_t)(hz ? ha : 0) << (4 * hb);
@@ -1235,20 +1233,31 @@ __device__ int lane_insert(const Lane &L, int p) {
     for (uint32_t m = hv; m; m &= m - 1) {
         const int a = __builtin_ctz(m);
         const uint32_t hw = S.H[a][t];
-        const int b = hw & 0xF, g = (hw >> 4) & 0x1F, f = (hw >> 9) & 0x1F, eg = (hw >> 14) & 3;
+        const int b = hw & 0xF, g = (hw >> 4) & 0x1F, f = (hw >> 9) & 0x1F;
         const int sa = field5(slo, shi, a);
         S.F[sa][t] = fpack(a, b, p, g, field5(slo, shi, b), field5(slo, shi, (int)nib(pred, a)));
+        // g (not visible, so never a slot taken here) holds the edge b -> a
+        // as its edge eg; only its links may have changed
+        const uint32_t gw = S.F[g][t];
+        const int eg = (fv(gw, 0) == b) ? 0 : ((fv(gw, 1) == b) ? 1 : 2);
         atomicXor(&S.F[g][t], (uint32_t)(f ^ sa) << (12 + 5 * eg));
     }
+    cv &= ~vis;  // the freed slots hold new facets
     return 1;
 }
 
 // the centre lies strictly inside every facet of the K-point hull:
-// det[a; b; c] > 0 exactly
-__device__ inline int lane_centre_inside(const Lane &L, int K) {
-    // two facets per step (2K - 4 is even), as in the insertion
-    for (int f = 0; f < 2 * K - 4; f += 2) {
-        const uint32_t w0 = L.S.F[f][L.t], w1 = L.S.F[f + 1][L.t];
+// det[a; b; c] > 0 exactly.  Facets in cv passed at a smaller hull and are
+// not tested again; on success every facet joins cv.
+__device__ inline int lane_centre_inside(const Lane &L, int K, uint32_t &cv) {
+    const uint32_t all = (1u << (2 * K - 4)) - 1;
+    // two facets per step, as in the insertion
+    for (uint32_t m = all & ~cv; m;) {
+        const int f0 = __builtin_ctz(m);
+        m &= m - 1;
+        const int f1 = m ? __builtin_ctz(m) : f0;  // (f0 again when it is the last)
+        m &= m - 1;
+        const uint32_t w0 = L.S.F[f0][L.t], w1 = L.S.F[f1][L.t];
         float a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
         L.load(fv(w0, 0), a0);
         L.load(fv(w0, 1), b0);
@@ -1262,6 +1271,7 @@ __device__ inline int lane_centre_inside(const Lane &L, int K) {
         if (!s0 && lane_det3(L, fv(w0, 0), fv(w0, 1), fv(w0, 2)) <= 0) return 0;
         if (!s1 && lane_det3(L, fv(w1, 0), fv(w1, 1), fv(w1, 2)) <= 0) return 0;
     }
+    cv |= all;
     return 1;
 }
 
@@ -1440,15 +1450,16 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
         // codes of the valid hulls, probed together after the last insertion
         uint64_t c6[6] = {}, c12[12] = {}, c14[14] = {}, h[NGRP] = {0, 0, 0};
         bool pend[NGRP] = {false, false, false};
+        uint32_t cv = 0;  // facet slots whose centre test passed
         for (int q = 4; q < kl; q++) {
-            if (!lane_insert(L, q)) break;
+            if (!lane_insert(L, q, cv)) break;
             const int K = q + 1;
             if (K == 6 && (want & 1)) {
-                if ((pend[0] = lane_centre_inside(L, 6))) h[0] = lane_code<6>(S.F, nt, c6, ordw[0]);
+                if ((pend[0] = lane_centre_inside(L, 6, cv))) h[0] = lane_code<6>(S.F, nt, c6, ordw[0]);
             } else if (K == 12 && (want & 2)) {
-                if ((pend[1] = lane_centre_inside(L, 12))) h[1] = lane_code<12>(S.F, nt, c12, ordw[1]);
+                if ((pend[1] = lane_centre_inside(L, 12, cv))) h[1] = lane_code<12>(S.F, nt, c12, ordw[1]);
             } else if (K == 14) {
-                if ((pend[2] = lane_centre_inside(L, 14))) h[2] = lane_code<14>(S.F, nt14, c14, ordw[2]);
+                if ((pend[2] = lane_centre_inside(L, 14, cv))) h[2] = lane_code<14>(S.F, nt14, c14, ordw[2]);
             }
         }
         // first slots of the three probes
