@@ -39,9 +39,9 @@ struct MatchOut {
 
 // Flat (atom, candidate) pair list of the match stage.
 struct MatchScratch {
-    int64_t *cnt;        // [n+1] candidates per atom
-    int64_t *off;        // [n+1] exclusive prefix sum (off[n] = total)
-    uint2 *pairs;        // [cap] (atom, group << 28 | candidate)
+    int64_t *cnt;        // [3n+1] candidates per (group, atom), group-major
+    int64_t *off;        // [3n+1] exclusive prefix sum (off[3n] = total)
+    uint2 *pairs;        // [cap] (atom, group << 28 | candidate), group-major
     double *r;           // [cap] RMSD of each pair
     void *qs;            // [cap][5] quaternion and scale of each pair, working precision
     int64_t cap;         // pair capacity
