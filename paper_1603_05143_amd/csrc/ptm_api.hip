@@ -42,7 +42,7 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     b += align_up(4 * (size_t)n * NGRP);      // code ids
     b += align_up(8 * (size_t)n * NGRP);      // labellings
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
-    b += align_up(8 * (size_t)(NGRP * n + 1)) * 2;  // candidate counts and offsets per (group, atom)
+    b += align_up(8 * (size_t)(pair_slots(n) + 1)) * 2;  // candidate counts and offsets per (atom, group)
     b += align_up(16 * (size_t)pair_capacity(n));  // pairs and their RMSD
     b += align_up(40 * (size_t)pair_capacity(n));  // their quaternion and scale
     b += align_up(scan_tmp);
@@ -61,7 +61,7 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
                                          (int)(cells + 1)) != hipSuccess ||
         hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp2, (int64_t *)nullptr, (int64_t *)nullptr,
-                                         (int64_t)NGRP * n + 1) != hipSuccess) {
+                                         pair_slots(n) + 1) != hipSuccess) {
         err = "hipcub scan size query failed";
         return false;
     }
@@ -98,8 +98,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     ord = (uint64_t *)take(8 * (size_t)n * NGRP);
     part = (double *)take(8 * 7 * (size_t)nb);
     match.cap = pair_capacity(n);
-    match.cnt = (int64_t *)take(8 * (size_t)(NGRP * n + 1));
-    match.off = (int64_t *)take(8 * (size_t)(NGRP * n + 1));
+    match.cnt = (int64_t *)take(8 * (size_t)(pair_slots(n) + 1));
+    match.off = (int64_t *)take(8 * (size_t)(pair_slots(n) + 1));
     match.pairs = (uint2 *)take(8 * (size_t)match.cap);
     match.r = (double *)take(8 * (size_t)match.cap);
     match.qs = take(40 * (size_t)match.cap);
@@ -448,7 +448,7 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
         int32_t left[2] = {0, 0};
         int64_t pairs = 0;
         PTM_HIP(ctx, hipMemcpy(left, ctx->main.count + cells + 1, 8, hipMemcpyDeviceToHost));
-        PTM_HIP(ctx, hipMemcpy(&pairs, ctx->main.match.off + NGRP * n_atoms, 8, hipMemcpyDeviceToHost));
+        PTM_HIP(ctx, hipMemcpy(&pairs, ctx->main.match.off + pair_slots(n_atoms), 8, hipMemcpyDeviceToHost));
         ctx->prof_info[PTM_INFO_CELLS] = cells;
         ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left[0] : n_atoms;
         ctx->prof_info[PTM_INFO_PAIRS] = pairs;

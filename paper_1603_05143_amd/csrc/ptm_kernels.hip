@@ -1983,31 +1983,34 @@ __device__ inline void load_templates(MatchShared &M, const TablesView &T) {
 
 // Candidates of one atom: pass 1 counts them (mask applied), pass 2 lists
 // them as (atom, group, candidate) pairs at the atom's offset.
-// The pair list is group-major: the pairs of hull group 0 of every atom,
-// then those of group 1, then group 2 (atom order inside each), so that the
-// superposition kernel's waves see one neighbour count K at a time.
-// cnt[g n + p] = enabled candidates of atom p in group g; cnt[3n] = 0, so
-// that the exclusive scan off[] ends with the total.
+// The pair list is ordered by tiles of PAIR_TILE atoms, then hull group,
+// then atom: the superposition kernel's waves see one neighbour count K at a
+// time (a tile's three group runs are short, so an atom's vectors are still
+// in the L2 when its next group comes).  cnt[pidx(p, g)] = enabled
+// candidates of atom p in group g (0 for the padding atoms p >= n);
+// cnt[pair_slots(n)] = 0, so that the exclusive scan off[] ends with the
+// total.
 __global__ void __launch_bounds__(256) k_cand_count(int64_t n, TablesView T, const int32_t *__restrict__ code,
                                                     uint32_t mask, int64_t *__restrict__ cnt) {
+    const int64_t np = pair_slots(n) / NGRP;  // atoms rounded up to whole tiles
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p > n) return;
-    if (p == n) {
-        cnt[(int64_t)NGRP * n] = 0;
+    if (p > np) return;
+    if (p == np) {
+        cnt[pair_slots(n)] = 0;
         return;
     }
     for (int g = 0; g < NGRP; g++) {
         int c = 0;
-        const int32_t cid = code[(int64_t)g * n + p];
+        const int32_t cid = p < n ? code[(int64_t)g * n + p] : -1;
         if (cid >= 0)
             for (int k = T.cstart[g][cid]; k < T.cstart[g][cid + 1]; k++) c += (mask >> T.cand[g][k].tmpl) & 1;
-        cnt[(int64_t)g * n + p] = c;
+        cnt[pidx(p, g)] = c;
     }
 }
 // an atom with a pair at or beyond the capacity: its group-2 range ends last
 // (off is monotone), so this one test covers all three ranges
-__device__ inline bool pairs_overflow(const int64_t *__restrict__ off, int64_t n, int64_t p, int64_t cap) {
-    return off[(int64_t)(NGRP - 1) * n + p + 1] > cap;
+__device__ inline bool pairs_overflow(const int64_t *__restrict__ off, int64_t p, int64_t cap) {
+    return off[pidx(p, NGRP - 1) + 1] > cap;
 }
 
 __global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, const int32_t *__restrict__ code,
@@ -2015,12 +2018,12 @@ __global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, cons
                                                    uint2 *__restrict__ pairs) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const bool over = pairs_overflow(off, n, p, cap);
+    const bool over = pairs_overflow(off, p, cap);
     for (int g = 0; g < NGRP; g++) {
-        int64_t q = off[(int64_t)g * n + p];
+        int64_t q = off[pidx(p, g)];
         if (over) {
             // evaluated directly by the decision kernel; mark its slots below cap
-            const int64_t q1 = min(off[(int64_t)g * n + p + 1], cap);
+            const int64_t q1 = min(off[pidx(p, g) + 1], cap);
             for (; q < q1; q++) pairs[q] = make_uint2(0xFFFFFFFFu, 0u);
             continue;
         }
@@ -2039,7 +2042,7 @@ __global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__
                                                   double *__restrict__ rout, RT *__restrict__ qsout) {
     __shared__ MatchShared M;
     load_templates(M, T);
-    int64_t total = off[(int64_t)NGRP * n];
+    int64_t total = off[pair_slots(n)];
     if (total > cap) total = cap;
     for (int64_t q = blockIdx.x * (int64_t)MB + threadIdx.x; q < total; q += (int64_t)gridDim.x * MB) {
         uint2 pr = pairs[q];
@@ -2090,7 +2093,7 @@ constexpr double RMSD_F32_BOUND = 4e-6;
 
 // Minimum over an atom's evaluated pairs: best and second-best RMSD and the
 // winning (group, candidate).  q1 > cap: the pairs did not fit the buffer.
-__device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t n, int64_t p,
+__device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t p,
                                     const uint2 *__restrict__ pairs, const double *__restrict__ rr, double &m1,
                                     double &m2, int &arg_grp, int &arg_c, int64_t &arg_q) {
     m1 = m2 = INFINITY;
@@ -2098,8 +2101,8 @@ __device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t n, 
     arg_q = -1;
     // the atom's ranges in group order, candidates in table order inside each
     for (int g = 0; g < NGRP; g++) {
-        const int64_t q1 = off[(int64_t)g * n + p + 1];
-        for (int64_t q = off[(int64_t)g * n + p]; q < q1; q++) {
+        const int64_t q1 = off[pidx(p, g) + 1];
+        for (int64_t q = off[pidx(p, g)]; q < q1; q++) {
             double r = rr[q];
             if (r < m1) {
                 m2 = m1;
@@ -2140,11 +2143,11 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
     double m1, m2;
     int arg_grp, arg_c;
     int64_t arg_q;
-    const bool over = pairs_overflow(off, n, p, cap);
+    const bool over = pairs_overflow(off, p, cap);
     m1 = m2 = INFINITY;
     arg_grp = arg_c = -1;
     arg_q = -1;
-    if (!over) pair_minimum(off, n, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
+    if (!over) pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
     bool full = over || (arg_c >= 0 && !(m2 > m1 + 1e-12));
     if (sizeof(RT) == 4 && arg_c >= 0)
         full = full || !(m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) || fabs(m1 - cutoff) <= RMSD_F32_BOUND;
@@ -2496,10 +2499,10 @@ void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const 
 }
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
                  hipStream_t st) {
-    unsigned nb = (unsigned)((n + 1 + 255) / 256);
+    unsigned nb = (unsigned)((pair_slots(n) / NGRP + 1 + 255) / 256);
     hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt);
     size_t tmp = W.scan_tmp_bytes;
-    (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, (int64_t)NGRP * n + 1, st);
+    (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, pair_slots(n) + 1, st);
     hipLaunchKernelGGL(k_cand_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, code, mask, W.off,
                        W.cap, W.pairs);
 }

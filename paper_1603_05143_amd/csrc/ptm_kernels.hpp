@@ -37,11 +37,21 @@ struct MatchOut {
     int8_t *best_type;
 };
 
-// Flat (atom, candidate) pair list of the match stage.
+// Flat (atom, candidate) pair list of the match stage, ordered by tiles of
+// PAIR_TILE atoms, then hull group, then atom: slot pidx(p, g) counts atom
+// p's pairs of group g; pair_slots(n) slots cover n atoms (the last tile
+// padded with empty atoms).
+constexpr int64_t PAIR_TILE = 1024;
+__host__ __device__ inline int64_t pidx(int64_t p, int g) {
+    return (p / PAIR_TILE) * (NGRP * PAIR_TILE) + g * PAIR_TILE + (p % PAIR_TILE);
+}
+__host__ __device__ inline int64_t pair_slots(int64_t n) {
+    return (n + PAIR_TILE - 1) / PAIR_TILE * (NGRP * PAIR_TILE);
+}
 struct MatchScratch {
-    int64_t *cnt;        // [3n+1] candidates per (group, atom), group-major
-    int64_t *off;        // [3n+1] exclusive prefix sum (off[3n] = total)
-    uint2 *pairs;        // [cap] (atom, group << 28 | candidate), group-major
+    int64_t *cnt;        // [pair_slots(n)+1] candidates per (atom, group) slot
+    int64_t *off;        // [pair_slots(n)+1] exclusive prefix sum (last = total)
+    uint2 *pairs;        // [cap] (atom, group << 28 | candidate), in slot order
     double *r;           // [cap] RMSD of each pair
     void *qs;            // [cap][5] quaternion and scale of each pair, working precision
     int64_t cap;         // pair capacity
