@@ -2136,35 +2136,72 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
                                                const RT *__restrict__ qs, double cutoff, MatchOut O,
                                                int32_t *__restrict__ todo, int32_t *__restrict__ todo_count) {
     __shared__ MatchShared M;
+    // the block's winners regrouped by hull size (see below)
+    __shared__ int32_t s_cnt[MB / 64][NGRP];
+    __shared__ int32_t s_p[MB], s_c[MB];
+    __shared__ int64_t s_q[MB];
+    __shared__ double s_r[MB];
+    __shared__ int8_t s_g[MB];
     load_templates(M, T);
     const int64_t p = blockIdx.x * (int64_t)MB + threadIdx.x;
-    if (p >= n) return;
-    const int32_t i = sid[p];
-    double m1, m2;
-    int arg_grp, arg_c;
-    int64_t arg_q;
-    const bool over = pairs_overflow(off, p, cap);
-    m1 = m2 = INFINITY;
-    arg_grp = arg_c = -1;
-    arg_q = -1;
-    if (!over) pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
-    bool full = over || (arg_c >= 0 && !(m2 > m1 + 1e-12));
-    if (sizeof(RT) == 4 && arg_c >= 0)
-        full = full || !(m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) || fabs(m1 - cutoff) <= RMSD_F32_BOUND;
-    if (full) {
-        todo[atomicAdd(todo_count, 1)] = (int32_t)p;
-        return;
+    double m1 = INFINITY, m2 = INFINITY;
+    int arg_grp = -1, arg_c = -1;
+    int64_t arg_q = -1;
+    int cls = -1;  // hull group of the winner to finish here, -1 for none
+    if (p < n) {
+        const bool over = pairs_overflow(off, p, cap);
+        if (!over) pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
+        bool full = over || (arg_c >= 0 && !(m2 > m1 + 1e-12));
+        if (sizeof(RT) == 4 && arg_c >= 0)
+            full = full || !(m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) || fabs(m1 - cutoff) <= RMSD_F32_BOUND;
+        if (full) todo[atomicAdd(todo_count, 1)] = (int32_t)p;
+        else if (arg_c < 0) write_none(O, sid[p]);
+        else cls = arg_grp;
     }
-    if (arg_c < 0) {
-        write_none(O, i);
-        return;
+    // Consecutive atoms in cell order span many grains, so a wave's winners
+    // mix the three hull sizes and each size's finishing code would run in
+    // turn.  The block's winners are regrouped by size (12, 14, then 6
+    // points; ballots give each lane its slot) and every lane finishes the
+    // winner in its slot: waves then mostly run one size's code.
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t bal[NGRP];
+#pragma unroll
+    for (int k = 0; k < NGRP; k++) bal[k] = __ballot(cls == k);
+    if (lane == 0)
+        for (int k = 0; k < NGRP; k++) s_cnt[wv][k] = __popcll(bal[k]);
+    __syncthreads();
+    constexpr int order[NGRP] = {1, 2, 0};
+    int total = 0, base = 0;
+#pragma unroll
+    for (int j = 0; j < NGRP; j++) {
+        const int k = order[j];
+        int tk = 0, before = 0;
+        for (int w2 = 0; w2 < MB / 64; w2++) {
+            tk += s_cnt[w2][k];
+            if (w2 < wv) before += s_cnt[w2][k];
+        }
+        if (k == cls) base = total + before + __popcll(bal[k] & ((1ull << lane) - 1));
+        total += tk;
     }
-    const uint64_t ord = ords[(int64_t)arg_grp * n + p];
-    const RT *w = qs + 5 * arg_q;
-    if (arg_grp == 0) finish_stored<6, RT>(M, T, 0, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
-    else if (arg_grp == 1)
-        finish_stored<12, RT>(M, T, 1, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
-    else finish_stored<14, RT>(M, T, 2, arg_c, ord, nbr_rel, m1, w, cutoff, p, n, i, nbr_id, species, O);
+    if (cls >= 0) {
+        s_p[base] = (int32_t)p;
+        s_c[base] = arg_c;
+        s_q[base] = arg_q;
+        s_r[base] = m1;
+        s_g[base] = (int8_t)cls;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= total) return;
+    const int64_t pw = s_p[threadIdx.x];
+    const int gw = s_g[threadIdx.x], cw = s_c[threadIdx.x];
+    const int32_t iw = sid[pw];
+    const uint64_t ord = ords[(int64_t)gw * n + pw];
+    const RT *w = qs + 5 * s_q[threadIdx.x];
+    const double rw = s_r[threadIdx.x];
+    if (gw == 0) finish_stored<6, RT>(M, T, 0, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
+    else if (gw == 1)
+        finish_stored<12, RT>(M, T, 1, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
+    else finish_stored<14, RT>(M, T, 2, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
 }
 
 // The atoms k_decide left (near ties, FP32 margins too small to trust, pairs
