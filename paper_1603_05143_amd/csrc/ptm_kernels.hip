@@ -849,10 +849,12 @@ __global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__
     bool topo = id18[(int64_t)(VK - 1) * n + p] >= 0;
     float m = 0;
     uint32_t hk[VK];  // a mix of each point's FP32 bits: equal points have equal keys
+    double nrm2[VK - 12];  // |n_q|^2 of points 12..17 (the inradius skip below)
 #pragma unroll
     for (int v = 0; v < VK; v++) {
         double x[3];
         dual_point(rel18, n, p, v, x);
+        if (v >= 12) nrm2[v - 12] = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
         // a neighbour at the centre has no bisector plane (its point is not
         // finite): the atom keeps its Euclidean order
         topo = topo && isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]);
@@ -896,11 +898,7 @@ __global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__
         double rin2 = -1.0;  // inradius bound of the 12-point hull
         for (int q = 4; q < VK && topo; q++) {
             if (q == 12) rin2 = vhull_inradius2(L, live);
-            if (q >= 12 && rin2 > 0) {
-                double pq[3];
-                dual_point(rel18, n, p, q, pq);
-                if ((pq[0] * pq[0] + pq[1] * pq[1]) + pq[2] * pq[2] < rin2) continue;  // strictly inside
-            }
+            if (q >= 12 && rin2 > 0 && nrm2[q - 12] < rin2) continue;  // strictly inside
             topo = vhull_insert(L, q, live);
         }
         // the centre strictly inside every facet
