@@ -929,6 +929,13 @@ __global__ void __launch_bounds__(VB) k_voronoi_order(int64_t n, const double *_
     for (int v = 0; v < VK; v++) key[v] = (uint32_t)v;
     const uint32_t live = vlive[p];
     if (live) {
+        // every load is issued before any is used (one wave per SIMD: no
+        // other wave hides a chain of round trips): all VF facet rows (each
+        // exists; dead slots are read and ignored) and the points
+        uint32_t fw[VF];
+#pragma unroll
+        for (int f = 0; f < VF; f++) fw[f] = vf[(int64_t)f * n + p];
+#pragma unroll
         for (int v = 0; v < VK; v++) {
             double x[3];
             dual_point(rel18, n, p, v, x);
@@ -939,9 +946,10 @@ __global__ void __launch_bounds__(VB) k_voronoi_order(int64_t n, const double *_
         // one facet at each vertex: 5-bit fields, 31 = not a vertex (a
         // vertex has at least three facets, so slot 31 is never needed)
         uint64_t at_lo = ~0ull, at_hi = ~0ull;
-        for (uint32_t mm = live; mm; mm &= mm - 1) {
-            const int f = __builtin_ctz(mm);
-            const uint32_t w = vf[(int64_t)f * n + p];
+#pragma unroll
+        for (int f = 0; f < VF; f++) {
+            if (!((live >> f) & 1)) continue;
+            const uint32_t w = fw[f];
             S.F[f][t] = w;
             if (f == 31) continue;
             for (int e = 0; e < 3; e++) {
