@@ -821,18 +821,34 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
 // hull.  -1 when the origin is not inside.
 __device__ inline double vhull_inradius2(const VLane &L, uint32_t live) {
     double r2 = INFINITY;
-    for (uint32_t m = live; m; m &= m - 1) {
-        const uint32_t w = L.S.F[__builtin_ctz(m)][L.t];
-        double a[3], b[3], c[3];
-        dual_point(L.rel18, L.n, L.p, vv(w, 0), a);
-        dual_point(L.rel18, L.n, L.p, vv(w, 1), b);
-        dual_point(L.rel18, L.n, L.p, vv(w, 2), c);
-        const double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
-        const double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
-        const double n0 = u1 * v2 - u2 * v1, n1 = u2 * v0 - u0 * v2, n2 = u0 * v1 - u1 * v0;
-        const double h = n0 * a[0] + n1 * a[1] + n2 * a[2];
-        if (!(h > 0)) return -1.0;  // the origin is not inside: no bound
-        r2 = fmin(r2, h * h / ((n0 * n0 + n1 * n1) + n2 * n2));
+    // four facets per step (the first one again where fewer are left), so
+    // that their 36 loads are in flight together
+    for (uint32_t m = live; m;) {
+        int f[4];
+        f[0] = __builtin_ctz(m);
+        m &= m - 1;
+#pragma unroll
+        for (int k = 1; k < 4; k++) {
+            f[k] = m ? __builtin_ctz(m) : f[0];
+            m &= m - 1;
+        }
+        double a[4][3], b[4][3], c[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t w = L.S.F[f[k]][L.t];
+            dual_point(L.rel18, L.n, L.p, vv(w, 0), a[k]);
+            dual_point(L.rel18, L.n, L.p, vv(w, 1), b[k]);
+            dual_point(L.rel18, L.n, L.p, vv(w, 2), c[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const double u0 = b[k][0] - a[k][0], u1 = b[k][1] - a[k][1], u2 = b[k][2] - a[k][2];
+            const double v0 = c[k][0] - a[k][0], v1 = c[k][1] - a[k][1], v2 = c[k][2] - a[k][2];
+            const double n0 = u1 * v2 - u2 * v1, n1 = u2 * v0 - u0 * v2, n2 = u0 * v1 - u1 * v0;
+            const double h = n0 * a[k][0] + n1 * a[k][1] + n2 * a[k][2];
+            if (!(h > 0)) return -1.0;  // the origin is not inside: no bound
+            r2 = fmin(r2, h * h / ((n0 * n0 + n1 * n1) + n2 * n2));
+        }
     }
     return r2 * (1.0 - 1e-6);
 }
