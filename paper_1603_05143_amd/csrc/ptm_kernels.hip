@@ -2121,21 +2121,43 @@ __device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t p,
     m1 = m2 = INFINITY;
     arg_grp = arg_c = -1;
     arg_q = -1;
-    // the atom's ranges in group order, candidates in table order inside each
+    int64_t q0[NGRP], q1[NGRP];
+#pragma unroll
     for (int g = 0; g < NGRP; g++) {
-        const int64_t q1 = off[pidx(p, g) + 1];
-        for (int64_t q = off[pidx(p, g)]; q < q1; q++) {
-            double r = rr[q];
-            if (r < m1) {
-                m2 = m1;
-                m1 = r;
-                arg_grp = pairs[q].y >> 28;
-                arg_c = pairs[q].y & 0x0FFFFFFF;
-                arg_q = q;
-            } else if (r < m2) {
-                m2 = r;
-            }
+        q0[g] = off[pidx(p, g)];
+        q1[g] = off[pidx(p, g) + 1];
+    }
+    // the first two pairs of every group load together (most atoms have no
+    // more); further pairs, rare, are read one by one.  The visiting order
+    // (group, then pair) and the strict comparisons are those of a plain
+    // scan, so ties go to the earlier pair as before.
+    double r2[NGRP][2];
+    uint32_t y2[NGRP][2];
+#pragma unroll
+    for (int g = 0; g < NGRP; g++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const bool in = q0[g] + j < q1[g];
+            r2[g][j] = in ? rr[q0[g] + j] : INFINITY;
+            y2[g][j] = in ? pairs[q0[g] + j].y : 0u;
         }
+    auto visit = [&](double r, uint32_t y, int64_t q) {
+        if (r < m1) {
+            m2 = m1;
+            m1 = r;
+            arg_grp = (int)(y >> 28);
+            arg_c = (int)(y & 0x0FFFFFFF);
+            arg_q = q;
+        } else if (r < m2) {
+            m2 = r;
+        }
+    };
+#pragma unroll
+    for (int g = 0; g < NGRP; g++) {
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+            if (q0[g] + j < q1[g]) visit(r2[g][j], y2[g][j], q0[g] + j);
+        for (int64_t q = q0[g] + 2; q < q1[g]; q++) visit(rr[q], pairs[q].y, q);
     }
 }
 
