@@ -2301,9 +2301,20 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
                 tmpl = cd.tmpl;
                 CandEval<double> ev;
                 const TemplateDev &D = M.tpl[cd.tmpl];
-                if (g == 0) eval_streamed<6, double>(nbr_rel, n, p, D, tv_of_rank(cd.perm, ord[0], 6), ev);
-                else if (g == 1) eval_streamed<12, double>(nbr_rel, n, p, D, tv_of_rank(cd.perm, ord[1], 12), ev);
-                else eval_streamed<14, double>(nbr_rel, n, p, D, tv_of_rank(cd.perm, ord[2], 14), ev);
+                // every point loaded at once: a wave per atom, few atoms, so
+                // nothing else hides the round trips (the same arithmetic as
+                // the winner's evaluation in finish)
+                double a[NMAX][3], Ga;
+                if (g == 0) {
+                    load_centred<6, double, true>(nbr_rel, n, p, a, Ga);
+                    eval_candidate<6, double>(a, Ga, D, tv_of_rank(cd.perm, ord[0], 6), ev);
+                } else if (g == 1) {
+                    load_centred<12, double, true>(nbr_rel, n, p, a, Ga);
+                    eval_candidate<12, double>(a, Ga, D, tv_of_rank(cd.perm, ord[1], 12), ev);
+                } else {
+                    load_centred<14, double, true>(nbr_rel, n, p, a, Ga);
+                    eval_candidate<14, double>(a, Ga, D, tv_of_rank(cd.perm, ord[2], 14), ev);
+                }
                 r = ev.r;
             }
         }
