@@ -1861,22 +1861,21 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
 // Winner outputs with the superposition recomputed from the points.
 template <int K, typename RT>
 __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
-                              const double *__restrict__ nbr_rel, double cutoff, int64_t p, int64_t n, int32_t i,
-                              const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
-                              const MatchOut &O) {
+                              const CandEval<RT> &ev, const double *__restrict__ nbr_rel, double cutoff, int64_t p,
+                              int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
+                              const int8_t *__restrict__ species, const MatchOut &O) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
     Candidate cd = T.cand[grp][c];
     const TemplateDev &D = M.tpl[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
-    CandEval<RT> ev;
     RT l = 0, resid = 0;
     RT At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     {
         RT a[NMAX][3], Ga;
+        // ev: the winner's superposition, already evaluated from these points
         load_centred<K, RT>(nbr_rel, n, p, a, Ga);
-        eval_candidate<K, RT>(a, Ga, D, tv, ev);
         for (int r = 0; r <= K; r++) l += sqrt(a[r][0] * a[r][0] + a[r][1] * a[r][1] + a[r][2] * a[r][2]);
         l /= RT(K + 1);
         for (int x = 0; x < 3; x++)
@@ -2295,15 +2294,15 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
             }
         }
         Candidate cd = {0, 0, 0};
+        CandEval<double> ev = {0, 0, {0, 0, 0, 0}};
         if (g >= 0) {
             cd = T.cand[g][c];
             if ((mask >> cd.tmpl) & 1) {
                 tmpl = cd.tmpl;
-                CandEval<double> ev;
                 const TemplateDev &D = M.tpl[cd.tmpl];
                 // every point loaded at once: a wave per atom, few atoms, so
-                // nothing else hides the round trips (the same arithmetic as
-                // the winner's evaluation in finish)
+                // nothing else hides the round trips (the winner's evaluation
+                // is handed to finish)
                 double a[NMAX][3], Ga;
                 if (g == 0) {
                     load_centred<6, double, true>(nbr_rel, n, p, a, Ga);
@@ -2346,10 +2345,16 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
             }
         }
         const int wg = __shfl(g, bl), wc = __shfl(c, bl);
+        // the winning lane's superposition, handed to the finishing lane
+        CandEval<double> we;
+        we.r = __shfl(ev.r, bl);
+        we.s = __shfl(ev.s, bl);
+        for (int k = 0; k < 4; k++) we.q[k] = __shfl(ev.q[k], bl);
         if (lane == 0) {
-            if (wg == 0) finish<6, double>(M, T, 0, wc, ord[0], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else if (wg == 1) finish<12, double>(M, T, 1, wc, ord[1], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else finish<14, double>(M, T, 2, wc, ord[2], nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            if (wg == 0) finish<6, double>(M, T, 0, wc, ord[0], we, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else if (wg == 1)
+                finish<12, double>(M, T, 1, wc, ord[1], we, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            else finish<14, double>(M, T, 2, wc, ord[2], we, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
         }
     }
 }
