@@ -2478,8 +2478,44 @@ __global__ void __launch_bounds__(256) k_misorientation(int64_t n, TablesView T,
             G[gbase[t] + h] = make_double4(g[0], g[1], g[2], g[3]);
         }
     __syncthreads();
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    // Waves of mixed types would each scan the largest group among their
+    // lanes (60 for ICO).  The block's pairs are regrouped by type first
+    // (wave ballots give each lane its slot) and every lane takes the pair
+    // in its slot: waves then mostly scan one group, and its LDS words are
+    // broadcasts.  Out-of-range types form a class of their own.
+    constexpr int NCLS = NT + 2;  // types 0..NT, then invalid
+    __shared__ int32_t s_cnt[4][NCLS];
+    __shared__ int64_t s_i[256];
+    {
+        const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+        int cls = -1;
+        if (i0 < n) {
+            const int t0 = type[i0];
+            cls = (t0 < 0 || t0 > NT) ? NT + 1 : t0;
+        }
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        uint64_t bal[NCLS];
+#pragma unroll
+        for (int k = 0; k < NCLS; k++) bal[k] = __ballot(cls == k);
+        if (lane == 0)
+            for (int k = 0; k < NCLS; k++) s_cnt[wv][k] = __popcll(bal[k]);
+        __syncthreads();
+        int total = 0, slot = 0;
+#pragma unroll
+        for (int k = 0; k < NCLS; k++) {
+            int before = 0, tk = 0;
+            for (int w2 = 0; w2 < 4; w2++) {
+                tk += s_cnt[w2][k];
+                if (w2 < wv) before += s_cnt[w2][k];
+            }
+            if (k == cls) slot = total + before + __popcll(bal[k] & ((1ull << lane) - 1));
+            total += tk;
+        }
+        if (cls >= 0) s_i[slot] = i0;
+        __syncthreads();
+        if ((int)threadIdx.x >= total) return;
+    }
+    const int64_t i = s_i[threadIdx.x];
     const int ty = type[i];
     double a0, a1, a2, a3, b0, b1, b2, b3;
     if (Vec) {  // 16-byte aligned quaternion arrays

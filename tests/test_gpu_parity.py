@@ -304,6 +304,17 @@ def test_misorientation(torch_cuda, oracle_lib):
         bad = torch.tensor([7], dtype=torch.int8, device="cuda:0")
         st = ptm.ptm_misorientation(ctx, bad.data_ptr(), dq1.data_ptr(), dq2.data_ptr(), 1, da.data_ptr())
         assert st == ptm.PTM_OK and np.isnan(da[0].item())
+        # out-of-range types among valid ones (device arrays are not checked
+        # on the host): NaN there, every other angle unchanged
+        mixed = types.copy()
+        mixed[3::7] = 7
+        mixed[5::11] = -2
+        dm = torch.from_numpy(mixed).to("cuda:0")
+        st = ptm.ptm_misorientation(ctx, dm.data_ptr(), dq1.data_ptr(), dq2.data_ptr(), n, da.data_ptr())
+        assert st == ptm.PTM_OK
+        gm = da.cpu().numpy()
+        inv = (mixed < 0) | (mixed > 5)
+        assert np.all(np.isnan(gm[inv])) and np.array_equal(gm[~inv], got[~inv])
     finally:
         ptm.ptm_destroy(ctx)
     hctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, ptm.PTM_F_HOST_POINTERS)
