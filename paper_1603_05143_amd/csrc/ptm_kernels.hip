@@ -1327,21 +1327,29 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
         // most significant field
         uint64_t seq = 0;
         int w = v0;
-        for (int j = 0; j < mindeg; j++) {
-            seq |= (uint64_t)nib(degs, w) << (56 - 4 * j);
-            w = (int)nib(ntu, w);
-        }
-        int v = v0;
-        for (int r = 0; r < mindeg; r++, v = (int)nib(ntu, v)) {
-            uint64_t sig = ((uint64_t)mindeg << 60) | seq;
-            if (sig < minsig) {
-                minsig = sig;
-                bu = u;
-                bv = v;
+        // the minimum degree of a triangulated sphere is 3, 4 or 5 (the
+        // mean is below 6), so the loops are unrolled to five predicated
+        // steps instead of a loop whose count differs between lanes
+#pragma unroll
+        for (int j = 0; j < 5; j++)
+            if (j < mindeg) {
+                seq |= (uint64_t)nib(degs, w) << (56 - 4 * j);
+                w = (int)nib(ntu, w);
             }
-            // next start: rotate the sequence by one neighbour
-            seq = ((seq << 4) & field) | ((seq >> 56) << low);
-        }
+        int v = v0;
+#pragma unroll
+        for (int r = 0; r < 5; r++)
+            if (r < mindeg) {
+                uint64_t sig = ((uint64_t)mindeg << 60) | seq;
+                if (sig < minsig) {
+                    minsig = sig;
+                    bu = u;
+                    bv = v;
+                }
+                // next start: rotate the sequence by one neighbour
+                seq = ((seq << 4) & field) | ((seq >> 56) << low);
+                v = (int)nib(ntu, v);
+            }
     }
     code[0] = minsig;
     uint64_t ntu = NT.get(bu);
