@@ -123,6 +123,28 @@ def test_mixed_periodic_open_axes(torch_cuda, clf, oracle_lib):
     compare(got, ref)
 
 
+@pytest.mark.parametrize("n", [1023, 1024, 1025, 2049])
+def test_pair_tile_boundaries(torch_cuda, clf, oracle_lib, n):
+    """Frames whose atom counts end just before, on and after a multiple of
+    the candidate pair list's 1024-atom tile, against the oracle atom by
+    atom: a perturbed FCC crystal of 8 x 8 x 4 cells (1024 sites) with sites
+    removed or interstitials added, and of 8 x 8 x 8 cells for 2049."""
+    rng = np.random.default_rng(n)
+    reps = (8, 8, 8) if n > 1025 else (8, 8, 4)
+    f = S.perfect_crystal("fcc", reps, a=3.615)
+    pos = f.positions + rng.normal(scale=0.08, size=f.positions.shape)
+    if n < len(pos):
+        pos = np.delete(pos, rng.choice(len(pos), len(pos) - n, replace=False), axis=0)
+    while len(pos) < n:  # an interstitial at an octahedral site
+        c = rng.integers(0, np.array(reps)) * 3.615 + 0.5 * 3.615
+        pos = np.vstack([pos, c[None, :]])
+    g = S.Frame(positions=S.wrap(pos, f.box), box=f.box)
+    assert g.n == n
+    got = run_gpu(torch_cuda, clf, g)
+    ref = run_ref(oracle_lib, g)
+    compare(got, ref)
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 13, 15])
 def test_tiny_systems(torch_cuda, clf, oracle_lib, n):
     rng = np.random.default_rng(n)
