@@ -27,6 +27,16 @@ TEMPLATES = ("SC", "FCC", "HCP", "ICO", "BCC")
 TEMPLATE_K = (6, 12, 12, 12, 14)
 MASK_ALL = 0x1F
 ORDER_TOPOLOGICAL = 0x100  # mask bit of the C oracle: topological neighbour ordering (Sec. 3)
+KNN_FORCE_GRID = 0x200     # mask bit: certified cell search whatever the frame size
+KNN_FORCE_BRUTE = 0x400    # mask bit: brute-force neighbours whatever the frame size
+BRUTE_MAX = 200000         # frames above this size use the cell search by default
+
+
+class BoxError(ValueError):
+    """A periodic box too short for the neighbour shell: some atom's K-th
+    minimum-image neighbour (K = 14, or 18 for the topological ordering) is
+    not strictly closer than half a periodic box length, so other periodic
+    images could belong to its shell (Sec. 5 periodic samples)."""
 
 
 def build(force: bool = True) -> str:
@@ -63,6 +73,13 @@ def lib():
         L.ptm_oracle_template_code.argtypes = [C.c_int, C.c_int, p, p]
         L.ptm_oracle_superpose.argtypes = [C.c_int, p, p, p, p, p, p]
         L.ptm_oracle_knn.argtypes = [p, C.c_int64, p, C.c_int64, C.c_int, p, p, p]
+        L.ptm_oracle_neighbours.restype = C.c_int
+        L.ptm_oracle_neighbours.argtypes = [p, p, C.c_int64, p, C.c_int64, C.c_int, C.c_int, C.c_int, p, p, p, p]
+        L.ptm_oracle_classify_given.restype = C.c_int
+        L.ptm_oracle_classify_given.argtypes = [p, p, C.c_uint32, C.c_double, p, C.c_int64, p, p, p, p, C.c_int,
+                                                p, p, p, p, p, p, p, p]
+        L.ptm_oracle_strain.restype = C.c_int
+        L.ptm_oracle_strain.argtypes = [C.c_int, p, p]
         _lib = L
     return _lib
 
@@ -72,17 +89,22 @@ def _ptr(a):
 
 
 def classify(positions, box, species=None, mask=MASK_ALL, cutoff=float("inf"), atoms=None,
-             threads=None, counters=False, ordering="euclidean"):
+             threads=None, counters=False, ordering="euclidean", knn_search="auto", allow_box=False):
     """Classify atoms (all, or the indices in ``atoms``).  Returns a dict of
     numpy arrays: type, alloy, rmsd, scale, quat (w,x,y,z), neighbours
     (template-vertex order), strain (3x3 row-major P), knn (distance order),
     margin, ncand, tmargin (topological ordering: distance of the nearest
-    area grid value to a rounding boundary); plus ``counters`` when
-    requested.  ``ordering``: "euclidean" or "topological" (Sec. 3)."""
+    area grid value to a rounding boundary), box_ok; plus ``counters`` when
+    requested.  ``ordering``: "euclidean" or "topological" (Sec. 3).
+    ``knn_search``: "auto" (brute force up to BRUTE_MAX atoms, else the
+    certified cell search), "grid" or "brute".  A periodic frame whose box
+    is too short for some listed atom's neighbour shell raises BoxError
+    unless ``allow_box`` (then ``box_ok`` is False)."""
     if ordering not in ("euclidean", "topological"):
         raise ValueError(ordering)
     if ordering == "topological":
         mask = mask | ORDER_TOPOLOGICAL
+    mask |= {"auto": 0, "grid": KNN_FORCE_GRID, "brute": KNN_FORCE_BRUTE}[knn_search]
     pos = np.ascontiguousarray(positions, dtype=np.float64)
     n = pos.shape[0]
     bx = np.ascontiguousarray(box, dtype=np.float64)
@@ -98,18 +120,87 @@ def classify(positions, box, species=None, mask=MASK_ALL, cutoff=float("inf"), a
     }
     cnt = np.zeros(5, np.int64)
     if threads is None:
-        threads = min(os.cpu_count() or 1, 16)
+        threads = default_threads()
     rc = lib().ptm_oracle_classify(_ptr(pos), _ptr(spc), _ptr(bx), n, mask, cutoff, _ptr(sel),
                                    m, threads, _ptr(out["type"]), _ptr(out["alloy"]),
                                    _ptr(out["rmsd"]), _ptr(out["scale"]), _ptr(out["quat"]),
                                    _ptr(out["neighbours"]), _ptr(out["strain"]), _ptr(out["knn"]),
                                    _ptr(out["margin"]), _ptr(out["ncand"]), _ptr(out["tmargin"]), _ptr(cnt))
-    if rc != 0:
+    if rc == 1:
         raise RuntimeError("oracle initialisation failed")
+    if rc == 2 and not allow_box:
+        raise BoxError("periodic box shorter than twice the neighbour shell")
+    out["box_ok"] = rc == 0
     if counters:
         out["counters"] = dict(zip(("hulls", "codes", "candidates", "orient_tests", "orient_exact"),
                                    cnt.tolist()))
     return out
+
+
+def default_threads() -> int:
+    """Threads for the oracle: the CPUs this process may run on, at most 16
+    (the host share of one GPU on the machines the GPU tests run on)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def neighbours(positions, box, atoms=None, K=14, knn_search="auto", threads=None):
+    """The neighbour search alone (Sec. 3 Euclidean order) for the atoms in
+    ``atoms`` (or all): (ids[m][K], rel[m][K][3], d2[m][K], cnt[m], box_ok)."""
+    pos = np.ascontiguousarray(positions, dtype=np.float64)
+    n = pos.shape[0]
+    bx = np.ascontiguousarray(box, dtype=np.float64)
+    sel = None if atoms is None else np.ascontiguousarray(atoms, dtype=np.int64)
+    m = n if sel is None else len(sel)
+    ids = np.full((m, K), -1, np.int32)
+    rel = np.zeros((m, K, 3))
+    d2 = np.zeros((m, K))
+    cnt = np.zeros(m, np.int32)
+    force = {"auto": 0, "grid": 1, "brute": 2}[knn_search]
+    rc = lib().ptm_oracle_neighbours(_ptr(pos), _ptr(bx), n, _ptr(sel), m, K, force,
+                                     threads or default_threads(), _ptr(ids), _ptr(rel), _ptr(d2), _ptr(cnt))
+    if rc == 1:
+        raise RuntimeError("oracle neighbour search failed")
+    return ids, rel, d2, cnt, rc == 0
+
+
+def classify_given(nbrs, atoms, box, species=None, mask=MASK_ALL, cutoff=float("inf"), threads=None,
+                   ordering="euclidean"):
+    """classify() with the neighbours already found by neighbours() for the
+    same atoms: the classification alone (the paper's timing excludes
+    neighbour-list generation, Table 2)."""
+    ids, rel, d2, cnt, _ = nbrs
+    if ordering == "topological":
+        mask = mask | ORDER_TOPOLOGICAL
+    sel = np.ascontiguousarray(atoms, dtype=np.int64)
+    m = len(sel)
+    bx = np.ascontiguousarray(box, dtype=np.float64)
+    spc = None if species is None else np.ascontiguousarray(species, dtype=np.int8)
+    out = {"type": np.zeros(m, np.int8), "alloy": np.zeros(m, np.int8), "rmsd": np.zeros(m),
+           "scale": np.zeros(m), "quat": np.zeros((m, 4)), "neighbours": np.zeros((m, 14), np.int32),
+           "strain": np.zeros((m, 9)), "knn": np.zeros((m, 14), np.int32)}
+    rc = lib().ptm_oracle_classify_given(_ptr(spc), _ptr(bx), mask, cutoff, _ptr(sel), m, _ptr(ids), _ptr(rel),
+                                         _ptr(d2), _ptr(cnt), threads or default_threads(), _ptr(out["type"]),
+                                         _ptr(out["alloy"]), _ptr(out["rmsd"]), _ptr(out["scale"]),
+                                         _ptr(out["quat"]), _ptr(out["neighbours"]), _ptr(out["strain"]),
+                                         _ptr(out["knn"]))
+    if rc == 1:
+        raise RuntimeError("oracle initialisation failed")
+    out["box_ok"] = rc == 0
+    return out
+
+
+def strain(t: int, obs):
+    """Sec. 8 strain P (3x3) of template t for the k+1 observed points in
+    template-vertex order, centre first."""
+    o = np.ascontiguousarray(obs, dtype=np.float64)
+    P = np.zeros(9)
+    if lib().ptm_oracle_strain(t, _ptr(o), _ptr(P)) != 0:
+        raise ValueError(t)
+    return P.reshape(3, 3)
 
 
 def orient(p4, idx=None, sos=True) -> int:

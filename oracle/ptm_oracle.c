@@ -1015,6 +1015,210 @@ static int knn_brute(const double *pos, int64_t n, const double box[3], int64_t 
     return cnt;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Certified cell search for large frames: the same (d^2, index) order as
+ * knn_brute, found by scanning growing blocks of cells.  Each block is
+ * rescanned from scratch (no incremental bookkeeping); it is accepted once
+ * the K-th distance found is strictly shorter than the distance from the
+ * atom to the nearest cell that the block leaves out, so no atom outside can
+ * equal or beat it.  An atom outside the block on a periodic axis has its
+ * minimum image outside the block's slab on that axis, so the same bound
+ * holds for it.                                                             */
+typedef struct {
+    int nc[3], periodic[3];
+    double lo[3], h[3], L[3];
+    int64_t ncell;
+    int64_t *first; /* [ncell + 1] start of each cell in idx */
+    int64_t *idx;   /* atom indices grouped by cell           */
+} cellgrid_t;
+
+static int cell_index_1d(const cellgrid_t *G, int a, double x) {
+    double u = G->periodic[a] ? x - G->L[a] * floor(x / G->L[a]) : x - G->lo[a];
+    double c = floor(u / G->h[a]);
+    if (c < 0) c = 0;
+    if (c > G->nc[a] - 1) c = G->nc[a] - 1;
+    return (int)c;
+}
+
+static int cellgrid_build(cellgrid_t *G, const double *pos, int64_t n, const double box[3]) {
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            if (pos[3 * i + a] < mn[a]) mn[a] = pos[3 * i + a];
+            if (pos[3 * i + a] > mx[a]) mx[a] = pos[3 * i + a];
+        }
+    double ext[3], vol = 1.0;
+    for (int a = 0; a < 3; a++) {
+        G->periodic[a] = box[a] > 0;
+        G->L[a] = box[a];
+        ext[a] = G->periodic[a] ? box[a] : mx[a] - mn[a];
+        G->lo[a] = G->periodic[a] ? 0.0 : mn[a];
+        vol *= ext[a] > 1.0 ? ext[a] : 1.0;
+    }
+    /* about four atoms per cell at the frame's mean density */
+    double h0 = cbrt(4.0 * vol / (double)n);
+    G->ncell = 1;
+    for (int a = 0; a < 3; a++) {
+        double c = floor(ext[a] / h0);
+        if (c < 1) c = 1;
+        if (c > 4096) c = 4096;
+        G->nc[a] = (int)c;
+        G->h[a] = ext[a] > 0 ? ext[a] / c : 1.0;
+        G->ncell *= G->nc[a];
+    }
+    G->first = (int64_t *)calloc((size_t)G->ncell + 1, sizeof(int64_t));
+    G->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!G->first || !G->idx || !cell) {
+        free(G->first);
+        free(G->idx);
+        free(cell);
+        return 0;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        int c0 = cell_index_1d(G, 0, pos[3 * i]), c1 = cell_index_1d(G, 1, pos[3 * i + 1]),
+            c2 = cell_index_1d(G, 2, pos[3 * i + 2]);
+        cell[i] = ((int64_t)c2 * G->nc[1] + c1) * G->nc[0] + c0;
+        G->first[cell[i] + 1]++;
+    }
+    for (int64_t c = 0; c < G->ncell; c++) G->first[c + 1] += G->first[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)G->ncell);
+    if (!fill) {
+        free(G->first);
+        free(G->idx);
+        free(cell);
+        return 0;
+    }
+    memcpy(fill, G->first, sizeof(int64_t) * (size_t)G->ncell);
+    for (int64_t i = 0; i < n; i++) G->idx[fill[cell[i]]++] = i;
+    free(fill);
+    free(cell);
+    return 1;
+}
+
+static void cellgrid_free(cellgrid_t *G) {
+    free(G->first);
+    free(G->idx);
+    G->first = NULL;
+    G->idx = NULL;
+}
+
+static int knn_grid(const cellgrid_t *G, const double *pos, const double box[3], int64_t i, int K,
+                    int32_t *ids, double (*rel)[3], double *d2out) {
+    double inv[3];
+    for (int d = 0; d < 3; d++) inv[d] = box[d] > 0 ? 1.0 / box[d] : 0.0;
+    int home[3];
+    double u[3];
+    for (int a = 0; a < 3; a++) {
+        home[a] = cell_index_1d(G, a, pos[3 * i + a]);
+        u[a] = G->periodic[a] ? pos[3 * i + a] - G->L[a] * floor(pos[3 * i + a] / G->L[a])
+                              : pos[3 * i + a] - G->lo[a];
+    }
+    for (int s = 1;; s++) {
+        /* cells of the block on each axis: [home - s, home + s], clipped to
+         * the grid on open axes and taken modulo nc (each cell once) on
+         * periodic ones; whole = the axis is covered completely */
+        int lo[3], hi[3], whole[3], all = 1;
+        for (int a = 0; a < 3; a++) {
+            if (G->periodic[a]) {
+                whole[a] = 2 * s + 1 >= G->nc[a];
+                lo[a] = whole[a] ? 0 : home[a] - s;
+                hi[a] = whole[a] ? G->nc[a] - 1 : home[a] + s;
+            } else {
+                lo[a] = home[a] - s < 0 ? 0 : home[a] - s;
+                hi[a] = home[a] + s > G->nc[a] - 1 ? G->nc[a] - 1 : home[a] + s;
+                whole[a] = lo[a] == 0 && hi[a] == G->nc[a] - 1;
+            }
+            all = all && whole[a];
+        }
+        int cnt = 0;
+        double kd2[TOPO_K + 1];
+        int32_t kid[TOPO_K + 1];
+        double kr[TOPO_K + 1][3];
+        for (int cz = lo[2]; cz <= hi[2]; cz++)
+            for (int cy = lo[1]; cy <= hi[1]; cy++)
+                for (int cx = lo[0]; cx <= hi[0]; cx++) {
+                    int wc[3] = {cx, cy, cz};
+                    for (int a = 0; a < 3; a++)
+                        if (G->periodic[a]) wc[a] = ((wc[a] % G->nc[a]) + G->nc[a]) % G->nc[a];
+                    int64_t c = ((int64_t)wc[2] * G->nc[1] + wc[1]) * G->nc[0] + wc[0];
+                    for (int64_t t = G->first[c]; t < G->first[c + 1]; t++) {
+                        int64_t j = G->idx[t];
+                        if (j == i) continue;
+                        double v[3];
+                        for (int d = 0; d < 3; d++) {
+                            double x = pos[3 * j + d] - pos[3 * i + d];
+                            if (box[d] > 0) {
+                                double sh = rint(x * inv[d]);
+                                x = x - sh * box[d];
+                            }
+                            v[d] = x;
+                        }
+                        double xx = v[0] * v[0], yy = v[1] * v[1], zz = v[2] * v[2];
+                        double dd = (xx + yy) + zz;
+                        if (cnt == K && !(dd < kd2[K - 1] || (dd == kd2[K - 1] && j < kid[K - 1]))) continue;
+                        int p = (cnt < K) ? cnt++ : K - 1;
+                        while (p > 0 && (dd < kd2[p - 1] || (dd == kd2[p - 1] && j < kid[p - 1]))) {
+                            kd2[p] = kd2[p - 1];
+                            kid[p] = kid[p - 1];
+                            memcpy(kr[p], kr[p - 1], sizeof kr[p]);
+                            p--;
+                        }
+                        kd2[p] = dd;
+                        kid[p] = (int32_t)j;
+                        memcpy(kr[p], v, sizeof v);
+                    }
+                }
+        int done = all;
+        if (!done && cnt == K) {
+            /* distance to the nearest cell outside the block (axes not
+             * covered completely), less a margin for the rounding of the
+             * cell assignment */
+            double gap = INFINITY;
+            for (int a = 0; a < 3; a++) {
+                if (whole[a]) continue;
+                double below = u[a] - (double)lo[a] * G->h[a];
+                double above = (double)(hi[a] + 1) * G->h[a] - u[a];
+                if (G->periodic[a] || lo[a] > 0)
+                    if (below < gap) gap = below;
+                if (G->periodic[a] || hi[a] < G->nc[a] - 1)
+                    if (above < gap) gap = above;
+            }
+            gap -= 1e-9 * (G->h[0] + G->h[1] + G->h[2]);
+            done = gap > 0 && kd2[K - 1] < gap * gap;
+        }
+        if (done) {
+            for (int r = 0; r < cnt; r++) {
+                ids[r] = kid[r];
+                memcpy(rel[r], kr[r], sizeof kr[r]);
+                if (d2out) d2out[r] = kd2[r];
+            }
+            return cnt;
+        }
+    }
+}
+
+/* Frames above this size search neighbours with the cell grid. */
+#define BRUTE_MAX 200000
+
+/* Sec. 5 samples are periodic.  A periodic axis of length L holds every
+ * image of an atom other than the minimum one at least L/2 away, so the
+ * minimum-image neighbours are the neighbours of the periodic crystal only
+ * when the K-th of them lies strictly closer than L/2 on every periodic
+ * axis.  Returns 1 when that holds for this atom (always on open frames).
+ * Reading: the comparison is made as 4 d^2 < L*L in FP64, with d^2 from the
+ * distance formula above; an atom with fewer than K neighbours in a frame
+ * with a periodic axis fails. */
+static int box_holds_shell(const double box[3], int nn, int K, const double *d2) {
+    int any = 0;
+    for (int a = 0; a < 3; a++) any |= box[a] > 0;
+    if (!any) return 1;
+    if (nn < K) return 0;
+    for (int a = 0; a < 3; a++)
+        if (box[a] > 0 && !(4.0 * d2[K - 1] < box[a] * box[a])) return 0;
+    return 1;
+}
+
 /* ======================================================================== */
 /* topological neighbour ordering (Sec. 3)                                   */
 /* ======================================================================== */
@@ -1178,6 +1382,46 @@ static void topological_order(int32_t *ids, double (*rel)[3], double *area_out, 
     memcpy(rel, rel2, sizeof rel2);
 }
 
+/* Sec. 8.  obs: the N = k+1 observed points in template-vertex order, the
+ * centre first.  eq.(6): A^T = V+ W', W' = obs centred and divided by its
+ * own mean distance l(.) (eq. 4), V+ the pseudoinverse of the normalised
+ * template; then the left polar decomposition A = P U with U orthogonal and
+ * right-handed.  A A^T = X S^2 X^T (Jacobi), so P = X diag(+-s_i) X^T with
+ * U = P^-1 A; U is right-handed iff det P has the sign of det A.  Reading:
+ * for det A < 0 the sign goes to the smallest s_i (the U that stays closest
+ * to A), and P is then not positive definite.  Writes P row-major. */
+static void strain_of(const templ_t *T, const double (*obs)[3], double P[9]) {
+    const int k = T->k;
+    double wn[NMAX][3];
+    normalise_points(k + 1, obs, wn);
+    double At[3][3] = {{0}};
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            for (int m = 0; m < k + 1; m++) At[r][c] += T->vpinv[r][m] * wn[m][c];
+    double detA = At[0][0] * (At[1][1] * At[2][2] - At[1][2] * At[2][1]) -
+                  At[0][1] * (At[1][0] * At[2][2] - At[1][2] * At[2][0]) +
+                  At[0][2] * (At[1][0] * At[2][1] - At[1][1] * At[2][0]);
+    double AAt[4][4] = {{0}};
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            for (int m = 0; m < 3; m++) AAt[r][c] += At[m][r] * At[m][c];
+    double ev[4], V[4][4];
+    jacobi_eigen(3, AAt, ev, V);
+    double sv[3];
+    int smallest = 0;
+    for (int m = 0; m < 3; m++) {
+        sv[m] = sqrt(ev[m] > 0 ? ev[m] : 0.0);
+        if (ev[m] < ev[smallest]) smallest = m;
+    }
+    if (detA < 0) sv[smallest] = -sv[smallest];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double s = 0;
+            for (int m = 0; m < 3; m++) s += V[r][m] * sv[m] * V[c][m];
+            P[r * 3 + c] = s;
+        }
+}
+
 /* lexicographically smallest rank vector over the template's rotation group
  * (the orientation representative); returns the group element used */
 static int representative(int t, const int *c, int *out) {
@@ -1202,12 +1446,16 @@ typedef struct {
     int32_t ncand;
 } atom_out_t;
 
-static void classify_atom(const double *pos, const int8_t *species, const double box[3], int64_t n,
-                          int64_t i, uint32_t mask, double cutoff, atom_out_t *o, counters_t *cnt) {
+/* Alg. 1 for atom i given its neighbours in Euclidean order (ids_in,
+ * rel_in: nn_in <= TOPO_K entries, as found by knn_brute / knn_grid). */
+static void classify_atom(const int8_t *species, int64_t i, uint32_t mask, double cutoff, const int32_t *ids_in,
+                          const double (*rel_in)[3], int nn_in, atom_out_t *o, counters_t *cnt) {
     int32_t ids[TOPO_K];
     double rel[TOPO_K][3];
     const int topo = (mask & ORDER_TOPOLOGICAL) != 0;
-    int nn = knn_brute(pos, n, box, i, topo ? TOPO_K : KMAX, ids, rel, NULL);
+    int nn = nn_in;
+    memcpy(ids, ids_in, sizeof(int32_t) * (size_t)nn);
+    memcpy(rel, rel_in, sizeof(double) * 3 * (size_t)nn);
     for (int r = 0; r < KMAX; r++) o->knn[r] = r < nn ? ids[r] : -1;
     o->tmargin = INFINITY;
     if (topo && nn == TOPO_K) { /* fewer than 18 neighbours: Euclidean order */
@@ -1335,29 +1583,12 @@ static void classify_atom(const double *pos, const int8_t *species, const double
     rot_to_quat(Rn, o->quat);
     quat_canonical_sign(o->quat);
 
-    /* eq.(6): A^T = V+ W', W' = observed points in template order, centred
-     * and normalised by their own mean distance; P = (A A^T)^(1/2)        */
+    /* eq.(6) and Sec. 8: the symmetric factor of the deformation gradient */
     {
-        double obs[NMAX][3], wn[NMAX][3];
+        double obs[NMAX][3];
         memset(obs[0], 0, sizeof obs[0]);
         for (int j = 0; j < k; j++) memcpy(obs[j + 1], rel[W->c[j]], sizeof obs[0]);
-        normalise_points(k + 1, (const double(*)[3])obs, wn);
-        double At[3][3] = {{0}};
-        for (int r = 0; r < 3; r++)
-            for (int c = 0; c < 3; c++)
-                for (int m = 0; m < k + 1; m++) At[r][c] += T->vpinv[r][m] * wn[m][c];
-        double AAt[4][4] = {{0}};
-        for (int r = 0; r < 3; r++)
-            for (int c = 0; c < 3; c++)
-                for (int m = 0; m < 3; m++) AAt[r][c] += At[m][r] * At[m][c];
-        double ev[4], V[4][4];
-        jacobi_eigen(3, AAt, ev, V);
-        for (int r = 0; r < 3; r++)
-            for (int c = 0; c < 3; c++) {
-                double s = 0;
-                for (int m = 0; m < 3; m++) s += V[r][m] * sqrt(ev[m] > 0 ? ev[m] : 0.0) * V[c][m];
-                o->strain[r * 3 + c] = s;
-            }
+        strain_of(T, (const double(*)[3])obs, o->strain);
     }
     /* alloy type (Sec. 6, Table 3) for FCC and BCC matches within cut-off */
     if (species && o->type) {
@@ -1394,6 +1625,9 @@ static void classify_atom(const double *pos, const int8_t *species, const double
 /* ======================================================================== */
 /* exported entry points (ctypes)                                           */
 /* ======================================================================== */
+#define KNN_FORCE_GRID 0x200u  /* mask bit: cell search whatever the frame size (tests)  */
+#define KNN_FORCE_BRUTE 0x400u /* mask bit: brute force whatever the frame size (tests) */
+
 typedef struct {
     const double *pos;
     const int8_t *species;
@@ -1403,20 +1637,53 @@ typedef struct {
     int64_t nsel;
     uint32_t mask;
     double cutoff;
+    const cellgrid_t *grid; /* NULL: brute-force neighbours */
+    /* neighbours given by the caller (ptm_oracle_classify_given), else NULL */
+    const int32_t *g_ids, *g_cnt;
+    const double *g_rel, *g_d2;
+    int K;                  /* neighbours per atom: 14, or 18 (topological) */
     int8_t *type, *alloy;
     double *rmsd, *scale, *quat, *strain, *margin, *tmargin;
     int32_t *nbr, *knn, *ncand;
+    /* ptm_oracle_neighbours: outputs of the neighbour search alone */
+    int32_t *o_ids, *o_cnt;
+    double *o_rel, *o_d2;
     int64_t lo, hi;
+    int box_fail;
     counters_t cnt;
 } job_t;
 
 static void *worker(void *arg) {
     job_t *J = (job_t *)arg;
     memset(&J->cnt, 0, sizeof J->cnt);
+    J->box_fail = 0;
+    const int K = J->K;
     for (int64_t s = J->lo; s < J->hi; s++) {
         int64_t i = J->sel ? J->sel[s] : s;
+        int32_t ids[TOPO_K];
+        double rel[TOPO_K][3], d2[TOPO_K];
+        int nn;
+        if (J->g_ids) {
+            nn = J->g_cnt[s];
+            memcpy(ids, J->g_ids + (size_t)s * K, sizeof(int32_t) * (size_t)nn);
+            memcpy(rel, J->g_rel + (size_t)s * K * 3, sizeof(double) * 3 * (size_t)nn);
+            memcpy(d2, J->g_d2 + (size_t)s * K, sizeof(double) * (size_t)nn);
+        } else if (J->grid) {
+            nn = knn_grid(J->grid, J->pos, J->box, i, K, ids, rel, d2);
+        } else {
+            nn = knn_brute(J->pos, J->n, J->box, i, K, ids, rel, d2);
+        }
+        if (J->o_ids) { /* neighbour search only */
+            J->o_cnt[s] = nn;
+            memcpy(J->o_ids + (size_t)s * K, ids, sizeof(int32_t) * (size_t)nn);
+            memcpy(J->o_rel + (size_t)s * K * 3, rel, sizeof(double) * 3 * (size_t)nn);
+            memcpy(J->o_d2 + (size_t)s * K, d2, sizeof(double) * (size_t)nn);
+            if (!box_holds_shell(J->box, nn, K, d2)) J->box_fail = 1;
+            continue;
+        }
+        if (!box_holds_shell(J->box, nn, K, d2)) J->box_fail = 1;
         atom_out_t o;
-        classify_atom(J->pos, J->species, J->box, J->n, i, J->mask, J->cutoff, &o, &J->cnt);
+        classify_atom(J->species, i, J->mask, J->cutoff, ids, (const double(*)[3])rel, nn, &o, &J->cnt);
         J->type[s] = o.type;
         if (J->alloy) J->alloy[s] = o.alloy;
         J->rmsd[s] = o.rmsd;
@@ -1432,35 +1699,20 @@ static void *worker(void *arg) {
     return NULL;
 }
 
-/* Classify the atoms listed in sel (or all n atoms when sel == NULL); output
- * slot s belongs to atom sel[s].  Returns 0 on success.  counters (optional,
- * 5 entries) receives hull, code, candidate, orientation-test and
- * exact-fallback counts. */
-int ptm_oracle_classify(const double *pos, const int8_t *species, const double *box, int64_t n,
-                        uint32_t mask, double cutoff, const int64_t *sel, int64_t nsel, int nthreads,
-                        int8_t *type, int8_t *alloy, double *rmsd, double *scale, double *quat,
-                        int32_t *nbr, double *strain, int32_t *knn, double *margin, int32_t *ncand,
-                        double *tmargin, int64_t *counters) {
-    if (!ensure_init()) return 1;
-    if (!sel) nsel = n;
-    if (nthreads < 1) nthreads = 1;
-    if (nthreads > 256) nthreads = 256;
-    job_t jobs[256];
+/* Run the prepared jobs on nthreads threads; returns 1 if an atom failed
+ * the periodic-box rule (box_holds_shell). */
+static int run_jobs(job_t *jobs, int nthreads, int64_t nsel, int64_t *counters) {
     pthread_t th[256];
     long o0 = g_cnt_orient, e0 = g_cnt_exact;
     for (int t = 0; t < nthreads; t++) {
-        job_t *J = &jobs[t];
-        J->pos = pos; J->species = species; J->box = box; J->n = n;
-        J->sel = sel; J->nsel = nsel; J->mask = mask; J->cutoff = cutoff;
-        J->type = type; J->alloy = alloy; J->rmsd = rmsd; J->scale = scale; J->quat = quat;
-        J->strain = strain; J->margin = margin; J->nbr = nbr; J->knn = knn; J->ncand = ncand;
-        J->tmargin = tmargin;
-        J->lo = nsel * t / nthreads;
-        J->hi = nsel * (t + 1) / nthreads;
+        jobs[t].lo = nsel * t / nthreads;
+        jobs[t].hi = nsel * (t + 1) / nthreads;
     }
     for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, worker, &jobs[t]);
     worker(&jobs[0]);
     for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
+    int fail = 0;
+    for (int t = 0; t < nthreads; t++) fail |= jobs[t].box_fail;
     if (counters) {
         memset(counters, 0, sizeof(int64_t) * 5);
         for (int t = 0; t < nthreads; t++) {
@@ -1471,7 +1723,95 @@ int ptm_oracle_classify(const double *pos, const int8_t *species, const double *
         counters[3] = g_cnt_orient - o0;
         counters[4] = g_cnt_exact - e0;
     }
-    return 0;
+    return fail;
+}
+
+static int clamp_threads(int nthreads) { return nthreads < 1 ? 1 : (nthreads > 256 ? 256 : nthreads); }
+
+/* Classify the atoms listed in sel (or all n atoms when sel == NULL); output
+ * slot s belongs to atom sel[s].  Neighbours by brute force up to BRUTE_MAX
+ * atoms, by the certified cell search above (mask bits KNN_FORCE_* override
+ * the choice).  Returns 0 on success, 1 if the tables could not be built,
+ * 2 if the frame is periodic and some listed atom fails box_holds_shell
+ * (every output is still written).  counters (optional, 5 entries)
+ * receives hull, code, candidate, orientation-test and exact-fallback
+ * counts. */
+int ptm_oracle_classify(const double *pos, const int8_t *species, const double *box, int64_t n,
+                        uint32_t mask, double cutoff, const int64_t *sel, int64_t nsel, int nthreads,
+                        int8_t *type, int8_t *alloy, double *rmsd, double *scale, double *quat,
+                        int32_t *nbr, double *strain, int32_t *knn, double *margin, int32_t *ncand,
+                        double *tmargin, int64_t *counters) {
+    if (!ensure_init()) return 1;
+    if (!sel) nsel = n;
+    nthreads = clamp_threads(nthreads);
+    cellgrid_t G;
+    int use_grid = (mask & KNN_FORCE_GRID) || (n > BRUTE_MAX && !(mask & KNN_FORCE_BRUTE));
+    if (use_grid && !cellgrid_build(&G, pos, n, box)) return 1;
+    job_t jobs[256];
+    for (int t = 0; t < nthreads; t++) {
+        job_t *J = &jobs[t];
+        memset(J, 0, sizeof *J);
+        J->pos = pos; J->species = species; J->box = box; J->n = n;
+        J->sel = sel; J->nsel = nsel; J->mask = mask; J->cutoff = cutoff;
+        J->grid = use_grid ? &G : NULL;
+        J->K = (mask & ORDER_TOPOLOGICAL) ? TOPO_K : KMAX;
+        J->type = type; J->alloy = alloy; J->rmsd = rmsd; J->scale = scale; J->quat = quat;
+        J->strain = strain; J->margin = margin; J->nbr = nbr; J->knn = knn; J->ncand = ncand;
+        J->tmargin = tmargin;
+    }
+    int fail = run_jobs(jobs, nthreads, nsel, counters);
+    if (use_grid) cellgrid_free(&G);
+    return fail ? 2 : 0;
+}
+
+/* The neighbour search alone (Sec. 3, Euclidean order) for the atoms in sel
+ * (or all): K = 14 or 18 entries per atom into ids[nsel][K], rel[nsel][K][3]
+ * and d2[nsel][K], the count into cnt[nsel].  force: 0 by frame size, 1
+ * cell search, 2 brute force.  Returns 0, 1 on failure, 2 as
+ * ptm_oracle_classify for the box rule. */
+int ptm_oracle_neighbours(const double *pos, const double *box, int64_t n, const int64_t *sel, int64_t nsel,
+                          int K, int force, int nthreads, int32_t *ids, double *rel, double *d2, int32_t *cnt) {
+    if (K != KMAX && K != TOPO_K) return 1;
+    if (!sel) nsel = n;
+    nthreads = clamp_threads(nthreads);
+    cellgrid_t G;
+    int use_grid = force == 1 || (force == 0 && n > BRUTE_MAX);
+    if (use_grid && !cellgrid_build(&G, pos, n, box)) return 1;
+    job_t jobs[256];
+    for (int t = 0; t < nthreads; t++) {
+        job_t *J = &jobs[t];
+        memset(J, 0, sizeof *J);
+        J->pos = pos; J->box = box; J->n = n; J->sel = sel; J->nsel = nsel;
+        J->grid = use_grid ? &G : NULL;
+        J->K = K;
+        J->o_ids = ids; J->o_rel = rel; J->o_d2 = d2; J->o_cnt = cnt;
+    }
+    int fail = run_jobs(jobs, nthreads, nsel, NULL);
+    if (use_grid) cellgrid_free(&G);
+    return fail ? 2 : 0;
+}
+
+/* ptm_oracle_classify with the neighbours given (as ptm_oracle_neighbours
+ * writes them, K = 14, or 18 with ORDER_TOPOLOGICAL); the atoms' ids in sel
+ * index the species array.  Same outputs and return codes. */
+int ptm_oracle_classify_given(const int8_t *species, const double *box, uint32_t mask, double cutoff,
+                              const int64_t *sel, int64_t nsel, const int32_t *ids, const double *rel,
+                              const double *d2, const int32_t *cnt, int nthreads, int8_t *type, int8_t *alloy,
+                              double *rmsd, double *scale, double *quat, int32_t *nbr, double *strain,
+                              int32_t *knn) {
+    if (!ensure_init() || !sel) return 1;
+    nthreads = clamp_threads(nthreads);
+    job_t jobs[256];
+    for (int t = 0; t < nthreads; t++) {
+        job_t *J = &jobs[t];
+        memset(J, 0, sizeof *J);
+        J->species = species; J->box = box; J->sel = sel; J->nsel = nsel; J->mask = mask; J->cutoff = cutoff;
+        J->K = (mask & ORDER_TOPOLOGICAL) ? TOPO_K : KMAX;
+        J->g_ids = ids; J->g_rel = rel; J->g_d2 = d2; J->g_cnt = cnt;
+        J->type = type; J->alloy = alloy; J->rmsd = rmsd; J->scale = scale; J->quat = quat;
+        J->strain = strain; J->nbr = nbr; J->knn = knn;
+    }
+    return run_jobs(jobs, nthreads, nsel, NULL) ? 2 : 0;
 }
 
 /* ---- narrow hooks used by the oracle's own pinning tests --------------- */
@@ -1600,4 +1940,12 @@ int ptm_oracle_voronoi(const double *rel18, double *area, int32_t *order, double
 /* areas alone, for any k <= 18 neighbour vectors of a bounded cell */
 void ptm_oracle_voronoi_areas(int k, const double *rel, double *area) {
     voronoi_areas(k, (const double(*)[3])rel, area);
+}
+
+/* Sec. 8 strain of template t for observed points obs[k+1][3] given in
+ * template-vertex order, centre first (as strain_of): P[9] row-major. */
+int ptm_oracle_strain(int t, const double *obs, double *P) {
+    if (!ensure_init() || t < 0 || t >= NTEMPL) return -1;
+    strain_of(&g_T[t], (const double(*)[3])obs, P);
+    return 0;
 }

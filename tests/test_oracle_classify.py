@@ -229,3 +229,63 @@ def test_too_few_neighbours(oracle_lib):
     assert np.all(o["knn"][:, 8:] == -1)
     assert np.all(o["neighbours"][:, 6:] == -1)
     assert np.all(o["type"] <= 1)
+
+
+def polar_left_proper(A):
+    """A = P U with U a proper rotation (det +1), from numpy's SVD: the sign
+    of det A goes to the smallest singular value."""
+    X, sv, Yt = np.linalg.svd(A)
+    d = np.sign(np.linalg.det(X @ Yt))
+    U = X @ np.diag([1.0, 1.0, d]) @ Yt
+    return A @ U.T, U
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("flip", [False, True])
+def test_strain_right_handed_rotation(oracle_lib, t, flip):
+    """Sec. 8: A = P U with U orthogonal and right-handed.  For an exact
+    affine image x' = F x of a template (centre at the origin) eq.(6) gives
+    A = F l(x) / l(Fx); P then equals A U^T for the proper rotation U of
+    the SVD polar decomposition, which for det F < 0 carries a negative
+    eigenvalue (the smallest singular value, negated)."""
+    rng = np.random.default_rng(40 + t)
+    d = oracle_lib.template(t)
+    w = d["w"]
+    for _ in range(6):
+        eps = rng.uniform(-0.2, 0.2, size=(3, 3))
+        F = S.random_rotations(rng, 1)[0] @ (np.eye(3) + eps)
+        if flip:
+            F = F @ np.diag([1.0, 1.0, -1.0])
+        assert (np.linalg.det(F) < 0) == flip
+        x = np.vstack([np.zeros(3), w * 2.3])
+        fx = x @ F.T
+        lx = np.linalg.norm(x - x.mean(0), axis=1).mean()
+        lfx = np.linalg.norm(fx - fx.mean(0), axis=1).mean()
+        A = F * lx / lfx
+        P_ref, U = polar_left_proper(A)
+        assert np.linalg.det(U) > 0 and np.allclose(P_ref, P_ref.T, atol=1e-12)
+        P = oracle_lib.strain(t, fx)
+        assert np.allclose(P, P_ref, atol=1e-12), (P, P_ref)
+        assert (np.linalg.det(P) < 0) == flip
+        # U = P^-1 A is a proper rotation
+        Uo = np.linalg.solve(P, A)
+        assert np.allclose(Uo @ Uo.T, np.eye(3), atol=1e-10) and np.linalg.det(Uo) > 0
+
+
+def test_strain_hook_matches_classification(oracle_lib):
+    """The strain entry point is the function the classification uses (on
+    the representative's neighbour order, which differs from the winning
+    correspondence by a template rotation that leaves P unchanged)."""
+    f = S.polycrystal(L=30.0, n_grains=3, sigma=0.1, seed=41)
+    atoms = np.arange(0, f.n, 7)[:200]
+    o = oracle_lib.classify(f.positions, f.box, atoms=atoms)
+    for s, i in enumerate(atoms):
+        t = int(o["type"][s]) - 1
+        if t < 0:
+            continue
+        k = oracle_lib.TEMPLATE_K[t]
+        nb = o["neighbours"][s, :k]
+        dv = f.positions[nb] - f.positions[i]
+        dv = dv - np.rint(dv * (1.0 / f.box)) * f.box
+        P = oracle_lib.strain(t, np.vstack([np.zeros(3), dv]))
+        assert np.allclose(P.reshape(-1), o["strain"][s], rtol=0, atol=1e-13)
