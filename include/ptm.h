@@ -41,7 +41,7 @@ typedef enum {
     PTM_E_INVALID = 1,   /* bad argument: NULL pointer, n < 0, bad box, NaN/Inf coordinate */
     PTM_E_NOMEM = 2,     /* device allocation failed or HBM budget exceeded */
     PTM_E_DEVICE = 3,    /* HIP runtime error (message in ptm_last_error) */
-    PTM_E_BOX = 4,       /* reserved: box unusable for the neighbour search */
+    PTM_E_BOX = 4,       /* periodic box too short for the neighbour shell (see ptm_classify) */
     PTM_E_TOO_LARGE = 5, /* n > PTM_MAX_ATOMS */
     PTM_E_BUSY = 6,      /* serving queue full */
     PTM_E_TIMEOUT = 7    /* ptm_wait timed out; the ticket stays valid */
@@ -93,9 +93,17 @@ enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2,
 typedef struct {
     int device;                /* HIP device ordinal */
     ptm_precision precision;   /* PTM_FP64 or PTM_FP32_MIXED */
-    void *hip_stream;          /* hipStream_t to run on; NULL = the context's own stream */
+    void *hip_stream;          /* hipStream_t to run on; NULL = the context's own (non-blocking) stream.
+                                  Device inputs written by work on another stream must be complete (or
+                                  that stream waited on) before a call: the library orders its work on
+                                  this stream only.  ptm_submit frames wait for this stream's prior
+                                  work before they start. */
     uint64_t hbm_budget_bytes; /* cap on scratch + in-flight frames; 0 = no cap */
     uint32_t flags;            /* PTM_F_* */
+    int64_t pair_capacity;     /* 0: the candidate pair list holds 6n + 64 (atom, correspondence)
+                                  pairs; a smaller positive value caps it there, for tests of the path
+                                  that decides the atoms past the capacity by the full rule (results
+                                  are unchanged).  Negative -> PTM_E_INVALID. */
 } ptm_config;
 
 /* Per-atom outputs, n entries each (arrays with a second dimension are
@@ -153,8 +161,16 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out);
  *   rmsd_cutoff    keep the type iff RMSD <= cutoff (+inf = no cut-off,
  *                  Sec. 5.1); must not be NaN.
  * Stream-ordered on the context's stream; synchronises before returning.
- * Errors: PTM_E_INVALID, PTM_E_TOO_LARGE, PTM_E_NOMEM, PTM_E_DEVICE.
- * n_atoms == 0 returns PTM_OK without touching the device. */
+ * Periodic boxes (Sec. 5 samples): neighbours are minimum images, which are
+ * the periodic crystal's neighbours only when every atom's 14th neighbour
+ * (18th with PTM_F_TOPOLOGICAL) lies strictly closer than half of each
+ * periodic box length -- every other image of an atom is at least half a
+ * length away.  Otherwise (tested as 4 d^2 < L*L in FP64, d^2 the squared
+ * minimum-image distance; also when a frame with a periodic axis gives some
+ * atom fewer than 14 / 18 neighbours) the call returns PTM_E_BOX and writes
+ * no output: replicate the cell first.
+ * Errors: PTM_E_INVALID, PTM_E_TOO_LARGE, PTM_E_NOMEM, PTM_E_DEVICE,
+ * PTM_E_BOX.  n_atoms == 0 returns PTM_OK without touching the device. */
 ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *species,
                         const double *box, int64_t n_atoms, uint32_t template_mask,
                         double rmsd_cutoff, const ptm_outputs *out);
@@ -170,7 +186,10 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
                       double rmsd_cutoff, const ptm_outputs *out, uint64_t *ticket);
 
 /* Wait for a ticket (timeout_us < 0: forever; 0: poll).  PTM_E_TIMEOUT if
- * not yet complete; PTM_E_INVALID for an unknown ticket.  stats may be NULL. */
+ * not yet complete (the ticket stays valid); PTM_E_INVALID for an unknown
+ * ticket; PTM_E_BOX when the frame's periodic box is too short (as for
+ * ptm_classify: no output is written, the ticket is consumed).  stats may be
+ * NULL. */
 ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame_stats *stats);
 
 /* Destroy a context (waits for in-flight tickets).  NULL is a no-op. */

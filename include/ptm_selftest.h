@@ -52,6 +52,21 @@ int ptm_selftest_det3_f32filter(const double *p9);
  * FP32). */
 int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q);
 
+/* Strain of one match (eq. (6) least-squares fit with the pseudoinverse of
+ * the normalised template, then P of the left polar decomposition A = P U
+ * with U right-handed; Sec. 8) by the library's strain arithmetic: template
+ * t (0..4), obs[k+1][3] the observed points in template-vertex order with
+ * the centre first, precision PTM_FP64 (0) or PTM_FP32_MIXED (1, the FP32
+ * arithmetic of that form).  Host evaluation; P[9] row-major.  Returns 0,
+ * or -1 for t or precision out of range. */
+int ptm_selftest_strain(int t, int precision, const double *obs, double *P);
+
+/* The same on the device of a context, by the code the decision kernels
+ * run, in the context's precision.  Host pointers; synchronous on the
+ * context's stream.  Returns 0 (PTM_OK) or a ptm_status code. */
+struct ptm_ctx;
+int ptm_selftest_strain_device(struct ptm_ctx *ctx, int t, const double *obs, double *P);
+
 #ifdef __cplusplus
 }
 #endif

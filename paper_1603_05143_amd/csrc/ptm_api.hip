@@ -29,13 +29,18 @@ namespace ptm {
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // capacity of the flat candidate-pair list (typical atoms have 1-3 pairs;
-// atoms beyond the capacity are evaluated directly by k_decide)
-static int64_t pair_capacity(int64_t n) { return 6 * n + 64; }
+// atoms beyond the capacity are decided by the full rule, k_decide_full);
+// cap_override > 0 replaces the default (a ptm_config field for tests)
+int64_t pair_capacity(int64_t n, int64_t cap_override) {
+    const int64_t def = 6 * n + 64;
+    return cap_override > 0 && cap_override < def ? cap_override : def;
+}
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo) {
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo, int64_t cap) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
-    b += align_up(4 * (size_t)(cells + 3)) * 2;  // count (+ k-NN and decision leftover counters), start
+    // count (+ the k-NN and decision leftover counters and the box flag), start
+    b += align_up(4 * (size_t)(cells + FRAME_COUNTERS)) * 2;
     b += align_up(8 * (size_t)n) * 3;         // sorted positions
     b += align_up(4 * (size_t)n * KMAX);      // neighbour ids
     b += align_up(8 * (size_t)n * KMAX * 3);  // neighbour vectors
@@ -43,8 +48,8 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     b += align_up(8 * (size_t)n * NGRP);      // labellings
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
     b += align_up(8 * (size_t)(pair_slots(n) + 1)) * 2;  // candidate counts and offsets per (atom, group)
-    b += align_up(16 * (size_t)pair_capacity(n));  // pairs and their RMSD
-    b += align_up(40 * (size_t)pair_capacity(n));  // their quaternion and scale
+    b += align_up(16 * (size_t)cap);  // pairs and their RMSD
+    b += align_up(40 * (size_t)cap);  // their quaternion and scale
     b += align_up(scan_tmp);
     if (topo) {
         b += align_up(4 * (size_t)n * VK);      // the 18 Euclidean neighbours' ids
@@ -55,7 +60,7 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     return b;
 }
 
-bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err) {
+bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, int64_t cap, std::string &err) {
     int nb = bounds_blocks(n);
     size_t scan_tmp = 0, scan_tmp2 = 0;
     if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
@@ -66,8 +71,13 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
         return false;
     }
     if (scan_tmp2 > scan_tmp) scan_tmp = scan_tmp2;
-    size_t need = frame_bytes(n, cells, nb, scan_tmp, topo);
+    size_t need = frame_bytes(n, cells, nb, scan_tmp, topo, cap);
     if (need > bytes) {
+        if (pooled) {
+            // a pooled buffer is sized for its class and never reallocated
+            err = "pooled scratch of " + std::to_string(bytes) + " bytes is too small for " + std::to_string(need);
+            return false;
+        }
         if (base) (void)hipFree(base);
         base = nullptr;
         bytes = 0;
@@ -87,8 +97,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     cell_of = (int32_t *)take(4 * (size_t)n);
     slot_of = (int32_t *)take(4 * (size_t)n);
     sid = (int32_t *)take(4 * (size_t)n);
-    count = (int32_t *)take(4 * (size_t)(cells + 3));
-    start = (int32_t *)take(4 * (size_t)(cells + 3));
+    count = (int32_t *)take(4 * (size_t)(cells + FRAME_COUNTERS));
+    start = (int32_t *)take(4 * (size_t)(cells + FRAME_COUNTERS));
     sx = (double *)take(8 * (size_t)n);
     sy = (double *)take(8 * (size_t)n);
     sz = (double *)take(8 * (size_t)n);
@@ -97,7 +107,7 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     code = (int32_t *)take(4 * (size_t)n * NGRP);
     ord = (uint64_t *)take(8 * (size_t)n * NGRP);
     part = (double *)take(8 * 7 * (size_t)nb);
-    match.cap = pair_capacity(n);
+    match.cap = cap;
     match.cnt = (int64_t *)take(8 * (size_t)(pair_slots(n) + 1));
     match.off = (int64_t *)take(8 * (size_t)(pair_slots(n) + 1));
     match.pairs = (uint2 *)take(8 * (size_t)match.cap);
@@ -200,8 +210,10 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     if ((ps = mark(PTM_STAGE_BIN)) != PTM_OK) return ps;
     int64_t cells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     // count[cells + 1] and count[cells + 2] count the atoms the fast k-NN
-    // search and the common-case decision leave over
-    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + 3), st));
+    // search and the common-case decision leave over; count[cells + 3] is
+    // the box flag (set by the k-NN kernels, read by every later stage)
+    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + FRAME_COUNTERS), st));
+    const int32_t *box_fail = S.count + cells + 3;
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
     size_t tmp = S.scan_tmp_bytes;
     PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
@@ -210,30 +222,32 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     // slot_of is free once the atoms are scattered: it holds the leftover list
     if (J.topo) {
         // the 18 Euclidean neighbours, then their topological order (Sec. 3)
-        launch_knn(n, g, VK, S.sx, S.sy, S.sz, S.sid, S.start, S.id18, S.rel18, J.out.knn, S.slot_of,
-                   S.count + cells + 1, st);
-        launch_voronoi(n, S.rel18, S.id18, S.vf, S.vlive, S.nbr_rel, S.nbr_id, st);
+        launch_knn(n, g, VK, S.sx, S.sy, S.sz, S.sid, S.start, S.id18, S.rel18, S.slot_of, S.count + cells + 1,
+                   S.count + cells + 3, st);
+        launch_voronoi(n, S.rel18, S.id18, S.vf, S.vlive, S.nbr_rel, S.nbr_id, box_fail, st);
     } else {
-        launch_knn(n, g, KMAX, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, J.out.knn, S.slot_of,
-                   S.count + cells + 1, st);
+        launch_knn(n, g, KMAX, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, S.slot_of, S.count + cells + 1,
+                   S.count + cells + 3, st);
     }
     if ((ps = mark(PTM_STAGE_TOPO)) != PTM_OK) return ps;
     const uint32_t m = J.mask;
     const uint32_t need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
-    launch_topo(n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, st);
+    launch_topo(n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, box_fail, st);
     if ((ps = mark(PTM_STAGE_CAND)) != PTM_OK) return ps;
     MatchOut O = {J.out.type,       J.out.alloy,     J.out.rmsd,
                   J.out.scale,      J.out.quat,      J.out.neighbours,
                   J.out.strain,     J.out.vm_strain, J.out.strain_residual,
                   J.out.nn_distance, J.out.quat_fz, J.out.best_type};
     const bool f32 = ctx->precision == PTM_FP32_MIXED;
-    launch_cand(n, ctx->view, S.code, m, S.match, st);
+    launch_cand(n, ctx->view, S.code, m, S.match, box_fail, st);
     if ((ps = mark(PTM_STAGE_EVAL)) != PTM_OK) return ps;
-    launch_eval(n, S.nbr_rel, ctx->view, S.ord, S.match, f32, st);
+    launch_eval(n, S.nbr_rel, ctx->view, S.ord, S.match, f32, box_fail, st);
     if ((ps = mark(PTM_STAGE_DECIDE)) != PTM_OK) return ps;
-    // slot_of (free since the scatter) holds the decision's leftover list
+    // slot_of (free since the scatter) holds the decision's leftover list;
+    // the knn output is the Euclidean order (the 18-neighbour list of the
+    // topological ordering starts with it)
     launch_decide(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match,
-                  S.slot_of, S.count + cells + 2, f32, st);
+                  S.slot_of, S.count + cells + 2, J.topo ? S.id18 : S.nbr_id, J.out.knn, box_fail, f32, st);
     if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;
@@ -261,6 +275,11 @@ ptm_status frame_bounds(ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_
         if (h[7 * b + 6] != 0.0) bad = true;
     }
     return PTM_OK;
+}
+
+const char *box_message(bool topo) {
+    return topo ? "a periodic box length is not more than twice some atom's 18th-neighbour distance"
+                : "a periodic box length is not more than twice some atom's 14th-neighbour distance";
 }
 
 ptm_status validate(ptm_ctx *ctx, const double *positions, const double *box, int64_t n, double cutoff,
@@ -352,6 +371,11 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
     ctx->precision = cfg->precision;
     ctx->budget = cfg->hbm_budget_bytes;
     ctx->flags = cfg->flags;
+    if (cfg->pair_capacity < 0) {
+        delete ctx;
+        return PTM_E_INVALID;
+    }
+    ctx->pair_cap = cfg->pair_capacity;
     if (hipSetDevice(ctx->device) != hipSuccess) {
         delete ctx;
         return PTM_E_DEVICE;
@@ -365,6 +389,12 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
             return PTM_E_DEVICE;
         }
         ctx->own_stream = true;
+    }
+    if (hipHostMalloc((void **)&ctx->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->pinned = nullptr;
+        ptm_destroy(ctx);
+        return PTM_E_NOMEM;
     }
     if (ctx->flags & PTM_F_PROFILE)
         for (int e = 0; e <= PTM_NSTAGES; e++)
@@ -398,6 +428,7 @@ void ptm_destroy(ptm_ctx *ctx) {
     for (int e = 0; e <= PTM_NSTAGES; e++)
         if (ctx->prof_ev[e]) (void)hipEventDestroy(ctx->prof_ev[e]);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
 }
 
@@ -419,8 +450,9 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
     HostStage H;
     st = stage_in(ctx, positions, species, out, n_atoms, J, H);
     if (st != PTM_OK) return st;
+    const int64_t cap = pair_capacity(n_atoms, ctx->pair_cap);
     // bounds first (needs scratch for the partials): reserve with a tiny grid
-    if (!ctx->main.reserve(n_atoms, 1, J.topo, ctx->err)) return PTM_E_NOMEM;
+    if (!ctx->main.reserve(n_atoms, 1, J.topo, cap, ctx->err)) return PTM_E_NOMEM;
     double mn[3], mx[3];
     bool bad = false;
     const bool prof = (ctx->flags & PTM_F_PROFILE) != 0;
@@ -434,21 +466,38 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
     }
     J.grid = make_grid(box, mn, mx, n_atoms, J.topo ? VK : KMAX);
     int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
-    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo) > ctx->budget) {
+    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo, cap) > ctx->budget) {
         ctx->err = "frame scratch exceeds the HBM budget";
         return PTM_E_NOMEM;
     }
-    if (!ctx->main.reserve(n_atoms, cells, J.topo, ctx->err)) return PTM_E_NOMEM;
+    if (!ctx->main.reserve(n_atoms, cells, J.topo, cap, ctx->err)) return PTM_E_NOMEM;
     st = enqueue_frame(ctx, ctx->main, J, ctx->stream, prof);
     if (st != PTM_OK) return st;
-    st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
-    if (st != PTM_OK) return st;
+    // the box flag comes back with the frame; host outputs are copied only
+    // once it is known to be clear (nothing is written on an error)
+    *ctx->pinned = 0;
+    PTM_HIP(ctx, hipMemcpyAsync(ctx->pinned, box_flag(ctx->main, J.grid), 4, hipMemcpyDeviceToHost, ctx->stream));
+    if (H.active) {
+        PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (*ctx->pinned) {
+            ctx->err = box_message(J.topo);
+            return PTM_E_BOX;
+        }
+        st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
+        if (st != PTM_OK) return st;
+    }
     PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (*ctx->pinned) {
+        ctx->err = box_message(J.topo);
+        return PTM_E_BOX;
+    }
     if (prof) {
         int32_t left[2] = {0, 0};
         int64_t pairs = 0;
         PTM_HIP(ctx, hipMemcpy(left, ctx->main.count + cells + 1, 8, hipMemcpyDeviceToHost));
         PTM_HIP(ctx, hipMemcpy(&pairs, ctx->main.match.off + pair_slots(n_atoms), 8, hipMemcpyDeviceToHost));
+        // the pairs past the capacity go to the full rule with their atoms
+        if (pairs > ctx->main.match.cap) pairs = ctx->main.match.cap;
         ctx->prof_info[PTM_INFO_CELLS] = cells;
         ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left[0] : n_atoms;
         ctx->prof_info[PTM_INFO_PAIRS] = pairs;
@@ -723,6 +772,82 @@ int ptm_selftest_superpose(int N, const double *obs, const double *tpl, double *
     *rmsd = sqrt(res / N);
     *scale = s;
     return 0;
+}
+
+}  // extern "C"
+
+// host tables for the self-check entry points that need a template
+static const HostTables *selftest_tables() {
+    static std::once_flag once;
+    static HostTables *T = nullptr;
+    std::call_once(once, [] {
+        HostTables *h = new (std::nothrow) HostTables();
+        std::string err;
+        if (h && build_tables(*h, err)) T = h;
+        else delete h;
+    });
+    return T;
+}
+
+template <int K, typename RT>
+static void selftest_strain_k(const TemplateDev &D, const double *obs, double *P) {
+    RT v[K][3];
+    double cb[3] = {0, 0, 0};
+    uint64_t tv = 0;
+    for (int r = 0; r < K; r++) {
+        for (int d = 0; d < 3; d++) {
+            const double x = obs[3 * (r + 1) + d] - obs[d];
+            v[r][d] = (RT)x;
+            cb[d] += x;
+        }
+        tv |= (uint64_t)r << (4 * r);
+    }
+    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
+    RT a0[3], At[3][3], l, Pm[3][3];
+    strain_inputs<K, RT>(D, tv, v, cb, a0, At, l);
+    polar_p<RT>(At, l, Pm);
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) P[3 * x + y] = (double)Pm[x][y];
+}
+
+template <typename RT>
+static void selftest_strain_rt(const TemplateDev &D, const double *obs, double *P) {
+    if (D.k == 6) selftest_strain_k<6, RT>(D, obs, P);
+    else if (D.k == 12) selftest_strain_k<12, RT>(D, obs, P);
+    else selftest_strain_k<14, RT>(D, obs, P);
+}
+
+extern "C" {
+
+int ptm_selftest_strain(int t, int precision, const double *obs, double *P) {
+    const HostTables *T = selftest_tables();
+    if (!T || t < 0 || t >= NT || (precision != PTM_FP64 && precision != PTM_FP32_MIXED) || !obs || !P) return -1;
+    if (precision == PTM_FP32_MIXED) selftest_strain_rt<float>(T->tpl[t], obs, P);
+    else selftest_strain_rt<double>(T->tpl[t], obs, P);
+    return 0;
+}
+
+int ptm_selftest_strain_device(ptm_ctx *ctx, int t, const double *obs, double *P) {
+    if (!ctx || t < 0 || t >= NT || !obs || !P) return PTM_E_INVALID;
+    PTM_HIP(ctx, hipSetDevice(ctx->device));
+    const int k = template_k(t);
+    double rel[KMAX * 3];
+    for (int r = 0; r < k; r++)
+        for (int d = 0; d < 3; d++) rel[3 * r + d] = obs[3 * (r + 1) + d] - obs[d];
+    double *buf = nullptr;
+    PTM_HIP(ctx, hipMalloc((void **)&buf, 8 * (KMAX * 3 + 9)));
+    ptm_status st = PTM_OK;
+    if (hipMemcpyAsync(buf, rel, 8 * 3 * (size_t)k, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) st = PTM_E_DEVICE;
+    if (st == PTM_OK) {
+        launch_selftest_strain(ctx->view, t, ctx->precision == PTM_FP32_MIXED, buf, buf + KMAX * 3, ctx->stream);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(P, buf + KMAX * 3, 72, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            st = PTM_E_DEVICE;
+    }
+    (void)hipFree(buf);
+    if (st != PTM_OK) ctx->err = "ptm_selftest_strain_device: HIP error";
+    return st;
 }
 
 int ptm_selftest_orient_f32filter(const double *p) {

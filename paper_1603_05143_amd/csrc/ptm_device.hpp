@@ -9,10 +9,14 @@
 //  * the QCP solve of the superposition of eqs. (2)-(4) (Theobald 2005; Liu
 //    et al. 2010): characteristic polynomial of Horn's 4x4 matrix, Newton
 //    from an upper bound, eigenvector from the adjugate;
-//  * cyclic Jacobi for 3x3 symmetric matrices (square root of A A^T, Sec. 8).
+//  * cyclic Jacobi for 3x3 symmetric matrices, and the strain of eq. (6) and
+//    Sec. 8 (pseudoinverse fit, symmetric factor of the left polar
+//    decomposition with a right-handed rotation).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "ptm_tables.hpp"
 
 namespace ptm {
 
@@ -491,6 +495,69 @@ __host__ __device__ inline void jacobi3(T A[3][3], T d[3], T V[3][3]) {
             }
     }
     d[0] = A[0][0]; d[1] = A[1][1]; d[2] = A[2][2];
+}
+
+// ---------------------------------------------------------------- strain
+// eq.(6) inputs of a match: with the K neighbour vectors v (rank order; the
+// centre is the origin) and their barycentre cb (of all K + 1 points, FP64),
+// the centred points a_0 = -cb (the centre) and a_r = v_r - cb; then
+// A^T l = sum_i V+_{:,i} a_i^T (V+ the pseudoinverse of the normalised
+// template, column tv(r) + 1 for rank r; tv: nibble r = template vertex of
+// rank r) and l = mean |a_i| (eq. 4, W' = a / l).
+template <int K, typename RT>
+__host__ __device__ inline void strain_inputs(const TemplateDev &D, uint64_t tv, const RT (&v)[K][3],
+                                              const double (&cb)[3], RT (&a0)[3], RT (&At)[3][3], RT &l) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
+    for (int d = 0; d < 3; d++) a0[d] = (RT)(-cb[d]);
+    l = sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) At[x][y] = (RT)D.vpinv[x][0] * a0[y];
+#pragma unroll
+    for (int rr = 0; rr < K; rr++) {
+        RT ar[3];
+        for (int d = 0; d < 3; d++) ar[d] = v[rr][d] - (RT)cb[d];
+        l += sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
+        const int col = (int)((tv >> (4 * rr)) & 0xF) + 1;
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * ar[y];
+    }
+    l /= RT(K + 1);
+}
+
+// Sec. 8: the symmetric factor P of the left polar decomposition A = P U,
+// U orthogonal and right-handed, from At = A^T l.  A A^T = X S^2 X^T
+// (cyclic Jacobi) and P = X diag(s) X^T, where the smallest singular value
+// takes the sign of det A: then det P has the sign of det A and U = P^-1 A
+// is a proper rotation (for det A > 0, P = (A A^T)^(1/2)).
+template <typename RT>
+__host__ __device__ inline void polar_p(const RT (&At)[3][3], RT l, RT (&P)[3][3]) {
+    // products and sums may fuse into FMAs here (one rounding instead of two; no
+    // result depends on a particular rounding)
+#pragma clang fp contract(fast)
+    RT AA[3][3];
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) {
+            RT s = 0;
+            for (int m = 0; m < 3; m++) s += At[m][x] * At[m][y];
+            AA[x][y] = s / (l * l);
+        }
+    RT ev[3], V[3][3];
+    jacobi3<RT>(AA, ev, V);
+    int sm = ev[1] < ev[0] ? 1 : 0;
+    if (ev[2] < ev[sm]) sm = 2;
+    for (int m = 0; m < 3; m++) ev[m] = sqrt(fmax(ev[m], RT(0)));
+    const RT det = At[0][0] * (At[1][1] * At[2][2] - At[1][2] * At[2][1]) -
+                   At[0][1] * (At[1][0] * At[2][2] - At[1][2] * At[2][0]) +
+                   At[0][2] * (At[1][0] * At[2][1] - At[1][1] * At[2][0]);
+    if (det < RT(0)) ev[sm] = -ev[sm];
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) {
+            RT s = 0;
+            for (int m = 0; m < 3; m++) s += V[x][m] * ev[m] * V[y][m];
+            P[x][y] = s;
+        }
 }
 
 }  // namespace ptm

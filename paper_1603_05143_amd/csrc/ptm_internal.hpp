@@ -23,10 +23,15 @@
 
 namespace ptm {
 
+// int32 entries after the cell counts: the scan's end, the k-NN and decision
+// leftover counters and the box flag
+constexpr int64_t FRAME_COUNTERS = 4;
+
 // Device scratch of one frame (one allocation, carved into arrays).
 struct FrameScratch {
     void *base = nullptr;
     size_t bytes = 0;
+    bool pooled = false;  // a serving-pool buffer of a fixed size class
     int32_t *cell_of = nullptr, *slot_of = nullptr, *sid = nullptr, *count = nullptr, *start = nullptr;
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     int32_t *nbr_id = nullptr;
@@ -41,7 +46,7 @@ struct FrameScratch {
     void *scan_tmp_ptr = nullptr;
     size_t scan_tmp_bytes = 0;
     MatchScratch match = {};
-    bool reserve(int64_t n, int64_t cells, bool topo, std::string &err);
+    bool reserve(int64_t n, int64_t cells, bool topo, int64_t cap, std::string &err);
     void release();
 };
 
@@ -84,15 +89,22 @@ struct Ticket {
     size_t footprint = 0;
     double t_submit = 0, t_start = 0, t_complete = 0;
     bool complete = false;
+    bool box_fail = false;  // the frame's periodic box was too short (PTM_E_BOX)
 };
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo);
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo, int64_t cap);
+int64_t pair_capacity(int64_t n, int64_t cap_override);
+// the box flag of a frame whose kernels have been enqueued (count[cells + 3])
+inline int32_t *box_flag(const FrameScratch &S, const Grid &g) {
+    return S.count + (int64_t)g.nc[0] * g.nc[1] * g.nc[2] + 3;
+}
 int bounds_blocks(int64_t n);
 Grid make_grid(const double box[3], const double mn[3], const double mx[3], int64_t n, int kn);
 ptm_status enqueue_frame(struct ::ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipStream_t st,
                          bool prof = false);
 ptm_status frame_bounds(struct ::ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_t n, double mn[3],
                         double mx[3], bool &bad, hipStream_t st);
+const char *box_message(bool topo);
 ptm_status validate(struct ::ptm_ctx *ctx, const double *positions, const double *box, int64_t n, double cutoff,
                     const ptm_outputs *out);
 ptm_status upload_tables(struct ::ptm_ctx *ctx);
@@ -118,6 +130,8 @@ struct ptm_ctx {
     bool own_stream = false;
     uint64_t budget = 0;
     uint32_t flags = 0;
+    int64_t pair_cap = 0;           // candidate pair capacity override (0: 6n + 64)
+    int32_t *pinned = nullptr;      // pinned host word: the box flag of the last ptm_classify
     ptm::HostTables host;
     std::vector<void *> table_buffers;
     ptm::TablesView view;
@@ -134,6 +148,7 @@ struct ptm_ctx {
     size_t pool_bytes = 0;      // scratch allocated by the pool (in flight + free)
     int next_stream = 0;
     double *bounds_part = nullptr;      // per-block bounds of the frame being admitted
+    hipEvent_t order_event = nullptr;   // orders serving frames after the context stream's work
     hipEvent_t ref_event = nullptr;     // device-timeline reference ...
     double ref_time_us = 0;             // ... and its host-clock time
     // stage profiling (PTM_F_PROFILE)

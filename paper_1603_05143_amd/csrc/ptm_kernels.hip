@@ -205,15 +205,31 @@ __device__ inline bool certified(const Grid &g, const int (&cc)[3], const double
     return found >= KN && dmin > 0 && kth < dmin * dmin;
 }
 
-// Write the K nearest neighbours of sorted atom p (original id i): ids and
+// Sec. 5 samples are periodic.  Every image of an atom other than its
+// minimum image lies at least half a box length away along that axis, so
+// the minimum-image shell is the periodic crystal's shell only when its
+// K-th member is strictly closer than half of every periodic length
+// (compared as 4 d^2 < L*L in FP64); a periodic frame whose atom has fewer
+// than K neighbours fails as well.  True = the frame is rejected.
+__device__ inline bool shell_exceeds_box(const Grid &g, int cnt, int K, double kth) {
+    bool periodic = false, bad = false;
+    for (int a = 0; a < 3; a++)
+        if (g.periodic[a]) {
+            periodic = true;
+            bad = bad || !(4.0 * kth < g.L[a] * g.L[a]);
+        }
+    return periodic && (cnt < K || bad);
+}
+
+// Write the K nearest neighbours of sorted atom p: ids and
 // minimum-image vectors in the component-major layout the hull kernels read.
 // sx[q] is a copy of pos[3 sid[q]], so the vectors are those of the input.
 template <int KN>
-__device__ inline void write_knn(int64_t n, int64_t p, int32_t i, int cnt, const int32_t (&kq)[KN], const Grid &g,
+__device__ inline void write_knn(int64_t n, int64_t p, int cnt, const int32_t (&kq)[KN], const Grid &g,
                                  double xi, double yi, double zi, const double *__restrict__ sx,
                                  const double *__restrict__ sy, const double *__restrict__ sz,
                                  const int32_t *__restrict__ sid, int32_t *__restrict__ nbr_id,
-                                 double *__restrict__ nbr_rel, int32_t *__restrict__ knn_out) {
+                                 double *__restrict__ nbr_rel) {
 #pragma unroll
     for (int m = 0; m < KN; m++) {
         int32_t j = -1;
@@ -229,7 +245,6 @@ __device__ inline void write_knn(int64_t n, int64_t p, int32_t i, int cnt, const
         nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
         nbr_rel[((int64_t)m * 3 + 1) * n + p] = r1;
         nbr_rel[((int64_t)m * 3 + 2) * n + p] = r2;
-        if (knn_out && m < KMAX) knn_out[(int64_t)i * KMAX + m] = j;
     }
 }
 
@@ -294,8 +309,8 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
                                                   const double *__restrict__ sy, const double *__restrict__ sz,
                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                                   int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
-                                                  int32_t *__restrict__ knn_out, int32_t *__restrict__ todo,
-                                                  int32_t *__restrict__ todo_count) {
+                                                  int32_t *__restrict__ todo, int32_t *__restrict__ todo_count,
+                                                  int32_t *__restrict__ box_fail) {
     int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
     constexpr int KN = NK + 1;
@@ -459,12 +474,13 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
         int lo[3] = {-2, -2, -2}, hi[3] = {2, 2, 2};
         bool all;
         ok = certified(g, cc, u, lo, hi, NK, NK, kth, all);
+        if (ok && shell_exceeds_box(g, NK, NK, kth)) atomicOr(box_fail, 1);
     }
     if (!ok) {
         todo[atomicAdd(todo_count, 1)] = (int32_t)p;
         return;
     }
-    write_knn<NK>(n, p, sid[p], NK, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel, knn_out);
+    write_knn<NK>(n, p, NK, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel);
 }
 
 // Exact search for the atoms the fast search left (or all atoms when todo
@@ -479,8 +495,9 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
                                                    const double *__restrict__ sy, const double *__restrict__ sz,
                                                    const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                                    int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
-                                                   int32_t *__restrict__ knn_out, const int32_t *__restrict__ todo,
-                                                   const int32_t *__restrict__ todo_count) {
+                                                   const int32_t *__restrict__ todo,
+                                                   const int32_t *__restrict__ todo_count,
+                                                   int32_t *__restrict__ box_fail) {
     constexpr int KN = NK;
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -505,6 +522,7 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
         double rd = INFINITY;
         int32_t rj = -1, rq = 0;
         int total = 0;
+        double kth = INFINITY;
         int plo[3] = {1, 1, 1}, phi[3] = {0, 0, 0};  // block already searched (empty)
         for (int s = 2;; s++) {
             int lo[3], hi[3], ext[3];
@@ -555,7 +573,7 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
                     kj[KN - 1] = 0x7fffffff;
                 }
             }
-            double kth = __shfl(rd, KN - 1);
+            kth = __shfl(rd, KN - 1);
             bool all;
             bool done = certified(g, cc, u, lo, hi, total, KN, kth, all);
             for (int a = 0; a < 3; a++) { plo[a] = lo[a]; phi[a] = hi[a]; }
@@ -572,6 +590,7 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
             found = lane == 0 ? total : 0;
         }
         const int cnt = total < KN ? total : KN;
+        if (lane == 0 && shell_exceeds_box(g, cnt, KN, kth)) atomicOr(box_fail, 1);
         if (lane < KN) {
             int32_t j = lane < cnt ? rj : -1;
             double r0 = 0, r1 = 0, r2 = 0;
@@ -584,7 +603,6 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
             nbr_rel[((int64_t)lane * 3 + 0) * n + p] = r0;
             nbr_rel[((int64_t)lane * 3 + 1) * n + p] = r1;
             nbr_rel[((int64_t)lane * 3 + 2) * n + p] = r2;
-            if (knn_out && lane < KMAX) knn_out[(int64_t)i * KMAX + lane] = j;
         }
     }
 }
@@ -857,11 +875,12 @@ __device__ inline double vhull_inradius2(const VLane &L, uint32_t live) {
 // 32-bit mask vlive[n], 0 when the atom keeps its Euclidean order).
 __global__ void __launch_bounds__(VB) k_voronoi_hull(int64_t n, const double *__restrict__ rel18,
                                                      const int32_t *__restrict__ id18, uint32_t *__restrict__ vf,
-                                                     uint32_t *__restrict__ vlive) {
+                                                     uint32_t *__restrict__ vlive,
+                                                     const int32_t *__restrict__ box_fail) {
     __shared__ VHullShared S;
     const int t = threadIdx.x;
     const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)VB + t;
-    if (p >= n) return;
+    if (p >= n || *box_fail) return;
     bool topo = id18[(int64_t)(VK - 1) * n + p] >= 0;
     float m = 0;
     uint32_t hk[VK];  // a mix of each point's FP32 bits: equal points have equal keys
@@ -933,12 +952,13 @@ __global__ void __launch_bounds__(VB) k_voronoi_order(int64_t n, const double *_
                                                       const int32_t *__restrict__ id18,
                                                       const uint32_t *__restrict__ vf,
                                                       const uint32_t *__restrict__ vlive,
-                                                      double *__restrict__ nbr_rel, int32_t *__restrict__ nbr_id) {
+                                                      double *__restrict__ nbr_rel, int32_t *__restrict__ nbr_id,
+                                                      const int32_t *__restrict__ box_fail) {
 #pragma clang fp contract(fast)
     __shared__ VAreaShared S;
     const int t = threadIdx.x;
     const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)VB + t;
-    if (p >= n) return;
+    if (p >= n || *box_fail) return;
     // Euclidean rank v goes to row pos(v); keys order (grid area descending, rank)
     uint32_t key[VK];
 #pragma unroll
@@ -1442,11 +1462,12 @@ __device__ int32_t probe_rest(const TablesView &T, int grp, const uint64_t (&bes
 // not needed).
 __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
                                               const int32_t *__restrict__ nbr_id, TablesView T, uint32_t need,
-                                              int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
+                                              int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out,
+                                              const int32_t *__restrict__ box_fail) {
     __shared__ TopoShared S;
     const int t = threadIdx.x;
     const int64_t p = blockIdx.x * (int64_t)TB + t;
-    if (p >= n) return;
+    if (p >= n || *box_fail) return;
     // the neighbour ids that say which hulls are possible (the K-th neighbour
     // exists) and all KMAX relative vectors are loaded in one round trip;
     // rows past the last wanted one are stored but never read
@@ -1809,22 +1830,13 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
         }
     }
     if (O.strain || O.vm_strain) {
-        // P = sqrt(A A^T) by the eigen-decomposition of the symmetric A A^T
-        RT AA[3][3];
-        for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) {
-                RT s = 0;
-                for (int m = 0; m < 3; m++) s += At[m][x] * At[m][y];
-                AA[x][y] = s / (l * l);
-            }
-        RT ev3[3], V[3][3];
-        jacobi3<RT>(AA, ev3, V);
-        for (int m = 0; m < 3; m++) ev3[m] = sqrt(fmax(ev3[m], RT(0)));
+        // Sec. 8: P of A = P U with U right-handed
+        RT P[3][3];
+        polar_p<RT>(At, l, P);
         RT sq = 0, tr = 0;
         for (int x = 0; x < 3; x++)
             for (int y = 0; y < 3; y++) {
-                RT s = 0;
-                for (int m = 0; m < 3; m++) s += V[x][m] * ev3[m] * V[y][m];
+                const RT s = P[x][y];
                 if (O.strain) O.strain[9 * (int64_t)i + 3 * x + y] = (double)s;
                 sq += s * s;
                 if (x == y) tr += s;
@@ -1944,21 +1956,8 @@ __device__ inline void finish_stored(const MatchShared &M, const TablesView &T, 
             cb[d] += x;
         }
     for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
-    RT a0[3] = {(RT)(-cb[0]), (RT)(-cb[1]), (RT)(-cb[2])};
-    RT l = sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
-    RT At[3][3];
-    for (int x = 0; x < 3; x++)
-        for (int y = 0; y < 3; y++) At[x][y] = (RT)D.vpinv[x][0] * a0[y];
-#pragma unroll
-    for (int rr = 0; rr < K; rr++) {
-        RT ar[3];
-        for (int d = 0; d < 3; d++) ar[d] = v[rr][d] - (RT)cb[d];
-        l += sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
-        int col = (int)nib(tv, rr) + 1;
-        for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * ar[y];
-    }
-    l /= RT(K + 1);
+    RT a0[3], At[3][3], l;
+    strain_inputs<K, RT>(D, tv, v, cb, a0, At, l);
     RT resid = 0;
     if (O.strain_residual) {
         // eq.(6) residual, a third pass over the points: sum of |V_i A^T - a_i|^2 / l^2
@@ -2020,10 +2019,11 @@ __device__ inline void load_templates(MatchShared &M, const TablesView &T) {
 // cnt[pair_slots(n)] = 0, so that the exclusive scan off[] ends with the
 // total.
 __global__ void __launch_bounds__(256) k_cand_count(int64_t n, TablesView T, const int32_t *__restrict__ code,
-                                                    uint32_t mask, int64_t *__restrict__ cnt) {
+                                                    uint32_t mask, int64_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ box_fail) {
     const int64_t np = pair_slots(n) / NGRP;  // atoms rounded up to whole tiles
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p > np) return;
+    if (p > np || *box_fail) return;
     if (p == np) {
         cnt[pair_slots(n)] = 0;
         return;
@@ -2044,9 +2044,9 @@ __device__ inline bool pairs_overflow(const int64_t *__restrict__ off, int64_t p
 
 __global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, const int32_t *__restrict__ code,
                                                    uint32_t mask, const int64_t *__restrict__ off, int64_t cap,
-                                                   uint2 *__restrict__ pairs) {
+                                                   uint2 *__restrict__ pairs, const int32_t *__restrict__ box_fail) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n || *box_fail) return;
     const bool over = pairs_overflow(off, p, cap);
     for (int g = 0; g < NGRP; g++) {
         int64_t q = off[pidx(p, g)];
@@ -2068,8 +2068,10 @@ template <typename RT>
 __global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
                                                   const uint64_t *__restrict__ ords, const int64_t *__restrict__ off,
                                                   int64_t cap, const uint2 *__restrict__ pairs,
-                                                  double *__restrict__ rout, RT *__restrict__ qsout) {
+                                                  double *__restrict__ rout, RT *__restrict__ qsout,
+                                                  const int32_t *__restrict__ box_fail) {
     __shared__ MatchShared M;
+    if (*box_fail) return;  // uniform over the grid
     load_templates(M, T);
     int64_t total = off[pair_slots(n)];
     if (total > cap) total = cap;
@@ -2185,7 +2187,9 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
                                                const int64_t *__restrict__ off, int64_t cap,
                                                const uint2 *__restrict__ pairs, const double *__restrict__ rr,
                                                const RT *__restrict__ qs, double cutoff, MatchOut O,
-                                               int32_t *__restrict__ todo, int32_t *__restrict__ todo_count) {
+                                               int32_t *__restrict__ todo, int32_t *__restrict__ todo_count,
+                                               const int32_t *__restrict__ knn_src, int32_t *__restrict__ knn_out,
+                                               const int32_t *__restrict__ box_fail) {
     __shared__ MatchShared M;
     // the block's winners regrouped by hull size (see below)
     __shared__ int32_t s_cnt[MB / 64][NGRP];
@@ -2193,6 +2197,7 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
     __shared__ int64_t s_q[MB];
     __shared__ double s_r[MB];
     __shared__ int8_t s_g[MB];
+    if (*box_fail) return;  // uniform over the grid
     load_templates(M, T);
     const int64_t p = blockIdx.x * (int64_t)MB + threadIdx.x;
     double m1 = INFINITY, m2 = INFINITY;
@@ -2200,6 +2205,12 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
     int64_t arg_q = -1;
     int cls = -1;  // hull group of the winner to finish here, -1 for none
     if (p < n) {
+        if (knn_out) {
+            // the Euclidean order (Sec. 3) whatever the ordering of the hulls
+            const int32_t i = sid[p];
+#pragma unroll
+            for (int m = 0; m < KMAX; m++) knn_out[(int64_t)i * KMAX + m] = knn_src[(int64_t)m * n + p];
+        }
         const bool over = pairs_overflow(off, p, cap);
         if (!over) pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
         bool full = over || (arg_c >= 0 && !(m2 > m1 + 1e-12));
@@ -2270,8 +2281,10 @@ __global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__r
                                                     const int32_t *__restrict__ code,
                                                     const uint64_t *__restrict__ ords, uint32_t mask, double cutoff,
                                                     MatchOut O, const int32_t *__restrict__ todo,
-                                                    const int32_t *__restrict__ todo_count) {
+                                                    const int32_t *__restrict__ todo_count,
+                                                    const int32_t *__restrict__ box_fail) {
     __shared__ MatchShared M;
+    if (*box_fail) return;  // uniform over the grid
     load_templates(M, T);
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (MB / 64);
@@ -2575,6 +2588,45 @@ void launch_misorientation(int64_t n, const TablesView &T, const int8_t *type, c
         hipLaunchKernelGGL(k_misorientation<false>, grid, dim3(256), 0, st, n, T, type, q1, q2, angle);
 }
 
+// ------------------------------------------------------------- self-check
+// The strain of one match on the device, as the decision kernels compute it
+// (strain_inputs, polar_p) in the working precision: K relative vectors rel
+// ([K][3], template-vertex order), template t; P[9] row-major.
+template <int K, typename RT>
+__global__ void k_selftest_strain(const TemplateDev *__restrict__ tpl, int t, const double *__restrict__ rel,
+                                  double *__restrict__ P) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const TemplateDev &D = tpl[t];
+    RT v[K][3];
+    double cb[3] = {0, 0, 0};
+    uint64_t tv = 0;
+    for (int r = 0; r < K; r++) {
+        for (int d = 0; d < 3; d++) {
+            v[r][d] = (RT)rel[3 * r + d];
+            cb[d] += rel[3 * r + d];
+        }
+        tv |= (uint64_t)r << (4 * r);
+    }
+    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
+    RT a0[3], At[3][3], l, Pm[3][3];
+    strain_inputs<K, RT>(D, tv, v, cb, a0, At, l);
+    polar_p<RT>(At, l, Pm);
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) P[3 * x + y] = (double)Pm[x][y];
+}
+
+template <typename RT>
+static void launch_selftest_strain_rt(const TablesView &T, int t, const double *rel, double *P, hipStream_t st) {
+    const int k = template_k(t);
+    if (k == 6) hipLaunchKernelGGL((k_selftest_strain<6, RT>), dim3(1), dim3(64), 0, st, T.tpl, t, rel, P);
+    else if (k == 12) hipLaunchKernelGGL((k_selftest_strain<12, RT>), dim3(1), dim3(64), 0, st, T.tpl, t, rel, P);
+    else hipLaunchKernelGGL((k_selftest_strain<14, RT>), dim3(1), dim3(64), 0, st, T.tpl, t, rel, P);
+}
+void launch_selftest_strain(const TablesView &T, int t, bool f32, const double *rel, double *P, hipStream_t st) {
+    if (f32) launch_selftest_strain_rt<float>(T, t, rel, P, st);
+    else launch_selftest_strain_rt<double>(T, t, rel, P, st);
+}
+
 // --------------------------------------------------------------- launches
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(nblocks), dim3(256), 0, st, pos, n, part);
@@ -2597,36 +2649,36 @@ bool knn_fast_applies(const Grid &g) {
 template <int NK>
 static void launch_knn_nk(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz,
                           const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel,
-                          int32_t *knn_out, int32_t *todo, int32_t *todo_count, hipStream_t st) {
+                          int32_t *todo, int32_t *todo_count, int32_t *box_fail, hipStream_t st) {
     int64_t blocks = (n + 255) / 256;
     if (knn_fast_applies(g)) {
         hipLaunchKernelGGL(k_knn_fast<NK>, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, sx, sy, sz, sid,
-                           start, nbr_id, nbr_rel, knn_out, todo, todo_count);
+                           start, nbr_id, nbr_rel, todo, todo_count, box_fail);
         // the atoms left over are few; 512 blocks of four waves (two per SIMD,
         // what its registers allow) stride over them
         hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>(blocks, 512)), dim3(256), 0, st, n, g,
-                           sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)todo,
-                           (const int32_t *)todo_count);
+                           sx, sy, sz, sid, start, nbr_id, nbr_rel, (const int32_t *)todo,
+                           (const int32_t *)todo_count, box_fail);
     } else {
         hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 16384)), dim3(256), 0, st, n,
-                           g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, (const int32_t *)nullptr,
-                           (const int32_t *)nullptr);
+                           g, sx, sy, sz, sid, start, nbr_id, nbr_rel, (const int32_t *)nullptr,
+                           (const int32_t *)nullptr, box_fail);
     }
 }
 void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double *sy, const double *sz,
-                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
-                int32_t *todo, int32_t *todo_count, hipStream_t st) {
+                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *todo,
+                int32_t *todo_count, int32_t *box_fail, hipStream_t st) {
     if (nk == VK)
-        launch_knn_nk<VK>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, todo, todo_count, st);
+        launch_knn_nk<VK>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, todo, todo_count, box_fail, st);
     else
-        launch_knn_nk<KMAX>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, knn_out, todo, todo_count, st);
+        launch_knn_nk<KMAX>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, todo, todo_count, box_fail, st);
 }
 void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_t *vf, uint32_t *vlive,
-                    double *nbr_rel, int32_t *nbr_id, hipStream_t st) {
+                    double *nbr_rel, int32_t *nbr_id, const int32_t *box_fail, hipStream_t st) {
     const unsigned grid = (unsigned)xcd_pad((n + VB - 1) / VB);
-    hipLaunchKernelGGL(k_voronoi_hull, dim3(grid), dim3(VB), 0, st, n, rel18, id18, vf, vlive);
+    hipLaunchKernelGGL(k_voronoi_hull, dim3(grid), dim3(VB), 0, st, n, rel18, id18, vf, vlive, box_fail);
     hipLaunchKernelGGL(k_voronoi_order, dim3(grid), dim3(VB), 0, st, n, rel18, id18, (const uint32_t *)vf,
-                       (const uint32_t *)vlive, nbr_rel, nbr_id);
+                       (const uint32_t *)vlive, nbr_rel, nbr_id, box_fail);
 }
 // Both precision forms use the FP32-storage hull kernel: every predicate is
 // exact (a filter on the FP32 copies decides only when its bound proves the
@@ -2634,32 +2686,33 @@ void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_
 // the exact path run on the originals), so the hulls, codes and labellings
 // are those of the FP64 kernel, with half the LDS per lane.
 void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
-                 int32_t *code, uint64_t *ord, hipStream_t st) {
+                 int32_t *code, uint64_t *ord, const int32_t *box_fail, hipStream_t st) {
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
-    hipLaunchKernelGGL(k_topo, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord);
+    hipLaunchKernelGGL(k_topo, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord, box_fail);
 }
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
-                 hipStream_t st) {
+                 const int32_t *box_fail, hipStream_t st) {
     unsigned nb = (unsigned)((pair_slots(n) / NGRP + 1 + 255) / 256);
-    hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt);
+    hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt, box_fail);
     size_t tmp = W.scan_tmp_bytes;
     (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, pair_slots(n) + 1, st);
     hipLaunchKernelGGL(k_cand_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, code, mask, W.off,
-                       W.cap, W.pairs);
+                       W.cap, W.pairs, box_fail);
 }
 void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
-                 bool f32, hipStream_t st) {
+                 bool f32, const int32_t *box_fail, hipStream_t st) {
     if (f32)
         hipLaunchKernelGGL(k_cand_eval<float>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs,
-                           W.r, (float *)W.qs);
+                           W.r, (float *)W.qs, box_fail);
     else
         hipLaunchKernelGGL(k_cand_eval<double>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap,
-                           W.pairs, W.r, (double *)W.qs);
+                           W.pairs, W.r, (double *)W.qs, box_fail);
 }
 void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
                    const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
                    uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
-                   int32_t *todo_count, bool f32, hipStream_t st) {
+                   int32_t *todo_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail, bool f32,
+                   hipStream_t st) {
     dim3 gd((unsigned)((n + MB - 1) / MB));
     // the full rule holds one wave per SIMD (its registers): 256 blocks of
     // four waves fill the chip, and a few left-over atoms do not pay for a
@@ -2667,14 +2720,16 @@ void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, cons
     dim3 gf((unsigned)std::min<int64_t>((n + MB / 64 - 1) / (MB / 64), 256));
     if (f32) {
         hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
-                           W.cap, W.pairs, W.r, (const float *)W.qs, cutoff, O, todo, todo_count);
+                           W.cap, W.pairs, W.r, (const float *)W.qs, cutoff, O, todo, todo_count, knn_src, knn_out,
+                           box_fail);
         hipLaunchKernelGGL(k_decide_full<float>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
-                           mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count);
+                           mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count, box_fail);
     } else {
         hipLaunchKernelGGL(k_decide<double>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
-                           W.off, W.cap, W.pairs, W.r, (const double *)W.qs, cutoff, O, todo, todo_count);
+                           W.off, W.cap, W.pairs, W.r, (const double *)W.qs, cutoff, O, todo, todo_count, knn_src,
+                           knn_out, box_fail);
         hipLaunchKernelGGL(k_decide_full<double>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code,
-                           ord, mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count);
+                           ord, mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count, box_fail);
     }
 }
 

@@ -68,37 +68,44 @@ void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, co
 // leaves in todo (n entries) / *todo_count (zeroed by the caller).
 bool knn_fast_applies(const Grid &g);
 // nk = 14 (Euclidean ordering) or VK = 18 (input of the topological
-// ordering) nearest neighbours, rank-major [nk][n] / [nk][3][n]; knn_out
-// receives the first 14 ([n][14])
+// ordering) nearest neighbours, rank-major [nk][n] / [nk][3][n].  *box_fail
+// (zeroed by the caller) is set when the frame has a periodic axis and some
+// atom's nk-th neighbour is not strictly closer than half a periodic length
+// (or it has fewer than nk neighbours); every later stage then does nothing.
 void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double *sy, const double *sz,
-                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *knn_out,
-                int32_t *todo, int32_t *todo_count, hipStream_t st);
+                const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *todo,
+                int32_t *todo_count, int32_t *box_fail, hipStream_t st);
 // topological order (Sec. 3) of the 18 neighbours in rel18 / id18: the first
 // 14 go to nbr_rel / nbr_id
 // (vf: [32][n] facet words, vlive: [n] facet masks, scratch between the two kernels)
 void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_t *vf, uint32_t *vlive,
-                    double *nbr_rel, int32_t *nbr_id, hipStream_t st);
+                    double *nbr_rel, int32_t *nbr_id, const int32_t *box_fail, hipStream_t st);
 // hulls of the first 6 / 12 / 14 neighbours (need: bit g for group g);
 // code ids and labellings into code / ord [group][n]
 void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
-                 int32_t *code, uint64_t *ord, hipStream_t st);
+                 int32_t *code, uint64_t *ord, const int32_t *box_fail, hipStream_t st);
 // match stage: candidate pair list, superposition of every pair, decision
 void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
-                 hipStream_t st);
+                 const int32_t *box_fail, hipStream_t st);
 void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
-                 bool f32, hipStream_t st);
+                 bool f32, const int32_t *box_fail, hipStream_t st);
 // decision: common atoms, then those left in todo / *todo_count (zeroed by
-// the caller) by the full rule
+// the caller) by the full rule; knn_out (nullable, [n][14] in input order)
+// receives the first 14 rows of knn_src (the Euclidean ids, rank-major)
 void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
                    const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
                    uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
-                   int32_t *todo_count, bool f32, hipStream_t st);
+                   int32_t *todo_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail, bool f32,
+                   hipStream_t st);
 
 // post-hoc cut-off and RMSD histograms (counts: device, 6 * nbins, zeroed by the caller)
 void launch_apply_cutoff(int64_t n, const int8_t *best_type, const double *rmsd, double cutoff, int8_t *type,
                          hipStream_t st);
 void launch_rmsd_histogram(int64_t n, const int8_t *best_type, const double *rmsd, int nbins, double rmax,
                            unsigned long long *counts, hipStream_t st);
+// self-check: the strain of one match (template t, K relative vectors rel
+// [K][3] in template-vertex order, device pointers) in the working precision
+void launch_selftest_strain(const TablesView &T, int t, bool f32, const double *rel, double *P, hipStream_t st);
 // misorientation angles of orientation pairs under each template's symmetry
 void launch_misorientation(int64_t n, const TablesView &T, const int8_t *type, const double *q1, const double *q2,
                            double *angle, hipStream_t st);

@@ -179,6 +179,7 @@ static ptm_status serve_init(ptm_ctx *ctx) {
     PTM_HIP(ctx, hipStreamCreateWithFlags(&ctx->bounds_stream, hipStreamNonBlocking));
     PTM_HIP(ctx, hipMalloc(&ctx->bounds_part, 8 * 7 * (size_t)bounds_blocks(PTM_MAX_ATOMS)));
     // reference point of the device timeline on the host clock
+    PTM_HIP(ctx, hipEventCreateWithFlags(&ctx->order_event, hipEventDisableTiming));
     PTM_HIP(ctx, hipEventCreate(&ctx->ref_event));
     PTM_HIP(ctx, hipEventRecord(ctx->ref_event, ctx->bounds_stream));
     PTM_HIP(ctx, hipEventSynchronize(ctx->ref_event));
@@ -188,13 +189,15 @@ static ptm_status serve_init(ptm_ctx *ctx) {
 
 // Size class of a frame's scratch: the next power of two (at least 1 MiB)
 // of an upper bound of its bytes that holds for any cell grid make_grid
-// may choose (at most 4n + 4096 cells).
-static size_t scratch_class(int64_t n, bool topo) {
+// may choose (at most 4n + 4096 cells), with the scan space of both scans
+// FrameScratch::reserve sizes (cell counts, candidate counts).
+static size_t scratch_class(int64_t n, bool topo, int64_t cap) {
     int64_t cells = 4 * n + 4096;
     size_t tmp = 0, tmp2 = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int32_t *)nullptr, (int32_t *)nullptr, (int)(cells + 1));
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2, (int64_t *)nullptr, (int64_t *)nullptr, (int)(n + 1));
-    size_t need = frame_bytes(n, cells, bounds_blocks(n), std::max(tmp, tmp2), topo);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2, (int64_t *)nullptr, (int64_t *)nullptr,
+                                           pair_slots(n) + 1);
+    size_t need = frame_bytes(n, cells, bounds_blocks(n), std::max(tmp, tmp2), topo, cap);
     size_t c = (size_t)1 << 20;
     while (c < need) c <<= 1;
     return c;
@@ -232,6 +235,7 @@ static ptm_status take_scratch(ptm_ctx *ctx, size_t c, FrameScratch &out) {
         return PTM_E_NOMEM;
     }
     out.bytes = c;
+    out.pooled = true;
     ctx->pool_bytes += c;
     return PTM_OK;
 }
@@ -259,6 +263,8 @@ void serve_shutdown(ptm_ctx *ctx) {
     ctx->bounds_part = nullptr;
     if (ctx->ref_event) (void)hipEventDestroy(ctx->ref_event);
     ctx->ref_event = nullptr;
+    if (ctx->order_event) (void)hipEventDestroy(ctx->order_event);
+    ctx->order_event = nullptr;
     for (auto s : ctx->serve_streams) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
@@ -293,6 +299,10 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
     T->job.topo = (ctx->flags & PTM_F_TOPOLOGICAL) != 0;
     if (n_atoms > 0) {
         hipStream_t bst = ctx->bounds_stream;
+        // the frame starts after the work already queued on the context's
+        // stream (which may have written its inputs)
+        PTM_HIP(ctx, hipEventRecord(ctx->order_event, ctx->stream));
+        PTM_HIP(ctx, hipStreamWaitEvent(bst, ctx->order_event, 0));
         // bounds first (synchronous on the bounds stream): the grid depends on them
         st = stage_in_buffers(ctx, T->staging, positions, species, out, n_atoms, T->job, T->stage, bst);
         double mn[3], mx[3];
@@ -308,10 +318,11 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
         if (st == PTM_OK) {
             T->job.grid = make_grid(box, mn, mx, n_atoms, T->job.topo ? VK : KMAX);
             cells = (int64_t)T->job.grid.nc[0] * T->job.grid.nc[1] * T->job.grid.nc[2];
-            T->footprint = scratch_class(n_atoms, T->job.topo);
+            const int64_t cap = pair_capacity(n_atoms, ctx->pair_cap);
+            T->footprint = scratch_class(n_atoms, T->job.topo, cap);
             st = take_scratch(ctx, T->footprint, T->scratch);
+            if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, T->job.topo, cap, ctx->err)) st = PTM_E_DEVICE;
         }
-        if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, T->job.topo, ctx->err)) st = PTM_E_NOMEM;
         if (st != PTM_OK) {
             if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);
             T->staging.release();
@@ -324,7 +335,8 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
         hipStream_t s = ctx->serve_streams[T->stream];
         T->t_start = now_us();
         st = enqueue_frame(ctx, T->scratch, T->job, s);
-        if (st == PTM_OK) st = stage_out(ctx, out, n_atoms, T->job, T->stage, s);
+        // (host outputs are copied back by ptm_wait once the box flag is
+        // known to be clear: nothing is written for a rejected frame)
         if (st == PTM_OK && hipEventCreate(&T->done) != hipSuccess) st = PTM_E_DEVICE;
         if (st == PTM_OK && hipEventRecord(T->done, s) != hipSuccess) st = PTM_E_DEVICE;
         if (st != PTM_OK) {
@@ -370,7 +382,22 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
         else
             T->t_complete = now_us();
         T->complete = true;
+        // the frame's box flag (its kernels are done; read on the side stream)
+        *ctx->pinned = 0;
+        PTM_HIP(ctx, hipMemcpyAsync(ctx->pinned, box_flag(T->scratch, T->job.grid), 4, hipMemcpyDeviceToHost,
+                                    ctx->bounds_stream));
+        PTM_HIP(ctx, hipStreamSynchronize(ctx->bounds_stream));
+        T->box_fail = *ctx->pinned != 0;
+        if (!T->box_fail && T->stage.active) {
+            hipStream_t s = ctx->serve_streams[T->stream];
+            ptm_status so = stage_out(ctx, &T->stage.host_out, T->job.n, T->job, T->stage, s);
+            if (so == PTM_OK) PTM_HIP(ctx, hipStreamSynchronize(s));
+            if (so != PTM_OK) return so;
+            T->t_complete = now_us();  // the outputs are in host memory only now
+        }
     }
+    const bool box_fail = T->box_fail;
+    const bool topo = T->job.topo;
     if (stats) {
         stats->submit_time_us = T->t_submit;
         stats->start_time_us = T->t_start;
@@ -381,6 +408,10 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
     retire(ctx, T);
     delete T;
     ctx->tickets.erase(it);
+    if (box_fail) {
+        ctx->err = box_message(topo);
+        return PTM_E_BOX;
+    }
     return PTM_OK;
 }
 

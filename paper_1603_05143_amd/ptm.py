@@ -27,7 +27,7 @@ ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", 
 
 class ptm_config(C.Structure):
     _fields_ = [("device", C.c_int), ("precision", C.c_int), ("hip_stream", C.c_void_p),
-                ("hbm_budget_bytes", C.c_uint64), ("flags", C.c_uint32)]
+                ("hbm_budget_bytes", C.c_uint64), ("flags", C.c_uint32), ("pair_capacity", C.c_int64)]
 
 
 OUTPUT_FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn",
@@ -100,8 +100,8 @@ def ptm_last_error(ctx) -> str:
     return lib().ptm_last_error(ctx).decode()
 
 
-def ptm_create(device=0, precision=PTM_FP64, hip_stream=None, hbm_budget_bytes=0, flags=0):
-    cfg = ptm_config(device, precision, hip_stream, hbm_budget_bytes, flags)
+def ptm_create(device=0, precision=PTM_FP64, hip_stream=None, hbm_budget_bytes=0, flags=0, pair_capacity=0):
+    cfg = ptm_config(device, precision, hip_stream, hbm_budget_bytes, flags, pair_capacity)
     ctx = C.c_void_p()
     st = lib().ptm_create(C.byref(cfg), C.byref(ctx))
     if st != PTM_OK:
@@ -183,12 +183,18 @@ class Classifier:
     """Owns a context; classifies torch tensors resident on the GPU."""
 
     def __init__(self, device: int = 0, precision: int = PTM_FP64, hbm_budget_bytes: int = 0,
-                 topological: bool = False):
-        import torch  # noqa: F401  (loads the HIP runtime the library shares)
+                 topological: bool = False, pair_capacity: int = 0):
+        import torch
         self.device = device
         self.precision = precision
         self.topological = topological
-        self.ctx = ptm_create(device, precision, None, hbm_budget_bytes, PTM_F_TOPOLOGICAL if topological else 0)
+        # the library runs on a torch stream of its own, which waits for the
+        # caller's current stream before every call (inputs written by torch
+        # kernels still in flight; output blocks the caching allocator handed
+        # out on that stream)
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = ptm_create(device, precision, self.stream.cuda_stream, hbm_budget_bytes,
+                              PTM_F_TOPOLOGICAL if topological else 0, pair_capacity)
 
     def close(self):
         if self.ctx is not None:
@@ -242,6 +248,7 @@ class Classifier:
         if species is not None:
             assert species.is_cuda and species.dtype == torch.int8 and species.is_contiguous()
             sp = species.data_ptr()
+        self.stream.wait_stream(torch.cuda.current_stream(positions.device))
         st = ptm_classify(self.ctx, positions.data_ptr() if n else None, sp, box, n, mask, cutoff,
                           self.outputs_struct(out))
         if st != PTM_OK:
@@ -254,6 +261,7 @@ class Classifier:
         import torch
         n = out["rmsd"].shape[0]
         t = torch.empty(n, dtype=torch.int8, device=out["rmsd"].device)
+        self.stream.wait_stream(torch.cuda.current_stream(t.device))
         st = ptm_apply_cutoff(self.ctx, out["best_type"].data_ptr() if n else None,
                               out["rmsd"].data_ptr() if n else None, n, cutoff, t.data_ptr() if n else None)
         if st != PTM_OK:
@@ -263,7 +271,9 @@ class Classifier:
     def rmsd_histogram(self, out, nbins, rmax):
         """Per-type RMSD histograms (6 x nbins int64 numpy array)."""
         import numpy as np
+        import torch
         n = out["rmsd"].shape[0]
+        self.stream.wait_stream(torch.cuda.current_stream(out["rmsd"].device))
         st, counts = ptm_rmsd_histogram(self.ctx, out["best_type"].data_ptr() if n else None,
                                         out["rmsd"].data_ptr() if n else None, n, nbins, rmax)
         if st != PTM_OK:

@@ -238,3 +238,37 @@ def test_superpose_f32_within_stated_tolerances(ptm, oracle_lib):
                 assert abs(s.value - s1) < 1e-6 * s1
                 if sig < 1.0:
                     assert quat_angle(q, q1) < 1e-5
+
+
+def planted_shell(oracle_lib, t, rng, flip):
+    """Observed points x' = F x of template t (centre at the origin), with
+    det F < 0 when flip."""
+    w = oracle_lib.template(t)["w"]
+    eps = rng.uniform(-0.2, 0.2, size=(3, 3))
+    F = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    F = F * np.sign(np.linalg.det(F)) @ (np.eye(3) + eps)
+    if flip:
+        F = F @ np.diag([1.0, 1.0, -1.0])
+    return np.ascontiguousarray(np.vstack([np.zeros(3), w * 2.4]) @ F.T + rng.normal(size=3)), F
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 2e-6)])
+def test_selftest_strain_agrees_with_oracle(ptm, oracle_lib, precision, tol):
+    """Sec. 8 strain (eq. (6) fit, polar factor with a right-handed U) of the
+    library's arithmetic, host-compiled, against the oracle -- including
+    reflected shells (det A < 0), where P carries a negative eigenvalue."""
+    L = ptm.lib()
+    L.ptm_selftest_strain.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    rng = np.random.default_rng(61)
+    for t in range(5):
+        for flip in (False, True):
+            for _ in range(4):
+                obs, F = planted_shell(oracle_lib, t, rng, flip)
+                P = np.zeros(9)
+                assert L.ptm_selftest_strain(t, precision, obs.ctypes.data, P.ctypes.data) == 0
+                ref = oracle_lib.strain(t, obs)
+                assert np.max(np.abs(P.reshape(3, 3) - ref)) <= tol, (t, flip)
+                assert (np.linalg.det(P.reshape(3, 3)) < 0) == flip
+    P = np.zeros(9)
+    assert L.ptm_selftest_strain(5, 0, obs.ctypes.data, P.ctypes.data) == -1
+    assert L.ptm_selftest_strain(0, 2, obs.ctypes.data, P.ctypes.data) == -1

@@ -38,9 +38,9 @@ def _frame(seed):
         F = np.eye(3) + rng.normal(scale=0.02, size=(3, 3))
         pos = (f.positions[keep] - f.box / 2) @ (F @ R).T + rng.normal(scale=0.05, size=(int(keep.sum()), 3))
         box = np.zeros(3)
-    elif kind == 3:  # tiny periodic box (fewer than five cells per axis)
+    elif kind == 3:  # small periodic box (fewer than five cells per axis); too short for the shell once
         k = ["fcc", "bcc"][int(rng.integers(0, 2))]
-        f = S.perfect_crystal(k, reps=(2, 2, 3), a=3.615 if k == "fcc" else 2.87)
+        f = S.perfect_crystal(k, reps=(2, 2, 3) if seed == 3 else (3, 3, 3), a=3.615 if k == "fcc" else 2.87)
         pos = f.positions + rng.normal(scale=0.08, size=f.positions.shape)
         box = f.box
     elif kind == 4:  # slab with a vacuum gap, periodic in x, y
@@ -78,20 +78,28 @@ def test_fuzz(torch_cuda, oracle_lib, precision, topological):
     torch = torch_cuda
     tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
     c = ptm.Classifier(device=0, precision=precision, topological=topological)
+    rejected = 0
     try:
         for seed in range(24):
             pos, box, species, label = _frame(seed)
             print(f"[fuzz] seed={seed} {label} n={len(pos)} box={box.tolist()} topo={topological}", flush=True)
             dpos = torch.from_numpy(pos).to("cuda:0")
             sp = None if species is None else torch.from_numpy(species).to("cuda:0")
+            ref = oracle_lib.classify(pos, box, species=species,
+                                      ordering="topological" if topological else "euclidean", allow_box=True)
+            if not ref["box_ok"]:  # the periodic box is too short for the neighbour shell
+                with pytest.raises(ptm.PTMError) as e:
+                    c.classify(dpos, box, species=sp, knn=True)
+                assert e.value.status == ptm.PTM_E_BOX
+                rejected += 1
+                continue
             out = c.classify(dpos, box, species=sp, knn=True)
             torch.cuda.synchronize()
             got = {k: out[k].cpu().numpy() for k in FIELDS}
-            ref = oracle_lib.classify(pos, box, species=species,
-                                      ordering="topological" if topological else "euclidean")
             sure = ~(ref["tmargin"] < 1e-6)
             assert np.sum(~sure) <= 2, (seed, np.sum(~sure))
             compare({k: v[sure] for k, v in got.items()}, {k: ref[k][sure] for k in FIELDS}, tol=tol,
                     check_alloy=species is not None, label=f"seed {seed} {label} ")
+        assert rejected >= 1
     finally:
         c.close()

@@ -145,12 +145,171 @@ def test_pair_tile_boundaries(torch_cuda, clf, oracle_lib, n):
     compare(got, ref)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 13, 15])
-def test_tiny_systems(torch_cuda, clf, oracle_lib, n):
+def expect_box_error(torch, clf, frame, **kw):
+    """The frame's periodic box is too short for its neighbour shell: the
+    call fails with PTM_E_BOX and leaves every output untouched."""
+    pos = torch.from_numpy(np.ascontiguousarray(frame.positions)).to("cuda:0")
+    out = clf.alloc_outputs(frame.n, "cuda:0", knn=True, derived=True)
+    for v in out.values():
+        v.fill_(7)
+    torch.cuda.synchronize()
+    with pytest.raises(ptm.PTMError) as e:
+        clf.classify(pos, frame.box, out=out, **kw)
+    assert e.value.status == ptm.PTM_E_BOX, e.value
+    torch.cuda.synchronize()
+    for k, v in out.items():
+        assert bool((v == 7).all()), f"{k} written on PTM_E_BOX"
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 13, 15, 40])
+def test_tiny_periodic_systems_rejected(torch_cuda, clf, oracle_lib, n):
+    """Periodic boxes holding too few atoms for a 14-neighbour shell within
+    half a box length: the oracle rejects them, and so does the library."""
     rng = np.random.default_rng(n)
     f = S.Frame(positions=rng.random((n, 3)) * 6.0, box=np.array([6.0, 6.0, 6.0]))
+    with pytest.raises(oracle_lib.BoxError):
+        run_ref(oracle_lib, f)
+    expect_box_error(torch_cuda, clf, f)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 13, 15])
+def test_tiny_open_systems(torch_cuda, clf, oracle_lib, n):
+    rng = np.random.default_rng(n)
+    f = S.Frame(positions=rng.random((n, 3)) * 6.0, box=np.zeros(3))
     got = run_gpu(torch_cuda, clf, f)
     ref = run_ref(oracle_lib, f)
+    compare(got, ref)
+
+
+@pytest.mark.parametrize("ordering", ["euclidean", "topological"])
+def test_box_rule_matches_oracle(torch_cuda, oracle_lib, ordering):
+    """Small periodic gases and crystals around the limit: the library
+    rejects a frame exactly when the oracle's rule (14th, or 18th,
+    neighbour strictly inside half of every periodic length) fails, and
+    otherwise classifies it as the oracle does."""
+    torch = torch_cuda
+    rng = np.random.default_rng(5 if ordering == "euclidean" else 6)
+    frames = []
+    for n in (20, 24, 28, 32, 40, 60):
+        L = (n / 0.085) ** (1 / 3)
+        frames.append(S.Frame(positions=rng.random((n, 3)) * L, box=np.array([L, L, L])))
+    for kind, reps, a in (("sc", (2, 2, 2), 2.6), ("sc", (3, 3, 3), 2.6), ("bcc", (3, 3, 3), 2.87),
+                          ("fcc", (3, 3, 3), 3.615)):
+        f = S.perfect_crystal(kind, reps, a=a)
+        f.positions = f.positions + rng.normal(scale=0.1, size=f.positions.shape)
+        frames.append(f)
+    seen = set()
+    for prec in (ptm.PTM_FP64, ptm.PTM_FP32_MIXED):
+        c = ptm.Classifier(device=0, precision=prec, topological=ordering == "topological")
+        try:
+            for f in frames:
+                print(f"[box] n={f.n} box={f.box.tolist()} {ordering} prec={prec}", flush=True)
+                ref = oracle_lib.classify(f.positions, f.box, ordering=ordering, allow_box=True)
+                seen.add(ref["box_ok"])
+                if ref["box_ok"]:
+                    pos = torch.from_numpy(np.ascontiguousarray(f.positions)).to("cuda:0")
+                    out = c.classify(pos, f.box, knn=True)
+                    torch.cuda.synchronize()
+                    got = {k: v.cpu().numpy() for k, v in out.items()}
+                    sure = ~(ref["tmargin"] < 1e-6)
+                    _compare({k: v[sure] for k, v in got.items()}, {k: ref[k][sure] for k in got},
+                             tol=TOL64 if prec == ptm.PTM_FP64 else TOL32)
+                else:
+                    expect_box_error(torch, c, f)
+        finally:
+            c.close()
+    assert seen == {True, False}
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_strain_right_handed_on_device(torch_cuda, oracle_lib, precision):
+    """Sec. 8 strain by the decision kernels' device code (eq. (6) fit, polar
+    factor with U right-handed) against the oracle, on planted deformations
+    of every template, reflected ones (det A < 0, P with a negative
+    eigenvalue) included.  No classified atom of the synthetic inputs has
+    det A <= 0 (orientation-preserving hull correspondences keep the fit's
+    handedness), so the branch is driven through this entry point."""
+    import ctypes as C
+    L = ptm.lib()
+    L.ptm_selftest_strain_device.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    tol = 1e-11 if precision == ptm.PTM_FP64 else 5e-6
+    ctx = ptm.ptm_create(0, precision)
+    try:
+        rng = np.random.default_rng(62)
+        for t in range(5):
+            w = oracle_lib.template(t)["w"]
+            for flip in (False, True):
+                for _ in range(3):
+                    F = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+                    F = F * np.sign(np.linalg.det(F)) @ (np.eye(3) + rng.uniform(-0.2, 0.2, (3, 3)))
+                    if flip:
+                        F = F @ np.diag([1.0, 1.0, -1.0])
+                    obs = np.ascontiguousarray(np.vstack([np.zeros(3), w * 2.4]) @ F.T + rng.normal(size=3))
+                    P = np.zeros(9)
+                    st = L.ptm_selftest_strain_device(ctx, t, obs.ctypes.data, P.ctypes.data)
+                    assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+                    ref = oracle_lib.strain(t, obs)
+                    assert np.max(np.abs(P.reshape(3, 3) - ref)) <= tol, (t, flip)
+                    assert (np.linalg.det(P.reshape(3, 3)) < 0) == flip
+    finally:
+        ptm.ptm_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+@pytest.mark.parametrize("share", [0.25, 0.7])
+def test_pair_capacity_overflow_path(torch_cuda, oracle_lib, precision, share):
+    """A candidate pair list capped below what the frame needs (a test-only
+    ptm_config field): the atoms past the capacity are decided by the full
+    rule, and every output still equals the oracle's."""
+    torch = torch_cuda
+    f = S.polycrystal(L=34.0, n_grains=4, sigma=0.12, seed=71)
+    ref = oracle_lib.classify(f.positions, f.box)
+    probe = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE)
+    pos = torch.from_numpy(f.positions).to("cuda:0")
+    try:
+        out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
+        assert ptm.ptm_classify(probe, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, math.inf,
+                                ptm.Classifier.outputs_struct(out)) == ptm.PTM_OK
+        pairs = ptm.ptm_frame_info(probe)["pairs"]
+    finally:
+        ptm.ptm_destroy(probe)
+    cap = int(pairs * share)
+    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE, cap)
+    try:
+        out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
+        st = ptm.ptm_classify(ctx, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, math.inf,
+                              ptm.Classifier.outputs_struct(out))
+        assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+        torch.cuda.synchronize()
+        info = ptm.ptm_frame_info(ctx)
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+    finally:
+        ptm.ptm_destroy(ctx)
+    print("capacity", cap, "of", pairs, info, flush=True)
+    assert info["pairs"] == cap and info["decide_full"] > 0.3 * (1 - share) * f.n
+    _compare(got, ref, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32)
+
+
+def test_inputs_written_by_torch_just_before(torch_cuda, oracle_lib):
+    """Positions produced by a torch kernel queued on the caller's stream
+    right before the call (behind a long matrix product): the library's
+    work waits for them."""
+    torch = torch_cuda
+    f = S.polycrystal(L=30.0, n_grains=3, sigma=0.1, seed=72)
+    ref = oracle_lib.classify(f.positions, f.box)
+    c = ptm.Classifier(device=0, precision=ptm.PTM_FP64)
+    try:
+        base = torch.from_numpy(f.positions).to("cuda:0")
+        big = torch.randn(4096, 4096, device="cuda:0")
+        torch.cuda.synchronize()
+        for _ in range(3):
+            big = big @ big
+            big = big / big.norm()
+        pos = (base * 2.0 - base).contiguous()  # the same values, written by a kernel behind the products
+        out = c.classify(pos, f.box, knn=True)
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+    finally:
+        c.close()
     compare(got, ref)
 
 

@@ -151,3 +151,64 @@ def test_empty_frame_ticket(torch_cuda):
         assert st == ptm.PTM_OK and s.n_atoms == 0
     finally:
         ptm.ptm_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_mixed_equals_oracle(torch_cuda, oracle_lib, frames, precision):
+    """The frames submitted together, overlapping on the device, against the
+    FP64 oracle frame by frame: decisions bit-exact, reals within the form's
+    tolerance."""
+    from parity_util import TOL32, TOL64, compare
+    torch = torch_cuda
+    ctx = ptm.ptm_create(0, precision, None, 0, 0)
+    try:
+        keep, tickets = _submit_all(torch, ctx, frames)
+        for t in tickets:
+            st, _ = ptm.ptm_wait(ctx, t, -1)
+            assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+        for (pos, sp, out, o), f in zip(keep, frames):
+            print(f"[serve-oracle] n={f.n} precision={precision}", flush=True)
+            got = {k: out[k].cpu().numpy() for k in FIELDS}
+            ref = oracle_lib.classify(f.positions, f.box, species=f.species)
+            compare(got, {k: ref[k] for k in FIELDS}, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32,
+                    check_alloy=f.species is not None, label=f"serving n={f.n} ")
+    finally:
+        ptm.ptm_destroy(ctx)
+
+
+def test_box_error_in_the_stream(torch_cuda, oracle_lib, frames):
+    """A frame whose periodic box is too short for its neighbour shell,
+    submitted between others: its ticket reports PTM_E_BOX and its outputs
+    stay untouched; the frames around it are unaffected."""
+    torch = torch_cuda
+    rng = np.random.default_rng(5)
+    bad = S.Frame(positions=rng.random((20, 3)) * 6.0, box=np.array([6.0, 6.0, 6.0]))
+    with pytest.raises(oracle_lib.BoxError):
+        oracle_lib.classify(bad.positions, bad.box)
+    mix = [frames[0], bad, frames[2]]
+    ref = _alone(torch, ptm.PTM_FP64, [frames[0], frames[2]])
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    try:
+        keep, tickets = [], []
+        for f in mix:
+            pos, sp = _device_frame(torch, f)
+            out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True, derived=True)
+            for v in out.values():
+                v.fill_(7)
+            torch.cuda.synchronize()
+            o = ptm.Classifier.outputs_struct(out)
+            st, t = ptm.ptm_submit(ctx, pos.data_ptr(), None if sp is None else sp.data_ptr(), f.box, f.n,
+                                   ptm.PTM_ALL, math.inf, o)
+            assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+            keep.append((pos, sp, out, o))
+            tickets.append(t)
+        status = [ptm.ptm_wait(ctx, t, -1)[0] for t in tickets]
+        assert status == [ptm.PTM_OK, ptm.PTM_E_BOX, ptm.PTM_OK]
+        torch.cuda.synchronize()
+        for k, v in keep[1][2].items():
+            assert bool((v == 7).all()), k
+        for (pos, sp, out, o), r in zip((keep[0], keep[2]), ref):
+            for k in out:
+                assert np.array_equal(out[k].cpu().numpy(), r[k], equal_nan=True), k
+    finally:
+        ptm.ptm_destroy(ctx)

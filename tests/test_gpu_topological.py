@@ -90,9 +90,10 @@ def test_free_surfaces(torch_cuda, clf, oracle_lib):
     assert np.sum(got["type"] == 0) > 100  # surface atoms
 
 
-@pytest.mark.parametrize("kind,reps,a", [("fcc", (3, 3, 3), 3.615), ("bcc", (3, 3, 3), 2.87), ("sc", (4, 4, 4), 2.6)])
+@pytest.mark.parametrize("kind,reps,a", [("fcc", (3, 3, 3), 3.615), ("bcc", (4, 4, 4), 2.87), ("sc", (4, 4, 4), 2.6)])
 def test_small_periodic_boxes(torch_cuda, clf, oracle_lib, kind, reps, a):
-    """Boxes with fewer than five cells per axis: the wave-per-atom k-NN."""
+    """Boxes with fewer than five cells per axis: the wave-per-atom k-NN
+    (each long enough for the 18-neighbour shell)."""
     pos, box = _hot(kind, reps, a, 0.12, 5)
     ref = oracle_lib.classify(pos, box, ordering="topological")
     got = _gpu(torch_cuda, clf, pos, box)
