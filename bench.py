@@ -3,16 +3,23 @@
 
 One step = one ptm_classify call over the whole frame (bounds, binning,
 k-NN, three hulls + canonical codes, candidate superposition, decision,
-strain, alloy, write-back) with inputs and outputs resident in HBM.  The
-workload is the ~0.92 M-atom periodic Voronoi polycrystal (L = 220 A, 16
-grains of FCC/BCC/HCP, sigma = 0.10 A), all five templates enabled.
+strain, alloy, write-back) with inputs and outputs resident in HBM, all five
+templates enabled.  The headline workload is the single ~31.7 M-atom frame:
+a periodic BCC matrix (a = 2.87 A, L = 256 a, 1 % vacancies) with 200 Mackay
+icosahedra, 10 simple-cubic cubes and a liquid-like slab of 15 % of the
+volume, sigma = 0.15 A.  ``value`` is the FP64 plain form (the paper's
+method as it computes it); the FP32-mixed form is reported beside it.  The
+~4.03 M-atom ordered-alloy slabs (species) and the 0.92 M-atom polycrystal
+are measured as extra lines.
 
-Prints one JSON line.  ``roofline`` covers the dominant kernel, timed with
-HIP events on the stream its kernels run on; ``cpu_baseline`` times the FP64
-reference implementation on a bounded sample of the same frame; ``serving``
-reports the serving loop (ptm_submit / ptm_wait) on a stream of frames of
-uneven size: throughput when saturated and p50/p99 frame latency under
-Poisson arrivals at 0.7 x the FP64 plain capacity.
+Prints one JSON line.  ``roofline`` covers the dominant kernel of the
+headline run, timed with HIP events on the stream its kernels run on;
+``cpu_baseline`` times the FP64 reference implementation on bounded samples
+of the same frame (all host threads of the GPU's share and one thread, each
+with and without the neighbour search); ``serving`` reports the serving loop
+(ptm_submit / ptm_wait) on a stream of frames of uneven size: throughput when
+saturated and p50/p99 frame latency under Poisson arrivals at 0.7 x the FP64
+plain capacity.
 """
 from __future__ import annotations
 
@@ -33,11 +40,6 @@ STAGES = ("bounds", "bin", "knn", "topo", "cand", "eval", "decide")
 # FP32 without packed instructions (the library is built without them)
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
-
-# kernel(s) behind each single-kernel stage, for the roofline line
-STAGE_KERNEL = {"knn": "k_knn_fast<14> + k_knn_exact<14>", "topo": "k_topo", "eval": "k_cand_eval<float>",
-                "decide": "k_decide<float> + k_decide_full<float>"}
-
 
 def orient_tests(K: int) -> int:
     """Orientation tests of the incremental hull of K points: the first
@@ -96,17 +98,28 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(stage: str, precision: str):
+def _profile_rows(name: str):
+    """Rows of a summary table under profiles/ whose last column is the
+    kernel source digest of this tree (numbers taken on other code are
+    stale and ignored)."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return []
+    digest = kernel_source_digest()
+    rows = []
+    for line in open(path):
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cols) >= 4 and cols[-1] == digest:
+            rows.append(cols)
+    return rows
+
+
+def measured_traffic(workload: str, stage: str, precision: str):
     """HBM bytes per launch of a stage's kernel from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary under profiles/ (scaled by the copy-kernel
     calibration recorded there), or None if absent or taken on other sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_polycrystal_919k.md")
-    if not os.path.exists(path):
-        return None
-    digest = kernel_source_digest()
-    for line in open(path):
-        cols = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cols) >= 6 and cols[0] == stage and cols[1] in (precision, "both") and cols[5] == digest:
+    for cols in _profile_rows(f"hbm_traffic_{workload}.md"):
+        if len(cols) >= 6 and cols[0] == stage and cols[1] in (precision, "both"):
             try:
                 return float(cols[2]) + float(cols[3])
             except ValueError:
@@ -114,23 +127,52 @@ def measured_traffic(stage: str, precision: str):
     return None
 
 
-def build_frame(args):
+def measured_valu_issue(workload: str, stage: str, precision: str):
+    """Share of the vector units' issue slots the stage's kernel used
+    (SQ_INSTS_VALU per wave x waves / (SIMDs x clock x kernel time)) from the
+    rocprofv3 counter summary under profiles/, or None."""
+    for cols in _profile_rows(f"valu_issue_{workload}.md"):
+        if len(cols) >= 4 and cols[0] == stage and cols[1] in (precision, "both"):
+            try:
+                return float(cols[2])
+            except ValueError:
+                return None
+    return None
+
+
+# workloads: (key used by profiles/, description, generator)
+WORKLOADS = {
+    "mixed_31.7m": ("single periodic frame: BCC matrix a=2.87 A (L=256a, 1% vacancies), 200 Mackay icosahedra "
+                    "(55/147 atoms, nn 2.55 A), 10 simple-cubic cubes (a=2.6 A), 15%-volume liquid-like slab "
+                    "(2.2 A minimum distance), sigma 0.15 A, all templates", "mixed_frame"),
+    "alloy_slabs_4.0m": ("ordered-alloy slabs with int8 species: L1_2 A3B (3.57 A), L1_0 AB (3.85 A, c/a 0.97), "
+                         "B2 AB (2.88 A), random FCC; 2% antisites, 1% vacancies, sigma 0.25 A, all templates",
+                         "alloy_slabs"),
+    "polycrystal_919k": ("periodic Voronoi polycrystal, L=220 A, 16 grains FCC 3.615/BCC 2.87/HCP 2.51 "
+                         "(c/a 1.633), sigma 0.10 A, all templates", "polycrystal"),
+}
+
+
+def build_frame(key: str):
     from paper_1603_05143_amd import synthetic as S
     t = time.time()
-    f = S.polycrystal()
-    return f, time.time() - t
+    f = getattr(S, WORKLOADS[key][1])()
+    print(f"[bench] {key}: n={f.n} generated in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
+    return f
 
 
 def run_gpu(frame, precision, steps, warmup, flags=0):
     import torch
     from paper_1603_05143_amd import ptm
     pos = torch.from_numpy(frame.positions).to("cuda:0")
+    spc = None if frame.species is None else torch.from_numpy(frame.species).to("cuda:0")
     ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE | flags)
     out = ptm.Classifier.alloc_outputs(frame.n, "cuda:0")
     o = ptm.Classifier.outputs_struct(out)
 
     def step():
-        st = ptm.ptm_classify(ctx, pos.data_ptr(), None, frame.box, frame.n, ptm.PTM_ALL, math.inf, o)
+        st = ptm.ptm_classify(ctx, pos.data_ptr(), None if spc is None else spc.data_ptr(), frame.box, frame.n,
+                              ptm.PTM_ALL, math.inf, o)
         if st != ptm.PTM_OK:
             raise RuntimeError(ptm.ptm_last_error(ctx))
 
@@ -149,6 +191,8 @@ def run_gpu(frame, precision, steps, warmup, flags=0):
     info = ptm.ptm_frame_info(ctx)
     types = torch.bincount(out["type"].long(), minlength=6).cpu().tolist()
     ptm.ptm_destroy(ctx)
+    del out, pos, spc
+    torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     return {"ms_per_step": ms, "atoms_per_s": frame.n / (ms / 1e3),
             "stage_ms": {s: acc[i] / steps for i, s in enumerate(STAGES)}, "types": types, "info": info}
@@ -243,15 +287,47 @@ def _mono_us():
     return time.clock_gettime(time.CLOCK_MONOTONIC) * 1e6  # the clock of ptm_frame_stats
 
 
-def serving_bench(n_frames, pool_levels, ring, budget_gb, seed_shift=0):
+def _pool_frame(arg):
+    from threadpoolctl import threadpool_limits
+
+    from paper_1603_05143_amd import synthetic as S
+    n, seed = arg
+    with threadpool_limits(1):  # one BLAS thread per worker process
+        return S.serving_frame(n, seed=seed)
+
+
+def serving_pool(pool_levels):
+    """The distinct frames the serving stream draws from: log-spaced sizes in
+    [1e3, 2e6], each its own seeded polycrystal (grain count, phases from the
+    polycrystal and alloy workloads, noise U[0.02, 0.3] A).  Generated by
+    worker processes before this process touches the GPU."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from paper_1603_05143_amd import synthetic as S
+    levels = np.exp(np.linspace(math.log(1e3), math.log(2e6), pool_levels))
+    jobs = [(int(round(n)), S.BASE_SEED + 300 + k) for k, n in enumerate(levels)]
+    t = time.time()
+    # largest first, so the long ones do not finish last
+    order = sorted(range(len(jobs)), key=lambda k: -jobs[k][0])
+    with mp.get_context("fork").Pool(processes=min(cpu_threads(), 16)) as pl:
+        made = pl.map(_pool_frame, [jobs[k] for k in order], chunksize=1)
+    pool = [None] * len(jobs)
+    for k, f in zip(order, made):
+        pool[k] = f
+    print(f"[serve] pool of {len(pool)} frames ({sum(f.n for f in pool)} atoms) in {time.time() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    return pool
+
+
+def serving_bench(pool, n_frames, ring, budget_gb, seed_shift=0):
     """Serving loop on a stream of frames with log-uniform sizes in [1e3, 2e6].
 
-    Frames are drawn from a pool of ``pool_levels`` generated frames with
-    log-spaced sizes (each stream frame takes the pool frame nearest to its
-    size in log scale), so that generating the stream stays cheap; the pool
-    is resident on the device.  ``ring`` output sets bound the frames in
-    flight on the client side; admission on the library side is by the HBM
-    budget.  Latency = device completion time - scheduled arrival time.
+    Each stream frame is the pool frame nearest to its size in log scale
+    (the pool of distinct frames is resident on the device).  ``ring``
+    output sets bound the frames in flight on the client side; admission on
+    the library side is by the HBM budget.  Latency = device completion time
+    - scheduled arrival time.
     """
     import collections
 
@@ -260,11 +336,6 @@ def serving_bench(n_frames, pool_levels, ring, budget_gb, seed_shift=0):
     from paper_1603_05143_amd import ptm, synthetic as S
 
     sizes, _ = S.serving_stream(n_frames)
-    levels = np.exp(np.linspace(math.log(1e3), math.log(2e6), pool_levels))
-    t = time.time()
-    pool = [S.serving_frame(int(round(n)), seed=S.BASE_SEED + 300 + k) for k, n in enumerate(levels)]
-    print(f"[serve] pool of {len(pool)} frames ({sum(f.n for f in pool)} atoms) in {time.time() - t:.1f}s",
-          file=sys.stderr, flush=True)
     pick = np.argmin(np.abs(np.log(sizes)[:, None] - np.log([f.n for f in pool])[None, :]), axis=1)
     dev = [(torch.from_numpy(f.positions).to("cuda:0"), torch.from_numpy(f.species).to("cuda:0"), f)
            for f in pool]
@@ -346,35 +417,98 @@ def serving_bench(n_frames, pool_levels, ring, budget_gb, seed_shift=0):
     del outs, dev
     return {"frames": n_frames, "sizes": "log-uniform in [1e3, 2e6] atoms",
             "pool_frames": len(pool), "pool_atoms": int(sum(f.n for f in pool)),
+            "distinct_frames_used": int(len(np.unique(pick))),
             "rate_hz": rate, "budget_gb": budget_gb, "client_ring": ring,
             "latency_over": f"frames 51-{n_frames}" if n_frames > 100 else "all frames",
             "fp64": res["fp64"], "fp32_mixed": res["fp32_mixed"]}
 
 
-def cpu_baseline(frame, sample):
+def cpu_threads() -> int:
+    """Host threads: the CPUs this process may use, at most 16 (the host
+    share of one GPU on the machines this runs on)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(frame, label, sample_all, sample_one):
+    """The FP64 oracle as it stands on the GPU machine's host: all threads
+    of the share and one thread, each with its neighbour search timed and
+    without it (neighbours found first, untimed: the paper's Table 2 timing
+    excludes neighbour-list generation).  Seeded atom samples of the frame."""
     import numpy as np
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    threads = cpu_threads()
     rng = np.random.default_rng(2024)
-    atoms = np.sort(rng.choice(frame.n, sample, replace=False))
+    big = np.sort(rng.choice(frame.n, sample_all, replace=False))
+    small = np.sort(rng.choice(big, sample_one, replace=False))
     oracle.lib()
-    t = time.perf_counter()
-    oracle.classify(frame.positions, frame.box, atoms=atoms, threads=threads)
-    dt = time.perf_counter() - t
-    return {"value": sample / dt, "unit": "atoms/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample} seeded atoms of the {frame.n}-atom polycrystal, each classified "
-                      f"with brute-force neighbours over all atoms ({dt:.1f} s wall)"}
+    res = {}
+    for name, atoms, th in (("all_threads", big, threads), ("single_thread", small, 1)):
+        t = time.perf_counter()
+        oracle.classify(frame.positions, frame.box, species=frame.species, atoms=atoms, threads=th)
+        dt = time.perf_counter() - t
+        nb = oracle.neighbours(frame.positions, frame.box, atoms=atoms, threads=threads)
+        t = time.perf_counter()
+        oracle.classify_given(nb, atoms, frame.box, species=frame.species, threads=th)
+        dt2 = time.perf_counter() - t
+        res[name] = {"atoms_per_s": len(atoms) / dt, "atoms_per_s_without_knn": len(atoms) / dt2,
+                     "threads": th, "sample_atoms": int(len(atoms)), "wall_s": round(dt, 2),
+                     "wall_s_without_knn": round(dt2, 2)}
+        print(f"[bench] cpu oracle {name}: {res[name]}", file=sys.stderr, flush=True)
+    nproc = os.cpu_count()
+    return {"value": res["all_threads"]["atoms_per_s"], "unit": "atoms/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_all} seeded atoms of the {frame.n}-atom {label} on {threads} threads "
+                      f"({res['all_threads']['wall_s']} s wall; neighbours by the oracle's certified cell "
+                      f"search, brute force below 2e5 atoms); also {sample_one} of them on one thread, "
+                      f"and both without the neighbour search",
+            "host_cpus_visible": nproc,
+            "all_threads_without_knn": res["all_threads"]["atoms_per_s_without_knn"],
+            "single_thread": res["single_thread"]["atoms_per_s"],
+            "single_thread_without_knn": res["single_thread"]["atoms_per_s_without_knn"],
+            "detail": res}
+
+
+def roofline(run, n, stage_kernel, workload, precision):
+    """Roofline object of the stage with the largest device time."""
+    stage_ms = run["stage_ms"]
+    dom = max(stage_kernel, key=lambda st: stage_ms[st])
+    bound, work, unit = work_model(dom, n, run["info"])
+    t = stage_ms[dom] / 1e3
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": work / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": work / t / 1e12, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(workload, dom, precision)
+    roof["valu_issue_frac"] = measured_valu_issue(workload, dom, precision)
+    roof["kernel"] = stage_kernel[dom]
+    roof["kernel_ms"] = stage_ms[dom]
+    roof["work_per_launch"] = work
+    roof["work_unit"] = unit
+    return roof
+
+
+def line_of(run):
+    return {"atoms_per_s": run["atoms_per_s"], "ms_per_step": round(run["ms_per_step"], 4),
+            "stage_ms": {k: round(v, 4) for k, v in run["stage_ms"].items()}, "work_counts": run["info"]}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=30000)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--only", choices=("all", "headline", "fp64", "fp32"), default="all",
+                    help="headline: the 31.7 M-atom frame alone (both forms, or one with fp64 / fp32); "
+                         "for profiling runs")
+    ap.add_argument("--cpu-sample", type=int, default=100000, help="atoms of the all-threads CPU sample")
+    ap.add_argument("--cpu-sample-1t", type=int, default=6000, help="atoms of the one-thread CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-frames", type=int, default=2000)
-    ap.add_argument("--serve-pool", type=int, default=12)
+    ap.add_argument("--serve-pool", type=int, default=200)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 256 MiB device buffer (reference kernel for HBM counters)")
@@ -383,6 +517,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
+    pool = None
+    if args.only == "all" and not args.no_serve:
+        pool = serving_pool(args.serve_pool)
     import torch  # (loads the HIP runtime shared with libptm)
     from paper_1603_05143_amd import ptm
 
@@ -393,81 +530,101 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    frame, gen_s = build_frame(args)
-    print(f"[bench] frame n={frame.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
-    r64 = run_gpu(frame, ptm.PTM_FP64, args.steps, args.warmup)
-    print(f"[bench] fp64 {r64['ms_per_step']:.2f} ms/step {r64['stage_ms']}", file=sys.stderr, flush=True)
-    r32 = run_gpu(frame, ptm.PTM_FP32_MIXED, args.steps, args.warmup)
-    print(f"[bench] fp32-mixed {r32['ms_per_step']:.2f} ms/step {r32['stage_ms']}", file=sys.stderr, flush=True)
-    # headline: the FP32-mixed form (decisions identical to FP64, reals within
-    # the stated tolerances); the FP64 plain form is reported beside it
-    main_run = r32
-    dtype = "f32-mixed"
 
-    stage_ms = main_run["stage_ms"]
-    dom = max(STAGE_KERNEL, key=lambda st: stage_ms[st])
-    bound, work, unit = work_model(dom, frame.n, main_run["info"])
-    t = stage_ms[dom] / 1e3
-    if bound == "hbm":
-        roof = {"bound": "hbm", "achieved": work / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": work / t / 1e12, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, "fp32_mixed")
-    roof["kernel"] = STAGE_KERNEL[dom] + " in the FP32-mixed frame"
-    roof["kernel_ms"] = stage_ms[dom]
-    roof["work_per_launch"] = work
-    roof["work_unit"] = unit
-
-    # topological neighbour ordering (Sec. 3): the same frame, both forms;
-    # its Voronoi kernel runs inside the k-NN stage
-    t64 = run_gpu(frame, ptm.PTM_FP64, args.steps, args.warmup, ptm.PTM_F_TOPOLOGICAL)
-    t32 = run_gpu(frame, ptm.PTM_FP32_MIXED, args.steps, args.warmup, ptm.PTM_F_TOPOLOGICAL)
-    print(f"[bench] topological fp32-mixed {t32['ms_per_step']:.2f} ms/step, fp64 {t64['ms_per_step']:.2f}",
-          file=sys.stderr, flush=True)
-    topological = {
-        "fp32_mixed_atoms_per_s": t32["atoms_per_s"], "fp64_atoms_per_s": t64["atoms_per_s"],
-        "fp32_mixed_ms_per_step": round(t32["ms_per_step"], 4), "fp64_ms_per_step": round(t64["ms_per_step"], 4),
-        "fp32_mixed_stage_ms": {k: round(v, 4) for k, v in t32["stage_ms"].items()},
-        "cost_over_euclidean": round(t32["ms_per_step"] / r32["ms_per_step"], 3),
-        "types": dict(zip(ptm.TYPE_NAMES, t32["types"])),
-    }
-    derived_ms = derived_overhead(frame, args.steps, args.warmup)
-    posthoc = posthoc_bench(1 << 27)
-    print(f"[bench] derived outputs {derived_ms:.2f} ms/step; post-hoc {posthoc}", file=sys.stderr, flush=True)
-
-    serving = None
-    if not args.no_serve:
-        serving = serving_bench(args.serve_frames, args.serve_pool, ring=24, budget_gb=200.0)
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(frame, args.cpu_sample)
-        print(f"[bench] cpu oracle {cpu['value']:.0f} atoms/s on {cpu['cores']} threads", file=sys.stderr,
+    # ---- headline: the 31.7 M-atom frame, FP64 plain (value) and FP32-mixed
+    head = "mixed_31.7m"
+    frame = build_frame(head)
+    r64 = r32 = None
+    if args.only in ("all", "headline", "fp64"):
+        r64 = run_gpu(frame, ptm.PTM_FP64, args.steps, args.warmup)
+        print(f"[bench] {head} fp64 {r64['ms_per_step']:.2f} ms/step {r64['stage_ms']}", file=sys.stderr, flush=True)
+    if args.only in ("all", "headline", "fp32"):
+        r32 = run_gpu(frame, ptm.PTM_FP32_MIXED, args.steps, args.warmup)
+        print(f"[bench] {head} fp32-mixed {r32['ms_per_step']:.2f} ms/step {r32['stage_ms']}", file=sys.stderr,
               flush=True)
+    main_run = r64 if r64 is not None else r32
+    dtype = "f64" if r64 is not None else "f32-mixed"
+    stage_kernel = {"knn": "k_knn_fast<14> + k_knn_exact<14>", "topo": "k_topo",
+                    "eval": "k_cand_eval<double>" if r64 is not None else "k_cand_eval<float>",
+                    "decide": "k_decide<double> + k_decide_full<double>" if r64 is not None
+                    else "k_decide<float> + k_decide_full<float>"}
+    roof = roofline(main_run, frame.n, stage_kernel, head, "fp64" if r64 is not None else "fp32_mixed")
+    roof["kernel"] += " in the " + ("FP64" if r64 is not None else "FP32-mixed") + " frame"
 
     line = {
         "metric": METRIC, "value": main_run["atoms_per_s"], "unit": "atoms/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "periodic Voronoi polycrystal, L=220 A, 16 grains FCC 3.615/BCC 2.87/HCP 2.51 "
-                               "(c/a 1.633), sigma 0.10 A, all templates",
-                   "n_atoms": frame.n, "template_mask": "SC|FCC|HCP|ICO|BCC", "rmsd_cutoff": "inf"},
-        "fp64_atoms_per_s": r64["atoms_per_s"],
-        "fp32_mixed_atoms_per_s": r32["atoms_per_s"],
-        "fp32_mixed_over_fp64": r32["atoms_per_s"] / r64["atoms_per_s"],
-        "fp64_stage_ms": {k: round(v, 4) for k, v in r64["stage_ms"].items()},
+        "config": {"workload": WORKLOADS[head][0], "n_atoms": frame.n, "template_mask": "SC|FCC|HCP|ICO|BCC",
+                   "rmsd_cutoff": "inf", "form": "FP64 plain" if r64 is not None else "FP32-mixed"},
+        "fp64_atoms_per_s": None if r64 is None else r64["atoms_per_s"],
+        "fp32_mixed_atoms_per_s": None if r32 is None else r32["atoms_per_s"],
+        "fp32_mixed_over_fp64": None if (r64 is None or r32 is None) else r32["atoms_per_s"] / r64["atoms_per_s"],
+        "fp32_mixed_over_fp64_target": 2.0,
+        "stage_ms": {k: round(v, 4) for k, v in main_run["stage_ms"].items()},
+        "fp32_mixed_stage_ms": None if r32 is None else {k: round(v, 4) for k, v in r32["stage_ms"].items()},
         "work_counts": main_run["info"],
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "types": dict(zip(ptm.TYPE_NAMES, main_run["types"])),
         "roofline": roof,
-        "topological": topological,
-        "derived_outputs_ms_per_step": round(derived_ms, 4),
-        "posthoc": posthoc,
-        "serving": serving,
-        "cpu_baseline": cpu,
     }
+    if args.only != "all":
+        print(json.dumps(line))
+        return
+
+    # ---- the other full-size workloads (extra lines)
+    extra = {}
+    alloy = build_frame("alloy_slabs_4.0m")
+    a64 = run_gpu(alloy, ptm.PTM_FP64, args.steps, args.warmup)
+    a32 = run_gpu(alloy, ptm.PTM_FP32_MIXED, args.steps, args.warmup)
+    print(f"[bench] alloy slabs fp64 {a64['ms_per_step']:.2f} fp32-mixed {a32['ms_per_step']:.2f} ms/step",
+          file=sys.stderr, flush=True)
+    extra["alloy_slabs_4.0m"] = {"workload": WORKLOADS["alloy_slabs_4.0m"][0], "n_atoms": alloy.n,
+                                 "fp32_mixed": line_of(a32), "fp64": line_of(a64),
+                                 "fp32_mixed_over_fp64": a32["atoms_per_s"] / a64["atoms_per_s"],
+                                 "types": dict(zip(ptm.TYPE_NAMES, a32["types"]))}
+    del alloy
+    poly = build_frame("polycrystal_919k")
+    p64 = run_gpu(poly, ptm.PTM_FP64, args.steps * 2, args.warmup)
+    p32 = run_gpu(poly, ptm.PTM_FP32_MIXED, args.steps * 2, args.warmup)
+    print(f"[bench] polycrystal fp64 {p64['ms_per_step']:.2f} fp32-mixed {p32['ms_per_step']:.2f} ms/step",
+          file=sys.stderr, flush=True)
+    # topological neighbour ordering (Sec. 3): the same frame, both forms;
+    # its Voronoi kernels run inside the k-NN stage
+    t64 = run_gpu(poly, ptm.PTM_FP64, args.steps * 2, args.warmup, ptm.PTM_F_TOPOLOGICAL)
+    t32 = run_gpu(poly, ptm.PTM_FP32_MIXED, args.steps * 2, args.warmup, ptm.PTM_F_TOPOLOGICAL)
+    print(f"[bench] topological fp32-mixed {t32['ms_per_step']:.2f} ms/step, fp64 {t64['ms_per_step']:.2f}",
+          file=sys.stderr, flush=True)
+    extra["polycrystal_919k"] = {
+        "workload": WORKLOADS["polycrystal_919k"][0], "n_atoms": poly.n,
+        "fp32_mixed": line_of(p32), "fp64": line_of(p64),
+        "fp32_mixed_over_fp64": p32["atoms_per_s"] / p64["atoms_per_s"],
+        "types": dict(zip(ptm.TYPE_NAMES, p32["types"])),
+        "topological": {
+            "fp32_mixed_atoms_per_s": t32["atoms_per_s"], "fp64_atoms_per_s": t64["atoms_per_s"],
+            "fp32_mixed_ms_per_step": round(t32["ms_per_step"], 4), "fp64_ms_per_step": round(t64["ms_per_step"], 4),
+            "fp32_mixed_stage_ms": {k: round(v, 4) for k, v in t32["stage_ms"].items()},
+            "cost_over_euclidean": round(t32["ms_per_step"] / p32["ms_per_step"], 3),
+            "types": dict(zip(ptm.TYPE_NAMES, t32["types"])),
+        },
+    }
+    derived_ms = derived_overhead(poly, args.steps * 2, args.warmup)
+    extra["polycrystal_919k"]["derived_outputs_ms_per_step"] = round(derived_ms, 4)
+    del poly
+    posthoc = posthoc_bench(1 << 27)
+    print(f"[bench] derived outputs {derived_ms:.2f} ms/step; post-hoc {posthoc}", file=sys.stderr, flush=True)
+
+    serving = None
+    if not args.no_serve:
+        serving = serving_bench(pool, args.serve_frames, ring=24, budget_gb=200.0)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(frame, "mixed frame", args.cpu_sample, args.cpu_sample_1t)
+        cpu["paper_single_core_context"] = ("1.08e5 atoms/s: the paper's one laptop core (i7-4770HQ, 2014) on an "
+                                            "88,737-atom system, neighbour lists excluded (Table 2, Sec. 9)")
+
+    line.update({"extra_workloads": extra, "posthoc": posthoc, "serving": serving, "cpu_baseline": cpu})
     print(json.dumps(line))
 
 

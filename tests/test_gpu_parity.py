@@ -348,19 +348,6 @@ def test_deterministic_and_translation_invariant(torch_cuda, clf):
         assert np.array_equal(a[k], c[k]), k
 
 
-def test_config1_sampled(torch_cuda, clf, oracle_lib):
-    """Full ~0.92 M-atom polycrystal on the GPU; a seeded sample of atoms
-    recomputed one by one by the oracle."""
-    f = S.polycrystal()
-    got = run_gpu(torch_cuda, clf, f)
-    rng = np.random.default_rng(0)
-    atoms = np.sort(rng.choice(f.n, 1500, replace=False))
-    ref = run_ref(oracle_lib, f, atoms=atoms)
-    sub = {k: v[atoms] for k, v in got.items()}
-    st = compare(sub, ref)
-    print("config1", f.n, np.bincount(got["type"], minlength=6).tolist(), st)
-
-
 def test_host_pointer_context(torch_cuda, oracle_lib):
     import ctypes as C
     f = S.config0()

@@ -1,21 +1,28 @@
-"""GPU parity at full size on the two large workloads, through the C ABI:
-the ~4 M-atom ordered-alloy slabs (with species) and the ~32 M-atom mixed
-frame (BCC matrix, Mackay icosahedra, simple-cubic cubes, adsorbed liquid
-slab).  The whole frame runs on the GPU in the launch configuration the
-benchmark uses; a seeded sample of atoms -- uniform plus every kind of
-region -- is recomputed one by one by the FP64 oracle (brute-force
-neighbours over all atoms).  Decisions bit-exact, reals within the form's
-tolerance."""
+"""GPU parity at full size, through the C ABI, in the launch configuration
+the benchmark uses (whole frames on the device, default context):
+
+* the 918,996-atom periodic polycrystal and the ~4.03 M-atom ordered-alloy
+  slabs (with species): every atom against the FP64 oracle;
+* the ~31.7 M-atom mixed frame (BCC matrix, Mackay icosahedra, simple-cubic
+  cubes, adsorbed liquid slab): a seeded sample of 2 x 10^6 atoms plus every
+  icosahedron centre and 150 atoms of each region kind;
+* with the topological ordering: samples of the polycrystal and the mixed
+  frame.
+
+Decisions (type, ordered neighbours, Euclidean neighbours, alloy) bit-exact,
+reals within the form's tolerance.  The oracle runs with its certified cell
+search for these frame sizes; its results are cached (tests/oracle_cache.py)
+so both precision forms compare against one oracle run."""
 import numpy as np
 import pytest
 
+import oracle_cache
 from paper_1603_05143_amd import ptm, synthetic as S
 from parity_util import TOL32, TOL64, compare
 
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn")
-_oracle_cache = {}
 
 
 @pytest.fixture(scope="module")
@@ -25,16 +32,21 @@ def torch_cuda():
     return torch
 
 
-def _gpu_sample(torch, precision, f, atoms, topological=False):
-    """Classify the whole frame on the GPU; return the outputs of the sample."""
-    print(f"[full] n={f.n} precision={precision} sample={len(atoms)} topological={topological}", flush=True)
+def _gpu(torch, precision, f, atoms=None, topological=False):
+    """Classify the whole frame on the GPU; return the outputs of the listed
+    atoms (all when atoms is None) and the type counts of the frame."""
+    m = f.n if atoms is None else len(atoms)
+    print(f"[full] n={f.n} precision={precision} compared={m} topological={topological}", flush=True)
     c = ptm.Classifier(device=0, precision=precision, topological=topological)
     try:
         pos = torch.from_numpy(np.ascontiguousarray(f.positions)).to("cuda:0")
         sp = None if f.species is None else torch.from_numpy(f.species).to("cuda:0")
         out = c.classify(pos, f.box, species=sp, knn=True, best_type=True)
-        idx = torch.from_numpy(np.asarray(atoms, dtype=np.int64)).to("cuda:0")
-        res = {k: out[k].index_select(0, idx).cpu().numpy() for k in FIELDS}
+        if atoms is None:
+            res = {k: out[k].cpu().numpy() for k in FIELDS}
+        else:
+            idx = torch.from_numpy(np.asarray(atoms, dtype=np.int64)).to("cuda:0")
+            res = {k: out[k].index_select(0, idx).cpu().numpy() for k in FIELDS}
         types = torch.bincount(out["type"].long(), minlength=6).cpu().numpy()
         # post-hoc outputs over the whole frame (properties that hold at any
         # size): without a cut-off the best match is the type, and the RMSD
@@ -51,22 +63,45 @@ def _gpu_sample(torch, precision, f, atoms, topological=False):
     return res, types
 
 
-def _oracle(oracle_lib, key, f, atoms, ordering="euclidean"):
-    if key not in _oracle_cache:
-        _oracle_cache[key] = oracle_lib.classify(f.positions, f.box, species=f.species, atoms=atoms,
-                                                 ordering=ordering)
-    return _oracle_cache[key]
+def _oracle(oracle_lib, f, atoms=None, **kw):
+    print(f"[full] oracle n={f.n} atoms={'all' if atoms is None else len(atoms)} {kw}", flush=True)
+    return oracle_cache.classify(oracle_lib, f, atoms=atoms, **kw)
+
+
+@pytest.fixture(scope="module")
+def poly():
+    return S.polycrystal()
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_polycrystal_every_atom(torch_cuda, oracle_lib, poly, precision):
+    """All 918,996 atoms of the polycrystal."""
+    f = poly
+    got, types = _gpu(torch_cuda, precision, f)
+    ref = _oracle(oracle_lib, f)
+    st = compare(got, ref, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32, check_alloy=False,
+                 label="polycrystal ")
+    assert np.array_equal(types, np.bincount(ref["type"], minlength=6))
+    near = int(np.sum(ref["margin"] < 1e-9))
+    print("polycrystal", f.n, types.tolist(), st, "near ties", near, flush=True)
 
 
 @pytest.fixture(scope="module")
 def alloy_frame():
-    f = S.alloy_slabs()
-    rng = np.random.default_rng(11)
-    slab = f.labels["slab"]
-    picks = [rng.choice(f.n, 1000, replace=False)]
-    for s in range(4):  # every slab, whatever its share
-        picks.append(rng.choice(np.nonzero(slab == s)[0], 150, replace=False))
-    return f, np.unique(np.concatenate(picks))
+    return S.alloy_slabs()
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_alloy_slabs_every_atom(torch_cuda, oracle_lib, alloy_frame, precision):
+    """All ~4.03 M atoms of the alloy slabs, species included."""
+    f = alloy_frame
+    got, types = _gpu(torch_cuda, precision, f)
+    ref = _oracle(oracle_lib, f)
+    tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
+    st = compare(got, ref, tol=tol, label="alloy-slabs ")
+    # the slabs hold L1_0, both L1_2 sites and B2
+    assert set(np.unique(ref["alloy"])) >= {2, 3, 4, 7}, np.unique(ref["alloy"])
+    print("alloy slabs", f.n, types.tolist(), st, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -81,29 +116,17 @@ def mixed():
     sizes = np.array([55] * (n_ico // 2) + [147] * (n_ico - n_ico // 2))
     centres = int(np.nonzero(kind == 1)[0][0]) + np.concatenate([[0], np.cumsum(sizes)[:-1]])
     assert np.all(kind[centres] == 1)
-    picks = [rng.choice(f.n, 600, replace=False), centres]
+    picks = [rng.choice(f.n, 2_000_000, replace=False), centres]
     for k in (1, 2, 3):
         picks.append(rng.choice(np.nonzero(kind == k)[0], 150, replace=False))
     return f, np.unique(np.concatenate(picks)), centres
 
 
 @pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
-def test_alloy_slabs_full_sampled(torch_cuda, oracle_lib, alloy_frame, precision):
-    f, atoms = alloy_frame
-    got, types = _gpu_sample(torch_cuda, precision, f, atoms)
-    ref = _oracle(oracle_lib, "alloy", f, atoms)
-    tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
-    st = compare(got, ref, tol=tol, label="alloy-slabs ")
-    # the slabs hold L1_0, both L1_2 sites and B2: each class occurs in the sample
-    assert set(np.unique(ref["alloy"])) >= {2, 3, 4, 7}, np.unique(ref["alloy"])
-    print("alloy slabs", f.n, types.tolist(), st)
-
-
-@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
-def test_mixed_frame_full_sampled(torch_cuda, oracle_lib, mixed, precision):
+def test_mixed_frame_2M_sample(torch_cuda, oracle_lib, mixed, precision):
     f, atoms, centres = mixed
-    got, types = _gpu_sample(torch_cuda, precision, f, atoms)
-    ref = _oracle(oracle_lib, "mixed", f, atoms)
+    got, types = _gpu(torch_cuda, precision, f, atoms)
+    ref = _oracle(oracle_lib, f, atoms)
     tol = TOL64 if precision == ptm.PTM_FP64 else TOL32
     st = compare(got, ref, tol=tol, check_alloy=False, label="mixed ")
     # every structure of the frame is found: BCC matrix, SC cubes,
@@ -112,14 +135,13 @@ def test_mixed_frame_full_sampled(torch_cuda, oracle_lib, mixed, precision):
     assert types[5] > 0.7 * np.sum(kind == 0) and types[1] > 0 and types[4] > 0 and types[0] > 0, types
     at_centres = ref["type"][np.searchsorted(atoms, centres)]
     assert np.mean(at_centres == 4) > 0.9, np.bincount(at_centres, minlength=6)
-    print("mixed frame", f.n, types.tolist(), st)
+    print("mixed frame", f.n, "compared", len(atoms), types.tolist(), st, flush=True)
 
 
 @pytest.fixture(scope="module")
-def poly():
-    f = S.polycrystal()
+def poly_sample(poly):
     rng = np.random.default_rng(13)
-    return f, np.unique(rng.choice(f.n, 1200, replace=False))
+    return poly, np.unique(rng.choice(poly.n, 20000, replace=False))
 
 
 def _sure(ref, got):
@@ -130,22 +152,26 @@ def _sure(ref, got):
 
 
 @pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
-def test_polycrystal_topological_full_sampled(torch_cuda, oracle_lib, poly, precision):
-    """The 918,996-atom polycrystal with topological ordering (Sec. 3)."""
-    f, atoms = poly
-    got, types = _gpu_sample(torch_cuda, precision, f, atoms, topological=True)
-    ref = _oracle(oracle_lib, "poly-topo", f, atoms, ordering="topological")
+def test_polycrystal_topological_sampled(torch_cuda, oracle_lib, poly_sample, precision):
+    """The 918,996-atom polycrystal with topological ordering (Sec. 3):
+    20,000 seeded atoms."""
+    f, atoms = poly_sample
+    got, types = _gpu(torch_cuda, precision, f, atoms, topological=True)
+    ref = _oracle(oracle_lib, f, atoms, ordering="topological")
     g, r = _sure(ref, got)
     st = compare(g, r, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32, check_alloy=False, label="poly topo ")
     print("polycrystal topological", f.n, types.tolist(), st)
 
 
 @pytest.mark.parametrize("precision", [ptm.PTM_FP32_MIXED], ids=["fp32mixed"])
-def test_mixed_frame_topological_full_sampled(torch_cuda, oracle_lib, mixed, precision):
-    """The ~32 M-atom mixed frame with topological ordering."""
+def test_mixed_frame_topological_sampled(torch_cuda, oracle_lib, mixed, precision):
+    """The ~32 M-atom mixed frame with topological ordering: 20,000 seeded
+    atoms plus the icosahedron centres and region picks."""
     f, atoms, centres = mixed
-    got, types = _gpu_sample(torch_cuda, precision, f, atoms, topological=True)
-    ref = _oracle(oracle_lib, "mixed-topo", f, atoms, ordering="topological")
+    rng = np.random.default_rng(14)
+    atoms = np.unique(np.concatenate([rng.choice(atoms, 20000, replace=False), centres]))
+    got, types = _gpu(torch_cuda, precision, f, atoms, topological=True)
+    ref = _oracle(oracle_lib, f, atoms, ordering="topological")
     g, r = _sure(ref, got)
     st = compare(g, r, tol=TOL32, check_alloy=False, label="mixed topo ")
     print("mixed frame topological", f.n, types.tolist(), st)
