@@ -175,6 +175,24 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
                         const double *box, int64_t n_atoms, uint32_t template_mask,
                         double rmsd_cutoff, const ptm_outputs *out);
 
+/* Largest frame of ptm_classify_noalloc. */
+#define PTM_NOALLOC_MAX_ATOMS 65536
+
+/* ptm_classify that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, outputs and errors as
+ * ptm_classify on a device-pointer context; the pipeline's scratch is a
+ * static 104 MiB array that each device the library runs on holds until the
+ * process ends (room for n_atoms <= PTM_NOALLOC_MAX_ATOMS with either
+ * neighbour ordering).  n_atoms above that -> PTM_E_TOO_LARGE, a
+ * PTM_F_HOST_POINTERS context -> PTM_E_INVALID, both before any device work.
+ * Every call on one device shares that array and leaves its contents behind:
+ * calls that overlap on one device (from several contexts or threads) race.
+ * Synchronises before returning, like ptm_classify. */
+ptm_status ptm_classify_noalloc(ptm_ctx *ctx, const double *positions, const int8_t *species,
+                                const double *box, int64_t n_atoms, uint32_t template_mask,
+                                double rmsd_cutoff, const ptm_outputs *out);
+
 /* Serving: enqueue one frame without waiting (continuous batching: frames
  * are admitted while the HBM budget allows, their work overlaps on the
  * device).  Arguments as ptm_classify; buffers must stay valid until

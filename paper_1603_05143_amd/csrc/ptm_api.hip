@@ -212,7 +212,7 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     // count[cells + 1] and count[cells + 2] count the atoms the fast k-NN
     // search and the common-case decision leave over; count[cells + 3] is
     // the box flag (set by the k-NN kernels, read by every later stage)
-    PTM_HIP(ctx, hipMemsetAsync(S.count, 0, 4 * (size_t)(cells + FRAME_COUNTERS), st));
+    launch_zero(S.count, cells + FRAME_COUNTERS, st);
     const int32_t *box_fail = S.count + cells + 3;
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
     size_t tmp = S.scan_tmp_bytes;
@@ -259,8 +259,8 @@ ptm_status frame_bounds(ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_
     int nb = bounds_blocks(n);
     launch_bounds(pos, n, S.part, nb, st);
     PTM_HIP(ctx, hipGetLastError());
-    std::vector<double> h((size_t)nb * 7);
-    PTM_HIP(ctx, hipMemcpyAsync(h.data(), S.part, h.size() * 8, hipMemcpyDeviceToHost, st));
+    double *h = ctx->pinned_bounds;  // pinned host space for 7 x 1024 partials
+    PTM_HIP(ctx, hipMemcpyAsync(h, S.part, (size_t)nb * 7 * 8, hipMemcpyDeviceToHost, st));
     PTM_HIP(ctx, hipStreamSynchronize(st));
     bad = false;
     for (int a = 0; a < 3; a++) {
@@ -310,6 +310,116 @@ ptm_status validate(ptm_ctx *ctx, const double *positions, const double *box, in
         ctx->err = "rmsd_cutoff is NaN";
         return PTM_E_INVALID;
     }
+    return PTM_OK;
+}
+
+// ------------------------------------------------------ static scratch
+// Device scratch of ptm_classify_noalloc: a file-scope array in every
+// device's memory for the life of the process, sized for PTM_NOALLOC_MAX_ATOMS
+// atoms with either neighbour ordering.  Host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device (the
+// array's name on the host is not a device address).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)104 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// this device's address of the array, looked up once per device (the device
+// must be current)
+hipError_t noalloc_scratch_of(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[256] = {};
+    if (device < 0 || device >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
+// One frame through the pipeline with the scratch S (the context's own,
+// grown on demand, or a fixed buffer when noalloc: then nothing is
+// allocated and a frame that does not fit is PTM_E_TOO_LARGE).
+ptm_status classify_frame(ptm_ctx *ctx, FrameScratch &S, bool noalloc, const double *positions,
+                          const int8_t *species, const double *box, int64_t n_atoms, uint32_t template_mask,
+                          double rmsd_cutoff, const ptm_outputs *out) {
+    ctx->err.clear();
+    if (n_atoms == 0) return PTM_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        ctx->err = "hipSetDevice failed";
+        return PTM_E_DEVICE;
+    }
+    FrameJob J;
+    J.n = n_atoms;
+    J.mask = template_mask & PTM_ALL;
+    J.cutoff = rmsd_cutoff;
+    J.topo = (ctx->flags & PTM_F_TOPOLOGICAL) != 0;
+    HostStage H;
+    ptm_status st = stage_in(ctx, positions, species, out, n_atoms, J, H);
+    if (st != PTM_OK) return st;
+    const int64_t cap = pair_capacity(n_atoms, ctx->pair_cap);
+    auto reserve = [&](int64_t cells) -> ptm_status {
+        if (S.reserve(n_atoms, cells, J.topo, cap, ctx->err)) return PTM_OK;
+        return noalloc ? PTM_E_TOO_LARGE : PTM_E_NOMEM;
+    };
+    // bounds first (needs scratch for the partials): reserve with a tiny grid
+    if ((st = reserve(1)) != PTM_OK) return st;
+    double mn[3], mx[3];
+    bool bad = false;
+    const bool prof = (ctx->flags & PTM_F_PROFILE) != 0;
+    ctx->prof_valid = false;
+    if (prof) PTM_HIP(ctx, hipEventRecord(ctx->prof_ev[PTM_STAGE_BOUNDS], ctx->stream));
+    st = frame_bounds(ctx, S, J.pos, n_atoms, mn, mx, bad, ctx->stream);
+    if (st != PTM_OK) return st;
+    if (bad) {
+        ctx->err = "non-finite coordinate";
+        return PTM_E_INVALID;
+    }
+    J.grid = make_grid(box, mn, mx, n_atoms, J.topo ? VK : KMAX);
+    int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
+    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo, cap) > ctx->budget) {
+        ctx->err = "frame scratch exceeds the HBM budget";
+        return PTM_E_NOMEM;
+    }
+    if ((st = reserve(cells)) != PTM_OK) return st;
+    st = enqueue_frame(ctx, S, J, ctx->stream, prof);
+    if (st != PTM_OK) return st;
+    // the box flag comes back with the frame; host outputs are copied only
+    // once it is known to be clear (nothing is written on an error)
+    *ctx->pinned = 0;
+    PTM_HIP(ctx, hipMemcpyAsync(ctx->pinned, box_flag(S, J.grid), 4, hipMemcpyDeviceToHost, ctx->stream));
+    if (H.active) {
+        PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (*ctx->pinned) {
+            ctx->err = box_message(J.topo);
+            return PTM_E_BOX;
+        }
+        st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
+        if (st != PTM_OK) return st;
+    }
+    PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (*ctx->pinned) {
+        ctx->err = box_message(J.topo);
+        return PTM_E_BOX;
+    }
+    if (prof) {
+        int32_t left[2] = {0, 0};
+        int64_t pairs = 0;
+        PTM_HIP(ctx, hipMemcpy(left, S.count + cells + 1, 8, hipMemcpyDeviceToHost));
+        PTM_HIP(ctx, hipMemcpy(&pairs, S.match.off + pair_slots(n_atoms), 8, hipMemcpyDeviceToHost));
+        // the pairs past the capacity go to the full rule with their atoms
+        if (pairs > S.match.cap) pairs = S.match.cap;
+        ctx->prof_info[PTM_INFO_CELLS] = cells;
+        ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left[0] : n_atoms;
+        ctx->prof_info[PTM_INFO_PAIRS] = pairs;
+        ctx->prof_info[PTM_INFO_DECIDE_FULL] = left[1];
+    }
+    ctx->prof_valid = prof;
     return PTM_OK;
 }
 
@@ -390,11 +500,17 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
         }
         ctx->own_stream = true;
     }
-    if (hipHostMalloc((void **)&ctx->pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    // pinned host words: the box flag, then the per-block bounds partials
+    if (hipHostMalloc((void **)&ctx->pinned, 256 + 8 * 7 * 1024, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         ctx->pinned = nullptr;
         ptm_destroy(ctx);
         return PTM_E_NOMEM;
+    }
+    ctx->pinned_bounds = (double *)((char *)ctx->pinned + 256);
+    if (noalloc_scratch_of(ctx->device, &ctx->noalloc_scratch) != hipSuccess) {
+        ptm_destroy(ctx);
+        return PTM_E_DEVICE;
     }
     if (ctx->flags & PTM_F_PROFILE)
         for (int e = 0; e <= PTM_NSTAGES; e++)
@@ -436,75 +552,28 @@ ptm_status ptm_classify(ptm_ctx *ctx, const double *positions, const int8_t *spe
                         int64_t n_atoms, uint32_t template_mask, double rmsd_cutoff, const ptm_outputs *out) {
     ptm_status st = validate(ctx, positions, box, n_atoms, rmsd_cutoff, out);
     if (st != PTM_OK) return st;
-    ctx->err.clear();
-    if (n_atoms == 0) return PTM_OK;
-    if (hipSetDevice(ctx->device) != hipSuccess) {
-        ctx->err = "hipSetDevice failed";
-        return PTM_E_DEVICE;
-    }
-    FrameJob J;
-    J.n = n_atoms;
-    J.mask = template_mask & PTM_ALL;
-    J.cutoff = rmsd_cutoff;
-    J.topo = (ctx->flags & PTM_F_TOPOLOGICAL) != 0;
-    HostStage H;
-    st = stage_in(ctx, positions, species, out, n_atoms, J, H);
+    return classify_frame(ctx, ctx->main, false, positions, species, box, n_atoms, template_mask, rmsd_cutoff, out);
+}
+
+ptm_status ptm_classify_noalloc(ptm_ctx *ctx, const double *positions, const int8_t *species, const double *box,
+                                int64_t n_atoms, uint32_t template_mask, double rmsd_cutoff,
+                                const ptm_outputs *out) {
+    ptm_status st = validate(ctx, positions, box, n_atoms, rmsd_cutoff, out);
     if (st != PTM_OK) return st;
-    const int64_t cap = pair_capacity(n_atoms, ctx->pair_cap);
-    // bounds first (needs scratch for the partials): reserve with a tiny grid
-    if (!ctx->main.reserve(n_atoms, 1, J.topo, cap, ctx->err)) return PTM_E_NOMEM;
-    double mn[3], mx[3];
-    bool bad = false;
-    const bool prof = (ctx->flags & PTM_F_PROFILE) != 0;
-    ctx->prof_valid = false;
-    if (prof) PTM_HIP(ctx, hipEventRecord(ctx->prof_ev[PTM_STAGE_BOUNDS], ctx->stream));
-    st = frame_bounds(ctx, ctx->main, J.pos, n_atoms, mn, mx, bad, ctx->stream);
-    if (st != PTM_OK) return st;
-    if (bad) {
-        ctx->err = "non-finite coordinate";
+    if (ctx->flags & PTM_F_HOST_POINTERS) {
+        ctx->err = "ptm_classify_noalloc: host-pointer contexts stage through allocated buffers";
         return PTM_E_INVALID;
     }
-    J.grid = make_grid(box, mn, mx, n_atoms, J.topo ? VK : KMAX);
-    int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
-    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo, cap) > ctx->budget) {
-        ctx->err = "frame scratch exceeds the HBM budget";
-        return PTM_E_NOMEM;
+    if (n_atoms > PTM_NOALLOC_MAX_ATOMS) {
+        ctx->err = "ptm_classify_noalloc: n_atoms exceeds PTM_NOALLOC_MAX_ATOMS";
+        return PTM_E_TOO_LARGE;
     }
-    if (!ctx->main.reserve(n_atoms, cells, J.topo, cap, ctx->err)) return PTM_E_NOMEM;
-    st = enqueue_frame(ctx, ctx->main, J, ctx->stream, prof);
-    if (st != PTM_OK) return st;
-    // the box flag comes back with the frame; host outputs are copied only
-    // once it is known to be clear (nothing is written on an error)
-    *ctx->pinned = 0;
-    PTM_HIP(ctx, hipMemcpyAsync(ctx->pinned, box_flag(ctx->main, J.grid), 4, hipMemcpyDeviceToHost, ctx->stream));
-    if (H.active) {
-        PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        if (*ctx->pinned) {
-            ctx->err = box_message(J.topo);
-            return PTM_E_BOX;
-        }
-        st = stage_out(ctx, out, n_atoms, J, H, ctx->stream);
-        if (st != PTM_OK) return st;
-    }
-    PTM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (*ctx->pinned) {
-        ctx->err = box_message(J.topo);
-        return PTM_E_BOX;
-    }
-    if (prof) {
-        int32_t left[2] = {0, 0};
-        int64_t pairs = 0;
-        PTM_HIP(ctx, hipMemcpy(left, ctx->main.count + cells + 1, 8, hipMemcpyDeviceToHost));
-        PTM_HIP(ctx, hipMemcpy(&pairs, ctx->main.match.off + pair_slots(n_atoms), 8, hipMemcpyDeviceToHost));
-        // the pairs past the capacity go to the full rule with their atoms
-        if (pairs > ctx->main.match.cap) pairs = ctx->main.match.cap;
-        ctx->prof_info[PTM_INFO_CELLS] = cells;
-        ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left[0] : n_atoms;
-        ctx->prof_info[PTM_INFO_PAIRS] = pairs;
-        ctx->prof_info[PTM_INFO_DECIDE_FULL] = left[1];
-    }
-    ctx->prof_valid = prof;
-    return PTM_OK;
+    // the device's static array, carved like a frame scratch (never reallocated)
+    FrameScratch S;
+    S.base = ctx->noalloc_scratch;
+    S.bytes = NOALLOC_SCRATCH_BYTES;
+    S.pooled = true;
+    return classify_frame(ctx, S, true, positions, species, box, n_atoms, template_mask, rmsd_cutoff, out);
 }
 
 ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n) {

@@ -105,6 +105,10 @@ ptm_status enqueue_frame(struct ::ptm_ctx *ctx, FrameScratch &S, const FrameJob 
 ptm_status frame_bounds(struct ::ptm_ctx *ctx, FrameScratch &S, const double *pos, int64_t n, double mn[3],
                         double mx[3], bool &bad, hipStream_t st);
 const char *box_message(bool topo);
+hipError_t noalloc_scratch_of(int device, void **ptr);
+ptm_status classify_frame(struct ::ptm_ctx *ctx, FrameScratch &S, bool noalloc, const double *positions,
+                          const int8_t *species, const double *box, int64_t n_atoms, uint32_t template_mask,
+                          double rmsd_cutoff, const ptm_outputs *out);
 ptm_status validate(struct ::ptm_ctx *ctx, const double *positions, const double *box, int64_t n, double cutoff,
                     const ptm_outputs *out);
 ptm_status upload_tables(struct ::ptm_ctx *ctx);
@@ -132,6 +136,8 @@ struct ptm_ctx {
     uint32_t flags = 0;
     int64_t pair_cap = 0;           // candidate pair capacity override (0: 6n + 64)
     int32_t *pinned = nullptr;      // pinned host word: the box flag of the last ptm_classify
+    double *pinned_bounds = nullptr;  // pinned host space: per-block bounds of the frame being set up
+    void *noalloc_scratch = nullptr;  // this device's static scratch array (ptm_classify_noalloc)
     ptm::HostTables host;
     std::vector<void *> table_buffers;
     ptm::TablesView view;

@@ -2628,6 +2628,16 @@ void launch_selftest_strain(const TablesView &T, int t, bool f32, const double *
 }
 
 // --------------------------------------------------------------- launches
+// zero n int32 words (a kernel rather than a memset node, so that a captured
+// stream replays it faithfully)
+__global__ void k_fill_zero(int32_t *__restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+void launch_zero(int32_t *p, int64_t n, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, p, n);
+}
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(nblocks), dim3(256), 0, st, pos, n, part);
 }

@@ -59,6 +59,7 @@ struct MatchScratch {
     size_t scan_tmp_bytes;
 };
 
+void launch_zero(int32_t *p, int64_t n, hipStream_t st);
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st);
 void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
                       int32_t *count, hipStream_t st);

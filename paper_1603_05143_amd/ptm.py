@@ -64,6 +64,9 @@ def lib():
         L.ptm_create.restype = C.c_int
         L.ptm_classify.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_double, C.POINTER(ptm_outputs)]
         L.ptm_classify.restype = C.c_int
+        L.ptm_classify_noalloc.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_double,
+                                           C.POINTER(ptm_outputs)]
+        L.ptm_classify_noalloc.restype = C.c_int
         L.ptm_submit.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_uint32, C.c_double, C.POINTER(ptm_outputs),
                                  C.POINTER(C.c_uint64)]
         L.ptm_submit.restype = C.c_int
@@ -117,6 +120,15 @@ def ptm_classify(ctx, positions_ptr, species_ptr, box, n_atoms, template_mask, r
     bx = (C.c_double * 3)(*[float(b) for b in box])
     return lib().ptm_classify(ctx, positions_ptr, species_ptr, bx, int(n_atoms), int(template_mask),
                               float(rmsd_cutoff), C.byref(outputs))
+
+
+def ptm_classify_noalloc(ctx, positions_ptr, species_ptr, box, n_atoms, template_mask, rmsd_cutoff, outputs):
+    bx = (C.c_double * 3)(*[float(b) for b in box])
+    return lib().ptm_classify_noalloc(ctx, positions_ptr, species_ptr, bx, int(n_atoms), int(template_mask),
+                                      float(rmsd_cutoff), C.byref(outputs))
+
+
+PTM_NOALLOC_MAX_ATOMS = 65536
 
 
 def ptm_submit(ctx, positions_ptr, species_ptr, box, n_atoms, template_mask, rmsd_cutoff, outputs):
