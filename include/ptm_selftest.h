@@ -49,8 +49,14 @@ int ptm_selftest_det3_f32filter(const double *p9);
 
 /* ptm_selftest_superpose evaluated in FP32 the way the FP32-mixed form
  * evaluates a candidate (centring in FP64, covariance, QCP and residual in
- * FP32). */
-int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q);
+ * FP32).  excess (nullable) receives the bound d2 the FP32-mixed decision
+ * keeps with the candidate: the amount by which the FP32 eigen-solve's
+ * rotation and scale can raise RMSD^2 above its minimum, from the
+ * conditioning of the top eigenpair of Horn's matrix (+inf when FP32
+ * cannot resolve it: nearly equal top eigenvalues, or an eigenpair whose
+ * Rayleigh quotient has not converged). */
+int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q,
+                               double *excess);
 
 /* Strain of one match (eq. (6) least-squares fit with the pseudoinverse of
  * the normalised template, then P of the left polar decomposition A = P U

@@ -939,7 +939,8 @@ int ptm_selftest_det3_f32filter(const double *p) {
     return det3_filter_f32in(f, f + 3, f + 6, f32_det3_bound(m));
 }
 
-int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q) {
+int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, double *rmsd, double *scale, double *q,
+                               double *excess) {
     if (N < 1 || N > NMAX) return -1;
     double ca[3] = {0, 0, 0}, cb[3] = {0, 0, 0};
     for (int i = 0; i < N; i++)
@@ -969,8 +970,9 @@ int ptm_selftest_superpose_f32(int N, const double *obs, const double *tpl, doub
             for (int y = 0; y < 3; y++) S[x][y] += b[i][x] * a[i][y];
         for (int d = 0; d < 3; d++) Gb += b[i][d] * b[i][d];
     }
-    float qf[4];
-    float lam = qcp_solve<float>(S, Ga, Gb, qf);
+    float qf[4], cf = 0.f;
+    float lam = qcp_solve<float>(S, Ga, Gb, qf, &cf);
+    if (excess) *excess = f32_excess_bound(lam, cf, Ga);
     float s = Ga > 0 ? lam / Ga : 0.f, R[3][3], res = 0;
     quat_rot<float>(qf, R);
     for (int i = 0; i < N; i++)

@@ -376,8 +376,21 @@ struct RealTraits<float> {
 // Largest eigenvalue and eigenvector of Horn's matrix for S_xy = sum b_x a_y
 // (template b, observation a); q (w,x,y,z) rotates b onto a.  Ga, Gb are the
 // inner products of the two sets (upper bound sqrt(Ga Gb) on lambda).
+// cond (optional) receives a conditioning measure of the computed top
+// eigenpair, 0 when it cannot be trusted: sqrt(best) / lambda^3, best the
+// largest squared column norm of adj(K - lambda I) -- for an exact top
+// eigenpair that column is |prod_j (lambda - lambda_j)| times a component
+// of the eigenvector (at least 1/2 in the largest), so cond bounds the
+// product of the gaps to the other three eigenvalues; each gap is at most
+// 4 lambda (K is traceless), hence the smallest gap is at least
+// cond * lambda / 16.  That reading holds only for a converged eigenpair:
+// Newton approaches the largest root from above (lambda >= lambda_1) and
+// the Rayleigh quotient rho = q^T K q is at most lambda_1, so
+// lambda - rho >= 0 bounds both the eigenvalue error and the eigenvector's
+// suboptimality; cond is 0 unless lambda - rho <= 64 u lambda (u the unit
+// roundoff of T), and 0 if lambda <= 0.
 template <typename T>
-__host__ __device__ inline T qcp_solve(const T S[3][3], T Ga, T Gb, T q[4]) {
+__host__ __device__ inline T qcp_solve(const T S[3][3], T Ga, T Gb, T q[4], T *cond = nullptr) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
@@ -441,7 +454,36 @@ __host__ __device__ inline T qcp_solve(const T S[3][3], T Ga, T Gb, T q[4]) {
         }
     }
     if (!(best > T(0))) { q[0] = 1; q[1] = q[2] = q[3] = 0; }
+    if (cond) {
+        T c = (lam > T(0) && best > T(0)) ? sqrt(best) / (lam * lam * lam) : T(0);
+        T rho = 0;
+        for (int i = 0; i < 4; i++) {
+            T kq = K[i][0] * q[0] + K[i][1] * q[1] + K[i][2] * q[2] + K[i][3] * q[3];
+            rho += q[i] * kq;
+        }
+        const T unit = sizeof(T) == 4 ? T(0x1p-24) : T(0x1p-53);
+        if (!(lam - rho <= T(64) * unit * lam)) c = T(0);
+        *cond = c;
+    }
     return lam;
+}
+
+// Bound d2 on how far the FP32 residual sum exceeds its minimum, per point
+// (on RMSD^2), from the eigen-solve.  With s = lambda / Ga the residual at
+// (s, q) exceeds the minimum by ((lambda - lambda_1)^2 + 2 lambda
+// (lambda_1 - rho)) / Ga (rho = q^T K q), which is second order in the
+// eigenvector's error when the eigenpair is converged and well separated:
+// the eigenvector's error is about c u lambda / gap per direction, so the
+// excess per point is at most 35 c^2 u^2 / cond (the gaps are at least
+// cond lambda / 16, lambda^2 / (Ga N) is at most Gb / N, about 1); with
+// c = 10 that is 3500 u^2 / cond.  Other eigenpairs (cond below 1/8, or a
+// Rayleigh quotient that leaves lambda by more than rounding) get no finite
+// bound: FP32 arithmetic cannot resolve nearly equal top eigenvalues, and
+// their atoms are decided in FP64.
+__host__ __device__ inline float f32_excess_bound(float lam, float cond, float Ga) {
+    const float unit = 0x1p-24f;
+    if (!(Ga > 0.f) || !(lam > 0.f) || !(cond >= 0.125f)) return INFINITY;
+    return 3500.f * unit * unit / cond;
 }
 
 template <typename T>

@@ -1576,6 +1576,7 @@ __device__ inline uint64_t rep_vector(const TemplateDev &D, uint64_t cmap, int &
 template <typename T>
 struct CandEval {
     T r, s, q[4];
+    T c;  // FP32 form: bound on the eigen-solve's excess of RMSD^2 (f32_excess_bound)
 };
 
 // eq.(3) for one candidate: observed rank r <-> template vertex tv(r).
@@ -1603,7 +1604,9 @@ __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const Templat
             for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[r + 1][y];
         Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
     }
-    T lam = qcp_solve<T>(S, Ga, Gb, out.q);
+    T cond = 0;
+    T lam = qcp_solve<T>(S, Ga, Gb, out.q, sizeof(T) == 4 ? &cond : nullptr);
+    if constexpr (sizeof(T) == 4) out.c = f32_excess_bound(lam, cond, Ga);
     T s = Ga > T(0) ? lam / Ga : T(0);
     T R[3][3];
     quat_rot<T>(out.q, R);
@@ -1670,7 +1673,9 @@ __device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t
         Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
     }
     const T Ga = (T)g;
-    T lam = qcp_solve<T>(S, Ga, Gb, out.q);
+    T cond = 0;
+    T lam = qcp_solve<T>(S, Ga, Gb, out.q, sizeof(T) == 4 ? &cond : nullptr);
+    if constexpr (sizeof(T) == 4) out.c = f32_excess_bound(lam, cond, Ga);
     T s = Ga > T(0) ? lam / Ga : T(0);
     T R[3][3];
     quat_rot<T>(out.q, R);
@@ -2063,6 +2068,11 @@ __global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, cons
     }
 }
 
+// Stored superposition of a pair: quaternion and scale, and in the FP32
+// form its conditioning (see rmsd_f32_bound).
+template <typename RT>
+constexpr int QS_STRIDE = sizeof(RT) == 4 ? 6 : 5;
+
 // One superposition per lane over the flat pair list (grid-stride).
 template <typename RT>
 __global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
@@ -2103,31 +2113,46 @@ __global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__
             else eval_streamed<14, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
         }
         rout[q] = (double)ev.r;
-        RT *o = qsout + 5 * q;
+        RT *o = qsout + QS_STRIDE<RT> * q;
         o[0] = ev.q[0];
         o[1] = ev.q[1];
         o[2] = ev.q[2];
         o[3] = ev.q[3];
         o[4] = ev.s;
+        if constexpr (sizeof(RT) == 4) o[5] = ev.c;
     }
 }
 
-// Bound on |RMSD_FP32 - RMSD_FP64| of one candidate evaluated in FP32 from
-// FP64-centred points.  The residual terms s a - R b are O(1) after the
-// normalisation of eq.(4); rounding the inputs and the residual arithmetic
-// to FP32 moves them by a few 2^-24, i.e. the RMSD by ~5e-7, while the
-// rotation and scale errors of the FP32 solve enter only at second order
-// (the RMSD is stationary in both at the optimum).  The bound keeps a factor
-// of eight over that estimate; decisions whose FP32 margins are below it
-// are redone in FP64.
-constexpr double RMSD_F32_BOUND = 4e-6;
+// Bound on |RMSD_FP32 - RMSD| of one candidate evaluated in FP32 from
+// FP64-centred points (u = 2^-24; the terms are derived with the FP32-mixed
+// form's description):
+//   first order, u (72 + 25 r): rounding of the inputs (2.7 u), the
+//     covariance sums seen as a perturbation of the inputs (36 u), the
+//     rotation built from a unit quaternion rounded to FP32 (15 u), the
+//     residual components (17 u), the 45-term sum of squares (23 u r), the
+//     division and square root (2 u r);
+//   the eigen-solve's excess d2 of RMSD^2 (stored with the pair by
+//     k_cand_eval, see f32_excess_bound; infinite for an eigenpair FP32
+//     cannot resolve): RMSD^2 + d2 has a square root below
+//     RMSD + d2 / (RMSD + sqrt(d2)).
+constexpr double RMSD_F32_U = 0x1p-24;
+__device__ inline double rmsd_f32_bound(double r, double d2) {
+    if (!(d2 < INFINITY)) return INFINITY;
+    return RMSD_F32_U * (72.0 + 25.0 * r) + d2 / (r + sqrt(d2));
+}
 
 // Minimum over an atom's evaluated pairs: best and second-best RMSD and the
 // winning (group, candidate).  q1 > cap: the pairs did not fit the buffer.
+// cs (FP32 form): the pairs' excess bounds d2 at stride 6; then b1 gets the
+// error bound of the winner and lo2 the smallest lower end r - bound over
+// the other pairs (nullptr in the FP64 form).
 __device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t p,
                                     const uint2 *__restrict__ pairs, const double *__restrict__ rr, double &m1,
-                                    double &m2, int &arg_grp, int &arg_c, int64_t &arg_q) {
+                                    double &m2, int &arg_grp, int &arg_c, int64_t &arg_q,
+                                    const float *__restrict__ cs, double &b1, double &lo2) {
     m1 = m2 = INFINITY;
+    b1 = 0.0;
+    lo2 = INFINITY;
     arg_grp = arg_c = -1;
     arg_q = -1;
     int64_t q0[NGRP], q1[NGRP];
@@ -2151,14 +2176,19 @@ __device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t p,
             y2[g][j] = in ? pairs[q0[g] + j].y : 0u;
         }
     auto visit = [&](double r, uint32_t y, int64_t q) {
+        double b = 0.0;
+        if (cs) b = rmsd_f32_bound(r, (double)cs[6 * q]);
         if (r < m1) {
+            if (cs) lo2 = fmin(lo2, m1 - b1);  // the previous winner joins the others
+            b1 = b;
             m2 = m1;
             m1 = r;
             arg_grp = (int)(y >> 28);
             arg_c = (int)(y & 0x0FFFFFFF);
             arg_q = q;
-        } else if (r < m2) {
-            m2 = r;
+        } else {
+            if (r < m2) m2 = r;
+            if (cs) lo2 = fmin(lo2, r - b);
         }
     };
 #pragma unroll
@@ -2212,10 +2242,17 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
             for (int m = 0; m < KMAX; m++) knn_out[(int64_t)i * KMAX + m] = knn_src[(int64_t)m * n + p];
         }
         const bool over = pairs_overflow(off, p, cap);
-        if (!over) pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q);
+        double b1 = 0.0, lo2 = INFINITY;
+        if (!over)
+            pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q,
+                         sizeof(RT) == 4 ? (const float *)qs + 5 : nullptr, b1, lo2);
         bool full = over || (arg_c >= 0 && !(m2 > m1 + 1e-12));
-        if (sizeof(RT) == 4 && arg_c >= 0)
-            full = full || !(m2 - m1 > 2 * RMSD_F32_BOUND + 1e-12) || fabs(m1 - cutoff) <= RMSD_F32_BOUND;
+        if (sizeof(RT) == 4 && arg_c >= 0) {
+            // the FP32 decision stands only where the error bounds prove it:
+            // every other pair's true RMSD exceeds the winner's by more than
+            // the tie tolerance, and the winner lies clear of the cut-off
+            full = full || !(lo2 - (m1 + b1) > 1e-12) || fabs(m1 - cutoff) <= b1;
+        }
         if (full) todo[atomicAdd(todo_count, 1)] = (int32_t)p;
         else if (arg_c < 0) write_none(O, sid[p]);
         else cls = arg_grp;
@@ -2258,7 +2295,7 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
     const int gw = s_g[threadIdx.x], cw = s_c[threadIdx.x];
     const int32_t iw = sid[pw];
     const uint64_t ord = ords[(int64_t)gw * n + pw];
-    const RT *w = qs + 5 * s_q[threadIdx.x];
+    const RT *w = qs + QS_STRIDE<RT> * s_q[threadIdx.x];
     const double rw = s_r[threadIdx.x];
     if (gw == 0) finish_stored<6, RT>(M, T, 0, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
     else if (gw == 1)

@@ -232,7 +232,7 @@ def test_superpose_f32_within_stated_tolerances(ptm, oracle_lib):
                 r, s, q = C.c_double(), C.c_double(), np.zeros(4)
                 L.ptm_selftest_superpose_f32(len(obs), obs.ctypes.data_as(C.c_void_p),
                                              tpl.ctypes.data_as(C.c_void_p), C.byref(r), C.byref(s),
-                                             q.ctypes.data_as(C.c_void_p))
+                                             q.ctypes.data_as(C.c_void_p), None)
                 r1, s1, q1, _ = oracle_lib.superpose(obs, tpl)
                 assert abs(r.value - r1) < 1e-6
                 assert abs(s.value - s1) < 1e-6 * s1
@@ -272,3 +272,100 @@ def test_selftest_strain_agrees_with_oracle(ptm, oracle_lib, precision, tol):
     P = np.zeros(9)
     assert L.ptm_selftest_strain(5, 0, obs.ctypes.data, P.ctypes.data) == -1
     assert L.ptm_selftest_strain(0, 2, obs.ctypes.data, P.ctypes.data) == -1
+
+
+def rmsd_f32_bound(r, d2):
+    """The FP32-mixed decision's bound on |RMSD_FP32 - RMSD| (restated from
+    the kernel): first-order rounding u (72 + 25 r), and the eigen-solve's
+    excess d2 of RMSD^2 (stored with each candidate) as d2 / (r + sqrt d2)."""
+    u = 2.0 ** -24
+    if not np.isfinite(d2):
+        return np.inf
+    return u * (72 + 25 * r) + d2 / (r + np.sqrt(d2))
+
+
+def f32_superpose(L, obs, tpl):
+    r, s, d2 = C.c_double(), C.c_double(), C.c_double()
+    q = np.zeros(4)
+    L.ptm_selftest_superpose_f32(len(obs), obs.ctypes.data_as(C.c_void_p), tpl.ctypes.data_as(C.c_void_p),
+                                 C.byref(r), C.byref(s), q.ctypes.data_as(C.c_void_p), C.byref(d2))
+    return r.value, s.value, q, d2.value
+
+
+def sig_of(nb, w):
+    """Rough noise level of a noisy rotated copy: the spread of the pair
+    distances from the template's."""
+    dn = np.linalg.norm(nb[:, None] - nb[None], axis=-1)
+    dw = np.linalg.norm(w[:, None] - w[None], axis=-1)
+    return float(np.sqrt(np.mean((dn - dw) ** 2)))
+
+
+def test_f32_rmsd_bound_adversarial(ptm, oracle_lib):
+    """The FP32 candidate RMSD against the FP64 oracle's (Jacobi eigen-solve,
+    explicit residual) on generic and adversarial correspondences: every
+    template; noise from 1e-7 to 2 (normalised units); near-degenerate top
+    eigenvalues of Horn's matrix (mirror images: det S < 0 with equal
+    singular values, spread apart by 0 .. 1e-1; near-colinear observations).
+    The error lies inside the bound for every candidate FP32 resolves; the
+    near-degenerate ones get no finite bound (their atoms are decided in
+    FP64)."""
+    from paper_1603_05143_amd.synthetic import random_rotations
+    L = ptm.lib()
+    rng = np.random.default_rng(21)
+    worst, tight, loose = 0.0, 0, 0
+    u = 2.0 ** -24
+    for t in range(5):
+        w = oracle_lib.template(t)["w"]
+        w = w / np.linalg.norm(w[0]) * 2.5
+        tpl = np.ascontiguousarray(np.vstack([np.zeros(3), w]))
+        cases = []
+        for sig in (1e-7, 1e-4, 0.01, 0.1, 0.5, 2.0):
+            for _ in range(40):
+                cases.append(("noise", w @ random_rotations(rng, 1)[0].T + rng.normal(scale=sig, size=w.shape)))
+        for eps in (0.0, 1e-7, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 0.1):
+            for _ in range(10):
+                M = np.diag([1.0, 1.0, -(1.0 - eps)])
+                R = random_rotations(rng, 1)[0]
+                cases.append(("mirror", w @ M.T @ R.T + rng.normal(scale=1e-6, size=w.shape)))
+        for _ in range(20):
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            line = np.outer(rng.normal(size=len(w)), d) * 2.5 + rng.normal(scale=1e-3, size=w.shape)
+            cases.append(("colinear", line))
+        for kind, nb in cases:
+            obs = np.ascontiguousarray(np.vstack([np.zeros(3), nb]))
+            r32, s32, q32, d2 = f32_superpose(L, obs, tpl)
+            r64 = oracle_lib.superpose(obs, tpl)[0]
+            ratio = abs(r32 - r64) / rmsd_f32_bound(r32, d2)
+            worst = max(worst, ratio)
+            assert ratio <= 1.0, (t, kind, r32, r64, d2)
+            if np.isfinite(d2):
+                tight += 1
+            else:
+                loose += 1
+                assert kind != "noise" or sig_of(nb, w) > 0.3
+    print("worst |dr| / bound:", worst, "bounded", tight, "unresolved", loose)
+    assert worst < 0.5 and loose > 0 and tight > 1000
+
+
+def test_f32_excess_bound_flags_degenerate_spectra(ptm, oracle_lib):
+    """A mirror image of a cubic template (det S < 0, equal singular values)
+    makes the top eigenvalues of Horn's matrix equal: FP32 cannot resolve
+    them and the candidate gets no finite bound; it gets a second-order one
+    once the singular values spread apart (the gap is 2 m eps for the cubic
+    templates' isotropic second moment m), and so does a rotated copy."""
+    from paper_1603_05143_amd.synthetic import random_rotations
+    L = ptm.lib()
+    rng = np.random.default_rng(22)
+    u = 2.0 ** -24
+    w = oracle_lib.template(1)["w"] / np.sqrt(2) * 2.5
+    tpl = np.ascontiguousarray(np.vstack([np.zeros(3), w]))
+    d2 = []
+    for eps in (0.0, 1e-3, 0.3):
+        R = random_rotations(rng, 1)[0]
+        obs = np.ascontiguousarray(np.vstack([np.zeros(3), w @ np.diag([1.0, 1.0, -(1.0 - eps)]).T @ R.T]))
+        d2.append(f32_superpose(L, obs, tpl)[3])
+    well = np.ascontiguousarray(np.vstack([np.zeros(3), w @ random_rotations(rng, 1)[0].T]))
+    d2_well = f32_superpose(L, well, tpl)[3]
+    assert not np.isfinite(d2[0]) and not np.isfinite(d2[1]), d2
+    assert d2[2] < 1e4 * u * u and d2_well < 1e4 * u * u, (d2, d2_well)

@@ -497,3 +497,82 @@ def test_misorientation(torch_cuda, oracle_lib):
                                       ha.ctypes.data) == ptm.PTM_E_INVALID
     finally:
         ptm.ptm_destroy(hctx)
+
+
+def _pyritohedral_shell(s, nn=2.55):
+    """The 12 points (0, +-1, +-s) and their cyclic permutations, at distance
+    nn: the cuboctahedron at s = 1, the icosahedron at s = golden ratio, and
+    in between a shell whose hull graph is the icosahedron's, a code that
+    the FCC and ICO tables share (Sec. 4)."""
+    v = []
+    for a in (1.0, -1.0):
+        for b in (1.0, -1.0):
+            base = np.array([0.0, a, b * s])
+            v += [base, np.roll(base, 1), np.roll(base, 2)]
+    v = np.array(v)
+    return v / np.linalg.norm(v[0]) * nn
+
+
+def _fcc_minus_ico(oracle_lib, s):
+    pts = np.vstack([np.zeros(3), _pyritohedral_shell(s)])
+    rf = oracle_lib.classify(pts, np.zeros(3), atoms=[0], mask=ptm.PTM_FCC)["rmsd"][0]
+    ri = oracle_lib.classify(pts, np.zeros(3), atoms=[0], mask=ptm.PTM_ICO)["rmsd"][0]
+    return rf - ri, ri
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_candidate_gaps_straddling_the_fp32_bound(torch_cuda, oracle_lib, precision):
+    """Atoms whose two best candidates (FCC and ICO of one shared hull code)
+    differ by planted RMSD gaps from 1e-8 to 2e-5 either way -- inside,
+    around and beyond twice the FP32-mixed decision bound -- and atoms whose
+    RMSD straddles the cut-off: the shells move along the
+    cuboctahedron-icosahedron path, rotated at random, and every decision
+    equals the oracle's.  In the FP32-mixed form the close ones are decided
+    by the FP64 full rule."""
+    torch = torch_cuda
+    lo, hi = 1.2318, 1.309  # r_FCC - r_ICO changes sign in between
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if _fcc_minus_ico(oracle_lib, mid)[0] < 0:
+            lo = mid
+        else:
+            hi = mid
+    s_star = 0.5 * (lo + hi)
+    slope = (_fcc_minus_ico(oracle_lib, s_star + 1e-4)[0] - _fcc_minus_ico(oracle_lib, s_star - 1e-4)[0]) / 2e-4
+    gaps = [g * sgn for g in (1e-8, 3e-7, 1e-6, 2e-6, 4e-6, 8e-6, 2e-5) for sgn in (-1, 1)]
+    rng = np.random.default_rng(91)
+    blocks, centres, planted = [], [], []
+    for k, g in enumerate(gaps * 3):
+        s = s_star + g / slope
+        planted.append(_fcc_minus_ico(oracle_lib, s)[0])
+        R = S.random_rotations(rng, 1)[0]
+        base = 12.0 * np.array([k % 5, (k // 5) % 5, k // 25], dtype=float)
+        centres.append(len(blocks) * 13)
+        blocks.append(np.vstack([base, base + _pyritohedral_shell(s) @ R.T]))
+    f = S.Frame(positions=np.vstack(blocks), box=np.zeros(3))
+    planted = np.array(planted)
+    assert np.sum(np.abs(planted) < 3e-6) >= 6 and np.sum(np.abs(planted) > 1e-5) >= 6
+    r_star = _fcc_minus_ico(oracle_lib, s_star)[1]
+    for cutoff in (math.inf, r_star - 1e-7, r_star - 1e-6, r_star - 3e-6):
+        ref = oracle_lib.classify(f.positions, f.box, cutoff=cutoff)
+        ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE)
+        try:
+            pos = torch.from_numpy(f.positions).to("cuda:0")
+            out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
+            st = ptm.ptm_classify(ctx, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, cutoff,
+                                  ptm.Classifier.outputs_struct(out))
+            assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+            info = ptm.ptm_frame_info(ctx)
+            got = {k: v.cpu().numpy() for k, v in out.items()}
+        finally:
+            ptm.ptm_destroy(ctx)
+        _compare(got, ref, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32, label=f"cutoff {cutoff} ")
+        types = got["type"][centres]
+        if cutoff == math.inf:
+            assert set(types.tolist()) == {2, 4}, types
+        else:
+            assert 0 in types and (2 in types or 4 in types), types
+        if precision == ptm.PTM_FP32_MIXED:
+            close = int(np.sum(np.abs(planted) < 2e-6))
+            assert info["decide_full"] >= close, (info, close)
+        print(f"[gaps] cutoff={cutoff} types={np.bincount(types, minlength=6).tolist()} info={info}", flush=True)
