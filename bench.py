@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "atoms/s (PTM, all templates) FP32-mixed vs FP64 plain; p50/p99 frame latency"
-STAGES = ("bounds", "bin", "knn", "topo", "cand", "eval", "decide")
+STAGES = ("bounds", "bin", "knn", "topo", "match")
 
 # MI355X published peaks: HBM3E bandwidth; vector FP64, which equals vector
 # FP32 without packed instructions (the library is built without them)
@@ -60,11 +60,11 @@ def work_model(stage: str, n: int, info: dict) -> tuple[str, float, str]:
               differences = 23 FLOP per test) read off at 6, 12 and 14 points,
               each checked for the centre (14 FLOP per facet: the centre is
               the origin)
-      eval    per superposed pair with N = 13 points: covariance 18N, G_b 6N,
-              residual 27N, key matrix + characteristic polynomial + Newton +
-              adjugate eigenvector + rotation ~290 FLOP
-      decide  winner re-evaluation (953) + quaternion (30) + strain (A^T =
-              V+ W' 234, A A^T 54, Jacobi 540, P 90) ~ 1.9 kFLOP per atom
+      match   per superposed candidate with N = 13 points: covariance 18N,
+              G_b 6N, residual 27N, key matrix + characteristic polynomial +
+              Newton + adjugate eigenvector + rotation ~290 FLOP; per atom
+              the winner's outputs: quaternion (30) + strain (A^T = V+ W'
+              234, A A^T 54, Jacobi 540, P 90) ~ 950 FLOP
       bin     104 B per atom (positions read twice, cell/slot/sorted writes)
               + 8 B per cell (histogram scan)
     """
@@ -75,11 +75,9 @@ def work_model(stage: str, n: int, info: dict) -> tuple[str, float, str]:
     if stage == "topo":
         inside = sum(2 * K - 4 for K in (6, 12, 14))
         return "alu", (23.0 * orient_tests(14) + 14.0 * inside) * n, "flop"
-    if stage == "eval":
+    if stage == "match":
         N = 13
-        return "alu", (51.0 * N + 290.0) * info.get("pairs", 0), "flop"
-    if stage == "decide":
-        return "alu", 1900.0 * n, "flop"
+        return "alu", (51.0 * N + 290.0) * info.get("pairs", 0) + 950.0 * n, "flop"
     raise KeyError(stage)
 
 
@@ -545,9 +543,7 @@ def main():
     main_run = r64 if r64 is not None else r32
     dtype = "f64" if r64 is not None else "f32-mixed"
     stage_kernel = {"knn": "k_knn_fast<14> + k_knn_exact<14>", "topo": "k_topo",
-                    "eval": "k_cand_eval<double>" if r64 is not None else "k_cand_eval<float>",
-                    "decide": "k_decide<double> + k_decide_full<double>" if r64 is not None
-                    else "k_decide<float> + k_decide_full<float>"}
+                    "match": "k_match<double>" if r64 is not None else "k_match<float>"}
     roof = roofline(main_run, frame.n, stage_kernel, head, "fp64" if r64 is not None else "fp32_mixed")
     roof["kernel"] += " in the " + ("FP64" if r64 is not None else "FP32-mixed") + " frame"
 

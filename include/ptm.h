@@ -82,13 +82,19 @@ enum { PTM_F_HOST_POINTERS = 1u << 0, /* inputs/outputs are host pointers (stage
         * hulls.  Atoms with fewer than 18 neighbours in the frame, or whose
         * cell is unbounded, keep the Euclidean order.  The knn output stays
         * Euclidean.  Costs 504 more bytes of scratch per atom. */
-       PTM_F_TOPOLOGICAL = 1u << 2 };
+       PTM_F_TOPOLOGICAL = 1u << 2,
+       /* decide every atom that has a candidate by the full rule (every
+        * candidate superposed in FP64, ties by template and representative,
+        * Alg. 1) instead of the working-precision common rule: results are
+        * unchanged, only slower.  For tests of the full rule's path. */
+       PTM_F_FULL_RULE = 1u << 3 };
 
 /* pipeline stages reported by ptm_stage_times */
 enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2,
        PTM_STAGE_TOPO = 3 /* hulls of 6, 12, 14 neighbours, codes, lookup */,
-       PTM_STAGE_CAND = 4 /* candidate pair list */, PTM_STAGE_EVAL = 5 /* superposition of every pair */,
-       PTM_STAGE_DECIDE = 6 /* decision, orientation, strain, alloy, write-back */, PTM_NSTAGES = 7 };
+       PTM_STAGE_MATCH = 4 /* superposition of every candidate, decision, orientation, strain, alloy,
+                              write-back */,
+       PTM_NSTAGES = 5 };
 
 typedef struct {
     int device;                /* HIP device ordinal */
@@ -100,10 +106,6 @@ typedef struct {
                                   work before they start. */
     uint64_t hbm_budget_bytes; /* cap on scratch + in-flight frames; 0 = no cap */
     uint32_t flags;            /* PTM_F_* */
-    int64_t pair_capacity;     /* 0: the candidate pair list holds 6n + 64 (atom, correspondence)
-                                  pairs; a smaller positive value caps it there, for tests of the path
-                                  that decides the atoms past the capacity by the full rule (results
-                                  are unchanged).  Negative -> PTM_E_INVALID. */
 } ptm_config;
 
 /* Per-atom outputs, n entries each (arrays with a second dimension are
@@ -232,7 +234,7 @@ ptm_status ptm_stage_times(const ptm_ctx *ctx, double *ms, int n);
 enum { PTM_INFO_CELLS = 0,      /* cells of the binning grid */
        PTM_INFO_KNN_EXACT = 1,  /* atoms whose neighbours the exact (whole-wave) search found */
        PTM_INFO_PAIRS = 2,      /* (atom, candidate correspondence) pairs superposed */
-       PTM_INFO_DECIDE_FULL = 3, /* atoms decided by the full rule (near tie, FP32 margin, overflow) */
+       PTM_INFO_DECIDE_FULL = 3, /* atoms decided by the full rule (near tie, FP32 margin) */
        PTM_NINFO = 4 };
 ptm_status ptm_frame_info(const ptm_ctx *ctx, int64_t *info, int n);
 

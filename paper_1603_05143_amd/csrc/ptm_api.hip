@@ -28,18 +28,10 @@ namespace ptm {
 // ------------------------------------------------------------ scratch
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// capacity of the flat candidate-pair list (typical atoms have 1-3 pairs;
-// atoms beyond the capacity are decided by the full rule, k_decide_full);
-// cap_override > 0 replaces the default (a ptm_config field for tests)
-int64_t pair_capacity(int64_t n, int64_t cap_override) {
-    const int64_t def = 6 * n + 64;
-    return cap_override > 0 && cap_override < def ? cap_override : def;
-}
-
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo, int64_t cap) {
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
-    // count (+ the k-NN and decision leftover counters and the box flag), start
+    // count (+ the frame's counters and the box flag), start
     b += align_up(4 * (size_t)(cells + FRAME_COUNTERS)) * 2;
     b += align_up(8 * (size_t)n) * 3;         // sorted positions
     b += align_up(4 * (size_t)n * KMAX);      // neighbour ids
@@ -47,9 +39,6 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     b += align_up(4 * (size_t)n * NGRP);      // code ids
     b += align_up(8 * (size_t)n * NGRP);      // labellings
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
-    b += align_up(8 * (size_t)(pair_slots(n) + 1)) * 2;  // candidate counts and offsets per (atom, group)
-    b += align_up(16 * (size_t)cap);  // pairs and their RMSD
-    b += align_up(40 * (size_t)cap);  // their quaternion and scale
     b += align_up(scan_tmp);
     if (topo) {
         b += align_up(4 * (size_t)n * VK);      // the 18 Euclidean neighbours' ids
@@ -60,18 +49,15 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     return b;
 }
 
-bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, int64_t cap, std::string &err) {
+bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err) {
     int nb = bounds_blocks(n);
-    size_t scan_tmp = 0, scan_tmp2 = 0;
+    size_t scan_tmp = 0;
     if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
-                                         (int)(cells + 1)) != hipSuccess ||
-        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp2, (int64_t *)nullptr, (int64_t *)nullptr,
-                                         pair_slots(n) + 1) != hipSuccess) {
+                                         (int)(cells + 1)) != hipSuccess) {
         err = "hipcub scan size query failed";
         return false;
     }
-    if (scan_tmp2 > scan_tmp) scan_tmp = scan_tmp2;
-    size_t need = frame_bytes(n, cells, nb, scan_tmp, topo, cap);
+    size_t need = frame_bytes(n, cells, nb, scan_tmp, topo);
     if (need > bytes) {
         if (pooled) {
             // a pooled buffer is sized for its class and never reallocated
@@ -107,16 +93,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, int64_t cap, std
     code = (int32_t *)take(4 * (size_t)n * NGRP);
     ord = (uint64_t *)take(8 * (size_t)n * NGRP);
     part = (double *)take(8 * 7 * (size_t)nb);
-    match.cap = cap;
-    match.cnt = (int64_t *)take(8 * (size_t)(pair_slots(n) + 1));
-    match.off = (int64_t *)take(8 * (size_t)(pair_slots(n) + 1));
-    match.pairs = (uint2 *)take(8 * (size_t)match.cap);
-    match.r = (double *)take(8 * (size_t)match.cap);
-    match.qs = take(40 * (size_t)match.cap);
     scan_tmp_ptr = take(scan_tmp);
     scan_tmp_bytes = scan_tmp;
-    match.scan_tmp = scan_tmp_ptr;
-    match.scan_tmp_bytes = scan_tmp;
     id18 = topo ? (int32_t *)take(4 * (size_t)n * VK) : nullptr;
     rel18 = topo ? (double *)take(8 * (size_t)n * VK * 3) : nullptr;
     vf = topo ? (uint32_t *)take(4 * (size_t)n * (2 * VK - 4)) : nullptr;
@@ -210,8 +188,9 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     if ((ps = mark(PTM_STAGE_BIN)) != PTM_OK) return ps;
     int64_t cells = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     // count[cells + 1] and count[cells + 2] count the atoms the fast k-NN
-    // search and the common-case decision leave over; count[cells + 3] is
-    // the box flag (set by the k-NN kernels, read by every later stage)
+    // search leaves over and those the full rule decides; count[cells + 3]
+    // is the box flag (set by the k-NN kernels, read by every later stage);
+    // job_counter() the candidates superposed
     launch_zero(S.count, cells + FRAME_COUNTERS, st);
     const int32_t *box_fail = S.count + cells + 3;
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
@@ -233,21 +212,17 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     const uint32_t m = J.mask;
     const uint32_t need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
     launch_topo(n, S.nbr_rel, S.nbr_id, ctx->view, need, S.code, S.ord, box_fail, st);
-    if ((ps = mark(PTM_STAGE_CAND)) != PTM_OK) return ps;
+    if ((ps = mark(PTM_STAGE_MATCH)) != PTM_OK) return ps;
     MatchOut O = {J.out.type,       J.out.alloy,     J.out.rmsd,
                   J.out.scale,      J.out.quat,      J.out.neighbours,
                   J.out.strain,     J.out.vm_strain, J.out.strain_residual,
                   J.out.nn_distance, J.out.quat_fz, J.out.best_type};
     const bool f32 = ctx->precision == PTM_FP32_MIXED;
-    launch_cand(n, ctx->view, S.code, m, S.match, box_fail, st);
-    if ((ps = mark(PTM_STAGE_EVAL)) != PTM_OK) return ps;
-    launch_eval(n, S.nbr_rel, ctx->view, S.ord, S.match, f32, box_fail, st);
-    if ((ps = mark(PTM_STAGE_DECIDE)) != PTM_OK) return ps;
-    // slot_of (free since the scatter) holds the decision's leftover list;
     // the knn output is the Euclidean order (the 18-neighbour list of the
     // topological ordering starts with it)
-    launch_decide(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff, O, S.match,
-                  S.slot_of, S.count + cells + 2, J.topo ? S.id18 : S.nbr_id, J.out.knn, box_fail, f32, st);
+    launch_match(n, S.nbr_rel, S.nbr_id, S.sid, J.species, ctx->view, S.code, S.ord, m, J.cutoff,
+                 (ctx->flags & PTM_F_FULL_RULE) != 0, O, S.count + cells + 2, job_counter(S.count, cells),
+                 J.topo ? S.id18 : S.nbr_id, J.out.knn, box_fail, f32, st);
     if ((ps = mark(PTM_NSTAGES)) != PTM_OK) return ps;
     PTM_HIP(ctx, hipGetLastError());
     return PTM_OK;
@@ -362,9 +337,8 @@ ptm_status classify_frame(ptm_ctx *ctx, FrameScratch &S, bool noalloc, const dou
     HostStage H;
     ptm_status st = stage_in(ctx, positions, species, out, n_atoms, J, H);
     if (st != PTM_OK) return st;
-    const int64_t cap = pair_capacity(n_atoms, ctx->pair_cap);
     auto reserve = [&](int64_t cells) -> ptm_status {
-        if (S.reserve(n_atoms, cells, J.topo, cap, ctx->err)) return PTM_OK;
+        if (S.reserve(n_atoms, cells, J.topo, ctx->err)) return PTM_OK;
         return noalloc ? PTM_E_TOO_LARGE : PTM_E_NOMEM;
     };
     // bounds first (needs scratch for the partials): reserve with a tiny grid
@@ -382,7 +356,7 @@ ptm_status classify_frame(ptm_ctx *ctx, FrameScratch &S, bool noalloc, const dou
     }
     J.grid = make_grid(box, mn, mx, n_atoms, J.topo ? VK : KMAX);
     int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
-    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo, cap) > ctx->budget) {
+    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo) > ctx->budget) {
         ctx->err = "frame scratch exceeds the HBM budget";
         return PTM_E_NOMEM;
     }
@@ -409,14 +383,12 @@ ptm_status classify_frame(ptm_ctx *ctx, FrameScratch &S, bool noalloc, const dou
     }
     if (prof) {
         int32_t left[2] = {0, 0};
-        int64_t pairs = 0;
+        unsigned long long pairs = 0;
         PTM_HIP(ctx, hipMemcpy(left, S.count + cells + 1, 8, hipMemcpyDeviceToHost));
-        PTM_HIP(ctx, hipMemcpy(&pairs, S.match.off + pair_slots(n_atoms), 8, hipMemcpyDeviceToHost));
-        // the pairs past the capacity go to the full rule with their atoms
-        if (pairs > S.match.cap) pairs = S.match.cap;
+        PTM_HIP(ctx, hipMemcpy(&pairs, job_counter(S.count, cells), 8, hipMemcpyDeviceToHost));
         ctx->prof_info[PTM_INFO_CELLS] = cells;
         ctx->prof_info[PTM_INFO_KNN_EXACT] = knn_fast_applies(J.grid) ? left[0] : n_atoms;
-        ctx->prof_info[PTM_INFO_PAIRS] = pairs;
+        ctx->prof_info[PTM_INFO_PAIRS] = (int64_t)pairs;
         ctx->prof_info[PTM_INFO_DECIDE_FULL] = left[1];
     }
     ctx->prof_valid = prof;
@@ -481,11 +453,6 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
     ctx->precision = cfg->precision;
     ctx->budget = cfg->hbm_budget_bytes;
     ctx->flags = cfg->flags;
-    if (cfg->pair_capacity < 0) {
-        delete ctx;
-        return PTM_E_INVALID;
-    }
-    ctx->pair_cap = cfg->pair_capacity;
     if (hipSetDevice(ctx->device) != hipSuccess) {
         delete ctx;
         return PTM_E_DEVICE;
@@ -860,20 +827,14 @@ static const HostTables *selftest_tables() {
 
 template <int K, typename RT>
 static void selftest_strain_k(const TemplateDev &D, const double *obs, double *P) {
-    RT v[K][3];
-    double cb[3] = {0, 0, 0};
+    double v[K][3];
     uint64_t tv = 0;
     for (int r = 0; r < K; r++) {
-        for (int d = 0; d < 3; d++) {
-            const double x = obs[3 * (r + 1) + d] - obs[d];
-            v[r][d] = (RT)x;
-            cb[d] += x;
-        }
+        for (int d = 0; d < 3; d++) v[r][d] = obs[3 * (r + 1) + d] - obs[d];
         tv |= (uint64_t)r << (4 * r);
     }
-    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
     RT a0[3], At[3][3], l, Pm[3][3];
-    strain_inputs<K, RT>(D, tv, v, cb, a0, At, l);
+    strain_inputs<K, RT>(D, tv, v, a0, At, l);
     polar_p<RT>(At, l, Pm);
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) P[3 * x + y] = (double)Pm[x][y];

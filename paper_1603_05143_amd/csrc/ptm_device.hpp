@@ -540,15 +540,17 @@ __host__ __device__ inline void jacobi3(T A[3][3], T d[3], T V[3][3]) {
 }
 
 // ---------------------------------------------------------------- strain
-// eq.(6) inputs of a match: with the K neighbour vectors v (rank order; the
-// centre is the origin) and their barycentre cb (of all K + 1 points, FP64),
-// the centred points a_0 = -cb (the centre) and a_r = v_r - cb; then
-// A^T l = sum_i V+_{:,i} a_i^T (V+ the pseudoinverse of the normalised
-// template, column tv(r) + 1 for rank r; tv: nibble r = template vertex of
-// rank r) and l = mean |a_i| (eq. 4, W' = a / l).
-template <int K, typename RT>
-__host__ __device__ inline void strain_inputs(const TemplateDev &D, uint64_t tv, const RT (&v)[K][3],
-                                              const double (&cb)[3], RT (&a0)[3], RT (&At)[3][3], RT &l) {
+// eq.(6) inputs of a match, gathered point by point: with the barycentre cb
+// of the K + 1 points (FP64; the centre is the origin), the centred points
+// are a_0 = -cb (the centre) and a_r = v_r - cb, the difference taken in
+// FP64 and then rounded to RT; A^T l = sum_i V+_{:,i} a_i^T (V+ the
+// pseudoinverse of the normalised template, column tv(r) + 1 for rank r)
+// and l = mean |a_i| (eq. 4, W' = a / l).  strain_begin takes the centre,
+// strain_add one neighbour, and the caller divides l by K + 1 at the end
+// (TPL: a template table entry with the pseudoinverse vpinv).
+template <typename RT, typename TPL>
+__host__ __device__ inline void strain_begin(const TPL &D, const double (&cb)[3], RT (&a0)[3],
+                                             RT (&At)[3][3], RT &l) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
@@ -556,14 +558,32 @@ __host__ __device__ inline void strain_inputs(const TemplateDev &D, uint64_t tv,
     l = sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) At[x][y] = (RT)D.vpinv[x][0] * a0[y];
-#pragma unroll
+}
+
+template <typename RT, typename TPL>
+__host__ __device__ inline void strain_add(const TPL &D, int col, const RT (&ar)[3], RT (&At)[3][3],
+                                           RT &l) {
+#pragma clang fp contract(fast)
+    l += sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * ar[y];
+}
+
+// The same for K neighbour vectors v held in an array (rank order; tv:
+// nibble r = template vertex of rank r): the self-check entry points use
+// it, with the arithmetic of the match kernel.
+template <int K, typename RT>
+__host__ __device__ inline void strain_inputs(const TemplateDev &D, uint64_t tv, const double (&v)[K][3],
+                                              RT (&a0)[3], RT (&At)[3][3], RT &l) {
+    double cb[3] = {0, 0, 0};
+    for (int rr = 0; rr < K; rr++)
+        for (int d = 0; d < 3; d++) cb[d] += v[rr][d];
+    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
+    strain_begin<RT>(D, cb, a0, At, l);
     for (int rr = 0; rr < K; rr++) {
         RT ar[3];
-        for (int d = 0; d < 3; d++) ar[d] = v[rr][d] - (RT)cb[d];
-        l += sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
-        const int col = (int)((tv >> (4 * rr)) & 0xF) + 1;
-        for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * ar[y];
+        for (int d = 0; d < 3; d++) ar[d] = (RT)(v[rr][d] - cb[d]);
+        strain_add<RT>(D, (int)((tv >> (4 * rr)) & 0xF) + 1, ar, At, l);
     }
     l /= RT(K + 1);
 }

@@ -23,9 +23,13 @@
 
 namespace ptm {
 
-// int32 entries after the cell counts: the scan's end, the k-NN and decision
-// leftover counters and the box flag
-constexpr int64_t FRAME_COUNTERS = 4;
+// int32 entries after the cell counts: the scan's end, the k-NN leftover
+// counter, the full-rule counter, the box flag, then (at the first 8-byte
+// aligned entry) the 64-bit count of superposed candidates
+constexpr int64_t FRAME_COUNTERS = 7;
+inline unsigned long long *job_counter(int32_t *count, int64_t cells) {
+    return (unsigned long long *)(count + ((cells + 5) & ~(int64_t)1));
+}
 
 // Device scratch of one frame (one allocation, carved into arrays).
 struct FrameScratch {
@@ -45,8 +49,7 @@ struct FrameScratch {
     double *part = nullptr;
     void *scan_tmp_ptr = nullptr;
     size_t scan_tmp_bytes = 0;
-    MatchScratch match = {};
-    bool reserve(int64_t n, int64_t cells, bool topo, int64_t cap, std::string &err);
+    bool reserve(int64_t n, int64_t cells, bool topo, std::string &err);
     void release();
 };
 
@@ -92,8 +95,7 @@ struct Ticket {
     bool box_fail = false;  // the frame's periodic box was too short (PTM_E_BOX)
 };
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo, int64_t cap);
-int64_t pair_capacity(int64_t n, int64_t cap_override);
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo);
 // the box flag of a frame whose kernels have been enqueued (count[cells + 3])
 inline int32_t *box_flag(const FrameScratch &S, const Grid &g) {
     return S.count + (int64_t)g.nc[0] * g.nc[1] * g.nc[2] + 3;
@@ -134,7 +136,6 @@ struct ptm_ctx {
     bool own_stream = false;
     uint64_t budget = 0;
     uint32_t flags = 0;
-    int64_t pair_cap = 0;           // candidate pair capacity override (0: 6n + 64)
     int32_t *pinned = nullptr;      // pinned host word: the box flag of the last ptm_classify
     double *pinned_bounds = nullptr;  // pinned host space: per-block bounds of the frame being set up
     void *noalloc_scratch = nullptr;  // this device's static scratch array (ptm_classify_noalloc)

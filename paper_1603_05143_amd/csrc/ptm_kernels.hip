@@ -12,15 +12,16 @@
 //   k_topo            hulls of the innermost 6 / 12 / 14 neighbours with exact
 //                     predicates (Sec. 4; Alg. 1 requires the centre strictly
 //                     inside), start-edge codes, template table lookups
-//   k_cand_count/fill candidate correspondences of every code (App. A)
-//   k_cand_eval       superposition of every candidate (eqs. 2-4)
-//   k_decide(_full)   decision (Alg. 1), representative, orientation, strain
-//                     (eq. 6, Sec. 8), alloy (Sec. 6, Table 3), derived outputs,
-//                     write-back in input order
+//   k_match           superposition of every candidate correspondence of
+//                     the codes (eqs. 2-4, App. A), decision (Alg. 1; the
+//                     full tie rule in FP64 where needed), representative,
+//                     orientation, strain (eq. 6, Sec. 8), alloy (Sec. 6,
+//                     Table 3), derived outputs, write-back in input order
 //   k_apply_cutoff, k_rmsd_histogram, k_misorientation: post-hoc utilities
 //                     (Sec. 5.1, Sec. 7)
-// One lane owns one atom in every per-atom kernel; atoms are processed in
-// cell order so the lanes of a wave read the same cells.
+// One lane owns one atom in every per-atom kernel (k_match also gives a
+// lane one candidate of its wave's atoms); atoms are processed in cell
+// order so the lanes of a wave read the same cells.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <stdint.h>
@@ -1539,15 +1540,25 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
 // ------------------------------------------------------------------ match
 constexpr int MB = 256;  // threads per block of the match kernels
 
+// What the match kernel keeps of each template in LDS: the normalised
+// points b (eq. 4), the pseudoinverse V+ (eq. 6), the inverses of the
+// rotation group's elements as vertex maps, k and the group order.  The
+// group's quaternions are read from the device tables.
+struct TemplateGeom {
+    double b[NMAX][3];
+    double vpinv[3][NMAX];
+    uint64_t ginv[GMAX];
+    int32_t k, ngroup;
+};
 struct MatchShared {
-    TemplateDev tpl[NT];
+    TemplateGeom geo[NT];
 };
 
 // rank vector of the representative: min over g of (c(g^-1(m)))_m, packed
 // with m = 0 in the most significant nibble.  Only the group elements whose
 // first entry is minimal can win, so the full vectors are built for those
 // alone (a vertex lies in the image of g^-1(0) for |G| / orbit elements).
-__device__ inline uint64_t rep_vector(const TemplateDev &D, uint64_t cmap, int &gbest) {
+__device__ inline uint64_t rep_vector(const TemplateGeom &D, uint64_t cmap, int &gbest) {
     uint32_t first = 16;
     uint64_t cand = 0;  // bit g: g attains the minimal first entry
     for (int g = 0; g < D.ngroup; g++) {
@@ -1579,11 +1590,13 @@ struct CandEval {
     T c;  // FP32 form: bound on the eigen-solve's excess of RMSD^2 (f32_excess_bound)
 };
 
-// eq.(3) for one candidate: observed rank r <-> template vertex tv(r).
-// a[] are the centred observed points (row 0 = centre), in the working
-// precision T; the template comes from the FP64 table.
-template <int K, typename T>
-__device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const TemplateDev &D, uint64_t tv_of_rank,
+// eq.(3) for one candidate of K = 6, 12 or 14 neighbours: observed rank r
+// <-> template vertex tv(r).  a[] are the centred observed points (row 0 =
+// centre, rows past K unused), in the working precision T; the template
+// comes from the FP64 table.  K is a run-time value, so lanes of different
+// hull sizes run one code path (ranks past a lane's K are skipped).
+template <typename T>
+__device__ inline void eval_candidate(int K, const T (&a)[NMAX][3], T Ga, const TemplateGeom &D, uint64_t tv_of_rank,
                                       CandEval<T> &out) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
@@ -1597,7 +1610,8 @@ __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const Templat
         Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
     }
 #pragma unroll
-    for (int r = 0; r < K; r++) {
+    for (int r = 0; r < KMAX; r++) {
+        if (r >= K) break;
         const double *b64 = D.b[nib(tv_of_rank, r) + 1];
         const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
         for (int x = 0; x < 3; x++)
@@ -1619,7 +1633,8 @@ __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const Templat
         }
     }
 #pragma unroll
-    for (int r = 0; r < K; r++) {
+    for (int r = 0; r < KMAX; r++) {
+        if (r >= K) break;
         const double *b64 = D.b[nib(tv_of_rank, r) + 1];
         const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
         for (int x = 0; x < 3; x++) {
@@ -1632,26 +1647,21 @@ __device__ inline void eval_candidate(const T (&a)[NMAX][3], T Ga, const Templat
 }
 
 // eq.(3) for one candidate with the observed points streamed from the
-// (cached) neighbour vectors instead of held in registers: the barycentre,
-// then covariance and G_a / G_b, then the residual, each pass recomputing
-// the centred points.  The arithmetic and its order are those of
-// load_centred followed by eval_candidate, so the results are identical.
-template <int K, typename T>
-__device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t n, int64_t p,
-                                     const TemplateDev &D, uint64_t tv, CandEval<T> &out) {
+// (cached) neighbour vectors instead of held in registers: covariance and
+// G_a / G_b in one pass, the residual in a second, each recomputing the
+// centred points from the barycentre cb (FP64, eq. 2).  K run-time, as in
+// eval_candidate.
+template <typename T>
+__device__ inline void eval_streamed(int K, const double *__restrict__ nbr_rel, int64_t n, int64_t p,
+                                     const double (&cb)[3], const TemplateGeom &D, uint64_t tv, CandEval<T> &out) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
-    double c[3] = {0, 0, 0};
-#pragma unroll 2
-    for (int r = 0; r < K; r++)
-        for (int d = 0; d < 3; d++) c[d] += nbr_rel[((int64_t)r * 3 + d) * n + p];
-    for (int d = 0; d < 3; d++) c[d] /= (K + 1);
     T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     T Gb = 0;
     double g = 0;
-    const T a0[3] = {(T)(-c[0]), (T)(-c[1]), (T)(-c[2])};
-    for (int d = 0; d < 3; d++) g += c[d] * c[d];
+    const T a0[3] = {(T)(-cb[0]), (T)(-cb[1]), (T)(-cb[2])};
+    for (int d = 0; d < 3; d++) g += cb[d] * cb[d];
     {
         const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
         for (int x = 0; x < 3; x++)
@@ -1662,7 +1672,7 @@ __device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t
     for (int r = 0; r < K; r++) {
         T a[3];
         for (int d = 0; d < 3; d++) {
-            double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d];
+            double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - cb[d];
             a[d] = (T)x;
             g += x * x;
         }
@@ -1690,7 +1700,7 @@ __device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t
 #pragma unroll 2
     for (int r = 0; r < K; r++) {
         T a[3];
-        for (int d = 0; d < 3; d++) a[d] = (T)(nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d]);
+        for (int d = 0; d < 3; d++) a[d] = (T)(nbr_rel[((int64_t)r * 3 + d) * n + p] - cb[d]);
         const double *b64 = D.b[nib(tv, r) + 1];
         const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
         for (int x = 0; x < 3; x++) {
@@ -1703,37 +1713,26 @@ __device__ inline void eval_streamed(const double *__restrict__ nbr_rel, int64_t
 }
 
 // observed points of one hull group: centre (row 0) and the innermost K
-// neighbours, minus their barycentre (eq. 2); Ga = sum of squared norms
-template <int K, typename T, bool OnePass = false>
-__device__ inline void load_centred(const double *__restrict__ nbr_rel, int64_t n, int64_t p, T (&a)[NMAX][3],
-                                    T &Ga) {
-    // OnePass: every FP64 input loaded at once (more loads in flight, more
-    // registers); otherwise two passes over the (cached) neighbour vectors,
-    // the barycentre and then the centred points.  Same arithmetic either way.
-    double v[OnePass ? KMAX : 1][3];
-    double c[3] = {0, 0, 0};
-#pragma unroll
-    for (int r = 0; r < K; r++)
-        for (int d = 0; d < 3; d++) {
-            double x = nbr_rel[((int64_t)r * 3 + d) * n + p];
-            if constexpr (OnePass) v[r][d] = x;
-            c[d] += x;
-        }
-    for (int d = 0; d < 3; d++) c[d] /= (K + 1);
+// neighbours (K run-time; rows past it are left alone), minus their
+// barycentre cb (eq. 2, FP64 differences rounded to T); Ga = sum of squared
+// norms
+template <typename T>
+__device__ inline void load_centred(int K, const double *__restrict__ nbr_rel, int64_t n, int64_t p,
+                                    const double (&cb)[3], T (&a)[NMAX][3], T &Ga) {
     double g = 0;
     for (int d = 0; d < 3; d++) {
-        a[0][d] = (T)(-c[d]);
-        g += c[d] * c[d];
+        a[0][d] = (T)(-cb[d]);
+        g += cb[d] * cb[d];
     }
 #pragma unroll
-    for (int r = 0; r < K; r++)
+    for (int r = 0; r < KMAX; r++) {
+        if (r >= K) break;
         for (int d = 0; d < 3; d++) {
-            double x;
-            if constexpr (OnePass) x = v[r][d] - c[d];
-            else x = nbr_rel[((int64_t)r * 3 + d) * n + p] - c[d];
+            const double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - cb[d];
             a[r + 1][d] = (T)x;
             g += x * x;
         }
+    }
     Ga = (T)g;
 }
 
@@ -1764,12 +1763,13 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
     Candidate cd = T.cand[grp][c];
-    const TemplateDev &D = M.tpl[cd.tmpl];
+    const TemplateGeom &G = M.geo[cd.tmpl];
+    const TemplateDev &D = T.tpl[cd.tmpl];  // the group's quaternions
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
     const int type = ((double)ev.r <= cutoff) ? cd.tmpl + 1 : 0;
     if (O.best_type) O.best_type[i] = (int8_t)(cd.tmpl + 1);
     int g;
-    const uint64_t rep = rep_vector(D, rank_of_tv(cd.perm, ord, K), g);
+    const uint64_t rep = rep_vector(G, rank_of_tv(cd.perm, ord, K), g);
     {
         // q' = q * conj(q_g), sign fixed so that the first non-zero component is positive
         const double *qg = D.gq[g];
@@ -1795,7 +1795,7 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
             const RT a0 = q[0] * sc, a1 = q[1] * sc, a2 = q[2] * sc, a3 = q[3] * sc;
             RT best[4] = {a0, a1, a2, a3};
             RT bw = RT(-1);
-            for (int h = 0; h < D.ngroup; h++) {
+            for (int h = 0; h < G.ngroup; h++) {
                 const double *qh = D.gq[h];
                 const RT w2 = (RT)qh[0], x2 = -(RT)qh[1], y2 = -(RT)qh[2], z2 = -(RT)qh[3];
                 const RT c0 = a0 * w2 - a1 * x2 - a2 * y2 - a3 * z2;
@@ -1818,7 +1818,7 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
         }
         if (O.nn_distance) {
             // hydrostatic part (Sec. 8): template vertex 0 lies at |b_1| in eq.(4) units
-            const double *b1 = D.b[1];
+            const double *b1 = G.b[1];
             O.nn_distance[i] = ev.s > RT(0) ? sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]) / (double)ev.s : 0.0;
         }
         if (O.strain_residual) O.strain_residual[i] = (double)resid;
@@ -1883,94 +1883,37 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
 }
 
 
-// Winner outputs with the superposition recomputed from the points.
+// Outputs of the winning candidate from its superposition ev (r, q, s):
+// the strain inputs are gathered from the points in one pass (the
+// barycentre cb is known); the optional eq.(6) residual takes a second.
 template <int K, typename RT>
 __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
-                              const CandEval<RT> &ev, const double *__restrict__ nbr_rel, double cutoff, int64_t p,
-                              int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
+                              const CandEval<RT> &ev, const double (&cb)[3], const double *__restrict__ nbr_rel,
+                              double cutoff, int64_t p, int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
                               const int8_t *__restrict__ species, const MatchOut &O) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
     Candidate cd = T.cand[grp][c];
-    const TemplateDev &D = M.tpl[cd.tmpl];
+    const TemplateGeom &D = M.geo[cd.tmpl];
     const uint64_t tv = tv_of_rank(cd.perm, ord, K);
-    RT l = 0, resid = 0;
-    RT At[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    {
-        RT a[NMAX][3], Ga;
-        // ev: the winner's superposition, already evaluated from these points
-        load_centred<K, RT>(nbr_rel, n, p, a, Ga);
-        for (int r = 0; r <= K; r++) l += sqrt(a[r][0] * a[r][0] + a[r][1] * a[r][1] + a[r][2] * a[r][2]);
-        l /= RT(K + 1);
-        for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][0] * a[0][y];
-#pragma unroll
-        for (int r = 0; r < K; r++) {
-            int col = (int)nib(tv, r) + 1;
-            for (int x = 0; x < 3; x++)
-                for (int y = 0; y < 3; y++) At[x][y] += (RT)D.vpinv[x][col] * a[r + 1][y];
-        }
-        if (O.strain_residual) {
-            // eq.(6) residual: sum over points of |V_i A^T - W'_i|^2 (W' = a / l)
-            for (int r = 0; r <= K; r++) {
-                const double *v = D.b[r == 0 ? 0 : (int)nib(tv, r - 1) + 1];
-                for (int y = 0; y < 3; y++) {
-                    RT d = (RT)v[0] * At[0][y] + (RT)v[1] * At[1][y] + (RT)v[2] * At[2][y] - a[r][y];
-                    resid += d * d;
-                }
-            }
-            resid /= l * l;
-        }
-    }
-    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, resid, cutoff, p, n, i, nbr_id, species, O);
-}
-
-// Winner outputs from the superposition stored by k_cand_eval (q, s) and
-// its RMSD r: only the strain inputs are gathered from the points, in two
-// passes (barycentre, then centred points) without holding them.
-template <int K, typename RT>
-__device__ inline void finish_stored(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
-                                     const double *__restrict__ nbr_rel, double r, const RT *__restrict__ qs,
-                                     double cutoff, int64_t p, int64_t n, int32_t i,
-                                     const int32_t *__restrict__ nbr_id, const int8_t *__restrict__ species,
-                                     const MatchOut &O) {
-    // products and sums may fuse into FMAs here (one rounding instead of two; no
-    // result depends on a particular rounding)
-#pragma clang fp contract(fast)
-    Candidate cd = T.cand[grp][c];
-    const TemplateDev &D = M.tpl[cd.tmpl];
-    const uint64_t tv = tv_of_rank(cd.perm, ord, K);
-    CandEval<RT> ev;
-    ev.r = (RT)r;
-    for (int k = 0; k < 4; k++) ev.q[k] = qs[k];
-    ev.s = qs[4];
-    // every point is loaded once and held in registers in the form's real
-    // type (a second pass over global memory misses the L2); the FP32 form
-    // centres the rounded points, an error of 2^-24 relative, far inside its
-    // strain tolerance.  The optional residual pass below reads the vectors
-    // again, so that they are dead once A^T is formed.
-    constexpr int HALF = K / 2;
-    RT v[K][3];
-    double cb[3] = {0, 0, 0};
-#pragma unroll
-    for (int rr = 0; rr < K; rr++)
-        for (int d = 0; d < 3; d++) {
-            const double x = nbr_rel[((int64_t)rr * 3 + d) * n + p];
-            v[rr][d] = (RT)x;
-            cb[d] += x;
-        }
-    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
     RT a0[3], At[3][3], l;
-    strain_inputs<K, RT>(D, tv, v, cb, a0, At, l);
+    strain_begin<RT>(D, cb, a0, At, l);
+#pragma unroll
+    for (int rr = 0; rr < K; rr++) {
+        RT ar[3];
+        for (int d = 0; d < 3; d++) ar[d] = (RT)(nbr_rel[((int64_t)rr * 3 + d) * n + p] - cb[d]);
+        strain_add<RT>(D, (int)nib(tv, rr) + 1, ar, At, l);
+    }
+    l /= RT(K + 1);
     RT resid = 0;
     if (O.strain_residual) {
-        // eq.(6) residual, a third pass over the points: sum of |V_i A^T - a_i|^2 / l^2
+        // eq.(6) residual: sum over points of |V_i A^T - a_i|^2 / l^2
         for (int y = 0; y < 3; y++) {
             RT d = (RT)D.b[0][0] * At[0][y] + (RT)D.b[0][1] * At[1][y] + (RT)D.b[0][2] * At[2][y] - a0[y];
             resid += d * d;
         }
-#pragma unroll HALF
+#pragma unroll 2
         for (int rr = 0; rr < K; rr++) {
             const double *v = D.b[(int)nib(tv, rr) + 1];
             for (int y = 0; y < 3; y++) {
@@ -2008,118 +1951,181 @@ __device__ inline void write_none(const MatchOut &O, int32_t i) {
 }
 
 __device__ inline void load_templates(MatchShared &M, const TablesView &T) {
-    const uint32_t *src = (const uint32_t *)T.tpl;
-    uint32_t *dst = (uint32_t *)M.tpl;
-    for (int w = threadIdx.x; w < (int)(sizeof(TemplateDev) * NT / 4); w += blockDim.x) dst[w] = src[w];
+    constexpr int NB = NMAX * 3;  // doubles of b, and of vpinv
+    for (int w = threadIdx.x; w < NT * 2 * NB; w += blockDim.x) {
+        const int t = w / (2 * NB), e = w % (2 * NB);
+        if (e < NB) (&M.geo[t].b[0][0])[e] = (&T.tpl[t].b[0][0])[e];
+        else (&M.geo[t].vpinv[0][0])[e - NB] = (&T.tpl[t].vpinv[0][0])[e - NB];
+    }
+    for (int w = threadIdx.x; w < NT * GMAX; w += blockDim.x) M.geo[w / GMAX].ginv[w % GMAX] = T.tpl[w / GMAX].ginv[w % GMAX];
+    if ((int)threadIdx.x < NT) {
+        M.geo[threadIdx.x].k = T.tpl[threadIdx.x].k;
+        M.geo[threadIdx.x].ngroup = T.tpl[threadIdx.x].ngroup;
+    }
     __syncthreads();
 }
 
-// Candidates of one atom: pass 1 counts them (mask applied), pass 2 lists
-// them as (atom, group, candidate) pairs at the atom's offset.
-// The pair list is ordered by tiles of PAIR_TILE atoms, then hull group,
-// then atom: the superposition kernel's waves see one neighbour count K at a
-// time (a tile's three group runs are short, so an atom's vectors are still
-// in the L2 when its next group comes).  cnt[pidx(p, g)] = enabled
-// candidates of atom p in group g (0 for the padding atoms p >= n);
-// cnt[pair_slots(n)] = 0, so that the exclusive scan off[] ends with the
-// total.
-__global__ void __launch_bounds__(256) k_cand_count(int64_t n, TablesView T, const int32_t *__restrict__ code,
-                                                    uint32_t mask, int64_t *__restrict__ cnt,
-                                                    const int32_t *__restrict__ box_fail) {
-    const int64_t np = pair_slots(n) / NGRP;  // atoms rounded up to whole tiles
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p > np || *box_fail) return;
-    if (p == np) {
-        cnt[pair_slots(n)] = 0;
+// ------------------------------------------------------------ match stage
+// One kernel superposes every candidate correspondence of the atoms' hull
+// codes (eq. 3), takes the decision of Alg. 1 and writes the outputs of the
+// winner.  A wave owns 64 consecutive atoms (cell order):
+//  A. lane = atom: the Euclidean neighbour list is copied out, the
+//     barycentres of the 6-, 12- and 14-neighbour groups (eq. 2, FP64) and
+//     the first candidate of each code go to LDS, the enabled candidates
+//     are counted;
+//  B. the wave's candidates form one job list, atom after atom and within
+//     an atom in (group, candidate) order, superposed 64 at a time with
+//     lane = job (the superposition takes the hull size as a run-time
+//     value, so a chunk mixing sizes runs one code path); after each chunk
+//     every atom lane folds its jobs of the chunk, in order, into its
+//     running minimum and marks itself as the owner of its jobs in the
+//     next chunk;
+//  C. an atom whose decision the common rule cannot take (a near tie, an
+//     FP32 margin that the error bounds do not clear) is decided by the
+//     full rule in FP64 by the whole wave; the other winners are regrouped
+//     by hull size across the block and finished with lane = atom.
+// Nothing per candidate leaves the chip: the neighbour vectors are read
+// once per atom in A and again from the caches by the jobs and the finish.
+
+// LDS of one wave during A and B
+template <typename RT>
+struct MatchWaveLds {
+    double cb[NGRP][3][64];  // barycentre of each hull group of the wave's atoms
+    int32_t k0[NGRP][64];    // first candidate of each atom's code in the group's list
+    int32_t cnt[64];         // enabled candidates of each atom per group, 8 bits each
+    int32_t off[64];         // each atom's first job
+    int32_t owner[64];       // the atom of each job of the current chunk
+    double r[64];            // the current chunk's results: RMSD,
+    RT qs[5][64];            // quaternion and scale,
+    float d2[64];            // FP32 form: excess bound (f32_excess_bound),
+    int32_t cand[64];        // candidate index in the group's list
+};
+// LDS of the block's regrouped winners (C)
+template <typename RT>
+struct MatchRegroupLds {
+    double r[MB];
+    double cb[3][MB];
+    RT qs[5][MB];
+    int32_t p[MB], c[MB];
+    int8_t g[MB];
+};
+template <typename RT>
+struct MatchLds {
+    MatchShared M;
+    // copies of the kernel's table view and output pointers for the full
+    // rule, a call: arguments it takes by reference would otherwise be
+    // copied to per-lane scratch memory by every lane
+    TablesView T;
+    MatchOut O;
+    int32_t cnt[MB / 64][NGRP];
+    union {
+        MatchWaveLds<RT> w[MB / 64];
+        MatchRegroupLds<RT> g;
+    } u;
+};
+
+// LDS written by some lanes of a wave and then read by others of the same
+// wave: a wave's LDS instructions complete in issue order, so the only
+// requirement is that the compiler keeps them on their side of this point.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one job: the candidate with tv of the atom at p, K neighbours, barycentre cb
+template <typename RT>
+__device__ inline void eval_job(int K, const double *__restrict__ nbr_rel, int64_t n, int64_t p,
+                                const double (&cb)[3], const TemplateGeom &D, uint64_t tv, CandEval<RT> &ev) {
+    eval_streamed<RT>(K, nbr_rel, n, p, cb, D, tv, ev);
+}
+
+// The full rule of Alg. 1 for the wave's atom a (at p), in FP64, by the
+// whole wave: lane j superposes the atom's j-th candidate (the codes of one
+// atom hold at most 64 together, checked when the tables are built), the
+// minimum r* is reduced over the wave, every enabled candidate within the
+// tie tolerance of r* computes its representative vector, the (template,
+// representative) minimum is reduced, and lane 0 finishes the winner.
+// Wave-uniform arguments; cbw: the barycentres of the wave's atoms.
+__device__ __noinline__ void full_rule(const MatchShared &M, const TablesView &T, int64_t n, int64_t p, int a,
+                          const double (&cbw)[NGRP][3][64], const double *__restrict__ nbr_rel,
+                          const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
+                          const int8_t *__restrict__ species, const int32_t *__restrict__ code,
+                          const uint64_t *__restrict__ ords, uint32_t mask, double cutoff, const MatchOut &O) {
+    const int lane = threadIdx.x & 63;
+    const int32_t i = sid[p];
+    int32_t c0[NGRP], nc[NGRP];
+    uint64_t ord[NGRP];
+    for (int g = 0; g < NGRP; g++) {
+        const int32_t cid = code[(int64_t)g * n + p];
+        ord[g] = ords[(int64_t)g * n + p];
+        c0[g] = cid >= 0 ? T.cstart[g][cid] : 0;
+        nc[g] = cid >= 0 ? T.cstart[g][cid + 1] - c0[g] : 0;
+    }
+    // this lane's candidate
+    int g = -1, c = -1, tmpl = 99;
+    double r = INFINITY;
+    {
+        int j = lane;
+        for (int gg = 0; gg < NGRP && g < 0; gg++) {
+            if (j < nc[gg]) {
+                g = gg;
+                c = c0[gg] + j;
+            } else {
+                j -= nc[gg];
+            }
+        }
+    }
+    Candidate cd = {0, 0, 0};
+    CandEval<double> ev = {0, 0, {0, 0, 0, 0}};
+    if (g >= 0) {
+        cd = T.cand[g][c];
+        if ((mask >> cd.tmpl) & 1) {
+            tmpl = cd.tmpl;
+            const double cb[3] = {cbw[g][0][a], cbw[g][1][a], cbw[g][2][a]};
+            const int K = group_k(g);
+            eval_streamed<double>(K, nbr_rel, n, p, cb, M.geo[cd.tmpl], tv_of_rank(cd.perm, ord[g], K), ev);
+            r = ev.r;
+        }
+    }
+    double m1 = r;
+    for (int off = 32; off > 0; off >>= 1) m1 = fmin(m1, __shfl_xor(m1, off));
+    if (m1 == INFINITY) {  // no candidate of an enabled template
+        if (lane == 0) write_none(O, i);
         return;
     }
-    for (int g = 0; g < NGRP; g++) {
-        int c = 0;
-        const int32_t cid = p < n ? code[(int64_t)g * n + p] : -1;
-        if (cid >= 0)
-            for (int k = T.cstart[g][cid]; k < T.cstart[g][cid + 1]; k++) c += (mask >> T.cand[g][k].tmpl) & 1;
-        cnt[pidx(p, g)] = c;
+    // tie rule: earliest template, then the smallest representative vector
+    int kt = 99;
+    uint64_t krep = ~0ull;
+    if (r <= m1 + 1e-12) {
+        int gsel;
+        kt = tmpl;
+        krep = rep_vector(M.geo[tmpl], rank_of_tv(cd.perm, ord[g], group_k(g)), gsel);
     }
-}
-// an atom with a pair at or beyond the capacity: its group-2 range ends last
-// (off is monotone), so this one test covers all three ranges
-__device__ inline bool pairs_overflow(const int64_t *__restrict__ off, int64_t p, int64_t cap) {
-    return off[pidx(p, NGRP - 1) + 1] > cap;
-}
-
-__global__ void __launch_bounds__(256) k_cand_fill(int64_t n, TablesView T, const int32_t *__restrict__ code,
-                                                   uint32_t mask, const int64_t *__restrict__ off, int64_t cap,
-                                                   uint2 *__restrict__ pairs, const int32_t *__restrict__ box_fail) {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= n || *box_fail) return;
-    const bool over = pairs_overflow(off, p, cap);
-    for (int g = 0; g < NGRP; g++) {
-        int64_t q = off[pidx(p, g)];
-        if (over) {
-            // evaluated directly by the decision kernel; mark its slots below cap
-            const int64_t q1 = min(off[pidx(p, g) + 1], cap);
-            for (; q < q1; q++) pairs[q] = make_uint2(0xFFFFFFFFu, 0u);
-            continue;
+    int bt = kt, bl = lane;
+    uint64_t brep = krep;
+    for (int off = 32; off > 0; off >>= 1) {
+        int ot = __shfl_xor(bt, off), ol = __shfl_xor(bl, off);
+        uint64_t orep = __shfl_xor(brep, off);
+        bool take = ot < bt || (ot == bt && (orep < brep || (orep == brep && ol < bl)));
+        if (take) {
+            bt = ot;
+            brep = orep;
+            bl = ol;
         }
-        const int32_t cid = code[(int64_t)g * n + p];
-        if (cid < 0) continue;
-        for (int k = T.cstart[g][cid]; k < T.cstart[g][cid + 1]; k++)
-            if ((mask >> T.cand[g][k].tmpl) & 1) pairs[q++] = make_uint2((uint32_t)p, ((uint32_t)g << 28) | (uint32_t)k);
     }
-}
-
-// Stored superposition of a pair: quaternion and scale, and in the FP32
-// form its conditioning (see rmsd_f32_bound).
-template <typename RT>
-constexpr int QS_STRIDE = sizeof(RT) == 4 ? 6 : 5;
-
-// One superposition per lane over the flat pair list (grid-stride).
-template <typename RT>
-__global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__restrict__ nbr_rel, TablesView T,
-                                                  const uint64_t *__restrict__ ords, const int64_t *__restrict__ off,
-                                                  int64_t cap, const uint2 *__restrict__ pairs,
-                                                  double *__restrict__ rout, RT *__restrict__ qsout,
-                                                  const int32_t *__restrict__ box_fail) {
-    __shared__ MatchShared M;
-    if (*box_fail) return;  // uniform over the grid
-    load_templates(M, T);
-    int64_t total = off[pair_slots(n)];
-    if (total > cap) total = cap;
-    for (int64_t q = blockIdx.x * (int64_t)MB + threadIdx.x; q < total; q += (int64_t)gridDim.x * MB) {
-        uint2 pr = pairs[q];
-        if (pr.x == 0xFFFFFFFFu) continue;  // atom handled by k_decide
-        int64_t p = pr.x;
-        int g = pr.y >> 28, k = pr.y & 0x0FFFFFFF;
-        Candidate cd = T.cand[g][k];
-        uint64_t ord = ords[(int64_t)g * n + p];
-        CandEval<RT> ev;
-        if constexpr (sizeof(RT) == 4) {
-            // FP32 points fit in registers: load once, evaluate
-            RT a[NMAX][3], Ga;
-            if (g == 0) {
-                load_centred<6, RT, true>(nbr_rel, n, p, a, Ga);
-                eval_candidate<6, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
-            } else if (g == 1) {
-                load_centred<12, RT, true>(nbr_rel, n, p, a, Ga);
-                eval_candidate<12, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
-            } else {
-                load_centred<14, RT, true>(nbr_rel, n, p, a, Ga);
-                eval_candidate<14, RT>(a, Ga, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
-            }
-        } else {
-            // FP64 points would take ~90 registers: stream them instead
-            if (g == 0) eval_streamed<6, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 6), ev);
-            else if (g == 1) eval_streamed<12, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 12), ev);
-            else eval_streamed<14, RT>(nbr_rel, n, p, M.tpl[cd.tmpl], tv_of_rank(cd.perm, ord, 14), ev);
-        }
-        rout[q] = (double)ev.r;
-        RT *o = qsout + QS_STRIDE<RT> * q;
-        o[0] = ev.q[0];
-        o[1] = ev.q[1];
-        o[2] = ev.q[2];
-        o[3] = ev.q[3];
-        o[4] = ev.s;
-        if constexpr (sizeof(RT) == 4) o[5] = ev.c;
+    const int wg = __shfl(g, bl), wc = __shfl(c, bl);
+    // the winning lane's superposition, handed to the finishing lane
+    CandEval<double> we;
+    we.r = __shfl(ev.r, bl);
+    we.s = __shfl(ev.s, bl);
+    for (int k = 0; k < 4; k++) we.q[k] = __shfl(ev.q[k], bl);
+    if (lane == 0) {
+        const double cb[3] = {cbw[wg][0][a], cbw[wg][1][a], cbw[wg][2][a]};
+        if (wg == 0) finish<6, double>(M, T, 0, wc, ord[0], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else if (wg == 1)
+            finish<12, double>(M, T, 1, wc, ord[1], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else finish<14, double>(M, T, 2, wc, ord[2], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
     }
 }
 
@@ -2131,144 +2137,204 @@ __global__ void __launch_bounds__(MB, 4) k_cand_eval(int64_t n, const double *__
 //     rotation built from a unit quaternion rounded to FP32 (15 u), the
 //     residual components (17 u), the 45-term sum of squares (23 u r), the
 //     division and square root (2 u r);
-//   the eigen-solve's excess d2 of RMSD^2 (stored with the pair by
-//     k_cand_eval, see f32_excess_bound; infinite for an eigenpair FP32
-//     cannot resolve): RMSD^2 + d2 has a square root below
-//     RMSD + d2 / (RMSD + sqrt(d2)).
+//   the eigen-solve's excess d2 of RMSD^2 (f32_excess_bound; infinite for
+//     an eigenpair FP32 cannot resolve): RMSD^2 + d2 has a square root
+//     below RMSD + d2 / (RMSD + sqrt(d2)).
 constexpr double RMSD_F32_U = 0x1p-24;
 __device__ inline double rmsd_f32_bound(double r, double d2) {
     if (!(d2 < INFINITY)) return INFINITY;
     return RMSD_F32_U * (72.0 + 25.0 * r) + d2 / (r + sqrt(d2));
 }
 
-// Minimum over an atom's evaluated pairs: best and second-best RMSD and the
-// winning (group, candidate).  q1 > cap: the pairs did not fit the buffer.
-// cs (FP32 form): the pairs' excess bounds d2 at stride 6; then b1 gets the
-// error bound of the winner and lo2 the smallest lower end r - bound over
-// the other pairs (nullptr in the FP64 form).
-__device__ inline void pair_minimum(const int64_t *__restrict__ off, int64_t p,
-                                    const uint2 *__restrict__ pairs, const double *__restrict__ rr, double &m1,
-                                    double &m2, int &arg_grp, int &arg_c, int64_t &arg_q,
-                                    const float *__restrict__ cs, double &b1, double &lo2) {
-    m1 = m2 = INFINITY;
-    b1 = 0.0;
-    lo2 = INFINITY;
-    arg_grp = arg_c = -1;
-    arg_q = -1;
-    int64_t q0[NGRP], q1[NGRP];
-#pragma unroll
-    for (int g = 0; g < NGRP; g++) {
-        q0[g] = off[pidx(p, g)];
-        q1[g] = off[pidx(p, g) + 1];
-    }
-    // the first two pairs of every group load together (most atoms have no
-    // more); further pairs, rare, are read one by one.  The visiting order
-    // (group, then pair) and the strict comparisons are those of a plain
-    // scan, so ties go to the earlier pair as before.
-    double r2[NGRP][2];
-    uint32_t y2[NGRP][2];
-#pragma unroll
-    for (int g = 0; g < NGRP; g++)
-#pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const bool in = q0[g] + j < q1[g];
-            r2[g][j] = in ? rr[q0[g] + j] : INFINITY;
-            y2[g][j] = in ? pairs[q0[g] + j].y : 0u;
-        }
-    auto visit = [&](double r, uint32_t y, int64_t q) {
-        double b = 0.0;
-        if (cs) b = rmsd_f32_bound(r, (double)cs[6 * q]);
-        if (r < m1) {
-            if (cs) lo2 = fmin(lo2, m1 - b1);  // the previous winner joins the others
-            b1 = b;
-            m2 = m1;
-            m1 = r;
-            arg_grp = (int)(y >> 28);
-            arg_c = (int)(y & 0x0FFFFFFF);
-            arg_q = q;
-        } else {
-            if (r < m2) m2 = r;
-            if (cs) lo2 = fmin(lo2, r - b);
-        }
-    };
-#pragma unroll
-    for (int g = 0; g < NGRP; g++) {
-#pragma unroll
-        for (int j = 0; j < 2; j++)
-            if (q0[g] + j < q1[g]) visit(r2[g][j], y2[g][j], q0[g] + j);
-        for (int64_t q = q0[g] + 2; q < q1[g]; q++) visit(rr[q], pairs[q].y, q);
-    }
-}
+constexpr uint32_t ALL_TEMPLATES = (1u << NT) - 1;
 
-// Per-atom decision over the evaluated pairs (Alg. 1 minimum with the tie
-// rule), then the outputs of the winner.  The common case -- a unique
-// winner by more than the tie tolerance (for FP32 pair RMSDs: by more than
-// twice the FP32 bound, and clear of the cut-off) -- is finished here in
-// the working precision; every other atom (a near tie, an FP32 margin too
-// small to trust, pairs that did not fit the buffer) is appended to todo for
-// k_decide_full, so that this kernel stays small.  Registers: the bound of
-// three blocks per CU (FP32) or two (FP64) lets the winner's points stay in
-// registers without spilling (146 and 162 are used: three waves per SIMD).
+// The match kernel (see the section head).  force_full: every atom with a
+// candidate takes the full rule (a test of that path).  full_count counts
+// the atoms the full rule decides, job_count the superposed candidates.
+// Registers: three blocks per CU (168 VGPRs at most) with the LDS of three.
 template <typename RT>
-__global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t n, const double *__restrict__ nbr_rel,
-                                               const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
-                                               const int8_t *__restrict__ species, TablesView T,
-                                               const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
-                                               const int64_t *__restrict__ off, int64_t cap,
-                                               const uint2 *__restrict__ pairs, const double *__restrict__ rr,
-                                               const RT *__restrict__ qs, double cutoff, MatchOut O,
-                                               int32_t *__restrict__ todo, int32_t *__restrict__ todo_count,
-                                               const int32_t *__restrict__ knn_src, int32_t *__restrict__ knn_out,
-                                               const int32_t *__restrict__ box_fail) {
-    __shared__ MatchShared M;
-    // the block's winners regrouped by hull size (see below)
-    __shared__ int32_t s_cnt[MB / 64][NGRP];
-    __shared__ int32_t s_p[MB], s_c[MB];
-    __shared__ int64_t s_q[MB];
-    __shared__ double s_r[MB];
-    __shared__ int8_t s_g[MB];
+__global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__restrict__ nbr_rel,
+                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
+                                                const int8_t *__restrict__ species, TablesView T,
+                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
+                                                uint32_t mask, double cutoff, int force_full, MatchOut O,
+                                                int32_t *__restrict__ full_count,
+                                                unsigned long long *__restrict__ job_count,
+                                                const int32_t *__restrict__ knn_src, int32_t *__restrict__ knn_out,
+                                                const int32_t *__restrict__ box_fail) {
+    __shared__ MatchLds<RT> L;
     if (*box_fail) return;  // uniform over the grid
-    load_templates(M, T);
-    const int64_t p = blockIdx.x * (int64_t)MB + threadIdx.x;
-    double m1 = INFINITY, m2 = INFINITY;
-    int arg_grp = -1, arg_c = -1;
-    int64_t arg_q = -1;
-    int cls = -1;  // hull group of the winner to finish here, -1 for none
-    if (p < n) {
+    if (threadIdx.x == 0) {
+        L.T = T;
+        L.O = O;
+    }
+    load_templates(L.M, T);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    MatchWaveLds<RT> &W = L.u.w[wv];
+    const int64_t wbase = ((int64_t)blockIdx.x * (MB / 64) + wv) * 64;
+    const int64_t p = wbase + lane;
+    const bool live = p < n;
+
+    // A. lane = atom
+    int cnt[NGRP] = {0, 0, 0};
+    if (live) {
         if (knn_out) {
             // the Euclidean order (Sec. 3) whatever the ordering of the hulls
             const int32_t i = sid[p];
 #pragma unroll
             for (int m = 0; m < KMAX; m++) knn_out[(int64_t)i * KMAX + m] = knn_src[(int64_t)m * n + p];
         }
-        const bool over = pairs_overflow(off, p, cap);
-        double b1 = 0.0, lo2 = INFINITY;
-        if (!over)
-            pair_minimum(off, p, pairs, rr, m1, m2, arg_grp, arg_c, arg_q,
-                         sizeof(RT) == 4 ? (const float *)qs + 5 : nullptr, b1, lo2);
-        bool full = over || (arg_c >= 0 && !(m2 > m1 + 1e-12));
-        if (sizeof(RT) == 4 && arg_c >= 0) {
-            // the FP32 decision stands only where the error bounds prove it:
-            // every other pair's true RMSD exceeds the winner's by more than
-            // the tie tolerance, and the winner lies clear of the cut-off
-            full = full || !(lo2 - (m1 + b1) > 1e-12) || fabs(m1 - cutoff) <= b1;
+        // barycentres of the centre and the first 6, 12 and 14 neighbours
+        double s[3] = {0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < KMAX; r++) {
+            for (int d = 0; d < 3; d++) s[d] += nbr_rel[((int64_t)r * 3 + d) * n + p];
+#pragma unroll
+            for (int g = 0; g < NGRP; g++)
+                if (r + 1 == group_k(g))
+                    for (int d = 0; d < 3; d++) W.cb[g][d][lane] = s[d] / (group_k(g) + 1);
         }
-        if (full) todo[atomicAdd(todo_count, 1)] = (int32_t)p;
-        else if (arg_c < 0) write_none(O, sid[p]);
-        else cls = arg_grp;
+        for (int g = 0; g < NGRP; g++) {
+            const int32_t cid = code[(int64_t)g * n + p];
+            int k0 = 0;
+            if (cid >= 0) {
+                k0 = T.cstart[g][cid];
+                const int k1 = T.cstart[g][cid + 1];
+                if ((mask & ALL_TEMPLATES) == ALL_TEMPLATES) cnt[g] = k1 - k0;
+                else
+                    for (int k = k0; k < k1; k++) cnt[g] += (mask >> T.cand[g][k].tmpl) & 1;
+            }
+            W.k0[g][lane] = k0;
+        }
+        W.cnt[lane] = cnt[0] | (cnt[1] << 8) | (cnt[2] << 16);
     }
+    // job offsets: exclusive scan over the wave
+    const int mine = cnt[0] + cnt[1] + cnt[2];
+    int my_off = mine;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(my_off, d);
+        if (lane >= d) my_off += y;
+    }
+    const int jobs = __shfl(my_off, 63);
+    my_off -= mine;
+    W.off[lane] = my_off;
+    if (lane == 0 && jobs > 0) atomicAdd(job_count, (unsigned long long)jobs);
+    for (int t = my_off; t < min(my_off + mine, 64); t++) W.owner[t] = lane;  // owners of the first chunk
+    wave_lds_sync();
+
+    // B. jobs, 64 at a time
+    double m1 = INFINITY, m2 = INFINITY, b1 = 0.0, lo2 = INFINITY;
+    int arg_g = -1, arg_c = -1;
+    RT wq[4] = {1, 0, 0, 0}, ws = 0;
+    for (int c0 = 0; c0 < jobs; c0 += 64) {
+        if (c0 + lane < jobs) {
+            const int a = W.owner[lane];
+            int j = c0 + lane - W.off[a];
+            const int32_t cn = W.cnt[a];
+            int g = 0;
+            if (j >= (cn & 0xFF)) {
+                j -= cn & 0xFF;
+                g = 1;
+                if (j >= ((cn >> 8) & 0xFF)) {
+                    j -= (cn >> 8) & 0xFF;
+                    g = 2;
+                }
+            }
+            const int64_t pa = wbase + a;
+            int k = W.k0[g][a];
+            if ((mask & ALL_TEMPLATES) == ALL_TEMPLATES) {
+                k += j;
+            } else {
+                // the j-th enabled candidate of the code
+                for (;; k++)
+                    if ((mask >> T.cand[g][k].tmpl) & 1) {
+                        if (j == 0) break;
+                        j--;
+                    }
+            }
+            const Candidate cd = T.cand[g][k];
+            const uint64_t ord = ords[(int64_t)g * n + pa];
+            const double cb[3] = {W.cb[g][0][a], W.cb[g][1][a], W.cb[g][2][a]};
+            const int K = group_k(g);
+            CandEval<RT> ev;
+            eval_job<RT>(K, nbr_rel, n, pa, cb, L.M.geo[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
+            W.r[lane] = (double)ev.r;
+            for (int e = 0; e < 4; e++) W.qs[e][lane] = ev.q[e];
+            W.qs[4][lane] = ev.s;
+            if constexpr (sizeof(RT) == 4) W.d2[lane] = ev.c;
+            W.cand[lane] = k;
+        }
+        wave_lds_sync();
+        if (mine > 0) {
+            // this atom's jobs of the chunk, in order (group, then
+            // candidate); strict comparisons: ties go to the earlier job
+            const int lo = max(my_off, c0), hi = min(my_off + mine, c0 + 64);
+            for (int t = lo; t < hi; t++) {
+                const int jj = t - my_off;
+                const int g = jj < cnt[0] ? 0 : (jj < cnt[0] + cnt[1] ? 1 : 2);
+                const int u = t - c0;
+                const double r = W.r[u];
+                double b = 0.0;
+                if constexpr (sizeof(RT) == 4) b = rmsd_f32_bound(r, (double)W.d2[u]);
+                if (r < m1) {
+                    if constexpr (sizeof(RT) == 4) lo2 = fmin(lo2, m1 - b1);  // the previous winner joins the others
+                    b1 = b;
+                    m2 = m1;
+                    m1 = r;
+                    arg_g = g;
+                    arg_c = W.cand[u];
+                    for (int e = 0; e < 4; e++) wq[e] = W.qs[e][u];
+                    ws = W.qs[4][u];
+                } else {
+                    if (r < m2) m2 = r;
+                    if constexpr (sizeof(RT) == 4) lo2 = fmin(lo2, r - b);
+                }
+            }
+            // owners of the next chunk (its jobs have read this one's)
+            for (int t = max(my_off, c0 + 64); t < min(my_off + mine, c0 + 128); t++) W.owner[t - c0 - 64] = lane;
+        }
+        wave_lds_sync();
+    }
+
+    // C. decision.  The common case -- a unique winner by more than the tie
+    // tolerance (FP32 form: by more than the two candidates' error bounds,
+    // and clear of the cut-off by the winner's) -- is finished below in the
+    // working precision; the others take the full rule.
+    bool full = false;
+    int cls = -1;  // hull group of the winner to finish below, -1 for none
+    double cbw[3] = {0, 0, 0};
+    if (live) {
+        full = arg_c >= 0 && (force_full || !(m2 > m1 + 1e-12));
+        if constexpr (sizeof(RT) == 4)
+            if (arg_c >= 0) full = full || !(lo2 - (m1 + b1) > 1e-12) || fabs(m1 - cutoff) <= b1;
+        if (!full) {
+            if (arg_c < 0) {
+                write_none(O, sid[p]);
+            } else {
+                cls = arg_g;
+                for (int d = 0; d < 3; d++) cbw[d] = W.cb[arg_g][d][lane];
+            }
+        }
+    }
+    uint64_t fb = __ballot(full);
+    if (lane == 0 && fb) atomicAdd(full_count, (int32_t)__popcll(fb));
+    while (fb) {
+        const int a = __builtin_ctzll(fb);
+        fb &= fb - 1;
+        full_rule(L.M, L.T, n, wbase + a, a, W.cb, nbr_rel, nbr_id, sid, species, code, ords, mask, cutoff, L.O);
+    }
+
     // Consecutive atoms in cell order span many grains, so a wave's winners
     // mix the three hull sizes and each size's finishing code would run in
     // turn.  The block's winners are regrouped by size (12, 14, then 6
     // points; ballots give each lane its slot) and every lane finishes the
     // winner in its slot: waves then mostly run one size's code.
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint64_t bal[NGRP];
 #pragma unroll
     for (int k = 0; k < NGRP; k++) bal[k] = __ballot(cls == k);
     if (lane == 0)
-        for (int k = 0; k < NGRP; k++) s_cnt[wv][k] = __popcll(bal[k]);
-    __syncthreads();
+        for (int k = 0; k < NGRP; k++) L.cnt[wv][k] = __popcll(bal[k]);
+    __syncthreads();  // every wave is done with its LDS of A and B
     constexpr int order[NGRP] = {1, 2, 0};
     int total = 0, base = 0;
 #pragma unroll
@@ -2276,145 +2342,37 @@ __global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 3 : 2) k_decide(int64_t 
         const int k = order[j];
         int tk = 0, before = 0;
         for (int w2 = 0; w2 < MB / 64; w2++) {
-            tk += s_cnt[w2][k];
-            if (w2 < wv) before += s_cnt[w2][k];
+            tk += L.cnt[w2][k];
+            if (w2 < wv) before += L.cnt[w2][k];
         }
         if (k == cls) base = total + before + __popcll(bal[k] & ((1ull << lane) - 1));
         total += tk;
     }
+    MatchRegroupLds<RT> &R = L.u.g;
     if (cls >= 0) {
-        s_p[base] = (int32_t)p;
-        s_c[base] = arg_c;
-        s_q[base] = arg_q;
-        s_r[base] = m1;
-        s_g[base] = (int8_t)cls;
+        R.p[base] = (int32_t)p;
+        R.c[base] = arg_c;
+        R.g[base] = (int8_t)cls;
+        R.r[base] = m1;
+        for (int e = 0; e < 4; e++) R.qs[e][base] = wq[e];
+        R.qs[4][base] = ws;
+        for (int d = 0; d < 3; d++) R.cb[d][base] = cbw[d];
     }
     __syncthreads();
     if ((int)threadIdx.x >= total) return;
-    const int64_t pw = s_p[threadIdx.x];
-    const int gw = s_g[threadIdx.x], cw = s_c[threadIdx.x];
+    const int u = threadIdx.x;
+    const int64_t pw = R.p[u];
+    const int gw = R.g[u], cw = R.c[u];
     const int32_t iw = sid[pw];
     const uint64_t ord = ords[(int64_t)gw * n + pw];
-    const RT *w = qs + QS_STRIDE<RT> * s_q[threadIdx.x];
-    const double rw = s_r[threadIdx.x];
-    if (gw == 0) finish_stored<6, RT>(M, T, 0, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
-    else if (gw == 1)
-        finish_stored<12, RT>(M, T, 1, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
-    else finish_stored<14, RT>(M, T, 2, cw, ord, nbr_rel, rw, w, cutoff, pw, n, iw, nbr_id, species, O);
-}
-
-// The atoms k_decide left (near ties, FP32 margins too small to trust, pairs
-// that did not fit the buffer), decided by the full rule in FP64 with one
-// wavefront per atom: each lane superposes one candidate of the atom's code
-// lists (at most 26 + 26 + 7), the minimum r* is reduced over the wave, every
-// candidate within the tie tolerance computes its representative vector, the
-// (template, representative) minimum is reduced, and one lane finishes the
-// winner in FP64.  Grid-stride over todo.
-template <typename RT>
-__global__ void __launch_bounds__(MB) k_decide_full(int64_t n, const double *__restrict__ nbr_rel,
-                                                    const int32_t *__restrict__ nbr_id,
-                                                    const int32_t *__restrict__ sid,
-                                                    const int8_t *__restrict__ species, TablesView T,
-                                                    const int32_t *__restrict__ code,
-                                                    const uint64_t *__restrict__ ords, uint32_t mask, double cutoff,
-                                                    MatchOut O, const int32_t *__restrict__ todo,
-                                                    const int32_t *__restrict__ todo_count,
-                                                    const int32_t *__restrict__ box_fail) {
-    __shared__ MatchShared M;
-    if (*box_fail) return;  // uniform over the grid
-    load_templates(M, T);
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * (MB / 64);
-    const int64_t cnt = *todo_count;
-    for (int64_t w = blockIdx.x * (int64_t)(MB / 64) + (threadIdx.x >> 6); w < cnt; w += nwaves) {
-        const int64_t p = todo[w];
-        const int32_t i = sid[p];
-        int32_t c0[NGRP], nc[NGRP];
-        uint64_t ord[NGRP];
-        for (int g = 0; g < NGRP; g++) {
-            const int32_t cid = code[(int64_t)g * n + p];
-            ord[g] = ords[(int64_t)g * n + p];
-            c0[g] = cid >= 0 ? T.cstart[g][cid] : 0;
-            nc[g] = cid >= 0 ? T.cstart[g][cid + 1] - c0[g] : 0;
-        }
-        // this lane's candidate
-        int g = -1, c = -1, tmpl = 99;
-        double r = INFINITY;
-        {
-            int j = lane;
-            for (int gg = 0; gg < NGRP && g < 0; gg++) {
-                if (j < nc[gg]) {
-                    g = gg;
-                    c = c0[gg] + j;
-                } else {
-                    j -= nc[gg];
-                }
-            }
-        }
-        Candidate cd = {0, 0, 0};
-        CandEval<double> ev = {0, 0, {0, 0, 0, 0}};
-        if (g >= 0) {
-            cd = T.cand[g][c];
-            if ((mask >> cd.tmpl) & 1) {
-                tmpl = cd.tmpl;
-                const TemplateDev &D = M.tpl[cd.tmpl];
-                // every point loaded at once: a wave per atom, few atoms, so
-                // nothing else hides the round trips (the winner's evaluation
-                // is handed to finish)
-                double a[NMAX][3], Ga;
-                if (g == 0) {
-                    load_centred<6, double, true>(nbr_rel, n, p, a, Ga);
-                    eval_candidate<6, double>(a, Ga, D, tv_of_rank(cd.perm, ord[0], 6), ev);
-                } else if (g == 1) {
-                    load_centred<12, double, true>(nbr_rel, n, p, a, Ga);
-                    eval_candidate<12, double>(a, Ga, D, tv_of_rank(cd.perm, ord[1], 12), ev);
-                } else {
-                    load_centred<14, double, true>(nbr_rel, n, p, a, Ga);
-                    eval_candidate<14, double>(a, Ga, D, tv_of_rank(cd.perm, ord[2], 14), ev);
-                }
-                r = ev.r;
-            }
-        }
-        double m1 = r;
-        for (int off = 32; off > 0; off >>= 1) m1 = fmin(m1, __shfl_xor(m1, off));
-        if (m1 == INFINITY) {  // no candidate of an enabled template
-            if (lane == 0) write_none(O, i);
-            continue;
-        }
-        // tie rule: earliest template, then the smallest representative vector
-        int kt = 99;
-        uint64_t krep = ~0ull;
-        if (r <= m1 + 1e-12) {
-            int gsel;
-            const int K = group_k(g);
-            kt = tmpl;
-            krep = rep_vector(M.tpl[tmpl], rank_of_tv(cd.perm, ord[g], K), gsel);
-        }
-        int bt = kt, bl = lane;
-        uint64_t brep = krep;
-        for (int off = 32; off > 0; off >>= 1) {
-            int ot = __shfl_xor(bt, off), ol = __shfl_xor(bl, off);
-            uint64_t orep = __shfl_xor(brep, off);
-            bool take = ot < bt || (ot == bt && (orep < brep || (orep == brep && ol < bl)));
-            if (take) {
-                bt = ot;
-                brep = orep;
-                bl = ol;
-            }
-        }
-        const int wg = __shfl(g, bl), wc = __shfl(c, bl);
-        // the winning lane's superposition, handed to the finishing lane
-        CandEval<double> we;
-        we.r = __shfl(ev.r, bl);
-        we.s = __shfl(ev.s, bl);
-        for (int k = 0; k < 4; k++) we.q[k] = __shfl(ev.q[k], bl);
-        if (lane == 0) {
-            if (wg == 0) finish<6, double>(M, T, 0, wc, ord[0], we, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else if (wg == 1)
-                finish<12, double>(M, T, 1, wc, ord[1], we, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-            else finish<14, double>(M, T, 2, wc, ord[2], we, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        }
-    }
+    CandEval<RT> ev;
+    ev.r = (RT)R.r[u];
+    for (int e = 0; e < 4; e++) ev.q[e] = R.qs[e][u];
+    ev.s = R.qs[4][u];
+    const double cb[3] = {R.cb[0][u], R.cb[1][u], R.cb[2][u]};
+    if (gw == 0) finish<6, RT>(L.M, T, 0, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+    else if (gw == 1) finish<12, RT>(L.M, T, 1, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+    else finish<14, RT>(L.M, T, 2, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
 }
 
 // ------------------------------------------------- post-hoc cut-off (Sec. 5.1)
@@ -2634,19 +2592,14 @@ __global__ void k_selftest_strain(const TemplateDev *__restrict__ tpl, int t, co
                                   double *__restrict__ P) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const TemplateDev &D = tpl[t];
-    RT v[K][3];
-    double cb[3] = {0, 0, 0};
+    double v[K][3];
     uint64_t tv = 0;
     for (int r = 0; r < K; r++) {
-        for (int d = 0; d < 3; d++) {
-            v[r][d] = (RT)rel[3 * r + d];
-            cb[d] += rel[3 * r + d];
-        }
+        for (int d = 0; d < 3; d++) v[r][d] = rel[3 * r + d];
         tv |= (uint64_t)r << (4 * r);
     }
-    for (int d = 0; d < 3; d++) cb[d] /= (K + 1);
     RT a0[3], At[3][3], l, Pm[3][3];
-    strain_inputs<K, RT>(D, tv, v, cb, a0, At, l);
+    strain_inputs<K, RT>(D, tv, v, a0, At, l);
     polar_p<RT>(At, l, Pm);
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) P[3 * x + y] = (double)Pm[x][y];
@@ -2737,47 +2690,19 @@ void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const 
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
     hipLaunchKernelGGL(k_topo, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord, box_fail);
 }
-void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
-                 const int32_t *box_fail, hipStream_t st) {
-    unsigned nb = (unsigned)((pair_slots(n) / NGRP + 1 + 255) / 256);
-    hipLaunchKernelGGL(k_cand_count, dim3(nb), dim3(256), 0, st, n, T, code, mask, W.cnt, box_fail);
-    size_t tmp = W.scan_tmp_bytes;
-    (void)hipcub::DeviceScan::ExclusiveSum(W.scan_tmp, tmp, W.cnt, W.off, pair_slots(n) + 1, st);
-    hipLaunchKernelGGL(k_cand_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T, code, mask, W.off,
-                       W.cap, W.pairs, box_fail);
-}
-void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
-                 bool f32, const int32_t *box_fail, hipStream_t st) {
+void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
+                  const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
+                  uint32_t mask, double cutoff, bool force_full, const MatchOut &O, int32_t *full_count,
+                  unsigned long long *job_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail,
+                  bool f32, hipStream_t st) {
+    if (n <= 0) return;
+    dim3 grid((unsigned)((n + MB - 1) / MB)), block(MB);
     if (f32)
-        hipLaunchKernelGGL(k_cand_eval<float>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap, W.pairs,
-                           W.r, (float *)W.qs, box_fail);
+        hipLaunchKernelGGL(k_match<float>, grid, block, 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, mask,
+                           cutoff, (int)force_full, O, full_count, job_count, knn_src, knn_out, box_fail);
     else
-        hipLaunchKernelGGL(k_cand_eval<double>, dim3(4096), dim3(MB), 0, st, n, nbr_rel, T, ord, W.off, W.cap,
-                           W.pairs, W.r, (double *)W.qs, box_fail);
-}
-void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
-                   const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
-                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
-                   int32_t *todo_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail, bool f32,
-                   hipStream_t st) {
-    dim3 gd((unsigned)((n + MB - 1) / MB));
-    // the full rule holds one wave per SIMD (its registers): 256 blocks of
-    // four waves fill the chip, and a few left-over atoms do not pay for a
-    // larger launch
-    dim3 gf((unsigned)std::min<int64_t>((n + MB / 64 - 1) / (MB / 64), 256));
-    if (f32) {
-        hipLaunchKernelGGL(k_decide<float>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord, W.off,
-                           W.cap, W.pairs, W.r, (const float *)W.qs, cutoff, O, todo, todo_count, knn_src, knn_out,
-                           box_fail);
-        hipLaunchKernelGGL(k_decide_full<float>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
-                           mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count, box_fail);
-    } else {
-        hipLaunchKernelGGL(k_decide<double>, gd, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
-                           W.off, W.cap, W.pairs, W.r, (const double *)W.qs, cutoff, O, todo, todo_count, knn_src,
-                           knn_out, box_fail);
-        hipLaunchKernelGGL(k_decide_full<double>, gf, dim3(MB), 0, st, n, nbr_rel, nbr_id, sid, species, T, code,
-                           ord, mask, cutoff, O, (const int32_t *)todo, (const int32_t *)todo_count, box_fail);
-    }
+        hipLaunchKernelGGL(k_match<double>, grid, block, 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
+                           mask, cutoff, (int)force_full, O, full_count, job_count, knn_src, knn_out, box_fail);
 }
 
 }  // namespace ptm

@@ -37,28 +37,6 @@ struct MatchOut {
     int8_t *best_type;
 };
 
-// Flat (atom, candidate) pair list of the match stage, ordered by tiles of
-// PAIR_TILE atoms, then hull group, then atom: slot pidx(p, g) counts atom
-// p's pairs of group g; pair_slots(n) slots cover n atoms (the last tile
-// padded with empty atoms).
-constexpr int64_t PAIR_TILE = 1024;
-__host__ __device__ inline int64_t pidx(int64_t p, int g) {
-    return (p / PAIR_TILE) * (NGRP * PAIR_TILE) + g * PAIR_TILE + (p % PAIR_TILE);
-}
-__host__ __device__ inline int64_t pair_slots(int64_t n) {
-    return (n + PAIR_TILE - 1) / PAIR_TILE * (NGRP * PAIR_TILE);
-}
-struct MatchScratch {
-    int64_t *cnt;        // [pair_slots(n)+1] candidates per (atom, group) slot
-    int64_t *off;        // [pair_slots(n)+1] exclusive prefix sum (last = total)
-    uint2 *pairs;        // [cap] (atom, group << 28 | candidate), in slot order
-    double *r;           // [cap] RMSD of each pair
-    void *qs;            // [cap][5] quaternion and scale of each pair, working precision
-    int64_t cap;         // pair capacity
-    void *scan_tmp;
-    size_t scan_tmp_bytes;
-};
-
 void launch_zero(int32_t *p, int64_t n, hipStream_t st);
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st);
 void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
@@ -85,19 +63,17 @@ void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_
 // code ids and labellings into code / ord [group][n]
 void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const TablesView &T, uint32_t need,
                  int32_t *code, uint64_t *ord, const int32_t *box_fail, hipStream_t st);
-// match stage: candidate pair list, superposition of every pair, decision
-void launch_cand(int64_t n, const TablesView &T, const int32_t *code, uint32_t mask, const MatchScratch &W,
-                 const int32_t *box_fail, hipStream_t st);
-void launch_eval(int64_t n, const double *nbr_rel, const TablesView &T, const uint64_t *ord, const MatchScratch &W,
-                 bool f32, const int32_t *box_fail, hipStream_t st);
-// decision: common atoms, then those left in todo / *todo_count (zeroed by
-// the caller) by the full rule; knn_out (nullable, [n][14] in input order)
-// receives the first 14 rows of knn_src (the Euclidean ids, rank-major)
-void launch_decide(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
-                   const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
-                   uint32_t mask, double cutoff, const MatchOut &O, const MatchScratch &W, int32_t *todo,
-                   int32_t *todo_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail, bool f32,
-                   hipStream_t st);
+// match stage: superposition of every candidate of the codes, decision
+// (the full rule where the common one cannot decide, or for every atom with
+// force_full), outputs in input order.  *full_count (int32) and *job_count
+// (zeroed by the caller) count the atoms the full rule decided and the
+// candidates superposed; knn_out (nullable, [n][14] in input order) receives
+// the first 14 rows of knn_src (the Euclidean ids, rank-major).
+void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
+                  const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
+                  uint32_t mask, double cutoff, bool force_full, const MatchOut &O, int32_t *full_count,
+                  unsigned long long *job_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail,
+                  bool f32, hipStream_t st);
 
 // post-hoc cut-off and RMSD histograms (counts: device, 6 * nbins, zeroed by the caller)
 void launch_apply_cutoff(int64_t n, const int8_t *best_type, const double *rmsd, double cutoff, int8_t *type,

@@ -189,15 +189,13 @@ static ptm_status serve_init(ptm_ctx *ctx) {
 
 // Size class of a frame's scratch: the next power of two (at least 1 MiB)
 // of an upper bound of its bytes that holds for any cell grid make_grid
-// may choose (at most 4n + 4096 cells), with the scan space of both scans
-// FrameScratch::reserve sizes (cell counts, candidate counts).
-static size_t scratch_class(int64_t n, bool topo, int64_t cap) {
+// may choose (at most 4n + 4096 cells), with the scan space
+// FrameScratch::reserve sizes.
+static size_t scratch_class(int64_t n, bool topo) {
     int64_t cells = 4 * n + 4096;
-    size_t tmp = 0, tmp2 = 0;
+    size_t tmp = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int32_t *)nullptr, (int32_t *)nullptr, (int)(cells + 1));
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp2, (int64_t *)nullptr, (int64_t *)nullptr,
-                                           pair_slots(n) + 1);
-    size_t need = frame_bytes(n, cells, bounds_blocks(n), std::max(tmp, tmp2), topo, cap);
+    size_t need = frame_bytes(n, cells, bounds_blocks(n), tmp, topo);
     size_t c = (size_t)1 << 20;
     while (c < need) c <<= 1;
     return c;
@@ -318,10 +316,9 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
         if (st == PTM_OK) {
             T->job.grid = make_grid(box, mn, mx, n_atoms, T->job.topo ? VK : KMAX);
             cells = (int64_t)T->job.grid.nc[0] * T->job.grid.nc[1] * T->job.grid.nc[2];
-            const int64_t cap = pair_capacity(n_atoms, ctx->pair_cap);
-            T->footprint = scratch_class(n_atoms, T->job.topo, cap);
+            T->footprint = scratch_class(n_atoms, T->job.topo);
             st = take_scratch(ctx, T->footprint, T->scratch);
-            if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, T->job.topo, cap, ctx->err)) st = PTM_E_DEVICE;
+            if (st == PTM_OK && !T->scratch.reserve(n_atoms, cells, T->job.topo, ctx->err)) st = PTM_E_DEVICE;
         }
         if (st != PTM_OK) {
             if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);

@@ -20,14 +20,15 @@ PTM_ALL = 0x1F
 PTM_F_HOST_POINTERS = 1
 PTM_F_PROFILE = 2
 PTM_F_TOPOLOGICAL = 4
-STAGE_NAMES = ("bounds", "bin", "knn", "topo", "cand", "eval", "decide")
+PTM_F_FULL_RULE = 8
+STAGE_NAMES = ("bounds", "bin", "knn", "topo", "match")
 TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
 ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")
 
 
 class ptm_config(C.Structure):
     _fields_ = [("device", C.c_int), ("precision", C.c_int), ("hip_stream", C.c_void_p),
-                ("hbm_budget_bytes", C.c_uint64), ("flags", C.c_uint32), ("pair_capacity", C.c_int64)]
+                ("hbm_budget_bytes", C.c_uint64), ("flags", C.c_uint32)]
 
 
 OUTPUT_FIELDS = ("type", "alloy", "rmsd", "scale", "quat", "neighbours", "strain", "knn",
@@ -103,8 +104,8 @@ def ptm_last_error(ctx) -> str:
     return lib().ptm_last_error(ctx).decode()
 
 
-def ptm_create(device=0, precision=PTM_FP64, hip_stream=None, hbm_budget_bytes=0, flags=0, pair_capacity=0):
-    cfg = ptm_config(device, precision, hip_stream, hbm_budget_bytes, flags, pair_capacity)
+def ptm_create(device=0, precision=PTM_FP64, hip_stream=None, hbm_budget_bytes=0, flags=0):
+    cfg = ptm_config(device, precision, hip_stream, hbm_budget_bytes, flags)
     ctx = C.c_void_p()
     st = lib().ptm_create(C.byref(cfg), C.byref(ctx))
     if st != PTM_OK:
@@ -195,7 +196,7 @@ class Classifier:
     """Owns a context; classifies torch tensors resident on the GPU."""
 
     def __init__(self, device: int = 0, precision: int = PTM_FP64, hbm_budget_bytes: int = 0,
-                 topological: bool = False, pair_capacity: int = 0):
+                 topological: bool = False, flags: int = 0):
         import torch
         self.device = device
         self.precision = precision
@@ -206,7 +207,7 @@ class Classifier:
         # out on that stream)
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = ptm_create(device, precision, self.stream.cuda_stream, hbm_budget_bytes,
-                              PTM_F_TOPOLOGICAL if topological else 0, pair_capacity)
+                              flags | (PTM_F_TOPOLOGICAL if topological else 0))
 
     def close(self):
         if self.ctx is not None:

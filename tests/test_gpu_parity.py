@@ -256,28 +256,21 @@ def test_strain_right_handed_on_device(torch_cuda, oracle_lib, precision):
 
 
 @pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
-@pytest.mark.parametrize("share", [0.25, 0.7])
-def test_pair_capacity_overflow_path(torch_cuda, oracle_lib, precision, share):
-    """A candidate pair list capped below what the frame needs (a test-only
-    ptm_config field): the atoms past the capacity are decided by the full
-    rule, and every output still equals the oracle's."""
+@pytest.mark.parametrize("mask", [ptm.PTM_ALL, ptm.PTM_FCC | ptm.PTM_HCP | ptm.PTM_BCC], ids=["all", "fcc-hcp-bcc"])
+def test_full_rule_for_every_atom(torch_cuda, oracle_lib, precision, mask):
+    """Every atom with a candidate decided by the full rule (the test-only
+    context flag PTM_F_FULL_RULE): each wave runs it for all its atoms in
+    turn, every candidate superposed in FP64 with the tie rule of Alg. 1.
+    The outputs equal the oracle's to the FP64 tolerance in both forms (the
+    full rule is FP64 throughout)."""
     torch = torch_cuda
     f = S.polycrystal(L=34.0, n_grains=4, sigma=0.12, seed=71)
-    ref = oracle_lib.classify(f.positions, f.box)
-    probe = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE)
-    pos = torch.from_numpy(f.positions).to("cuda:0")
+    ref = oracle_lib.classify(f.positions, f.box, mask=mask)
+    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE | ptm.PTM_F_FULL_RULE)
     try:
+        pos = torch.from_numpy(f.positions).to("cuda:0")
         out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
-        assert ptm.ptm_classify(probe, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, math.inf,
-                                ptm.Classifier.outputs_struct(out)) == ptm.PTM_OK
-        pairs = ptm.ptm_frame_info(probe)["pairs"]
-    finally:
-        ptm.ptm_destroy(probe)
-    cap = int(pairs * share)
-    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PROFILE, cap)
-    try:
-        out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True)
-        st = ptm.ptm_classify(ctx, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, math.inf,
+        st = ptm.ptm_classify(ctx, pos.data_ptr(), None, f.box, f.n, mask, math.inf,
                               ptm.Classifier.outputs_struct(out))
         assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
         torch.cuda.synchronize()
@@ -285,9 +278,9 @@ def test_pair_capacity_overflow_path(torch_cuda, oracle_lib, precision, share):
         got = {k: v.cpu().numpy() for k, v in out.items()}
     finally:
         ptm.ptm_destroy(ctx)
-    print("capacity", cap, "of", pairs, info, flush=True)
-    assert info["pairs"] == cap and info["decide_full"] > 0.3 * (1 - share) * f.n
-    _compare(got, ref, tol=TOL64 if precision == ptm.PTM_FP64 else TOL32)
+    print("full rule", f.n, info, flush=True)
+    assert info["decide_full"] == int(np.sum(np.isfinite(ref["rmsd"]))) > 0.5 * f.n
+    _compare(got, ref, tol=TOL64)
 
 
 def test_inputs_written_by_torch_just_before(torch_cuda, oracle_lib):
