@@ -304,16 +304,14 @@ inline int64_t xcd_pad(int64_t nblocks) { return (nblocks + NXCD - 1) / NXCD * N
 
 // NK = 14 neighbours (Euclidean ordering), or 18 (the input of the
 // topological ordering); the list holds NK + 1 keys, the last one certifies
-// the boundary.
+// the boundary.  One atom (lane); false: not certified, nothing written
+// (the exact search must take it).
 template <int NK>
-__global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ sx,
-                                                  const double *__restrict__ sy, const double *__restrict__ sz,
-                                                  const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
-                                                  int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
-                                                  int32_t *__restrict__ todo, int32_t *__restrict__ todo_count,
-                                                  int32_t *__restrict__ box_fail) {
-    int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+__device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const double *__restrict__ sx,
+                                     const double *__restrict__ sy, const double *__restrict__ sz,
+                                     const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                                     int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                                     int32_t *__restrict__ box_fail) {
     constexpr int KN = NK + 1;
     const double xi = sx[p], yi = sy[p], zi = sz[p];
     const double xs[3] = {xi, yi, zi};
@@ -477,11 +475,22 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
         ok = certified(g, cc, u, lo, hi, NK, NK, kth, all);
         if (ok && shell_exceeds_box(g, NK, NK, kth)) atomicOr(box_fail, 1);
     }
-    if (!ok) {
-        todo[atomicAdd(todo_count, 1)] = (int32_t)p;
-        return;
-    }
+    if (!ok) return false;
     write_knn<NK>(n, p, NK, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel);
+    return true;
+}
+
+template <int NK>
+__global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ sx,
+                                                  const double *__restrict__ sy, const double *__restrict__ sz,
+                                                  const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                                                  int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                                                  int32_t *__restrict__ todo, int32_t *__restrict__ todo_count,
+                                                  int32_t *__restrict__ box_fail) {
+    int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (!knn_fast_atom<NK>(p, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail))
+        todo[atomicAdd(todo_count, 1)] = (int32_t)p;
 }
 
 // Exact search for the atoms the fast search left (or all atoms when todo
@@ -491,20 +500,16 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
 // heads gives the atom's ordered neighbours, and the shells grow until the
 // searched block certifies the 14th distance.  A wave per atom keeps the
 // latency of a few left-over atoms short: each lane scans one or two cells.
+// One atom p (wave-uniform) by the whole wave.
 template <int NK>
-__global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const double *__restrict__ sx,
-                                                   const double *__restrict__ sy, const double *__restrict__ sz,
-                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
-                                                   int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
-                                                   const int32_t *__restrict__ todo,
-                                                   const int32_t *__restrict__ todo_count,
-                                                   int32_t *__restrict__ box_fail) {
+__device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double *__restrict__ sx,
+                               const double *__restrict__ sy, const double *__restrict__ sz,
+                               const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                               int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                               int32_t *__restrict__ box_fail) {
     constexpr int KN = NK;
     const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int64_t cnt_todo = todo ? (int64_t)*todo_count : n;
-    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); w < cnt_todo; w += nwaves) {
-        const int64_t p = todo ? (int64_t)todo[w] : w;
+    {
         const double xi = sx[p], yi = sy[p], zi = sz[p];
         const int32_t i = sid[p];
         const double xs[3] = {xi, yi, zi};
@@ -606,6 +611,20 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
             nbr_rel[((int64_t)lane * 3 + 2) * n + p] = r2;
         }
     }
+}
+
+template <int NK>
+__global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const double *__restrict__ sx,
+                                                   const double *__restrict__ sy, const double *__restrict__ sz,
+                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
+                                                   int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
+                                                   const int32_t *__restrict__ todo,
+                                                   const int32_t *__restrict__ todo_count,
+                                                   int32_t *__restrict__ box_fail) {
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t cnt_todo = todo ? (int64_t)*todo_count : n;
+    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); w < cnt_todo; w += nwaves)
+        knn_exact_atom<NK>(todo ? (int64_t)todo[w] : w, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail);
 }
 
 // ------------------------------------------------- topological ordering
@@ -1461,14 +1480,10 @@ __device__ int32_t probe_rest(const TablesView &T, int grp, const uint64_t (&bes
 // enabled by need: bit g for hull group g), code ids and labellings into
 // code_out / ord_out [group][n] (-1 / 0 for a group without a valid hull or
 // not needed).
-__global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
-                                              const int32_t *__restrict__ nbr_id, TablesView T, uint32_t need,
-                                              int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out,
-                                              const int32_t *__restrict__ box_fail) {
-    __shared__ TopoShared S;
-    const int t = threadIdx.x;
-    const int64_t p = blockIdx.x * (int64_t)TB + t;
-    if (p >= n || *box_fail) return;
+// One atom p per lane t of a 64-lane wave, with the wave's LDS S.
+__device__ void topo_atom(TopoShared &S, int t, int64_t p, int64_t n, const double *__restrict__ nbr_rel,
+                          const int32_t *__restrict__ nbr_id, const TablesView &T, uint32_t need,
+                          int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
     // the neighbour ids that say which hulls are possible (the K-th neighbour
     // exists) and all KMAX relative vectors are loaded in one round trip;
     // rows past the last wanted one are stored but never read
@@ -1535,6 +1550,17 @@ __global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict
         code_out[(int64_t)g * n + p] = cid[g];
         ord_out[(int64_t)g * n + p] = cid[g] >= 0 ? ordw[g] : 0;
     }
+}
+
+__global__ void __launch_bounds__(TB) k_topo(int64_t n, const double *__restrict__ nbr_rel,
+                                              const int32_t *__restrict__ nbr_id, TablesView T, uint32_t need,
+                                              int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out,
+                                              const int32_t *__restrict__ box_fail) {
+    __shared__ TopoShared S;
+    const int t = threadIdx.x;
+    const int64_t p = blockIdx.x * (int64_t)TB + t;
+    if (p >= n || *box_fail) return;
+    topo_atom(S, t, p, n, nbr_rel, nbr_id, T, need, code_out, ord_out);
 }
 
 // ------------------------------------------------------------------ match
@@ -2000,16 +2026,25 @@ struct MatchWaveLds {
     float d2[64];            // FP32 form: excess bound (f32_excess_bound),
     int32_t cand[64];        // candidate index in the group's list
 };
-// LDS of the block's regrouped winners (C)
-template <typename RT>
+// LDS of the block's regrouped winners (C), NB slots
+template <typename RT, int NB>
 struct MatchRegroupLds {
-    double r[MB];
-    double cb[3][MB];
-    RT qs[5][MB];
-    int32_t p[MB], c[MB];
-    int8_t g[MB];
+    double r[NB];
+    double cb[3][NB];
+    RT qs[5][NB];
+    int32_t p[NB], c[NB];
+    int8_t g[NB];
 };
-template <typename RT>
+// working LDS of a block of NW waves
+template <typename RT, int NW>
+struct MatchWork {
+    int32_t cnt[NW][NGRP];
+    union {
+        MatchWaveLds<RT> w[NW];
+        MatchRegroupLds<RT, NW * 64> g;
+    } u;
+};
+template <typename RT, int NW>
 struct MatchLds {
     MatchShared M;
     // copies of the kernel's table view and output pointers for the full
@@ -2017,11 +2052,7 @@ struct MatchLds {
     // copied to per-lane scratch memory by every lane
     TablesView T;
     MatchOut O;
-    int32_t cnt[MB / 64][NGRP];
-    union {
-        MatchWaveLds<RT> w[MB / 64];
-        MatchRegroupLds<RT> g;
-    } u;
+    MatchWork<RT, NW> work;
 };
 
 // LDS written by some lanes of a wave and then read by others of the same
@@ -2148,30 +2179,24 @@ __device__ inline double rmsd_f32_bound(double r, double d2) {
 
 constexpr uint32_t ALL_TEMPLATES = (1u << NT) - 1;
 
-// The match kernel (see the section head).  force_full: every atom with a
-// candidate takes the full rule (a test of that path).  full_count counts
-// the atoms the full rule decides, job_count the superposed candidates.
-// Registers: three blocks per CU (168 VGPRs at most) with the LDS of three.
-template <typename RT>
-__global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__restrict__ nbr_rel,
-                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
-                                                const int8_t *__restrict__ species, TablesView T,
-                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
-                                                uint32_t mask, double cutoff, int force_full, MatchOut O,
-                                                int32_t *__restrict__ full_count,
-                                                unsigned long long *__restrict__ job_count,
-                                                const int32_t *__restrict__ knn_src, int32_t *__restrict__ knn_out,
-                                                const int32_t *__restrict__ box_fail) {
-    __shared__ MatchLds<RT> L;
-    if (*box_fail) return;  // uniform over the grid
-    if (threadIdx.x == 0) {
-        L.T = T;
-        L.O = O;
-    }
-    load_templates(L.M, T);
+// The match stage for the NW * 64 atoms from first (see the section head),
+// by a block of NW waves: templates in M, the LDS copies Tl / Ol of the
+// table view and outputs (for the full rule), working LDS Wk.  force_full:
+// every atom with a candidate takes the full rule (a test of that path).
+// full_count counts the atoms the full rule decides, job_count the
+// superposed candidates.
+template <typename RT, int NW>
+__device__ void match_block(const MatchShared &M, const TablesView &Tl, const MatchOut &Ol, MatchWork<RT, NW> &Wk,
+                            int64_t first, int64_t n, const double *__restrict__ nbr_rel,
+                            const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
+                            const int8_t *__restrict__ species, const TablesView &T,
+                            const int32_t *__restrict__ code, const uint64_t *__restrict__ ords, uint32_t mask,
+                            double cutoff, int force_full, const MatchOut &O, int32_t *__restrict__ full_count,
+                            unsigned long long *__restrict__ job_count, const int32_t *__restrict__ knn_src,
+                            int32_t *__restrict__ knn_out) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    MatchWaveLds<RT> &W = L.u.w[wv];
-    const int64_t wbase = ((int64_t)blockIdx.x * (MB / 64) + wv) * 64;
+    MatchWaveLds<RT> &W = Wk.u.w[wv];
+    const int64_t wbase = first + (int64_t)wv * 64;
     const int64_t p = wbase + lane;
     const bool live = p < n;
 
@@ -2257,7 +2282,7 @@ __global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__rest
             const double cb[3] = {W.cb[g][0][a], W.cb[g][1][a], W.cb[g][2][a]};
             const int K = group_k(g);
             CandEval<RT> ev;
-            eval_job<RT>(K, nbr_rel, n, pa, cb, L.M.geo[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
+            eval_job<RT>(K, nbr_rel, n, pa, cb, M.geo[cd.tmpl], tv_of_rank(cd.perm, ord, K), ev);
             W.r[lane] = (double)ev.r;
             for (int e = 0; e < 4; e++) W.qs[e][lane] = ev.q[e];
             W.qs[4][lane] = ev.s;
@@ -2321,7 +2346,7 @@ __global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__rest
     while (fb) {
         const int a = __builtin_ctzll(fb);
         fb &= fb - 1;
-        full_rule(L.M, L.T, n, wbase + a, a, W.cb, nbr_rel, nbr_id, sid, species, code, ords, mask, cutoff, L.O);
+        full_rule(M, Tl, n, wbase + a, a, W.cb, nbr_rel, nbr_id, sid, species, code, ords, mask, cutoff, Ol);
     }
 
     // Consecutive atoms in cell order span many grains, so a wave's winners
@@ -2333,7 +2358,7 @@ __global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__rest
 #pragma unroll
     for (int k = 0; k < NGRP; k++) bal[k] = __ballot(cls == k);
     if (lane == 0)
-        for (int k = 0; k < NGRP; k++) L.cnt[wv][k] = __popcll(bal[k]);
+        for (int k = 0; k < NGRP; k++) Wk.cnt[wv][k] = __popcll(bal[k]);
     __syncthreads();  // every wave is done with its LDS of A and B
     constexpr int order[NGRP] = {1, 2, 0};
     int total = 0, base = 0;
@@ -2341,14 +2366,14 @@ __global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__rest
     for (int j = 0; j < NGRP; j++) {
         const int k = order[j];
         int tk = 0, before = 0;
-        for (int w2 = 0; w2 < MB / 64; w2++) {
-            tk += L.cnt[w2][k];
-            if (w2 < wv) before += L.cnt[w2][k];
+        for (int w2 = 0; w2 < NW; w2++) {
+            tk += Wk.cnt[w2][k];
+            if (w2 < wv) before += Wk.cnt[w2][k];
         }
         if (k == cls) base = total + before + __popcll(bal[k] & ((1ull << lane) - 1));
         total += tk;
     }
-    MatchRegroupLds<RT> &R = L.u.g;
+    MatchRegroupLds<RT, NW * 64> &R = Wk.u.g;
     if (cls >= 0) {
         R.p[base] = (int32_t)p;
         R.c[base] = arg_c;
@@ -2359,20 +2384,44 @@ __global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__rest
         for (int d = 0; d < 3; d++) R.cb[d][base] = cbw[d];
     }
     __syncthreads();
-    if ((int)threadIdx.x >= total) return;
     const int u = threadIdx.x;
-    const int64_t pw = R.p[u];
-    const int gw = R.g[u], cw = R.c[u];
-    const int32_t iw = sid[pw];
-    const uint64_t ord = ords[(int64_t)gw * n + pw];
-    CandEval<RT> ev;
-    ev.r = (RT)R.r[u];
-    for (int e = 0; e < 4; e++) ev.q[e] = R.qs[e][u];
-    ev.s = R.qs[4][u];
-    const double cb[3] = {R.cb[0][u], R.cb[1][u], R.cb[2][u]};
-    if (gw == 0) finish<6, RT>(L.M, T, 0, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
-    else if (gw == 1) finish<12, RT>(L.M, T, 1, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
-    else finish<14, RT>(L.M, T, 2, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+    if (u < total) {
+        const int64_t pw = R.p[u];
+        const int gw = R.g[u], cw = R.c[u];
+        const int32_t iw = sid[pw];
+        const uint64_t ord = ords[(int64_t)gw * n + pw];
+        CandEval<RT> ev;
+        ev.r = (RT)R.r[u];
+        for (int e = 0; e < 4; e++) ev.q[e] = R.qs[e][u];
+        ev.s = R.qs[4][u];
+        const double cb[3] = {R.cb[0][u], R.cb[1][u], R.cb[2][u]};
+        if (gw == 0) finish<6, RT>(M, T, 0, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+        else if (gw == 1) finish<12, RT>(M, T, 1, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+        else finish<14, RT>(M, T, 2, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+    }
+}
+
+// The match kernel: blocks of four waves, 256 atoms each.  Registers: three
+// blocks per CU (168 VGPRs at most) with the LDS of three.
+template <typename RT>
+__global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__restrict__ nbr_rel,
+                                                const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
+                                                const int8_t *__restrict__ species, TablesView T,
+                                                const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
+                                                uint32_t mask, double cutoff, int force_full, MatchOut O,
+                                                int32_t *__restrict__ full_count,
+                                                unsigned long long *__restrict__ job_count,
+                                                const int32_t *__restrict__ knn_src, int32_t *__restrict__ knn_out,
+                                                const int32_t *__restrict__ box_fail) {
+    __shared__ MatchLds<RT, MB / 64> L;
+    if (*box_fail) return;  // uniform over the grid
+    if (threadIdx.x == 0) {
+        L.T = T;
+        L.O = O;
+    }
+    load_templates(L.M, T);
+    match_block<RT, MB / 64>(L.M, L.T, L.O, L.work, (int64_t)blockIdx.x * MB, n, nbr_rel, nbr_id, sid, species, T,
+                             code, ords, mask, cutoff, force_full, O, full_count, job_count, knn_src, knn_out);
 }
 
 // ------------------------------------------------- post-hoc cut-off (Sec. 5.1)
