@@ -87,7 +87,18 @@ enum { PTM_F_HOST_POINTERS = 1u << 0, /* inputs/outputs are host pointers (stage
         * candidate superposed in FP64, ties by template and representative,
         * Alg. 1) instead of the working-precision common rule: results are
         * unchanged, only slower.  For tests of the full rule's path. */
-       PTM_F_FULL_RULE = 1u << 3 };
+       PTM_F_FULL_RULE = 1u << 3,
+       /* serving (ptm_submit / ptm_wait) through one persistent kernel: the
+        * frame is handed over in pinned host memory and every stage of it
+        * (bounds, grid, binning and its scan, k-NN, hulls, match) runs as
+        * work items of that kernel, frames overlapping stage by stage; no
+        * launch or host round trip per frame.  The kernel exits after
+        * 20 ms without work and is relaunched by the next ptm_submit or
+        * ptm_wait.  Euclidean ordering only (with PTM_F_TOPOLOGICAL:
+        * PTM_E_INVALID at ptm_create).  A non-finite coordinate is reported
+        * by ptm_wait (PTM_E_INVALID), not by ptm_submit.  ptm_submit waits
+        * on the host for the context stream's prior work. */
+       PTM_F_PERSISTENT = 1u << 4 };
 
 /* pipeline stages reported by ptm_stage_times */
 enum { PTM_STAGE_BOUNDS = 0, PTM_STAGE_BIN = 1, PTM_STAGE_KNN = 2,

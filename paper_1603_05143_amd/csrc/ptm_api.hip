@@ -39,6 +39,8 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     b += align_up(4 * (size_t)n * NGRP);      // code ids
     b += align_up(8 * (size_t)n * NGRP);      // labellings
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
+    b += align_up(8 * 7 * (size_t)serve_bounds_items(n));  // persistent serving: per-item bounds
+    b += align_up(4 * (size_t)(serve_scan_items(n) + 1));  // and per-item scan totals
     b += align_up(scan_tmp);
     if (topo) {
         b += align_up(4 * (size_t)n * VK);      // the 18 Euclidean neighbours' ids
@@ -93,6 +95,8 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     code = (int32_t *)take(4 * (size_t)n * NGRP);
     ord = (uint64_t *)take(8 * (size_t)n * NGRP);
     part = (double *)take(8 * 7 * (size_t)nb);
+    sv_part = (double *)take(8 * 7 * (size_t)serve_bounds_items(n));
+    sv_bsum = (int32_t *)take(4 * (size_t)(serve_scan_items(n) + 1));
     scan_tmp_ptr = take(scan_tmp);
     scan_tmp_bytes = scan_tmp;
     id18 = topo ? (int32_t *)take(4 * (size_t)n * VK) : nullptr;
@@ -453,6 +457,10 @@ ptm_status ptm_create(const ptm_config *cfg, ptm_ctx **out) {
     ctx->precision = cfg->precision;
     ctx->budget = cfg->hbm_budget_bytes;
     ctx->flags = cfg->flags;
+    if ((ctx->flags & PTM_F_PERSISTENT) && (ctx->flags & PTM_F_TOPOLOGICAL)) {
+        delete ctx;
+        return PTM_E_INVALID;
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) {
         delete ctx;
         return PTM_E_DEVICE;

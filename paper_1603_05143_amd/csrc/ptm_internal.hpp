@@ -23,14 +23,6 @@
 
 namespace ptm {
 
-// int32 entries after the cell counts: the scan's end, the k-NN leftover
-// counter, the full-rule counter, the box flag, then (at the first 8-byte
-// aligned entry) the 64-bit count of superposed candidates
-constexpr int64_t FRAME_COUNTERS = 7;
-inline unsigned long long *job_counter(int32_t *count, int64_t cells) {
-    return (unsigned long long *)(count + ((cells + 5) & ~(int64_t)1));
-}
-
 // Device scratch of one frame (one allocation, carved into arrays).
 struct FrameScratch {
     void *base = nullptr;
@@ -47,6 +39,8 @@ struct FrameScratch {
     int32_t *code = nullptr;
     uint64_t *ord = nullptr;
     double *part = nullptr;
+    double *sv_part = nullptr;   // persistent serving: per-item bounds
+    int32_t *sv_bsum = nullptr;  // and per-item scan totals
     void *scan_tmp_ptr = nullptr;
     size_t scan_tmp_bytes = 0;
     bool reserve(int64_t n, int64_t cells, bool topo, std::string &err);
@@ -93,6 +87,9 @@ struct Ticket {
     double t_submit = 0, t_start = 0, t_complete = 0;
     bool complete = false;
     bool box_fail = false;  // the frame's periodic box was too short (PTM_E_BOX)
+    bool nonfinite = false; // (persistent serving) a coordinate was not finite
+    int slot = -1;          // persistent serving: the frame's slot and generation
+    uint64_t gen = 0;
 };
 
 size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo);
@@ -158,6 +155,18 @@ struct ptm_ctx {
     hipEvent_t order_event = nullptr;   // orders serving frames after the context stream's work
     hipEvent_t ref_event = nullptr;     // device-timeline reference ...
     double ref_time_us = 0;             // ... and its host-clock time
+    // persistent serving (PTM_F_PERSISTENT)
+    ptm::ServeDev *sv_dev = nullptr;    // device queue and slots
+    ptm::ServeHost *sv_host = nullptr;  // pinned block shared with the kernel
+    long long *sv_clock = nullptr;      // pinned word: device wall clock reference
+    hipStream_t sv_stream = nullptr;    // the persistent kernel's stream
+    hipEvent_t sv_exit = nullptr;       // recorded after the last launch of the kernel
+    bool sv_launched = false;
+    std::vector<int> sv_free;           // free slots
+    uint64_t sv_gen = 0;
+    double sv_clock_khz = 0;            // device wall clock rate
+    double sv_ref_host_us = 0;          // host time of ...
+    long long sv_ref_dev = 0;           // ... this device wall clock value
     // stage profiling (PTM_F_PROFILE)
     hipEvent_t prof_ev[PTM_NSTAGES + 1] = {};
     bool prof_valid = false;

@@ -46,7 +46,8 @@ __device__ inline int cell_coord(double x, const Grid &g, int d) {
         u = x - g.lo[d];
     }
     double f = floor(u * g.inv_h[d]);
-    int c = (f < 0.0) ? 0 : (f >= (double)(g.nc[d] - 1) ? g.nc[d] - 1 : (int)f);
+    // NaN (a non-finite coordinate, refused later) also lands in cell 0
+    int c = !(f >= 0.0) ? 0 : (f >= (double)(g.nc[d] - 1) ? g.nc[d] - 1 : (int)f);
     return c;
 }
 
@@ -2739,6 +2740,443 @@ void launch_topo(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const 
     dim3 grid((unsigned)((n + TB - 1) / TB)), block(TB);
     hipLaunchKernelGGL(k_topo, grid, block, 0, st, n, nbr_rel, nbr_id, T, need, code, ord, box_fail);
 }
+// ======================================== serving: one persistent kernel
+// Every frame runs as nine stages of work items; the last item of a stage
+// queues the next one (so stages of one frame follow each other, stages of
+// different frames overlap).  A workgroup is one wave: it claims the item at
+// the front of the device queue (an atomic range counter per (frame, stage)
+// entry), runs it and counts it done.  Idle waves pull new frames from the
+// pinned host block (one at a time, under a try-lock) and exit after a
+// stretch of the device wall clock without work, or when the host sets
+// stop: no wave waits on another, so every wave reaches an exit.
+enum {
+    PH_BOUNDS = 0,   // per-item bounds and non-finite flag
+    PH_GRID = 1,     // one item: the grid from the bounds (make_grid on the device)
+    PH_ZERO = 2,     // cell counters and frame counters to zero
+    PH_COUNT = 3,    // cell of every atom, slot in its cell (atomic counts)
+    PH_SCAN = 4,     // exclusive scan of the counts within each item, item totals
+    PH_SCANTOP = 5,  // one item: exclusive scan of the item totals
+    PH_SCATTER = 6,  // final cell starts (into the count array) and the sorted copy
+    PH_KNN = 7,      // neighbours (fast search, exact search for what it leaves)
+    PH_MATCH = 8     // hulls and codes, then the match stage, 64 atoms at a time
+};
+
+__device__ inline Grid make_grid_dev(const double (&box)[3], const double (&mn)[3], const double (&mx)[3], int64_t n,
+                                     int kn) {
+    // the host's make_grid (ptm_api.hip), same arithmetic
+    Grid g;
+    double ext[3], vol = 1.0;
+    int flat = 0;
+    for (int a = 0; a < 3; a++) {
+        g.periodic[a] = box[a] > 0;
+        ext[a] = g.periodic[a] ? box[a] : fmax(mx[a] - mn[a], 0.0);
+        if (ext[a] > 0) vol *= ext[a];
+        else flat++;
+    }
+    double h;
+    if (flat == 0 && vol > 0) {
+        const double rho = (double)n / vol;
+        h = 0.6 * cbrt((double)kn / (4.1887902047863905 * rho));
+    } else {
+        h = 1.0;
+        for (int a = 0; a < 3; a++) h = fmax(h, ext[a] / 16.0);
+    }
+    for (int iter = 0; iter < 200; iter++) {
+        double cells = 1;
+        for (int a = 0; a < 3; a++) {
+            int nc;
+            if (g.periodic[a]) nc = (int)fmin(floor(ext[a] / h), (double)(1 << 20));
+            else nc = ext[a] > 0 ? (int)fmin(floor(ext[a] / h), (double)(1 << 20)) : 1;
+            if (g.periodic[a] && nc < 3) nc = 3;
+            if (nc < 1) nc = 1;
+            g.nc[a] = nc;
+            cells *= nc;
+        }
+        if (cells <= (double)(1 << 30) && cells <= 4.0 * (double)n + 4096.0) break;
+        h *= 1.25;
+    }
+    double hmax = 0;
+    for (int a = 0; a < 3; a++) {
+        if (g.periodic[a]) {
+            g.L[a] = box[a];
+            g.invL[a] = 1.0 / box[a];
+            g.lo[a] = 0.0;
+            g.h[a] = box[a] / g.nc[a];
+            g.inv_h[a] = g.nc[a] / box[a];
+        } else {
+            g.L[a] = 0.0;
+            g.invL[a] = 0.0;
+            g.lo[a] = mn[a];
+            g.h[a] = ext[a] > 0 ? ext[a] / g.nc[a] : 1.0;
+            g.inv_h[a] = ext[a] > 0 ? g.nc[a] / ext[a] : 1.0;
+        }
+        hmax = fmax(hmax, g.h[a]);
+    }
+    g.margin = 1e-9 * hmax;
+    g.canonical = 1;
+    for (int a = 0; a < 3; a++)
+        if (g.periodic[a] && !(mn[a] >= 0.0 && mx[a] < box[a])) g.canonical = 0;
+    return g;
+}
+
+__device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// queue entry: slot (16 bits), stage (8), generation (40)
+__device__ inline unsigned long long serve_entry(int slot, int ph, unsigned long long gen) {
+    return (unsigned long long)slot | ((unsigned long long)ph << 16) | (gen << 24);
+}
+
+// a stage's claim counter: the frame's generation over a 24-bit item index
+__device__ inline unsigned long long serve_counter(unsigned long long gen) { return gen << 24; }
+
+// append (slot, stage); the stage's item count and counter are set before
+// (one lane)
+__device__ inline void serve_push(ServeDev *dev, int slot, int ph, unsigned long long gen) {
+    const unsigned long long pos = atomicAdd(&dev->tail, 1ull);
+    dev->entry[pos % SERVE_FIFO] = serve_entry(slot, ph, gen);
+    __threadfence();
+    __hip_atomic_store(&dev->seq[pos % SERVE_FIFO], pos + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the frame is finished: status, completion time, generation (one lane)
+__device__ inline void serve_complete(ServeHost *host, int slot, unsigned long long gen, int status) {
+    __threadfence_system();
+    __hip_atomic_store(&host->status[slot], status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&host->t_done[slot], (long long)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&host->done[slot], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// exclusive scan over the wave
+__device__ inline long long wave_excl_scan(long long v, long long &total) {
+    const int lane = threadIdx.x & 63;
+    long long x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const long long y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+template <typename RT>
+union ServeWork {
+    TopoShared topo;
+    MatchWork<RT, 1> mw;
+};
+
+// Stage ph, item r of the frame in slot S (the whole wave).  Returns the
+// stage's status for its last item (see serve_advance).
+template <typename RT>
+__device__ void serve_item(const MatchShared &M, const TablesView &Tl, MatchOut &Ol, ServeWork<RT> &U,
+                           const TablesView &T, ServeSlot &S, int ph, int64_t r) {
+    const int lane = threadIdx.x & 63;
+    const ServeRequest &R = S.r;
+    const int64_t n = R.n;
+    if (ph == PH_BOUNDS) {
+        const int64_t b = r * SERVE_ATOMS_LIGHT, e = min(n, b + SERVE_ATOMS_LIGHT);
+        double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
+        int bad = 0;
+        for (int64_t i = b + lane; i < e; i += 64)
+            for (int d = 0; d < 3; d++) {
+                const double x = R.pos[3 * i + d];
+                if (!isfinite(x)) bad = 1;
+                mn[d] = fmin(mn[d], x);
+                mx[d] = fmax(mx[d], x);
+            }
+        for (int off = 32; off > 0; off >>= 1) {
+            for (int d = 0; d < 3; d++) {
+                mn[d] = fmin(mn[d], __shfl_xor(mn[d], off));
+                mx[d] = fmax(mx[d], __shfl_xor(mx[d], off));
+            }
+            bad |= __shfl_xor(bad, off);
+        }
+        if (lane == 0) {
+            double *o = R.part + 7 * r;
+            for (int d = 0; d < 3; d++) {
+                o[d] = mn[d];
+                o[3 + d] = mx[d];
+            }
+            o[6] = (double)bad;
+        }
+    } else if (ph == PH_GRID) {
+        const int64_t nb = S.nr[PH_BOUNDS];
+        double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
+        int bad = 0;
+        for (int64_t k = lane; k < nb; k += 64) {
+            const double *o = R.part + 7 * k;
+            for (int d = 0; d < 3; d++) {
+                mn[d] = fmin(mn[d], o[d]);
+                mx[d] = fmax(mx[d], o[3 + d]);
+            }
+            bad |= o[6] != 0.0;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            for (int d = 0; d < 3; d++) {
+                mn[d] = fmin(mn[d], __shfl_xor(mn[d], off));
+                mx[d] = fmax(mx[d], __shfl_xor(mx[d], off));
+            }
+            bad |= __shfl_xor(bad, off);
+        }
+        if (lane == 0) {
+            const double box[3] = {R.box[0], R.box[1], R.box[2]};
+            S.g = make_grid_dev(box, mn, mx, n, KMAX);
+            S.cells = (int64_t)S.g.nc[0] * S.g.nc[1] * S.g.nc[2];
+            bool fast = true;
+            for (int a = 0; a < 3; a++)
+                if (S.g.periodic[a] && S.g.nc[a] < 5) fast = false;
+            S.fast = fast;
+            S.bad = bad;  // non-finite coordinate: the frame stops here
+        }
+    } else if (ph == PH_ZERO) {
+        const int64_t m = S.cells + FRAME_COUNTERS;
+        const int64_t b = r * SERVE_ZERO_CELLS, e = min(m, b + SERVE_ZERO_CELLS);
+        for (int64_t c = b + lane; c < e; c += 64) R.count[c] = 0;
+    } else if (ph == PH_COUNT) {
+        const int64_t b = r * SERVE_ATOMS_LIGHT, e = min(n, b + SERVE_ATOMS_LIGHT);
+        const Grid &g = S.g;
+        for (int64_t i = b + lane; i < e; i += 64) {
+            const int cx = cell_coord(R.pos[3 * i + 0], g, 0);
+            const int cy = cell_coord(R.pos[3 * i + 1], g, 1);
+            const int cz = cell_coord(R.pos[3 * i + 2], g, 2);
+            const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+            R.cell_of[i] = c;
+            R.slot_of[i] = atomicAdd(&R.count[c], 1);
+        }
+    } else if (ph == PH_SCAN) {
+        // cells 0..cells (the last one counts zero: its start is the total)
+        const int64_t m = S.cells + 1;
+        const int64_t b = r * SERVE_SCAN_CELLS, e = min(m, b + SERVE_SCAN_CELLS);
+        constexpr int64_t PER = SERVE_SCAN_CELLS / 64;
+        const int64_t lb = b + lane * PER, le = min(e, lb + PER);
+        long long sum = 0;
+        for (int64_t c = lb; c < le; c++) sum += c < S.cells ? R.count[c] : 0;
+        long long total;
+        long long run = wave_excl_scan(sum, total);
+        for (int64_t c = lb; c < le; c++) {
+            R.start[c] = (int32_t)run;
+            run += c < S.cells ? R.count[c] : 0;
+        }
+        if (lane == 0) R.bsum[r] = (int32_t)total;
+    } else if (ph == PH_SCANTOP) {
+        const int64_t m = S.nr[PH_SCAN];
+        const int64_t per = ceil_div(m, 64);
+        const int64_t lb = lane * per, le = min(m, lb + per);
+        long long sum = 0;
+        for (int64_t k = lb; k < le; k++) sum += R.bsum[k];
+        long long total;
+        long long run = wave_excl_scan(sum, total);
+        for (int64_t k = lb; k < le; k++) {
+            const int32_t v = R.bsum[k];
+            R.bsum[k] = (int32_t)run;
+            run += v;
+        }
+    } else if (ph == PH_SCATTER) {
+        // final starts of this item's cells (the k-NN reads them from count)
+        const int64_t m = S.cells + 1;
+        const int64_t cb = r * SERVE_SCAN_CELLS, ce = min(m, cb + SERVE_SCAN_CELLS);
+        if (cb < m) {
+            const int32_t off = R.bsum[r];
+            for (int64_t c = cb + lane; c < ce; c += 64) R.count[c] = R.start[c] + off;
+        }
+        const int64_t b = r * SERVE_ATOMS_LIGHT, e = min(n, b + SERVE_ATOMS_LIGHT);
+        for (int64_t i = b + lane; i < e; i += 64) {
+            const int32_t c = R.cell_of[i];
+            const int64_t p = (int64_t)R.start[c] + R.bsum[c / SERVE_SCAN_CELLS] + R.slot_of[i];
+            R.sx[p] = R.pos[3 * i + 0];
+            R.sy[p] = R.pos[3 * i + 1];
+            R.sz[p] = R.pos[3 * i + 2];
+            R.sid[p] = (int32_t)i;
+        }
+    } else if (ph == PH_KNN) {
+        const int64_t b = r * SERVE_ATOMS, e = min(n, b + SERVE_ATOMS);
+        int32_t *box_fail = R.count + S.cells + 3;
+        for (int64_t sub = b; sub < e; sub += 64) {
+            const int64_t p = sub + lane;
+            bool ok = true;
+            if (p < e)
+                ok = S.fast && knn_fast_atom<KMAX>(p, n, S.g, R.sx, R.sy, R.sz, R.sid, R.count, R.nbr_id, R.nbr_rel,
+                                                   box_fail);
+            uint64_t left = __ballot(!ok);
+            while (left) {
+                const int l = __builtin_ctzll(left);
+                left &= left - 1;
+                knn_exact_atom<KMAX>(sub + l, n, S.g, R.sx, R.sy, R.sz, R.sid, R.count, R.nbr_id, R.nbr_rel,
+                                     box_fail);
+            }
+        }
+    } else {  // PH_MATCH
+        const int64_t b = r * SERVE_ATOMS, e = min(n, b + SERVE_ATOMS);
+        if (lane == 0) Ol = R.O;
+        int32_t *full_count = R.count + S.cells + 2;
+        unsigned long long *job_count = job_counter(R.count, S.cells);
+        for (int64_t sub = b; sub < e; sub += 64) {
+            const int64_t p = sub + lane;
+            __syncthreads();  // the previous sub-block's match LDS is free
+            if (p < e) topo_atom(U.topo, lane, p, n, R.nbr_rel, R.nbr_id, T, R.need, R.code, R.ord);
+            // the wave's code / ord writes before other lanes read them
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __syncthreads();
+            match_block<RT, 1>(M, Tl, Ol, U.mw, sub, n, R.nbr_rel, R.nbr_id, R.sid, R.species, T, R.code, R.ord,
+                               R.mask, R.cutoff, 0, R.O, full_count, job_count, R.nbr_id, R.knn_out);
+        }
+    }
+}
+
+// One item of (slot, ph) is done: the last one of a stage queues the next
+// stage (or completes the frame).  Whole wave; one lane acts.
+__device__ inline void serve_advance(ServeDev *dev, ServeHost *host, int slot, int ph, unsigned long long gen) {
+    const int lane = threadIdx.x & 63;
+    __threadfence();  // this item's writes before its count
+    if (lane != 0) return;
+    ServeSlot &S = dev->slot[slot];
+    const long long d = __hip_atomic_fetch_add(&S.done[ph], 1ll, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (d != S.nr[ph]) return;
+    __threadfence();  // every item's writes of the stage
+    int next = ph + 1;
+    if (ph == PH_GRID && S.bad) {
+        serve_complete(host, slot, gen, SERVE_NONFINITE);
+        return;
+    }
+    if (ph == PH_KNN && __hip_atomic_load(S.r.count + S.cells + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        serve_complete(host, slot, gen, SERVE_BOX);
+        return;
+    }
+    if (ph == PH_MATCH) {
+        serve_complete(host, slot, gen, SERVE_OK);
+        return;
+    }
+    const int64_t n = S.r.n;
+    long long nr = 1;
+    switch (next) {
+        case PH_ZERO: nr = ceil_div(S.cells + FRAME_COUNTERS, SERVE_ZERO_CELLS); break;
+        case PH_COUNT: nr = ceil_div(n, SERVE_ATOMS_LIGHT); break;
+        case PH_SCAN: nr = ceil_div(S.cells + 1, SERVE_SCAN_CELLS); break;
+        case PH_SCANTOP: nr = 1; break;
+        case PH_SCATTER: nr = max(ceil_div(S.cells + 1, SERVE_SCAN_CELLS), ceil_div(n, SERVE_ATOMS_LIGHT)); break;
+        case PH_KNN: nr = ceil_div(n, SERVE_ATOMS); break;
+        case PH_MATCH: nr = ceil_div(n, SERVE_ATOMS); break;
+        default: nr = 1;
+    }
+    S.nr[next] = nr;
+    S.done[next] = 0;
+    __threadfence();
+    __hip_atomic_store(&S.next[next], serve_counter(gen), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    serve_push(dev, slot, next, gen);
+}
+
+// An idle wave pulls the next frame the host published, if any, and queues
+// its first stage.  Returns true if it did.
+__device__ inline bool serve_pull(ServeDev *dev, ServeHost *host) {
+    const int lane = threadIdx.x & 63;
+    int slot = -1;
+    if (lane == 0 && atomicCAS(&dev->poll_lock, 0, 1) == 0) {
+        const unsigned long long ht = __hip_atomic_load(&host->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        const unsigned long long pulled = __hip_atomic_load(&dev->pulled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (pulled < ht) {
+            slot = __hip_atomic_load(&host->ring[pulled % SERVE_SLOTS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&dev->pulled, pulled + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __hip_atomic_store(&dev->poll_lock, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    slot = __shfl(slot, 0);
+    if (slot < 0) return false;
+    // copy the request out of host memory, a word per lane
+    ServeSlot &S = dev->slot[slot];
+    constexpr int WORDS = sizeof(ServeRequest) / 8;
+    static_assert(sizeof(ServeRequest) % 8 == 0, "request copied in 8-byte words");
+    const unsigned long long *src = (const unsigned long long *)&host->req[slot];
+    unsigned long long *dst = (unsigned long long *)&S.r;
+    for (int w = lane; w < WORDS; w += 64)
+        dst[w] = __hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence();
+    if (lane == 0) {
+        const unsigned long long gen = S.r.gen;
+        for (int k = 0; k < SERVE_NPH; k++) S.done[k] = 0;
+        S.nr[PH_BOUNDS] = ceil_div(S.r.n, SERVE_ATOMS_LIGHT);
+        S.bad = 0;
+        __threadfence();
+        __hip_atomic_store(&S.next[PH_BOUNDS], serve_counter(gen), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        serve_push(dev, slot, PH_BOUNDS, gen);
+    }
+    return true;
+}
+
+// The persistent kernel: one wave per workgroup (LDS: templates, the hull
+// stage's per-lane state or the match stage's, in a union).
+template <typename RT>
+__global__ void __launch_bounds__(64, 2) k_serve(TablesView T, ServeDev *dev, ServeHost *host, long long idle_ticks) {
+    __shared__ MatchShared M;
+    __shared__ TablesView Tl;
+    __shared__ MatchOut Ol;
+    __shared__ ServeWork<RT> U;
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) Tl = T;
+    load_templates(M, T);
+    long long idle_from = wall_clock64();
+    for (;;) {
+        int slot = -1, ph = 0;
+        long long r = -1;
+        unsigned long long gen = 0;
+        if (lane == 0) {
+            unsigned long long hd = __hip_atomic_load(&dev->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long tl = __hip_atomic_load(&dev->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (unsigned long long pos = hd; pos < tl && pos < hd + 64; pos++) {
+                if (__hip_atomic_load(&dev->seq[pos % SERVE_FIFO], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                    pos + 1)
+                    break;
+                const unsigned long long e = dev->entry[pos % SERVE_FIFO];
+                const int sl = (int)(e & 0xFFFF), p2 = (int)((e >> 16) & 0xFF);
+                const unsigned long long g2 = e >> 24;
+                ServeSlot &S = dev->slot[sl];
+                // claim the next item: a compare-and-swap on a counter that
+                // carries the frame's generation, so that an entry left over
+                // from the slot's previous frame never takes an item
+                unsigned long long v = __hip_atomic_load(&S.next[p2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                bool got = false;
+                while ((v >> 24) == g2 && (long long)(v & 0xFFFFFF) < S.nr[p2]) {
+                    if (__hip_atomic_compare_exchange_strong(&S.next[p2], &v, v + 1, __ATOMIC_ACQ_REL,
+                                                             __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+                        got = true;
+                        break;
+                    }
+                }
+                if (got) {
+                    slot = sl;
+                    ph = p2;
+                    r = (long long)(v & 0xFFFFFF);
+                    gen = g2;
+                    break;
+                }
+                // exhausted (or stale): the front entry leaves the queue
+                if (pos == hd && atomicCAS(&dev->head, hd, hd + 1) == hd) hd++;
+            }
+        }
+        slot = __shfl(slot, 0);
+        if (slot < 0) {
+            if (serve_pull(dev, host)) {
+                idle_from = wall_clock64();
+                continue;
+            }
+            const int stop = __hip_atomic_load(&host->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (stop || wall_clock64() - idle_from > idle_ticks) break;
+            __builtin_amdgcn_s_sleep(20);
+            continue;
+        }
+        ph = __shfl(ph, 0);
+        r = __shfl(r, 0);
+        gen = __shfl(gen, 0);
+        __threadfence();  // (acquire side: the stage's inputs)
+        serve_item<RT>(M, Tl, Ol, U, T, dev->slot[slot], ph, r);
+        serve_advance(dev, host, slot, ph, gen);
+        __syncthreads();
+        idle_from = wall_clock64();
+    }
+}
+
+__global__ void k_wall_clock(long long *out) {
+    if (threadIdx.x == 0) __hip_atomic_store(out, (long long)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const int32_t *sid,
                   const int8_t *species, const TablesView &T, const int32_t *code, const uint64_t *ord,
                   uint32_t mask, double cutoff, bool force_full, const MatchOut &O, int32_t *full_count,
@@ -2752,6 +3190,27 @@ void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const
     else
         hipLaunchKernelGGL(k_match<double>, grid, block, 0, st, n, nbr_rel, nbr_id, sid, species, T, code, ord,
                            mask, cutoff, (int)force_full, O, full_count, job_count, knn_src, knn_out, box_fail);
+}
+
+template <typename RT>
+static int launch_serve_rt(const TablesView &T, ServeDev *dev, ServeHost *host, long long idle_ticks,
+                           hipStream_t st) {
+    int per_cu = 0, cus = 0, device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve<RT>, 64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int blocks = per_cu * cus;
+    hipLaunchKernelGGL(k_serve<RT>, dim3((unsigned)blocks), dim3(64), 0, st, T, dev, host, idle_ticks);
+    return hipGetLastError() == hipSuccess ? blocks : 0;
+}
+int launch_serve(bool f32, const TablesView &T, ServeDev *dev, ServeHost *host, long long idle_ticks,
+                 hipStream_t st) {
+    return f32 ? launch_serve_rt<float>(T, dev, host, idle_ticks, st)
+               : launch_serve_rt<double>(T, dev, host, idle_ticks, st);
+}
+void launch_wall_clock(long long *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_wall_clock, dim3(1), dim3(64), 0, st, out);
 }
 
 }  // namespace ptm

@@ -75,6 +75,92 @@ void launch_match(int64_t n, const double *nbr_rel, const int32_t *nbr_id, const
                   unsigned long long *job_count, const int32_t *knn_src, int32_t *knn_out, const int32_t *box_fail,
                   bool f32, hipStream_t st);
 
+// int32 entries after the cell counts of a frame's count array: the scan's
+// end, the k-NN leftover counter, the full-rule counter, the box flag, then
+// (at the first 8-byte aligned entry) the 64-bit count of superposed
+// candidates
+constexpr int64_t FRAME_COUNTERS = 7;
+__host__ __device__ inline unsigned long long *job_counter(int32_t *count, int64_t cells) {
+    return (unsigned long long *)(count + ((cells + 5) & ~(int64_t)1));
+}
+
+// ------------------------------------- serving through one persistent kernel
+// The host hands frames over through pinned memory (ServeHost); one
+// persistent kernel (k_serve) pulls them into its device queue and runs
+// every stage of every frame as work items: bounds, grid, zeroing, cell
+// counts, two-level scan, scatter, k-NN, hulls + match.  Completion is
+// written back to the pinned block.
+constexpr int SERVE_SLOTS = 256;              // frames in flight at most
+constexpr int SERVE_FIFO = 4096;              // device queue of (frame, stage) entries
+constexpr int SERVE_NPH = 9;                  // stages of a frame
+constexpr int64_t SERVE_ATOMS_LIGHT = 4096;   // atoms per item: bounds, counts, scatter
+constexpr int64_t SERVE_ATOMS = 256;          // atoms per item: k-NN, hulls + match (at most 2^24 items)
+constexpr int64_t SERVE_ZERO_CELLS = 65536;   // cells per item: zeroing
+constexpr int64_t SERVE_SCAN_CELLS = 16384;   // cells per item: scan
+enum { SERVE_OK = 0, SERVE_BOX = 1, SERVE_NONFINITE = 2 };
+
+// One frame as the host hands it over: inputs, outputs and the frame's
+// device scratch, carved for the largest grid (4n + 4096 cells).
+struct ServeRequest {
+    int64_t n;
+    double box[3];
+    double cutoff;
+    uint32_t mask, need;
+    const double *pos;
+    const int8_t *species;
+    MatchOut O;
+    int32_t *knn_out;
+    int32_t *cell_of, *slot_of, *sid, *count, *start;
+    double *sx, *sy, *sz;
+    int32_t *nbr_id;
+    double *nbr_rel;
+    int32_t *code;
+    uint64_t *ord;
+    double *part;   // [7][bounds items] per-item bounds
+    int32_t *bsum;  // scan: per-item totals, then their exclusive prefix
+    uint64_t gen;   // ticket generation of the slot
+};
+
+// Pinned host block shared by the host and the kernel.
+struct ServeHost {
+    unsigned long long tail;              // requests published (host)
+    int32_t ring[SERVE_SLOTS];            // slot of request k at ring[k % SERVE_SLOTS] (host)
+    ServeRequest req[SERVE_SLOTS];        // (host)
+    unsigned long long done[SERVE_SLOTS]; // generation of the slot's last completed frame (kernel)
+    long long t_done[SERVE_SLOTS];        // device wall clock at completion (kernel)
+    int32_t status[SERVE_SLOTS];          // SERVE_* (kernel)
+    int32_t stop;                         // set by the host: every wave exits (host)
+};
+
+// Device state of one slot and of the queue (device memory, zeroed once).
+struct ServeSlot {
+    ServeRequest r;
+    Grid g;
+    int64_t cells;
+    int32_t fast, bad;
+    unsigned long long next[SERVE_NPH];  // claim counters: generation << 24 | next item
+    long long done[SERVE_NPH], nr[SERVE_NPH];
+};
+struct ServeDev {
+    unsigned long long head, tail, pulled;
+    int32_t poll_lock, pad;
+    unsigned long long seq[SERVE_FIFO];
+    unsigned long long entry[SERVE_FIFO];
+    ServeSlot slot[SERVE_SLOTS];
+};
+
+// scratch of the serving stages beyond the stream path's, for n atoms
+inline int64_t serve_bounds_items(int64_t n) { return (n + SERVE_ATOMS_LIGHT - 1) / SERVE_ATOMS_LIGHT; }
+inline int64_t serve_scan_items(int64_t n) { return (4 * n + 4096 + 1 + SERVE_SCAN_CELLS - 1) / SERVE_SCAN_CELLS; }
+
+// Launch the persistent kernel (grid: what fits on the device at once);
+// its waves exit after idle_ticks of the device wall clock without work,
+// or when host->stop is set.  Returns the number of workgroups, 0 on error.
+int launch_serve(bool f32, const TablesView &T, ServeDev *dev, ServeHost *host, long long idle_ticks,
+                 hipStream_t st);
+// device wall clock into *out (pinned), for the host's clock reference
+void launch_wall_clock(long long *out, hipStream_t st);
+
 // post-hoc cut-off and RMSD histograms (counts: device, 6 * nbins, zeroed by the caller)
 void launch_apply_cutoff(int64_t n, const int8_t *best_type, const double *rmsd, double cutoff, int8_t *type,
                          hipStream_t st);

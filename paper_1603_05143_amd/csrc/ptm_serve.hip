@@ -11,12 +11,19 @@
 // context's HBM budget next to that of all in-flight frames; otherwise
 // ptm_submit returns PTM_E_BUSY and the caller retries after a ptm_wait.
 // Completion times are read from timing events on the device timeline.
+//
+// With PTM_F_PERSISTENT the frames go to one persistent kernel instead
+// (k_serve): ptm_submit writes the frame's request (inputs, outputs and
+// its pooled scratch) into a pinned block and returns; the kernel pulls it
+// and runs every stage as work items; ptm_wait polls the completion word
+// the kernel writes back, relaunching the kernel if it has exited idle.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ptm_internal.hpp"
 
@@ -170,8 +177,9 @@ ptm_status stage_out(ptm_ctx *ctx, const ptm_outputs *out, int64_t n, const Fram
 }
 
 static ptm_status serve_init(ptm_ctx *ctx) {
-    if (!ctx->serve_streams.empty()) return PTM_OK;
-    for (int s = 0; s < SERVE_STREAMS; s++) {
+    if (ctx->bounds_stream) return PTM_OK;
+    // (persistent serving runs no per-frame work on streams)
+    for (int s = 0; s < ((ctx->flags & PTM_F_PERSISTENT) ? 0 : SERVE_STREAMS); s++) {
         hipStream_t h;
         PTM_HIP(ctx, hipStreamCreateWithFlags(&h, hipStreamNonBlocking));
         ctx->serve_streams.push_back(h);
@@ -240,6 +248,8 @@ static ptm_status take_scratch(ptm_ctx *ctx, size_t c, FrameScratch &out) {
 
 static void retire(ptm_ctx *ctx, Ticket *T) {
     ctx->inflight_bytes -= T->footprint;
+    if (T->slot >= 0) ctx->sv_free.push_back(T->slot);
+    T->slot = -1;
     if (T->done) (void)hipEventDestroy(T->done);
     T->done = nullptr;
     if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);
@@ -247,12 +257,203 @@ static void retire(ptm_ctx *ctx, Ticket *T) {
     T->staging.release();
 }
 
+// ------------------------------------------------ persistent serving
+// (PTM_F_PERSISTENT; the kernel is k_serve in ptm_kernels.hip).  The host
+// side: a pinned block shared with the kernel (requests in, completions
+// out), a free list of slots, and the kernel's launch state.
+static constexpr double SERVE_IDLE_MS = 20.0;
+
+static ptm_status persistent_init(ptm_ctx *ctx) {
+    if (ctx->sv_dev) return PTM_OK;
+    PTM_HIP(ctx, hipMalloc(&ctx->sv_dev, sizeof(ServeDev)));
+    PTM_HIP(ctx, hipMemset(ctx->sv_dev, 0, sizeof(ServeDev)));
+    PTM_HIP(ctx, hipHostMalloc((void **)&ctx->sv_host, sizeof(ServeHost), hipHostMallocCoherent));
+    std::memset((void *)ctx->sv_host, 0, sizeof(ServeHost));
+    PTM_HIP(ctx, hipHostMalloc((void **)&ctx->sv_clock, sizeof(long long), hipHostMallocCoherent));
+    // The kernel's stream gets a hardware queue of its own: a stream with a
+    // CU mask (here every CU) is not multiplexed with other streams, so work
+    // the application queues on its streams never waits behind the
+    // long-running kernel.
+    int cus = 0;
+    PTM_HIP(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    std::vector<uint32_t> cu_mask((size_t)(cus + 31) / 32, 0u);
+    for (int c = 0; c < cus; c++) cu_mask[(size_t)c / 32] |= 1u << (c % 32);
+    if (hipExtStreamCreateWithCUMask(&ctx->sv_stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        PTM_HIP(ctx, hipStreamCreateWithFlags(&ctx->sv_stream, hipStreamNonBlocking));
+    }
+    PTM_HIP(ctx, hipEventCreateWithFlags(&ctx->sv_exit, hipEventDisableTiming));
+    int khz = 0;
+    PTM_HIP(ctx, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+    ctx->sv_clock_khz = khz > 0 ? (double)khz : 1e5;
+    // the device wall clock against the host clock: a kernel that reads it,
+    // bracketed by host times (the tightest of three)
+    double best = 1e300;
+    for (int k = 0; k < 3; k++) {
+        *ctx->sv_clock = 0;
+        const double t0 = now_us();
+        launch_wall_clock(ctx->sv_clock, ctx->sv_stream);
+        PTM_HIP(ctx, hipStreamSynchronize(ctx->sv_stream));
+        const double t1 = now_us();
+        if (t1 - t0 < best) {
+            best = t1 - t0;
+            ctx->sv_ref_host_us = 0.5 * (t0 + t1);
+            ctx->sv_ref_dev = *ctx->sv_clock;
+        }
+    }
+    ctx->sv_free.clear();
+    for (int k = SERVE_SLOTS - 1; k >= 0; k--) ctx->sv_free.push_back(k);
+    return PTM_OK;
+}
+
+// (re)launch the persistent kernel unless it is running
+static ptm_status persistent_run(ptm_ctx *ctx) {
+    if (ctx->sv_launched) {
+        const hipError_t q = hipEventQuery(ctx->sv_exit);
+        if (q == hipErrorNotReady) return PTM_OK;
+        if (q != hipSuccess) {
+            ctx->err = std::string("persistent serving kernel failed: ") + hipGetErrorString(q);
+            return PTM_E_DEVICE;
+        }
+    }
+    const long long idle = (long long)(SERVE_IDLE_MS * ctx->sv_clock_khz);
+    if (launch_serve(ctx->precision == PTM_FP32_MIXED, ctx->view, ctx->sv_dev, ctx->sv_host, idle,
+                     ctx->sv_stream) <= 0) {
+        ctx->err = "launch of the persistent serving kernel failed";
+        return PTM_E_DEVICE;
+    }
+    PTM_HIP(ctx, hipEventRecord(ctx->sv_exit, ctx->sv_stream));
+    ctx->sv_launched = true;
+    return PTM_OK;
+}
+
+static bool persistent_done(const ptm_ctx *ctx, const Ticket *T) {
+    return __atomic_load_n(&ctx->sv_host->done[T->slot], __ATOMIC_ACQUIRE) == T->gen;
+}
+
+// hand the frame of ticket T over to the kernel
+static ptm_status persistent_submit(ptm_ctx *ctx, const double *positions, const int8_t *species,
+                                    const double *box, const ptm_outputs *out, Ticket *T) {
+    ptm_status st;
+    if ((st = persistent_init(ctx)) != PTM_OK) return st;
+    if (ctx->sv_free.empty()) {
+        ctx->err = "every serving slot is in flight";
+        return PTM_E_BUSY;
+    }
+    const int64_t n = T->job.n;
+    // the frame's inputs may be written by work queued on the context stream
+    PTM_HIP(ctx, hipEventRecord(ctx->order_event, ctx->stream));
+    PTM_HIP(ctx, hipEventSynchronize(ctx->order_event));
+    st = stage_in_buffers(ctx, T->staging, positions, species, out, n, T->job, T->stage, ctx->bounds_stream);
+    if (st == PTM_OK && T->stage.active) PTM_HIP(ctx, hipStreamSynchronize(ctx->bounds_stream));
+    if (st != PTM_OK) return st;
+    // scratch for the largest grid the kernel can choose
+    T->footprint = scratch_class(n, false);
+    st = take_scratch(ctx, T->footprint, T->scratch);
+    if (st == PTM_OK && !T->scratch.reserve(n, 4 * n + 4096, false, ctx->err)) st = PTM_E_DEVICE;
+    if (st != PTM_OK) {
+        if (T->scratch.base) ctx->free_scratch.push_back(T->scratch);
+        T->scratch = FrameScratch();
+        T->staging.release();
+        return st;
+    }
+    ctx->inflight_bytes += T->footprint;
+    T->slot = ctx->sv_free.back();
+    ctx->sv_free.pop_back();
+    T->gen = ++ctx->sv_gen;
+    const uint32_t m = T->job.mask;
+    const ptm_outputs &o = T->job.out;
+    const FrameScratch &S = T->scratch;
+    ServeRequest R;
+    std::memset(&R, 0, sizeof(R));
+    R.n = n;
+    for (int a = 0; a < 3; a++) R.box[a] = box[a];
+    R.cutoff = T->job.cutoff;
+    R.mask = m;
+    R.need = ((m & 0x1u) ? 1u : 0u) | ((m & 0xEu) ? 2u : 0u) | ((m & 0x10u) ? 4u : 0u);
+    R.pos = T->job.pos;
+    R.species = T->job.species;
+    R.O = MatchOut{o.type, o.alloy, o.rmsd, o.scale, o.quat, o.neighbours, o.strain, o.vm_strain, o.strain_residual,
+                   o.nn_distance, o.quat_fz, o.best_type};
+    R.knn_out = o.knn;
+    R.cell_of = S.cell_of;
+    R.slot_of = S.slot_of;
+    R.sid = S.sid;
+    R.count = S.count;
+    R.start = S.start;
+    R.sx = S.sx;
+    R.sy = S.sy;
+    R.sz = S.sz;
+    R.nbr_id = S.nbr_id;
+    R.nbr_rel = S.nbr_rel;
+    R.code = S.code;
+    R.ord = S.ord;
+    R.part = S.sv_part;
+    R.bsum = S.sv_bsum;
+    R.gen = T->gen;
+    // request, then its ring entry, then the tail (the kernel reads them in
+    // the opposite order with acquire loads)
+    ServeHost *H = ctx->sv_host;
+    std::memcpy((void *)&H->req[T->slot], &R, sizeof(R));
+    const unsigned long long tail = __atomic_load_n(&H->tail, __ATOMIC_RELAXED);
+    __atomic_store_n(&H->ring[tail % SERVE_SLOTS], T->slot, __ATOMIC_RELEASE);
+    __atomic_store_n(&H->tail, tail + 1, __ATOMIC_RELEASE);
+    T->t_start = now_us();
+    return persistent_run(ctx);
+}
+
+// wait for a persistent ticket's completion (timeout_us < 0: forever)
+static ptm_status persistent_wait(ptm_ctx *ctx, Ticket *T, int64_t timeout_us) {
+    const double t0 = now_us();
+    while (!persistent_done(ctx, T)) {
+        if (timeout_us >= 0 && now_us() - t0 >= (double)timeout_us) return PTM_E_TIMEOUT;
+        ptm_status rs = persistent_run(ctx);  // relaunch if the kernel has exited
+        if (rs != PTM_OK) return rs;
+    }
+    const ServeHost *H = ctx->sv_host;
+    const int status = __atomic_load_n(&H->status[T->slot], __ATOMIC_RELAXED);
+    const long long td = __atomic_load_n(&H->t_done[T->slot], __ATOMIC_RELAXED);
+    T->t_complete = ctx->sv_ref_host_us + (double)(td - ctx->sv_ref_dev) * 1e3 / ctx->sv_clock_khz;
+    T->complete = true;
+    T->box_fail = status == SERVE_BOX;
+    T->nonfinite = status == SERVE_NONFINITE;
+    if (status == SERVE_OK && T->stage.active) {
+        ptm_status so = stage_out(ctx, &T->stage.host_out, T->job.n, T->job, T->stage, ctx->bounds_stream);
+        if (so != PTM_OK) return so;
+        PTM_HIP(ctx, hipStreamSynchronize(ctx->bounds_stream));
+        T->t_complete = now_us();  // the outputs are in host memory only now
+    }
+    return PTM_OK;
+}
+
+static void persistent_shutdown(ptm_ctx *ctx) {
+    if (!ctx->sv_dev) return;
+    if (ctx->sv_host) __atomic_store_n(&ctx->sv_host->stop, 1, __ATOMIC_RELEASE);
+    if (ctx->sv_stream) (void)hipStreamSynchronize(ctx->sv_stream);
+    (void)hipFree(ctx->sv_dev);
+    ctx->sv_dev = nullptr;
+    if (ctx->sv_host) (void)hipHostFree((void *)ctx->sv_host);
+    ctx->sv_host = nullptr;
+    if (ctx->sv_clock) (void)hipHostFree(ctx->sv_clock);
+    ctx->sv_clock = nullptr;
+    if (ctx->sv_exit) (void)hipEventDestroy(ctx->sv_exit);
+    ctx->sv_exit = nullptr;
+    if (ctx->sv_stream) (void)hipStreamDestroy(ctx->sv_stream);
+    ctx->sv_stream = nullptr;
+    ctx->sv_launched = false;
+}
+
 void serve_shutdown(ptm_ctx *ctx) {
     for (auto &kv : ctx->tickets) {
-        if (kv.second->done) (void)hipEventSynchronize(kv.second->done);
-        retire(ctx, kv.second);
-        delete kv.second;
+        Ticket *T = kv.second;
+        if (T->done) (void)hipEventSynchronize(T->done);
+        // a persistent frame still in flight: its scratch is in use until
+        // it completes (bounded wait: 60 s)
+        if (T->slot >= 0 && !T->complete) (void)persistent_wait(ctx, T, 60000000);
+        retire(ctx, T);
+        delete T;
     }
+    persistent_shutdown(ctx);
     ctx->tickets.clear();
     for (auto &s : ctx->free_scratch) s.release();
     ctx->free_scratch.clear();
@@ -295,7 +496,20 @@ ptm_status ptm_submit(ptm_ctx *ctx, const double *positions, const int8_t *speci
     T->job.mask = template_mask & PTM_ALL;
     T->job.cutoff = rmsd_cutoff;
     T->job.topo = (ctx->flags & PTM_F_TOPOLOGICAL) != 0;
-    if (n_atoms > 0) {
+    if (n_atoms > 0 && (ctx->flags & PTM_F_PERSISTENT)) {
+        st = persistent_submit(ctx, positions, species, box, out, T);
+        if (st != PTM_OK) {
+            if (T->slot >= 0) {
+                // handed over already (only the launch failed): it stays a ticket
+                uint64_t id = ctx->next_ticket++;
+                ctx->tickets[id] = T;
+                *ticket = id;
+            } else {
+                delete T;
+            }
+            return st;
+        }
+    } else if (n_atoms > 0) {
         hipStream_t bst = ctx->bounds_stream;
         // the frame starts after the work already queued on the context's
         // stream (which may have written its inputs)
@@ -360,7 +574,11 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
         return PTM_E_INVALID;
     }
     Ticket *T = it->second;
-    if (!T->complete) {
+    if (!T->complete && T->slot >= 0) {
+        PTM_HIP(ctx, hipSetDevice(ctx->device));
+        ptm_status ws = persistent_wait(ctx, T, timeout_us);
+        if (ws != PTM_OK) return ws;
+    } else if (!T->complete) {
         PTM_HIP(ctx, hipSetDevice(ctx->device));
         double t0 = now_us();
         for (;;) {
@@ -393,7 +611,7 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
             T->t_complete = now_us();  // the outputs are in host memory only now
         }
     }
-    const bool box_fail = T->box_fail;
+    const bool box_fail = T->box_fail, nonfinite = T->nonfinite;
     const bool topo = T->job.topo;
     if (stats) {
         stats->submit_time_us = T->t_submit;
@@ -408,6 +626,10 @@ ptm_status ptm_wait(ptm_ctx *ctx, uint64_t ticket, int64_t timeout_us, ptm_frame
     if (box_fail) {
         ctx->err = box_message(topo);
         return PTM_E_BOX;
+    }
+    if (nonfinite) {
+        ctx->err = "non-finite coordinate";
+        return PTM_E_INVALID;
     }
     return PTM_OK;
 }

@@ -21,6 +21,7 @@ PTM_F_HOST_POINTERS = 1
 PTM_F_PROFILE = 2
 PTM_F_TOPOLOGICAL = 4
 PTM_F_FULL_RULE = 8
+PTM_F_PERSISTENT = 16
 STAGE_NAMES = ("bounds", "bin", "knn", "topo", "match")
 TYPE_NAMES = ("NONE", "SC", "FCC", "HCP", "ICO", "BCC")
 ALLOY_NAMES = ("NONE", "A1", "L1_0", "L1_2_maj", "L1_2_min", "FCC_other", "A2", "B2", "BCC_other")

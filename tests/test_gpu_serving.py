@@ -1,4 +1,6 @@
-"""Serving loop (ptm_submit / ptm_wait) on the GPU, through the C ABI.
+"""Serving loop (ptm_submit / ptm_wait) on the GPU, through the C ABI, in
+both of its forms: frames on a pool of streams, and frames drained by one
+persistent kernel (PTM_F_PERSISTENT).
 
 Frames of uneven size are submitted back to back so that their work
 overlaps on the device; each result must equal the result of the same frame
@@ -25,10 +27,23 @@ def torch_cuda():
     return torch
 
 
+MODES = [0, ptm.PTM_F_PERSISTENT]
+MODE_IDS = ["streams", "persistent"]
+
+
+def _open_cluster(shells, seed):
+    """An open-boundary frame: a thermally displaced Mackay icosahedron."""
+    rng = np.random.default_rng(seed)
+    pos = S.mackay_icosahedron(shells)
+    return S.Frame(positions=pos + rng.normal(0.0, 0.05, pos.shape), box=np.zeros(3))
+
+
 @pytest.fixture(scope="module")
 def frames():
     sizes = [1200, 40000, 3000, 150000, 700, 12000, 90000, 5000]
-    return [S.serving_frame(int(n), seed=1000 + k) for k, n in enumerate(sizes)]
+    fr = [S.serving_frame(int(n), seed=1000 + k) for k, n in enumerate(sizes)]
+    fr.insert(3, _open_cluster(5, 7))  # open axes: the grid follows from the bounds
+    return fr
 
 
 def _device_frame(torch, f):
@@ -63,11 +78,12 @@ def _submit_all(torch, ctx, frames):
     return keep, tickets
 
 
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
-def test_mixed_equals_alone(torch_cuda, frames, precision):
+def test_mixed_equals_alone(torch_cuda, frames, precision, mode):
     torch = torch_cuda
     ref = _alone(torch, precision, frames)
-    ctx = ptm.ptm_create(0, precision, None, 0, 0)
+    ctx = ptm.ptm_create(0, precision, None, 0, mode)
     try:
         for rep in range(2):  # the second pass reuses pooled scratch
             keep, tickets = _submit_all(torch, ctx, frames)
@@ -89,18 +105,19 @@ def test_mixed_equals_alone(torch_cuda, frames, precision):
         ptm.ptm_destroy(ctx)
 
 
-def test_budget_admission(torch_cuda, frames):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_budget_admission(torch_cuda, frames, mode):
     torch = torch_cuda
     big = max(frames, key=lambda f: f.n)
     # a budget that holds one frame of this size but not two
-    probe = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    probe = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, mode)
     keep, (t,) = _submit_all(torch, probe, [big])
     st, s = ptm.ptm_wait(probe, t, -1)
     assert st == ptm.PTM_OK
     ptm.ptm_destroy(probe)
     cls = s.scratch_bytes
     assert cls >= 24 * big.n and cls & (cls - 1) == 0
-    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, cls + cls // 2, 0)
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, cls + cls // 2, mode)
     try:
         pos, sp = _device_frame(torch, big)
         outs = [ptm.Classifier.alloc_outputs(big.n, "cuda:0") for _ in range(2)]
@@ -117,7 +134,7 @@ def test_budget_admission(torch_cuda, frames):
         for k in ("type", "rmsd", "neighbours"):
             assert torch.equal(outs[0][k], outs[1][k])
         # a budget smaller than one frame's class is a hard error
-        tiny = ptm.ptm_create(0, ptm.PTM_FP64, None, 1 << 20, 0)
+        tiny = ptm.ptm_create(0, ptm.PTM_FP64, None, 1 << 20, mode)
         st3, _ = ptm.ptm_submit(tiny, pos.data_ptr(), None, big.box, big.n, ptm.PTM_ALL, math.inf, o1)
         assert st3 == ptm.PTM_E_NOMEM
         ptm.ptm_destroy(tiny)
@@ -125,9 +142,10 @@ def test_budget_admission(torch_cuda, frames):
         ptm.ptm_destroy(ctx)
 
 
-def test_wait_timeout_and_unknown_ticket(torch_cuda, frames):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_wait_timeout_and_unknown_ticket(torch_cuda, frames, mode):
     torch = torch_cuda
-    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, mode)
     try:
         big = max(frames, key=lambda f: f.n)
         keep, (t,) = _submit_all(torch, ctx, [big])
@@ -141,8 +159,9 @@ def test_wait_timeout_and_unknown_ticket(torch_cuda, frames):
         ptm.ptm_destroy(ctx)
 
 
-def test_empty_frame_ticket(torch_cuda):
-    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_empty_frame_ticket(torch_cuda, mode):
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, mode)
     try:
         o = ptm.ptm_outputs()
         st, t = ptm.ptm_submit(ctx, None, None, (10.0, 10.0, 10.0), 0, ptm.PTM_ALL, math.inf, o)
@@ -153,14 +172,15 @@ def test_empty_frame_ticket(torch_cuda):
         ptm.ptm_destroy(ctx)
 
 
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 @pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
-def test_mixed_equals_oracle(torch_cuda, oracle_lib, frames, precision):
+def test_mixed_equals_oracle(torch_cuda, oracle_lib, frames, precision, mode):
     """The frames submitted together, overlapping on the device, against the
     FP64 oracle frame by frame: decisions bit-exact, reals within the form's
     tolerance."""
     from parity_util import TOL32, TOL64, compare
     torch = torch_cuda
-    ctx = ptm.ptm_create(0, precision, None, 0, 0)
+    ctx = ptm.ptm_create(0, precision, None, 0, mode)
     try:
         keep, tickets = _submit_all(torch, ctx, frames)
         for t in tickets:
@@ -176,7 +196,8 @@ def test_mixed_equals_oracle(torch_cuda, oracle_lib, frames, precision):
         ptm.ptm_destroy(ctx)
 
 
-def test_box_error_in_the_stream(torch_cuda, oracle_lib, frames):
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_box_error_in_the_stream(torch_cuda, oracle_lib, frames, mode):
     """A frame whose periodic box is too short for its neighbour shell,
     submitted between others: its ticket reports PTM_E_BOX and its outputs
     stay untouched; the frames around it are unaffected."""
@@ -187,7 +208,7 @@ def test_box_error_in_the_stream(torch_cuda, oracle_lib, frames):
         oracle_lib.classify(bad.positions, bad.box)
     mix = [frames[0], bad, frames[2]]
     ref = _alone(torch, ptm.PTM_FP64, [frames[0], frames[2]])
-    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, 0)
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, mode)
     try:
         keep, tickets = [], []
         for f in mix:
@@ -212,3 +233,83 @@ def test_box_error_in_the_stream(torch_cuda, oracle_lib, frames):
                 assert np.array_equal(out[k].cpu().numpy(), r[k], equal_nan=True), k
     finally:
         ptm.ptm_destroy(ctx)
+
+
+def test_persistent_nonfinite_frame(torch_cuda, frames):
+    """A non-finite coordinate in a frame handed to the persistent kernel:
+    ptm_submit accepts it (nothing is checked on the host), ptm_wait reports
+    PTM_E_INVALID, the outputs stay untouched and the next frame is served."""
+    torch = torch_cuda
+    f = frames[0]
+    bad = f.positions.copy()
+    bad[17, 1] = np.nan
+    ctx = ptm.ptm_create(0, ptm.PTM_FP64, None, 0, ptm.PTM_F_PERSISTENT)
+    try:
+        pos = torch.from_numpy(bad).to("cuda:0")
+        out = ptm.Classifier.alloc_outputs(f.n, "cuda:0")
+        for v in out.values():
+            v.fill_(7)
+        torch.cuda.synchronize()
+        st, t = ptm.ptm_submit(ctx, pos.data_ptr(), None, f.box, f.n, ptm.PTM_ALL, math.inf,
+                               ptm.Classifier.outputs_struct(out))
+        assert st == ptm.PTM_OK
+        assert ptm.ptm_wait(ctx, t, -1)[0] == ptm.PTM_E_INVALID
+        assert "non-finite" in ptm.ptm_last_error(ctx)
+        torch.cuda.synchronize()
+        for k, v in out.items():
+            assert bool((v == 7).all()), k
+        keep, (t2,) = _submit_all(torch, ctx, [f])
+        assert ptm.ptm_wait(ctx, t2, -1)[0] == ptm.PTM_OK
+    finally:
+        ptm.ptm_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [ptm.PTM_FP64, ptm.PTM_FP32_MIXED], ids=["fp64", "fp32mixed"])
+def test_persistent_many_frames(torch_cuda, precision):
+    """300 frames of 64 to 6000 atoms (periodic and open) through the
+    persistent kernel, more than its 256 slots: submissions past the slots
+    return PTM_E_BUSY and are retried after waiting for the oldest ticket;
+    every frame equals the same frame classified alone."""
+    torch = torch_cuda
+    rng = np.random.default_rng(31)
+    fr = []
+    for k in range(300):
+        if k % 7 == 3:
+            fr.append(_open_cluster(int(rng.integers(2, 5)), 100 + k))
+        else:
+            fr.append(S.serving_frame(int(rng.integers(64, 6000)), seed=2000 + k))
+    ref = _alone(torch, precision, fr)
+    ctx = ptm.ptm_create(0, precision, None, 0, ptm.PTM_F_PERSISTENT)
+    try:
+        pending, done, busy = [], {}, 0
+        for k, f in enumerate(fr):
+            pos, sp = _device_frame(torch, f)
+            out = ptm.Classifier.alloc_outputs(f.n, "cuda:0", knn=True, derived=True)
+            o = ptm.Classifier.outputs_struct(out)
+            while True:
+                st, t = ptm.ptm_submit(ctx, pos.data_ptr(), None if sp is None else sp.data_ptr(), f.box, f.n,
+                                       ptm.PTM_ALL, math.inf, o)
+                if st != ptm.PTM_E_BUSY:
+                    break
+                busy += 1
+                j, t0, keep0 = pending.pop(0)
+                assert ptm.ptm_wait(ctx, t0, -1)[0] == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+                done[j] = keep0
+            assert st == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+            pending.append((k, t, (pos, sp, out, o)))
+        for j, t0, keep0 in pending:
+            assert ptm.ptm_wait(ctx, t0, -1)[0] == ptm.PTM_OK, ptm.ptm_last_error(ctx)
+            done[j] = keep0
+        assert busy > 0
+        for k, f in enumerate(fr):
+            out = done[k][2]
+            for key, v in out.items():
+                assert np.array_equal(v.cpu().numpy(), ref[k][key], equal_nan=True), (k, f.n, key)
+        print("persistent frames", len(fr), "busy retries", busy, flush=True)
+    finally:
+        ptm.ptm_destroy(ctx)
+
+
+def test_persistent_with_topological_is_refused():
+    with pytest.raises(ptm.PTMError):
+        ptm.ptm_create(0, ptm.PTM_FP64, None, 0, ptm.PTM_F_PERSISTENT | ptm.PTM_F_TOPOLOGICAL)
