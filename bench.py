@@ -319,13 +319,18 @@ def serving_pool(pool_levels):
 
 
 def serving_bench(pool, n_frames, ring, budget_gb, seed_shift=0):
-    """Serving loop on a stream of frames with log-uniform sizes in [1e3, 2e6].
+    """Serving loop on a stream of frames with log-uniform sizes in [1e3, 2e6],
+    in both serving forms: the persistent kernel (PTM_F_PERSISTENT, first:
+    the headline p50/p99) and the pool of streams.
 
     Each stream frame is the pool frame nearest to its size in log scale
     (the pool of distinct frames is resident on the device).  ``ring``
     output sets bound the frames in flight on the client side; admission on
-    the library side is by the HBM budget.  Latency = device completion time
-    - scheduled arrival time.
+    the library side is by the HBM budget.  Per form and precision: the
+    saturated rate (every frame submitted as soon as an output set is free),
+    then latency at one Poisson arrival rate for all runs, 0.7 x the
+    persistent FP64 saturated frame rate.  Latency = completion time on the
+    host clock - scheduled arrival time.
     """
     import collections
 
@@ -388,37 +393,46 @@ def serving_bench(pool, n_frames, ring, budget_gb, seed_shift=0):
 
     res = {}
     rate = None
-    for name, prec in (("fp64", ptm.PTM_FP64), ("fp32_mixed", ptm.PTM_FP32_MIXED)):
-        ctx = ptm.ptm_create(0, prec, None, int(budget_gb * 1e9), 0)
-        # warm the scratch pool: every pool frame twice, in flight together
-        keep = []
-        for rep in range(2):
-            for j, (pos, spc, f) in enumerate(dev):
-                st, tk = ptm.ptm_submit(ctx, pos.data_ptr(), spc.data_ptr(), f.box, f.n, ptm.PTM_ALL, math.inf,
-                                        structs[(rep * len(dev) + j) % ring])
-                keep.append(tk)
-        for tk in keep:
-            ptm.ptm_wait(ctx, tk, -1)
-        t0, _, done = run(ctx, None)
-        span_s = (done.max() - t0) / 1e6
-        r = {"atoms_per_s": atoms.sum() / span_s, "frames_per_s": n_frames / span_s}
-        if rate is None:
-            rate = 0.7 * r["frames_per_s"]  # same arrival rate for both forms
-        t0, arrive, done = run(ctx, rate)
-        lat_ms = (done - (t0 + arrive)) / 1e3
-        lat = lat_ms[50:] if n_frames > 100 else lat_ms
-        r.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "mean_ms": float(lat.mean())})
-        ptm.ptm_destroy(ctx)
-        print(f"[serve] {name}: {r}", file=sys.stderr, flush=True)
-        res[name] = r
+    for mode, flags in (("persistent", ptm.PTM_F_PERSISTENT), ("streams", 0)):
+        for name, prec in (("fp64", ptm.PTM_FP64), ("fp32_mixed", ptm.PTM_FP32_MIXED)):
+            ctx = ptm.ptm_create(0, prec, None, int(budget_gb * 1e9), flags)
+            # warm the scratch pool: every pool frame twice, in flight together
+            keep = []
+            for rep in range(2):
+                for j, (pos, spc, f) in enumerate(dev):
+                    while True:
+                        st, tk = ptm.ptm_submit(ctx, pos.data_ptr(), spc.data_ptr(), f.box, f.n, ptm.PTM_ALL,
+                                                math.inf, structs[(rep * len(dev) + j) % ring])
+                        if st != ptm.PTM_E_BUSY or not keep:
+                            break
+                        ptm.ptm_wait(ctx, keep.pop(0), -1)
+                    if st != ptm.PTM_OK:
+                        raise RuntimeError(ptm.ptm_last_error(ctx))
+                    keep.append(tk)
+            for tk in keep:
+                ptm.ptm_wait(ctx, tk, -1)
+            t0, _, done = run(ctx, None)
+            span_s = (done.max() - t0) / 1e6
+            r = {"atoms_per_s": atoms.sum() / span_s, "frames_per_s": n_frames / span_s}
+            if rate is None:
+                rate = 0.7 * r["frames_per_s"]  # same arrival rate for both forms
+            t0, arrive, done = run(ctx, rate)
+            lat_ms = (done - (t0 + arrive)) / 1e3
+            lat = lat_ms[50:] if n_frames > 100 else lat_ms
+            r.update({"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                      "mean_ms": float(lat.mean())})
+            ptm.ptm_destroy(ctx)
+            print(f"[serve] {mode} {name}: {r}", file=sys.stderr, flush=True)
+            res.setdefault(mode, {})[name] = r
     del outs, dev
     return {"frames": n_frames, "sizes": "log-uniform in [1e3, 2e6] atoms",
             "pool_frames": len(pool), "pool_atoms": int(sum(f.n for f in pool)),
             "distinct_frames_used": int(len(np.unique(pick))),
             "rate_hz": rate, "budget_gb": budget_gb, "client_ring": ring,
             "latency_over": f"frames 51-{n_frames}" if n_frames > 100 else "all frames",
-            "fp64": res["fp64"], "fp32_mixed": res["fp32_mixed"]}
+            "form": "persistent kernel (PTM_F_PERSISTENT)",
+            "fp64": res["persistent"]["fp64"], "fp32_mixed": res["persistent"]["fp32_mixed"],
+            "streams": res["streams"]}
 
 
 def cpu_threads() -> int:

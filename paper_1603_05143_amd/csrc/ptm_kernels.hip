@@ -1481,8 +1481,9 @@ __device__ int32_t probe_rest(const TablesView &T, int grp, const uint64_t (&bes
 // enabled by need: bit g for hull group g), code ids and labellings into
 // code_out / ord_out [group][n] (-1 / 0 for a group without a valid hull or
 // not needed).
-// One atom p per lane t of a 64-lane wave, with the wave's LDS S.
-__device__ void topo_atom(TopoShared &S, int t, int64_t p, int64_t n, const double *__restrict__ nbr_rel,
+// One atom p per lane t of a 64-lane wave, with the wave's LDS S (always
+// inlined: the LDS accesses must stay LDS instructions).
+__device__ __attribute__((always_inline)) inline void topo_atom(TopoShared &S, int t, int64_t p, int64_t n, const double *__restrict__ nbr_rel,
                           const int32_t *__restrict__ nbr_id, const TablesView &T, uint32_t need,
                           int32_t *__restrict__ code_out, uint64_t *__restrict__ ord_out) {
     // the neighbour ids that say which hulls are possible (the K-th neighbour
@@ -2826,8 +2827,10 @@ __device__ inline unsigned long long serve_entry(int slot, int ph, unsigned long
     return (unsigned long long)slot | ((unsigned long long)ph << 16) | (gen << 24);
 }
 
-// a stage's claim counter: the frame's generation over a 24-bit item index
-__device__ inline unsigned long long serve_counter(unsigned long long gen) { return gen << 24; }
+// a stage's claim counter: the frame's generation (36 bits) over a 28-bit item index
+constexpr int SERVE_IDX_BITS = 28;
+constexpr unsigned long long SERVE_IDX_MASK = (1ull << SERVE_IDX_BITS) - 1;
+__device__ inline unsigned long long serve_counter(unsigned long long gen) { return gen << SERVE_IDX_BITS; }
 
 // append (slot, stage); the stage's item count and counter are set before
 // (one lane)
@@ -2863,6 +2866,77 @@ union ServeWork {
     TopoShared topo;
     MatchWork<RT, 1> mw;
 };
+
+// k-NN stage item: the fast search lane by lane, the exact one for what it
+// leaves, a wave per atom (a call of its own: its registers apart)
+__device__ __noinline__ void serve_knn(ServeSlot &S, int64_t r) {
+    const int lane = threadIdx.x & 63;
+    // the grid and the arrays in registers: the searches' stores cannot
+    // alias them
+    const Grid g = S.g;
+    const int64_t n = S.r.n;
+    const bool fast = S.fast;
+    const double *sx = S.r.sx, *sy = S.r.sy, *sz = S.r.sz;
+    const int32_t *sid = S.r.sid, *start = S.r.count;
+    int32_t *nbr_id = S.r.nbr_id;
+    double *nbr_rel = S.r.nbr_rel;
+    int32_t *box_fail = S.r.count + S.cells + 3;
+    const int64_t b = r * SERVE_ATOMS, e = min(n, b + SERVE_ATOMS);
+    for (int64_t sub = b; sub < e; sub += 64) {
+        const int64_t p = sub + lane;
+        bool ok = true;
+        if (p < e) ok = fast && knn_fast_atom<KMAX>(p, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail);
+        uint64_t left = __ballot(!ok);
+        while (left) {
+            const int l = __builtin_ctzll(left);
+            left &= left - 1;
+            knn_exact_atom<KMAX>(sub + l, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail);
+        }
+    }
+}
+
+// hulls + match stage item, 64 atoms at a time (a call of its own)
+// The LDS objects (templates, table view, outputs, working space) come as
+// LDS-space pointers: a call's reference parameters are generic, and
+// generic accesses to LDS are slower flat instructions; the generic views
+// below derive from the LDS pointers, so the compiler turns their accesses
+// back into LDS instructions.
+template <typename RT>
+__device__ __noinline__ void serve_match(__attribute__((address_space(3))) MatchShared *Mp,
+                                         __attribute__((address_space(3))) TablesView *Tp,
+                                         __attribute__((address_space(3))) MatchOut *Op,
+                                         __attribute__((address_space(3))) ServeWork<RT> *Up, ServeSlot &S,
+                                         int64_t r) {
+    const MatchShared &M = *(const MatchShared *)Mp;
+    const TablesView &T = *(const TablesView *)Tp;
+    MatchOut &Ol = *(MatchOut *)Op;
+    ServeWork<RT> &U = *(ServeWork<RT> *)Up;
+    const int lane = threadIdx.x & 63;
+    // the frame's parameters in registers (the stages' stores cannot alias them)
+    const int64_t n = S.r.n, cells = S.cells;
+    const double *nbr_rel = S.r.nbr_rel;
+    const int32_t *nbr_id = S.r.nbr_id, *sid = S.r.sid;
+    const int8_t *species = S.r.species;
+    int32_t *code = S.r.code;
+    uint64_t *ord = S.r.ord;
+    int32_t *count = S.r.count, *knn_out = S.r.knn_out;
+    const uint32_t mask = S.r.mask, need = S.r.need;
+    const double cutoff = S.r.cutoff;
+    const int64_t b = r * SERVE_ATOMS, e = min(n, b + SERVE_ATOMS);
+    if (lane == 0) Ol = S.r.O;
+    int32_t *full_count = count + cells + 2;
+    unsigned long long *job_count = job_counter(count, cells);
+    for (int64_t sub = b; sub < e; sub += 64) {
+        const int64_t p = sub + lane;
+        __syncthreads();  // the previous sub-block's match LDS is free; Ol is written
+        if (p < e) topo_atom(U.topo, lane, p, n, nbr_rel, nbr_id, T, need, code, ord);
+        // the wave's code / ord writes before other lanes read them
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __syncthreads();
+        match_block<RT, 1>(M, T, Ol, U.mw, sub, n, nbr_rel, nbr_id, sid, species, T, code, ord, mask, cutoff, 0,
+                           Ol, full_count, job_count, nbr_id, knn_out);
+    }
+}
 
 // Stage ph, item r of the frame in slot S (the whole wave).  Returns the
 // stage's status for its last item (see serve_advance).
@@ -2988,50 +3062,29 @@ __device__ void serve_item(const MatchShared &M, const TablesView &Tl, MatchOut 
             R.sid[p] = (int32_t)i;
         }
     } else if (ph == PH_KNN) {
-        const int64_t b = r * SERVE_ATOMS, e = min(n, b + SERVE_ATOMS);
-        int32_t *box_fail = R.count + S.cells + 3;
-        for (int64_t sub = b; sub < e; sub += 64) {
-            const int64_t p = sub + lane;
-            bool ok = true;
-            if (p < e)
-                ok = S.fast && knn_fast_atom<KMAX>(p, n, S.g, R.sx, R.sy, R.sz, R.sid, R.count, R.nbr_id, R.nbr_rel,
-                                                   box_fail);
-            uint64_t left = __ballot(!ok);
-            while (left) {
-                const int l = __builtin_ctzll(left);
-                left &= left - 1;
-                knn_exact_atom<KMAX>(sub + l, n, S.g, R.sx, R.sy, R.sz, R.sid, R.count, R.nbr_id, R.nbr_rel,
-                                     box_fail);
-            }
-        }
+        serve_knn(S, r);
     } else {  // PH_MATCH
-        const int64_t b = r * SERVE_ATOMS, e = min(n, b + SERVE_ATOMS);
-        if (lane == 0) Ol = R.O;
-        int32_t *full_count = R.count + S.cells + 2;
-        unsigned long long *job_count = job_counter(R.count, S.cells);
-        for (int64_t sub = b; sub < e; sub += 64) {
-            const int64_t p = sub + lane;
-            __syncthreads();  // the previous sub-block's match LDS is free
-            if (p < e) topo_atom(U.topo, lane, p, n, R.nbr_rel, R.nbr_id, T, R.need, R.code, R.ord);
-            // the wave's code / ord writes before other lanes read them
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __syncthreads();
-            match_block<RT, 1>(M, Tl, Ol, U.mw, sub, n, R.nbr_rel, R.nbr_id, R.sid, R.species, T, R.code, R.ord,
-                               R.mask, R.cutoff, 0, R.O, full_count, job_count, R.nbr_id, R.knn_out);
-        }
+        serve_match<RT>((__attribute__((address_space(3))) MatchShared *)&M,
+                        (__attribute__((address_space(3))) TablesView *)&Tl,
+                        (__attribute__((address_space(3))) MatchOut *)&Ol,
+                        (__attribute__((address_space(3))) ServeWork<RT> *)&U, S, r);
     }
 }
 
-// One item of (slot, ph) is done: the last one of a stage queues the next
-// stage (or completes the frame).  Whole wave; one lane acts.
-__device__ inline void serve_advance(ServeDev *dev, ServeHost *host, int slot, int ph, unsigned long long gen) {
+// `count` items of (slot, ph) are done: the stage's last one queues the next
+// stage (or completes the frame).  Whole wave; one lane acts.  A wave counts
+// its items of one stage together, when it moves to another stage or runs
+// out of work: the release that makes its writes visible to the other XCDs
+// (a write-back of the L2) then happens once per stage, not per item.
+__device__ inline void serve_advance(ServeDev *dev, ServeHost *host, int slot, int ph, unsigned long long gen,
+                                     long long count) {
     const int lane = threadIdx.x & 63;
-    __threadfence();  // this item's writes before its count
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // these items' writes before their count
     if (lane != 0) return;
     ServeSlot &S = dev->slot[slot];
-    const long long d = __hip_atomic_fetch_add(&S.done[ph], 1ll, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    const long long d = __hip_atomic_fetch_add(&S.done[ph], count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + count;
     if (d != S.nr[ph]) return;
-    __threadfence();  // every item's writes of the stage
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every item's writes of the stage
     int next = ph + 1;
     if (ph == PH_GRID && S.bad) {
         serve_complete(host, slot, gen, SERVE_NONFINITE);
@@ -3113,6 +3166,11 @@ __global__ void __launch_bounds__(64, 2) k_serve(TablesView T, ServeDev *dev, Se
     if (lane == 0) Tl = T;
     load_templates(M, T);
     long long idle_from = wall_clock64();
+    int idle_rounds = 0;
+    // the stage of this wave's items not yet counted (see serve_advance)
+    int cur_slot = -1, cur_ph = 0;
+    unsigned long long cur_gen = 0;
+    long long pending = 0;
     for (;;) {
         int slot = -1, ph = 0;
         long long r = -1;
@@ -3128,24 +3186,25 @@ __global__ void __launch_bounds__(64, 2) k_serve(TablesView T, ServeDev *dev, Se
                 const int sl = (int)(e & 0xFFFF), p2 = (int)((e >> 16) & 0xFF);
                 const unsigned long long g2 = e >> 24;
                 ServeSlot &S = dev->slot[sl];
-                // claim the next item: a compare-and-swap on a counter that
-                // carries the frame's generation, so that an entry left over
-                // from the slot's previous frame never takes an item
-                unsigned long long v = __hip_atomic_load(&S.next[p2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                bool got = false;
-                while ((v >> 24) == g2 && (long long)(v & 0xFFFFFF) < S.nr[p2]) {
-                    if (__hip_atomic_compare_exchange_strong(&S.next[p2], &v, v + 1, __ATOMIC_ACQ_REL,
-                                                             __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
-                        got = true;
+                // claim the next item.  The counter carries the frame's
+                // generation: an entry left over from the slot's previous
+                // frame sees another generation and leaves it alone; a claim
+                // that races with the counter's reset for a new frame takes
+                // an item of that frame, and runs it as such (the generation
+                // comes from the counter).  Exhausted counters are not
+                // incremented, so the index stays within its bits.
+                const unsigned long long v = __hip_atomic_load(&S.next[p2], __ATOMIC_ACQUIRE,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                if ((v >> SERVE_IDX_BITS) == g2 && (long long)(v & SERVE_IDX_MASK) < S.nr[p2]) {
+                    const unsigned long long w = __hip_atomic_fetch_add(&S.next[p2], 1ull, __ATOMIC_ACQ_REL,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                    if ((long long)(w & SERVE_IDX_MASK) < S.nr[p2]) {
+                        slot = sl;
+                        ph = p2;
+                        r = (long long)(w & SERVE_IDX_MASK);
+                        gen = w >> SERVE_IDX_BITS;
                         break;
                     }
-                }
-                if (got) {
-                    slot = sl;
-                    ph = p2;
-                    r = (long long)(v & 0xFFFFFF);
-                    gen = g2;
-                    break;
                 }
                 // exhausted (or stale): the front entry leaves the queue
                 if (pos == hd && atomicCAS(&dev->head, hd, hd + 1) == hd) hd++;
@@ -3153,24 +3212,54 @@ __global__ void __launch_bounds__(64, 2) k_serve(TablesView T, ServeDev *dev, Se
         }
         slot = __shfl(slot, 0);
         if (slot < 0) {
-            if (serve_pull(dev, host)) {
-                idle_from = wall_clock64();
+            if (pending) {
+                // out of work: count what this wave did (it may finish a stage)
+                serve_advance(dev, host, cur_slot, cur_ph, cur_gen, pending);
+                __syncthreads();
+                pending = 0;
+                cur_slot = -1;
                 continue;
             }
-            const int stop = __hip_atomic_load(&host->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (stop || wall_clock64() - idle_from > idle_ticks) break;
-            __builtin_amdgcn_s_sleep(20);
+            // Idle.  Waves that find nothing back off (up to ~10 us between
+            // looks at the queue), only one wave in 16 looks for new frames
+            // in host memory, and the stop word (host memory too) is read
+            // every 32nd idle round: idle waves keep the queue's cache lines
+            // and the host link free for the working ones.
+            if ((blockIdx.x & 15) == (idle_rounds & 15) && serve_pull(dev, host)) {
+                idle_from = wall_clock64();
+                idle_rounds = 0;
+                continue;
+            }
+            idle_rounds++;
+            if ((idle_rounds & 31) == 0 &&
+                __hip_atomic_load(&host->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+                break;
+            if (wall_clock64() - idle_from > idle_ticks) break;
+            const int naps = idle_rounds < 6 ? (1 << idle_rounds) : 48;
+            for (int z = 0; z < naps; z++) __builtin_amdgcn_s_sleep(8);
             continue;
         }
+        idle_rounds = 0;
         ph = __shfl(ph, 0);
         r = __shfl(r, 0);
         gen = __shfl(gen, 0);
-        __threadfence();  // (acquire side: the stage's inputs)
+        if (slot != cur_slot || ph != cur_ph || gen != cur_gen) {
+            // a new stage for this wave: count the previous one's items, and
+            // see the new stage's inputs (an invalidation of the L2, once)
+            if (pending) serve_advance(dev, host, cur_slot, cur_ph, cur_gen, pending);
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            cur_slot = slot;
+            cur_ph = ph;
+            cur_gen = gen;
+            pending = 0;
+        }
         serve_item<RT>(M, Tl, Ol, U, T, dev->slot[slot], ph, r);
-        serve_advance(dev, host, slot, ph, gen);
+        pending++;
         __syncthreads();
         idle_from = wall_clock64();
     }
+    if (pending) serve_advance(dev, host, cur_slot, cur_ph, cur_gen, pending);
 }
 
 __global__ void k_wall_clock(long long *out) {

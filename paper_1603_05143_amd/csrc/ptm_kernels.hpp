@@ -93,10 +93,12 @@ __host__ __device__ inline unsigned long long *job_counter(int32_t *count, int64
 constexpr int SERVE_SLOTS = 256;              // frames in flight at most
 constexpr int SERVE_FIFO = 4096;              // device queue of (frame, stage) entries
 constexpr int SERVE_NPH = 9;                  // stages of a frame
-constexpr int64_t SERVE_ATOMS_LIGHT = 4096;   // atoms per item: bounds, counts, scatter
-constexpr int64_t SERVE_ATOMS = 256;          // atoms per item: k-NN, hulls + match (at most 2^24 items)
-constexpr int64_t SERVE_ZERO_CELLS = 65536;   // cells per item: zeroing
-constexpr int64_t SERVE_SCAN_CELLS = 16384;   // cells per item: scan
+// Items are small, so that a small frame's stage spreads over many waves
+// (a stage of one item is as slow as one wave); a stage holds at most 2^28.
+constexpr int64_t SERVE_ATOMS_LIGHT = 512;    // atoms per item: bounds, counts, scatter
+constexpr int64_t SERVE_ATOMS = 64;           // atoms per item: k-NN, hulls + match
+constexpr int64_t SERVE_ZERO_CELLS = 16384;   // cells per item: zeroing
+constexpr int64_t SERVE_SCAN_CELLS = 2048;    // cells per item: scan
 enum { SERVE_OK = 0, SERVE_BOX = 1, SERVE_NONFINITE = 2 };
 
 // One frame as the host hands it over: inputs, outputs and the frame's
@@ -118,7 +120,7 @@ struct ServeRequest {
     uint64_t *ord;
     double *part;   // [7][bounds items] per-item bounds
     int32_t *bsum;  // scan: per-item totals, then their exclusive prefix
-    uint64_t gen;   // ticket generation of the slot
+    uint64_t gen;   // ticket generation of the slot (below 2^36)
 };
 
 // Pinned host block shared by the host and the kernel.
@@ -138,7 +140,7 @@ struct ServeSlot {
     Grid g;
     int64_t cells;
     int32_t fast, bad;
-    unsigned long long next[SERVE_NPH];  // claim counters: generation << 24 | next item
+    unsigned long long next[SERVE_NPH];  // claim counters: generation << 28 | next item
     long long done[SERVE_NPH], nr[SERVE_NPH];
 };
 struct ServeDev {

@@ -360,7 +360,10 @@ static ptm_status persistent_submit(ptm_ctx *ctx, const double *positions, const
     ctx->inflight_bytes += T->footprint;
     T->slot = ctx->sv_free.back();
     ctx->sv_free.pop_back();
-    T->gen = ++ctx->sv_gen;
+    // generations count from 1 and stay below 2^36 (the claim counters'
+    // field); a wrap would take 6.9e10 frames
+    ctx->sv_gen = (ctx->sv_gen % ((1ull << 36) - 1)) + 1;
+    T->gen = ctx->sv_gen;
     const uint32_t m = T->job.mask;
     const ptm_outputs &o = T->job.out;
     const FrameScratch &S = T->scratch;
