@@ -1678,8 +1678,12 @@ __device__ inline void eval_candidate(int K, const T (&a)[NMAX][3], T Ga, const 
 // (cached) neighbour vectors instead of held in registers: covariance and
 // G_a / G_b in one pass, the residual in a second, each recomputing the
 // centred points from the barycentre cb (FP64, eq. 2).  K run-time, as in
-// eval_candidate.
-template <typename T>
+// eval_candidate.  Moments (FP64 only): the residual at (s, q) is also
+// G_b + s (s G_a - 2 rho), rho = sum_i a_i . R b_i = tr(R S^T); it is
+// stationary in q and s at the optimum, and its rounding error, a few ulps
+// of G_b ~ N, is at most 2e-13 in the RMSD once RMSD >= 0.01 (the
+// difference cancels below that, where the explicit second pass runs).
+template <typename T, bool Moments = false>
 __device__ inline void eval_streamed(int K, const double *__restrict__ nbr_rel, int64_t n, int64_t p,
                                      const double (&cb)[3], const TemplateGeom &D, uint64_t tv, CandEval<T> &out) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
@@ -1717,6 +1721,17 @@ __device__ inline void eval_streamed(int K, const double *__restrict__ nbr_rel, 
     T s = Ga > T(0) ? lam / Ga : T(0);
     T R[3][3];
     quat_rot<T>(out.q, R);
+    if constexpr (Moments && sizeof(T) == 8) {
+        T rho = 0;
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) rho += R[x][y] * S[y][x];
+        const T rm = Gb + s * (s * Ga - T(2) * rho);
+        if (rm >= T(1e-4) * T(K + 1)) {
+            out.r = sqrt(rm / T(K + 1));
+            out.s = s;
+            return;
+        }
+    }
     T res = 0;
     {
         const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
@@ -2070,7 +2085,8 @@ __device__ inline void wave_lds_sync() {
 template <typename RT>
 __device__ inline void eval_job(int K, const double *__restrict__ nbr_rel, int64_t n, int64_t p,
                                 const double (&cb)[3], const TemplateGeom &D, uint64_t tv, CandEval<RT> &ev) {
-    eval_streamed<RT>(K, nbr_rel, n, p, cb, D, tv, ev);
+    // (FP64: the residual from the moments where that is exact enough)
+    eval_streamed<RT, true>(K, nbr_rel, n, p, cb, D, tv, ev);
 }
 
 // The full rule of Alg. 1 for the wave's atom a (at p), in FP64, by the
@@ -2332,8 +2348,14 @@ __device__ void match_block(const MatchShared &M, const TablesView &Tl, const Ma
     double cbw[3] = {0, 0, 0};
     if (live) {
         full = arg_c >= 0 && (force_full || !(m2 > m1 + 1e-12));
-        if constexpr (sizeof(RT) == 4)
+        if constexpr (sizeof(RT) == 4) {
             if (arg_c >= 0) full = full || !(lo2 - (m1 + b1) > 1e-12) || fabs(m1 - cutoff) <= b1;
+        } else {
+            // RMSDs from the moments carry up to 2e-13 each: near ties and
+            // the cut-off get that much room (the full rule uses explicit
+            // residuals)
+            if (arg_c >= 0) full = full || !(m2 > m1 + 2e-12) || fabs(m1 - cutoff) <= 1e-12;
+        }
         if (!full) {
             if (arg_c < 0) {
                 write_none(O, sid[p]);
