@@ -508,13 +508,52 @@ def line_of(run):
             "stage_ms": {k: round(v, 4) for k, v in run["stage_ms"].items()}, "work_counts": run["info"]}
 
 
+def polycrystal_extras(args):
+    """The 0.92 M-atom polycrystal in both forms, with and without the
+    topological ordering and with every derived output; then the post-hoc
+    entry points."""
+    from paper_1603_05143_amd import ptm
+    extra = {}
+    poly = build_frame("polycrystal_919k")
+    p64 = run_gpu(poly, ptm.PTM_FP64, args.steps * 2, args.warmup)
+    p32 = run_gpu(poly, ptm.PTM_FP32_MIXED, args.steps * 2, args.warmup)
+    print(f"[bench] polycrystal fp64 {p64['ms_per_step']:.2f} fp32-mixed {p32['ms_per_step']:.2f} ms/step",
+          file=sys.stderr, flush=True)
+    # topological neighbour ordering (Sec. 3): the same frame, both forms;
+    # its Voronoi kernels run inside the k-NN stage
+    t64 = run_gpu(poly, ptm.PTM_FP64, args.steps * 2, args.warmup, ptm.PTM_F_TOPOLOGICAL)
+    t32 = run_gpu(poly, ptm.PTM_FP32_MIXED, args.steps * 2, args.warmup, ptm.PTM_F_TOPOLOGICAL)
+    print(f"[bench] topological fp32-mixed {t32['ms_per_step']:.2f} ms/step, fp64 {t64['ms_per_step']:.2f}",
+          file=sys.stderr, flush=True)
+    extra["polycrystal_919k"] = {
+        "workload": WORKLOADS["polycrystal_919k"][0], "n_atoms": poly.n,
+        "fp32_mixed": line_of(p32), "fp64": line_of(p64),
+        "fp32_mixed_over_fp64": p32["atoms_per_s"] / p64["atoms_per_s"],
+        "types": dict(zip(ptm.TYPE_NAMES, p32["types"])),
+        "topological": {
+            "fp32_mixed_atoms_per_s": t32["atoms_per_s"], "fp64_atoms_per_s": t64["atoms_per_s"],
+            "fp32_mixed_ms_per_step": round(t32["ms_per_step"], 4), "fp64_ms_per_step": round(t64["ms_per_step"], 4),
+            "fp32_mixed_stage_ms": {k: round(v, 4) for k, v in t32["stage_ms"].items()},
+            "cost_over_euclidean": round(t32["ms_per_step"] / p32["ms_per_step"], 3),
+            "types": dict(zip(ptm.TYPE_NAMES, t32["types"])),
+        },
+    }
+    derived_ms = derived_overhead(poly, args.steps * 2, args.warmup)
+    extra["polycrystal_919k"]["derived_outputs_ms_per_step"] = round(derived_ms, 4)
+    del poly
+    posthoc = posthoc_bench(1 << 27)
+    print(f"[bench] derived outputs {derived_ms:.2f} ms/step; post-hoc {posthoc}", file=sys.stderr, flush=True)
+    return extra["polycrystal_919k"], posthoc
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=("all", "headline", "fp64", "fp32"), default="all",
+    ap.add_argument("--only", choices=("all", "headline", "fp64", "fp32", "polycrystal"), default="all",
                     help="headline: the 31.7 M-atom frame alone (both forms, or one with fp64 / fp32); "
+                         "polycrystal: the 0.92 M-atom frame's lines and the post-hoc entry points alone; "
                          "for profiling runs")
     ap.add_argument("--cpu-sample", type=int, default=100000, help="atoms of the all-threads CPU sample")
     ap.add_argument("--cpu-sample-1t", type=int, default=6000, help="atoms of the one-thread CPU sample")
@@ -542,6 +581,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.only == "polycrystal":
+        poly_line, posthoc = polycrystal_extras(args)
+        print(json.dumps({"polycrystal_919k": poly_line, "posthoc": posthoc}))
+        return
 
     # ---- headline: the 31.7 M-atom frame, FP64 plain (value) and FP32-mixed
     head = "mixed_31.7m"
@@ -594,35 +638,7 @@ def main():
                                  "fp32_mixed_over_fp64": a32["atoms_per_s"] / a64["atoms_per_s"],
                                  "types": dict(zip(ptm.TYPE_NAMES, a32["types"]))}
     del alloy
-    poly = build_frame("polycrystal_919k")
-    p64 = run_gpu(poly, ptm.PTM_FP64, args.steps * 2, args.warmup)
-    p32 = run_gpu(poly, ptm.PTM_FP32_MIXED, args.steps * 2, args.warmup)
-    print(f"[bench] polycrystal fp64 {p64['ms_per_step']:.2f} fp32-mixed {p32['ms_per_step']:.2f} ms/step",
-          file=sys.stderr, flush=True)
-    # topological neighbour ordering (Sec. 3): the same frame, both forms;
-    # its Voronoi kernels run inside the k-NN stage
-    t64 = run_gpu(poly, ptm.PTM_FP64, args.steps * 2, args.warmup, ptm.PTM_F_TOPOLOGICAL)
-    t32 = run_gpu(poly, ptm.PTM_FP32_MIXED, args.steps * 2, args.warmup, ptm.PTM_F_TOPOLOGICAL)
-    print(f"[bench] topological fp32-mixed {t32['ms_per_step']:.2f} ms/step, fp64 {t64['ms_per_step']:.2f}",
-          file=sys.stderr, flush=True)
-    extra["polycrystal_919k"] = {
-        "workload": WORKLOADS["polycrystal_919k"][0], "n_atoms": poly.n,
-        "fp32_mixed": line_of(p32), "fp64": line_of(p64),
-        "fp32_mixed_over_fp64": p32["atoms_per_s"] / p64["atoms_per_s"],
-        "types": dict(zip(ptm.TYPE_NAMES, p32["types"])),
-        "topological": {
-            "fp32_mixed_atoms_per_s": t32["atoms_per_s"], "fp64_atoms_per_s": t64["atoms_per_s"],
-            "fp32_mixed_ms_per_step": round(t32["ms_per_step"], 4), "fp64_ms_per_step": round(t64["ms_per_step"], 4),
-            "fp32_mixed_stage_ms": {k: round(v, 4) for k, v in t32["stage_ms"].items()},
-            "cost_over_euclidean": round(t32["ms_per_step"] / p32["ms_per_step"], 3),
-            "types": dict(zip(ptm.TYPE_NAMES, t32["types"])),
-        },
-    }
-    derived_ms = derived_overhead(poly, args.steps * 2, args.warmup)
-    extra["polycrystal_919k"]["derived_outputs_ms_per_step"] = round(derived_ms, 4)
-    del poly
-    posthoc = posthoc_bench(1 << 27)
-    print(f"[bench] derived outputs {derived_ms:.2f} ms/step; post-hoc {posthoc}", file=sys.stderr, flush=True)
+    extra["polycrystal_919k"], posthoc = polycrystal_extras(args)
 
     serving = None
     if not args.no_serve:
