@@ -24,9 +24,10 @@ int ptm_selftest_det3(const double *p9);
 
 /* Key set of a triangulated sphere with k <= 14 vertices given as ntri
  * outward counter-clockwise triangles (int32 [ntri][3]): the start-edge
- * codes (k words each) of its start edges of minimum signature, in the
- * order the topology kernel scans them (the first is the one the kernel
- * looks up).  Writes up to max_codes codes to codes[max_codes][k] and their
+ * codes (k words each) of its start edges from vertices of minimum
+ * degree, u ascending, then counter-clockwise around u from its
+ * lowest-numbered neighbour (the first is the one the topology kernel looks
+ * up).  Writes up to max_codes codes to codes[max_codes][k] and their
  * number to *n_codes.  Isomorphic graphs have equal key sets and the first
  * code of a graph lies in the key set of exactly the graphs isomorphic to
  * it.  Returns 0, or -1 if the triangles are not a closed oriented

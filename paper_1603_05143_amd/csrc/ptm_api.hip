@@ -764,7 +764,7 @@ int ptm_selftest_codes(int k, const int32_t *tris, int ntri, uint64_t *codes, in
             nxt[a] |= (uint64_t)c << (4 * b);
             deg[a]++;
         }
-    auto darts = min_signature_darts(k, nxt, deg);
+    auto darts = min_degree_darts(k, nxt, deg);
     int m = 0;
     for (auto &d : darts) {
         if (m >= max_codes) break;

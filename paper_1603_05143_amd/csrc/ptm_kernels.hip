@@ -1338,12 +1338,13 @@ __device__ inline int lane_centre_inside(const Lane &L, int K, uint32_t &cv) {
     return 1;
 }
 
-// Start-edge code (definition in ptm_tables.cpp) of the first start edge
-// of minimum signature in scan order (u ascending over the minimum-degree
-// vertices, v counter-clockwise from u's lowest-numbered neighbour).
-// code[] receives the K words; the return value is the labelling (nibble
-// l = vertex of label l).  One code per hull: the tables hold every
-// minimum-signature start edge of every template triangulation.
+// Start-edge code (definition in ptm_tables.cpp) of the start edge u -> v
+// with u the lowest-numbered vertex of minimum degree and v its
+// lowest-numbered neighbour.  code[] receives the K words; the return value
+// is the labelling (nibble l = vertex of label l).  One code per hull: the
+// tables hold the codes of every start edge from a vertex of minimum degree
+// of every template triangulation, so the choice among them needs no
+// search.
 template <int K>
 __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64_t (&code)[K]) {
     int mindeg = 15;
@@ -1352,58 +1353,25 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
     uint32_t mdmask = 0;
 #pragma unroll
     for (int x = 0; x < K; x++) mdmask |= (uint32_t)(nib(degs, x) == (uint32_t)mindeg) << x;
-    uint64_t minsig = ~0ull;
-    int bu = 0, bv = 0;
-    // signature fields below the degree: mindeg nibbles from bit 56 down
-    const int low = 60 - 4 * mindeg;
-    const uint64_t field = (~0ull >> (4 + low)) << low;  // bits low .. 59
-    for (uint32_t m = mdmask; m; m &= m - 1) {
-        int u = __builtin_ctz(m);
-        uint64_t ntu = NT.get(u);
-        // lowest-numbered neighbour: first nibble of ntu that is not 0xF
-        uint64_t z = ~ntu;
-        z = (z | (z >> 1) | (z >> 2) | (z >> 3)) & 0x1111111111111111ull;
-        int v0 = __builtin_ctzll(z) >> 2;
-        // degrees of u's neighbours counter-clockwise from v0, first in the
-        // most significant field
-        uint64_t seq = 0;
-        int w = v0;
-        // the minimum degree of a triangulated sphere is 3, 4 or 5 (the
-        // mean is below 6), so the loops are unrolled to five predicated
-        // steps instead of a loop whose count differs between lanes
-#pragma unroll
-        for (int j = 0; j < 5; j++)
-            if (j < mindeg) {
-                seq |= (uint64_t)nib(degs, w) << (56 - 4 * j);
-                w = (int)nib(ntu, w);
-            }
-        int v = v0;
-#pragma unroll
-        for (int r = 0; r < 5; r++)
-            if (r < mindeg) {
-                uint64_t sig = ((uint64_t)mindeg << 60) | seq;
-                if (sig < minsig) {
-                    minsig = sig;
-                    bu = u;
-                    bv = v;
-                }
-                // next start: rotate the sequence by one neighbour
-                seq = ((seq << 4) & field) | ((seq >> 56) << low);
-                v = (int)nib(ntu, v);
-            }
-    }
-    code[0] = minsig;
-    uint64_t ntu = NT.get(bu);
-    // every nibble below is written once, from 0xF (lab) or 0 (ord, par), so
-    // a single XOR or OR sets it
+    const int bu = __builtin_ctz(mdmask);
+    const uint64_t ntu = NT.get(bu);
+    // lowest-numbered neighbour: first nibble of ntu that is not 0xF
+    uint64_t z = ~ntu;
+    z = (z | (z >> 1) | (z >> 2) | (z >> 3)) & 0x1111111111111111ull;
+    const int bv = __builtin_ctzll(z) >> 2;
+    // every nibble below is written once, from 0xF (lab) or 0 (ord, par, the
+    // signature), so a single XOR or OR sets it
     uint64_t lab = ~0ull ^ (0xFull << (4 * bu)), ord = (uint64_t)bu, par = 0;
+    uint64_t sig = (uint64_t)mindeg << 60;
     int y = bv;
     for (int j = 0; j < mindeg; j++) {
         lab ^= (uint64_t)(0xF ^ (j + 1)) << (4 * y);
         ord |= (uint64_t)y << (4 * (j + 1));
         par |= (uint64_t)bu << (4 * y);
+        sig |= (uint64_t)nib(degs, y) << (56 - 4 * j);
         y = (int)nib(ntu, y);
     }
+    code[0] = sig;
     uint32_t nl = mindeg + 1;
 #pragma unroll
     for (int i = 1; i < K; i++) {

@@ -206,12 +206,13 @@ std::vector<std::vector<int>> shell_faces(const std::vector<V3> &w) {
 //     top nibble, then the labels of its neighbours counter-clockwise from
 //     the vertex that labelled x, new vertices being labelled in that order.
 // The words determine the labelled rotation system.  A graph's key set is
-// the set of codes of its start edges of minimum signature; isomorphisms
-// map such start edges onto each other, so the code of any one of them is
-// found in the key set of every graph it is isomorphic to (and in no
-// other), and pairing the labellings of the two start edges gives the
-// isomorphism.  The tables hold the key sets of all template
-// triangulations; a hull needs the code of a single start edge.
+// the set of codes of its start edges from vertices of minimum degree;
+// isomorphisms preserve degrees and so map such start edges onto each
+// other, so the code of any one of them is found in the key set of every
+// graph it is isomorphic to (and in no other), and pairing the labellings
+// of the two start edges gives the isomorphism.  The tables hold the key
+// sets of all template triangulations; a hull needs the code of a single
+// start edge, which the kernel takes without a search.
 uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u, int v) {
     (void)k;
     uint64_t sig = ((uint64_t)deg[u] << 60) | ((uint64_t)deg[v] << 56);
@@ -258,25 +259,20 @@ void dart_code(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_
     *ordp = o;
 }
 
-// Start edges of minimum signature, in the order the kernel scans them:
-// u ascending, then v counter-clockwise around u from its lowest-numbered
-// neighbour.  The first one is the start edge the kernel uses.
-std::vector<std::pair<int, int>> min_signature_darts(int k, const uint64_t *nxt, const int *deg) {
-    uint64_t minsig = ~0ull;
+// Start edges from the vertices of minimum degree: u ascending, then v
+// counter-clockwise around u from its lowest-numbered neighbour.  The first
+// one is the start edge the kernel uses.
+std::vector<std::pair<int, int>> min_degree_darts(int k, const uint64_t *nxt, const int *deg) {
+    int mindeg = KMAX;
+    for (int u = 0; u < k; u++) mindeg = std::min(mindeg, deg[u]);
     std::vector<std::pair<int, int>> out;
     for (int u = 0; u < k; u++) {
+        if (deg[u] != mindeg) continue;
         int v0 = 0;
         while (v0 < k && ((nxt[u] >> (4 * v0)) & 0xF) == 0xF) v0++;
         if (v0 >= k) continue;
         int v = v0;
-        for (int r = 0; r < deg[u]; r++, v = (int)((nxt[u] >> (4 * v)) & 0xF)) {
-            uint64_t sg = dart_signature(k, nxt, deg, u, v);
-            if (sg < minsig) {
-                minsig = sg;
-                out.clear();
-            }
-            if (sg == minsig) out.push_back({u, v});
-        }
+        for (int r = 0; r < deg[u]; r++, v = (int)((nxt[u] >> (4 * v)) & 0xF)) out.push_back({u, v});
     }
     return out;
 }
@@ -374,7 +370,7 @@ bool build_tables(HostTables &T, std::string &err) {
                     nxt[a] |= (uint64_t)cc << (4 * bb);
                     deg[a]++;
                 }
-            for (auto &d : min_signature_darts(k, nxt, deg)) {
+            for (auto &d : min_degree_darts(k, nxt, deg)) {
                 uint64_t rows[KMAX], perm;
                 dart_code(k, nxt, deg, d.first, d.second, rows, &perm);
                 std::vector<uint64_t> key(rows, rows + k);

@@ -87,6 +87,6 @@ bool build_tables(HostTables &T, std::string &err);
 // self-check entry points.
 uint64_t dart_signature(int k, const uint64_t *nxt, const int *deg, int u, int v);
 void dart_code(int k, const uint64_t *nxt, const int *deg, int u, int v, uint64_t *rows, uint64_t *ordp);
-std::vector<std::pair<int, int>> min_signature_darts(int k, const uint64_t *nxt, const int *deg);
+std::vector<std::pair<int, int>> min_degree_darts(int k, const uint64_t *nxt, const int *deg);
 
 } // namespace ptm
