@@ -60,6 +60,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime under the soname the library
+        # links against.  Loaded after torch, the library binds to torch's
+        # copy, so device pointers and streams from torch are valid in it;
+        # loaded first, torch would bring a second runtime into the process
+        # and the library's calls would fail.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.ptm_create.argtypes = [C.POINTER(ptm_config), C.POINTER(vp)]

@@ -54,6 +54,14 @@ def test_template_info_matches_paper(ptm):
         ptm.ptm_template_info(5)
 
 
+def test_binding_loads_after_torch(ptm):
+    """torch ships a HIP runtime under the library's soname: the binding
+    imports torch before loading the library, so both share one runtime."""
+    import sys
+    ptm.lib()
+    assert "torch" in sys.modules
+
+
 def test_status_strings_and_errors_without_device(ptm):
     for s in range(8):
         assert ptm.ptm_status_string(s)
