@@ -366,11 +366,13 @@ template <>
 struct RealTraits<double> {
     static constexpr double newton_tol = 1e-15;
     static constexpr double jacobi_off = 1e-36;
+    static constexpr double polar_step = 1e-8;
 };
 template <>
 struct RealTraits<float> {
     static constexpr float newton_tol = 2e-7f;
     static constexpr float jacobi_off = 1e-14f;
+    static constexpr float polar_step = 2e-4f;
 };
 
 // Largest eigenvalue and eigenvector of Horn's matrix for S_xy = sum b_x a_y
@@ -589,15 +591,62 @@ __host__ __device__ inline void strain_inputs(const TemplateDev &D, uint64_t tv,
 }
 
 // Sec. 8: the symmetric factor P of the left polar decomposition A = P U,
-// U orthogonal and right-handed, from At = A^T l.  A A^T = X S^2 X^T
-// (cyclic Jacobi) and P = X diag(s) X^T, where the smallest singular value
-// takes the sign of det A: then det P has the sign of det A and U = P^-1 A
-// is a proper rotation (for det A > 0, P = (A A^T)^(1/2)).
+// U orthogonal and right-handed, from At = A^T l.  For det A > 0, U is the
+// limit of Newton's iteration X <- (X + X^-T) / 2 from X = A (quadratic
+// convergence: a step of size e leaves an error of about e^2 / 2, so the
+// iteration stops after a step below polar_step, with X then exact to the
+// working precision) and P = A U^T, symmetrised.  Otherwise, or if the iteration has not settled
+// after 12 steps: A A^T = X S^2 X^T (cyclic Jacobi) and P = X diag(s) X^T,
+// where the smallest singular value takes the sign of det A: then det P has
+// the sign of det A and U = P^-1 A is a proper rotation (for det A > 0,
+// P = (A A^T)^(1/2) in both branches).
 template <typename RT>
 __host__ __device__ inline void polar_p(const RT (&At)[3][3], RT l, RT (&P)[3][3]) {
     // products and sums may fuse into FMAs here (one rounding instead of two; no
     // result depends on a particular rounding)
 #pragma clang fp contract(fast)
+    RT A[3][3];
+    for (int x = 0; x < 3; x++)
+        for (int y = 0; y < 3; y++) A[x][y] = At[y][x] / l;
+    const RT detA = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                    A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                    A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (detA > RT(0)) {
+        RT X[3][3];
+        for (int x = 0; x < 3; x++)
+            for (int y = 0; y < 3; y++) X[x][y] = A[x][y];
+        bool settled = false;
+        for (int it = 0; it < 12 && !settled; it++) {
+            // X^-T = cofactor matrix / det X
+            const RT C[3][3] = {{X[1][1] * X[2][2] - X[1][2] * X[2][1], X[1][2] * X[2][0] - X[1][0] * X[2][2],
+                                 X[1][0] * X[2][1] - X[1][1] * X[2][0]},
+                                {X[0][2] * X[2][1] - X[0][1] * X[2][2], X[0][0] * X[2][2] - X[0][2] * X[2][0],
+                                 X[0][1] * X[2][0] - X[0][0] * X[2][1]},
+                                {X[0][1] * X[1][2] - X[0][2] * X[1][1], X[0][2] * X[1][0] - X[0][0] * X[1][2],
+                                 X[0][0] * X[1][1] - X[0][1] * X[1][0]}};
+            const RT inv = RT(1) / (X[0][0] * C[0][0] + X[0][1] * C[0][1] + X[0][2] * C[0][2]);
+            RT step = 0;
+            for (int x = 0; x < 3; x++)
+                for (int y = 0; y < 3; y++) {
+                    const RT xn = RT(0.5) * (X[x][y] + C[x][y] * inv);
+                    step = fmax(step, fabs(xn - X[x][y]));
+                    X[x][y] = xn;
+                }
+            settled = step <= RealTraits<RT>::polar_step;
+        }
+        if (settled) {
+            RT Q[3][3];
+            for (int x = 0; x < 3; x++)
+                for (int y = 0; y < 3; y++) {
+                    RT s = 0;
+                    for (int m = 0; m < 3; m++) s += A[x][m] * X[y][m];
+                    Q[x][y] = s;
+                }
+            for (int x = 0; x < 3; x++)
+                for (int y = 0; y < 3; y++) P[x][y] = RT(0.5) * (Q[x][y] + Q[y][x]);
+            return;
+        }
+    }
     RT AA[3][3];
     for (int x = 0; x < 3; x++)
         for (int y = 0; y < 3; y++) {
