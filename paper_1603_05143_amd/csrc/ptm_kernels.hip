@@ -1469,15 +1469,18 @@ __device__ __attribute__((always_inline)) inline void topo_atom(TopoShared &S, i
     uint64_t ordw[NGRP] = {0, 0, 0};
     if (want) {
         const int kl = (want & 4) ? 14 : ((want & 2) ? 12 : 6);  // last point to insert
-        double m64 = 0;  // largest coordinate (FP64) and of its stored form
+        // The first six points go to LDS first: their loads were issued
+        // first, so the 6-point hull is built while the others arrive.  The
+        // filter bounds come from the largest coordinate (FP64, and of its
+        // stored form) of the points inserted so far, which bounds every
+        // predicate on them.
+        double m64 = 0;
         float m32 = 0;
-        for (int r = 0; r < KMAX; r++)
+        for (int r = 0; r < 6; r++)
             for (int d = 0; d < 3; d++) {
                 S.P[d][r][t] = (float)x[r][d];
-                if (r < kl) {
-                    m64 = fmax(m64, fabs(x[r][d]));
-                    m32 = fmaxf(m32, fabsf((float)x[r][d]));
-                }
+                m64 = fmax(m64, fabs(x[r][d]));
+                m32 = fmaxf(m32, fabsf((float)x[r][d]));
             }
         Lane L{S, t, nbr_rel, n, p, f32_orient_bound(m32), f32_det3_bound(m32), f64_orient_bound(m64),
                f64_det3_bound(m64)};
@@ -1488,12 +1491,27 @@ __device__ __attribute__((always_inline)) inline void topo_atom(TopoShared &S, i
         uint64_t c6[6] = {}, c12[12] = {}, c14[14] = {}, h[NGRP] = {0, 0, 0};
         bool pend[NGRP] = {false, false, false};
         uint32_t cv = 0;  // facet slots whose centre test passed
-        for (int q = 4; q < kl; q++) {
+        bool ok = lane_insert(L, 4, cv) && lane_insert(L, 5, cv);
+        if (ok && (want & 1))
+            if ((pend[0] = lane_centre_inside(L, 6, cv))) h[0] = lane_code<6>(S.F, nt, c6, ordw[0]);
+        // the other points (rows past the last wanted one are stored but
+        // never read)
+        for (int r = 6; r < KMAX; r++)
+            for (int d = 0; d < 3; d++) {
+                S.P[d][r][t] = (float)x[r][d];
+                if (r < kl) {
+                    m64 = fmax(m64, fabs(x[r][d]));
+                    m32 = fmaxf(m32, fabsf((float)x[r][d]));
+                }
+            }
+        L.bo = f32_orient_bound(m32);
+        L.bd = f32_det3_bound(m32);
+        L.bo64 = f64_orient_bound(m64);
+        L.bd64 = f64_det3_bound(m64);
+        for (int q = 6; ok && q < kl; q++) {
             if (!lane_insert(L, q, cv)) break;
             const int K = q + 1;
-            if (K == 6 && (want & 1)) {
-                if ((pend[0] = lane_centre_inside(L, 6, cv))) h[0] = lane_code<6>(S.F, nt, c6, ordw[0]);
-            } else if (K == 12 && (want & 2)) {
+            if (K == 12 && (want & 2)) {
                 if ((pend[1] = lane_centre_inside(L, 12, cv))) h[1] = lane_code<12>(S.F, nt, c12, ordw[1]);
             } else if (K == 14) {
                 if ((pend[2] = lane_centre_inside(L, 14, cv))) h[2] = lane_code<14>(S.F, nt14, c14, ordw[2]);
