@@ -1783,8 +1783,8 @@ __device__ inline uint64_t rank_of_tv(uint64_t perm, uint64_t ord, int k) {
 // Outputs of the winning candidate from its superposition ev and the
 // strain inputs A^T (sum over points of V+ columns times centred points, in
 // template order) and l (mean point norm).
-template <int K, typename RT>
-__device__ inline void finish_outputs(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
+template <typename RT>
+__device__ inline void finish_outputs(int K, const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
                                       const CandEval<RT> &ev, RT l, const RT (&At)[3][3], RT resid, double cutoff,
                                       int64_t p, int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
                                       const int8_t *__restrict__ species, const MatchOut &O) {
@@ -1885,7 +1885,8 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
             const int8_t me = species[i];
             uint32_t cnt = 0;  // 8-bit counters: FCC groups 0..2, BCC inner/outer
 #pragma unroll
-            for (int r = 0; r < K; r++) {
+            for (int r = 0; r < KMAX; r++) {
+                if (r >= K) break;
                 int32_t j = nbr_id[(int64_t)r * n + p];
                 int other = species[j] != me;
                 int tvx = (int)nib(tv, r);
@@ -1915,8 +1916,8 @@ __device__ inline void finish_outputs(const MatchShared &M, const TablesView &T,
 // Outputs of the winning candidate from its superposition ev (r, q, s):
 // the strain inputs are gathered from the points in one pass (the
 // barycentre cb is known); the optional eq.(6) residual takes a second.
-template <int K, typename RT>
-__device__ inline void finish(const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
+template <typename RT>
+__device__ inline void finish(int K, const MatchShared &M, const TablesView &T, int grp, int c, uint64_t ord,
                               const CandEval<RT> &ev, const double (&cb)[3], const double *__restrict__ nbr_rel,
                               double cutoff, int64_t p, int64_t n, int32_t i, const int32_t *__restrict__ nbr_id,
                               const int8_t *__restrict__ species, const MatchOut &O) {
@@ -1929,7 +1930,8 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
     RT a0[3], At[3][3], l;
     strain_begin<RT>(D, cb, a0, At, l);
 #pragma unroll
-    for (int rr = 0; rr < K; rr++) {
+    for (int rr = 0; rr < KMAX; rr++) {
+        if (rr >= K) break;
         RT ar[3];
         for (int d = 0; d < 3; d++) ar[d] = (RT)(nbr_rel[((int64_t)rr * 3 + d) * n + p] - cb[d]);
         strain_add<RT>(D, (int)nib(tv, rr) + 1, ar, At, l);
@@ -1953,7 +1955,7 @@ __device__ inline void finish(const MatchShared &M, const TablesView &T, int grp
         }
         resid /= l * l;
     }
-    finish_outputs<K, RT>(M, T, grp, c, ord, ev, l, At, resid, cutoff, p, n, i, nbr_id, species, O);
+    finish_outputs<RT>(K, M, T, grp, c, ord, ev, l, At, resid, cutoff, p, n, i, nbr_id, species, O);
 }
 
 __device__ inline void write_none(const MatchOut &O, int32_t i) {
@@ -2011,12 +2013,13 @@ __device__ inline void load_templates(MatchShared &M, const TablesView &T) {
 //     next chunk;
 //  C. an atom whose decision the common rule cannot take (a near tie, an
 //     FP32 margin that the error bounds do not clear) is decided by the
-//     full rule in FP64 by the whole wave; the other winners are regrouped
-//     by hull size across the block and finished with lane = atom.
+//     full rule in FP64 by the whole wave; every other lane finishes its
+//     own winner (the hull size is a run-time value there too, so a wave
+//     mixing sizes runs one code path).
 // Nothing per candidate leaves the chip: the neighbour vectors are read
 // once per atom in A and again from the caches by the jobs and the finish.
 
-// LDS of one wave during A and B
+// LDS of one wave
 template <typename RT>
 struct MatchWaveLds {
     double cb[NGRP][3][64];  // barycentre of each hull group of the wave's atoms
@@ -2029,23 +2032,10 @@ struct MatchWaveLds {
     float d2[64];            // FP32 form: excess bound (f32_excess_bound),
     int32_t cand[64];        // candidate index in the group's list
 };
-// LDS of the block's regrouped winners (C), NB slots
-template <typename RT, int NB>
-struct MatchRegroupLds {
-    double r[NB];
-    double cb[3][NB];
-    RT qs[5][NB];
-    int32_t p[NB], c[NB];
-    int8_t g[NB];
-};
 // working LDS of a block of NW waves
 template <typename RT, int NW>
 struct MatchWork {
-    int32_t cnt[NW][NGRP];
-    union {
-        MatchWaveLds<RT> w[NW];
-        MatchRegroupLds<RT, NW * 64> g;
-    } u;
+    MatchWaveLds<RT> w[NW];
 };
 template <typename RT, int NW>
 struct MatchLds {
@@ -2157,10 +2147,10 @@ __device__ __noinline__ void full_rule(const MatchShared &M, const TablesView &T
     for (int k = 0; k < 4; k++) we.q[k] = __shfl(ev.q[k], bl);
     if (lane == 0) {
         const double cb[3] = {cbw[wg][0][a], cbw[wg][1][a], cbw[wg][2][a]};
-        if (wg == 0) finish<6, double>(M, T, 0, wc, ord[0], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        if (wg == 0) finish<double>(6, M, T, 0, wc, ord[0], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
         else if (wg == 1)
-            finish<12, double>(M, T, 1, wc, ord[1], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
-        else finish<14, double>(M, T, 2, wc, ord[2], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+            finish<double>(12, M, T, 1, wc, ord[1], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
+        else finish<double>(14, M, T, 2, wc, ord[2], we, cb, nbr_rel, cutoff, p, n, i, nbr_id, species, O);
     }
 }
 
@@ -2199,7 +2189,7 @@ __device__ void match_block(const MatchShared &M, const TablesView &Tl, const Ma
                             unsigned long long *__restrict__ job_count, const int32_t *__restrict__ knn_src,
                             int32_t *__restrict__ knn_out) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    MatchWaveLds<RT> &W = Wk.u.w[wv];
+    MatchWaveLds<RT> &W = Wk.w[wv];
     const int64_t wbase = first + (int64_t)wv * 64;
     const int64_t p = wbase + lane;
     const bool live = p < n;
@@ -2359,55 +2349,15 @@ __device__ void match_block(const MatchShared &M, const TablesView &Tl, const Ma
         full_rule(M, Tl, n, wbase + a, a, W.cb, nbr_rel, nbr_id, sid, species, code, ords, mask, cutoff, Ol);
     }
 
-    // Consecutive atoms in cell order span many grains, so a wave's winners
-    // mix the three hull sizes and each size's finishing code would run in
-    // turn.  The block's winners are regrouped by size (12, 14, then 6
-    // points; ballots give each lane its slot) and every lane finishes the
-    // winner in its slot: waves then mostly run one size's code.
-    uint64_t bal[NGRP];
-#pragma unroll
-    for (int k = 0; k < NGRP; k++) bal[k] = __ballot(cls == k);
-    if (lane == 0)
-        for (int k = 0; k < NGRP; k++) Wk.cnt[wv][k] = __popcll(bal[k]);
-    __syncthreads();  // every wave is done with its LDS of A and B
-    constexpr int order[NGRP] = {1, 2, 0};
-    int total = 0, base = 0;
-#pragma unroll
-    for (int j = 0; j < NGRP; j++) {
-        const int k = order[j];
-        int tk = 0, before = 0;
-        for (int w2 = 0; w2 < NW; w2++) {
-            tk += Wk.cnt[w2][k];
-            if (w2 < wv) before += Wk.cnt[w2][k];
-        }
-        if (k == cls) base = total + before + __popcll(bal[k] & ((1ull << lane) - 1));
-        total += tk;
-    }
-    MatchRegroupLds<RT, NW * 64> &R = Wk.u.g;
+    // every lane finishes its own winner, whatever its hull size
     if (cls >= 0) {
-        R.p[base] = (int32_t)p;
-        R.c[base] = arg_c;
-        R.g[base] = (int8_t)cls;
-        R.r[base] = m1;
-        for (int e = 0; e < 4; e++) R.qs[e][base] = wq[e];
-        R.qs[4][base] = ws;
-        for (int d = 0; d < 3; d++) R.cb[d][base] = cbw[d];
-    }
-    __syncthreads();
-    const int u = threadIdx.x;
-    if (u < total) {
-        const int64_t pw = R.p[u];
-        const int gw = R.g[u], cw = R.c[u];
-        const int32_t iw = sid[pw];
-        const uint64_t ord = ords[(int64_t)gw * n + pw];
+        const int32_t iw = sid[p];
+        const uint64_t ord = ords[(int64_t)cls * n + p];
         CandEval<RT> ev;
-        ev.r = (RT)R.r[u];
-        for (int e = 0; e < 4; e++) ev.q[e] = R.qs[e][u];
-        ev.s = R.qs[4][u];
-        const double cb[3] = {R.cb[0][u], R.cb[1][u], R.cb[2][u]};
-        if (gw == 0) finish<6, RT>(M, T, 0, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
-        else if (gw == 1) finish<12, RT>(M, T, 1, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
-        else finish<14, RT>(M, T, 2, cw, ord, ev, cb, nbr_rel, cutoff, pw, n, iw, nbr_id, species, O);
+        ev.r = (RT)m1;
+        for (int e = 0; e < 4; e++) ev.q[e] = wq[e];
+        ev.s = ws;
+        finish<RT>(group_k(cls), M, T, cls, arg_c, ord, ev, cbw, nbr_rel, cutoff, p, n, iw, nbr_id, species, O);
     }
 }
 
