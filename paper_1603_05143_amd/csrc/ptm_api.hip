@@ -33,7 +33,7 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
     // count (+ the frame's counters and the box flag), start
     b += align_up(4 * (size_t)(cells + FRAME_COUNTERS)) * 2;
-    b += align_up(8 * (size_t)n) * 3;         // sorted positions
+    b += align_up(24 * (size_t)n);           // sorted positions
     b += align_up(4 * (size_t)n * KMAX);      // neighbour ids
     b += align_up(8 * (size_t)n * KMAX * 3);  // neighbour vectors
     b += align_up(4 * (size_t)n * NGRP);      // code ids
@@ -87,9 +87,7 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     sid = (int32_t *)take(4 * (size_t)n);
     count = (int32_t *)take(4 * (size_t)(cells + FRAME_COUNTERS));
     start = (int32_t *)take(4 * (size_t)(cells + FRAME_COUNTERS));
-    sx = (double *)take(8 * (size_t)n);
-    sy = (double *)take(8 * (size_t)n);
-    sz = (double *)take(8 * (size_t)n);
+    spos = (double *)take(24 * (size_t)n);
     nbr_id = (int32_t *)take(4 * (size_t)n * KMAX);
     nbr_rel = (double *)take(8 * (size_t)n * KMAX * 3);
     code = (int32_t *)take(4 * (size_t)n * NGRP);
@@ -200,16 +198,16 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
     size_t tmp = S.scan_tmp_bytes;
     PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
-    launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.sx, S.sy, S.sz, S.sid, st);
+    launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.spos, S.sid, st);
     if ((ps = mark(PTM_STAGE_KNN)) != PTM_OK) return ps;
     // slot_of is free once the atoms are scattered: it holds the leftover list
     if (J.topo) {
         // the 18 Euclidean neighbours, then their topological order (Sec. 3)
-        launch_knn(n, g, VK, S.sx, S.sy, S.sz, S.sid, S.start, S.id18, S.rel18, S.slot_of, S.count + cells + 1,
+        launch_knn(n, g, VK, S.spos, S.sid, S.start, S.id18, S.rel18, S.slot_of, S.count + cells + 1,
                    S.count + cells + 3, st);
         launch_voronoi(n, S.rel18, S.id18, S.vf, S.vlive, S.nbr_rel, S.nbr_id, box_fail, st);
     } else {
-        launch_knn(n, g, KMAX, S.sx, S.sy, S.sz, S.sid, S.start, S.nbr_id, S.nbr_rel, S.slot_of, S.count + cells + 1,
+        launch_knn(n, g, KMAX, S.spos, S.sid, S.start, S.nbr_id, S.nbr_rel, S.slot_of, S.count + cells + 1,
                    S.count + cells + 3, st);
     }
     if ((ps = mark(PTM_STAGE_TOPO)) != PTM_OK) return ps;

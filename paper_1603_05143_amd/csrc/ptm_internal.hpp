@@ -29,7 +29,7 @@ struct FrameScratch {
     size_t bytes = 0;
     bool pooled = false;  // a serving-pool buffer of a fixed size class
     int32_t *cell_of = nullptr, *slot_of = nullptr, *sid = nullptr, *count = nullptr, *start = nullptr;
-    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    double *spos = nullptr;  // sorted positions, x y z of each atom together
     int32_t *nbr_id = nullptr;
     double *nbr_rel = nullptr;
     int32_t *id18 = nullptr;    // topological ordering: the 18 Euclidean neighbours

@@ -106,14 +106,14 @@ __global__ void k_bin_count(const double *__restrict__ pos, int64_t n, Grid g, i
 
 __global__ void k_bin_scatter(const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ cell_of,
                               const int32_t *__restrict__ slot_of, const int32_t *__restrict__ start,
-                              double *__restrict__ sx, double *__restrict__ sy, double *__restrict__ sz,
+                              double *__restrict__ spos,
                               int32_t *__restrict__ sid) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t p = (int64_t)start[cell_of[i]] + slot_of[i];
-    sx[p] = pos[3 * i + 0];
-    sy[p] = pos[3 * i + 1];
-    sz[p] = pos[3 * i + 2];
+    spos[3 * (int64_t)(p)] = pos[3 * i + 0];
+    spos[3 * (int64_t)(p) + 1] = pos[3 * i + 1];
+    spos[3 * (int64_t)(p) + 2] = pos[3 * i + 2];
     sid[p] = (int32_t)i;
 }
 
@@ -166,17 +166,16 @@ __device__ inline void shell_range(const Grid &g, int a, int s, int &lo, int &hi
 // scan the atoms of cell c into the top-K list
 template <int KN>
 __device__ inline void scan_cell(int c, const Grid &g, double xi, double yi, double zi, int32_t i,
-                                 const double *__restrict__ sx, const double *__restrict__ sy,
-                                 const double *__restrict__ sz, const int32_t *__restrict__ sid,
+                                 const double *__restrict__ spos, const int32_t *__restrict__ sid,
                                  const int32_t *__restrict__ start, double (&kd)[KN], int32_t (&kj)[KN],
                                  int32_t (&kq)[KN], int &found) {
     int q1 = start[c + 1];
     for (int q = start[c]; q < q1; q++) {
         int32_t j = sid[q];
         if (j == i) continue;
-        double dx = min_image(sx[q] - xi, g, 0);
-        double dy = min_image(sy[q] - yi, g, 1);
-        double dz = min_image(sz[q] - zi, g, 2);
+        double dx = min_image(spos[3 * (int64_t)(q)] - xi, g, 0);
+        double dy = min_image(spos[3 * (int64_t)(q) + 1] - yi, g, 1);
+        double dz = min_image(spos[3 * (int64_t)(q) + 2] - zi, g, 2);
         double xx = dx * dx, yy = dy * dy, zz = dz * dz;
         double d2 = (xx + yy) + zz;
         found++;
@@ -225,11 +224,10 @@ __device__ inline bool shell_exceeds_box(const Grid &g, int cnt, int K, double k
 
 // Write the K nearest neighbours of sorted atom p: ids and
 // minimum-image vectors in the component-major layout the hull kernels read.
-// sx[q] is a copy of pos[3 sid[q]], so the vectors are those of the input.
+// spos[3q .. 3q+2] is a copy of pos[3 sid[q] ..], so the vectors are those of the input.
 template <int KN>
 __device__ inline void write_knn(int64_t n, int64_t p, int cnt, const int32_t (&kq)[KN], const Grid &g,
-                                 double xi, double yi, double zi, const double *__restrict__ sx,
-                                 const double *__restrict__ sy, const double *__restrict__ sz,
+                                 double xi, double yi, double zi, const double *__restrict__ spos,
                                  const int32_t *__restrict__ sid, int32_t *__restrict__ nbr_id,
                                  double *__restrict__ nbr_rel) {
 #pragma unroll
@@ -239,9 +237,9 @@ __device__ inline void write_knn(int64_t n, int64_t p, int cnt, const int32_t (&
         if (m < cnt) {
             int32_t q = kq[m];
             j = sid[q];
-            r0 = min_image(sx[q] - xi, g, 0);
-            r1 = min_image(sy[q] - yi, g, 1);
-            r2 = min_image(sz[q] - zi, g, 2);
+            r0 = min_image(spos[3 * (int64_t)(q)] - xi, g, 0);
+            r1 = min_image(spos[3 * (int64_t)(q) + 1] - yi, g, 1);
+            r2 = min_image(spos[3 * (int64_t)(q) + 2] - zi, g, 2);
         }
         nbr_id[(int64_t)m * n + p] = j;
         nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
@@ -308,13 +306,12 @@ inline int64_t xcd_pad(int64_t nblocks) { return (nblocks + NXCD - 1) / NXCD * N
 // the boundary.  One atom (lane); false: not certified, nothing written
 // (the exact search must take it).
 template <int NK>
-__device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const double *__restrict__ sx,
-                                     const double *__restrict__ sy, const double *__restrict__ sz,
+__device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const double *__restrict__ spos,
                                      const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                      int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                      int32_t *__restrict__ box_fail) {
     constexpr int KN = NK + 1;
-    const double xi = sx[p], yi = sy[p], zi = sz[p];
+    const double xi = spos[3 * (int64_t)(p)], yi = spos[3 * (int64_t)(p) + 1], zi = spos[3 * (int64_t)(p) + 2];
     const double xs[3] = {xi, yi, zi};
     int cc[3];
     double u[3];
@@ -428,8 +425,8 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
         if (q < qend) {
             const bool two = q + 1 < qend;
             const int q2 = two ? q + 1 : q;  // (a repeated, in-bounds load when there is no second)
-            const double ax = sx[q], ay = sy[q], az = sz[q];
-            const double bx = sx[q2], by = sy[q2], bz = sz[q2];
+            const double ax = spos[3 * (int64_t)(q)], ay = spos[3 * (int64_t)(q) + 1], az = spos[3 * (int64_t)(q) + 2];
+            const double bx = spos[3 * (int64_t)(q2)], by = spos[3 * (int64_t)(q2) + 1], bz = spos[3 * (int64_t)(q2) + 2];
             double dx, dy, dz, ex, ey, ez;
             if (shifted) {
                 dx = (ax - xi) - shx;
@@ -467,9 +464,9 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
     for (int m = 0; m < NK; m++) kq[m] = key_q(key[m]);
     if (ok) {
         int32_t q13 = kq[NK - 1];
-        double ex = min_image(sx[q13] - xi, g, 0);
-        double ey = min_image(sy[q13] - yi, g, 1);
-        double ez = min_image(sz[q13] - zi, g, 2);
+        double ex = min_image(spos[3 * (int64_t)(q13)] - xi, g, 0);
+        double ey = min_image(spos[3 * (int64_t)(q13) + 1] - yi, g, 1);
+        double ez = min_image(spos[3 * (int64_t)(q13) + 2] - zi, g, 2);
         double kth = (ex * ex + ey * ey) + ez * ez;
         int lo[3] = {-2, -2, -2}, hi[3] = {2, 2, 2};
         bool all;
@@ -477,20 +474,19 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
         if (ok && shell_exceeds_box(g, NK, NK, kth)) atomicOr(box_fail, 1);
     }
     if (!ok) return false;
-    write_knn<NK>(n, p, NK, kq, g, xi, yi, zi, sx, sy, sz, sid, nbr_id, nbr_rel);
+    write_knn<NK>(n, p, NK, kq, g, xi, yi, zi, spos, sid, nbr_id, nbr_rel);
     return true;
 }
 
 template <int NK>
-__global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ sx,
-                                                  const double *__restrict__ sy, const double *__restrict__ sz,
+__global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const double *__restrict__ spos,
                                                   const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                                   int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                                   int32_t *__restrict__ todo, int32_t *__restrict__ todo_count,
                                                   int32_t *__restrict__ box_fail) {
     int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    if (!knn_fast_atom<NK>(p, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail))
+    if (!knn_fast_atom<NK>(p, n, g, spos, sid, start, nbr_id, nbr_rel, box_fail))
         todo[atomicAdd(todo_count, 1)] = (int32_t)p;
 }
 
@@ -503,15 +499,14 @@ __global__ void __launch_bounds__(256) k_knn_fast(int64_t n, Grid g, const doubl
 // latency of a few left-over atoms short: each lane scans one or two cells.
 // One atom p (wave-uniform) by the whole wave.
 template <int NK>
-__device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double *__restrict__ sx,
-                               const double *__restrict__ sy, const double *__restrict__ sz,
+__device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double *__restrict__ spos,
                                const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                int32_t *__restrict__ box_fail) {
     constexpr int KN = NK;
     const int lane = threadIdx.x & 63;
     {
-        const double xi = sx[p], yi = sy[p], zi = sz[p];
+        const double xi = spos[3 * (int64_t)(p)], yi = spos[3 * (int64_t)(p) + 1], zi = spos[3 * (int64_t)(p) + 2];
         const int32_t i = sid[p];
         const double xs[3] = {xi, yi, zi};
         int cc[3];
@@ -552,7 +547,7 @@ __device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double
                 else if (cy < 0 || cy >= g.nc[1]) continue;
                 if (g.periodic[2]) cz = (cz % g.nc[2] + g.nc[2]) % g.nc[2];
                 else if (cz < 0 || cz >= g.nc[2]) continue;
-                scan_cell<KN>((cz * g.nc[1] + cy) * g.nc[0] + cx, g, xi, yi, zi, i, sx, sy, sz, sid, start, kd, kj,
+                scan_cell<KN>((cz * g.nc[1] + cy) * g.nc[0] + cx, g, xi, yi, zi, i, spos, sid, start, kd, kj,
                               kq, found);
             }
             // wave-wide merge of the list heads, smallest (d^2, id) first
@@ -602,9 +597,9 @@ __device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double
             int32_t j = lane < cnt ? rj : -1;
             double r0 = 0, r1 = 0, r2 = 0;
             if (lane < cnt) {
-                r0 = min_image(sx[rq] - xi, g, 0);
-                r1 = min_image(sy[rq] - yi, g, 1);
-                r2 = min_image(sz[rq] - zi, g, 2);
+                r0 = min_image(spos[3 * (int64_t)(rq)] - xi, g, 0);
+                r1 = min_image(spos[3 * (int64_t)(rq) + 1] - yi, g, 1);
+                r2 = min_image(spos[3 * (int64_t)(rq) + 2] - zi, g, 2);
             }
             nbr_id[(int64_t)lane * n + p] = j;
             nbr_rel[((int64_t)lane * 3 + 0) * n + p] = r0;
@@ -615,8 +610,7 @@ __device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double
 }
 
 template <int NK>
-__global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const double *__restrict__ sx,
-                                                   const double *__restrict__ sy, const double *__restrict__ sz,
+__global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const double *__restrict__ spos,
                                                    const int32_t *__restrict__ sid, const int32_t *__restrict__ start,
                                                    int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                                    const int32_t *__restrict__ todo,
@@ -625,7 +619,7 @@ __global__ void __launch_bounds__(256) k_knn_exact(int64_t n, Grid g, const doub
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t cnt_todo = todo ? (int64_t)*todo_count : n;
     for (int64_t w = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); w < cnt_todo; w += nwaves)
-        knn_exact_atom<NK>(todo ? (int64_t)todo[w] : w, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail);
+        knn_exact_atom<NK>(todo ? (int64_t)todo[w] : w, n, g, spos, sid, start, nbr_id, nbr_rel, box_fail);
 }
 
 // ------------------------------------------------- topological ordering
@@ -2646,9 +2640,9 @@ void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell
                        count);
 }
 void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
-                        const int32_t *start, double *sx, double *sy, double *sz, int32_t *sid, hipStream_t st) {
+                        const int32_t *start, double *spos, int32_t *sid, hipStream_t st) {
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, cell_of, slot_of,
-                       start, sx, sy, sz, sid);
+                       start, spos, sid);
 }
 bool knn_fast_applies(const Grid &g) {
     for (int a = 0; a < 3; a++)
@@ -2656,31 +2650,31 @@ bool knn_fast_applies(const Grid &g) {
     return true;
 }
 template <int NK>
-static void launch_knn_nk(int64_t n, const Grid &g, const double *sx, const double *sy, const double *sz,
+static void launch_knn_nk(int64_t n, const Grid &g, const double *spos,
                           const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel,
                           int32_t *todo, int32_t *todo_count, int32_t *box_fail, hipStream_t st) {
     int64_t blocks = (n + 255) / 256;
     if (knn_fast_applies(g)) {
-        hipLaunchKernelGGL(k_knn_fast<NK>, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, sx, sy, sz, sid,
+        hipLaunchKernelGGL(k_knn_fast<NK>, dim3((unsigned)xcd_pad(blocks)), dim3(256), 0, st, n, g, spos, sid,
                            start, nbr_id, nbr_rel, todo, todo_count, box_fail);
         // the atoms left over are few; 512 blocks of four waves (two per SIMD,
         // what its registers allow) stride over them
         hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>(blocks, 512)), dim3(256), 0, st, n, g,
-                           sx, sy, sz, sid, start, nbr_id, nbr_rel, (const int32_t *)todo,
+                           spos, sid, start, nbr_id, nbr_rel, (const int32_t *)todo,
                            (const int32_t *)todo_count, box_fail);
     } else {
         hipLaunchKernelGGL(k_knn_exact<NK>, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 16384)), dim3(256), 0, st, n,
-                           g, sx, sy, sz, sid, start, nbr_id, nbr_rel, (const int32_t *)nullptr,
+                           g, spos, sid, start, nbr_id, nbr_rel, (const int32_t *)nullptr,
                            (const int32_t *)nullptr, box_fail);
     }
 }
-void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double *sy, const double *sz,
+void launch_knn(int64_t n, const Grid &g, int nk, const double *spos,
                 const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *todo,
                 int32_t *todo_count, int32_t *box_fail, hipStream_t st) {
     if (nk == VK)
-        launch_knn_nk<VK>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, todo, todo_count, box_fail, st);
+        launch_knn_nk<VK>(n, g, spos, sid, start, nbr_id, nbr_rel, todo, todo_count, box_fail, st);
     else
-        launch_knn_nk<KMAX>(n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, todo, todo_count, box_fail, st);
+        launch_knn_nk<KMAX>(n, g, spos, sid, start, nbr_id, nbr_rel, todo, todo_count, box_fail, st);
 }
 void launch_voronoi(int64_t n, const double *rel18, const int32_t *id18, uint32_t *vf, uint32_t *vlive,
                     double *nbr_rel, int32_t *nbr_id, const int32_t *box_fail, hipStream_t st) {
@@ -2834,7 +2828,7 @@ __device__ __noinline__ void serve_knn(ServeSlot &S, int64_t r) {
     const Grid g = S.g;
     const int64_t n = S.r.n;
     const bool fast = S.fast;
-    const double *sx = S.r.sx, *sy = S.r.sy, *sz = S.r.sz;
+    const double *spos = S.r.spos;
     const int32_t *sid = S.r.sid, *start = S.r.count;
     int32_t *nbr_id = S.r.nbr_id;
     double *nbr_rel = S.r.nbr_rel;
@@ -2843,12 +2837,12 @@ __device__ __noinline__ void serve_knn(ServeSlot &S, int64_t r) {
     for (int64_t sub = b; sub < e; sub += 64) {
         const int64_t p = sub + lane;
         bool ok = true;
-        if (p < e) ok = fast && knn_fast_atom<KMAX>(p, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail);
+        if (p < e) ok = fast && knn_fast_atom<KMAX>(p, n, g, spos, sid, start, nbr_id, nbr_rel, box_fail);
         uint64_t left = __ballot(!ok);
         while (left) {
             const int l = __builtin_ctzll(left);
             left &= left - 1;
-            knn_exact_atom<KMAX>(sub + l, n, g, sx, sy, sz, sid, start, nbr_id, nbr_rel, box_fail);
+            knn_exact_atom<KMAX>(sub + l, n, g, spos, sid, start, nbr_id, nbr_rel, box_fail);
         }
     }
 }
@@ -3014,9 +3008,9 @@ __device__ void serve_item(const MatchShared &M, const TablesView &Tl, MatchOut 
         for (int64_t i = b + lane; i < e; i += 64) {
             const int32_t c = R.cell_of[i];
             const int64_t p = (int64_t)R.start[c] + R.bsum[c / SERVE_SCAN_CELLS] + R.slot_of[i];
-            R.sx[p] = R.pos[3 * i + 0];
-            R.sy[p] = R.pos[3 * i + 1];
-            R.sz[p] = R.pos[3 * i + 2];
+            R.spos[3 * (int64_t)(p)] = R.pos[3 * i + 0];
+            R.spos[3 * (int64_t)(p) + 1] = R.pos[3 * i + 1];
+            R.spos[3 * (int64_t)(p) + 2] = R.pos[3 * i + 2];
             R.sid[p] = (int32_t)i;
         }
     } else if (ph == PH_KNN) {

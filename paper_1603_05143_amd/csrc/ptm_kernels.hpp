@@ -42,7 +42,7 @@ void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipS
 void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
                       int32_t *count, hipStream_t st);
 void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
-                        const int32_t *start, double *sx, double *sy, double *sz, int32_t *sid, hipStream_t st);
+                        const int32_t *start, double *spos, int32_t *sid, hipStream_t st);
 // k-NN: fast block search, then the exact shell search for the atoms it
 // leaves in todo (n entries) / *todo_count (zeroed by the caller).
 bool knn_fast_applies(const Grid &g);
@@ -51,7 +51,7 @@ bool knn_fast_applies(const Grid &g);
 // (zeroed by the caller) is set when the frame has a periodic axis and some
 // atom's nk-th neighbour is not strictly closer than half a periodic length
 // (or it has fewer than nk neighbours); every later stage then does nothing.
-void launch_knn(int64_t n, const Grid &g, int nk, const double *sx, const double *sy, const double *sz,
+void launch_knn(int64_t n, const Grid &g, int nk, const double *spos,
                 const int32_t *sid, const int32_t *start, int32_t *nbr_id, double *nbr_rel, int32_t *todo,
                 int32_t *todo_count, int32_t *box_fail, hipStream_t st);
 // topological order (Sec. 3) of the 18 neighbours in rel18 / id18: the first
@@ -113,7 +113,7 @@ struct ServeRequest {
     MatchOut O;
     int32_t *knn_out;
     int32_t *cell_of, *slot_of, *sid, *count, *start;
-    double *sx, *sy, *sz;
+    double *spos;
     int32_t *nbr_id;
     double *nbr_rel;
     int32_t *code;

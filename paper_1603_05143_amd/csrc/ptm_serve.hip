@@ -384,9 +384,7 @@ static ptm_status persistent_submit(ptm_ctx *ctx, const double *positions, const
     R.sid = S.sid;
     R.count = S.count;
     R.start = S.start;
-    R.sx = S.sx;
-    R.sy = S.sy;
-    R.sz = S.sz;
+    R.spos = S.spos;
     R.nbr_id = S.nbr_id;
     R.nbr_rel = S.nbr_rel;
     R.code = S.code;
