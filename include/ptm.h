@@ -121,7 +121,10 @@ typedef struct {
 
 /* Per-atom outputs, n entries each (arrays with a second dimension are
  * row-major [n][m]).  Every pointer except type may be NULL to skip it
- * (type too when n == 0). */
+ * (type too when n == 0).  Device outputs (contexts without
+ * PTM_F_HOST_POINTERS): quat and quat_fz 16-byte aligned, neighbours
+ * 8-byte aligned (records are written as 16- and 8-byte pairs; any HIP or
+ * PyTorch allocation is), else PTM_E_INVALID. */
 typedef struct {
     int8_t *type;        /* PTM_TYPE_*: best template if its RMSD <= rmsd_cutoff, else NONE      */
     int8_t *alloy;       /* PTM_ALLOY_*; NONE when species == NULL or type not FCC/BCC            */

@@ -287,6 +287,12 @@ ptm_status validate(ptm_ctx *ctx, const double *positions, const double *box, in
         ctx->err = "rmsd_cutoff is NaN";
         return PTM_E_INVALID;
     }
+    // the match kernel writes these records as 16- and 8-byte pairs
+    if (!(ctx->flags & PTM_F_HOST_POINTERS) &&
+        (((uintptr_t)out->quat & 15) || ((uintptr_t)out->quat_fz & 15) || ((uintptr_t)out->neighbours & 7))) {
+        ctx->err = "device outputs: quat and quat_fz must be 16-byte aligned, neighbours 8-byte aligned";
+        return PTM_E_INVALID;
+    }
     return PTM_OK;
 }
 

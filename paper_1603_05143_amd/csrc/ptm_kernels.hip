@@ -111,9 +111,9 @@ __global__ void k_bin_scatter(const double *__restrict__ pos, int64_t n, const i
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t p = (int64_t)start[cell_of[i]] + slot_of[i];
-    spos[3 * (int64_t)(p)] = pos[3 * i + 0];
-    spos[3 * (int64_t)(p) + 1] = pos[3 * i + 1];
-    spos[3 * (int64_t)(p) + 2] = pos[3 * i + 2];
+    spos[3 * (int64_t)p] = pos[3 * i + 0];
+    spos[3 * (int64_t)p + 1] = pos[3 * i + 1];
+    spos[3 * (int64_t)p + 2] = pos[3 * i + 2];
     sid[p] = (int32_t)i;
 }
 
@@ -173,9 +173,9 @@ __device__ inline void scan_cell(int c, const Grid &g, double xi, double yi, dou
     for (int q = start[c]; q < q1; q++) {
         int32_t j = sid[q];
         if (j == i) continue;
-        double dx = min_image(spos[3 * (int64_t)(q)] - xi, g, 0);
-        double dy = min_image(spos[3 * (int64_t)(q) + 1] - yi, g, 1);
-        double dz = min_image(spos[3 * (int64_t)(q) + 2] - zi, g, 2);
+        double dx = min_image(spos[3 * (int64_t)q] - xi, g, 0);
+        double dy = min_image(spos[3 * (int64_t)q + 1] - yi, g, 1);
+        double dz = min_image(spos[3 * (int64_t)q + 2] - zi, g, 2);
         double xx = dx * dx, yy = dy * dy, zz = dz * dz;
         double d2 = (xx + yy) + zz;
         found++;
@@ -237,9 +237,9 @@ __device__ inline void write_knn(int64_t n, int64_t p, int cnt, const int32_t (&
         if (m < cnt) {
             int32_t q = kq[m];
             j = sid[q];
-            r0 = min_image(spos[3 * (int64_t)(q)] - xi, g, 0);
-            r1 = min_image(spos[3 * (int64_t)(q) + 1] - yi, g, 1);
-            r2 = min_image(spos[3 * (int64_t)(q) + 2] - zi, g, 2);
+            r0 = min_image(spos[3 * (int64_t)q] - xi, g, 0);
+            r1 = min_image(spos[3 * (int64_t)q + 1] - yi, g, 1);
+            r2 = min_image(spos[3 * (int64_t)q + 2] - zi, g, 2);
         }
         nbr_id[(int64_t)m * n + p] = j;
         nbr_rel[((int64_t)m * 3 + 0) * n + p] = r0;
@@ -311,7 +311,7 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
                                      int32_t *__restrict__ nbr_id, double *__restrict__ nbr_rel,
                                      int32_t *__restrict__ box_fail) {
     constexpr int KN = NK + 1;
-    const double xi = spos[3 * (int64_t)(p)], yi = spos[3 * (int64_t)(p) + 1], zi = spos[3 * (int64_t)(p) + 2];
+    const double xi = spos[3 * (int64_t)p], yi = spos[3 * (int64_t)p + 1], zi = spos[3 * (int64_t)p + 2];
     const double xs[3] = {xi, yi, zi};
     int cc[3];
     double u[3];
@@ -425,8 +425,8 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
         if (q < qend) {
             const bool two = q + 1 < qend;
             const int q2 = two ? q + 1 : q;  // (a repeated, in-bounds load when there is no second)
-            const double ax = spos[3 * (int64_t)(q)], ay = spos[3 * (int64_t)(q) + 1], az = spos[3 * (int64_t)(q) + 2];
-            const double bx = spos[3 * (int64_t)(q2)], by = spos[3 * (int64_t)(q2) + 1], bz = spos[3 * (int64_t)(q2) + 2];
+            const double ax = spos[3 * (int64_t)q], ay = spos[3 * (int64_t)q + 1], az = spos[3 * (int64_t)q + 2];
+            const double bx = spos[3 * (int64_t)q2], by = spos[3 * (int64_t)q2 + 1], bz = spos[3 * (int64_t)q2 + 2];
             double dx, dy, dz, ex, ey, ez;
             if (shifted) {
                 dx = (ax - xi) - shx;
@@ -463,15 +463,20 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
 #pragma unroll
     for (int m = 0; m < NK; m++) kq[m] = key_q(key[m]);
     if (ok) {
-        int32_t q13 = kq[NK - 1];
-        double ex = min_image(spos[3 * (int64_t)(q13)] - xi, g, 0);
-        double ey = min_image(spos[3 * (int64_t)(q13) + 1] - yi, g, 1);
-        double ez = min_image(spos[3 * (int64_t)(q13) + 2] - zi, g, 2);
-        double kth = (ex * ex + ey * ey) + ez * ez;
+        // certified on the key's upper bound of the K-th distance, so the
+        // K-th neighbour's position is read only when the box check needs
+        // the exact distance
+        const double kth_up = key_d2_upper(key[NK - 1]);
         int lo[3] = {-2, -2, -2}, hi[3] = {2, 2, 2};
         bool all;
-        ok = certified(g, cc, u, lo, hi, NK, NK, kth, all);
-        if (ok && shell_exceeds_box(g, NK, NK, kth)) atomicOr(box_fail, 1);
+        ok = certified(g, cc, u, lo, hi, NK, NK, kth_up, all);
+        if (ok && shell_exceeds_box(g, NK, NK, kth_up)) {
+            const int32_t q13 = kq[NK - 1];
+            const double ex = min_image(spos[3 * (int64_t)q13] - xi, g, 0);
+            const double ey = min_image(spos[3 * (int64_t)q13 + 1] - yi, g, 1);
+            const double ez = min_image(spos[3 * (int64_t)q13 + 2] - zi, g, 2);
+            if (shell_exceeds_box(g, NK, NK, (ex * ex + ey * ey) + ez * ez)) atomicOr(box_fail, 1);
+        }
     }
     if (!ok) return false;
     write_knn<NK>(n, p, NK, kq, g, xi, yi, zi, spos, sid, nbr_id, nbr_rel);
@@ -506,7 +511,7 @@ __device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double
     constexpr int KN = NK;
     const int lane = threadIdx.x & 63;
     {
-        const double xi = spos[3 * (int64_t)(p)], yi = spos[3 * (int64_t)(p) + 1], zi = spos[3 * (int64_t)(p) + 2];
+        const double xi = spos[3 * (int64_t)p], yi = spos[3 * (int64_t)p + 1], zi = spos[3 * (int64_t)p + 2];
         const int32_t i = sid[p];
         const double xs[3] = {xi, yi, zi};
         int cc[3];
@@ -597,9 +602,9 @@ __device__ void knn_exact_atom(int64_t p, int64_t n, const Grid &g, const double
             int32_t j = lane < cnt ? rj : -1;
             double r0 = 0, r1 = 0, r2 = 0;
             if (lane < cnt) {
-                r0 = min_image(spos[3 * (int64_t)(rq)] - xi, g, 0);
-                r1 = min_image(spos[3 * (int64_t)(rq) + 1] - yi, g, 1);
-                r2 = min_image(spos[3 * (int64_t)(rq) + 2] - zi, g, 2);
+                r0 = min_image(spos[3 * (int64_t)rq] - xi, g, 0);
+                r1 = min_image(spos[3 * (int64_t)rq + 1] - yi, g, 1);
+                r2 = min_image(spos[3 * (int64_t)rq + 2] - zi, g, 2);
             }
             nbr_id[(int64_t)lane * n + p] = j;
             nbr_rel[((int64_t)lane * 3 + 0) * n + p] = r0;
@@ -1810,8 +1815,12 @@ __device__ inline void finish_outputs(int K, const MatchShared &M, const TablesV
         O.type[i] = (int8_t)type;
         if (O.rmsd) O.rmsd[i] = (double)ev.r;
         if (O.scale) O.scale[i] = (double)ev.s;
-        if (O.quat)
-            for (int k = 0; k < 4; k++) O.quat[4 * (int64_t)i + k] = (double)(q[k] * sc);
+        if (O.quat) {
+            // records as 16-byte pairs (the arrays are 16-byte aligned)
+            double2 *qo = reinterpret_cast<double2 *>(O.quat + 4 * (int64_t)i);
+            qo[0] = make_double2((double)(q[0] * sc), (double)(q[1] * sc));
+            qo[1] = make_double2((double)(q[2] * sc), (double)(q[3] * sc));
+        }
         if (O.quat_fz) {
             // Sec. 7: of the equivalent orientations q' x conj(q_h), the one
             // closest to the identity (largest |w|; the first on ties)
@@ -1837,7 +1846,9 @@ __device__ inline void finish_outputs(int K, const MatchShared &M, const TablesV
                         sg = best[k] < RT(0) ? RT(-1) : RT(1);
                         break;
                     }
-            for (int k = 0; k < 4; k++) O.quat_fz[4 * (int64_t)i + k] = (double)(sg * best[k]);
+            double2 *qo = reinterpret_cast<double2 *>(O.quat_fz + 4 * (int64_t)i);
+            qo[0] = make_double2((double)(sg * best[0]), (double)(sg * best[1]));
+            qo[1] = make_double2((double)(sg * best[2]), (double)(sg * best[3]));
         }
         if (O.nn_distance) {
             // hydrostatic part (Sec. 8): template vertex 0 lies at |b_1| in eq.(4) units
@@ -1847,6 +1858,7 @@ __device__ inline void finish_outputs(int K, const MatchShared &M, const TablesV
         if (O.strain_residual) O.strain_residual[i] = (double)resid;
     }
     if (O.neighbours) {
+        int32_t ids[KMAX];
 #pragma unroll
         for (int m = 0; m < KMAX; m++) {
             int32_t id = -1;
@@ -1854,8 +1866,12 @@ __device__ inline void finish_outputs(int K, const MatchShared &M, const TablesV
                 int rank = (int)((rep >> (4 * (15 - m))) & 0xF);
                 id = nbr_id[(int64_t)rank * n + p];
             }
-            O.neighbours[(int64_t)i * KMAX + m] = id;
+            ids[m] = id;
         }
+        // as 8-byte pairs (the array is 8-byte aligned)
+        int2 *no = reinterpret_cast<int2 *>(O.neighbours + (int64_t)i * KMAX);
+#pragma unroll
+        for (int m = 0; m < KMAX / 2; m++) no[m] = make_int2(ids[2 * m], ids[2 * m + 1]);
     }
     if (O.strain || O.vm_strain) {
         // Sec. 8: P of A = P U with U right-handed
@@ -3008,9 +3024,9 @@ __device__ void serve_item(const MatchShared &M, const TablesView &Tl, MatchOut 
         for (int64_t i = b + lane; i < e; i += 64) {
             const int32_t c = R.cell_of[i];
             const int64_t p = (int64_t)R.start[c] + R.bsum[c / SERVE_SCAN_CELLS] + R.slot_of[i];
-            R.spos[3 * (int64_t)(p)] = R.pos[3 * i + 0];
-            R.spos[3 * (int64_t)(p) + 1] = R.pos[3 * i + 1];
-            R.spos[3 * (int64_t)(p) + 2] = R.pos[3 * i + 2];
+            R.spos[3 * (int64_t)p] = R.pos[3 * i + 0];
+            R.spos[3 * (int64_t)p + 1] = R.pos[3 * i + 1];
+            R.spos[3 * (int64_t)p + 2] = R.pos[3 * i + 2];
             R.sid[p] = (int32_t)i;
         }
     } else if (ph == PH_KNN) {

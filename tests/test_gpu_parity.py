@@ -341,6 +341,30 @@ def test_deterministic_and_translation_invariant(torch_cuda, clf):
         assert np.array_equal(a[k], c[k]), k
 
 
+def test_misaligned_device_outputs_refused(torch_cuda, clf):
+    """quat / quat_fz records are written as 16-byte pairs and neighbours as
+    8-byte pairs: device arrays that are not aligned for that are refused
+    before any work, and aligned views of the same buffers are accepted."""
+    torch = torch_cuda
+    f = S.polycrystal(L=30.0, n_grains=3, sigma=0.1, seed=16)
+    pos = torch.from_numpy(f.positions).to("cuda:0")
+    n = f.n
+    ref = clf.classify(pos, f.box, derived=True)
+    torch.cuda.synchronize()
+    for key, width, dtype in (("quat", 4, torch.float64), ("quat_fz", 4, torch.float64),
+                              ("neighbours", 14, torch.int32)):
+        flat = torch.empty(n * width + 2, dtype=dtype, device="cuda:0")
+        out = ptm.Classifier.alloc_outputs(n, "cuda:0", derived=True)
+        out[key] = flat[1:1 + n * width].view(n, width)  # one element past an aligned base
+        with pytest.raises(ptm.PTMError) as e:
+            clf.classify(pos, f.box, out=out, derived=True)
+        assert e.value.status == ptm.PTM_E_INVALID, key
+        out[key] = flat[2:2 + n * width].view(n, width) if dtype == torch.int32 else flat[:n * width].view(n, width)
+        got = clf.classify(pos, f.box, out=out, derived=True)
+        torch.cuda.synchronize()
+        assert torch.equal(got[key].cpu(), ref[key].cpu()), key
+
+
 def test_host_pointer_context(torch_cuda, oracle_lib):
     import ctypes as C
     f = S.config0()
