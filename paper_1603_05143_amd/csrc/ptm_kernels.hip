@@ -1419,6 +1419,43 @@ __device__ uint64_t lane_code(const uint32_t (*F)[TB], const RotSys &NT, uint64_
     return code_hash(best, K);
 }
 
+// The 6-point hull: the only template triangulation of six points is the
+// SC octahedron, and a triangulated sphere of six vertices is the
+// octahedron exactly when every vertex has degree 4; the tables hold its one
+// start-edge code (code 0 of the group; they refuse to build otherwise).  So
+// the hull either is the octahedron -- code 0, with the labelling of the
+// start edge from vertex 0 to its lowest-numbered neighbour read off the
+// rotation around vertex 0: that neighbour, the next three counter-clockwise,
+// then the one vertex not adjacent to 0 -- or has no candidate.  Only vertex
+// 0's row of the rotation system is needed, built in a register.
+__device__ inline bool lane_octahedron(const uint32_t (*F)[TB], int t, uint64_t &ordw) {
+    uint64_t degs = 0, row = 0;  // row 0, complemented (0 = no neighbour)
+#pragma unroll
+    for (int f = 0; f < 8; f++) {
+        const uint32_t w = F[f][t];
+        const int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
+        degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
+        if (a == 0) row |= (uint64_t)(c ^ 0xF) << (4 * b);
+        if (b == 0) row |= (uint64_t)(a ^ 0xF) << (4 * c);
+        if (c == 0) row |= (uint64_t)(b ^ 0xF) << (4 * a);
+    }
+    if (degs != 0x444444ull) return false;
+    const uint64_t nt0 = ~row;
+    uint64_t z = row;
+    z = (z | (z >> 1) | (z >> 2) | (z >> 3)) & 0x1111111111111111ull;
+    int y = __builtin_ctzll(z) >> 2;  // lowest-numbered neighbour of 0
+    uint64_t ord = 0;
+    int sum = 0;
+#pragma unroll
+    for (int j = 1; j <= 4; j++) {
+        ord |= (uint64_t)y << (4 * j);
+        sum += y;
+        y = (int)nib(nt0, y);
+    }
+    ordw = ord | ((uint64_t)(15 - sum) << 20);  // the vertices 0..5 sum to 15
+    return true;
+}
+
 // code row c of group grp equals best (all K words compared)
 template <int K>
 __device__ inline bool row_equal(const TablesView &T, int grp, int32_t c, const uint64_t (&best)[K]) {
@@ -1487,12 +1524,12 @@ __device__ __attribute__((always_inline)) inline void topo_atom(TopoShared &S, i
         const RotSys nt{S.NT, t};
         const RotSys nt14{reinterpret_cast<uint64_t (*)[TB]>(&S.P[0][0][0]), t};
         // codes of the valid hulls, probed together after the last insertion
-        uint64_t c6[6] = {}, c12[12] = {}, c14[14] = {}, h[NGRP] = {0, 0, 0};
+        uint64_t c12[12] = {}, c14[14] = {}, h[NGRP] = {0, 0, 0};
         bool pend[NGRP] = {false, false, false};
         uint32_t cv = 0;  // facet slots whose centre test passed
         bool ok = lane_insert(L, 4, cv) && lane_insert(L, 5, cv);
         if (ok && (want & 1))
-            if ((pend[0] = lane_centre_inside(L, 6, cv))) h[0] = lane_code<6>(S.F, nt, c6, ordw[0]);
+            pend[0] = lane_centre_inside(L, 6, cv) && lane_octahedron(S.F, t, ordw[0]);
         // the other points (rows past the last wanted one are stored but
         // never read)
         for (int r = 6; r < KMAX; r++)
@@ -1516,20 +1553,19 @@ __device__ __attribute__((always_inline)) inline void topo_atom(TopoShared &S, i
                 if ((pend[2] = lane_centre_inside(L, 14, cv))) h[2] = lane_code<14>(S.F, nt14, c14, ordw[2]);
             }
         }
-        // first slots of the three probes
+        cid[0] = pend[0] ? 0 : -1;  // the octahedron's code
+        // first slots of the other two probes
         int sl[NGRP];
         int32_t c[NGRP];
-        for (int g = 0; g < NGRP; g++) {
+        for (int g = 1; g < NGRP; g++) {
             sl[g] = (int)(h[g] & (uint64_t)T.hmask[g]);
             c[g] = pend[g] ? T.slots[g][sl[g]] : -1;
         }
         // every group has a code row 0 (the tables refuse to build
-        // otherwise): it stands in for a missing hit, so the three rows load
+        // otherwise): it stands in for a missing hit, so the rows load
         // unconditionally, before any comparison waits
-        const bool hit0 = row_equal<6>(T, 0, max(c[0], 0), c6) & (c[0] >= 0);
         const bool hit1 = row_equal<12>(T, 1, max(c[1], 0), c12) & (c[1] >= 0);
         const bool hit2 = row_equal<14>(T, 2, max(c[2], 0), c14) & (c[2] >= 0);
-        cid[0] = probe_rest<6>(T, 0, c6, sl[0], c[0], hit0);
         cid[1] = probe_rest<12>(T, 1, c12, sl[1], c[1], hit1);
         cid[2] = probe_rest<14>(T, 2, c14, sl[2], c[2], hit2);
     }

@@ -413,6 +413,10 @@ bool build_tables(HostTables &T, std::string &err) {
             err = "template tables: no code for hull size " + std::to_string(k);
             return false;
         }
+        if (g == 0 && nc != 1) {  // the hull kernel takes the octahedron's code as code 0
+            err = "template tables: more than one code for six points";
+            return false;
+        }
         T.ncodes[g] = nc;
         int size = 16;
         while (size < 4 * nc) size <<= 1;
