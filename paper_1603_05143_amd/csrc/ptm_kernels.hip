@@ -4,7 +4,8 @@
 //   k_bounds          finite check + bounding box (open axes)
 //   k_bin_count       cell id + per-cell counter (counting sort, pass 1)
 //   (scan)            exclusive prefix sum of the counters
-//   k_bin_scatter     sorted SoA copy of the positions (counting sort, pass 2)
+//   k_bin_scatter     sorted copy of the positions, x y z of an atom together
+//                     (counting sort, pass 2)
 //   k_knn_fast/exact  14 (or 18) nearest neighbours by (d^2, id), Sec. 3
 //                     Euclidean order
 //   k_voronoi_hull/   optional topological order (Sec. 3): Voronoi interface
