@@ -2906,6 +2906,15 @@ __device__ __noinline__ void serve_knn(ServeSlot &S, int64_t r) {
 // generic accesses to LDS are slower flat instructions; the generic views
 // below derive from the LDS pointers, so the compiler turns their accesses
 // back into LDS instructions.
+// The hulls of one atom per lane, in a call of their own: its registers
+// apart from the match's (LDS operands passed as LDS pointers)
+__device__ __noinline__ void serve_topo(__attribute__((address_space(3))) TopoShared *Sp,
+                                        __attribute__((address_space(3))) TablesView *Tp, int lane, int64_t p,
+                                        int64_t n, const double *nbr_rel, const int32_t *nbr_id, uint32_t need,
+                                        int32_t *code, uint64_t *ord) {
+    topo_atom(*(TopoShared *)Sp, lane, p, n, nbr_rel, nbr_id, *(const TablesView *)Tp, need, code, ord);
+}
+
 template <typename RT>
 __device__ __noinline__ void serve_match(__attribute__((address_space(3))) MatchShared *Mp,
                                          __attribute__((address_space(3))) TablesView *Tp,
@@ -2934,7 +2943,7 @@ __device__ __noinline__ void serve_match(__attribute__((address_space(3))) Match
     for (int64_t sub = b; sub < e; sub += 64) {
         const int64_t p = sub + lane;
         __syncthreads();  // the previous sub-block's match LDS is free; Ol is written
-        if (p < e) topo_atom(U.topo, lane, p, n, nbr_rel, nbr_id, T, need, code, ord);
+        if (p < e) serve_topo(&Up->topo, Tp, lane, p, n, nbr_rel, nbr_id, need, code, ord);
         // the wave's code / ord writes before other lanes read them
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __syncthreads();
