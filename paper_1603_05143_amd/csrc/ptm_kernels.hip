@@ -452,10 +452,17 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
             if (two && q2 != (int)p) t2 = pack_key(e2, q2);
             q += two ? 2 : 1;
         }
+        // the two insertions interleaved, the second one step behind the
+        // first (step m of the second reads key[m] after step m of the
+        // first): two independent dependency chains instead of one of twice
+        // the length, with the result of inserting t, then t2
+        minmax_step(key[0], t);
 #pragma unroll
-        for (int m = 0; m < KN; m++) minmax_step(key[m], t);
-#pragma unroll
-        for (int m = 0; m < KN; m++) minmax_step(key[m], t2);
+        for (int m = 1; m < KN; m++) {
+            minmax_step(key[m], t);
+            minmax_step(key[m - 1], t2);
+        }
+        minmax_step(key[KN - 1], t2);
     } while (more);
     bool ok = key[NK - 1] != INF;
 #pragma unroll
