@@ -1113,28 +1113,55 @@ constexpr int TB = 64;  // threads per block of the topology kernel
 // LDS of one block.  P: the neighbour vectors rounded to FP32 (the input of
 // the predicate filters; every predicate is decided exactly, so both
 // precision forms use this kernel); F: facets; H: the horizon of the
-// current insertion, which shares its space with the rotation system of a
-// finished 6- or 12-point hull (built between insertions).  The 14-point
-// hull is the last: its rotation system takes the space of P, which is no
-// longer read.  23,040 bytes: seven blocks per CU.
+// current insertion.  The rotation system of the 12-point hull, built
+// between insertions, packs into H and the four facet slots that hull
+// leaves free (F[20..23], which H follows in memory); the 14-point hull is
+// the last, and its rotation system takes the space of P, which is no
+// longer read.  20,480 bytes: eight blocks per CU.
 struct TopoShared {
     float P[3][KMAX][TB];
     uint32_t F[2 * KMAX - 4][TB];
-    union {
-        uint32_t H[KMAX][TB];
-        uint64_t NT[KMAX - 2][TB];
-    };
+    uint32_t H[KMAX][TB];
 };
 static_assert(sizeof(float) * 3 * KMAX >= sizeof(uint64_t) * KMAX, "a 14-row rotation system fits in P");
+static_assert(offsetof(TopoShared, H) == offsetof(TopoShared, F) + sizeof(uint32_t) * (2 * KMAX - 4) * TB,
+              "H follows F");
+static_assert(sizeof(TopoShared) == 20480, "eight blocks of the topology kernel per CU");
 
-// A lane's rotation system: row x = 64-bit word whose nibble y is the
-// vertex after y counter-clockwise around x (0xF: not a neighbour), kept in
-// LDS complemented.
+// A lane's rotation system: row x maps each neighbour y (nibble y) to the
+// vertex after y counter-clockwise around x (0xF: not a neighbour).  Rows
+// are kept complemented (0 = no neighbour), so they are built by atomic ORs
+// that need no read-modify-write round trips.
+// Rows of 16 nibbles, one 64-bit word each (the 14-point hull, in P):
 struct RotSys {
     uint64_t (*w)[TB];
     int t;
-    __device__ uint64_t get(int x) const { return ~w[x][t]; }  // rows are stored complemented
-    __device__ void set(int x, uint64_t v) const { w[x][t] = v; }
+    __device__ void clear(int k) const {
+        for (int x = 0; x < k; x++) w[x][t] = 0;
+    }
+    __device__ void set_next(int x, int y, int z) const {
+        atomicOr((unsigned long long *)&w[x][t], (unsigned long long)(z ^ 0xF) << (4 * y));
+    }
+    __device__ uint64_t get(int x) const { return ~w[x][t]; }
+};
+// Rows of 12 nibbles packed into 18 consecutive 32-bit words (the 12-point
+// hull: row x starts at bit 48 x, so it spans two words and starts at bit
+// 0 or 16 of the first):
+struct RotSys12 {
+    uint32_t (*w)[TB];
+    int t;
+    __device__ void clear(int) const {
+        for (int i = 0; i < 18; i++) w[i][t] = 0;
+    }
+    __device__ void set_next(int x, int y, int z) const {
+        const int bit = 48 * x + 4 * y;
+        atomicOr(&w[bit >> 5][t], (uint32_t)(z ^ 0xF) << (bit & 31));
+    }
+    __device__ uint64_t get(int x) const {
+        const int i = (48 * x) >> 5, sh = (48 * x) & 31;
+        const uint64_t two = ((uint64_t)w[i + 1][t] << 32) | w[i][t];
+        return ~((two >> sh) & 0xFFFFFFFFFFFFull);  // nibbles 12..15 read as no neighbour
+    }
 };
 
 // facet word: v0 | v1<<4 | v2<<8 | nb0<<12 | nb1<<17 | nb2<<22
@@ -1352,8 +1379,8 @@ __device__ inline int lane_centre_inside(const Lane &L, int K, uint32_t &cv) {
 // tables hold the codes of every start edge from a vertex of minimum degree
 // of every template triangulation, so the choice among them needs no
 // search.
-template <int K>
-__device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64_t (&code)[K]) {
+template <int K, typename RS>
+__device__ uint64_t lane_start_edge_code(const RS &NT, uint64_t degs, uint64_t (&code)[K]) {
     int mindeg = 15;
 #pragma unroll
     for (int x = 0; x < K; x++) mindeg = min(mindeg, (int)nib(degs, x));
@@ -1407,20 +1434,18 @@ __device__ uint64_t lane_start_edge_code(const RotSys &NT, uint64_t degs, uint64
 // Rotation system and canonical code of the K-point hull now held in F: the
 // K code words into best, the labelling into ordw; returns the code's hash
 // (the table probe comes after the last insertion).
-template <int K>
-__device__ uint64_t lane_code(const uint32_t (*F)[TB], const RotSys &NT, uint64_t (&best)[K], uint64_t &ordw) {
+template <int K, typename RS>
+__device__ uint64_t lane_code(const uint32_t (*F)[TB], const RS &NT, uint64_t (&best)[K], uint64_t &ordw) {
     const int t = NT.t;
-    // rows are built complemented (0 = no neighbour) by LDS atomic ORs, so
-    // the 3 (2K - 4) updates need no read-modify-write round trips; every
-    // (x, y) nibble is written once
+    // every (x, y) nibble is written once
     uint64_t degs = 0;
-    for (int x = 0; x < K; x++) NT.w[x][t] = 0;
+    NT.clear(K);
     for (int f = 0; f < 2 * K - 4; f++) {
         uint32_t w = F[f][t];
         int a = fv(w, 0), b = fv(w, 1), c = fv(w, 2);
-        atomicOr((unsigned long long *)&NT.w[a][t], (unsigned long long)(c ^ 0xF) << (4 * b));
-        atomicOr((unsigned long long *)&NT.w[b][t], (unsigned long long)(a ^ 0xF) << (4 * c));
-        atomicOr((unsigned long long *)&NT.w[c][t], (unsigned long long)(b ^ 0xF) << (4 * a));
+        NT.set_next(a, b, c);
+        NT.set_next(b, c, a);
+        NT.set_next(c, a, b);
         degs += (1ull << (4 * a)) + (1ull << (4 * b)) + (1ull << (4 * c));
     }
     ordw = lane_start_edge_code<K>(NT, degs, best);
@@ -1529,7 +1554,7 @@ __device__ __attribute__((always_inline)) inline void topo_atom(TopoShared &S, i
         Lane L{S, t, nbr_rel, n, p, f32_orient_bound(m32), f32_det3_bound(m32), f64_orient_bound(m64),
                f64_det3_bound(m64)};
         lane_hull_start(L);
-        const RotSys nt{S.NT, t};
+        const RotSys12 nt{&S.F[2 * 12 - 4], t};
         const RotSys nt14{reinterpret_cast<uint64_t (*)[TB]>(&S.P[0][0][0]), t};
         // codes of the valid hulls, probed together after the last insertion
         uint64_t c12[12] = {}, c14[14] = {}, h[NGRP] = {0, 0, 0};
