@@ -381,11 +381,15 @@ __device__ inline bool knn_fast_atom(int64_t p, int64_t n, const Grid &g, const 
                     if (rem < 0) {
                         skip = true;
                     } else {
-                        // cells whose x-gap exceeds sqrt(rem) cannot hold a better neighbour
-                        double reach = sqrt(rem) + g.margin;
-                        double x0 = u[0] - cc[0] * g.h[0];  // offset of the atom inside its cell
-                        while (xlo < 0 && (-xlo - 1) * g.h[0] + x0 > reach) xlo++;
-                        while (xhi > 0 && (xhi - 1) * g.h[0] + (g.h[0] - x0) > reach) xhi--;
+                        // cells whose x-gap less the margin exceeds sqrt(rem)
+                        // cannot hold a better neighbour (compared squared)
+                        const double x0 = u[0] - cc[0] * g.h[0];  // offset of the atom inside its cell
+                        auto beyond = [&](double gap) {
+                            const double e = gap - g.margin;
+                            return e > 0 && e * e > rem;
+                        };
+                        while (xlo < 0 && beyond((-xlo - 1) * g.h[0] + x0)) xlo++;
+                        while (xhi > 0 && beyond((xhi - 1) * g.h[0] + (g.h[0] - x0))) xhi--;
                     }
                 }
                 cyz = (cz * g.nc[1] + cy) * nx;
