@@ -2444,10 +2444,11 @@ __device__ void match_block(const MatchShared &M, const TablesView &Tl, const Ma
     }
 }
 
-// The match kernel: blocks of four waves, 256 atoms each.  Registers: three
-// blocks per CU (168 VGPRs at most) with the LDS of three.
+// The match kernel: blocks of four waves, 256 atoms each.  FP64: three
+// blocks per CU (168 VGPRs at most) with the LDS of three; FP32: four (128
+// VGPRs at most, the spills only around the rare full-rule call).
 template <typename RT>
-__global__ void __launch_bounds__(MB, 3) k_match(int64_t n, const double *__restrict__ nbr_rel,
+__global__ void __launch_bounds__(MB, sizeof(RT) == 4 ? 4 : 3) k_match(int64_t n, const double *__restrict__ nbr_rel,
                                                 const int32_t *__restrict__ nbr_id, const int32_t *__restrict__ sid,
                                                 const int8_t *__restrict__ species, TablesView T,
                                                 const int32_t *__restrict__ code, const uint64_t *__restrict__ ords,
