@@ -1676,67 +1676,13 @@ struct CandEval {
     T c;  // FP32 form: bound on the eigen-solve's excess of RMSD^2 (f32_excess_bound)
 };
 
-// eq.(3) for one candidate of K = 6, 12 or 14 neighbours: observed rank r
-// <-> template vertex tv(r).  a[] are the centred observed points (row 0 =
-// centre, rows past K unused), in the working precision T; the template
-// comes from the FP64 table.  K is a run-time value, so lanes of different
-// hull sizes run one code path (ranks past a lane's K are skipped).
-template <typename T>
-__device__ inline void eval_candidate(int K, const T (&a)[NMAX][3], T Ga, const TemplateGeom &D, uint64_t tv_of_rank,
-                                      CandEval<T> &out) {
-    // products and sums may fuse into FMAs here (one rounding instead of two; no
-    // result depends on a particular rounding)
-#pragma clang fp contract(fast)
-    T S[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    T Gb = 0;
-    {
-        const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
-        for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[0][y];
-        Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
-    }
-#pragma unroll
-    for (int r = 0; r < KMAX; r++) {
-        if (r >= K) break;
-        const double *b64 = D.b[nib(tv_of_rank, r) + 1];
-        const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
-        for (int x = 0; x < 3; x++)
-            for (int y = 0; y < 3; y++) S[x][y] += bb[x] * a[r + 1][y];
-        Gb += bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
-    }
-    T cond = 0;
-    T lam = qcp_solve<T>(S, Ga, Gb, out.q, sizeof(T) == 4 ? &cond : nullptr);
-    if constexpr (sizeof(T) == 4) out.c = f32_excess_bound(lam, cond, Ga);
-    T s = Ga > T(0) ? lam / Ga : T(0);
-    T R[3][3];
-    quat_rot<T>(out.q, R);
-    T res = 0;
-    {
-        const T bb[3] = {(T)D.b[0][0], (T)D.b[0][1], (T)D.b[0][2]};
-        for (int x = 0; x < 3; x++) {
-            T d = s * a[0][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
-            res += d * d;
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < KMAX; r++) {
-        if (r >= K) break;
-        const double *b64 = D.b[nib(tv_of_rank, r) + 1];
-        const T bb[3] = {(T)b64[0], (T)b64[1], (T)b64[2]};
-        for (int x = 0; x < 3; x++) {
-            T d = s * a[r + 1][x] - (R[x][0] * bb[0] + R[x][1] * bb[1] + R[x][2] * bb[2]);
-            res += d * d;
-        }
-    }
-    out.r = sqrt(res / T(K + 1));
-    out.s = s;
-}
-
-// eq.(3) for one candidate with the observed points streamed from the
-// (cached) neighbour vectors instead of held in registers: covariance and
-// G_a / G_b in one pass, the residual in a second, each recomputing the
-// centred points from the barycentre cb (FP64, eq. 2).  K run-time, as in
-// eval_candidate.  Moments (FP64 only): the residual at (s, q) is also
+// eq.(3) for one candidate of K = 6, 12 or 14 neighbours (observed rank r
+// <-> template vertex tv(r); the template from the FP64 table) with the
+// observed points streamed from the (cached) neighbour vectors instead of
+// held in registers: covariance and G_a / G_b in one pass, the residual in
+// a second, each recomputing the centred points from the barycentre cb
+// (FP64, eq. 2).  K is a run-time value, so lanes of different hull sizes
+// run one code path.  Moments (FP64 only): the residual at (s, q) is also
 // G_b + s (s G_a - 2 rho), rho = sum_i a_i . R b_i = tr(R S^T); it is
 // stationary in q and s at the optimum, and its rounding error, a few ulps
 // of G_b ~ N, is at most 2e-13 in the RMSD once RMSD >= 0.01 (the
@@ -1811,30 +1757,6 @@ __device__ inline void eval_streamed(int K, const double *__restrict__ nbr_rel, 
     }
     out.r = sqrt(res / T(K + 1));
     out.s = s;
-}
-
-// observed points of one hull group: centre (row 0) and the innermost K
-// neighbours (K run-time; rows past it are left alone), minus their
-// barycentre cb (eq. 2, FP64 differences rounded to T); Ga = sum of squared
-// norms
-template <typename T>
-__device__ inline void load_centred(int K, const double *__restrict__ nbr_rel, int64_t n, int64_t p,
-                                    const double (&cb)[3], T (&a)[NMAX][3], T &Ga) {
-    double g = 0;
-    for (int d = 0; d < 3; d++) {
-        a[0][d] = (T)(-cb[d]);
-        g += cb[d] * cb[d];
-    }
-#pragma unroll
-    for (int r = 0; r < KMAX; r++) {
-        if (r >= K) break;
-        for (int d = 0; d < 3; d++) {
-            const double x = nbr_rel[((int64_t)r * 3 + d) * n + p] - cb[d];
-            a[r + 1][d] = (T)x;
-            g += x * x;
-        }
-    }
-    Ga = (T)g;
 }
 
 // template vertex of each observed rank for candidate perm (label -> vertex)
