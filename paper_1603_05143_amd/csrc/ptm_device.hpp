@@ -266,30 +266,42 @@ PTM_HD double f32_det3_bound(double m) {
 PTM_HD double f64_orient_bound(double m) { return fmax(7e-14 * m * m * m, 1e-290); }
 PTM_HD double f64_det3_bound(double m) { return fmax(5.4e-15 * m * m * m, 1e-290); }
 
-// det[b-a; c-a; d-a] sign from FP32 points in FP32 arithmetic (evaluated as
-// -det[a-d; b-d; c-d]); 0 when |det| <= bound (f32_orient_bound).
-PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d, double bound) {
+// det[a-d; b-d; c-d] = -det[b-a; c-a; d-a] from FP32 points in FP32
+// arithmetic: the value the FP32 orientation filter compares with its bound
+PTM_HD float orient_det_f32in(const float *a, const float *b, const float *c, const float *d) {
     // fused multiply-adds round once where a product and a sum round twice,
     // so the error bound of the unfused evaluation covers them
 #pragma clang fp contract(fast)
     const float adx = a[0] - d[0], ady = a[1] - d[1], adz = a[2] - d[2];
     const float bdx = b[0] - d[0], bdy = b[1] - d[1], bdz = b[2] - d[2];
     const float cdx = c[0] - d[0], cdy = c[1] - d[1], cdz = c[2] - d[2];
-    const float det = adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
+    return adz * (bdx * cdy - cdx * bdy) + bdz * (cdx * ady - adx * cdy) + cdz * (adx * bdy - bdx * ady);
+}
+
+// det[b-a; c-a; d-a] sign from FP32 points in FP32 arithmetic; 0 when |det| <=
+// bound (f32_orient_bound).
+PTM_HD int orient_filter_f32in(const float *a, const float *b, const float *c, const float *d, double bound) {
+    const float det = orient_det_f32in(a, b, c, d);
     const float bf = (float)bound;
     if (det > bf) return -1;
     if (det < -bf) return 1;
     return 0;
 }
 
-// det[a; b; c] sign from FP32 points in FP32 arithmetic; 0 when |det| <=
-// bound (f32_det3_bound)
-PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c, double bound) {
+// det[a; b; c] from FP32 points in FP32 arithmetic: the value the FP32
+// determinant filter compares with its bound
+PTM_HD float det3_f32in(const float *a, const float *b, const float *c) {
     // fused multiply-adds round once where a product and a sum round twice,
     // so the error bound of the unfused evaluation covers them
 #pragma clang fp contract(fast)
-    const float det = a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
-                      a[2] * (b[0] * c[1] - b[1] * c[0]);
+    return a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+           a[2] * (b[0] * c[1] - b[1] * c[0]);
+}
+
+// det[a; b; c] sign from FP32 points in FP32 arithmetic; 0 when |det| <=
+// bound (f32_det3_bound)
+PTM_HD int det3_filter_f32in(const float *a, const float *b, const float *c, double bound) {
+    const float det = det3_f32in(a, b, c);
     const float bf = (float)bound;
     if (det > bf) return 1;
     if (det < -bf) return -1;

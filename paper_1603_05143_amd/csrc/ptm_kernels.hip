@@ -1198,11 +1198,9 @@ struct Lane {
     }
 };
 
-// orientation of facet (a,b,c), its points given, against point q
-__device__ inline int lane_orient_pts(const Lane &L, int a, int b, int c, const float (&pa)[3], const float (&pb)[3],
-                                      const float (&pc)[3], const float (&pq)[3], int q) {
-    int s = orient_filter_f32in(pa, pb, pc, pq, L.bo);
-    if (s) return s;
+// orientation of facet (a,b,c) against point q where the FP32 filter
+// cannot decide: the FP64 filter, then exact arithmetic with SoS
+__device__ inline int lane_orient_exact(const Lane &L, int a, int b, int c, int q) {
     double da[3], db[3], dc[3], dq[3];
     L.load64(a, da);
     L.load64(b, db);
@@ -1211,27 +1209,23 @@ __device__ inline int lane_orient_pts(const Lane &L, int a, int b, int c, const 
     return orient_sos64b(da, db, dc, dq, a, b, c, q, L.bo64);
 }
 
+// det[a; b; c] sign where the FP32 filter cannot decide
+__device__ inline int lane_det3_exact(const Lane &L, int a, int b, int c) {
+    double da[3], db[3], dc[3];
+    L.load64(a, da);
+    L.load64(b, db);
+    L.load64(c, dc);
+    return det3_sign64b(da, db, dc, L.bd64);
+}
+
 // orientation of facet (a,b,c) against point q (held in registers)
 __device__ inline int lane_orient(const Lane &L, int a, int b, int c, const float (&pq)[3], int q) {
     float pa[3], pb[3], pc[3];
     L.load(a, pa);
     L.load(b, pb);
     L.load(c, pc);
-    return lane_orient_pts(L, a, b, c, pa, pb, pc, pq, q);
-}
-
-__device__ inline int lane_det3(const Lane &L, int a, int b, int c) {
-    float pa[3], pb[3], pc[3];
-    L.load(a, pa);
-    L.load(b, pb);
-    L.load(c, pc);
-    int s = det3_filter_f32in(pa, pb, pc, L.bd);
-    if (s) return s;
-    double da[3], db[3], dc[3];
-    L.load64(a, da);
-    L.load64(b, db);
-    L.load64(c, dc);
-    return det3_sign64b(da, db, dc, L.bd64);
+    const int s = orient_filter_f32in(pa, pb, pc, pq, L.bo);
+    return s ? s : lane_orient_exact(L, a, b, c, q);
 }
 
 // first tetrahedron of points 0..3, positively oriented; facets 0..3
@@ -1257,11 +1251,12 @@ __device__ int lane_insert(const Lane &L, int p, uint32_t &cv) {
     const int t = L.t;
     const int nf = 2 * p - 4;
     uint32_t vis = 0;
-    int nvis = 0;
     float pp[3];
     L.load(p, pp);
+    const float bf = (float)L.bo;
     // two facets per step (nf is even): both filters' loads are issued
-    // together; the rare undecided test falls back to the exact path
+    // together.  A facet is visible when its FP32 determinant lies below
+    // -bound; the rare one within the bound (or NaN) takes the exact path.
     for (int f = 0; f < nf; f += 2) {
         const uint32_t w0 = S.F[f][t], w1 = S.F[f + 1][t];
         float a0[3], b0[3], c0[3], a1[3], b1[3], c1[3];
@@ -1271,20 +1266,14 @@ __device__ int lane_insert(const Lane &L, int p, uint32_t &cv) {
         L.load(fv(w1, 0), a1);
         L.load(fv(w1, 1), b1);
         L.load(fv(w1, 2), c1);
-        int s0 = orient_filter_f32in(a0, b0, c0, pp, L.bo);
-        int s1 = orient_filter_f32in(a1, b1, c1, pp, L.bo);
-        if (!s0) s0 = lane_orient_pts(L, fv(w0, 0), fv(w0, 1), fv(w0, 2), a0, b0, c0, pp, p);
-        if (!s1) s1 = lane_orient_pts(L, fv(w1, 0), fv(w1, 1), fv(w1, 2), a1, b1, c1, pp, p);
-        if (s0 > 0) {
-            vis |= 1u << f;
-            nvis++;
-        }
-        if (s1 > 0) {
-            vis |= 2u << f;
-            nvis++;
-        }
+        const float d0 = orient_det_f32in(a0, b0, c0, pp), d1 = orient_det_f32in(a1, b1, c1, pp);
+        bool v0 = d0 < -bf, v1 = d1 < -bf;
+        if (!(fabsf(d0) > bf)) v0 = lane_orient_exact(L, fv(w0, 0), fv(w0, 1), fv(w0, 2), p) > 0;
+        if (!(fabsf(d1) > bf)) v1 = lane_orient_exact(L, fv(w1, 0), fv(w1, 1), fv(w1, 2), p) > 0;
+        vis |= (v0 ? 1u << f : 0u) | (v1 ? 2u << f : 0u);
     }
-    if (nvis == 0) return 0;  // p inside: never a vertex
+    if (vis == 0) return 0;  // p inside: never a vertex
+    const int nvis = __builtin_popcount(vis);
     // horizon edges (a -> b) of the visible facets f whose neighbour g is
     // not visible, one per start vertex: H[a] = b | g << 4 | f << 9.  Inner
     // edges write to row KMAX - 1, which is no start vertex (a < p <=
@@ -1352,6 +1341,7 @@ __device__ int lane_insert(const Lane &L, int p, uint32_t &cv) {
 // not tested again; on success every facet joins cv.
 __device__ inline int lane_centre_inside(const Lane &L, int K, uint32_t &cv) {
     const uint32_t all = (1u << (2 * K - 4)) - 1;
+    const float bd = (float)L.bd;
     // two facets per step, as in the insertion
     for (uint32_t m = all & ~cv; m;) {
         const int f0 = __builtin_ctz(m);
@@ -1366,11 +1356,11 @@ __device__ inline int lane_centre_inside(const Lane &L, int K, uint32_t &cv) {
         L.load(fv(w1, 0), a1);
         L.load(fv(w1, 1), b1);
         L.load(fv(w1, 2), c1);
-        const int s0 = det3_filter_f32in(a0, b0, c0, L.bd);
-        const int s1 = det3_filter_f32in(a1, b1, c1, L.bd);
-        if (s0 < 0 || s1 < 0) return 0;
-        if (!s0 && lane_det3(L, fv(w0, 0), fv(w0, 1), fv(w0, 2)) <= 0) return 0;
-        if (!s1 && lane_det3(L, fv(w1, 0), fv(w1, 1), fv(w1, 2)) <= 0) return 0;
+        // outside below -bound; within the bound (or NaN) the exact path decides
+        const float e0 = det3_f32in(a0, b0, c0), e1 = det3_f32in(a1, b1, c1);
+        if (e0 < -bd || e1 < -bd) return 0;
+        if (!(e0 > bd) && lane_det3_exact(L, fv(w0, 0), fv(w0, 1), fv(w0, 2)) <= 0) return 0;
+        if (!(e1 > bd) && lane_det3_exact(L, fv(w1, 0), fv(w1, 1), fv(w1, 2)) <= 0) return 0;
     }
     cv |= all;
     return 1;
