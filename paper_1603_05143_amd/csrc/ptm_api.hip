@@ -7,7 +7,6 @@
 // with per-frame scratch, admitted against the HBM budget (see
 // ptm_serve.hip).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 #include <cstdio>
@@ -28,7 +27,7 @@ namespace ptm {
 // ------------------------------------------------------------ scratch
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo) {
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, bool topo) {
     size_t b = 0;
     b += align_up(4 * (size_t)n) * 3;         // cell_of, slot_of, sid
     // count (+ the frame's counters and the box flag), start
@@ -40,8 +39,7 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
     b += align_up(8 * (size_t)n * NGRP);      // labellings
     b += align_up(8 * 7 * (size_t)nbounds);   // bounds partials
     b += align_up(8 * 7 * (size_t)serve_bounds_items(n));  // persistent serving: per-item bounds
-    b += align_up(4 * (size_t)(serve_scan_items(n) + 1));  // and per-item scan totals
-    b += align_up(scan_tmp);
+    b += align_up(4 * (size_t)(serve_scan_items(n) + 1));  // per-item totals of the cell-start scan
     if (topo) {
         b += align_up(4 * (size_t)n * VK);      // the 18 Euclidean neighbours' ids
         b += align_up(8 * (size_t)n * VK * 3);  // and vectors
@@ -53,13 +51,11 @@ size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool 
 
 bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err) {
     int nb = bounds_blocks(n);
-    size_t scan_tmp = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (int32_t *)nullptr, (int32_t *)nullptr,
-                                         (int)(cells + 1)) != hipSuccess) {
-        err = "hipcub scan size query failed";
+    if (scan_items(cells) > serve_scan_items(n)) {  // make_grid keeps cells <= 4n + 4096
+        err = "cell grid larger than the scratch layout allows";
         return false;
     }
-    size_t need = frame_bytes(n, cells, nb, scan_tmp, topo);
+    size_t need = frame_bytes(n, cells, nb, topo);
     if (need > bytes) {
         if (pooled) {
             // a pooled buffer is sized for its class and never reallocated
@@ -95,8 +91,6 @@ bool FrameScratch::reserve(int64_t n, int64_t cells, bool topo, std::string &err
     part = (double *)take(8 * 7 * (size_t)nb);
     sv_part = (double *)take(8 * 7 * (size_t)serve_bounds_items(n));
     sv_bsum = (int32_t *)take(4 * (size_t)(serve_scan_items(n) + 1));
-    scan_tmp_ptr = take(scan_tmp);
-    scan_tmp_bytes = scan_tmp;
     id18 = topo ? (int32_t *)take(4 * (size_t)n * VK) : nullptr;
     rel18 = topo ? (double *)take(8 * (size_t)n * VK * 3) : nullptr;
     vf = topo ? (uint32_t *)take(4 * (size_t)n * (2 * VK - 4)) : nullptr;
@@ -196,8 +190,7 @@ ptm_status enqueue_frame(ptm_ctx *ctx, FrameScratch &S, const FrameJob &J, hipSt
     launch_zero(S.count, cells + FRAME_COUNTERS, st);
     const int32_t *box_fail = S.count + cells + 3;
     launch_bin_count(J.pos, n, g, S.cell_of, S.slot_of, S.count, st);
-    size_t tmp = S.scan_tmp_bytes;
-    PTM_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(S.scan_tmp_ptr, tmp, S.count, S.start, (int)(cells + 1), st));
+    launch_cell_starts(S.count, cells, S.sv_bsum, S.start, st);
     launch_bin_scatter(J.pos, n, S.cell_of, S.slot_of, S.start, S.spos, S.sid, st);
     if ((ps = mark(PTM_STAGE_KNN)) != PTM_OK) return ps;
     // slot_of is free once the atoms are scattered: it holds the leftover list
@@ -364,7 +357,7 @@ ptm_status classify_frame(ptm_ctx *ctx, FrameScratch &S, bool noalloc, const dou
     }
     J.grid = make_grid(box, mn, mx, n_atoms, J.topo ? VK : KMAX);
     int64_t cells = (int64_t)J.grid.nc[0] * J.grid.nc[1] * J.grid.nc[2];
-    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), 0, J.topo) > ctx->budget) {
+    if (ctx->budget && frame_bytes(n_atoms, cells, bounds_blocks(n_atoms), J.topo) > ctx->budget) {
         ctx->err = "frame scratch exceeds the HBM budget";
         return PTM_E_NOMEM;
     }

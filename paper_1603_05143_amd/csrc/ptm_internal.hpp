@@ -40,9 +40,7 @@ struct FrameScratch {
     uint64_t *ord = nullptr;
     double *part = nullptr;
     double *sv_part = nullptr;   // persistent serving: per-item bounds
-    int32_t *sv_bsum = nullptr;  // and per-item scan totals
-    void *scan_tmp_ptr = nullptr;
-    size_t scan_tmp_bytes = 0;
+    int32_t *sv_bsum = nullptr;  // per-item totals of the cell-start scan (every path)
     bool reserve(int64_t n, int64_t cells, bool topo, std::string &err);
     void release();
 };
@@ -92,7 +90,7 @@ struct Ticket {
     uint64_t gen = 0;
 };
 
-size_t frame_bytes(int64_t n, int64_t cells, int nbounds, size_t scan_tmp, bool topo);
+size_t frame_bytes(int64_t n, int64_t cells, int nbounds, bool topo);
 // the box flag of a frame whose kernels have been enqueued (count[cells + 3])
 inline int32_t *box_flag(const FrameScratch &S, const Grid &g) {
     return S.count + (int64_t)g.nc[0] * g.nc[1] * g.nc[2] + 3;

@@ -24,7 +24,6 @@
 // lane one candidate of its wave's atoms); atoms are processed in cell
 // order so the lanes of a wave read the same cells.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 #include <stdint.h>
 
 #include "ptm_device.hpp"
@@ -103,6 +102,117 @@ __global__ void k_bin_count(const double *__restrict__ pos, int64_t n, Grid g, i
     int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
     cell_of[i] = c;
     slot_of[i] = atomicAdd(&count[c], 1);
+}
+
+// Cell starts: the exclusive scan of the counts over cells + 1 entries (the
+// last start is the number of atoms), in items of SERVE_SCAN_CELLS cells --
+// the items' totals, their exclusive scan, then each item's cells from its
+// offset (three passes: every atomic count must be final before the first).
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_PER = (int)(SERVE_SCAN_CELLS / SCAN_THREADS);  // cells per thread
+static_assert(SERVE_SCAN_CELLS % SCAN_THREADS == 0 && SCAN_PER % 4 == 0, "an item is whole threads' 16-byte runs");
+
+// exclusive scan over a block of NT threads (ws: NT / 64 words of LDS);
+// total: the block's sum
+template <int NT>
+__device__ inline int32_t block_excl_scan(int32_t v, int32_t &total, int32_t *ws) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    int32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; k++) {
+        const int32_t t = ws[k];
+        before += k < w ? t : 0;
+        all += t;
+    }
+    total = all;
+    return before + x - v;
+}
+
+// item totals: 16-byte reads interleaved across the block, so they
+// coalesce (count is 256-byte aligned and items are multiples of 4 cells)
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_totals(const int32_t *__restrict__ count, int64_t cells,
+                                                               int32_t *__restrict__ bsum) {
+    __shared__ int32_t ws[SCAN_THREADS / 64];
+    const int64_t b = (int64_t)blockIdx.x * SERVE_SCAN_CELLS + 4 * (int64_t)threadIdx.x;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER / 4; k++) {
+        const int64_t c = b + (int64_t)k * 4 * SCAN_THREADS;
+        if (c + 4 <= cells) {
+            const int4 x = *reinterpret_cast<const int4 *>(count + c);
+            s += (x.x + x.y) + (x.z + x.w);
+        } else {
+            for (int j = 0; j < 4; j++) s += c + j < cells ? count[c + j] : 0;
+        }
+    }
+    int32_t total;
+    (void)block_excl_scan<SCAN_THREADS>(s, total, ws);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// exclusive scan of the item totals in place, one block
+__global__ void __launch_bounds__(1024) k_scan_top(int32_t *__restrict__ bsum, int64_t items) {
+    __shared__ int32_t ws[1024 / 64];
+    const int64_t per = (items + 1023) / 1024;
+    const int64_t lb = threadIdx.x * per, le = min(items, lb + per);
+    int32_t s = 0;
+    for (int64_t k = lb; k < le; k++) s += bsum[k];
+    int32_t total;
+    int32_t run = block_excl_scan<1024>(s, total, ws);
+    for (int64_t k = lb; k < le; k++) {
+        const int32_t v = bsum[k];
+        bsum[k] = run;
+        run += v;
+    }
+}
+
+// each item's cells: a run of SCAN_PER consecutive cells per thread
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_cells(const int32_t *__restrict__ count, int64_t cells,
+                                                              const int32_t *__restrict__ bsum,
+                                                              int32_t *__restrict__ start) {
+    __shared__ int32_t ws[SCAN_THREADS / 64];
+    const int64_t b = (int64_t)blockIdx.x * SERVE_SCAN_CELLS + (int64_t)threadIdx.x * SCAN_PER;
+    int32_t v[SCAN_PER], s = 0;
+    if (b + SCAN_PER <= cells) {  // whole run in range: 16-byte reads (b is a multiple of 8)
+        const int4 *q = reinterpret_cast<const int4 *>(count + b);
+#pragma unroll
+        for (int k = 0; k < SCAN_PER / 4; k++) {
+            const int4 x = q[k];
+            v[4 * k] = x.x;
+            v[4 * k + 1] = x.y;
+            v[4 * k + 2] = x.z;
+            v[4 * k + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_PER; k++) v[k] = b + k < cells ? count[b + k] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) s += v[k];
+    int32_t total;
+    int32_t run = bsum[blockIdx.x] + block_excl_scan<SCAN_THREADS>(s, total, ws);
+    int32_t o[SCAN_PER];
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) {
+        o[k] = run;
+        run += v[k];
+    }
+    if (b + SCAN_PER <= cells + 1) {
+        int4 *q = reinterpret_cast<int4 *>(start + b);
+#pragma unroll
+        for (int k = 0; k < SCAN_PER / 4; k++) q[k] = make_int4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_PER; k++)
+            if (b + k <= cells) start[b + k] = o[k];
+    }
 }
 
 __global__ void k_bin_scatter(const double *__restrict__ pos, int64_t n, const int32_t *__restrict__ cell_of,
@@ -2640,6 +2750,13 @@ void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell
                       int32_t *count, hipStream_t st) {
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, g, cell_of, slot_of,
                        count);
+}
+void launch_cell_starts(const int32_t *count, int64_t cells, int32_t *bsum, int32_t *start, hipStream_t st) {
+    const int64_t items = scan_items(cells);
+    hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)items), dim3(SCAN_THREADS), 0, st, count, cells, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, bsum, items);
+    hipLaunchKernelGGL(k_scan_cells, dim3((unsigned)items), dim3(SCAN_THREADS), 0, st, count, cells,
+                       (const int32_t *)bsum, start);
 }
 void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
                         const int32_t *start, double *spos, int32_t *sid, hipStream_t st) {

@@ -41,6 +41,9 @@ void launch_zero(int32_t *p, int64_t n, hipStream_t st);
 void launch_bounds(const double *pos, int64_t n, double *part, int nblocks, hipStream_t st);
 void launch_bin_count(const double *pos, int64_t n, const Grid &g, int32_t *cell_of, int32_t *slot_of,
                       int32_t *count, hipStream_t st);
+// start[0 .. cells] = exclusive scan of count[0 .. cells - 1] (start[cells]
+// = the total); bsum: scan_items(cells) words of scratch
+void launch_cell_starts(const int32_t *count, int64_t cells, int32_t *bsum, int32_t *start, hipStream_t st);
 void launch_bin_scatter(const double *pos, int64_t n, const int32_t *cell_of, const int32_t *slot_of,
                         const int32_t *start, double *spos, int32_t *sid, hipStream_t st);
 // k-NN: fast block search, then the exact shell search for the atoms it
@@ -153,7 +156,9 @@ struct ServeDev {
 
 // scratch of the serving stages beyond the stream path's, for n atoms
 inline int64_t serve_bounds_items(int64_t n) { return (n + SERVE_ATOMS_LIGHT - 1) / SERVE_ATOMS_LIGHT; }
-inline int64_t serve_scan_items(int64_t n) { return (4 * n + 4096 + 1 + SERVE_SCAN_CELLS - 1) / SERVE_SCAN_CELLS; }
+// items of the cell-start scan over cells + 1 entries
+inline int64_t scan_items(int64_t cells) { return (cells + 1 + SERVE_SCAN_CELLS - 1) / SERVE_SCAN_CELLS; }
+inline int64_t serve_scan_items(int64_t n) { return scan_items(4 * n + 4096); }
 
 // Launch the persistent kernel (grid: what fits on the device at once);
 // its waves exit after idle_ticks of the device wall clock without work,

@@ -18,7 +18,6 @@
 // and runs every stage as work items; ptm_wait polls the completion word
 // the kernel writes back, relaunching the kernel if it has exited idle.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -197,13 +196,10 @@ static ptm_status serve_init(ptm_ctx *ctx) {
 
 // Size class of a frame's scratch: the next power of two (at least 1 MiB)
 // of an upper bound of its bytes that holds for any cell grid make_grid
-// may choose (at most 4n + 4096 cells), with the scan space
-// FrameScratch::reserve sizes.
+// may choose (at most 4n + 4096 cells).
 static size_t scratch_class(int64_t n, bool topo) {
     int64_t cells = 4 * n + 4096;
-    size_t tmp = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (int32_t *)nullptr, (int32_t *)nullptr, (int)(cells + 1));
-    size_t need = frame_bytes(n, cells, bounds_blocks(n), tmp, topo);
+    size_t need = frame_bytes(n, cells, bounds_blocks(n), topo);
     size_t c = (size_t)1 << 20;
     while (c < need) c <<= 1;
     return c;
