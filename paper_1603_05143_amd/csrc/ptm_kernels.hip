@@ -832,19 +832,23 @@ struct VLane {
         x[1] = S.P[1][j][t];
         x[2] = S.P[2][j][t];
     }
-    __device__ int orient(int a, int b, int c, const float (&pq)[3], int q) const {
-        float pa[3], pb[3], pc[3];
-        load(a, pa);
-        load(b, pb);
-        load(c, pc);
-        const int s = orient_filter_f32in(pa, pb, pc, pq, bo);
-        if (s) return s;
+    // where the FP32 filter cannot decide: the FP64 filter, then exact
+    // arithmetic with SoS
+    __device__ int orient_exact(int a, int b, int c, int q) const {
         double da[3], db[3], dc[3], dq[3];
         dual_point(rel18, n, p, a, da);
         dual_point(rel18, n, p, b, db);
         dual_point(rel18, n, p, c, dc);
         dual_point(rel18, n, p, q, dq);
         return orient_sos64b(da, db, dc, dq, a, b, c, q, bo64);
+    }
+    __device__ int orient(int a, int b, int c, const float (&pq)[3], int q) const {
+        float pa[3], pb[3], pc[3];
+        load(a, pa);
+        load(b, pb);
+        load(c, pc);
+        const int s = orient_filter_f32in(pa, pb, pc, pq, bo);
+        return s ? s : orient_exact(a, b, c, q);
     }
     __device__ int det3(uint32_t f) const {
         float pa[3], pb[3], pc[3];
@@ -897,8 +901,10 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
     float pp[3];
     L.load(p, pp);
     uint32_t vis = 0;
-    // two facets per step: both filters' loads are issued together; the
-    // rare undecided test falls back to the exact path
+    const float bf = (float)L.bo;
+    // two facets per step: both filters' loads are issued together.  A facet
+    // is visible when its FP32 determinant lies below -bound; the rare one
+    // within the bound (or NaN) takes the exact path.
     for (uint32_t m = live; m;) {
         const int f0 = __builtin_ctz(m);
         m &= m - 1;
@@ -913,12 +919,11 @@ __device__ inline bool vhull_insert(const VLane &L, int p, uint32_t &live) {
         L.load(vv(w1, 0), a1);
         L.load(vv(w1, 1), b1);
         L.load(vv(w1, 2), c1);
-        int s0 = orient_filter_f32in(a0, b0, c0, pp, L.bo);
-        int s1 = orient_filter_f32in(a1, b1, c1, pp, L.bo);
-        if (!s0) s0 = L.orient(vv(w0, 0), vv(w0, 1), vv(w0, 2), pp, p);
-        if (two && !s1) s1 = L.orient(vv(w1, 0), vv(w1, 1), vv(w1, 2), pp, p);
-        if (s0 > 0) vis |= 1u << f0;
-        if (two && s1 > 0) vis |= 1u << f1;
+        const float d0 = orient_det_f32in(a0, b0, c0, pp), d1 = orient_det_f32in(a1, b1, c1, pp);
+        bool v0 = d0 < -bf, v1 = d1 < -bf;
+        if (!(fabsf(d0) > bf)) v0 = L.orient_exact(vv(w0, 0), vv(w0, 1), vv(w0, 2), p) > 0;
+        if (two && !(fabsf(d1) > bf)) v1 = L.orient_exact(vv(w1, 0), vv(w1, 1), vv(w1, 2), p) > 0;
+        vis |= (v0 ? 1u << f0 : 0u) | (two && v1 ? 1u << f1 : 0u);
     }
     if (!vis) return true;
     // horizon edges (a -> b) of the visible facets whose neighbour g is not
